@@ -1,0 +1,59 @@
+"""Pencil-beam spots and treatment-plan style spot lists.
+
+A spot is a Gaussian pencil beam travelling along +z from the phantom's
+entrance face: nominal energy E (MeV) with relative Gaussian spread sigmaE,
+lateral centre (x, y) in cm with Gaussian spread sigma_xy, a weight (the
+number of protons the spot stands for) and the number of simulated
+histories.  Each simulated history carries weight/n_histories.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Spot:
+    E_MeV: float
+    sigmaE_rel: float = 0.0
+    x_cm: float = 0.0
+    y_cm: float = 0.0
+    sigma_xy_cm: float = 0.0
+    weight: float = 1.0
+    n_histories: int = 0
+
+
+def single_spot(E_MeV: float, n: int, sigmaE_rel: float = 0.0, sigma_xy_cm: float = 0.0,
+                x_cm: float = 0.0, y_cm: float = 0.0, weight: float | None = None) -> List[Spot]:
+    """One spot; by default its weight equals its history count (dose of n protons)."""
+    return [Spot(E_MeV, sigmaE_rel, x_cm, y_cm, sigma_xy_cm,
+                 float(n) if weight is None else float(weight), int(n))]
+
+
+def plan_spots(n_spots: int = 1000, pitch_cm: float = 0.5, e_lo: float = 70.0,
+               e_hi: float = 230.0, w_sigma: float = 0.5, logn_lo: float = 3.0,
+               logn_hi: float = 5.0, sigmaE_rel: float = 0.01, sigma_xy_cm: float = 0.3,
+               seed: int = 102, n_scale: float = 1.0) -> List[Spot]:
+    """Raster of spots on a square lateral grid, centred on the axis.
+
+    Energies U(e_lo, e_hi), weights LogNormal(0, w_sigma), histories
+    round(10**U(logn_lo, logn_hi)) (times ``n_scale``, at least 1), all from
+    one seeded generator.  Positions fill a ceil(sqrt(n))^2 raster row by row.
+    """
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(np.sqrt(n_spots)))
+    E = rng.uniform(e_lo, e_hi, n_spots)
+    w = rng.lognormal(0.0, w_sigma, n_spots)
+    n = np.rint(10.0 ** rng.uniform(logn_lo, logn_hi, n_spots))
+    n = np.maximum(1, np.rint(n * n_scale)).astype(np.int64)
+    spots = []
+    for k in range(n_spots):
+        iy, ix = divmod(k, side)
+        x = (ix - (side - 1) / 2.0) * pitch_cm
+        y = (iy - (side - 1) / 2.0) * pitch_cm
+        spots.append(Spot(float(E[k]), sigmaE_rel, float(x), float(y), sigma_xy_cm,
+                          float(w[k]), int(n[k])))
+    return spots

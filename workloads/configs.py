@@ -1,0 +1,91 @@
+"""Named workloads with their sizes and seeds.
+
+* ``water100_small``: 100 MeV monoenergetic point beam, 1e4 histories, water
+  40 x 40 x 150 mm at 1 mm voxels, seed 0 (small parity case).
+* ``water150``: 150 MeV, 1 % Gaussian energy spread, 3 mm Gaussian lateral
+  spread, 1e7 histories, water 200 x 200 x 300 mm at 1 mm, seed 1 (the
+  throughput workload).
+* ``slab``/``insert``: 100 or 150 MeV with the water150 beam model,
+  200 x 200 x 200 mm at 1 mm.
+* ``plan``: 1000 spots, 70-230 MeV, lognormal weights, 1e3-1e5 histories per
+  spot, 256 x 256 x 200 voxels of 2 mm with a random density field.
+
+Physics parameters are the paper's run settings (section 2.2, "Test cases",
+and section 2.1): step 0.5 mm, Lynch-Dahl path length 0.05 cm, F = 0.98,
+absorption energy 0.05 MeV, Rutherford cut 0.02 rad, backscatter cut 0.04 rad.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List
+
+from .beams import Spot, single_spot, plan_spots
+from .nuclear import EnergyLattice
+from .phantoms import Phantom, water_box, slab_phantom, insert_phantom, grf_phantom
+
+# physics switches (bit values shared by both implementations' interfaces)
+F_LOSS = 1
+F_STRAGGLE = 2
+F_MCS = 4
+F_ELASTIC = 8
+F_INELASTIC = 16
+F_END_OF_RANGE = 32
+F_ALL = 63
+
+
+@dataclass(frozen=True)
+class PhysicsParams:
+    step_cm: float = 0.05
+    ld_z_cm: float = 0.05
+    e_min_MeV: float = 0.05
+    e_max_MeV: float = 260.0
+    ld_F: float = 0.98
+    theta_cut_rad: float = 0.02
+    backscatter_cut_rad: float = 0.04
+    n_energy: int = 1024
+    flags: int = F_ALL
+    max_steps: int = 65536
+
+    def lattice(self) -> EnergyLattice:
+        return EnergyLattice(self.n_energy, self.e_min_MeV, self.e_max_MeV)
+
+
+@dataclass
+class Workload:
+    name: str
+    phantom: Phantom
+    spots: List[Spot]
+    seed: int
+    params: PhysicsParams = field(default_factory=PhysicsParams)
+
+    @property
+    def n_histories(self) -> int:
+        return int(sum(s.n_histories for s in self.spots))
+
+
+def water100_small(n: int = 10_000, seed: int = 0) -> Workload:
+    return Workload("water100_small", water_box(40, 40, 150, 0.1),
+                    single_spot(100.0, n), seed)
+
+
+def water150(n: int = 10_000_000, seed: int = 1) -> Workload:
+    return Workload("water150", water_box(200, 200, 300, 0.1),
+                    single_spot(150.0, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
+
+
+def slab(E: float = 150.0, n: int = 10_000_000, seed: int = 2, size: int = 200) -> Workload:
+    return Workload(f"slab{int(E)}", slab_phantom(size, 0.1),
+                    single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
+
+
+def insert(E: float = 150.0, n: int = 10_000_000, seed: int = 4, size: int = 200) -> Workload:
+    return Workload(f"insert{int(E)}", insert_phantom(size, 0.1),
+                    single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
+
+
+def plan(n_spots: int = 1000, n_scale: float = 1.0, seed: int = 6,
+         shape=(256, 256, 200)) -> Workload:
+    nx, ny, nz = shape
+    return Workload("plan", grf_phantom(nx, ny, nz, 0.2),
+                    plan_spots(n_spots, n_scale=n_scale), seed)

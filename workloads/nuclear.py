@@ -1,0 +1,96 @@
+"""Placeholder nuclear inelastic tables.
+
+The paper takes the inelastic proton-nucleus data (rate sigma_ne(E), the
+outgoing-energy distribution pi_ne(E; du), and the Kalbach-Mann parameters
+r(E, u) and a(E, u)) from the ENDF/B-VIII.1 and JEFF-4.0 libraries
+(section 2.1, "Parameterisation for inelastic proton-nucleus interactions").
+Those libraries are not available here, so this module writes smooth,
+documented placeholder tables of the same shape.  Every physics statement
+that depends on them is a statement about the placeholder, not about nature.
+
+Table layout (shared definition of the input, consumed by both the oracle
+and the HIP path):
+
+* energy lattice: ``n_e`` points uniform in ln E over [e_lo, e_hi];
+* ``sigma[t, i]``: total inelastic cross section of element t at E_i, barn;
+  values between lattice points are linear in the lattice coordinate;
+* ``u_icdf[t, i, j]``: inverse CDF of the energy-loss fraction u at
+  U_j = j/(n_u-1); a sample is the bilinear interpolation at (E, U);
+* ``kalbach_r[t, i, j]``, ``kalbach_a[t, i, j]``: r and a at (E_i, u_j) with
+  u_j = j/(n_u-1); bilinear interpolation at (E, u).
+
+Hydrogen has no inelastic channel below the pion threshold, so it gets no
+table.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Sequence
+
+import numpy as np
+
+# nuclear radius parameter of the geometric placeholder cross section, fm
+_R0_FM = 1.2
+# placeholder reaction threshold, MeV
+_E_THRESH = 10.0
+
+
+@dataclass(frozen=True)
+class EnergyLattice:
+    n: int = 1024
+    e_lo: float = 0.05
+    e_hi: float = 260.0
+
+    def energies(self) -> np.ndarray:
+        return np.exp(np.linspace(np.log(self.e_lo), np.log(self.e_hi), self.n))
+
+
+@dataclass
+class NuclearTables:
+    lattice: EnergyLattice
+    n_u: int
+    Z: np.ndarray          # int32 [n_tab]
+    A: np.ndarray          # float64 [n_tab], g/mol (for reference only)
+    sigma: np.ndarray      # float64 [n_tab, n_e] barn
+    u_icdf: np.ndarray     # float64 [n_tab, n_e, n_u]
+    kalbach_r: np.ndarray  # float64 [n_tab, n_e, n_u]
+    kalbach_a: np.ndarray  # float64 [n_tab, n_e, n_u]
+
+
+def placeholder_nuclear_tables(elements: Sequence[int], atomic_weights: Sequence[float],
+                               lattice: EnergyLattice = EnergyLattice(),
+                               n_u: int = 33) -> NuclearTables:
+    """Write placeholder inelastic tables for every element with Z > 1.
+
+    sigma(E) = pi r0^2 A^(2/3) (1 - E_th/E) above E_th = 10 MeV (geometric
+    size with a threshold factor).  The energy-loss fraction u follows a
+    truncated exponential on [0.02, 1] with an E-dependent scale
+    lam(E) = 0.15 + 0.15 E/250 MeV.  Kalbach r = 0.1 + 0.5 (1 - u),
+    a = 0.5 + 2 (1 - u) + E/200 MeV (more forward for small losses).
+    """
+    E = lattice.energies()
+    zs, As = [], []
+    for z, a in zip(elements, atomic_weights):
+        if int(z) > 1 and int(z) not in zs:
+            zs.append(int(z))
+            As.append(float(a))
+    n_t = len(zs)
+    sigma = np.zeros((n_t, lattice.n))
+    u_icdf = np.zeros((n_t, lattice.n, n_u))
+    kr = np.zeros((n_t, lattice.n, n_u))
+    ka = np.zeros((n_t, lattice.n, n_u))
+    U = np.linspace(0.0, 1.0, n_u)
+    u_min = 0.02
+    for t, a in enumerate(As):
+        geo_b = np.pi * _R0_FM ** 2 * a ** (2.0 / 3.0) * 1e-2   # fm^2 -> barn
+        sigma[t] = np.where(E > _E_THRESH, geo_b * (1.0 - _E_THRESH / E), 0.0)
+        lam = 0.15 + 0.15 * E / 250.0
+        span = 1.0 - np.exp(-(1.0 - u_min) / lam)
+        u_icdf[t] = u_min - lam[:, None] * np.log1p(-U[None, :] * span[:, None])
+        u_icdf[t, :, -1] = 1.0
+        kr[t] = 0.1 + 0.5 * (1.0 - U)[None, :] + 0.0 * E[:, None]
+        ka[t] = 0.5 + 2.0 * (1.0 - U)[None, :] + E[:, None] / 200.0
+    return NuclearTables(lattice=lattice, n_u=n_u, Z=np.array(zs, dtype=np.int32),
+                         A=np.array(As), sigma=sigma, u_icdf=u_icdf,
+                         kalbach_r=kr, kalbach_a=ka)
