@@ -1,0 +1,568 @@
+// C ABI of libsde (declared in include/sde.h): validation, device tables,
+// plans (persistent launch + hipGraph replay), dose conversion and gamma.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sde.h"
+#include "sde_host.hpp"
+#include "sde_internal.hpp"
+
+using namespace sde;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct State {
+    bool ready = false;
+    HostTables host;
+    float4* hot = nullptr;
+    double2* rg64 = nullptr;
+    MatDev* mats = nullptr;
+    float *nuc_sigma = nullptr, *nuc_u = nullptr, *nuc_r = nullptr, *nuc_a = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t own = nullptr;   // for graph capture when the caller uses the null stream
+    int n_cu = 0;
+    size_t max_lds = 0;
+};
+State g;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? SDE_E_NOMEM : SDE_E_HIP,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void release_tables() {
+    dfree(g.hot);
+    dfree(g.rg64);
+    dfree(g.mats);
+    dfree(g.nuc_sigma);
+    dfree(g.nuc_u);
+    dfree(g.nuc_r);
+    dfree(g.nuc_a);
+    g.ready = false;
+}
+
+template <class T>
+int upload(T** dst, const std::vector<T>& src) {
+    HIP_TRY(hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1)));
+    HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return SDE_OK;
+}
+
+int device_info() {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int cu = 0, lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    g.n_cu = cu;
+    g.max_lds = (size_t)lds;
+    HIP_TRY(transport_kernel_attributes(g.max_lds));
+    return SDE_OK;
+}
+
+hipStream_t cur_stream() { return g.stream; }
+
+}  // namespace
+
+struct sde_plan {
+    KParams kp{};
+    int grid = 0, block = 0;
+    size_t lds = 0;
+    uint2* vox = nullptr;
+    unsigned long long* tally = nullptr;
+    unsigned long long* ledger = nullptr;
+    unsigned long long* counter = nullptr;
+    unsigned int* bad = nullptr;
+    SpotDev* spots = nullptr;
+    unsigned long long* prefix = nullptr;
+    size_t nvox = 0;
+    double scale = 1.0;
+    double voxel_cm3 = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double* graph_dose = nullptr;
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+namespace {
+
+void plan_free(sde_plan* p) {
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    dfree(p->vox);
+    dfree(p->tally);
+    dfree(p->ledger);
+    dfree(p->counter);
+    dfree(p->bad);
+    dfree(p->spots);
+    dfree(p->prefix);
+    delete p;
+}
+
+// Enqueue reset, transport and (optionally) conversion on stream s; with
+// timing, HIP events bracket the transport launch.
+int plan_enqueue(sde_plan* p, double* dose_out, hipStream_t s, bool timing = false) {
+    HIP_TRY(launch_reset(p->tally, p->nvox, p->ledger, p->counter, s));
+    if (timing) {
+        if (!p->ev0) HIP_TRY(hipEventCreate(&p->ev0));
+        if (!p->ev1) HIP_TRY(hipEventCreate(&p->ev1));
+        HIP_TRY(hipEventRecord(p->ev0, s));
+    }
+    HIP_TRY(launch_transport(p->kp, p->grid, p->block, p->lds, s));
+    if (timing) {
+        HIP_TRY(hipEventRecord(p->ev1, s));
+        p->timed = true;
+    }
+    if (dose_out)
+        HIP_TRY(launch_convert(p->tally, p->vox, p->nvox, 1.0 / p->scale, p->voxel_cm3, dose_out,
+                               p->ledger, s));
+    return SDE_OK;
+}
+
+int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories, uint64_t seed,
+              const sde_launch* launch, sde_plan** out) {
+    if (!g.ready) return fail(SDE_E_STATE, "sde_init_materials has not been called");
+    if (!beam || beam->n_spots < 1 || !beam->spots) return fail(SDE_E_INVALID, "empty beam");
+    if (!ph || ph->nx < 1 || ph->ny < 1 || ph->nz < 1 || !(ph->dx_cm > 0) || !(ph->dy_cm > 0) ||
+        !(ph->dz_cm > 0) || !ph->material_id || !ph->density)
+        return fail(SDE_E_INVALID, "invalid phantom");
+    const size_t nvox = (size_t)ph->nx * ph->ny * ph->nz;
+    if (nvox >= (1ull << 31)) return fail(SDE_E_INVALID, "phantom too large (>= 2^31 voxels)");
+    const HostTables& T = g.host;
+    const sde_physics_params& pp = T.params;
+
+    // history counts
+    const int ns = beam->n_spots;
+    std::vector<uint64_t> counts(ns);
+    uint64_t total = 0;
+    for (int i = 0; i < ns; ++i) {
+        counts[i] = beam->spots[i].n_histories;
+        total += counts[i];
+    }
+    if (n_histories) {
+        if (ns == 1) {
+            counts[0] = n_histories;
+            total = n_histories;
+        } else if (n_histories != total) {
+            return fail(SDE_E_INVALID, "n_histories differs from the sum of the spot counts");
+        }
+    }
+    if (total == 0) return fail(SDE_E_INVALID, "no histories");
+
+    // energy range and fixed-point scale
+    double emax_sum = 0;
+    for (int i = 0; i < ns; ++i) {
+        const sde_spot& s = beam->spots[i];
+        if (!(s.E_MeV > 0) || !(s.sigmaE_rel >= 0) || !(s.sigma_xy_cm >= 0) || !(s.weight >= 0) ||
+            !std::isfinite(s.x_cm) || !std::isfinite(s.y_cm))
+            return fail(SDE_E_INVALID, "invalid spot " + std::to_string(i));
+        if (counts[i] == 0) continue;
+        const double ehi = s.E_MeV * (1.0 + kBoxMullerMax * s.sigmaE_rel);
+        if (ehi > pp.e_max_MeV)
+            return fail(SDE_E_RANGE, "spot " + std::to_string(i) + " energy exceeds e_max");
+        if (s.E_MeV * (1.0 - kBoxMullerMax * s.sigmaE_rel) < 0.0)
+            return fail(SDE_E_RANGE, "spot " + std::to_string(i) + " energy spread reaches zero");
+        emax_sum += s.weight * ehi;
+    }
+    if (!(emax_sum > 0) || !std::isfinite(emax_sum))
+        return fail(SDE_E_INVALID, "total weighted energy must be positive and finite");
+    const int k = (int)std::floor(62.0 - std::log2(emax_sum));
+    if (k < -60 || k > 100) return fail(SDE_E_OVERFLOW, "fixed-point scale out of range");
+    const double scale = std::ldexp(1.0, k);
+
+    sde_plan* p = new sde_plan();
+    p->nvox = nvox;
+    p->scale = scale;
+    p->voxel_cm3 = ph->dx_cm * ph->dy_cm * ph->dz_cm;
+
+    std::vector<SpotDev> sd(ns);
+    std::vector<unsigned long long> pre(ns + 1, 0);
+    for (int i = 0; i < ns; ++i) {
+        const sde_spot& s = beam->spots[i];
+        sd[i] = SpotDev{(float)s.E_MeV, (float)s.sigmaE_rel, (float)s.x_cm, (float)s.y_cm,
+                        (float)s.sigma_xy_cm,
+                        counts[i] ? (float)(s.weight / (double)counts[i] * scale) : 0.f, 0.f, 0.f};
+        pre[i + 1] = pre[i] + counts[i];
+    }
+    auto bail = [&](int rc) {
+        plan_free(p);
+        return rc;
+    };
+    int rc;
+    if ((rc = upload(&p->spots, sd)) != SDE_OK) return bail(rc);
+    if ((rc = upload(&p->prefix, pre)) != SDE_OK) return bail(rc);
+    hipError_t e;
+    if ((e = hipMalloc((void**)&p->vox, sizeof(uint2) * nvox)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->tally, sizeof(unsigned long long) * nvox)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->ledger, sizeof(unsigned long long) * kLedgerN)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->counter, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc((void**)&p->bad, sizeof(unsigned int))) != hipSuccess) {
+        plan_free(p);
+        return fail(SDE_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
+    hipStream_t s = cur_stream();
+    if ((e = hipMemsetAsync(p->bad, 0, sizeof(unsigned int), s)) != hipSuccess ||
+        (e = launch_pack_phantom(ph->material_id, ph->density, p->vox, nvox, T.n_mat, p->bad, s)) !=
+            hipSuccess) {
+        plan_free(p);
+        return fail(SDE_E_HIP, std::string("phantom packing failed: ") + hipGetErrorString(e));
+    }
+    unsigned int bad = 0;
+    if ((e = hipMemcpyAsync(&bad, p->bad, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        plan_free(p);
+        return fail(SDE_E_HIP, std::string("phantom check failed: ") + hipGetErrorString(e));
+    }
+    if (bad) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, std::to_string(bad) +
+                                       " voxels have a material id >= n_mats or a density that "
+                                       "is not finite and positive");
+    }
+
+    // launch configuration
+    sde_launch L{};
+    if (launch) L = *launch;
+    int block = L.block ? L.block : 512;
+    if (block < 64 || block > 1024 || block % 64) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, "block must be a multiple of 64 in 64..1024");
+    }
+    int grid = L.grid ? L.grid : 2 * std::max(1, g.n_cu);
+    if (grid < 1) grid = 1;
+    int refill = L.refill ? L.refill : 1;
+    if (refill < 1 || refill > 64) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, "refill must be in 1..64");
+    }
+    const int tnx = std::max(0, L.tile_nx), tny = std::max(0, L.tile_ny),
+              tnz = std::max(0, L.tile_nz);
+    const bool tile_on = tnx > 0 && tny > 0 && tnz > 0;
+    if (tile_on && (L.tile_x0 < 0 || L.tile_y0 < 0 || L.tile_z0 < 0 ||
+                    L.tile_x0 + tnx > ph->nx || L.tile_y0 + tny > ph->ny ||
+                    L.tile_z0 + tnz > ph->nz)) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, "LDS tile outside the phantom");
+    }
+    const size_t tab_bytes = (size_t)T.n_mat * T.n_e * sizeof(float4);
+    const size_t tile_bytes = tile_on ? (size_t)tnx * tny * tnz * 8 : 0;
+    if (tab_bytes + tile_bytes > g.max_lds) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, "tables and tally tile exceed the LDS per workgroup (" +
+                                       std::to_string(tab_bytes + tile_bytes) + " > " +
+                                       std::to_string(g.max_lds) + " bytes)");
+    }
+    p->grid = grid;
+    p->block = block;
+    p->lds = tab_bytes + tile_bytes;
+
+    KParams& kp = p->kp;
+    kp.hot = g.hot;
+    kp.rg64 = g.rg64;
+    kp.mats = g.mats;
+    kp.nuc_sigma = g.nuc_sigma;
+    kp.nuc_u = g.nuc_u;
+    kp.nuc_r = g.nuc_r;
+    kp.nuc_a = g.nuc_a;
+    kp.n_mat = T.n_mat;
+    kp.n_e = T.n_e;
+    kp.n_u = T.n_u;
+    kp.n_tab = T.n_tab;
+    kp.ln_e_lo = (float)T.ln_e_lo;
+    kp.inv_dln = (float)(1.0 / T.dln);
+    kp.ln_e_lo_d = T.ln_e_lo;
+    kp.inv_dln_d = 1.0 / T.dln;
+    kp.step_d = pp.step_cm;
+    kp.step = (float)pp.step_cm;
+    kp.half_step = (float)(0.5 * pp.step_cm);
+    kp.sqrt_step = (float)std::sqrt(pp.step_cm);
+    kp.e_min = (float)pp.e_min_MeV;
+    kp.c_bethe = (float)kBethe;
+    kp.c_strag = (float)T.c_strag;
+    kp.ruth_T = (float)T.ruth_T;
+    kp.mott_lo = (float)T.mott_lo;
+    kp.mott_hi = (float)T.mott_hi;
+    kp.mott_D0 = (float)T.mott_D0;
+    kp.mott_Lhi = (float)T.mott_Lhi;
+    kp.mott_Llo = (float)T.mott_Llo;
+    kp.flags = pp.flags;
+    kp.max_steps = pp.max_steps;
+    kp.vox = p->vox;
+    kp.nx = ph->nx;
+    kp.ny = ph->ny;
+    kp.nz = ph->nz;
+    const double d[3] = {ph->dx_cm, ph->dy_cm, ph->dz_cm};
+    const int nn[3] = {ph->nx, ph->ny, ph->nz};
+    for (int a = 0; a < 3; ++a) {
+        kp.lo[a] = (float)ph->origin_cm[a];
+        kp.hi[a] = (float)(ph->origin_cm[a] + nn[a] * d[a]);
+        kp.inv_d[a] = (float)(1.0 / d[a]);
+    }
+    kp.spots = p->spots;
+    kp.prefix = p->prefix;
+    kp.n_spots = ns;
+    kp.n_hist = total;
+    kp.seed = seed;
+    kp.tally = p->tally;
+    kp.ledger = p->ledger;
+    kp.counter = p->counter;
+    kp.refill = refill;
+    if (tile_on) {
+        kp.tile_nx = tnx;
+        kp.tile_ny = tny;
+        kp.tile_nz = tnz;
+        kp.tile_x0 = L.tile_x0;
+        kp.tile_y0 = L.tile_y0;
+        kp.tile_z0 = L.tile_z0;
+    }
+    *out = p;
+    return SDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sde_init_materials(const sde_material_desc* mats, int n_mats, const sde_physics_params* params,
+                       const sde_nuclear_tables* nuclear) {
+    g_err.clear();
+    HostTables T;
+    std::string err;
+    const int rc = build_host_tables(mats, n_mats, params, nuclear, &T, &err);
+    if (rc != SDE_OK) return fail(rc, err);
+    release_tables();
+    if (int r = device_info()) return r;
+    int r;
+    if ((r = upload(&g.hot, T.hot)) || (r = upload(&g.rg64, T.rg64)) ||
+        (r = upload(&g.mats, T.mats)) || (r = upload(&g.nuc_sigma, T.nuc_sigma)) ||
+        (r = upload(&g.nuc_u, T.nuc_u)) || (r = upload(&g.nuc_r, T.nuc_r)) ||
+        (r = upload(&g.nuc_a, T.nuc_a))) {
+        release_tables();
+        return r;
+    }
+    g.host = std::move(T);
+    g.ready = true;
+    return SDE_OK;
+}
+
+int sde_set_stream(void* hip_stream) {
+    g.stream = (hipStream_t)hip_stream;
+    return SDE_OK;
+}
+
+int sde_plan_create(const sde_beam* beam, const sde_phantom* phantom, uint64_t n_histories,
+                    uint64_t seed, const sde_launch* launch, sde_plan** plan_out) {
+    g_err.clear();
+    if (!plan_out) return fail(SDE_E_INVALID, "plan_out is NULL");
+    *plan_out = nullptr;
+    return make_plan(beam, phantom, n_histories, seed, launch, plan_out);
+}
+
+int sde_plan_execute(sde_plan* p, double* dose_out, int use_graph) {
+    g_err.clear();
+    if (!p) return fail(SDE_E_INVALID, "plan is NULL");
+    if (!use_graph) return plan_enqueue(p, dose_out, cur_stream(), true);
+    hipStream_t s = cur_stream();
+    if (!s) {
+        if (!g.own) HIP_TRY(hipStreamCreate(&g.own));
+        s = g.own;
+    }
+    if (!p->gexec || p->graph_dose != dose_out || p->graph_stream != s) {
+        if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int rc = plan_enqueue(p, dose_out, s);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &gr);
+        if (rc != SDE_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(SDE_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+        p->graph = gr;
+        HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+        p->graph_dose = dose_out;
+        p->graph_stream = s;
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, s));
+    if (s != cur_stream()) HIP_TRY(hipStreamSynchronize(s));
+    return SDE_OK;
+}
+
+int sde_plan_results(sde_plan* p, int64_t* tally_out, int64_t* ledger_out, double* scale_out) {
+    g_err.clear();
+    if (!p) return fail(SDE_E_INVALID, "plan is NULL");
+    if (scale_out) *scale_out = p->scale;
+    hipStream_t s = cur_stream();
+    if (p->graph_stream && p->graph_stream != s) HIP_TRY(hipStreamSynchronize(p->graph_stream));
+    if (tally_out)
+        HIP_TRY(hipMemcpyAsync(tally_out, p->tally, sizeof(int64_t) * p->nvox,
+                               hipMemcpyDeviceToDevice, s));
+    if (ledger_out)
+        HIP_TRY(hipMemcpyAsync(ledger_out, p->ledger, sizeof(int64_t) * kLedgerN,
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SDE_OK;
+}
+
+int sde_plan_kernel_ms(sde_plan* p, float* ms_out) {
+    g_err.clear();
+    if (!p || !ms_out) return fail(SDE_E_INVALID, "plan or ms_out is NULL");
+    if (!p->timed) return fail(SDE_E_STATE, "no timed execution");
+    HIP_TRY(hipEventSynchronize(p->ev1));
+    HIP_TRY(hipEventElapsedTime(ms_out, p->ev0, p->ev1));
+    return SDE_OK;
+}
+
+int sde_plan_destroy(sde_plan* p) {
+    g_err.clear();
+    if (p) {
+        (void)hipStreamSynchronize(cur_stream());
+        plan_free(p);
+    }
+    return SDE_OK;
+}
+
+int sde_transport_ex(const sde_beam* beam, const sde_phantom* phantom, uint64_t n_histories,
+                     uint64_t seed, double* dose_out, int64_t* tally_out, int64_t* ledger_out,
+                     double* scale_out, const sde_launch* launch) {
+    g_err.clear();
+    sde_plan* p = nullptr;
+    int rc = make_plan(beam, phantom, n_histories, seed, launch, &p);
+    if (rc != SDE_OK) return rc;
+    hipStream_t s = cur_stream();
+    rc = plan_enqueue(p, dose_out, s);
+    if (rc == SDE_OK && !dose_out && ledger_out) {
+        // the deposited slot is summed by the conversion pass; run it into a scratch dose
+        double* tmp = nullptr;
+        if (hipMalloc((void**)&tmp, sizeof(double) * p->nvox) != hipSuccess) {
+            plan_free(p);
+            return fail(SDE_E_NOMEM, "scratch dose allocation failed");
+        }
+        const hipError_t e = launch_convert(p->tally, p->vox, p->nvox, 1.0 / p->scale,
+                                            p->voxel_cm3, tmp, p->ledger, s);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) rc = fail(SDE_E_HIP, hipGetErrorString(e));
+    }
+    if (rc == SDE_OK && tally_out) {
+        const hipError_t e = hipMemcpyAsync(tally_out, p->tally, sizeof(int64_t) * p->nvox,
+                                            hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = fail(SDE_E_HIP, hipGetErrorString(e));
+    }
+    if (rc == SDE_OK && ledger_out) {
+        const hipError_t e = hipMemcpyAsync(ledger_out, p->ledger, sizeof(int64_t) * kLedgerN,
+                                            hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) rc = fail(SDE_E_HIP, hipGetErrorString(e));
+    }
+    if (scale_out) *scale_out = p->scale;
+    const hipError_t e = hipStreamSynchronize(s);
+    if (rc == SDE_OK && e != hipSuccess) rc = fail(SDE_E_HIP, hipGetErrorString(e));
+    plan_free(p);
+    return rc;
+}
+
+int sde_transport(const sde_beam* beam, const sde_phantom* phantom, uint64_t n_histories,
+                  uint64_t seed, double* dose_out) {
+    if (!dose_out) return fail(SDE_E_INVALID, "dose_out is NULL");
+    return sde_transport_ex(beam, phantom, n_histories, seed, dose_out, nullptr, nullptr, nullptr,
+                            nullptr);
+}
+
+int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
+              double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int interp,
+              int local, int64_t* counts_out) {
+    g_err.clear();
+    if (!ref || !ev || !counts_out || nx < 1 || ny < 1 || nz < 1 || !(dx_cm > 0) ||
+        !(dy_cm > 0) || !(dz_cm > 0) || !(dd > 0) || !(dta_cm > 0) || !(thresh >= 0) ||
+        interp < 1 || interp > 50)
+        return fail(SDE_E_INVALID, "invalid gamma arguments");
+    // integer offsets on the dta/interp lattice within dta, nearest first
+    std::vector<int4> off;
+    const double st = dta_cm / interp;
+    for (int a = -interp; a <= interp; ++a)
+        for (int b = -interp; b <= interp; ++b)
+            for (int c = -interp; c <= interp; ++c) {
+                const double ox = a * st, oy = b * st, oz = c * st;
+                if (ox * ox + oy * oy + oz * oz <= dta_cm * dta_cm * (1.0 + 1e-12))
+                    off.push_back(make_int4(a, b, c, a * a + b * b + c * c));
+            }
+    std::stable_sort(off.begin(), off.end(),
+                     [](const int4& u, const int4& v) { return u.w < v.w; });
+    const size_t nvox = (size_t)nx * ny * nz;
+    hipStream_t s = cur_stream();
+    int4* doff = nullptr;
+    unsigned long long* buf = nullptr;
+    HIP_TRY(hipMalloc((void**)&doff, sizeof(int4) * off.size()));
+    HIP_TRY(hipMalloc((void**)&buf, sizeof(unsigned long long) * 3));
+    int rc = SDE_OK;
+    unsigned long long host[3] = {0, 0, 0};
+    do {
+        hipError_t e;
+        if ((e = hipMemcpyAsync(doff, off.data(), sizeof(int4) * off.size(),
+                                hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemsetAsync(buf, 0, sizeof(unsigned long long) * 3, s)) != hipSuccess ||
+            (e = launch_max(ref, nvox, buf + 2, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(host, buf, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess) {
+            rc = fail(SDE_E_HIP, hipGetErrorString(e));
+            break;
+        }
+        double mx;
+        std::memcpy(&mx, &host[2], sizeof mx);
+        const double dvec[3] = {dx_cm, dy_cm, dz_cm};
+        if ((e = launch_gamma(ref, ev, nx, ny, nz, doff, (int)off.size(), st, dd, dta_cm,
+                              thresh * mx, mx, local, dvec, buf, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(host, buf, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
+                                s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess) {
+            rc = fail(SDE_E_HIP, hipGetErrorString(e));
+            break;
+        }
+        counts_out[0] = (int64_t)host[0];
+        counts_out[1] = (int64_t)host[1];
+    } while (0);
+    (void)hipFree(doff);
+    (void)hipFree(buf);
+    return rc;
+}
+
+void sde_free(void) {
+    release_tables();
+    if (g.own) {
+        (void)hipStreamDestroy(g.own);
+        g.own = nullptr;
+    }
+}
+
+const char* sde_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal layouts shared by the host side of libsde and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sde {
+
+constexpr int kMaxElem = 16;
+constexpr int kMaxMat = 8;
+constexpr int kLedgerN = 8;
+
+// Physical constants (CODATA 2018), MeV based.
+constexpr double kMp = 938.27208816;       // proton rest energy
+constexpr double kMe = 0.51099895000;      // electron rest energy
+constexpr double kAlpha = 7.2973525693e-3;
+constexpr double kNa = 6.02214076e23;
+constexpr double kHbarcFm = 197.3269804;   // MeV fm
+constexpr double kAmu = 931.49410242;      // MeV
+constexpr double kMevToJ = 1.602176634e-13;
+constexpr double kBethe = 0.3072;          // Eq. (bethbloch) constant, MeV cm^2/mol
+constexpr double kBoxMullerMax = 5.77;     // |Z| bound of a 23-bit Box-Muller draw
+
+// One element of a medium, read only inside the (rare) jump branch.
+struct ElemDev {
+    float Z;
+    float m2;        // target rest energy A * amu, MeV
+    float el_coef;   // elastic rate = rho * el_coef / E^2 (times the Mott bracket for H)
+    float ne_coef;   // inelastic rate = rho * ne_coef * sigma_barn(E)
+    int is_h;        // hydrogen: Mott (identical-particle) cross section
+    int tab;         // row of the inelastic tables, -1 if none
+    int pad0, pad1;
+};
+
+struct MatDev {
+    float zoa;             // sum_i w_i Z_i / A_i
+    float log_pre;         // ln(2 m_e / I) - 2 ln(m_p): Bethe log = log_pre + ln(p^2) - beta^2
+    int n_elem;
+    int pad;
+    ElemDev el[kMaxElem];
+};
+
+// Per-spot source data on the device.  wscale = weight / n * 2^k.
+struct SpotDev {
+    float E, sigmaE, x, y, sxy, wscale, pad0, pad1;
+};
+
+// Everything the transport kernel reads; passed by value.
+struct KParams {
+    // tables
+    const float4* hot;         // [n_mat][n_e] {A1, A2, rate/rho, Rg (FP32)}
+    const double2* rg64;       // [n_mat][n_e] {Rg, dRg/dt} for the FP64 end of range
+    const MatDev* mats;        // [n_mat]
+    const float* nuc_sigma;    // [n_tab][n_e] barn
+    const float* nuc_u;        // [n_tab][n_e][n_u]
+    const float* nuc_r;
+    const float* nuc_a;
+    int n_mat, n_e, n_u, n_tab;
+    float ln_e_lo, inv_dln;
+    double ln_e_lo_d, inv_dln_d;
+    // scheme
+    double step_d;
+    float step, half_step, sqrt_step, e_min;
+    float c_bethe, c_strag;          // 0.3072, 4 pi N_A (alpha hbar c)^2
+    float ruth_T;                    // 1 / (1 - cos theta_cut)
+    float mott_lo, mott_hi;          // CM cosine limits of hydrogen elastic
+    float mott_D0, mott_Lhi, mott_Llo;
+    unsigned flags;
+    int pad0;
+    long long max_steps;
+    // phantom
+    const uint2* vox;                // [nz][ny][nx] {density bits, material}
+    int nx, ny, nz, pad1;
+    float lo[3], hi[3], inv_d[3], pad2;
+    // beam
+    const SpotDev* spots;
+    const unsigned long long* prefix;   // [n_spots + 1] cumulative history counts
+    int n_spots, pad3;
+    unsigned long long n_hist;
+    unsigned long long seed;
+    // outputs and work queue
+    unsigned long long* tally;       // [nvox] fixed point
+    unsigned long long* ledger;      // [kLedgerN]
+    unsigned long long* counter;     // next history
+    int refill;
+    int tile_nx, tile_ny, tile_nz, tile_x0, tile_y0, tile_z0, pad4;
+};
+
+// Launchers (sde_kernels.hip)
+hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox,
+                               int n_mat, unsigned int* bad, hipStream_t s);
+hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long long* ledger,
+                        unsigned long long* counter, hipStream_t s);
+hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
+                            hipStream_t s);
+hipError_t launch_convert(const unsigned long long* tally, const uint2* vox, size_t nvox,
+                          double inv_scale, double voxel_cm3, double* dose,
+                          unsigned long long* ledger, hipStream_t s);
+hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
+                        const int4* offsets, int n_off, double step, double dd, double dta,
+                        double thr_abs, double max_ref, int local, const double* d,
+                        unsigned long long* counts, hipStream_t s);
+hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s);
+hipError_t transport_kernel_attributes(size_t lds_bytes);
+
+}  // namespace sde

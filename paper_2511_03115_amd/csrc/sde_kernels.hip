@@ -1,0 +1,673 @@
+// HIP kernels of libsde for gfx950 (CDNA4, wave64).
+//
+// k_transport: one lane per proton history in a persistent loop.  Lanes whose
+// proton has stopped or left the phantom claim new history indices from a
+// global counter, a wave at a time (one atomic per refill).  Each lane steps
+// its history with the explicit Euler-Maruyama scheme of Eq. (VSDE):
+// coefficients at Y_n, continuous loss with clamped straggling, small-angle
+// diffusion, then a Poisson-clocked jump drawn from the mixture Eq. (Npi).
+// Randomness is Philox4x32-10 keyed by the seed with counter
+// (history, step, block), so a history's arithmetic does not depend on which
+// lane, wave or launch runs it.  Energy is scored as int64 fixed point with
+// integer atomics (an LDS tile first when one is configured), so the tally
+// is the same for every launch shape.
+#include <hip/hip_runtime.h>
+
+#include "sde_internal.hpp"
+
+namespace sde {
+namespace {
+
+constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelastic = 16u,
+                   kEor = 32u;
+
+constexpr float kMpF = (float)kMp;
+constexpr float kAlphaF = (float)kAlpha;
+constexpr float kLn2 = 0.69314718055994530942f;
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 32x32->64 products, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// (2k+1) 2^-24 from the top 23 bits: exact in FP32, never 0 or 1.
+__device__ __forceinline__ float u_hi(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+// Same from the 23 low bits that u_hi leaves unused in three words.
+__device__ __forceinline__ float u_lo(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t k = (a & 0x1FFu) | ((b & 0x1FFu) << 9) | ((c & 0x1Fu) << 18);
+    return ((float)k + 0.5f) * 0x1p-23f;
+}
+
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// sin and cos of 2 pi u for u in (0, 1): the hardware takes revolutions.
+__device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf(u); }
+__device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
+
+// cos and sin of a polar angle given its square: Taylor in theta^2 for small
+// angles (where the hardware sine would lose relative accuracy), the library
+// otherwise.
+__device__ __forceinline__ void polar_cs(float th2, float& c, float& s) {
+    if (th2 < 0.25f) {
+        const float x = th2;
+        c = fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, -2.7557319e-7f, 2.4801587e-5f),
+                                         -1.3888889e-3f), 4.1666667e-2f), -0.5f), 1.0f);
+        const float sc = fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, -2.5052108e-8f, 2.7557319e-6f),
+                                              -1.9841270e-4f), 8.3333333e-3f),
+                                      -1.6666667e-1f), 1.0f);
+        s = fsqrt(x) * sc;
+    } else {
+        sincosf(sqrtf(th2), &s, &c);
+    }
+}
+
+// Turn unit d by (ct, st) about itself, azimuth (cp, sp) from b1 of the
+// Duff et al. (JCGT 2017) orthonormal basis of d.
+__device__ __forceinline__ void turn(float& dx, float& dy, float& dz, float ct, float st,
+                                     float cp, float sp) {
+    const float sg = copysignf(1.0f, dz);
+    const float a = -1.0f / (sg + dz);
+    const float b = dx * dy * a;
+    const float b1x = 1.0f + sg * dx * dx * a, b1y = sg * b, b1z = -sg * dx;
+    const float b2x = b, b2y = sg + dy * dy * a, b2z = -dy;
+    const float ex = cp * b1x + sp * b2x, ey = cp * b1y + sp * b2y, ez = cp * b1z + sp * b2z;
+    const float nx = ct * dx + st * ex, ny = ct * dy + st * ey, nz = ct * dz + st * ez;
+    dx = nx;
+    dy = ny;
+    dz = nz;
+}
+
+__device__ __forceinline__ bool inside(const KParams& P, float x, float y, float z) {
+    return x >= P.lo[0] && x <= P.hi[0] && y >= P.lo[1] && y <= P.hi[1] && z >= P.lo[2] &&
+           z <= P.hi[2];
+}
+
+// Voxel of an inside point; the upper face belongs to the last voxel.
+__device__ __forceinline__ void voxel3(const KParams& P, float x, float y, float z, int& ix,
+                                       int& iy, int& iz) {
+    ix = min((int)((x - P.lo[0]) * P.inv_d[0]), P.nx - 1);
+    iy = min((int)((y - P.lo[1]) * P.inv_d[1]), P.ny - 1);
+    iz = min((int)((z - P.lo[2]) * P.inv_d[2]), P.nz - 1);
+}
+
+__device__ __forceinline__ long long fixp(float e, float wsc) {
+    return (long long)rintf(e * wsc);
+}
+
+// Score energy e at point (x,y,z): LDS tile, global tally, or escaped.
+__device__ __forceinline__ void score(const KParams& P, unsigned long long* tile, float x,
+                                      float y, float z, float e, float wsc, long long& esc) {
+    const long long q = fixp(e, wsc);
+    if (!inside(P, x, y, z)) {
+        esc += q;
+        return;
+    }
+    if (q == 0) return;
+    int ix, iy, iz;
+    voxel3(P, x, y, z, ix, iy, iz);
+    const unsigned tx = (unsigned)(ix - P.tile_x0), ty = (unsigned)(iy - P.tile_y0),
+                   tz = (unsigned)(iz - P.tile_z0);
+    if (tx < (unsigned)P.tile_nx && ty < (unsigned)P.tile_ny && tz < (unsigned)P.tile_nz) {
+        atomicAdd(&tile[(tz * P.tile_ny + ty) * P.tile_nx + tx], (unsigned long long)q);
+    } else {
+        const size_t v = ((size_t)iz * P.ny + iy) * P.nx + ix;
+        atomicAdd(&P.tally[v], (unsigned long long)q);
+    }
+}
+
+// Hydrogen (Mott) antiderivative in units of (eta/k)^2, Appendix A.2 with
+// sin(eta ln((1+mu)/(1-mu))).
+__device__ __forceinline__ float mott_G(float eta, float mu) {
+    return 2.0f * mu / ((1.0f - mu) * (1.0f + mu)) -
+           sinf(eta * logf((1.0f + mu) / (1.0f - mu))) / (2.0f * eta);
+}
+
+__device__ __forceinline__ float lerp_row(const float* row, int i, float f) {
+    return fmaf(f, row[i + 1] - row[i], row[i]);
+}
+
+// Bilinear value of a [n_e][n_u] table at lattice (i, f) and x in [0, 1].
+__device__ __forceinline__ float table_eu(const float* tab, int n_u, int i, float f, float x) {
+    float tu = fminf(fmaxf(x * (float)(n_u - 1), 0.0f), (float)(n_u - 1));
+    int j = min((int)tu, n_u - 2);
+    const float g = tu - (float)j;
+    const float* r0 = tab + (size_t)i * n_u;
+    const float* r1 = r0 + n_u;
+    const float a = fmaf(g, r0[j + 1] - r0[j], r0[j]);
+    const float b = fmaf(g, r1[j + 1] - r1[j], r1[j]);
+    return fmaf(f, b - a, a);
+}
+
+// One large-angle jump at state energy E in material md (Eq. (Npi)):
+// channel by its rate, CM cosine from its law, CM -> lab by Eq. (cm_to_lab).
+// Returns the loss fraction u (0 for elastic) and the lab (cos, sin) and
+// azimuth (cos, sin) of the turn.
+__device__ __forceinline__ void jump(const KParams& P, const MatDev* md, float E, float rho, int li,
+                                  float lf, uint4 q, float& u_loss, float& jc, float& js,
+                                  float& jcp, float& jsp) {
+    const float inv_e2 = 1.0f / (E * E);
+    const float eta = kAlphaF * sqrtf(kMpF / (2.0f * E));
+    const bool el = (P.flags & kElastic) != 0, ne = (P.flags & kInelastic) != 0;
+    const int nel = md->n_elem;
+    float mott = 0.0f;
+    bool has_h = false;
+    for (int e = 0; e < nel; ++e) has_h |= (md->el[e].is_h != 0);
+    if (el && has_h)
+        mott = P.mott_D0 - (sinf(eta * P.mott_Lhi) - sinf(eta * P.mott_Llo)) / (2.0f * eta);
+    float tot = 0.0f;
+    for (int e = 0; e < nel; ++e) {
+        const ElemDev& d = md->el[e];
+        if (el) tot += rho * d.el_coef * inv_e2 * (d.is_h ? mott : 1.0f);
+        if (ne && d.tab >= 0)
+            tot += rho * d.ne_coef * lerp_row(P.nuc_sigma + (size_t)d.tab * P.n_e, li, lf);
+    }
+    const float target = u_hi(q.x) * tot;
+    float acc = 0.0f;
+    int ce = nel - 1, cin = 0;
+    bool found = false;
+    for (int e = 0; e < nel && !found; ++e) {
+        const ElemDev& d = md->el[e];
+        if (el) {
+            acc += rho * d.el_coef * inv_e2 * (d.is_h ? mott : 1.0f);
+            if (target < acc) { ce = e; cin = 0; found = true; break; }
+        }
+        if (ne && d.tab >= 0) {
+            acc += rho * d.ne_coef * lerp_row(P.nuc_sigma + (size_t)d.tab * P.n_e, li, lf);
+            if (target < acc) { ce = e; cin = 1; found = true; break; }
+        }
+    }
+    if (!found) {   // rounding at the top end: last channel with a rate
+        ce = nel - 1;
+        cin = (ne && md->el[ce].tab >= 0) ? 1 : 0;
+    }
+    const ElemDev& d = md->el[ce];
+    float cmc, cms;
+    u_loss = 0.0f;
+    if (!cin) {
+        const float U = u_hi(q.y);
+        if (d.is_h) {
+            // invert the Mott CDF by bisection on its exact antiderivative
+            float a = P.mott_lo, b = P.mott_hi;
+            const float G0 = mott_G(eta, a), G1 = mott_G(eta, b);
+            const float tgt = fmaf(U, G1 - G0, G0);
+            for (int it = 0; it < 40; ++it) {
+                const float mid = 0.5f * (a + b);
+                if (mid <= a || mid >= b) break;
+                if (mott_G(eta, mid) < tgt) a = mid; else b = mid;
+            }
+            cmc = 0.5f * (a + b);
+            cms = sqrtf(fmaxf(0.0f, (1.0f - cmc) * (1.0f + cmc)));
+        } else {
+            // closed-form Rutherford inverse, in 1 - mu
+            const float om = 1.0f / fmaf(U, P.ruth_T - 0.5f, 0.5f);
+            cmc = 1.0f - om;
+            cms = sqrtf(om * (2.0f - om));
+        }
+    } else {
+        const size_t off = (size_t)d.tab * P.n_e * P.n_u;
+        float u = table_eu(P.nuc_u + off, P.n_u, li, lf, u_hi(q.y));
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        u_loss = u;
+        const float a = table_eu(P.nuc_a + off, P.n_u, li, lf, u);
+        const float r = table_eu(P.nuc_r + off, P.n_u, li, lf, u);
+        const float U = u_hi(q.w);
+        float mu;
+        if (a < 1e-6f) {
+            mu = 2.0f * U - 1.0f;
+        } else {
+            const float sh = sinhf(a), ch = coshf(a);
+            const float C = 2.0f * sh * U + r * ch - sh;
+            mu = logf((C + sqrtf(C * C - r * r + 1.0f)) / (1.0f + r)) / a;
+            mu = fminf(fmaxf(mu, -1.0f), 1.0f);
+        }
+        cmc = mu;
+        cms = sqrtf(fmaxf(0.0f, (1.0f - mu) * (1.0f + mu)));
+    }
+    // CM -> lab (Appendix A.1): K = E, m1 = m_p, E* = u E
+    const float m1 = kMpF, m2 = d.m2;
+    const float E1 = E + m1;
+    const float p1 = sqrtf(E * (E + 2.0f * m1));
+    const float ucm = p1 / (E1 + m2);
+    const float gu = 1.0f / sqrtf((1.0f - ucm) * (1.0f + ucm));
+    const float K2 = E * (1.0f - u_loss);
+    const float E1p = K2 + m1;
+    const float p1p = sqrtf(K2 * (K2 + 2.0f * m1));
+    const float v1c = (p1p - ucm * E1p) / (E1p - ucm * p1p);
+    const float X = gu * (cmc + ucm / v1c), Y = cms;
+    const float rn = 1.0f / sqrtf(X * X + Y * Y);
+    jc = X * rn;
+    js = Y * rn;
+    const float phi = u_hi(q.z);
+    jcp = cos_rev(phi);
+    jsp = sin_rev(phi);
+}
+
+// FP64 residual range R_g(E) (g/cm^2) by cubic Hermite on the lattice.
+__device__ __forceinline__ double range_g64(const KParams& P, int mat, float E) {
+    const double t = (log((double)E) - P.ln_e_lo_d) * P.inv_dln_d;
+    int i = (int)floor(t);
+    i = max(0, min(i, P.n_e - 2));
+    const double s = t - (double)i;
+    const double2 a = P.rg64[(size_t)mat * P.n_e + i];
+    const double2 b = P.rg64[(size_t)mat * P.n_e + i + 1];
+    const double s2 = s * s, s3 = s2 * s;
+    return (2.0 * s3 - 3.0 * s2 + 1.0) * a.x + (s3 - 2.0 * s2 + s) * a.y +
+           (-2.0 * s3 + 3.0 * s2) * b.x + (s3 - s2) * b.y;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ void __launch_bounds__(1024) k_transport(KParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float4* tab = reinterpret_cast<float4*>(smem);
+    const int ntab = P.n_mat * P.n_e;
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = P.hot[i];
+    unsigned long long* tile = reinterpret_cast<unsigned long long*>(smem + (size_t)ntab * 16);
+    const int tile_n = P.tile_nx * P.tile_ny * P.tile_nz;
+    for (int i = threadIdx.x; i < tile_n; i += blockDim.x) tile[i] = 0ull;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
+    bool alive = false;
+    bool more = true;   // wave-uniform: the work counter may still hold histories
+
+    unsigned long long h = 0;
+    unsigned n = 0;
+    float E = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f, ox = 0.0f, oy = 0.0f, oz = 1.0f, wsc = 0.0f;
+    int vcache = -1, mat = 0;
+    float rho = 1.0f;
+    long long l_esc = 0, l_nuc = 0, l_e0 = 0;
+    unsigned l_steps = 0, l_jumps = 0, l_hist = 0;
+
+    for (;;) {
+        const unsigned long long dead = __ballot(!alive);
+        const int ndead = __popcll(dead);
+        if (more && (ndead >= P.refill || ndead == 64)) {
+            const int leader = __ffsll((long long)dead) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)ndead);
+            base = __shfl(base, leader);
+            if (base + (unsigned long long)ndead >= P.n_hist) more = false;
+            if (!alive) {
+                const unsigned rank = __popcll(dead & ((1ull << lane) - 1ull));
+                const unsigned long long hh = base + rank;
+                if (hh < P.n_hist) {
+                    // Source: spot by cumulative count; Box-Muller pairs from
+                    // block (h, 2^32-1, 0): (w0, w1) lateral, (w2, w3) energy.
+                    h = hh;
+                    n = 0;
+                    int lo = 0, hi = P.n_spots - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (P.prefix[mid] <= hh) lo = mid; else hi = mid - 1;
+                    }
+                    const SpotDev sp = P.spots[lo];
+                    const uint4 w = philox((uint32_t)h, (uint32_t)(h >> 32), 0xFFFFFFFFu, 0u, k0, k1);
+                    const float rr = fsqrt(-2.0f * flog(u_hi(w.x)));
+                    const float a1 = u_hi(w.y);
+                    const float z1 = rr * cos_rev(a1), z2 = rr * sin_rev(a1);
+                    const float z3 = fsqrt(-2.0f * flog(u_hi(w.z))) * cos_rev(u_hi(w.w));
+                    E = sp.E * (1.0f + sp.sigmaE * z3);
+                    rx = sp.x + sp.sxy * z1;
+                    ry = sp.y + sp.sxy * z2;
+                    rz = P.lo[2];
+                    ox = 0.0f;
+                    oy = 0.0f;
+                    oz = 1.0f;
+                    wsc = sp.wscale;
+                    vcache = -1;
+                    l_hist++;
+                    l_e0 += fixp(E, wsc);
+                    if (!inside(P, rx, ry, rz)) {
+                        l_esc += fixp(E, wsc);
+                    } else if (E < P.e_min) {
+                        score(P, tile, rx, ry, rz, E, wsc, l_esc);
+                    } else {
+                        alive = true;
+                    }
+                }
+            }
+        }
+        if (!more && __ballot(alive) == 0ull) break;
+        if (!alive) continue;
+
+        // ---------------- one step of Eq. (VSDE) ----------------
+        if ((long long)n >= P.max_steps) {
+            atomicAdd(&P.ledger[4], (unsigned long long)fixp(E, wsc));
+            alive = false;
+            continue;
+        }
+        int ix, iy, iz;
+        voxel3(P, rx, ry, rz, ix, iy, iz);
+        const int v = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx + (unsigned)ix);
+        if (v != vcache) {
+            const uint2 pk = P.vox[v];
+            rho = __uint_as_float(pk.x);
+            mat = (int)pk.y;
+            vcache = v;
+        }
+        const float lnE = flog(E);
+        const float tl = (lnE - P.ln_e_lo) * P.inv_dln;
+        const int li = max(0, min((int)tl, P.n_e - 2));
+        const float lf = tl - (float)li;
+        const float4 ta = tab[mat * P.n_e + li], tb = tab[mat * P.n_e + li + 1];
+        const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
+        const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
+        const float rate = fmaf(lf, tb.z - ta.z, ta.z);
+        const float rg32 = fmaf(lf, tb.w - ta.w, ta.w);
+
+        // End of range: residual range within one step, decided in FP64.
+        if ((P.flags & kEor) && rg32 <= P.step * rho * 1.001f) {
+            const double rres = range_g64(P, mat, E) / (double)rho;
+            if (rres <= P.step_d) {
+                const float hr = (float)(0.5 * rres);
+                score(P, tile, fmaf(ox, hr, rx), fmaf(oy, hr, ry), fmaf(oz, hr, rz), E, wsc,
+                      l_esc);
+                l_steps++;
+                alive = false;
+                continue;
+            }
+        }
+
+        const uint4 w = philox((uint32_t)h, (uint32_t)(h >> 32), n, 0u, k0, k1);
+        const MatDev* md = P.mats + mat;
+
+        // Continuous loss, Eq. (bethbloch) with Bragg additivity; clamped
+        // straggling, Eq. (energystraggling), B_n ~ N(0, Delta).
+        const float p2 = E * (E + 2.0f * kMpF);
+        const float g = E + kMpF;
+        const float b2 = p2 / (g * g);
+        float s1 = 0.0f;
+        if (P.flags & kLoss) {
+            const float L = md->log_pre + flog(p2) - b2;
+            s1 = rho * P.c_bethe * md->zoa * L * (g * g) / p2;
+        }
+        const float a = s1 * P.step;
+        float X = 0.0f;
+        if (P.flags & kStraggle) {
+            const float gm = g * (1.0f / kMpF);
+            const float var = rho * P.c_strag * md->zoa * gm * gm * (1.0f - 0.5f * b2);
+            const float zE = fsqrt(-2.0f * flog(u_hi(w.x))) * cos_rev(u_hi(w.y));
+            X = fminf(fmaxf(fsqrt(var) * P.sqrt_step * zE, -a), a);
+        }
+        const float Ep = fmaxf(E - a + X, 0.0f);
+
+        // Jump: none with probability exp(-Delta sigma), else Eq. (Npi).
+        float u_loss = 0.0f, jc = 1.0f, js = 0.0f, jcp = 1.0f, jsp = 0.0f;
+        bool jumped = false;
+        if (P.flags & (kElastic | kInelastic)) {
+            const float lam = P.step * rho * rate;
+            const float pj = lam < 0.05f
+                ? lam * fmaf(-0.5f * lam, fmaf(-lam * (1.0f / 3.0f), fmaf(-0.25f, lam, 1.0f), 1.0f), 1.0f)
+                : 1.0f - __expf(-lam);
+            if (u_lo(w.x, w.y, w.z) < pj) {
+                const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), n, 1u, k0, k1);
+                jump(P, md, E, rho, li, lf, q, u_loss, jc, js, jcp, jsp);
+                jumped = true;
+                l_jumps++;
+            }
+        }
+        const float En = Ep * (1.0f - u_loss);
+        l_nuc += fixp(Ep, wsc) - fixp(En, wsc);
+
+        // Deposit E_n - E' at the step midpoint (pre-step direction).
+        score(P, tile, fmaf(ox, P.half_step, rx), fmaf(oy, P.half_step, ry),
+              fmaf(oz, P.half_step, rz), E - Ep, wsc, l_esc);
+        rx = fmaf(ox, P.step, rx);
+        ry = fmaf(oy, P.step, ry);
+        rz = fmaf(oz, P.step, rz);
+
+        // Direction: small-angle diffusion (geodesic Gaussian step of
+        // variance sigma^2 Delta / z per axis), then the jump, renormalised.
+        if (P.flags & kMcs) {
+            const float nu = rho * A2;
+            const float br = (1.0f + frcp(nu)) * flog(1.0f + nu) - 1.0f;
+            const float sig2 = rho * A1 * br;
+            const float th2 = -2.0f * sig2 * flog(u_hi(w.z));
+            float ct, st;
+            polar_cs(th2, ct, st);
+            const float ph = u_hi(w.w);
+            turn(ox, oy, oz, ct, st, cos_rev(ph), sin_rev(ph));
+        }
+        if (jumped) turn(ox, oy, oz, jc, js, jcp, jsp);
+        const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+        ox *= inv;
+        oy *= inv;
+        oz *= inv;
+
+        E = En;
+        n++;
+        l_steps++;
+        if (!inside(P, rx, ry, rz)) {
+            l_esc += fixp(E, wsc);
+            alive = false;
+        } else if (E < P.e_min) {
+            score(P, tile, rx, ry, rz, E, wsc, l_esc);
+            alive = false;
+        }
+    }
+
+    // ledger: wave sums, one atomic per slot per wave
+    const unsigned long long s_esc = wave_sum((unsigned long long)l_esc);
+    const unsigned long long s_nuc = wave_sum((unsigned long long)l_nuc);
+    const unsigned long long s_e0 = wave_sum((unsigned long long)l_e0);
+    const unsigned long long s_st = wave_sum((unsigned long long)l_steps);
+    const unsigned long long s_hi = wave_sum((unsigned long long)l_hist);
+    const unsigned long long s_ju = wave_sum((unsigned long long)l_jumps);
+    if (lane == 0) {
+        atomicAdd(&P.ledger[1], s_esc);
+        atomicAdd(&P.ledger[2], s_nuc);
+        atomicAdd(&P.ledger[3], s_e0);
+        atomicAdd(&P.ledger[5], s_st);
+        atomicAdd(&P.ledger[6], s_hi);
+        atomicAdd(&P.ledger[7], s_ju);
+    }
+
+    // flush the LDS tile
+    __syncthreads();
+    for (int i = threadIdx.x; i < tile_n; i += blockDim.x) {
+        const unsigned long long q = tile[i];
+        if (q) {
+            const int tx = i % P.tile_nx, ty = (i / P.tile_nx) % P.tile_ny,
+                      tz = i / (P.tile_nx * P.tile_ny);
+            const size_t vv = ((size_t)(tz + P.tile_z0) * P.ny + (ty + P.tile_y0)) * P.nx +
+                              (tx + P.tile_x0);
+            atomicAdd(&P.tally[vv], q);
+        }
+    }
+}
+
+// Interleave density and material into one 8-byte word per voxel and count
+// invalid voxels (material out of range, density not finite and positive).
+__global__ void k_pack(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox, int n_mat,
+                       unsigned int* bad) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint8_t m = mat[i];
+        const float r = rho[i];
+        const bool ok = (int)m < n_mat && r > 0.0f && r < 1e30f;
+        if (!ok) atomicAdd(bad, 1u);
+        vox[i] = make_uint2(__float_as_uint(ok ? r : 1.0f), ok ? (unsigned)m : 0u);
+    }
+}
+
+__global__ void k_reset(unsigned long long* tally, size_t nvox, unsigned long long* ledger,
+                        unsigned long long* counter) {
+    const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (size_t i = tid; i < nvox; i += (size_t)gridDim.x * blockDim.x) tally[i] = 0ull;
+    if (tid < (size_t)kLedgerN) ledger[tid] = 0ull;
+    if (tid == 0) *counter = 0ull;
+}
+
+// Dose to medium in FP64: E / (rho V), section 2.2.2; also sums the tally
+// into the ledger's deposited slot (integer, order independent).
+__global__ void __launch_bounds__(256) k_convert(const unsigned long long* tally, const uint2* vox,
+                                                 size_t nvox, double inv_scale, double vcm3,
+                                                 double* dose, unsigned long long* ledger) {
+    unsigned long long s = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const unsigned long long q = tally[i];
+        s += q;
+        const double r = (double)__uint_as_float(vox[i].x);
+        dose[i] = (double)(long long)q * inv_scale * kMevToJ / (r * vcm3 * 1e-3);
+    }
+    s = wave_sum(s);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+        atomicAdd(&ledger[0], t);
+    }
+}
+
+// Gamma index, one thread per reference voxel.  Offsets are integer lattice
+// vectors (a, b, c, a^2+b^2+c^2) of spacing step = dta/interp within dta,
+// sorted by length so a passing voxel stops early.  counts[0] evaluated,
+// counts[1] passed.
+__global__ void __launch_bounds__(256) k_gamma(const double* ref, const double* ev, int nx,
+                                               int ny, int nz, const int4* off, int n_off,
+                                               double step, double dd, double dta, double thr_abs,
+                                               double max_ref, int local, double dx, double dy,
+                                               double dz, unsigned long long* counts) {
+    const size_t nvox = (size_t)nx * ny * nz;
+    unsigned long long ne = 0, np = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double dr = ref[i];
+        if (!(dr >= thr_abs) || dr <= 0.0) continue;
+        ne++;
+        const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((size_t)nx * ny));
+        const double norm = dd * (local ? dr : max_ref);
+        bool pass = false;
+        for (int k = 0; k < n_off && !pass; ++k) {
+            const int4 o = off[k];
+            const double ox = o.x * step, oy = o.y * step, oz = o.z * step;
+            const double fx = ix + ox / dx, fy = iy + oy / dy, fz = iz + oz / dz;
+            if (fx < 0.0 || fy < 0.0 || fz < 0.0 || fx > nx - 1 || fy > ny - 1 || fz > nz - 1)
+                continue;
+            int x0 = (int)floor(fx), y0 = (int)floor(fy), z0 = (int)floor(fz);
+            if (x0 > nx - 2) x0 = nx > 1 ? nx - 2 : 0;
+            if (y0 > ny - 2) y0 = ny > 1 ? ny - 2 : 0;
+            if (z0 > nz - 2) z0 = nz > 1 ? nz - 2 : 0;
+            const double tx = fx - x0, ty = fy - y0, tz = fz - z0;
+            const int x1 = nx > 1 ? x0 + 1 : x0, y1 = ny > 1 ? y0 + 1 : y0, z1 = nz > 1 ? z0 + 1 : z0;
+#define EV(a, b, c) ev[((size_t)(c) * ny + (b)) * nx + (a)]
+            const double c00 = EV(x0, y0, z0) * (1 - tx) + EV(x1, y0, z0) * tx;
+            const double c10 = EV(x0, y1, z0) * (1 - tx) + EV(x1, y1, z0) * tx;
+            const double c01 = EV(x0, y0, z1) * (1 - tx) + EV(x1, y0, z1) * tx;
+            const double c11 = EV(x0, y1, z1) * (1 - tx) + EV(x1, y1, z1) * tx;
+#undef EV
+            const double c0 = c00 * (1 - ty) + c10 * ty, c1 = c01 * (1 - ty) + c11 * ty;
+            const double de = c0 * (1 - tz) + c1 * tz;
+            const double r2 = ox * ox + oy * oy + oz * oz;
+            const double g2 = r2 / (dta * dta) + (de - dr) * (de - dr) / (norm * norm);
+            if (g2 <= 1.0) pass = true;
+        }
+        np += pass ? 1ull : 0ull;
+    }
+    ne = wave_sum(ne);
+    np = wave_sum(np);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&counts[0], ne);
+        atomicAdd(&counts[1], np);
+    }
+}
+
+// Maximum of a non-negative double array via its bit pattern.
+__global__ void k_max(const double* a, size_t n, unsigned long long* out) {
+    double m = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        m = fmax(m, a[i]);
+    unsigned long long b = (unsigned long long)__double_as_longlong(m);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long c = __shfl_xor(b, o);
+        b = c > b ? c : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, b);
+}
+
+int grid_for(size_t n, int block) {
+    size_t g = (n + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox,
+                               int n_mat, unsigned int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(nvox, 256)), dim3(256), 0, s, mat, rho, vox, nvox,
+                       n_mat, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long long* ledger,
+                        unsigned long long* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(grid_for(nvox, 256)), dim3(256), 0, s, tally, nvox, ledger,
+                       counter);
+    return hipGetLastError();
+}
+
+hipError_t transport_kernel_attributes(size_t lds_bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_transport, dim3(grid), dim3(block), lds_bytes, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const unsigned long long* tally, const uint2* vox, size_t nvox,
+                          double inv_scale, double voxel_cm3, double* dose,
+                          unsigned long long* ledger, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert, dim3(grid_for(nvox, 256)), dim3(256), 0, s, tally, vox, nvox,
+                       inv_scale, voxel_cm3, dose, ledger);
+    return hipGetLastError();
+}
+
+hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
+                        const int4* offsets, int n_off, double step, double dd, double dta,
+                        double thr_abs, double max_ref, int local, const double* d,
+                        unsigned long long* counts, hipStream_t s) {
+    const size_t nvox = (size_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_gamma, dim3(grid_for(nvox, 256)), dim3(256), 0, s, ref, ev, nx, ny, nz,
+                       offsets, n_off, step, dd, dta, thr_abs, max_ref, local, d[0], d[1], d[2],
+                       counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s) {
+    hipLaunchKernelGGL(k_max, dim3(grid_for(n, 256)), dim3(256), 0, s, a, n, out_bits);
+    return hipGetLastError();
+}
+
+}  // namespace sde

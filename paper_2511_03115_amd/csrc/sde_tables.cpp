@@ -1,0 +1,278 @@
+// Host-side FP64 table generation for libsde.
+//
+// For every medium, on the lattice of n_energy points uniform in ln E over
+// [e_min, e_max]:
+//   hot[i]  = {A1, A2, rate, Rg} (FP32, staged in LDS by the transport kernel)
+//     A1 = chi_c^2/rho / (1 + F^2) * Delta / z     (per unit density)
+//     A2 = chi_c^2/rho / (2 chi_alpha^2 (1 - F))   (so nu = rho A2)
+//     so that the per-step polar width is sigma^2 = rho A1 ((1+nu)/nu ln(1+nu) - 1),
+//     the Lynch-Dahl width of section 2.1.4 scaled to the step;
+//     rate = sum of elastic and inelastic jump rates per unit density;
+//     Rg   = residual CSDA range in g/cm^2, used only to pre-screen the end of range;
+//   rg64[i] = {Rg, dRg/dt} in FP64 for the cubic-Hermite end-of-range decision.
+// Per element: the constants of the rate laws (section 2.1.4, Eq.
+// (large_elastic_cm) and Eq. (large_elastic_cm_hydrogen); section 2.1.5).
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "sde.h"
+#include "sde_host.hpp"
+#include "sde_internal.hpp"
+
+namespace sde {
+
+namespace {
+
+struct Medium {
+    int n;
+    double Z[kMaxElem], A[kMaxElem], w[kMaxElem];
+    double I_MeV;
+};
+
+double zoa(const Medium& m) {
+    double s = 0;
+    for (int i = 0; i < m.n; ++i) s += m.w[i] * m.Z[i] / m.A[i];
+    return s;
+}
+
+// Mass stopping power (MeV cm^2/g), Eq. (bethbloch) with Bragg additivity.
+double stopping(const Medium& m, double E) {
+    const double g = E + kMp;
+    const double p2 = E * (E + 2.0 * kMp);
+    const double b2 = p2 / (g * g);
+    const double L = std::log(2.0 * kMe * p2 / (kMp * kMp) / m.I_MeV) - b2;
+    return kBethe * zoa(m) / b2 * L;
+}
+
+// Gauss-Legendre rule of order 12 by Newton iteration on P_12.
+struct Gauss {
+    double x[12], w[12];
+    Gauss() {
+        const int n = 12;
+        for (int i = 0; i < n; ++i) {
+            double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), d = 1.0;
+            for (int it = 0; it < 60; ++it) {
+                double a = 1.0, b = z;
+                for (int k = 2; k <= n; ++k) {
+                    const double c = ((2.0 * k - 1.0) * z * b - (k - 1.0) * a) / k;
+                    a = b;
+                    b = c;
+                }
+                d = n * (z * b - a) / (z * z - 1.0);
+                const double dz = b / d;
+                z -= dz;
+                if (std::fabs(dz) < 1e-15) break;
+            }
+            x[i] = z;
+            w[i] = 2.0 / ((1.0 - z * z) * d * d);
+        }
+    }
+};
+
+// int_{E0}^{E1} dE / S = int E/S d(ln E), Gauss-Legendre in ln E.
+double range_piece(const Medium& m, const Gauss& G, double E0, double E1) {
+    const double a = std::log(E0), b = std::log(E1);
+    const double c = 0.5 * (a + b), h = 0.5 * (b - a);
+    double s = 0;
+    for (int k = 0; k < 12; ++k) {
+        const double E = std::exp(c + h * G.x[k]);
+        s += G.w[k] * E / stopping(m, E);
+    }
+    return s * h;
+}
+
+// Lynch-Dahl chi_c^2 per unit density and chi_alpha^2 (section 2.1.4).
+void lynch_dahl(const Medium& m, double E, double z, double& chic2_per_rho, double& chia2) {
+    const double p2 = E * (E + 2.0 * kMp);
+    const double pb = p2 / (E + kMp);
+    const double b2 = p2 / ((E + kMp) * (E + kMp));
+    double c = 0, num = 0, den = 0;
+    for (int i = 0; i < m.n; ++i) {
+        const double Z = m.Z[i];
+        const double wz = m.w[i] * Z * (Z + 1.0) / m.A[i];
+        c += 0.157 * wz * z / (pb * pb);
+        const double za = Z * kAlpha;
+        num += wz * std::log(2.007e-5 * std::cbrt(Z * Z) * (1.0 + 3.34 * za * za / b2) / p2);
+        den += wz;
+    }
+    chic2_per_rho = c;
+    chia2 = std::exp(num / den);
+}
+
+}  // namespace
+
+// Build all tables; returns SDE_OK or an error code with a message.
+int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physics_params* p,
+                      const sde_nuclear_tables* nuc, HostTables* out, std::string* err) {
+    if (!mats || n_mats < 1 || n_mats > kMaxMat) {
+        *err = "n_mats must be in 1..8";
+        return SDE_E_INVALID;
+    }
+    if (!p || !(p->step_cm > 0) || !(p->ld_z_cm > 0) || !(p->e_min_MeV > 0) ||
+        !(p->e_max_MeV > p->e_min_MeV) || p->n_energy < 16 || !(p->ld_F > 0 && p->ld_F < 1) ||
+        !(p->theta_cut_rad > 0 && p->theta_cut_rad < M_PI) ||
+        !(p->backscatter_cut_rad > 0 && p->backscatter_cut_rad < M_PI) || p->max_steps < 1) {
+        *err = "invalid physics parameters";
+        return SDE_E_INVALID;
+    }
+    HostTables& T = *out;
+    T = HostTables();
+    T.params = *p;
+    T.n_mat = n_mats;
+    T.n_e = p->n_energy;
+    T.e_lo = p->e_min_MeV;
+    T.e_hi = p->e_max_MeV;
+    T.ln_e_lo = std::log(T.e_lo);
+    T.dln = (std::log(T.e_hi) - T.ln_e_lo) / (T.n_e - 1);
+    const double ahc = kAlpha * kHbarcFm;                 // MeV fm
+    const double ahc_cm = ahc * 1e-13;
+    T.c_strag = 4.0 * M_PI * kNa * ahc_cm * ahc_cm;        // MeV^2 cm^2 / mol
+    // angular limits of the large-angle laws
+    const double omc = 2.0 * std::pow(std::sin(0.5 * p->theta_cut_rad), 2);   // 1 - cos
+    T.ruth_T = 1.0 / omc;
+    T.mott_hi = std::cos(p->theta_cut_rad);
+    T.mott_lo = -std::cos(p->backscatter_cut_rad);
+    {
+        const double s_hi = std::sin(p->theta_cut_rad), s_lo = std::sin(p->backscatter_cut_rad);
+        T.mott_D0 = 2.0 * T.mott_hi / (s_hi * s_hi) - 2.0 * T.mott_lo / (s_lo * s_lo);
+        T.mott_Lhi = std::log((1.0 + T.mott_hi) / omc);
+        const double omb = 2.0 * std::pow(std::sin(0.5 * p->backscatter_cut_rad), 2);
+        T.mott_Llo = std::log(omb / (1.0 - T.mott_lo));
+    }
+
+    // nuclear tables
+    const bool use_ne = nuc && nuc->n_tab > 0;
+    if (use_ne) {
+        if (!nuc->Z || !nuc->sigma_barn || !nuc->u_icdf || !nuc->kalbach_r || !nuc->kalbach_a ||
+            nuc->n_u < 2 || nuc->n_tab > 64) {
+            *err = "invalid nuclear tables";
+            return SDE_E_INVALID;
+        }
+        T.n_tab = nuc->n_tab;
+        T.n_u = nuc->n_u;
+        const size_t ns = (size_t)T.n_tab * T.n_e, nu = ns * T.n_u;
+        T.nuc_sigma.resize(ns);
+        T.nuc_u.resize(nu);
+        T.nuc_r.resize(nu);
+        T.nuc_a.resize(nu);
+        for (size_t i = 0; i < ns; ++i) {
+            if (!(nuc->sigma_barn[i] >= 0)) { *err = "negative cross section"; return SDE_E_INVALID; }
+            T.nuc_sigma[i] = (float)nuc->sigma_barn[i];
+        }
+        for (size_t i = 0; i < nu; ++i) {
+            T.nuc_u[i] = (float)nuc->u_icdf[i];
+            T.nuc_r[i] = (float)nuc->kalbach_r[i];
+            T.nuc_a[i] = (float)nuc->kalbach_a[i];
+        }
+    } else {
+        T.nuc_sigma.assign(1, 0.f);
+        T.nuc_u.assign(2, 0.f);
+        T.nuc_r.assign(2, 0.f);
+        T.nuc_a.assign(2, 0.f);
+    }
+
+    const Gauss G;
+    T.hot.resize((size_t)n_mats * T.n_e);
+    T.rg64.resize((size_t)n_mats * T.n_e);
+    T.mats.resize(n_mats);
+    std::vector<double> E(T.n_e);
+    for (int i = 0; i < T.n_e; ++i) E[i] = std::exp(T.ln_e_lo + i * T.dln);
+    E[0] = T.e_lo;
+    E[T.n_e - 1] = T.e_hi;
+
+    for (int k = 0; k < n_mats; ++k) {
+        const sde_material_desc& d = mats[k];
+        if (d.n_elem < 1 || d.n_elem > kMaxElem || !d.Z || !d.A || !d.w || !(d.I_eV > 0)) {
+            *err = "invalid material " + std::to_string(k);
+            return SDE_E_INVALID;
+        }
+        Medium m{};
+        m.n = d.n_elem;
+        double wsum = 0;
+        for (int i = 0; i < m.n; ++i) {
+            if (d.Z[i] < 1 || d.Z[i] > 100 || !(d.A[i] > 0) || !(d.w[i] >= 0)) {
+                *err = "invalid element in material " + std::to_string(k);
+                return SDE_E_INVALID;
+            }
+            m.Z[i] = d.Z[i];
+            m.A[i] = d.A[i];
+            m.w[i] = d.w[i];
+            wsum += d.w[i];
+        }
+        if (!(wsum > 0)) { *err = "mass fractions sum to zero"; return SDE_E_INVALID; }
+        for (int i = 0; i < m.n; ++i) m.w[i] /= wsum;
+        m.I_MeV = d.I_eV * 1e-6;
+        if (!(stopping(m, T.e_lo) > 0)) {
+            *err = "stopping power not positive at e_min for material " + std::to_string(k);
+            return SDE_E_INVALID;
+        }
+
+        MatDev& md = T.mats[k];
+        md = MatDev{};
+        md.zoa = (float)zoa(m);
+        md.log_pre = (float)(std::log(2.0 * kMe / m.I_MeV) - 2.0 * std::log(kMp));
+        md.n_elem = m.n;
+        for (int i = 0; i < m.n; ++i) {
+            ElemDev& e = md.el[i];
+            const double Z = m.Z[i], A = m.A[i];
+            const double nd = kNa * m.w[i] / A;                 // atoms per g
+            const double ek = Z * ahc * (1.0 + A) / (2.0 * A);  // (eta/k) E, fm MeV
+            e.Z = (float)Z;
+            e.m2 = (float)(A * kAmu);
+            e.is_h = (d.Z[i] == 1);
+            // 2 pi (azimuth) x atoms/g x 1e-24 cm^2/barn x 0.01 barn/fm^2
+            const double pre = 2.0 * M_PI * nd * 1e-24 * 0.01 * ek * ek;
+            e.el_coef = (float)(e.is_h ? pre : pre * (T.ruth_T - 0.5));
+            e.ne_coef = (float)(nd * 1e-24);
+            e.tab = -1;
+            if (use_ne)
+                for (int t = 0; t < nuc->n_tab; ++t)
+                    if (nuc->Z[t] == d.Z[i]) e.tab = t;
+            if (e.is_h) e.tab = -1;
+        }
+
+        // rate per unit density at E (FP64 twin of the kernel's jump branch)
+        auto rate_at = [&](int li, double En) {
+            double r = 0;
+            const double eta = kAlpha * std::sqrt(kMp / (2.0 * En));
+            for (int i = 0; i < m.n; ++i) {
+                const ElemDev& e = md.el[i];
+                const double Z = m.Z[i], A = m.A[i];
+                const double ek = Z * ahc * (1.0 + A) / (2.0 * A);
+                const double pre = 2.0 * M_PI * kNa * m.w[i] / A * 1e-26 * ek * ek / (En * En);
+                if (p->flags & SDE_ELASTIC) {
+                    if (e.is_h)
+                        r += pre * (T.mott_D0 - (std::sin(eta * T.mott_Lhi) -
+                                                 std::sin(eta * T.mott_Llo)) / (2.0 * eta));
+                    else
+                        r += pre * (T.ruth_T - 0.5);
+                }
+                if ((p->flags & SDE_INELASTIC) && e.tab >= 0)
+                    r += kNa * m.w[i] / A * 1e-24 * nuc->sigma_barn[(size_t)e.tab * T.n_e + li];
+            }
+            return r;
+        };
+
+        double Rg = 0;
+        const double Fp = p->ld_F;
+        for (int i = 0; i < T.n_e; ++i) {
+            if (i > 0) Rg += range_piece(m, G, E[i - 1], E[i]);
+            double c2, ca2;
+            lynch_dahl(m, E[i], p->ld_z_cm, c2, ca2);
+            float4 h;
+            h.x = (float)(c2 / (1.0 + Fp * Fp) * p->step_cm / p->ld_z_cm);
+            h.y = (float)(c2 / (2.0 * ca2 * (1.0 - Fp)));
+            h.z = (float)rate_at(i, E[i]);
+            h.w = (float)Rg;
+            T.hot[(size_t)k * T.n_e + i] = h;
+            double2 r;
+            r.x = Rg;
+            r.y = E[i] / stopping(m, E[i]) * T.dln;   // dRg / dt, t the lattice coordinate
+            T.rg64[(size_t)k * T.n_e + i] = r;
+        }
+    }
+    return SDE_OK;
+}
+
+}  // namespace sde

@@ -8,7 +8,7 @@ what it produces; neither imports the other.
 """
 
 from .materials import ELEMENTS, material, water, bone, lung  # noqa: F401
-from .nuclear import placeholder_nuclear_tables, EnergyLattice  # noqa: F401
+from .nuclear import placeholder_nuclear_tables, nuclear_for_phantom, EnergyLattice  # noqa: F401
 from .phantoms import (Phantom, water_box, slab_phantom, insert_phantom,  # noqa: F401
                        grf_phantom)
 from .beams import Spot, single_spot, plan_spots  # noqa: F401

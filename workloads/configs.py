@@ -74,13 +74,15 @@ def water150(n: int = 10_000_000, seed: int = 1) -> Workload:
                     single_spot(150.0, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
 
 
-def slab(E: float = 150.0, n: int = 10_000_000, seed: int = 2, size: int = 200) -> Workload:
-    return Workload(f"slab{int(E)}", slab_phantom(size, 0.1),
+def slab(E: float = 150.0, n: int = 10_000_000, seed: int = 2, size: int = 200,
+         depth: int = 200) -> Workload:
+    return Workload(f"slab{int(E)}", slab_phantom(size, 0.1, nz=depth),
                     single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
 
 
-def insert(E: float = 150.0, n: int = 10_000_000, seed: int = 4, size: int = 200) -> Workload:
-    return Workload(f"insert{int(E)}", insert_phantom(size, 0.1),
+def insert(E: float = 150.0, n: int = 10_000_000, seed: int = 4, size: int = 200,
+           depth: int = 200) -> Workload:
+    return Workload(f"insert{int(E)}", insert_phantom(size, 0.1, nz=depth),
                     single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
 
 

@@ -94,3 +94,10 @@ def placeholder_nuclear_tables(elements: Sequence[int], atomic_weights: Sequence
     return NuclearTables(lattice=lattice, n_u=n_u, Z=np.array(zs, dtype=np.int32),
                          A=np.array(As), sigma=sigma, u_icdf=u_icdf,
                          kalbach_r=kr, kalbach_a=ka)
+
+
+def nuclear_for_phantom(phantom, lattice: EnergyLattice) -> NuclearTables:
+    """Placeholder tables for every element of a phantom's materials."""
+    zs = [z for m in phantom.materials for z in m.Z]
+    As = [a for m in phantom.materials for a in m.A]
+    return placeholder_nuclear_tables(zs, As, lattice)

@@ -56,13 +56,14 @@ def water_box(nx: int, ny: int, nz: int, d_cm: float = 0.1) -> Phantom:
 
 
 def slab_phantom(n: int = 200, d_cm: float = 0.1,
-                 layers_cm=((0.0, 2.0, 0), (2.0, 4.0, 1), (4.0, 7.0, 2))) -> Phantom:
+                 layers_cm=((0.0, 2.0, 0), (2.0, 4.0, 1), (4.0, 7.0, 2)),
+                 nz: int | None = None) -> Phantom:
     """Longitudinal slabs: water 0-2 cm, bone 2-4 cm, lung 4-7 cm, water beyond.
 
     Layer bounds are (z_lo, z_hi, material index) with materials
     [water, bone, lung]; voxels whose centre lies in a layer take it.
     """
-    ph = _box(n, n, n, d_cm, [water(), bone(), lung()])
+    ph = _box(n, n, nz or n, d_cm, [water(), bone(), lung()])
     zc = ph.centers(2)
     for lo, hi, m in layers_cm:
         sel = (zc >= lo) & (zc < hi)
@@ -72,12 +73,12 @@ def slab_phantom(n: int = 200, d_cm: float = 0.1,
 
 
 def insert_phantom(n: int = 200, d_cm: float = 0.1, z_lo: float = 3.0,
-                   z_hi: float = 5.0) -> Phantom:
+                   z_hi: float = 5.0, nz: int | None = None) -> Phantom:
     """Water with a bone block for y >= 0 and z_lo <= z < z_hi (cm).
 
     The interface y = 0 is parallel to the beam and contains the beam axis.
     """
-    ph = _box(n, n, n, d_cm, [water(), bone()])
+    ph = _box(n, n, nz or n, d_cm, [water(), bone()])
     zc, yc = ph.centers(2), ph.centers(1)
     sel = ((zc >= z_lo) & (zc < z_hi))[:, None, None] & (yc >= 0.0)[None, :, None]
     sel = np.broadcast_to(sel, ph.material_id.shape)
