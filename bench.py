@@ -26,11 +26,15 @@ METRIC = "proton histories/s @150 MeV water; time-to-gamma≥95% denoised vs pla
 # MI355X issue capacity for non-packed 32-bit VALU work: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz, in lane-operations per second.
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
-# VALU instruction slots of one straight-line Euler-Maruyama step of the
-# transport kernel (no jump, refill or end-of-range), counted from the gfx950
-# ISA of the step body with quarter-rate instructions weighted by 4; see the
-# design notes.  Used as the algorithmic work per step.
-STEP_SLOTS = 262
+# Algorithmic work of one Euler-Maruyama step in VALU issue slots: the
+# straight path of a step (voxel and table lookup, one Philox4x32-10 block,
+# Bethe loss, straggling, jump test, midpoint deposit, move, Lynch-Dahl
+# turn, renormalisation), counted operation by operation with quarter-rate
+# operations (transcendentals, 32x32->64 products) weighted by 4.  The
+# breakdown is in the design notes.
+STEP_SLOTS = 372
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2511_03115_amd", "csrc", "sde_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_transport_water150_traffic.json")
 
 
 def parse():
@@ -42,7 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", type=str, default="", help="JSON launch overrides")
+    ap.add_argument("--launch", type=str, default="auto",
+                    help="'auto' (autotuner), 'default', or a JSON launch configuration")
     return ap.parse_args()
 
 
@@ -52,12 +57,17 @@ def cpu_baseline(wl, target_s: float) -> dict:
     import workloads
     nuc = workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice())
     threads = oracle.n_threads_default()
-    n = 2000
-    t0 = time.perf_counter()
-    oracle.transport(wl.phantom, wl.spots, wl.params, nuc, seed=wl.seed, h_begin=0, h_end=n,
-                     n_threads=threads)
-    dt = time.perf_counter() - t0
-    n2 = int(min(wl.n_histories, max(n, n * target_s / max(dt, 1e-3))))
+    # calibrate on two sizes so the fixed set-up cost (tables, per-thread
+    # tallies) is not mistaken for per-history work
+    times = []
+    for n in (2000, 20000):
+        t0 = time.perf_counter()
+        oracle.transport(wl.phantom, wl.spots, wl.params, nuc, seed=wl.seed, h_begin=0,
+                         h_end=n, n_threads=threads)
+        times.append(time.perf_counter() - t0)
+    per_h = max((times[1] - times[0]) / 18000.0, 1e-7)
+    fixed = max(times[0] - 2000 * per_h, 0.0)
+    n2 = int(min(wl.n_histories, max(20000, (target_s - fixed) / per_h)))
     t0 = time.perf_counter()
     oracle.transport(wl.phantom, wl.spots, wl.params, nuc, seed=wl.seed, h_begin=0, h_end=n2,
                      n_threads=threads)
@@ -65,6 +75,21 @@ def cpu_baseline(wl, target_s: float) -> dict:
     return {"value": n2 / dt2, "unit": "histories/s", "cores": threads, "kind": "oracle",
             "sample": f"histories 0..{n2} of the same workload (FP64, {threads} threads, "
                       f"{dt2:.1f} s)"}
+
+
+def measured_traffic(launch, histories):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on the current kernel source, launch and size."""
+    import hashlib
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if t.get("kernel_sha256") != src or t.get("histories") != histories or \
+            t.get("launch") != launch:
+        return None
+    return t.get("bytes_per_launch")
 
 
 def main():
@@ -81,13 +106,20 @@ def main():
     from workloads import configs
 
     wl = configs.water150(n=a.histories)
-    launch = json.loads(a.launch) if a.launch else None
     print(f"[bench] workload {wl.name} n={wl.n_histories} shape={wl.phantom.shape}", flush=True)
     stream = torch.cuda.Stream()
     sde.set_stream(stream)
     sde.init_materials(wl.phantom.materials, wl.params,
                        workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
     dph = sde.DevicePhantom.from_host(wl.phantom)
+    if a.launch == "auto":
+        from paper_2511_03115_amd import autotune
+        launch = autotune.tune(wl.spots, dph, wl.seed, verbose=True)
+    elif a.launch == "default":
+        launch = None
+    else:
+        launch = json.loads(a.launch)
+    print(f"[bench] launch {json.dumps(launch)}", flush=True)
     plan = sde.Plan(wl.spots, dph, wl.seed, launch=launch)
     dose = torch.zeros(wl.phantom.material_id.shape, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -123,7 +155,8 @@ def main():
                                "200x200x300 mm at 1 mm voxels, FP32 stepping, int64 tally",
                    "histories": n, "seed": wl.seed, "launch": launch or "default"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK,
-                     "unit": "lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "unit": "lane-op/s", "frac": achieved / VALU_PEAK,
+                     "traffic": measured_traffic(launch, n),
                      "kernel": "k_transport", "kernel_ms": kms,
                      "work_per_unit": f"{STEP_SLOTS} VALU slots per step",
                      "units_per_launch": steps_per_launch},

@@ -142,6 +142,9 @@ typedef struct {
     int block;        /* threads per workgroup, multiple of 64, <= 1024 (512) */
     int grid;         /* workgroups (0: 2 per compute unit) */
     int refill;       /* refill when at least this many lanes of a wave are idle, 1..64 (1) */
+    int jump_batch;   /* finish deferred jumps when this many lanes of a wave wait, 1..64 (8) */
+    int tally_replicas; /* global tally copies, chosen per XCD and summed at the end, 1..16 (8) */
+    int claim_chunk;  /* history indices a wave takes from the work counter at once, >= 64 (64) */
     int tile_nx, tile_ny, tile_nz;   /* LDS tally tile extent in voxels (0: none) */
     int tile_x0, tile_y0, tile_z0;   /* tile low corner in voxels */
 } sde_launch;
@@ -197,6 +200,13 @@ int sde_plan_destroy(sde_plan* plan);
  * from HIP events recorded on the plan's stream around that launch.
  * Synchronises on the stop event.  SDE_E_STATE if none was recorded. */
 int sde_plan_kernel_ms(sde_plan* plan, float* ms_out);
+/* Optional per-history records for diagnosis: rec (device, n_histories x 12
+ * floats, NULL = off) receives {E0, steps, jumps, end, x, y, z, E, first
+ * jump step, last jump step, 0, 0} when a history ends, end being 1 end of
+ * range, 2 left the phantom, 3 below e_min, 4 step limit, 5 started outside
+ * or below e_min; (x, y, z) is where it stopped and E its energy at that
+ * event (-1 jump steps: none).  Applies to later executions. */
+int sde_plan_set_records(sde_plan* plan, float* rec);
 
 /* Gamma index pass count (section 2.2.3): for each reference voxel with
  * dose >= thresh * max(ref), gamma = min over offsets x on the lattice of
@@ -208,6 +218,11 @@ int sde_plan_kernel_ms(sde_plan* plan, float* ms_out);
 int sde_gamma(const double* ref, const double* eval, int nx, int ny, int nz, double dx_cm,
               double dy_cm, double dz_cm, double dd, double dta_cm, double thresh,
               int interp, int local, int64_t* counts_out);
+
+/* Launch limits for choosing a configuration: compute units, LDS bytes per
+ * workgroup, and LDS bytes the current tables take (0 before
+ * sde_init_materials).  Any pointer may be NULL. */
+int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes);
 
 /* Release tables, buffers and plans-independent state. */
 void sde_free(void);

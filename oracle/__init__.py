@@ -36,7 +36,8 @@ ALL = 63
 # ledger slots and record fields (mirror the enums of sde_oracle.c)
 L_DEP, L_ESC, L_NUC, L_E0, L_TRUNC, L_STEPS, L_HIST, L_JUMPS = range(8)
 (R_E0, R_DEP, R_ESC, R_NUC, R_TRUNC, R_STEPS, R_NEL, R_NNE, R_END,
- R_X, R_Y, R_Z, R_OX, R_OY, R_OZ, R_EEND) = range(16)
+ R_X, R_Y, R_Z, R_OX, R_OY, R_OZ, R_EEND, R_J1, R_J2) = range(18)
+R_N = 18
 END_EOR, END_EXIT, END_EMIN, END_MAXSTEPS, END_SOURCE = 1, 2, 3, 4, 5
 
 
@@ -143,10 +144,16 @@ def _ptr(a: np.ndarray, ct):
 
 
 def n_threads_default() -> int:
+    """Host threads for the oracle: the affinity set, at most 16 (the CPU share
+    of one GPU on the target machines), or SDE_ORACLE_THREADS."""
+    env = os.environ.get("SDE_ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
     try:
-        return max(1, len(os.sched_getaffinity(0)))
+        n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
-        return os.cpu_count() or 1
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
 
 
 def material_struct(m) -> Material:
@@ -216,7 +223,7 @@ def spots_struct(spots) -> C.Array:
 class TransportResult:
     edep: Optional[np.ndarray]      # (nz, ny, nx) weighted MeV
     ledger: np.ndarray              # [8]
-    records: Optional[np.ndarray]   # (n, 16)
+    records: Optional[np.ndarray]   # (n, 18)
 
 
 def transport(phantom, spots, params, nuclear=None, seed: int = 0, h_begin: int = 0,
@@ -237,7 +244,7 @@ def transport(phantom, spots, params, nuclear=None, seed: int = 0, h_begin: int 
     nz_ny_nx = phantom.material_id.shape
     edep = np.zeros(nz_ny_nx, dtype=np.float64) if tally else None
     ledger = np.zeros(8, dtype=np.float64)
-    rec = np.zeros((h_end - h_begin, 16), dtype=np.float64) if records else None
+    rec = np.zeros((h_end - h_begin, R_N), dtype=np.float64) if records else None
     nt = n_threads_default() if n_threads is None else int(n_threads)
     rc = L.or_transport(mats, len(phantom.materials), C.byref(ps),
                         C.byref(ns) if ns is not None else None, C.byref(phs), sps, len(spots),

@@ -570,7 +570,7 @@ static size_t voxel(const or_phantom* ph, const double r[3]) {
 enum { L_DEP = 0, L_ESC, L_NUC, L_E0, L_TRUNC, L_STEPS, L_HIST, L_JUMPS, L_N };
 /* Per-history record fields */
 enum { R_E0 = 0, R_DEP, R_ESC, R_NUC, R_TRUNC, R_STEPS, R_NEL, R_NNE, R_END,
-       R_X, R_Y, R_Z, R_OX, R_OY, R_OZ, R_EEND, R_N };
+       R_X, R_Y, R_Z, R_OX, R_OY, R_OZ, R_EEND, R_J1, R_J2, R_N };
 /* End codes */
 enum { END_EOR = 1, END_EXIT = 2, END_EMIN = 3, END_MAXSTEPS = 4, END_SOURCE = 5 };
 
@@ -613,6 +613,9 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
 
     int end = 0;
     long long n = 0;
+    double e_end = E;
+    sc->hist[R_J1] = -1.0;
+    sc->hist[R_J2] = -1.0;
     if (!inside(ph, R)) {
         sc->hist[R_ESC] += E; E = 0.0; end = END_SOURCE;
     } else if (E < p->e_min) {
@@ -620,6 +623,7 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
     }
 
     while (!end) {
+        e_end = E;
         if (n >= p->max_steps) { sc->hist[R_TRUNC] += E; end = END_MAXSTEPS; break; }
         size_t v = voxel(ph, R);
         const or_material* m = &mats[ph->mat[v]];
@@ -706,6 +710,8 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
                 jc = cos(thl); js = sin(thl);
                 jphi = TWO_PI * u_hi(q[2]);
                 jumped = 1;
+                if (sc->hist[R_J1] < 0.0) sc->hist[R_J1] = (double)n;
+                sc->hist[R_J2] = (double)n;
             }
         }
         double En = Ep * (1.0 - u_loss);
@@ -730,6 +736,7 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
         memcpy(R, Rn, sizeof R);
         E = En;
         n++;
+        e_end = E;
         if (!inside(ph, R)) { sc->hist[R_ESC] += E; E = 0.0; end = END_EXIT; break; }
         if (E < p->e_min) { deposit(ph, sc, R, E); E = 0.0; end = END_EMIN; break; }
     }
@@ -737,14 +744,16 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
     sc->hist[R_END] = end;
     sc->hist[R_X] = R[0]; sc->hist[R_Y] = R[1]; sc->hist[R_Z] = R[2];
     sc->hist[R_OX] = O[0]; sc->hist[R_OY] = O[1]; sc->hist[R_OZ] = O[2];
-    sc->hist[R_EEND] = E;
+    sc->hist[R_EEND] = e_end;
 }
 
 /* Transport histories [h_begin, h_end) of the spot list.  History h belongs
  * to the spot whose cumulative count range holds it and carries weight
  * weight/n of that spot.  edep (nvox doubles, may be NULL) receives the
  * weighted deposited energy in MeV; ledger[8] the weighted energy balance
- * and counts; records ((h_end-h_begin) x 16, may be NULL) per-history data.
+ * and counts; records ((h_end-h_begin) x 18, may be NULL) per-history data
+ * (R_EEND: energy at the end event, before absorption; R_J1, R_J2: first and
+ * last jump step, -1 if none).
  * Returns 0, or -1 on invalid input. */
 int or_transport(const or_material* mats, int n_mat, const or_params* p, const or_nuclear* nu,
                  const or_phantom* ph, const or_spot* spots, int n_spots, uint64_t seed,

@@ -1,0 +1,130 @@
+"""Launch-configuration autotuner for the transport kernel.
+
+Chooses the workgroup size, grid, lane-refill granularity and the LDS tally
+tile (its extent and placement) by timing a short run of each candidate on
+the actual beam and phantom.  Every candidate computes the same integer
+tally (the kernel's arithmetic per history does not depend on the launch),
+so the choice changes only speed.  Results are cached per device and
+workload class, in memory and optionally in a JSON file named by the
+SDE_AUTOTUNE_CACHE environment variable.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, List, Optional
+
+from . import sde
+
+_MEM: Dict[str, dict] = {}
+
+
+def _key(spots, phantom) -> str:
+    import torch
+    name = torch.cuda.get_device_name(0)
+    E = max(s.E_MeV for s in spots)
+    cx = sum(s.x_cm * s.weight for s in spots) / max(sum(s.weight for s in spots), 1e-30)
+    cy = sum(s.y_cm * s.weight for s in spots) / max(sum(s.weight for s in spots), 1e-30)
+    return json.dumps([name, list(phantom.shape), [round(v, 4) for v in phantom.voxel_cm],
+                       len(spots), round(E, 1), round(cx, 2), round(cy, 2)])
+
+
+def _water_range_cm(E: float) -> float:
+    """Rough water range (Bragg-Kleeman) used only to place the tile."""
+    return 0.0022 * E ** 1.77
+
+
+def tile_candidates(spots, phantom, budget_bytes: int) -> List[dict]:
+    """Tiles centred on the weighted beam centroid, deep enough for the
+    highest-energy spot, filling at most budget_bytes of LDS."""
+    nx, ny, nz = phantom.shape
+    dx, dy, dz = phantom.voxel_cm
+    w = sum(s.weight for s in spots) or 1.0
+    cx = sum(s.x_cm * s.weight for s in spots) / w
+    cy = sum(s.y_cm * s.weight for s in spots) / w
+    ix = int(math.floor((cx - phantom.origin_cm[0]) / dx))
+    iy = int(math.floor((cy - phantom.origin_cm[1]) / dy))
+    emax = max(s.E_MeV for s in spots)
+    depth = min(nz, int(math.ceil(_water_range_cm(emax) * 1.15 / dz)) + 2)
+    out = []
+    for T in (6, 8, 10, 12, 16):
+        if T > nx or T > ny:
+            continue
+        D = min(depth, budget_bytes // (8 * T * T))
+        if D < 8:
+            continue
+        x0 = min(max(ix - T // 2, 0), nx - T)
+        y0 = min(max(iy - T // 2, 0), ny - T)
+        out.append({"tile_nx": T, "tile_ny": T, "tile_nz": D, "tile_x0": x0, "tile_y0": y0,
+                    "tile_z0": 0})
+    return out
+
+
+def candidates(spots, phantom) -> List[dict]:
+    n_cu, max_lds, table = sde.launch_limits()
+    cands = [{"block": 512, "grid": 2 * n_cu, "refill": r} for r in (1, 8)]
+    spread = max(s.sigma_xy_cm for s in spots)
+    xs = [s.x_cm for s in spots]
+    ys = [s.y_cm for s in spots]
+    footprint = max(max(xs) - min(xs), max(ys) - min(ys)) + 6 * spread
+    if footprint < 4.0:   # a concentrated beam: its core is worth privatising in LDS
+        for t in tile_candidates(spots, phantom, max_lds - table):
+            for r in (1, 8):
+                cands.append(dict({"block": 1024, "grid": n_cu, "refill": r}, **t))
+        for t in tile_candidates(spots, phantom, max_lds // 2 - table):
+            cands.append(dict({"block": 512, "grid": 2 * n_cu, "refill": 1}, **t))
+    return cands
+
+
+def tune(spots, phantom, seed: int = 0, n_tune: int = 1_000_000, use_cache: bool = True,
+         verbose: bool = False) -> dict:
+    """Fastest launch configuration for this beam and (device) phantom."""
+    import torch
+    key = _key(spots, phantom)
+    path = os.environ.get("SDE_AUTOTUNE_CACHE")
+    if use_cache:
+        if key in _MEM:
+            return dict(_MEM[key])
+        if path and os.path.exists(path):
+            try:
+                disk = json.load(open(path))
+                if key in disk:
+                    _MEM[key] = disk[key]
+                    return dict(disk[key])
+            except (OSError, ValueError):
+                pass
+    total = sum(s.n_histories for s in spots)
+    scale = min(1.0, n_tune / max(total, 1))
+    from dataclasses import replace
+    tune_spots = [replace(s, n_histories=max(1, int(round(s.n_histories * scale))))
+                  for s in spots]
+    best, best_ms = None, float("inf")
+    for c in candidates(spots, phantom):
+        try:
+            plan = sde.Plan(tune_spots, phantom, seed, launch=c)
+        except sde.SdeError:
+            continue
+        plan.execute(None)
+        ms = []
+        for _ in range(2):
+            plan.execute(None)
+            ms.append(plan.kernel_ms())
+        plan.close()
+        t = min(ms)
+        if verbose:
+            print(f"[autotune] {c} {t:.3f} ms", flush=True)
+        if t < best_ms:
+            best, best_ms = c, t
+    torch.cuda.synchronize()
+    best = best or {}
+    _MEM[key] = best
+    if path:
+        try:
+            disk = json.load(open(path)) if os.path.exists(path) else {}
+            disk[key] = best
+            json.dump(disk, open(path, "w"), indent=1)
+        except (OSError, ValueError):
+            pass
+    return dict(best)

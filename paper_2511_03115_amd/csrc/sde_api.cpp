@@ -93,10 +93,11 @@ struct sde_plan {
     unsigned long long* tally = nullptr;
     unsigned long long* ledger = nullptr;
     unsigned long long* counter = nullptr;
-    unsigned int* bad = nullptr;
+    unsigned int* bad = nullptr;    // [1 + kMaxMat]: invalid-voxel count, per-material max density
     SpotDev* spots = nullptr;
     unsigned long long* prefix = nullptr;
     size_t nvox = 0;
+    int n_rep = 1;
     double scale = 1.0;
     double voxel_cm3 = 0;
     hipGraph_t graph = nullptr;
@@ -125,10 +126,10 @@ void plan_free(sde_plan* p) {
     delete p;
 }
 
-// Enqueue reset, transport and (optionally) conversion on stream s; with
-// timing, HIP events bracket the transport launch.
+// Enqueue reset, transport and the replica sum / dose conversion on stream s
+// (dose_out may be NULL); with timing, HIP events bracket the transport launch.
 int plan_enqueue(sde_plan* p, double* dose_out, hipStream_t s, bool timing = false) {
-    HIP_TRY(launch_reset(p->tally, p->nvox, p->ledger, p->counter, s));
+    HIP_TRY(launch_reset(p->tally, p->nvox * p->n_rep, p->ledger, p->counter, s));
     if (timing) {
         if (!p->ev0) HIP_TRY(hipEventCreate(&p->ev0));
         if (!p->ev1) HIP_TRY(hipEventCreate(&p->ev1));
@@ -139,9 +140,8 @@ int plan_enqueue(sde_plan* p, double* dose_out, hipStream_t s, bool timing = fal
         HIP_TRY(hipEventRecord(p->ev1, s));
         p->timed = true;
     }
-    if (dose_out)
-        HIP_TRY(launch_convert(p->tally, p->vox, p->nvox, 1.0 / p->scale, p->voxel_cm3, dose_out,
-                               p->ledger, s));
+    HIP_TRY(launch_convert(p->tally, p->n_rep, p->vox, p->nvox, 1.0 / p->scale, p->voxel_cm3,
+                           dose_out, p->ledger, s));
     return SDE_OK;
 }
 
@@ -196,8 +196,14 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     if (k < -60 || k > 100) return fail(SDE_E_OVERFLOW, "fixed-point scale out of range");
     const double scale = std::ldexp(1.0, k);
 
+    sde_launch L{};
+    if (launch) L = *launch;
+    const int n_rep = L.tally_replicas ? L.tally_replicas : 8;
+    if (n_rep < 1 || n_rep > 16) return fail(SDE_E_INVALID, "tally_replicas must be in 1..16");
+
     sde_plan* p = new sde_plan();
     p->nvox = nvox;
+    p->n_rep = n_rep;
     p->scale = scale;
     p->voxel_cm3 = ph->dx_cm * ph->dy_cm * ph->dz_cm;
 
@@ -219,26 +225,27 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     if ((rc = upload(&p->prefix, pre)) != SDE_OK) return bail(rc);
     hipError_t e;
     if ((e = hipMalloc((void**)&p->vox, sizeof(uint2) * nvox)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->tally, sizeof(unsigned long long) * nvox)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->tally, sizeof(unsigned long long) * nvox * n_rep)) != hipSuccess ||
         (e = hipMalloc((void**)&p->ledger, sizeof(unsigned long long) * kLedgerN)) != hipSuccess ||
         (e = hipMalloc((void**)&p->counter, sizeof(unsigned long long))) != hipSuccess ||
-        (e = hipMalloc((void**)&p->bad, sizeof(unsigned int))) != hipSuccess) {
+        (e = hipMalloc((void**)&p->bad, sizeof(unsigned int) * (1 + kMaxMat))) != hipSuccess) {
         plan_free(p);
         return fail(SDE_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
     }
     hipStream_t s = cur_stream();
-    if ((e = hipMemsetAsync(p->bad, 0, sizeof(unsigned int), s)) != hipSuccess ||
-        (e = launch_pack_phantom(ph->material_id, ph->density, p->vox, nvox, T.n_mat, p->bad, s)) !=
-            hipSuccess) {
+    if ((e = hipMemsetAsync(p->bad, 0, sizeof(unsigned int) * (1 + kMaxMat), s)) != hipSuccess ||
+        (e = launch_pack_phantom(ph->material_id, ph->density, p->vox, nvox, T.n_mat, p->bad,
+                                 p->bad + 1, s)) != hipSuccess) {
         plan_free(p);
         return fail(SDE_E_HIP, std::string("phantom packing failed: ") + hipGetErrorString(e));
     }
-    unsigned int bad = 0;
-    if ((e = hipMemcpyAsync(&bad, p->bad, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    unsigned int chk[1 + kMaxMat] = {0};
+    if ((e = hipMemcpyAsync(chk, p->bad, sizeof chk, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
         plan_free(p);
         return fail(SDE_E_HIP, std::string("phantom check failed: ") + hipGetErrorString(e));
     }
+    const unsigned int bad = chk[0];
     if (bad) {
         plan_free(p);
         return fail(SDE_E_INVALID, std::to_string(bad) +
@@ -247,8 +254,6 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     }
 
     // launch configuration
-    sde_launch L{};
-    if (launch) L = *launch;
     int block = L.block ? L.block : 512;
     if (block < 64 || block > 1024 || block % 64) {
         plan_free(p);
@@ -261,6 +266,16 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
         plan_free(p);
         return fail(SDE_E_INVALID, "refill must be in 1..64");
     }
+    const int claim_chunk = L.claim_chunk ? L.claim_chunk : 64;
+    if (claim_chunk < 64 || claim_chunk > (1 << 20)) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, "claim_chunk must be in 64..2^20");
+    }
+    int jump_batch = L.jump_batch ? L.jump_batch : 8;
+    if (jump_batch < 1 || jump_batch > 64) {
+        plan_free(p);
+        return fail(SDE_E_INVALID, "jump_batch must be in 1..64");
+    }
     const int tnx = std::max(0, L.tile_nx), tny = std::max(0, L.tile_ny),
               tnz = std::max(0, L.tile_nz);
     const bool tile_on = tnx > 0 && tny > 0 && tnz > 0;
@@ -270,7 +285,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
         plan_free(p);
         return fail(SDE_E_INVALID, "LDS tile outside the phantom");
     }
-    const size_t tab_bytes = (size_t)T.n_mat * T.n_e * sizeof(float4);
+    const size_t tab_bytes = ((size_t)T.n_mat * T.n_e + T.n_mat) * sizeof(float4);
     const size_t tile_bytes = tile_on ? (size_t)tnx * tny * tnz * 8 : 0;
     if (tab_bytes + tile_bytes > g.max_lds) {
         plan_free(p);
@@ -311,6 +326,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     kp.mott_D0 = (float)T.mott_D0;
     kp.mott_Lhi = (float)T.mott_Lhi;
     kp.mott_Llo = (float)T.mott_Llo;
+    kp.eta_pre = (float)(kAlpha * std::sqrt(0.5 * kMp));
     kp.flags = pp.flags;
     kp.max_steps = pp.max_steps;
     kp.vox = p->vox;
@@ -330,9 +346,30 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     kp.n_hist = total;
     kp.seed = seed;
     kp.tally = p->tally;
+    kp.rep_stride = nvox;
+    kp.n_rep = n_rep;
     kp.ledger = p->ledger;
     kp.counter = p->counter;
     kp.refill = refill;
+    kp.jump_batch = jump_batch;
+    kp.claim_chunk = claim_chunk;
+    // End-of-range screen: for E above ec[m] the residual range exceeds the
+    // step at every voxel of material m (densest voxel, 0.1 % margin); below
+    // it the kernel decides in FP64.
+    for (int m = 0; m < kMaxMat; ++m) kp.ec[m] = 0.0f;
+    for (int m = 0; m < T.n_mat; ++m) {
+        float rmax;
+        std::memcpy(&rmax, &chk[1 + m], sizeof rmax);
+        if (!(rmax > 0.0f)) continue;
+        const double limit = pp.step_cm * (double)rmax * 1.001;
+        double ec = T.e_hi;
+        for (int j = 0; j < T.n_e; ++j)
+            if (T.rg64[(size_t)m * T.n_e + j].x >= limit) {
+                ec = std::exp(T.ln_e_lo + j * T.dln);
+                break;
+            }
+        kp.ec[m] = (float)(ec * (1.0 + 1e-6));
+    }
     if (tile_on) {
         kp.tile_nx = tnx;
         kp.tile_ny = tny;
@@ -442,6 +479,17 @@ int sde_plan_kernel_ms(sde_plan* p, float* ms_out) {
     return SDE_OK;
 }
 
+int sde_plan_set_records(sde_plan* p, float* rec) {
+    g_err.clear();
+    if (!p) return fail(SDE_E_INVALID, "plan is NULL");
+    p->kp.rec = rec;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+    return SDE_OK;
+}
+
 int sde_plan_destroy(sde_plan* p) {
     g_err.clear();
     if (p) {
@@ -460,19 +508,6 @@ int sde_transport_ex(const sde_beam* beam, const sde_phantom* phantom, uint64_t 
     if (rc != SDE_OK) return rc;
     hipStream_t s = cur_stream();
     rc = plan_enqueue(p, dose_out, s);
-    if (rc == SDE_OK && !dose_out && ledger_out) {
-        // the deposited slot is summed by the conversion pass; run it into a scratch dose
-        double* tmp = nullptr;
-        if (hipMalloc((void**)&tmp, sizeof(double) * p->nvox) != hipSuccess) {
-            plan_free(p);
-            return fail(SDE_E_NOMEM, "scratch dose allocation failed");
-        }
-        const hipError_t e = launch_convert(p->tally, p->vox, p->nvox, 1.0 / p->scale,
-                                            p->voxel_cm3, tmp, p->ledger, s);
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(tmp);
-        if (e != hipSuccess) rc = fail(SDE_E_HIP, hipGetErrorString(e));
-    }
     if (rc == SDE_OK && tally_out) {
         const hipError_t e = hipMemcpyAsync(tally_out, p->tally, sizeof(int64_t) * p->nvox,
                                             hipMemcpyDeviceToDevice, s);
@@ -553,6 +588,19 @@ int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, doubl
     (void)hipFree(doff);
     (void)hipFree(buf);
     return rc;
+}
+
+int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes) {
+    g_err.clear();
+    if (!g.n_cu)
+        if (int r = device_info()) return r;
+    if (n_cu) *n_cu = g.n_cu;
+    if (max_lds_bytes) *max_lds_bytes = (int)g.max_lds;
+    if (table_lds_bytes)
+        *table_lds_bytes = g.ready ? (int)(((size_t)g.host.n_mat * g.host.n_e + g.host.n_mat) *
+                                           sizeof(float4))
+                                   : 0;
+    return SDE_OK;
 }
 
 void sde_free(void) {

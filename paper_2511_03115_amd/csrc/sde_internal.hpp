@@ -37,6 +37,9 @@ struct MatDev {
     float log_pre;         // ln(2 m_e / I) - 2 ln(m_p): Bethe log = log_pre + ln(p^2) - beta^2
     int n_elem;
     int pad;
+    float c_ruth;          // sum of non-hydrogen el_coef: Rutherford rate = rho c_ruth / E^2
+    float c_mott;          // hydrogen el_coef: Mott rate = rho c_mott / E^2 * bracket(E)
+    float pad1, pad2;
     ElemDev el[kMaxElem];
 };
 
@@ -48,7 +51,7 @@ struct SpotDev {
 // Everything the transport kernel reads; passed by value.
 struct KParams {
     // tables
-    const float4* hot;         // [n_mat][n_e] {A1, A2, rate/rho, Rg (FP32)}
+    const float4* hot;         // [n_mat][n_e] {A1, A2, inelastic rate/rho, elastic rate E^2/rho}
     const double2* rg64;       // [n_mat][n_e] {Rg, dRg/dt} for the FP64 end of range
     const MatDev* mats;        // [n_mat]
     const float* nuc_sigma;    // [n_tab][n_e] barn
@@ -57,6 +60,7 @@ struct KParams {
     const float* nuc_a;
     int n_mat, n_e, n_u, n_tab;
     float ln_e_lo, inv_dln;
+    int pad5;
     double ln_e_lo_d, inv_dln_d;
     // scheme
     double step_d;
@@ -65,6 +69,7 @@ struct KParams {
     float ruth_T;                    // 1 / (1 - cos theta_cut)
     float mott_lo, mott_hi;          // CM cosine limits of hydrogen elastic
     float mott_D0, mott_Lhi, mott_Llo;
+    float eta_pre;                   // alpha sqrt(m_p / 2): eta = eta_pre / sqrt(E)
     unsigned flags;
     int pad0;
     long long max_steps;
@@ -79,21 +84,28 @@ struct KParams {
     unsigned long long n_hist;
     unsigned long long seed;
     // outputs and work queue
-    unsigned long long* tally;       // [nvox] fixed point
+    unsigned long long* tally;       // [n_rep][nvox] fixed point, one replica per XCD
+    unsigned long long rep_stride;   // nvox
+    int n_rep, pad6;
     unsigned long long* ledger;      // [kLedgerN]
     unsigned long long* counter;     // next history
+    float* rec;                      // optional [n_hist][12] per-history records
+    float ec[kMaxMat];               // end-of-range screen energy per material (this phantom)
+    int jump_batch;                  // finish pending jumps when this many lanes wait
+    int claim_chunk;                 // history indices a wave takes from the counter at once
     int refill;
     int tile_nx, tile_ny, tile_nz, tile_x0, tile_y0, tile_z0, pad4;
 };
 
 // Launchers (sde_kernels.hip)
 hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox,
-                               int n_mat, unsigned int* bad, hipStream_t s);
-hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long long* ledger,
+                               int n_mat, unsigned int* bad, unsigned int* rho_max_bits,
+                               hipStream_t s);
+hipError_t launch_reset(unsigned long long* tally, size_t n, unsigned long long* ledger,
                         unsigned long long* counter, hipStream_t s);
 hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
                             hipStream_t s);
-hipError_t launch_convert(const unsigned long long* tally, const uint2* vox, size_t nvox,
+hipError_t launch_convert(unsigned long long* tally, int n_rep, const uint2* vox, size_t nvox,
                           double inv_scale, double voxel_cm3, double* dose,
                           unsigned long long* ledger, hipStream_t s);
 hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,

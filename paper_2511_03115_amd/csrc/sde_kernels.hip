@@ -13,6 +13,8 @@
 // is the same for every launch shape.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sde_internal.hpp"
 
 namespace sde {
@@ -61,8 +63,8 @@ __device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf
 __device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
 
 // cos and sin of a polar angle given its square: Taylor in theta^2 for small
-// angles (where the hardware sine would lose relative accuracy), the library
-// otherwise.
+// angles (where the hardware sine would lose relative accuracy), the hardware
+// sine and cosine (absolute error ~1e-7) otherwise.
 __device__ __forceinline__ void polar_cs(float th2, float& c, float& s) {
     if (th2 < 0.25f) {
         const float x = th2;
@@ -73,7 +75,9 @@ __device__ __forceinline__ void polar_cs(float th2, float& c, float& s) {
                                       -1.6666667e-1f), 1.0f);
         s = fsqrt(x) * sc;
     } else {
-        sincosf(sqrtf(th2), &s, &c);
+        const float r = sqrtf(th2) * 0.15915494309189535f;   // revolutions
+        s = sin_rev(r);
+        c = cos_rev(r);
     }
 }
 
@@ -110,32 +114,89 @@ __device__ __forceinline__ long long fixp(float e, float wsc) {
     return (long long)rintf(e * wsc);
 }
 
-// Score energy e at point (x,y,z): LDS tile, global tally, or escaped.
-__device__ __forceinline__ void score(const KParams& P, unsigned long long* tile, float x,
-                                      float y, float z, float e, float wsc, long long& esc) {
+// Add q to voxel v: the workgroup's LDS tile if v lies in it, else this
+// XCD's replica of the global tally (hot lines then stay in one L2).
+__device__ __forceinline__ void tally_add(const KParams& P, unsigned long long* tile,
+                                          unsigned long long* rep, int v, long long q) {
+    const int ix = v % P.nx, iy = (v / P.nx) % P.ny, iz = v / (P.nx * P.ny);
+    const unsigned tx = (unsigned)(ix - P.tile_x0), ty = (unsigned)(iy - P.tile_y0),
+                   tz = (unsigned)(iz - P.tile_z0);
+    if (tx < (unsigned)P.tile_nx && ty < (unsigned)P.tile_ny && tz < (unsigned)P.tile_nz)
+        atomicAdd(&tile[(tz * P.tile_ny + ty) * P.tile_nx + tx], (unsigned long long)q);
+    else
+        atomicAdd(&rep[v], (unsigned long long)q);
+}
+
+// Per-lane deposit accumulator: consecutive deposits into the same voxel are
+// summed in registers and written once when the voxel changes.
+struct Acc {
+    int v;
+    long long q;
+};
+
+__device__ __forceinline__ void acc_flush(const KParams& P, unsigned long long* tile,
+                                          unsigned long long* rep, Acc& a) {
+    if (a.v >= 0 && a.q != 0) tally_add(P, tile, rep, a.v, a.q);
+    a.v = -1;
+    a.q = 0;
+}
+
+// Score energy e at point (x,y,z): into the accumulator, or escaped.
+__device__ __forceinline__ void score(const KParams& P, unsigned long long* tile,
+                                      unsigned long long* rep, Acc& a, float x, float y, float z,
+                                      float e, float wsc, long long& esc) {
     const long long q = fixp(e, wsc);
     if (!inside(P, x, y, z)) {
         esc += q;
         return;
     }
-    if (q == 0) return;
     int ix, iy, iz;
     voxel3(P, x, y, z, ix, iy, iz);
-    const unsigned tx = (unsigned)(ix - P.tile_x0), ty = (unsigned)(iy - P.tile_y0),
-                   tz = (unsigned)(iz - P.tile_z0);
-    if (tx < (unsigned)P.tile_nx && ty < (unsigned)P.tile_ny && tz < (unsigned)P.tile_nz) {
-        atomicAdd(&tile[(tz * P.tile_ny + ty) * P.tile_nx + tx], (unsigned long long)q);
+    const int v = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx +
+                        (unsigned)ix);
+    if (v == a.v) {
+        a.q += q;
     } else {
-        const size_t v = ((size_t)iz * P.ny + iy) * P.nx + ix;
-        atomicAdd(&P.tally[v], (unsigned long long)q);
+        acc_flush(P, tile, rep, a);
+        a.v = v;
+        a.q = q;
     }
 }
 
 // Hydrogen (Mott) antiderivative in units of (eta/k)^2, Appendix A.2 with
-// sin(eta ln((1+mu)/(1-mu))).
-__device__ __forceinline__ float mott_G(float eta, float mu) {
-    return 2.0f * mu / ((1.0f - mu) * (1.0f + mu)) -
-           sinf(eta * logf((1.0f + mu) / (1.0f - mu))) / (2.0f * eta);
+// sin(eta ln((1+mu)/(1-mu))), and its derivative (the Mott cross section of
+// section 2.1.4 in the same units).
+__device__ __forceinline__ void mott_G_dG(float eta, float mu, float& G, float& dG) {
+    const float omm = (1.0f - mu) * (1.0f + mu);
+    const float L = logf((1.0f + mu) / (1.0f - mu));
+    const float r = eta * L * 0.15915494309189535f;   // revolutions, |r| < 1 for E >= e_min
+    const float sn = sin_rev(r), cs = cos_rev(r);
+    G = 2.0f * mu / omm - sn / (2.0f * eta);
+    dG = 2.0f / omm * ((1.0f + mu * mu) / omm - 0.5f * cs);
+}
+
+// Invert the hydrogen elastic CDF, (G(mu) - G(lo)) / (G(hi) - G(lo)) = U, by
+// Newton's method kept inside a shrinking bracket.  First guess: the
+// interference term dropped, 2 mu / (1 - mu^2) = target.
+__device__ __forceinline__ float mott_invert(const KParams& P, float eta, float U) {
+    float a = P.mott_lo, b = P.mott_hi, G0, G1, d;
+    mott_G_dG(eta, a, G0, d);
+    mott_G_dG(eta, b, G1, d);
+    const float tgt = fmaf(U, G1 - G0, G0);
+    float mu = tgt / (1.0f + sqrtf(1.0f + tgt * tgt));
+    mu = fminf(fmaxf(mu, a), b);
+    for (int it = 0; it < 24; ++it) {
+        float G, dG;
+        mott_G_dG(eta, mu, G, dG);
+        const float g = G - tgt;
+        if (g < 0.0f) a = mu; else b = mu;
+        float nx = mu - g / dG;
+        if (!(nx > a && nx < b)) nx = 0.5f * (a + b);
+        const float step = fabsf(nx - mu);
+        mu = nx;
+        if (step <= 1e-7f * fmaxf(1.0f - fabsf(mu), 1e-3f) || !(b > a)) break;
+    }
+    return mu;
 }
 
 __device__ __forceinline__ float lerp_row(const float* row, int i, float f) {
@@ -154,45 +215,55 @@ __device__ __forceinline__ float table_eu(const float* tab, int n_u, int i, floa
     return fmaf(f, b - a, a);
 }
 
-// One large-angle jump at state energy E in material md (Eq. (Npi)):
-// channel by its rate, CM cosine from its law, CM -> lab by Eq. (cm_to_lab).
-// Returns the loss fraction u (0 for elastic) and the lab (cos, sin) and
-// azimuth (cos, sin) of the turn.
-__device__ __forceinline__ void jump(const KParams& P, const MatDev* md, float E, float rho, int li,
-                                  float lf, uint4 q, float& u_loss, float& jc, float& js,
-                                  float& jcp, float& jsp) {
+// Rate of channel (element e, elastic or inelastic) per cm at E.
+__device__ __forceinline__ float channel_rate(const KParams& P, const ElemDev& d, bool inel,
+                                              float rho, float inv_e2, float mott, int li,
+                                              float lf) {
+    if (!inel) return rho * d.el_coef * inv_e2 * (d.is_h ? mott : 1.0f);
+    return rho * d.ne_coef * lerp_row(P.nuc_sigma + (size_t)d.tab * P.n_e, li, lf);
+}
+
+// One large-angle jump at energy E (the state energy E_n) in material md,
+// Eq. (Npi): channel by its rate, CM cosine from its law (closed-form
+// Rutherford inverse, Mott by Newton, Kalbach-Mann inverse), CM -> lab by
+// Eq. (cm_to_lab).  Outputs the loss fraction u (0 for elastic), the lab
+// polar (cos, sin) and the azimuth (cos, sin).
+__device__ void jump(const KParams& P, const MatDev* md, float E, float rho, uint4 q,
+                     float& u_loss, float& jc, float& js, float& jcp, float& jsp) {
+    const float tl = (flog(E) - P.ln_e_lo) * P.inv_dln;
+    const int li = max(0, min((int)tl, P.n_e - 2));
+    const float lf = tl - (float)li;
     const float inv_e2 = 1.0f / (E * E);
-    const float eta = kAlphaF * sqrtf(kMpF / (2.0f * E));
+    const float eta = P.eta_pre * __builtin_amdgcn_rsqf(E);
     const bool el = (P.flags & kElastic) != 0, ne = (P.flags & kInelastic) != 0;
     const int nel = md->n_elem;
     float mott = 0.0f;
-    bool has_h = false;
-    for (int e = 0; e < nel; ++e) has_h |= (md->el[e].is_h != 0);
-    if (el && has_h)
-        mott = P.mott_D0 - (sinf(eta * P.mott_Lhi) - sinf(eta * P.mott_Llo)) / (2.0f * eta);
+    if (el && md->c_mott != 0.0f) {
+        const float k = 0.15915494309189535f;   // revolutions per radian
+        mott = P.mott_D0 -
+               (sin_rev(eta * P.mott_Lhi * k) - sin_rev(eta * P.mott_Llo * k)) / (2.0f * eta);
+    }
     float tot = 0.0f;
     for (int e = 0; e < nel; ++e) {
         const ElemDev& d = md->el[e];
-        if (el) tot += rho * d.el_coef * inv_e2 * (d.is_h ? mott : 1.0f);
-        if (ne && d.tab >= 0)
-            tot += rho * d.ne_coef * lerp_row(P.nuc_sigma + (size_t)d.tab * P.n_e, li, lf);
+        if (el) tot += channel_rate(P, d, false, rho, inv_e2, mott, li, lf);
+        if (ne && d.tab >= 0) tot += channel_rate(P, d, true, rho, inv_e2, mott, li, lf);
     }
     const float target = u_hi(q.x) * tot;
     float acc = 0.0f;
-    int ce = nel - 1, cin = 0;
-    bool found = false;
-    for (int e = 0; e < nel && !found; ++e) {
+    int ce = -1, cin = 0;
+    for (int e = 0; e < nel && ce < 0; ++e) {
         const ElemDev& d = md->el[e];
         if (el) {
-            acc += rho * d.el_coef * inv_e2 * (d.is_h ? mott : 1.0f);
-            if (target < acc) { ce = e; cin = 0; found = true; break; }
+            acc += channel_rate(P, d, false, rho, inv_e2, mott, li, lf);
+            if (target < acc) { ce = e; cin = 0; break; }
         }
         if (ne && d.tab >= 0) {
-            acc += rho * d.ne_coef * lerp_row(P.nuc_sigma + (size_t)d.tab * P.n_e, li, lf);
-            if (target < acc) { ce = e; cin = 1; found = true; break; }
+            acc += channel_rate(P, d, true, rho, inv_e2, mott, li, lf);
+            if (target < acc) { ce = e; cin = 1; break; }
         }
     }
-    if (!found) {   // rounding at the top end: last channel with a rate
+    if (ce < 0) {   // rounding at the top end: the last channel with a rate
         ce = nel - 1;
         cin = (ne && md->el[ce].tab >= 0) ? 1 : 0;
     }
@@ -202,20 +273,10 @@ __device__ __forceinline__ void jump(const KParams& P, const MatDev* md, float E
     if (!cin) {
         const float U = u_hi(q.y);
         if (d.is_h) {
-            // invert the Mott CDF by bisection on its exact antiderivative
-            float a = P.mott_lo, b = P.mott_hi;
-            const float G0 = mott_G(eta, a), G1 = mott_G(eta, b);
-            const float tgt = fmaf(U, G1 - G0, G0);
-            for (int it = 0; it < 40; ++it) {
-                const float mid = 0.5f * (a + b);
-                if (mid <= a || mid >= b) break;
-                if (mott_G(eta, mid) < tgt) a = mid; else b = mid;
-            }
-            cmc = 0.5f * (a + b);
+            cmc = mott_invert(P, eta, U);
             cms = sqrtf(fmaxf(0.0f, (1.0f - cmc) * (1.0f + cmc)));
         } else {
-            // closed-form Rutherford inverse, in 1 - mu
-            const float om = 1.0f / fmaf(U, P.ruth_T - 0.5f, 0.5f);
+            const float om = 1.0f / fmaf(U, P.ruth_T - 0.5f, 0.5f);   // 1 - mu
             cmc = 1.0f - om;
             cms = sqrtf(om * (2.0f - om));
         }
@@ -239,7 +300,7 @@ __device__ __forceinline__ void jump(const KParams& P, const MatDev* md, float E
         cmc = mu;
         cms = sqrtf(fmaxf(0.0f, (1.0f - mu) * (1.0f + mu)));
     }
-    // CM -> lab (Appendix A.1): K = E, m1 = m_p, E* = u E
+    // CM -> lab (Appendix A.1): K = E, m1 = m_p, outgoing lab energy E - u E
     const float m1 = kMpF, m2 = d.m2;
     const float E1 = E + m1;
     const float p1 = sqrtf(E * (E + 2.0f * m1));
@@ -271,47 +332,97 @@ __device__ __forceinline__ double range_g64(const KParams& P, int mat, float E) 
            (-2.0 * s3 + 3.0 * s2) * b.x + (s3 - s2) * b.y;
 }
 
+// Per-history record {E0, steps, jumps, end, x, y, z, E, first jump step,
+// last jump step, 0, 0}: end 1 = end of range, 2 = left the phantom,
+// 3 = below e_min, 4 = step limit, 5 = source; E is the energy at the end
+// event (before absorption).
+__device__ __forceinline__ void record(const KParams& P, unsigned long long h, float e0,
+                                      unsigned steps, unsigned jumps, int end, float x, float y,
+                                      float z, float e, int j1, int j2) {
+    if (!P.rec) return;
+    float* r = P.rec + h * 12;
+    r[0] = e0;
+    r[1] = (float)steps;
+    r[2] = (float)jumps;
+    r[3] = (float)end;
+    r[4] = x;
+    r[5] = y;
+    r[6] = z;
+    r[7] = e;
+    r[8] = (float)j1;
+    r[9] = (float)j2;
+    r[10] = 0.0f;
+    r[11] = 0.0f;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
+enum : int { kDead = 0, kStep = 1, kJump = 2 };
+
 __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     float4* tab = reinterpret_cast<float4*>(smem);
     const int ntab = P.n_mat * P.n_e;
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = P.hot[i];
-    unsigned long long* tile = reinterpret_cast<unsigned long long*>(smem + (size_t)ntab * 16);
+    float4* matc = tab + ntab;   // per material {zoa, Bethe log offset, end-of-range screen, 0}
+    for (int i = threadIdx.x; i < P.n_mat; i += blockDim.x)
+        matc[i] = make_float4(P.mats[i].zoa, P.mats[i].log_pre, P.ec[i], 0.0f);
+    unsigned long long* tile =
+        reinterpret_cast<unsigned long long*>(smem + (size_t)(ntab + P.n_mat) * 16);
     const int tile_n = P.tile_nx * P.tile_ny * P.tile_nz;
     for (int i = threadIdx.x; i < tile_n; i += blockDim.x) tile[i] = 0ull;
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
-    bool alive = false;
+    // tally replica of this XCD (any choice is correct; this one keeps hot
+    // lines in one L2)
+    const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;   // HW_REG_XCC_ID
+    unsigned long long* rep = P.tally + (size_t)(xcc % (unsigned)P.n_rep) * P.rep_stride;
+    Acc acc{-1, 0};
+    int state = kDead;
     bool more = true;   // wave-uniform: the work counter may still hold histories
+    unsigned long long q_next = 0, q_end = 0;   // wave-local range of history indices
 
     unsigned long long h = 0;
     unsigned n = 0;
     float E = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f, ox = 0.0f, oy = 0.0f, oz = 1.0f, wsc = 0.0f;
     int vcache = -1, mat = 0;
-    float rho = 1.0f;
+    float rho = 1.0f, e0 = 0.0f;
+    // pending jump: state energy, material, density and step index at the jump
+    float ej = 0.0f, rhoj = 1.0f;
+    int matj = 0;
+    unsigned nj = 0;
+    unsigned hj = 0;
+    int j1 = -1, j2 = -1;
     long long l_esc = 0, l_nuc = 0, l_e0 = 0;
     unsigned l_steps = 0, l_jumps = 0, l_hist = 0;
 
     for (;;) {
-        const unsigned long long dead = __ballot(!alive);
+        if (state == kDead) acc_flush(P, tile, rep, acc);
+        // ---------------- refill idle lanes ----------------
+        // History indices come from a wave-local range [q_next, q_end) that is
+        // refilled a chunk at a time from the global counter (one atomic per
+        // chunk); the range is wave-uniform.
+        const unsigned long long dead = __ballot(state == kDead);
         const int ndead = __popcll(dead);
         if (more && (ndead >= P.refill || ndead == 64)) {
             const int leader = __ffsll((long long)dead) - 1;
+            const unsigned long long lim = q_end < P.n_hist ? q_end : P.n_hist;
+            const unsigned long long avail = q_next < lim ? lim - q_next : 0ull;
             unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)ndead);
-            base = __shfl(base, leader);
-            if (base + (unsigned long long)ndead >= P.n_hist) more = false;
-            if (!alive) {
-                const unsigned rank = __popcll(dead & ((1ull << lane) - 1ull));
-                const unsigned long long hh = base + rank;
+            const bool claim = avail < (unsigned long long)ndead;
+            if (claim) {
+                if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)P.claim_chunk);
+                base = __shfl(base, leader);
+            }
+            if (state == kDead) {
+                const unsigned long long rank = __popcll(dead & ((1ull << lane) - 1ull));
+                const unsigned long long hh = rank < avail ? q_next + rank : base + (rank - avail);
                 if (hh < P.n_hist) {
                     // Source: spot by cumulative count; Box-Muller pairs from
                     // block (h, 2^32-1, 0): (w0, w1) lateral, (w2, w3) energy.
@@ -336,62 +447,108 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                     oy = 0.0f;
                     oz = 1.0f;
                     wsc = sp.wscale;
-                    vcache = -1;
+                    e0 = E;
+                    hj = 0;
+                    j1 = -1;
+                    j2 = -1;
                     l_hist++;
                     l_e0 += fixp(E, wsc);
                     if (!inside(P, rx, ry, rz)) {
                         l_esc += fixp(E, wsc);
+                        record(P, h, e0, 0, 0, 5, rx, ry, rz, E, -1, -1);
                     } else if (E < P.e_min) {
-                        score(P, tile, rx, ry, rz, E, wsc, l_esc);
+                        score(P, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                        record(P, h, e0, 0, 0, 5, rx, ry, rz, E, -1, -1);
                     } else {
-                        alive = true;
+                        int ix, iy, iz;
+                        voxel3(P, rx, ry, rz, ix, iy, iz);
+                        vcache = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) *
+                                           (unsigned)P.nx + (unsigned)ix);
+                        const uint2 pk = P.vox[vcache];
+                        rho = __uint_as_float(pk.x);
+                        mat = (int)pk.y;
+                        state = kStep;
                     }
                 }
             }
+            if (claim) {
+                q_next = base + ((unsigned long long)ndead - avail);
+                q_end = base + (unsigned long long)P.claim_chunk;
+                if (base >= P.n_hist) more = false;
+            } else {
+                q_next += (unsigned long long)ndead;
+            }
         }
-        if (!more && __ballot(alive) == 0ull) break;
-        if (!alive) continue;
+        if (!more && __ballot(state != kDead) == 0ull) break;
+
+        // ---------------- finish pending jumps, a batch at a time ----------------
+        const unsigned long long pend = __ballot(state == kJump);
+        const unsigned long long stepping = __ballot(state == kStep);
+        if (pend && (__popcll(pend) >= P.jump_batch || stepping == 0ull)) {
+            if (state == kJump) {
+                const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), nj, 1u, k0, k1);
+                float u_loss, jc, js, jcp, jsp;
+                jump(P, P.mats + matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp);
+                // E holds E' (after continuous loss); the jump removes u E'
+                const float En = E * (1.0f - u_loss);
+                l_nuc += fixp(E, wsc) - fixp(En, wsc);
+                E = En;
+                turn(ox, oy, oz, jc, js, jcp, jsp);
+                const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+                ox *= inv;
+                oy *= inv;
+                oz *= inv;
+                l_jumps++;
+                hj++;
+                if (j1 < 0) j1 = (int)nj;
+                j2 = (int)nj;
+                state = kStep;
+                if (!inside(P, rx, ry, rz)) {
+                    l_esc += fixp(E, wsc);
+                    record(P, h, e0, n, hj, 2, rx, ry, rz, E, j1, j2);
+                    state = kDead;
+                } else if (E < P.e_min) {
+                    score(P, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                    record(P, h, e0, n, hj, 3, rx, ry, rz, E, j1, j2);
+                    state = kDead;
+                }
+            }
+        }
+        if (state != kStep) continue;
 
         // ---------------- one step of Eq. (VSDE) ----------------
         if ((long long)n >= P.max_steps) {
             atomicAdd(&P.ledger[4], (unsigned long long)fixp(E, wsc));
-            alive = false;
+            record(P, h, e0, n, hj, 4, rx, ry, rz, E, j1, j2);
+            state = kDead;
             continue;
         }
-        int ix, iy, iz;
-        voxel3(P, rx, ry, rz, ix, iy, iz);
-        const int v = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx + (unsigned)ix);
-        if (v != vcache) {
-            const uint2 pk = P.vox[v];
-            rho = __uint_as_float(pk.x);
-            mat = (int)pk.y;
-            vcache = v;
+        const float4 mc = matc[mat];
+
+        // End of range: residual range within one step, decided in FP64; the
+        // FP32 screen E <= ec(material) is exact-safe (ec bounds the energy
+        // whose range fits a step at the densest voxel of that material).
+        if ((P.flags & kEor) && E <= mc.z) {
+            const double rres = range_g64(P, mat, E) / (double)rho;
+            if (rres <= P.step_d) {
+                const float hr = (float)(0.5 * rres);
+                score(P, tile, rep, acc, fmaf(ox, hr, rx), fmaf(oy, hr, ry), fmaf(oz, hr, rz), E, wsc,
+                      l_esc);
+                l_steps++;
+                const float fr = (float)rres;
+                record(P, h, e0, n + 1, hj, 1, fmaf(ox, fr, rx), fmaf(oy, fr, ry),
+                       fmaf(oz, fr, rz), E, j1, j2);
+                state = kDead;
+                continue;
+            }
         }
+
         const float lnE = flog(E);
         const float tl = (lnE - P.ln_e_lo) * P.inv_dln;
         const int li = max(0, min((int)tl, P.n_e - 2));
         const float lf = tl - (float)li;
         const float4 ta = tab[mat * P.n_e + li], tb = tab[mat * P.n_e + li + 1];
-        const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
-        const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
-        const float rate = fmaf(lf, tb.z - ta.z, ta.z);
-        const float rg32 = fmaf(lf, tb.w - ta.w, ta.w);
-
-        // End of range: residual range within one step, decided in FP64.
-        if ((P.flags & kEor) && rg32 <= P.step * rho * 1.001f) {
-            const double rres = range_g64(P, mat, E) / (double)rho;
-            if (rres <= P.step_d) {
-                const float hr = (float)(0.5 * rres);
-                score(P, tile, fmaf(ox, hr, rx), fmaf(oy, hr, ry), fmaf(oz, hr, rz), E, wsc,
-                      l_esc);
-                l_steps++;
-                alive = false;
-                continue;
-            }
-        }
-
         const uint4 w = philox((uint32_t)h, (uint32_t)(h >> 32), n, 0u, k0, k1);
-        const MatDev* md = P.mats + mat;
 
         // Continuous loss, Eq. (bethbloch) with Bragg additivity; clamped
         // straggling, Eq. (energystraggling), B_n ~ N(0, Delta).
@@ -400,47 +557,57 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         const float b2 = p2 / (g * g);
         float s1 = 0.0f;
         if (P.flags & kLoss) {
-            const float L = md->log_pre + flog(p2) - b2;
-            s1 = rho * P.c_bethe * md->zoa * L * (g * g) / p2;
+            const float L = mc.y + flog(p2) - b2;
+            s1 = rho * P.c_bethe * mc.x * L * (g * g) / p2;
         }
         const float a = s1 * P.step;
         float X = 0.0f;
         if (P.flags & kStraggle) {
             const float gm = g * (1.0f / kMpF);
-            const float var = rho * P.c_strag * md->zoa * gm * gm * (1.0f - 0.5f * b2);
+            const float var = rho * P.c_strag * mc.x * gm * gm * (1.0f - 0.5f * b2);
             const float zE = fsqrt(-2.0f * flog(u_hi(w.x))) * cos_rev(u_hi(w.y));
             X = fminf(fmaxf(fsqrt(var) * P.sqrt_step * zE, -a), a);
         }
         const float Ep = fmaxf(E - a + X, 0.0f);
 
-        // Jump: none with probability exp(-Delta sigma), else Eq. (Npi).
-        float u_loss = 0.0f, jc = 1.0f, js = 0.0f, jcp = 1.0f, jsp = 0.0f;
+        // Jump test: none with probability exp(-Delta sigma).  Elastic rate
+        // (Rutherford + Mott) = el_E2 / E^2 with el_E2 smooth in ln E;
+        // inelastic rate linear on the lattice.
         bool jumped = false;
         if (P.flags & (kElastic | kInelastic)) {
+            const float el_e2 = fmaf(lf, tb.w - ta.w, ta.w);
+            const float ne_rate = fmaf(lf, tb.z - ta.z, ta.z);
+            const float rate = ((P.flags & kElastic) ? el_e2 * frcp(E * E) : 0.0f) +
+                               ((P.flags & kInelastic) ? ne_rate : 0.0f);
             const float lam = P.step * rho * rate;
             const float pj = lam < 0.05f
                 ? lam * fmaf(-0.5f * lam, fmaf(-lam * (1.0f / 3.0f), fmaf(-0.25f, lam, 1.0f), 1.0f), 1.0f)
                 : 1.0f - __expf(-lam);
-            if (u_lo(w.x, w.y, w.z) < pj) {
-                const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), n, 1u, k0, k1);
-                jump(P, md, E, rho, li, lf, q, u_loss, jc, js, jcp, jsp);
-                jumped = true;
-                l_jumps++;
-            }
+            jumped = u_lo(w.x, w.y, w.z) < pj;
         }
-        const float En = Ep * (1.0f - u_loss);
-        l_nuc += fixp(Ep, wsc) - fixp(En, wsc);
 
-        // Deposit E_n - E' at the step midpoint (pre-step direction).
-        score(P, tile, fmaf(ox, P.half_step, rx), fmaf(oy, P.half_step, ry),
+        // Deposit E_n - E' at the step midpoint (pre-step direction), move.
+        score(P, tile, rep, acc, fmaf(ox, P.half_step, rx), fmaf(oy, P.half_step, ry),
               fmaf(oz, P.half_step, rz), E - Ep, wsc, l_esc);
         rx = fmaf(ox, P.step, rx);
         ry = fmaf(oy, P.step, ry);
         rz = fmaf(oz, P.step, rz);
+        const bool in_next = inside(P, rx, ry, rz);
+        uint2 pk_next = make_uint2(0u, 0u);
+        int v_next = vcache;
+        if (in_next) {   // prefetch the next voxel while the direction is updated
+            int ix, iy, iz;
+            voxel3(P, rx, ry, rz, ix, iy, iz);
+            v_next = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx +
+                           (unsigned)ix);
+            if (v_next != vcache) pk_next = P.vox[v_next];
+        }
 
-        // Direction: small-angle diffusion (geodesic Gaussian step of
-        // variance sigma^2 Delta / z per axis), then the jump, renormalised.
+        // Small-angle diffusion: geodesic Gaussian step of per-axis variance
+        // sigma^2 Delta / z, sigma the Lynch-Dahl width.
         if (P.flags & kMcs) {
+            const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
+            const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
             const float nu = rho * A2;
             const float br = (1.0f + frcp(nu)) * flog(1.0f + nu) - 1.0f;
             const float sig2 = rho * A1 * br;
@@ -450,24 +617,41 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
             const float ph = u_hi(w.w);
             turn(ox, oy, oz, ct, st, cos_rev(ph), sin_rev(ph));
         }
-        if (jumped) turn(ox, oy, oz, jc, js, jcp, jsp);
-        const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
-        ox *= inv;
-        oy *= inv;
-        oz *= inv;
-
-        E = En;
-        n++;
         l_steps++;
-        if (!inside(P, rx, ry, rz)) {
-            l_esc += fixp(E, wsc);
-            alive = false;
-        } else if (E < P.e_min) {
-            score(P, tile, rx, ry, rz, E, wsc, l_esc);
-            alive = false;
+        if (jumped) {
+            // the jump (and the renormalisation after it) is finished in a batch
+            ej = E;
+            matj = mat;
+            rhoj = rho;
+            nj = n;
+            E = Ep;
+            n++;
+            state = kJump;
+        } else {
+            const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+            ox *= inv;
+            oy *= inv;
+            oz *= inv;
+            E = Ep;
+            n++;
+            if (!in_next) {
+                l_esc += fixp(E, wsc);
+                record(P, h, e0, n, hj, 2, rx, ry, rz, E, j1, j2);
+                state = kDead;
+            } else if (E < P.e_min) {
+                score(P, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                record(P, h, e0, n, hj, 3, rx, ry, rz, E, j1, j2);
+                state = kDead;
+            }
+        }
+        if (in_next && v_next != vcache) {
+            rho = __uint_as_float(pk_next.x);
+            mat = (int)pk_next.y;
+            vcache = v_next;
         }
     }
 
+    acc_flush(P, tile, rep, acc);
     // ledger: wave sums, one atomic per slot per wave
     const unsigned long long s_esc = wave_sum((unsigned long long)l_esc);
     const unsigned long long s_nuc = wave_sum((unsigned long long)l_nuc);
@@ -493,22 +677,44 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                       tz = i / (P.tile_nx * P.tile_ny);
             const size_t vv = ((size_t)(tz + P.tile_z0) * P.ny + (ty + P.tile_y0)) * P.nx +
                               (tx + P.tile_x0);
-            atomicAdd(&P.tally[vv], q);
+            atomicAdd(&rep[vv], q);
         }
     }
 }
 
-// Interleave density and material into one 8-byte word per voxel and count
-// invalid voxels (material out of range, density not finite and positive).
+// Interleave density and material into one 8-byte word per voxel, count
+// invalid voxels (material out of range, density not finite and positive)
+// and record the largest density of each material (positive floats order
+// like their bit patterns).
 __global__ void k_pack(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox, int n_mat,
-                       unsigned int* bad) {
+                       unsigned int* bad, unsigned int* rho_max_bits) {
+    unsigned rmax[kMaxMat];
+#pragma unroll
+    for (int m = 0; m < kMaxMat; ++m) rmax[m] = 0u;
+    unsigned nbad = 0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
          i += (size_t)gridDim.x * blockDim.x) {
         const uint8_t m = mat[i];
         const float r = rho[i];
         const bool ok = (int)m < n_mat && r > 0.0f && r < 1e30f;
-        if (!ok) atomicAdd(bad, 1u);
+        nbad += ok ? 0u : 1u;
+#pragma unroll
+        for (int k = 0; k < kMaxMat; ++k)
+            if (ok && (int)m == k) rmax[k] = max(rmax[k], __float_as_uint(r));
         vox[i] = make_uint2(__float_as_uint(ok ? r : 1.0f), ok ? (unsigned)m : 0u);
+    }
+    // one atomic per wave and slot
+#pragma unroll
+    for (int k = 0; k < kMaxMat; ++k) {
+        unsigned v = rmax[k];
+        for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o));
+        rmax[k] = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) nbad += (unsigned)__shfl_xor((int)nbad, o);
+    if ((threadIdx.x & 63) == 0) {
+        if (nbad) atomicAdd(bad, nbad);
+        for (int k = 0; k < n_mat && k < kMaxMat; ++k)
+            if (rmax[k]) atomicMax(&rho_max_bits[k], rmax[k]);
     }
 }
 
@@ -522,16 +728,21 @@ __global__ void k_reset(unsigned long long* tally, size_t nvox, unsigned long lo
 
 // Dose to medium in FP64: E / (rho V), section 2.2.2; also sums the tally
 // into the ledger's deposited slot (integer, order independent).
-__global__ void __launch_bounds__(256) k_convert(const unsigned long long* tally, const uint2* vox,
-                                                 size_t nvox, double inv_scale, double vcm3,
-                                                 double* dose, unsigned long long* ledger) {
+__global__ void __launch_bounds__(256) k_convert(unsigned long long* tally, int n_rep,
+                                                 const uint2* vox, size_t nvox, double inv_scale,
+                                                 double vcm3, double* dose,
+                                                 unsigned long long* ledger) {
     unsigned long long s = 0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
          i += (size_t)gridDim.x * blockDim.x) {
-        const unsigned long long q = tally[i];
+        unsigned long long q = tally[i];
+        for (int r = 1; r < n_rep; ++r) q += tally[(size_t)r * nvox + i];
+        if (n_rep > 1) tally[i] = q;   // replica 0 holds the total afterwards
         s += q;
-        const double r = (double)__uint_as_float(vox[i].x);
-        dose[i] = (double)(long long)q * inv_scale * kMevToJ / (r * vcm3 * 1e-3);
+        if (dose) {
+            const double r = (double)__uint_as_float(vox[i].x);
+            dose[i] = (double)(long long)q * inv_scale * kMevToJ / (r * vcm3 * 1e-3);
+        }
     }
     s = wave_sum(s);
     __shared__ unsigned long long part[4];
@@ -622,9 +833,11 @@ int grid_for(size_t n, int block) {
 }  // namespace
 
 hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox,
-                               int n_mat, unsigned int* bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(nvox, 256)), dim3(256), 0, s, mat, rho, vox, nvox,
-                       n_mat, bad);
+                               int n_mat, unsigned int* bad, unsigned int* rho_max_bits,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3(std::min(grid_for(nvox, 256), 4096)), dim3(256), 0, s, mat,
+                       rho, vox, nvox,
+                       n_mat, bad, rho_max_bits);
     return hipGetLastError();
 }
 
@@ -646,10 +859,12 @@ hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_by
     return hipGetLastError();
 }
 
-hipError_t launch_convert(const unsigned long long* tally, const uint2* vox, size_t nvox,
+hipError_t launch_convert(unsigned long long* tally, int n_rep, const uint2* vox, size_t nvox,
                           double inv_scale, double voxel_cm3, double* dose,
                           unsigned long long* ledger, hipStream_t s) {
-    hipLaunchKernelGGL(k_convert, dim3(grid_for(nvox, 256)), dim3(256), 0, s, tally, vox, nvox,
+    // a bounded grid keeps the per-block ledger atomics few
+    const int grid = std::min(grid_for(nvox, 256), 2048);
+    hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, s, tally, n_rep, vox, nvox,
                        inv_scale, voxel_cm3, dose, ledger);
     return hipGetLastError();
 }

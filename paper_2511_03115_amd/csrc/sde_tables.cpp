@@ -2,13 +2,16 @@
 //
 // For every medium, on the lattice of n_energy points uniform in ln E over
 // [e_min, e_max]:
-//   hot[i]  = {A1, A2, rate, Rg} (FP32, staged in LDS by the transport kernel)
+//   hot[i]  = {A1, A2, ne, el} (FP32, staged in LDS by the transport kernel)
 //     A1 = chi_c^2/rho / (1 + F^2) * Delta / z     (per unit density)
 //     A2 = chi_c^2/rho / (2 chi_alpha^2 (1 - F))   (so nu = rho A2)
 //     so that the per-step polar width is sigma^2 = rho A1 ((1+nu)/nu ln(1+nu) - 1),
 //     the Lynch-Dahl width of section 2.1.4 scaled to the step;
-//     rate = sum of elastic and inelastic jump rates per unit density;
-//     Rg   = residual CSDA range in g/cm^2, used only to pre-screen the end of range;
+//     ne = inelastic jump rate per unit density (piecewise linear on the
+//          lattice by definition, so linear interpolation is exact);
+//     el = elastic jump rate per unit density times E^2: the Rutherford part
+//          is constant and the Mott part nearly so, so interpolating el and
+//          dividing by E^2 keeps the rate's 1/E^2 shape exact;
 //   rg64[i] = {Rg, dRg/dt} in FP64 for the cubic-Hermite end-of-range decision.
 // Per element: the constants of the rate laws (section 2.1.4, Eq.
 // (large_elastic_cm) and Eq. (large_elastic_cm_hydrogen); section 2.1.5).
@@ -208,8 +211,8 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             return SDE_E_INVALID;
         }
 
-        MatDev& md = T.mats[k];
-        md = MatDev{};
+        MatDev md{};
+        double c_ruth_d = 0, c_mott_d = 0;   // FP64 sums of the elastic coefficients
         md.zoa = (float)zoa(m);
         md.log_pre = (float)(std::log(2.0 * kMe / m.I_MeV) - 2.0 * std::log(kMp));
         md.n_elem = m.n;
@@ -230,26 +233,25 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
                 for (int t = 0; t < nuc->n_tab; ++t)
                     if (nuc->Z[t] == d.Z[i]) e.tab = t;
             if (e.is_h) e.tab = -1;
+            const double coef = e.is_h ? pre : pre * (T.ruth_T - 0.5);
+            if (e.is_h) c_mott_d += coef; else c_ruth_d += coef;
         }
 
-        // rate per unit density at E (FP64 twin of the kernel's jump branch)
-        auto rate_at = [&](int li, double En) {
-            double r = 0;
+        // elastic rate per unit density times E^2 at En
+        auto el_e2_at = [&](double En) {
             const double eta = kAlpha * std::sqrt(kMp / (2.0 * En));
+            const double mott = T.mott_D0 - (std::sin(eta * T.mott_Lhi) -
+                                             std::sin(eta * T.mott_Llo)) / (2.0 * eta);
+            return (p->flags & SDE_ELASTIC) ? c_ruth_d + c_mott_d * mott : 0.0;
+        };
+        // inelastic rate per unit density at lattice point li
+        auto ne_rate_at = [&](int li) {
+            double r = 0;
             for (int i = 0; i < m.n; ++i) {
                 const ElemDev& e = md.el[i];
-                const double Z = m.Z[i], A = m.A[i];
-                const double ek = Z * ahc * (1.0 + A) / (2.0 * A);
-                const double pre = 2.0 * M_PI * kNa * m.w[i] / A * 1e-26 * ek * ek / (En * En);
-                if (p->flags & SDE_ELASTIC) {
-                    if (e.is_h)
-                        r += pre * (T.mott_D0 - (std::sin(eta * T.mott_Lhi) -
-                                                 std::sin(eta * T.mott_Llo)) / (2.0 * eta));
-                    else
-                        r += pre * (T.ruth_T - 0.5);
-                }
                 if ((p->flags & SDE_INELASTIC) && e.tab >= 0)
-                    r += kNa * m.w[i] / A * 1e-24 * nuc->sigma_barn[(size_t)e.tab * T.n_e + li];
+                    r += kNa * m.w[i] / m.A[i] * 1e-24 *
+                         nuc->sigma_barn[(size_t)e.tab * T.n_e + li];
             }
             return r;
         };
@@ -263,14 +265,17 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             float4 h;
             h.x = (float)(c2 / (1.0 + Fp * Fp) * p->step_cm / p->ld_z_cm);
             h.y = (float)(c2 / (2.0 * ca2 * (1.0 - Fp)));
-            h.z = (float)rate_at(i, E[i]);
-            h.w = (float)Rg;
+            h.z = (float)ne_rate_at(i);
+            h.w = (float)el_e2_at(E[i]);
             T.hot[(size_t)k * T.n_e + i] = h;
             double2 r;
             r.x = Rg;
             r.y = E[i] / stopping(m, E[i]) * T.dln;   // dRg / dt, t the lattice coordinate
             T.rg64[(size_t)k * T.n_e + i] = r;
         }
+        md.c_ruth = (float)c_ruth_d;
+        md.c_mott = (float)c_mott_d;
+        T.mats[k] = md;
     }
     return SDE_OK;
 }

@@ -24,7 +24,8 @@ LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, END_OF_RANGE, ALL = 1, 2, 4, 8, 16, 32,
  LEDGER_STEPS, LEDGER_HISTORIES, LEDGER_JUMPS) = range(8)
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",
            "sde_plan_create", "sde_plan_execute", "sde_plan_results", "sde_plan_destroy",
-           "sde_plan_kernel_ms", "sde_gamma", "sde_free", "sde_last_error")
+           "sde_plan_kernel_ms", "sde_plan_set_records", "sde_gamma", "sde_launch_limits",
+           "sde_free", "sde_last_error")
 
 
 class SdeError(RuntimeError):
@@ -69,6 +70,7 @@ class PhantomS(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("block", C.c_int), ("grid", C.c_int), ("refill", C.c_int),
+                ("jump_batch", C.c_int), ("tally_replicas", C.c_int), ("claim_chunk", C.c_int),
                 ("tile_nx", C.c_int), ("tile_ny", C.c_int), ("tile_nz", C.c_int),
                 ("tile_x0", C.c_int), ("tile_y0", C.c_int), ("tile_z0", C.c_int)]
 
@@ -88,8 +90,10 @@ def _load():
     L.sde_plan_results.argtypes = [V, V, P(C.c_int64), P(C.c_double)]
     L.sde_plan_destroy.argtypes = [V]
     L.sde_plan_kernel_ms.argtypes = [V, P(C.c_float)]
+    L.sde_plan_set_records.argtypes = [V, V]
     L.sde_gamma.argtypes = [V, V, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                             C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, P(C.c_int64)]
+    L.sde_launch_limits.argtypes = [P(C.c_int), P(C.c_int), P(C.c_int)]
     L.sde_free.argtypes = []
     L.sde_free.restype = None
     L.sde_last_error.argtypes = []
@@ -252,6 +256,8 @@ class Plan:
         del keep
         self._h = h
         self.phantom = phantom
+        self.n_histories = (int(n_histories) if n_histories and len(spots) == 1
+                            else int(sum(sp.n_histories for sp in spots)))
 
     def execute(self, dose_out=None, use_graph: bool = False) -> None:
         _check(lib.sde_plan_execute(self._h, C.c_void_p(_dptr(dose_out) if dose_out is not None
@@ -266,6 +272,14 @@ class Plan:
                                                         else None),
                                     ledger.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(sc)))
         return ledger, sc.value
+
+    def set_records(self, rec) -> None:
+        """Per-history records into rec (cuda float32 (n, 12)) from the next execution."""
+        if rec is not None and (rec.dtype.itemsize != 4 or rec.numel() < 12 * self.n_histories):
+            raise ValueError("records need a float32 buffer of n_histories x 12")
+        _check(lib.sde_plan_set_records(self._h, C.c_void_p(_dptr(rec) if rec is not None
+                                                            else None)))
+        self._rec = rec
 
     def kernel_ms(self) -> float:
         """Event-timed duration of the transport kernel of the last plain execution."""
@@ -297,6 +311,13 @@ def gamma(ref, ev, voxel_cm, dd: float = 0.02, dta_cm: float = 0.05, thresh: flo
                          int(local), cnt.ctypes.data_as(C.POINTER(C.c_int64))))
     ne, npass = int(cnt[0]), int(cnt[1])
     return (npass / ne if ne else 1.0), ne, npass
+
+
+def launch_limits():
+    """(compute units, LDS bytes per workgroup, LDS bytes used by the tables)."""
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(lib.sde_launch_limits(C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
 
 
 def free() -> None:

@@ -57,3 +57,35 @@ def parity_metrics(d_ref, d_gpu, phantom):
     r_gpu = oracle.range_rx(d_gpu, dz, 0.8)
     return dict(max_rel_diff=float(dmax), gamma_1pct_05mm=float(g), gamma_n=ne,
                 r80_ref_cm=r_ref, r80_gpu_cm=r_gpu, dr80_mm=abs(r_ref - r_gpu) * 10)
+
+
+def run_gpu_records(wl, flags=None):
+    """(records numpy (n, 12), dose numpy) from a plan with per-history records."""
+    import torch
+    from paper_2511_03115_amd import sde
+    params = wl.params if flags is None else replace(wl.params, flags=flags)
+    sde.init_materials(wl.phantom.materials, params, nuclear_for(wl.phantom, params))
+    dph = sde.DevicePhantom.from_host(wl.phantom)
+    plan = sde.Plan(wl.spots, dph, wl.seed)
+    rec = torch.zeros((plan.n_histories, 12), dtype=torch.float32, device="cuda")
+    plan.set_records(rec)
+    dose = torch.zeros(wl.phantom.material_id.shape, dtype=torch.float64, device="cuda")
+    plan.execute(dose)
+    out = rec.cpu().numpy().astype(np.float64), dose.cpu().numpy()
+    plan.close()
+    return out
+
+
+def history_agreement(g, o):
+    """Fractions of histories whose discrete path (steps, jump count, first and
+    last jump step, end event) is identical, and, among those, the end-position
+    and end-energy differences."""
+    oj = o[:, oracle.R_NEL] + o[:, oracle.R_NNE]
+    same = ((g[:, 1] == o[:, oracle.R_STEPS]) & (g[:, 2] == oj) & (g[:, 3] == o[:, oracle.R_END])
+            & (g[:, 8] == o[:, oracle.R_J1]) & (g[:, 9] == o[:, oracle.R_J2]))
+    pos = np.sqrt(((g[:, 4:7] - o[:, [oracle.R_X, oracle.R_Y, oracle.R_Z]]) ** 2).sum(1))
+    dE = np.abs(g[:, 7] - o[:, oracle.R_EEND])
+    return dict(same_frac=float(same.mean()), pos_p99=float(np.percentile(pos[same], 99)),
+                pos_close_frac=float((pos[same] < 1e-3).mean()),
+                dE_p99=float(np.percentile(dE[same], 99)),
+                e0_equal=float(np.mean(np.abs(g[:, 0] - o[:, oracle.R_E0]) <= 1e-5 * o[:, oracle.R_E0])))

@@ -118,6 +118,7 @@ def test_straggling_clamped_normal_moments(water):
     rec = r.records
     assert np.all(rec[:, oracle.R_STEPS] == 1)
     loss = rec[:, oracle.R_E0] - rec[:, oracle.R_ESC]   # exit energy is escaped
+    assert np.allclose(rec[:, oracle.R_EEND], rec[:, oracle.R_ESC])
     a = oracle.stopping_mass(water, E0) * D
     s = math.sqrt(oracle.straggle_mass(water, E0) * D)
     c = a / s
