@@ -1,0 +1,81 @@
+"""The C-ABI library without a GPU: it loads, exports every declared entry
+point, and rejects bad input before any device work."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sde.h")
+LIB = os.path.join(ROOT, "paper_2511_03115_amd", "libsde.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2511_03115_amd import build
+        build.build()
+    return C.CDLL(LIB)
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sde_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("sde_init_materials", "sde_transport", "sde_free", "sde_set_stream",
+                 "sde_transport_ex", "sde_plan_create", "sde_gamma", "sde_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_binding_names_match_header():
+    import importlib
+    sde = importlib.import_module("paper_2511_03115_amd.sde")
+    assert set(sde.EXPORTS) == set(declared_functions())
+
+
+def test_host_validation_without_gpu(lib):
+    from paper_2511_03115_amd import sde
+    # transport before tables: state error, no device call
+    beam = sde.Beam(0, None)
+    assert lib.sde_transport(C.byref(beam), None, C.c_uint64(0), C.c_uint64(0), None) in (
+        sde.E_STATE, sde.E_INVALID)
+    # invalid materials and parameters are rejected by the host table build
+    pp = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63, 65536)
+    assert lib.sde_init_materials(None, 0, C.byref(pp), None) == sde.E_INVALID
+    bad = sde.PhysicsParams(-1.0, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63, 65536)
+    Z = (C.c_int * 1)(1)
+    A = (C.c_double * 1)(1.008)
+    w = (C.c_double * 1)(1.0)
+    m = sde.MaterialDesc(1, C.cast(Z, C.POINTER(C.c_int)), C.cast(A, C.POINTER(C.c_double)),
+                         C.cast(w, C.POINTER(C.c_double)), 19.2)
+    lib.sde_init_materials.argtypes = [C.POINTER(sde.MaterialDesc), C.c_int,
+                                       C.POINTER(sde.PhysicsParams), C.c_void_p]
+    assert lib.sde_init_materials(C.byref(m), 1, C.byref(bad), None) == sde.E_INVALID
+    lib.sde_last_error.restype = C.c_char_p
+    assert b"invalid physics parameters" in lib.sde_last_error()
+    # a medium whose Bethe stopping power is negative at e_min (I far too large)
+    m.I_eV = 5000.0
+    assert lib.sde_init_materials(C.byref(m), 1, C.byref(pp), None) == sde.E_INVALID
+    assert b"stopping power" in lib.sde_last_error()
+    # gamma argument checks
+    cnt = (C.c_int64 * 2)()
+    assert lib.sde_gamma(None, None, 1, 1, 1, C.c_double(0.1), C.c_double(0.1),
+                         C.c_double(0.1), C.c_double(0.02), C.c_double(0.05), C.c_double(0.01),
+                         10, 1, cnt) == sde.E_INVALID

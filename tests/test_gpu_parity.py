@@ -79,9 +79,10 @@ def test_history_by_history_agreement():
 @pytest.mark.parametrize("kind,E", [("slab", 100.0), ("insert", 150.0)])
 def test_parity_heterogeneous(kind, E):
     # FP32 positions differ from FP64 by ~1e-5 cm, so about 1e-4 of the
-    # histories see the other material at an interface; enough histories keep
-    # each such history's share of a voxel below the 1e-3 bar.
-    n = 300_000
+    # histories see the other material at an interface (the insert's
+    # interface contains the beam axis); enough histories keep each such
+    # history's share of a voxel below the 1e-3 bar.
+    n = 1_000_000 if kind == "slab" else 2_000_000
     wl = (configs.slab(E, n=n, size=80) if kind == "slab" else configs.insert(E, n=n, size=80))
     # 8 x 8 cm lateral, 20 cm deep so the Bragg peaks stay inside
     ph = wl.phantom
