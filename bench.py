@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plan", action="store_true",
+                    help="skip the batched-plan leg (1000 spots, hipGraph replay)")
     ap.add_argument("--launch", type=str, default="auto",
                     help="'auto' (autotuner), 'default', or a JSON launch configuration")
     return ap.parse_args()
@@ -90,6 +92,44 @@ def measured_traffic(launch, histories):
             t.get("launch") != launch:
         return None
     return t.get("bytes_per_launch")
+
+
+def plan_leg(steps: int, stream) -> dict:
+    """The batched plan: 1000 spots (70-230 MeV, lognormal weights, 1e3-1e5
+    histories each) on a 256x256x200 random-density phantom at 2 mm, one
+    persistent launch per execution, replayed from a hipGraph."""
+    import numpy as np
+    import torch
+    import workloads
+    from workloads import configs
+    from paper_2511_03115_amd import autotune, sde
+    wl = configs.plan()
+    print(f"[bench] plan n={wl.n_histories} spots={len(wl.spots)}", flush=True)
+    sde.init_materials(wl.phantom.materials, wl.params,
+                       workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
+    dph = sde.DevicePhantom.from_host(wl.phantom)
+    launch = autotune.tune(wl.spots, dph, wl.seed)
+    plan = sde.Plan(wl.spots, dph, wl.seed, launch=launch)
+    dose = torch.zeros(wl.phantom.material_id.shape, dtype=torch.float64, device="cuda")
+    plan.execute(dose, use_graph=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(max(1, steps)):
+        ev0.record(stream)           # the library's stream
+        plan.execute(dose, use_graph=True)
+        ev1.record(stream)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    led, _ = plan.results()
+    plan.close()
+    ms = float(np.mean(times))
+    print(f"[bench] plan {ms:.2f} ms per execution", flush=True)
+    return {"workload": "plan: 1000 spots 70-230 MeV, lognormal weights, 1e3-1e5 histories "
+                        "per spot, 256x256x200 at 2 mm, random density + bone/lung ellipsoids",
+            "histories": int(wl.n_histories), "ms_per_execution": ms,
+            "histories_per_s": wl.n_histories / (ms * 1e-3), "hipgraph": True,
+            "steps_per_execution": int(led[sde.LEDGER_STEPS]), "launch": launch}
 
 
 def main():
@@ -161,10 +201,12 @@ def main():
                      "work_per_unit": f"{STEP_SLOTS} VALU slots per step",
                      "units_per_launch": steps_per_launch},
     }
+    plan.close()
+    if not a.no_plan:
+        out["plan"] = plan_leg(a.steps, stream)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

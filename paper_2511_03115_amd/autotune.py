@@ -6,7 +6,10 @@ the actual beam and phantom.  Every candidate computes the same integer
 tally (the kernel's arithmetic per history does not depend on the launch),
 so the choice changes only speed.  Results are cached per device and
 workload class, in memory and optionally in a JSON file named by the
-SDE_AUTOTUNE_CACHE environment variable.
+SDE_AUTOTUNE_CACHE environment variable; the package ships the results of
+earlier tuning runs on gfx950 (tuned_launches.json) so that repeated runs of
+a known workload use one launch.  A later candidate replaces the best so far
+only when it is more than 2 % faster, which keeps near-ties stable.
 """
 
 from __future__ import annotations
@@ -19,11 +22,17 @@ from typing import Dict, List, Optional
 from . import sde
 
 _MEM: Dict[str, dict] = {}
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_launches.json")
+MARGIN = 0.98
 
 
-def _key(spots, phantom) -> str:
+def device_arch() -> str:
     import torch
-    name = torch.cuda.get_device_name(0)
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _key(spots, phantom, arch: Optional[str] = None) -> str:
+    name = arch or device_arch()
     E = max(s.E_MeV for s in spots)
     cx = sum(s.x_cm * s.weight for s in spots) / max(sum(s.weight for s in spots), 1e-30)
     cy = sum(s.y_cm * s.weight for s in spots) / max(sum(s.weight for s in spots), 1e-30)
@@ -87,14 +96,16 @@ def tune(spots, phantom, seed: int = 0, n_tune: int = 1_000_000, use_cache: bool
     if use_cache:
         if key in _MEM:
             return dict(_MEM[key])
-        if path and os.path.exists(path):
+        for f in (path, SHIPPED):
+            if not f or not os.path.exists(f):
+                continue
             try:
-                disk = json.load(open(path))
-                if key in disk:
-                    _MEM[key] = disk[key]
-                    return dict(disk[key])
+                disk = json.load(open(f))
             except (OSError, ValueError):
-                pass
+                continue
+            if key in disk:
+                _MEM[key] = disk[key]
+                return dict(disk[key])
     total = sum(s.n_histories for s in spots)
     scale = min(1.0, n_tune / max(total, 1))
     from dataclasses import replace
@@ -115,7 +126,7 @@ def tune(spots, phantom, seed: int = 0, n_tune: int = 1_000_000, use_cache: bool
         t = min(ms)
         if verbose:
             print(f"[autotune] {c} {t:.3f} ms", flush=True)
-        if t < best_ms:
+        if t < best_ms * MARGIN:
             best, best_ms = c, t
     torch.cuda.synchronize()
     best = best or {}
