@@ -10,6 +10,8 @@ HIP library; both consume the seeded inputs of ``workloads``.
   index of section 2.2, all in FP64.
 * this module: the ctypes binding and the analysis of section 2.2 in numpy
   (integrated depth dose, R80/R90, D99-normalised differences).
+* ``nn_oracle``: the dose denoiser (layers, network, loss, Adam) in float64
+  numpy, the reference for the learned part's kernels.
 """
 
 from __future__ import annotations
