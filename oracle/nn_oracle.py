@@ -24,6 +24,14 @@ Layout and conventions (shared with the HIP side only through this text):
 * loss: weighted mean squared error ``mean(m (out - tgt)^2)``;
 * optimiser: Adam (Kingma and Ba, 2015) with bias correction.
 
+Storage precision.  With ``bf16_storage=True`` the network rounds, to the
+nearest bf16 value (ties to even), exactly the quantities that a bf16
+implementation stores: the conv weights, the network input's conv channels,
+every activation after LeakyReLU, every pooled tensor, and the activation
+gradient that enters the weight- and input-gradient products.  Everything
+else (sums, the residual, the head, the loss, the gradients themselves)
+stays float64.  With ``False`` (the default) nothing is rounded.
+
 Parameter order (``param_shapes``): for each level l = 0..L-1 the encoder
 convs ``enc{l}a``, ``enc{l}b``; then for l = L-2..0 the decoder convs
 ``dec{l}a``, ``dec{l}b``; each conv as (weight, bias); then the head weight
@@ -42,6 +50,15 @@ TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0,
 # ---------------------------------------------------------------------------
 # layers
 # ---------------------------------------------------------------------------
+
+def bf16(a: np.ndarray) -> np.ndarray:
+    """Nearest bf16 value (ties to even) of each element, as float64: the
+    float32 bit pattern with its low 16 bits rounded away."""
+    bits = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (bits >> np.uint64(16)) & np.uint64(1)
+    bits = ((bits + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
 
 def conv3d(x: np.ndarray, w: np.ndarray, b: np.ndarray | None) -> np.ndarray:
     """y[b, z, y, x, co] = b[co] + sum_t sum_ci x[b, z+dz, y+dy, x+dx, ci] w[co, t, ci],
@@ -174,21 +191,24 @@ class UNet:
     dose in channel 0; the output (B, D, H, W) is x[..., 0] plus the head."""
 
     def __init__(self, params: Dict[str, np.ndarray], levels: int, c0: int, cin: int,
-                 alpha: float = 0.01):
-        self.p, self.L, self.c0, self.cin, self.alpha = params, levels, c0, cin, alpha
+                 alpha: float = 0.01, bf16_storage: bool = False):
+        self.L, self.c0, self.cin, self.alpha = levels, c0, cin, alpha
+        self.r = bf16 if bf16_storage else (lambda a: a)
+        self.p = {k: (self.r(v) if k.endswith(".w") and np.ndim(v) == 3 else v)
+                  for k, v in params.items()}
 
     def _conv(self, name, x, cache):
         z = conv3d(x, self.p[name + ".w"], self.p[name + ".b"])
         cache[name] = (x, z)
-        return lrelu(z, self.alpha)
+        return self.r(lrelu(z, self.alpha))
 
     def forward(self, x: np.ndarray):
         cache: Dict[str, tuple] = {}
         skips = []
-        h = x
+        h = self.r(x)
         for l in range(self.L):
             if l > 0:
-                h = pool2(h)
+                h = self.r(pool2(h))
             h = self._conv(f"enc{l}a", h, cache)
             h = self._conv(f"enc{l}b", h, cache)
             skips.append(h)
@@ -202,7 +222,7 @@ class UNet:
 
     def _conv_back(self, name, dy, cache, grads, need_dx=True):
         x, z = cache[name]
-        dz = lrelu_backward(dy, z, self.alpha)
+        dz = self.r(lrelu_backward(dy, z, self.alpha))
         dx, dw, db = conv3d_backward(dz, x, self.p[name + ".w"], need_dx)
         grads[name + ".w"] = dw
         grads[name + ".b"] = db

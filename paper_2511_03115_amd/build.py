@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsde.so")
 
-SOURCES = ["sde_kernels.hip", "sde_tables.cpp", "sde_api.cpp"]
+SOURCES = ["sde_kernels.hip", "sde_tables.cpp", "sde_api.cpp", "nn_kernels.hip", "nn_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # packed FP32 VALU forms are switched off for device code
@@ -31,7 +31,9 @@ def build(verbose: bool = False) -> str:
         cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.PIPE)
+        r = subprocess.run(cmd, stderr=None if verbose else subprocess.PIPE, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr or ''}")
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

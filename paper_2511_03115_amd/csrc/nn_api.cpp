@@ -1,0 +1,503 @@
+// C ABI of the denoiser (declared in include/sde_nn.h): the network object
+// (parameters, Adam state, activation and gradient buffers) and the
+// sequence of kernel launches for inference, loss/gradient and update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "nn_internal.hpp"
+#include "sde_nn.h"
+
+using namespace sde;
+using namespace sde::nn;
+
+namespace {
+
+#define NN_TRY(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return report_error(e_ == hipErrorOutOfMemory ? SDE_E_NOMEM : SDE_E_HIP,        \
+                                (std::string(#expr) + ": " + hipGetErrorString(e_)).c_str()); \
+    } while (0)
+
+#define NN_CHECK(cond, msg)                                          \
+    do {                                                             \
+        if (!(cond)) return report_error(SDE_E_INVALID, (msg));      \
+    } while (0)
+
+// largest wgrad split-K partial buffer (floats)
+constexpr long long kMaxPartFloats = 32LL << 20;
+
+bool nt_ok(int co) {
+    if (co % 16) return false;
+    const int nt = co / 16;
+    return nt == 1 || nt == 2 || nt == 3 || nt == 4 || nt == 6 || nt == 8 || nt == 12;
+}
+
+struct ConvP {
+    long long w = 0, b = 0;   // offsets into the parameter vector
+    int ci = 0, co = 0;
+};
+
+struct Level {
+    uint16_t *ea = nullptr, *eb = nullptr, *pin = nullptr, *cat = nullptr, *da = nullptr,
+             *db = nullptr;
+    float *gE = nullptr, *gEa = nullptr, *gP = nullptr, *gCat = nullptr, *gDa = nullptr,
+          *gDb = nullptr;
+};
+
+}  // namespace
+
+struct sde_nn {
+    sde_nn_config cfg{};
+    int L = 0, c0 = 0, cin = 0;
+    std::vector<int> c;
+    std::vector<ConvP> enc_a, enc_b, dec_a, dec_b;   // dec_* indexed by level (L-1 entries)
+    long long head_w = 0, head_b = 0, n_params = 0;
+    float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;
+    uint16_t* P16 = nullptr;
+    long long step = 0;
+    long long max_nv0 = 0;
+    uint16_t* x16 = nullptr;
+    float *resid = nullptr, *out = nullptr;
+    std::vector<Level> lv;
+    float *dout = nullptr, *loss_part = nullptr, *loss_dev = nullptr, *head_part = nullptr;
+    uint16_t *dz = nullptr, *wt = nullptr;
+    float* wpart = nullptr;
+    unsigned long long* maxbits = nullptr;
+    std::vector<void*> allocs;
+    bool have_grad = false;
+
+    ~sde_nn() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+template <class T>
+hipError_t dalloc(sde_nn* n, T** p, long long count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    n->allocs.push_back(q);
+    *p = (T*)q;
+    return hipSuccess;
+}
+
+void dims_at(const int* d0, int l, int* d) {
+    d[0] = d0[0];
+    d[1] = d0[1] >> l;
+    d[2] = d0[2] >> l;
+    d[3] = d0[3] >> l;
+}
+
+long long nvox(const int* d) { return (long long)d[0] * d[1] * d[2] * d[3]; }
+
+int check_dims(const sde_nn* n, int B, int D, int H, int W) {
+    const int m = 1 << (n->L - 1);
+    NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
+    NN_CHECK(D % m == 0 && H % m == 0 && W % m == 0,
+             "D, H, W must be multiples of 2^(levels-1)");
+    NN_CHECK((long long)B * D * H * W <= n->max_nv0, "volume exceeds the network's buffers");
+    return SDE_OK;
+}
+
+// conv + LeakyReLU into bf16
+int conv_act(sde_nn* n, const uint16_t* x, const ConvP& cp, const int* d, uint16_t* y) {
+    NN_TRY(conv_fwd(x, n->P16 + cp.w, n->P + cp.b, d, cp.ci, cp.co, n->cfg.leaky_alpha, 1, y,
+                    nullptr, 0, library_stream()));
+    return SDE_OK;
+}
+
+int run_forward(sde_nn* n, const int* d0) {
+    hipStream_t s = library_stream();
+    int d[4], dc[4];
+    for (int l = 0; l < n->L; ++l) {
+        dims_at(d0, l, d);
+        Level& v = n->lv[l];
+        const uint16_t* in = n->x16;
+        if (l > 0) {
+            NN_TRY(pool_fwd(n->lv[l - 1].eb, d, n->c[l - 1], v.pin, s));
+            in = v.pin;
+        }
+        if (int r = conv_act(n, in, n->enc_a[l], d, v.ea)) return r;
+        if (int r = conv_act(n, v.ea, n->enc_b[l], d, v.eb)) return r;
+    }
+    const uint16_t* top = n->lv[n->L - 1].eb;
+    for (int l = n->L - 2; l >= 0; --l) {
+        dims_at(d0, l, d);
+        dims_at(d0, l + 1, dc);
+        (void)dc;
+        Level& v = n->lv[l];
+        const int Cf = n->c[l] + n->c[l + 1];
+        NN_TRY(copy_channels(v.eb, nvox(d), n->c[l], Cf, 0, v.cat, s));
+        NN_TRY(up_fwd(top, d, n->c[l + 1], Cf, n->c[l], v.cat, s));
+        if (int r = conv_act(n, v.cat, n->dec_a[l], d, v.da)) return r;
+        if (int r = conv_act(n, v.da, n->dec_b[l], d, v.db)) return r;
+        top = v.db;
+    }
+    NN_TRY(head_fwd(top, n->P + n->head_w, n->P + n->head_b, n->resid, nvox(d0), n->c0, n->out, s));
+    return SDE_OK;
+}
+
+// backward through conv + LeakyReLU: weight/bias gradients into G, input
+// gradient (FP32) into dx when non-null
+int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, const ConvP& cp,
+             const int* d, float* dx) {
+    hipStream_t s = library_stream();
+    NN_TRY(lrelu_bwd(dy, y, n->cfg.leaky_alpha, nvox(d) * cp.co, n->dz, s));
+    const int chunk = wgrad_chunk_for(d, cp.ci, cp.co, kMaxPartFloats);
+    NN_TRY(wgrad(n->dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
+    if (dx) {
+        NN_TRY(flip_transpose(n->P16 + cp.w, n->wt, cp.ci, cp.co, s));
+        NN_TRY(conv_fwd(n->dz, n->wt, nullptr, d, cp.co, cp.ci, 0.0f, 0, nullptr, dx, 0, s));
+    }
+    return SDE_OK;
+}
+
+int run_backward(sde_nn* n, const int* d0) {
+    hipStream_t s = library_stream();
+    const int L = n->L;
+    int d[4], dc[4];
+    const long long nv0 = nvox(d0);
+    const uint16_t* top0 = L > 1 ? n->lv[0].db : n->lv[0].eb;
+    float* gtop0 = L > 1 ? n->lv[0].gDb : n->lv[0].gE;
+    NN_TRY(head_bwd(n->out /* holds dL/dout */, top0, n->P + n->head_w, nv0, n->c0, gtop0,
+                    n->head_part, s));
+    NN_TRY(sum_rows(n->head_part, head_bwd_blocks(nv0), n->c0 + 1, n->G + n->head_w, s));
+    for (int l = 0; l <= L - 2; ++l) {
+        dims_at(d0, l, d);
+        dims_at(d0, l + 1, dc);
+        Level& v = n->lv[l];
+        const int Cf = n->c[l] + n->c[l + 1];
+        if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa)) return r;
+        if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, v.gCat)) return r;
+        NN_TRY(slice_copy(v.gCat, nvox(d), n->c[l], Cf, 0, v.gE, s));
+        float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
+        NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s));
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        dims_at(d0, l, d);
+        Level& v = n->lv[l];
+        if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, v.gEa)) return r;
+        const uint16_t* in = l == 0 ? n->x16 : v.pin;
+        if (int r = conv_bwd(n, v.gEa, v.ea, in, n->enc_a[l], d, l > 0 ? v.gP : nullptr)) return r;
+        if (l > 0) {
+            int df[4];
+            dims_at(d0, l - 1, df);
+            NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gE, s));
+        }
+    }
+    return SDE_OK;
+}
+
+int alloc_all(sde_nn* n) {
+    const sde_nn_config& c = n->cfg;
+    const int L = n->L;
+    n->max_nv0 = (long long)c.max_batch * c.max_d * c.max_h * c.max_w;
+    NN_TRY(dalloc(n, &n->P, n->n_params));
+    NN_TRY(dalloc(n, &n->P16, n->n_params));
+    NN_TRY(hipMemset(n->P, 0, sizeof(float) * n->n_params));
+    NN_TRY(hipMemset(n->P16, 0, sizeof(uint16_t) * n->n_params));
+    NN_TRY(dalloc(n, &n->x16, n->max_nv0 * n->cin));
+    NN_TRY(dalloc(n, &n->resid, n->max_nv0));
+    NN_TRY(dalloc(n, &n->out, n->max_nv0));
+    NN_TRY(dalloc(n, &n->maxbits, 1));
+    n->lv.assign(L, Level{});
+    for (int l = 0; l < L; ++l) {
+        const long long nv = n->max_nv0 >> (3 * l);
+        Level& v = n->lv[l];
+        NN_TRY(dalloc(n, &v.ea, nv * n->c[l]));
+        NN_TRY(dalloc(n, &v.eb, nv * n->c[l]));
+        if (l > 0) NN_TRY(dalloc(n, &v.pin, nv * n->c[l - 1]));
+        if (l <= L - 2) {
+            NN_TRY(dalloc(n, &v.cat, nv * (n->c[l] + n->c[l + 1])));
+            NN_TRY(dalloc(n, &v.da, nv * n->c[l]));
+            NN_TRY(dalloc(n, &v.db, nv * n->c[l]));
+        }
+        if (!c.train) continue;
+        NN_TRY(dalloc(n, &v.gE, nv * n->c[l]));
+        NN_TRY(dalloc(n, &v.gEa, nv * n->c[l]));
+        if (l > 0) NN_TRY(dalloc(n, &v.gP, nv * n->c[l - 1]));
+        if (l <= L - 2) {
+            NN_TRY(dalloc(n, &v.gCat, nv * (n->c[l] + n->c[l + 1])));
+            NN_TRY(dalloc(n, &v.gDa, nv * n->c[l]));
+            NN_TRY(dalloc(n, &v.gDb, nv * n->c[l]));
+        }
+    }
+    if (!c.train) return SDE_OK;
+    long long max_w = 0;
+    for (auto* vec : {&n->enc_a, &n->enc_b, &n->dec_a, &n->dec_b})
+        for (const ConvP& cp : *vec) max_w = std::max<long long>(max_w, 27LL * cp.ci * cp.co);
+    NN_TRY(dalloc(n, &n->G, n->n_params));
+    NN_TRY(dalloc(n, &n->M, n->n_params));
+    NN_TRY(dalloc(n, &n->V, n->n_params));
+    NN_TRY(hipMemset(n->G, 0, sizeof(float) * n->n_params));
+    NN_TRY(hipMemset(n->M, 0, sizeof(float) * n->n_params));
+    NN_TRY(hipMemset(n->V, 0, sizeof(float) * n->n_params));
+    NN_TRY(dalloc(n, &n->dz, n->max_nv0 * n->c0));
+    NN_TRY(dalloc(n, &n->wt, max_w));
+    NN_TRY(dalloc(n, &n->wpart, std::max(kMaxPartFloats, max_w)));
+    NN_TRY(dalloc(n, &n->dout, n->max_nv0));
+    NN_TRY(dalloc(n, &n->loss_part, mse_blocks(n->max_nv0)));
+    NN_TRY(dalloc(n, &n->loss_dev, 1));
+    NN_TRY(dalloc(n, &n->head_part, (long long)head_bwd_blocks(n->max_nv0) * (n->c0 + 1)));
+    return SDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sde_nn_create(const sde_nn_config* cfg, sde_nn** out) {
+    NN_CHECK(cfg && out, "null argument");
+    *out = nullptr;
+    const sde_nn_config& c = *cfg;
+    NN_CHECK(c.levels >= 1 && c.levels <= 5, "levels must be 1..5");
+    NN_CHECK(c.base_channels == 16 || c.base_channels == 32, "base_channels must be 16 or 32");
+    NN_CHECK(c.in_channels >= 16 && c.in_channels % 16 == 0, "in_channels must be a multiple of 16");
+    NN_CHECK(c.leaky_alpha > 0.0f, "leaky_alpha must be positive");
+    NN_CHECK(c.max_batch >= 1 && c.max_d >= 1 && c.max_h >= 1 && c.max_w >= 1,
+             "maximum sizes must be positive");
+    const int m = 1 << (c.levels - 1);
+    NN_CHECK(c.max_d % m == 0 && c.max_h % m == 0 && c.max_w % m == 0,
+             "maximum D, H, W must be multiples of 2^(levels-1)");
+    sde_nn* n = new sde_nn();
+    n->cfg = c;
+    n->L = c.levels;
+    n->c0 = c.base_channels;
+    n->cin = c.in_channels;
+    for (int l = 0; l < n->L; ++l) n->c.push_back(n->c0 << l);
+    long long off = 0;
+    auto conv = [&](int ci, int co) {
+        ConvP p;
+        p.ci = ci;
+        p.co = co;
+        p.w = off;
+        off += 27LL * ci * co;
+        p.b = off;
+        off += co;
+        return p;
+    };
+    n->dec_a.resize(std::max(0, n->L - 1));
+    n->dec_b.resize(std::max(0, n->L - 1));
+    for (int l = 0; l < n->L; ++l) {
+        n->enc_a.push_back(conv(l == 0 ? n->cin : n->c[l - 1], n->c[l]));
+        n->enc_b.push_back(conv(n->c[l], n->c[l]));
+    }
+    for (int l = n->L - 2; l >= 0; --l) {
+        n->dec_a[l] = conv(n->c[l] + n->c[l + 1], n->c[l]);
+        n->dec_b[l] = conv(n->c[l], n->c[l]);
+    }
+    n->head_w = off;
+    off += n->c0;
+    n->head_b = off;
+    off += 1;
+    n->n_params = off;
+    bool ok = true;
+    for (auto* vec : {&n->enc_a, &n->enc_b, &n->dec_a, &n->dec_b})
+        for (const ConvP& cp : *vec)
+            ok = ok && nt_ok(cp.co) && nt_ok(cp.ci) && (cp.co / 16) * (cp.ci / 16) <= 128;
+    if (!ok) {
+        delete n;
+        return report_error(SDE_E_INVALID, "channel counts outside the kernels' tile set");
+    }
+    n->cfg.adam_beta1 = c.adam_beta1 > 0 ? c.adam_beta1 : 0.9f;
+    n->cfg.adam_beta2 = c.adam_beta2 > 0 ? c.adam_beta2 : 0.999f;
+    n->cfg.adam_eps = c.adam_eps > 0 ? c.adam_eps : 1e-8f;
+    if (int r = alloc_all(n)) {
+        delete n;
+        return r;
+    }
+    *out = n;
+    return SDE_OK;
+}
+
+int sde_nn_destroy(sde_nn* net) {
+    if (net) {
+        (void)hipStreamSynchronize(library_stream());
+        delete net;
+    }
+    return SDE_OK;
+}
+
+int sde_nn_param_count(const sde_nn* net, int64_t* n_out) {
+    NN_CHECK(net && n_out, "null argument");
+    *n_out = net->n_params;
+    return SDE_OK;
+}
+
+int sde_nn_set_params(sde_nn* net, const float* params, int64_t n) {
+    NN_CHECK(net && params, "null argument");
+    NN_CHECK(n == net->n_params, "parameter count mismatch");
+    hipStream_t s = library_stream();
+    NN_TRY(hipMemcpyAsync(net->P, params, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    NN_TRY(f32_to_bf16(net->P, n, net->P16, s));
+    NN_TRY(hipStreamSynchronize(s));
+    return SDE_OK;
+}
+
+int sde_nn_get_params(sde_nn* net, float* params, int64_t n) {
+    NN_CHECK(net && params, "null argument");
+    NN_CHECK(n == net->n_params, "parameter count mismatch");
+    hipStream_t s = library_stream();
+    NN_TRY(hipMemcpyAsync(params, net->P, sizeof(float) * n, hipMemcpyDeviceToHost, s));
+    NN_TRY(hipStreamSynchronize(s));
+    return SDE_OK;
+}
+
+int sde_nn_set_adam_state(sde_nn* net, const float* m, const float* v, int64_t n, int64_t step) {
+    NN_CHECK(net && m && v, "null argument");
+    NN_CHECK(net->cfg.train, "network was created without training buffers");
+    NN_CHECK(n == net->n_params && step >= 0, "parameter count mismatch or negative step");
+    hipStream_t s = library_stream();
+    NN_TRY(hipMemcpyAsync(net->M, m, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    NN_TRY(hipMemcpyAsync(net->V, v, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    NN_TRY(hipStreamSynchronize(s));
+    net->step = step;
+    return SDE_OK;
+}
+
+int sde_nn_get_adam_state(sde_nn* net, float* m, float* v, int64_t n, int64_t* step) {
+    NN_CHECK(net && m && v && step, "null argument");
+    NN_CHECK(net->cfg.train, "network was created without training buffers");
+    NN_CHECK(n == net->n_params, "parameter count mismatch");
+    hipStream_t s = library_stream();
+    NN_TRY(hipMemcpyAsync(m, net->M, sizeof(float) * n, hipMemcpyDeviceToHost, s));
+    NN_TRY(hipMemcpyAsync(v, net->V, sizeof(float) * n, hipMemcpyDeviceToHost, s));
+    NN_TRY(hipStreamSynchronize(s));
+    *step = net->step;
+    return SDE_OK;
+}
+
+int sde_nn_get_grads(sde_nn* net, float* grads, int64_t n) {
+    NN_CHECK(net && grads, "null argument");
+    NN_CHECK(net->cfg.train, "network was created without training buffers");
+    NN_CHECK(n == net->n_params, "parameter count mismatch");
+    hipStream_t s = library_stream();
+    NN_TRY(hipMemcpyAsync(grads, net->G, sizeof(float) * n, hipMemcpyDeviceToHost, s));
+    NN_TRY(hipStreamSynchronize(s));
+    return SDE_OK;
+}
+
+int sde_nn_forward(sde_nn* net, const float* dose, const float* rho, int B, int D, int H, int W,
+                   float* out) {
+    NN_CHECK(net && dose && out, "null argument");
+    if (int r = check_dims(net, B, D, H, W)) return r;
+    const int d0[4] = {B, D, H, W};
+    hipStream_t s = library_stream();
+    NN_TRY(assemble_f32(dose, rho, nvox(d0), net->cin, net->x16, net->resid, s));
+    if (int r = run_forward(net, d0)) return r;
+    NN_TRY(hipMemcpyAsync(out, net->out, sizeof(float) * nvox(d0), hipMemcpyDeviceToDevice, s));
+    return SDE_OK;
+}
+
+int sde_nn_loss_grad(sde_nn* net, const float* dose, const float* rho, const float* target,
+                     const float* weight, int B, int D, int H, int W, float* loss_out) {
+    NN_CHECK(net && dose && target && loss_out, "null argument");
+    NN_CHECK(net->cfg.train, "network was created without training buffers");
+    if (int r = check_dims(net, B, D, H, W)) return r;
+    const int d0[4] = {B, D, H, W};
+    const long long nv0 = nvox(d0);
+    hipStream_t s = library_stream();
+    NN_TRY(assemble_f32(dose, rho, nv0, net->cin, net->x16, net->resid, s));
+    if (int r = run_forward(net, d0)) return r;
+    // dL/dout overwrites the output buffer (the forward result is not kept)
+    NN_TRY(mse(net->out, target, weight, nv0, net->out, net->loss_part, s));
+    NN_TRY(sum_rows(net->loss_part, mse_blocks(nv0), 1, net->loss_dev, s));
+    if (int r = run_backward(net, d0)) return r;
+    NN_TRY(hipMemcpyAsync(loss_out, net->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s));
+    NN_TRY(hipStreamSynchronize(s));
+    net->have_grad = true;
+    return SDE_OK;
+}
+
+int sde_nn_adam_step(sde_nn* net, float lr) {
+    NN_CHECK(net, "null argument");
+    NN_CHECK(net->cfg.train, "network was created without training buffers");
+    NN_CHECK(net->have_grad, "no gradient: call sde_nn_loss_grad first");
+    NN_CHECK(lr > 0.0f, "learning rate must be positive");
+    net->step += 1;
+    NN_TRY(adam(net->P, net->G, net->M, net->V, net->n_params, lr, net->cfg.adam_beta1,
+                net->cfg.adam_beta2, net->cfg.adam_eps, (int)std::min<long long>(net->step, 1 << 30),
+                net->P16, library_stream()));
+    return SDE_OK;
+}
+
+int sde_nn_denoise(sde_nn* net, const double* dose, const float* rho, int nx, int ny, int nz,
+                   double* out) {
+    NN_CHECK(net && dose && out, "null argument");
+    NN_CHECK(nx >= 1 && ny >= 1 && nz >= 1, "grid sizes must be positive");
+    const int m = 1 << (net->L - 1);
+    const int D = (nz + m - 1) / m * m, H = (ny + m - 1) / m * m, W = (nx + m - 1) / m * m;
+    if (int r = check_dims(net, 1, D, H, W)) return r;
+    const int d0[4] = {1, D, H, W};
+    const int src[3] = {nz, ny, nx}, dst[3] = {D, H, W};
+    hipStream_t s = library_stream();
+    NN_TRY(fill_u32((uint32_t*)net->maxbits, 2, 0u, s));
+    NN_TRY(max_abs(dose, (long long)nx * ny * nz, net->maxbits, s));
+    const double* maxp = (const double*)net->maxbits;
+    NN_TRY(assemble_grid(dose, rho, src, dst, maxp, net->cin, net->x16, net->resid, s));
+    if (int r = run_forward(net, d0)) return r;
+    NN_TRY(finish_grid(net->out, src, dst, maxp, out, s));
+    return SDE_OK;
+}
+
+int sde_nn_conv3d_fwd(const uint16_t* x, const uint16_t* w, const float* bias, int B, int D,
+                      int H, int W, int Ci, int Co, float alpha, int act, uint16_t* y16,
+                      float* y32) {
+    NN_CHECK(x && w && (y16 || y32), "null argument");
+    NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
+    NN_CHECK(Ci >= 16 && Ci % 16 == 0 && nt_ok(Co), "unsupported channel counts");
+    const int d[4] = {B, D, H, W};
+    NN_TRY(conv_fwd(x, w, bias, d, Ci, Co, alpha, act ? 1 : 0, y16, y32, 0, library_stream()));
+    return SDE_OK;
+}
+
+int sde_nn_conv3d_workspace(int B, int D, int H, int W, int Ci, int Co, size_t* bytes) {
+    NN_CHECK(bytes, "null argument");
+    NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
+    NN_CHECK(Ci >= 16 && Ci % 16 == 0 && Co >= 16 && Co % 16 == 0, "unsupported channel counts");
+    const int d[4] = {B, D, H, W};
+    const long long wfl = 27LL * Ci * Co;
+    const int chunk = wgrad_chunk_for(d, Ci, Co, kMaxPartFloats);
+    const long long part = wgrad_chunks(d, chunk) * wfl * (long long)sizeof(float);
+    *bytes = (size_t)std::max<long long>(part, wfl * (long long)sizeof(uint16_t));
+    return SDE_OK;
+}
+
+int sde_nn_conv3d_dgrad(const uint16_t* dz, const uint16_t* w, int B, int D, int H, int W, int Ci,
+                        int Co, float* dx, void* workspace, size_t workspace_bytes) {
+    NN_CHECK(dz && w && dx && workspace, "null argument");
+    NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
+    NN_CHECK(Co >= 16 && Co % 16 == 0 && nt_ok(Ci), "unsupported channel counts");
+    NN_CHECK(workspace_bytes >= 27ULL * Ci * Co * sizeof(uint16_t), "workspace too small");
+    const int d[4] = {B, D, H, W};
+    hipStream_t s = library_stream();
+    uint16_t* wt = (uint16_t*)workspace;
+    NN_TRY(flip_transpose(w, wt, Ci, Co, s));
+    NN_TRY(conv_fwd(dz, wt, nullptr, d, Co, Ci, 0.0f, 0, nullptr, dx, 0, s));
+    return SDE_OK;
+}
+
+int sde_nn_conv3d_wgrad(const uint16_t* dz, const uint16_t* x, int B, int D, int H, int W, int Ci,
+                        int Co, float* dw, float* db, void* workspace, size_t workspace_bytes) {
+    NN_CHECK(dz && x && dw && workspace, "null argument");
+    NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
+    NN_CHECK(Ci >= 16 && Ci % 16 == 0 && Co >= 16 && Co % 16 == 0 &&
+                 (Co / 16) * (Ci / 16) <= 128,
+             "unsupported channel counts");
+    size_t need = 0;
+    if (int r = sde_nn_conv3d_workspace(B, D, H, W, Ci, Co, &need)) return r;
+    NN_CHECK(workspace_bytes >= need, "workspace too small");
+    const int d[4] = {B, D, H, W};
+    const int chunk = wgrad_chunk_for(d, Ci, Co, kMaxPartFloats);
+    NN_TRY(wgrad(dz, x, d, Ci, Co, chunk, (float*)workspace, dw, db, library_stream()));
+    return SDE_OK;
+}
+
+}  // extern "C"

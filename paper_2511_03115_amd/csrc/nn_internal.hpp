@@ -1,0 +1,71 @@
+// Launchers of the denoiser kernels (nn_kernels.hip), used by nn_api.cpp.
+// Volumes are channels-last [B][D][H][W][C]; dims = {B, D, H, W}.  bf16
+// values travel as uint16_t bit patterns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sde {
+namespace nn {
+
+// 3x3x3 conv, zero padding 1; y = act(conv(x, w) + bias) to bf16 y16 and/or
+// FP32 y32 (y32 += result when accumulate).  Ci % 8 == 0, Co % 16 == 0 and
+// Co / 16 in {1, 2, 3, 4, 6, 8, 12}.  bias may be null; act = LeakyReLU(alpha).
+hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
+                    int Ci, int Co, float alpha, int act, uint16_t* y16, float* y32,
+                    int accumulate, hipStream_t s);
+// wt[ci][26 - t][co] = w[co][t][ci] (weights of the input-gradient conv)
+hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
+// weight gradient: part needs wgrad_chunks * 27 * Co * Ci floats; dw [Co][27][Ci],
+// db [Co] (nullable).  Ci % 16 == 0, Co % 16 == 0, chunk % 32 == 0.
+long long wgrad_chunks(const int* dims, int chunk);
+int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats);
+hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
+                 float* part, float* dw, float* db, hipStream_t s);
+hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n, uint16_t* dz,
+                     hipStream_t s);
+hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, hipStream_t s);
+hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s);
+hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0, uint16_t* y,
+                  hipStream_t s);
+hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
+                  hipStream_t s);
+hipError_t copy_channels(const uint16_t* x, long long nv, int C, int Cf, int c0, uint16_t* y,
+                         hipStream_t s);
+hipError_t slice_copy(const float* dy, long long nv, int C, int Cf, int c0, float* dx,
+                      hipStream_t s);
+// network input from normalised FP32 maps (rho nullable): channel 0 dose,
+// channel 1 density, the rest zero; resid = dose
+hipError_t assemble_f32(const float* dose, const float* rho, long long nv, int Cx, uint16_t* x,
+                        float* resid, hipStream_t s);
+// network input from a dose grid [nz][ny][nx] (FP64) divided by *maxp, zero
+// padded into [D][H][W]; rho (FP32, nullable) padded likewise
+hipError_t assemble_grid(const double* dose, const float* rho, const int* src, const int* dst,
+                         const double* maxp, int Cx, uint16_t* x, float* resid, hipStream_t s);
+// out (FP64 [nz][ny][nx]) = max(0, net[D][H][W] cropped) * (*maxp)
+hipError_t finish_grid(const float* net, const int* src, const int* dst, const double* maxp,
+                       double* out, hipStream_t s);
+hipError_t max_abs(const double* a, long long n, unsigned long long* out_bits, hipStream_t s);
+hipError_t head_fwd(const uint16_t* x, const float* w, const float* b, const float* resid,
+                    long long nv, int C, float* out, hipStream_t s);
+int head_bwd_blocks(long long nv);
+hipError_t head_bwd(const float* dout, const uint16_t* x, const float* w, long long nv, int C,
+                    float* dx, float* part, hipStream_t s);
+int mse_blocks(long long n);
+hipError_t mse(const float* out, const float* tgt, const float* wgt, long long n, float* dout,
+               float* part, hipStream_t s);
+// out[c] = sum_r part[r * ncol + c] for r < nrow (fixed order)
+hipError_t sum_rows(const float* part, int nrow, int ncol, float* out, hipStream_t s);
+hipError_t adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                float b2, float eps, int step, uint16_t* p16, hipStream_t s);
+hipError_t f32_to_bf16(const float* a, long long n, uint16_t* b, hipStream_t s);
+hipError_t fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
+
+}  // namespace nn
+
+// the library's current stream and error reporting (sde_api.cpp)
+hipStream_t library_stream();
+int report_error(int code, const char* msg);
+
+}  // namespace sde

@@ -1,0 +1,704 @@
+// HIP kernels of the dose denoiser for gfx950: a 3D convolutional
+// encoder-decoder trained and run entirely on these kernels.
+//
+// Tensors are channels-last volumes [B][D][H][W][C]; activations and conv
+// weights are bf16, accumulation FP32 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), gradients and master weights FP32.
+//
+// MFMA 16x16x32 bf16 operand layout (lane l of a wave64, i = 0..7 / 0..3):
+//   A[m = l%16][k = (l/16)*8 + i],  B[k = (l/16)*8 + i][n = l%16],
+//   D[m = (l/16)*4 + i][n = l%16].
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nn_internal.hpp"
+
+namespace sde {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// float -> bf16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+struct Geo {
+    int B, D, H, W;
+    __host__ __device__ __forceinline__ long long nvox() const { return (long long)B * D * H * W; }
+};
+
+// Voxel v shifted by tap t (t = (dz+1)*9 + (dy+1)*3 + (dx+1)) or -1 outside.
+__device__ __forceinline__ long long shifted(const Geo& g, long long v, int t) {
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)((v / ((long long)g.W * g.H)) % g.D);
+    const int xs = x + dx, ys = y + dy, zs = z + dz;
+    if (xs < 0 || ys < 0 || zs < 0 || xs >= g.W || ys >= g.H || zs >= g.D) return -1;
+    return v + dx + (long long)dy * g.W + (long long)dz * g.W * g.H;
+}
+
+// ---------------------------------------------------------------------------
+// conv3d 3x3x3, zero padding 1, stride 1: y[v][co] = act(bias[co] +
+//   sum_{t, ci} x[shift(v, t)][ci] w[co][t][ci]).
+// Implicit GEMM: M = voxels, N = Co, K = 27 Ci (k = t*Ci + ci).  One wave owns
+// 16 voxels and all Co (Co/16 accumulator tiles); a workgroup has 4 waves.
+// Outputs: bf16 (optional) and/or FP32 (optional, added to when accumulate).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_fwd(const uint16_t* __restrict__ x,
+                                                  const uint16_t* __restrict__ w,
+                                                  const float* __restrict__ bias, Geo g, int Ci,
+                                                  int Co, float alpha, int act,
+                                                  uint16_t* __restrict__ y16,
+                                                  float* __restrict__ y32, int accumulate) {
+    const int lane = threadIdx.x & 63;
+    const long long base = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    const long long nv = g.nvox();
+    if (base >= nv) return;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const long long vrow = base + (lane & 15);   // A row of this lane
+    const int K = 27 * Ci;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int kk = k0 + (lane >> 4) * 8;      // first k of this lane's 8
+        uint4 av = make_uint4(0, 0, 0, 0);
+        int t = 0, ci = 0;
+        const bool kin = kk < K;
+        if (kin) {
+            t = kk / Ci;
+            ci = kk - t * Ci;
+            if (vrow < nv) {
+                const long long s = shifted(g, vrow, t);
+                if (s >= 0) av = *reinterpret_cast<const uint4*>(x + s * Ci + ci);
+            }
+        }
+        const bf16x8 a = as_bf16x8(av);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = j * 16 + (lane & 15);
+            uint4 bv = make_uint4(0, 0, 0, 0);
+            if (kin && co < Co) bv = *reinterpret_cast<const uint4*>(w + ((size_t)co * 27 + t) * Ci + ci);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(bv), acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = j * 16 + (lane & 15);
+        if (co >= Co) continue;
+        const float b = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long v = base + (lane >> 4) * 4 + i;
+            if (v >= nv) continue;
+            float r = acc[j][i] + b;
+            if (act) r = r > 0.0f ? r : alpha * r;
+            if (y16) y16[v * Co + co] = f2bf(r);
+            if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + r : r;
+        }
+    }
+}
+
+// wt[ci][26 - t][co] = w[co][t][ci]: the weights of the input-gradient conv.
+__global__ void k_flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co) {
+    const int n = Co * 27 * Ci;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int ci = i % Ci, t = (i / Ci) % 27, co = i / (27 * Ci);
+        wt[((size_t)ci * 27 + (26 - t)) * Co + co] = w[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient, split over voxel chunks: part[c][t][co][ci] =
+//   sum_{v in chunk c} dz[v][co] x[shift(v, t)][ci].  Workgroup = (chunk, tap).
+// 32-voxel slices of dz and of the shifted x are staged transposed in LDS
+// ([channel][voxel], rows padded to 40 elements so that the 16 rows a
+// quarter-wave reads fall on distinct banks); each lane reads its 8
+// consecutive voxels in one 16-byte load.  Waves own 16x16 (co, ci) tiles.
+// ---------------------------------------------------------------------------
+constexpr int kWgMaxTiles = 16;
+constexpr int kWgRow = 40;
+
+__global__ void __launch_bounds__(512) k_wgrad_partial(const uint16_t* __restrict__ dz,
+                                                       const uint16_t* __restrict__ x, Geo g,
+                                                       int Ci, int Co, int chunk,
+                                                       float* __restrict__ part) {
+    extern __shared__ __align__(16) uint16_t lds[];   // [Co][kWgRow] then [Ci][kWgRow]
+    uint16_t* dzT = lds;
+    uint16_t* xT = lds + Co * kWgRow;
+    const int t = blockIdx.y;
+    const long long c = blockIdx.x;
+    const long long v0 = c * chunk;
+    const long long nv = g.nvox();
+    const long long v1 = v0 + chunk < nv ? v0 + chunk : nv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int tci = Ci / 16, ntiles = (Co / 16) * tci;
+    f32x4 acc[kWgMaxTiles];
+#pragma unroll
+    for (int j = 0; j < kWgMaxTiles; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (long long s0 = v0; s0 < v1; s0 += 32) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 32 * Co; i += blockDim.x) {
+            const int vv = i / Co, ch = i - vv * Co;
+            const long long v = s0 + vv;
+            dzT[ch * kWgRow + vv] = v < v1 ? dz[v * Co + ch] : (uint16_t)0;
+        }
+        for (int i = threadIdx.x; i < 32 * Ci; i += blockDim.x) {
+            const int vv = i / Ci, ch = i - vv * Ci;
+            const long long v = s0 + vv;
+            uint16_t val = 0;
+            if (v < v1) {
+                const long long sv = shifted(g, v, t);
+                if (sv >= 0) val = x[sv * Ci + ch];
+            }
+            xT[ch * kWgRow + vv] = val;
+        }
+        __syncthreads();
+        const int koff = (lane >> 4) * 8;
+#pragma unroll
+        for (int j = 0; j < kWgMaxTiles; ++j) {
+            const int tile = wave + j * nwaves;
+            if (tile >= ntiles) break;
+            const int co0 = (tile / tci) * 16, ci0 = (tile % tci) * 16;
+            const uint4 av = *reinterpret_cast<const uint4*>(dzT + (co0 + (lane & 15)) * kWgRow + koff);
+            const uint4 bv = *reinterpret_cast<const uint4*>(xT + (ci0 + (lane & 15)) * kWgRow + koff);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc[j],
+                                                             0, 0, 0);
+        }
+    }
+    float* out = part + ((size_t)c * 27 + t) * Co * Ci;
+#pragma unroll
+    for (int j = 0; j < kWgMaxTiles; ++j) {
+        const int tile = wave + j * nwaves;
+        if (tile >= ntiles) break;
+        const int co0 = (tile / tci) * 16, ci0 = (tile % tci) * 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            out[(size_t)(co0 + (lane >> 4) * 4 + i) * Ci + ci0 + (lane & 15)] = acc[j][i];
+    }
+}
+
+// dW[co][t][ci] = sum_c part[c][t][co][ci] (fixed order: deterministic).
+__global__ void k_wgrad_reduce(const float* part, int nchunk, int Ci, int Co, float* dw) {
+    const int n = 27 * Co * Ci;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int ci = i % Ci, co = (i / Ci) % Co, t = i / (Ci * Co);
+        float s = 0.0f;
+        for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
+        dw[((size_t)co * 27 + t) * Ci + ci] = s;
+    }
+}
+
+// db[co] = sum_v dz[v][co], one block per channel (fixed order within the block).
+__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* dz, long long nv, int Co,
+                                                   float* db) {
+    const int co = blockIdx.x;
+    float s = 0.0f;
+    for (long long v = threadIdx.x; v < nv; v += blockDim.x) s += bf2f(dz[v * Co + co]);
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] = red[0];
+}
+
+// dz = dy * (y > 0 ? 1 : alpha), in bf16 (LeakyReLU backward from the output sign).
+__global__ void k_lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n,
+                            uint16_t* dz) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float yy = bf2f(y[i]);
+        dz[i] = f2bf(yy > 0.0f ? dy[i] : alpha * dy[i]);
+    }
+}
+
+// 2x2x2 average pooling (dims even): y[b][z][y][x][c] = mean of the 8 children.
+__global__ void k_pool_fwd(const uint16_t* x, Geo go, int C, uint16_t* y) {
+    const long long n = go.nvox() * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int xo = (int)(v % go.W), yo = (int)((v / go.W) % go.H);
+        const int zo = (int)((v / ((long long)go.W * go.H)) % go.D);
+        const long long b = v / ((long long)go.W * go.H * go.D);
+        const int Wi = go.W * 2, Hi = go.H * 2, Di = go.D * 2;
+        float s = 0.0f;
+        for (int d = 0; d < 8; ++d) {
+            const long long vi = (((b * Di + 2 * zo + (d >> 2)) * Hi + 2 * yo + ((d >> 1) & 1)) * Wi +
+                                  2 * xo + (d & 1));
+            s += bf2f(x[vi * C + c]);
+        }
+        y[i] = f2bf(0.125f * s);
+    }
+}
+
+// Pooling backward: dx (FP32, fine grid) += dy(parent) / 8.
+__global__ void k_pool_bwd(const float* dy, Geo gi, int C, float* dx) {
+    const long long n = gi.nvox() * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int xi = (int)(v % gi.W), yi = (int)((v / gi.W) % gi.H);
+        const int zi = (int)((v / ((long long)gi.W * gi.H)) % gi.D);
+        const long long b = v / ((long long)gi.W * gi.H * gi.D);
+        const int Wo = gi.W / 2, Ho = gi.H / 2, Do = gi.D / 2;
+        const long long vo = ((b * Do + zi / 2) * Ho + yi / 2) * Wo + xi / 2;
+        dx[i] += 0.125f * dy[vo * C + c];
+    }
+}
+
+// Nearest x2 upsampling of a coarse tensor into channels [c0, c0+C) of a fine
+// tensor with Cf channels (the up half of a concatenation).
+__global__ void k_up_fwd(const uint16_t* x, Geo gf, int C, int Cf, int c0, uint16_t* y) {
+    const long long n = gf.nvox() * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int xf = (int)(v % gf.W), yf = (int)((v / gf.W) % gf.H);
+        const int zf = (int)((v / ((long long)gf.W * gf.H)) % gf.D);
+        const long long b = v / ((long long)gf.W * gf.H * gf.D);
+        const long long vc = ((b * (gf.D / 2) + zf / 2) * (gf.H / 2) + yf / 2) * (gf.W / 2) + xf / 2;
+        y[v * Cf + c0 + c] = x[vc * C + c];
+    }
+}
+
+// Upsampling backward: dx(coarse) = sum over the 8 children of dy[.][c0 + c].
+__global__ void k_up_bwd(const float* dy, Geo gc, int C, int Cf, int c0, float* dx) {
+    const long long n = gc.nvox() * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int xc = (int)(v % gc.W), yc = (int)((v / gc.W) % gc.H);
+        const int zc = (int)((v / ((long long)gc.W * gc.H)) % gc.D);
+        const long long b = v / ((long long)gc.W * gc.H * gc.D);
+        const int Wf = gc.W * 2, Hf = gc.H * 2, Df = gc.D * 2;
+        float s = 0.0f;
+        for (int d = 0; d < 8; ++d) {
+            const long long vf = (((b * Df + 2 * zc + (d >> 2)) * Hf + 2 * yc + ((d >> 1) & 1)) * Wf +
+                                  2 * xc + (d & 1));
+            s += dy[vf * Cf + c0 + c];
+        }
+        dx[i] = s;
+    }
+}
+
+// Copy channels [0, C) of x into channels [c0, c0+C) of y (Cf channels): the
+// skip half of a concatenation; and its backward (dx += dy slice).
+__global__ void k_copy_channels(const uint16_t* x, long long nv, int C, int Cf, int c0, uint16_t* y) {
+    const long long n = nv * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i / C;
+        y[v * Cf + c0 + (i % C)] = x[i];
+    }
+}
+__global__ void k_slice_copy(const float* dy, long long nv, int C, int Cf, int c0, float* dx) {
+    const long long n = nv * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i / C;
+        dx[i] = dy[v * Cf + c0 + (i % C)];
+    }
+}
+
+// Network input from normalised maps: x[v] = {dose, rho, 0, ...} (Cx channels).
+__global__ void k_assemble_f32(const float* dose, const float* rho, long long nv, int Cx,
+                               uint16_t* x, float* resid) {
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
+         v += (long long)gridDim.x * blockDim.x) {
+        const float d = dose[v];
+        resid[v] = d;
+        x[v * Cx] = f2bf(d);
+        x[v * Cx + 1] = f2bf(rho ? rho[v] : 0.0f);
+        for (int c = 2; c < Cx; ++c) x[v * Cx + c] = 0;
+    }
+}
+
+// Network input from a dose grid [nz][ny][nx] scaled by 1 / *maxp, zero
+// padded into [D][H][W] (batch 1).
+__global__ void k_assemble_grid(const double* dose, const float* rho, int nx, int ny, int nz,
+                                int W, int H, int D, const double* maxp, int Cx, uint16_t* x,
+                                float* resid) {
+    const long long nv = (long long)W * H * D;
+    const double m = *maxp;
+    const double inv = m > 0.0 ? 1.0 / m : 0.0;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
+         v += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(v % W), j = (int)((v / W) % H), k = (int)(v / ((long long)W * H));
+        float d = 0.0f, r = 0.0f;
+        if (i < nx && j < ny && k < nz) {
+            const long long u = ((long long)k * ny + j) * nx + i;
+            d = (float)(dose[u] * inv);
+            r = rho ? rho[u] : 0.0f;
+        }
+        resid[v] = d;
+        x[v * Cx] = f2bf(d);
+        x[v * Cx + 1] = f2bf(r);
+        for (int c = 2; c < Cx; ++c) x[v * Cx + c] = 0;
+    }
+}
+
+// out[nz][ny][nx] = max(0, net cropped) * (*maxp)
+__global__ void k_finish_grid(const float* net, int nx, int ny, int nz, int W, int H,
+                              const double* maxp, double* out) {
+    const long long n = (long long)nx * ny * nz;
+    const double m = *maxp;
+    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < n;
+         u += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(u % nx), j = (int)((u / nx) % ny), k = (int)(u / ((long long)nx * ny));
+        const float y = net[((long long)k * H + j) * W + i];
+        out[u] = y > 0.0f ? (double)y * m : 0.0;
+    }
+}
+
+// Maximum of |a| as the bit pattern of a non-negative double (out zeroed first).
+__global__ void k_max_abs(const double* a, long long n, unsigned long long* out) {
+    double m = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(a[i]));
+    unsigned long long b = (unsigned long long)__double_as_longlong(m);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long c = __shfl_xor(b, o);
+        b = c > b ? c : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, b);
+}
+
+// Head: out[v] = resid[v] + b + sum_c w[c] x[v][c] (1x1x1 conv to one channel).
+template <int C>
+__global__ void k_head_fwd(const uint16_t* x, const float* w, const float* b, const float* resid,
+                           long long nv, float* out) {
+    float wr[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) wr[c] = w[c];
+    const float bb = b[0];
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
+         v += (long long)gridDim.x * blockDim.x) {
+        float s = bb + resid[v];
+#pragma unroll
+        for (int c = 0; c < C; ++c) s += wr[c] * bf2f(x[v * C + c]);
+        out[v] = s;
+    }
+}
+
+// Head backward: dx[v][c] = dout[v] w[c]; per-block partial sums of dw (C) and db.
+template <int C>
+__global__ void __launch_bounds__(256) k_head_bwd(const float* dout, const uint16_t* x,
+                                                  const float* w, long long nv, float* dx,
+                                                  float* part) {
+    float s[C + 1];
+    float wr[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        s[c] = 0.0f;
+        wr[c] = w[c];
+    }
+    s[C] = 0.0f;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
+         v += (long long)gridDim.x * blockDim.x) {
+        const float d = dout[v];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            dx[v * C + c] = d * wr[c];
+            s[c] += d * bf2f(x[v * C + c]);
+        }
+        s[C] += d;
+    }
+    __shared__ float red[256];
+#pragma unroll
+    for (int c = 0; c <= C; ++c) {
+        red[threadIdx.x] = s[c];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 1) + c] = red[0];
+        __syncthreads();
+    }
+}
+
+// out[c] = sum_r part[r * ncol + c] (fixed order: deterministic)
+__global__ void k_sum_rows(const float* part, int nrow, int ncol, float* out) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int r = 0; r < nrow; ++r) s += part[(size_t)r * ncol + c];
+        out[c] = s;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Weighted squared error: loss partials and dout = 2 m (out - tgt) / n.
+__global__ void __launch_bounds__(256) k_mse(const float* out, const float* tgt, const float* wgt,
+                                             long long n, float* dout, float* part) {
+    float s = 0.0f;
+    const float inv = 1.0f / (float)n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float m = wgt ? wgt[i] : 1.0f;
+        const float d = out[i] - tgt[i];
+        s += m * d * d;
+        if (dout) dout[i] = 2.0f * m * d * inv;
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] * inv;
+}
+
+// Adam (Kingma and Ba) on FP32 master weights; refreshes the bf16 copy.
+__global__ void k_adam(float* p, const float* g, float* m, float* v, long long n, float lr,
+                       float b1, float b2, float eps, float bc1, float bc2, uint16_t* p16) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        p[i] = pi;
+        if (p16) p16[i] = f2bf(pi);
+    }
+}
+
+__global__ void k_f32_to_bf16(const float* a, long long n, uint16_t* b) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+
+inline int blocks_for(long long n, int bs = 256, int cap = 16384) {
+    long long g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
+                    int Ci, int Co, float alpha, int act, uint16_t* y16, float* y32,
+                    int accumulate, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    const long long nv = g.nvox();
+    const int grid = (int)((nv + 63) / 64);
+    const int nt = (Co + 15) / 16;
+#define LAUNCH(NT)                                                                           \
+    hipLaunchKernelGGL(k_conv_fwd<NT>, dim3(grid), dim3(256), 0, s, x, w, bias, g, Ci, Co, \
+                       alpha, act, y16, y32, accumulate)
+    switch (nt) {
+        case 1: LAUNCH(1); break;
+        case 2: LAUNCH(2); break;
+        case 3: LAUNCH(3); break;
+        case 4: LAUNCH(4); break;
+        case 6: LAUNCH(6); break;
+        case 8: LAUNCH(8); break;
+        case 12: LAUNCH(12); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s) {
+    hipLaunchKernelGGL(k_flip_transpose, dim3(blocks_for((long long)Co * 27 * Ci)), dim3(256), 0, s,
+                       w, wt, Ci, Co);
+    return hipGetLastError();
+}
+
+long long wgrad_chunks(const int* dims, int chunk) {
+    const long long nv = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    return (nv + chunk - 1) / chunk;
+}
+
+int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats) {
+    const long long nv = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    long long target = max_part_floats / (27LL * Ci * Co);
+    if (target > 128) target = 128;
+    if (target < 1) target = 1;
+    long long chunk = (nv + target - 1) / target;
+    if (chunk < 256) chunk = 256;
+    chunk = (chunk + 31) / 32 * 32;
+    return (int)chunk;
+}
+
+hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
+                 float* part, float* dw, float* db, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    const long long nchunk = wgrad_chunks(dims, chunk);
+    const int ntiles = (Co / 16) * (Ci / 16);
+    int waves = (ntiles + kWgMaxTiles - 1) / kWgMaxTiles;
+    if (waves < 4) waves = 4;
+    if (waves > 8) return hipErrorInvalidValue;
+    const size_t lds = (size_t)(Co + Ci) * kWgRow * sizeof(uint16_t);
+    hipLaunchKernelGGL(k_wgrad_partial, dim3((unsigned)nchunk, 27), dim3(64 * waves), lds, s, dz, x,
+                       g, Ci, Co, chunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(27LL * Co * Ci)), dim3(256), 0, s, part,
+                       (int)nchunk, Ci, Co, dw);
+    e = hipGetLastError();
+    if (e != hipSuccess || !db) return e;
+    hipLaunchKernelGGL(k_bias_grad, dim3(Co), dim3(256), 0, s, dz, g.nvox(), Co, db);
+    return hipGetLastError();
+}
+
+hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n, uint16_t* dz,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_lrelu_bwd, dim3(blocks_for(n)), dim3(256), 0, s, dy, y, alpha, n, dz);
+    return hipGetLastError();
+}
+
+hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, hipStream_t s) {
+    Geo g{dims_out[0], dims_out[1], dims_out[2], dims_out[3]};
+    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, x, g, C, y);
+    return hipGetLastError();
+}
+
+hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s) {
+    Geo g{dims_in[0], dims_in[1], dims_in[2], dims_in[3]};
+    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, dy, g, C, dx);
+    return hipGetLastError();
+}
+
+hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0, uint16_t* y,
+                  hipStream_t s) {
+    Geo g{dims_fine[0], dims_fine[1], dims_fine[2], dims_fine[3]};
+    hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, x, g, C, Cf, c0, y);
+    return hipGetLastError();
+}
+
+hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
+                  hipStream_t s) {
+    Geo g{dims_coarse[0], dims_coarse[1], dims_coarse[2], dims_coarse[3]};
+    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, dy, g, C, Cf, c0, dx);
+    return hipGetLastError();
+}
+
+hipError_t copy_channels(const uint16_t* x, long long nv, int C, int Cf, int c0, uint16_t* y,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_channels, dim3(blocks_for(nv * C)), dim3(256), 0, s, x, nv, C, Cf, c0, y);
+    return hipGetLastError();
+}
+
+hipError_t slice_copy(const float* dy, long long nv, int C, int Cf, int c0, float* dx,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_slice_copy, dim3(blocks_for(nv * C)), dim3(256), 0, s, dy, nv, C, Cf, c0, dx);
+    return hipGetLastError();
+}
+
+hipError_t assemble_f32(const float* dose, const float* rho, long long nv, int Cx, uint16_t* x,
+                        float* resid, hipStream_t s) {
+    if (Cx < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_assemble_f32, dim3(blocks_for(nv)), dim3(256), 0, s, dose, rho, nv, Cx, x,
+                       resid);
+    return hipGetLastError();
+}
+
+hipError_t assemble_grid(const double* dose, const float* rho, const int* src, const int* dst,
+                         const double* maxp, int Cx, uint16_t* x, float* resid, hipStream_t s) {
+    if (Cx < 2) return hipErrorInvalidValue;
+    const long long nv = (long long)dst[0] * dst[1] * dst[2];
+    hipLaunchKernelGGL(k_assemble_grid, dim3(blocks_for(nv)), dim3(256), 0, s, dose, rho, src[2],
+                       src[1], src[0], dst[2], dst[1], dst[0], maxp, Cx, x, resid);
+    return hipGetLastError();
+}
+
+hipError_t finish_grid(const float* net, const int* src, const int* dst, const double* maxp,
+                       double* out, hipStream_t s) {
+    const long long n = (long long)src[0] * src[1] * src[2];
+    hipLaunchKernelGGL(k_finish_grid, dim3(blocks_for(n)), dim3(256), 0, s, net, src[2], src[1],
+                       src[0], dst[2], dst[1], maxp, out);
+    return hipGetLastError();
+}
+
+hipError_t max_abs(const double* a, long long n, unsigned long long* out_bits, hipStream_t s) {
+    hipLaunchKernelGGL(k_max_abs, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, a, n, out_bits);
+    return hipGetLastError();
+}
+
+hipError_t head_fwd(const uint16_t* x, const float* w, const float* b, const float* resid,
+                    long long nv, int C, float* out, hipStream_t s) {
+    if (C == 16)
+        hipLaunchKernelGGL(k_head_fwd<16>, dim3(blocks_for(nv)), dim3(256), 0, s, x, w, b, resid, nv, out);
+    else if (C == 32)
+        hipLaunchKernelGGL(k_head_fwd<32>, dim3(blocks_for(nv)), dim3(256), 0, s, x, w, b, resid, nv, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int head_bwd_blocks(long long nv) { return blocks_for(nv, 256, 1024); }
+
+hipError_t head_bwd(const float* dout, const uint16_t* x, const float* w, long long nv, int C,
+                    float* dx, float* part, hipStream_t s) {
+    const int g = head_bwd_blocks(nv);
+    if (C == 16)
+        hipLaunchKernelGGL(k_head_bwd<16>, dim3(g), dim3(256), 0, s, dout, x, w, nv, dx, part);
+    else if (C == 32)
+        hipLaunchKernelGGL(k_head_bwd<32>, dim3(g), dim3(256), 0, s, dout, x, w, nv, dx, part);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t sum_rows(const float* part, int nrow, int ncol, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(blocks_for(ncol)), dim3(256), 0, s, part, nrow, ncol, out);
+    return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+int mse_blocks(long long n) { return blocks_for(n, 256, 1024); }
+
+hipError_t mse(const float* out, const float* tgt, const float* wgt, long long n, float* dout,
+               float* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_mse, dim3(mse_blocks(n)), dim3(256), 0, s, out, tgt, wgt, n, dout, part);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                float b2, float eps, int step, uint16_t* p16, hipStream_t s) {
+    const float bc1 = 1.0f - powf(b1, (float)step), bc2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps,
+                       bc1, bc2, p16);
+    return hipGetLastError();
+}
+
+hipError_t f32_to_bf16(const float* a, long long n, uint16_t* b, hipStream_t s) {
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_for(n)), dim3(256), 0, s, a, n, b);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace sde

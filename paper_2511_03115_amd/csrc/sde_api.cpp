@@ -11,6 +11,7 @@
 #include "sde.h"
 #include "sde_host.hpp"
 #include "sde_internal.hpp"
+#include "nn_internal.hpp"
 
 using namespace sde;
 
@@ -84,6 +85,11 @@ int device_info() {
 hipStream_t cur_stream() { return g.stream; }
 
 }  // namespace
+
+namespace sde {
+hipStream_t library_stream() { return g.stream; }
+int report_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace sde
 
 struct sde_plan {
     KParams kp{};

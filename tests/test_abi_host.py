@@ -9,7 +9,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sde.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("sde.h", "sde_nn.h")]
 LIB = os.path.join(ROOT, "paper_2511_03115_amd", "libsde.so")
 
 
@@ -22,9 +22,11 @@ def lib():
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sde_\w+)\s*\(", src, re.M)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sde_\w+)\s*\(", src, re.M))
+    return sorted(names)
 
 
 def test_header_declares_entry_points():
@@ -47,7 +49,9 @@ def test_library_exports_every_declared_symbol(lib):
 def test_binding_names_match_header():
     import importlib
     sde = importlib.import_module("paper_2511_03115_amd.sde")
-    assert set(sde.EXPORTS) == set(declared_functions())
+    nn = importlib.import_module("paper_2511_03115_amd.nn")
+    assert not set(sde.EXPORTS) & set(nn.EXPORTS)
+    assert set(sde.EXPORTS) | set(nn.EXPORTS) == set(declared_functions())
 
 
 def test_host_validation_without_gpu(lib):
@@ -79,3 +83,29 @@ def test_host_validation_without_gpu(lib):
     assert lib.sde_gamma(None, None, 1, 1, 1, C.c_double(0.1), C.c_double(0.1),
                          C.c_double(0.1), C.c_double(0.02), C.c_double(0.05), C.c_double(0.01),
                          10, 1, cnt) == sde.E_INVALID
+
+
+def test_nn_config_validation_without_gpu(lib):
+    from paper_2511_03115_amd import nn
+    h = C.c_void_p()
+
+    def create(**kw):
+        base = dict(levels=4, base_channels=16, in_channels=16, leaky_alpha=0.01, max_batch=1,
+                    max_d=64, max_h=64, max_w=64, train=0, adam_beta1=0.9, adam_beta2=0.999,
+                    adam_eps=1e-8)
+        base.update(kw)
+        cfg = nn.Config(*[base[f] for f, _ in nn.Config._fields_])
+        return lib.sde_nn_create(C.byref(cfg), C.byref(h))
+
+    from paper_2511_03115_amd import sde
+    assert create(levels=0) == sde.E_INVALID
+    assert create(base_channels=24) == sde.E_INVALID
+    assert create(in_channels=2) == sde.E_INVALID
+    assert create(leaky_alpha=0.0) == sde.E_INVALID
+    assert create(max_d=60) == sde.E_INVALID          # not a multiple of 2^(L-1)
+    assert create(levels=5) == sde.E_INVALID          # 256 channels: outside the tile set
+    assert b"tile set" in lib.sde_last_error()
+    n = C.c_size_t()
+    assert lib.sde_nn_conv3d_workspace(1, 4, 4, 4, 8, 16, C.byref(n)) == sde.E_INVALID
+    assert lib.sde_nn_conv3d_workspace(2, 4, 4, 4, 32, 64, C.byref(n)) == sde.OK
+    assert n.value >= 27 * 32 * 64 * 4

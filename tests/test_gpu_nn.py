@@ -1,0 +1,263 @@
+"""Denoiser kernels and network vs the FP64 oracle, through the C ABI.
+
+The GPU multiplies bf16 operands with FP32 accumulation and stores the
+activations in bf16.  Single layers are compared with the float64 oracle on
+the same bf16-rounded operands: an FP32 output agrees to FP32 accumulation
+error (1e-5 of the sum of |products|), a bf16 output to one bf16 rounding
+(2^-8 relative).  The whole network is compared with the oracle network that
+rounds to bf16 at the same storage points.  The two still differ where a
+different FP32 summation order flips a bf16 rounding, and a flipped
+activation propagates through the later layers, so the bar is set by the
+rounding noise itself, measured by the oracle as the distance d between its
+bf16-storage and its unrounded network: per parameter tensor the GPU
+gradient lies within max(1e-2, 0.75 d) of the bf16-storage oracle and within
+2 d + 1e-2 of the unrounded one (relative L2 norm); the forward within
+max(5e-3, 0.75 d) of the head's output scale; the loss within 1e-3.  A
+wrong term, index or connection is off by O(1).
+"""
+
+import numpy as np
+import pytest
+
+from gpu_common import log
+from oracle import nn_oracle as nno
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest bf16 value (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def to_bf16_dev(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+
+
+def he_params(levels, c0, cin, seed, head_scale=0.1):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in nno.param_shapes(levels, c0, cin):
+        if name.endswith(".w") and len(shp) == 3:
+            p[name] = rng.normal(scale=np.sqrt(2.0 / (27 * shp[2])), size=shp)
+        elif name == "head.w":
+            p[name] = rng.normal(scale=head_scale, size=shp)
+        else:
+            p[name] = rng.normal(scale=0.05, size=shp)
+    return p
+
+
+@pytest.mark.parametrize("shape,ci,co", [((2, 6, 5, 7), 16, 16), ((1, 5, 9, 4), 48, 32),
+                                         ((2, 4, 4, 6), 32, 64), ((1, 3, 4, 5), 64, 128),
+                                         ((1, 4, 3, 5), 16, 48), ((1, 3, 3, 3), 128, 192),
+                                         ((1, 1, 1, 1), 16, 16)])
+def test_conv3d_fwd(shape, ci, co):
+    import torch
+    from paper_2511_03115_amd import nn
+    rng = np.random.default_rng(ci * 1000 + co)
+    x = bf16_round(rng.normal(size=shape + (ci,)))
+    w = bf16_round(rng.normal(scale=0.2, size=(co, 27, ci)))
+    b = rng.normal(size=co).astype(np.float32)
+    log(f"conv fwd shape={shape} ci={ci} co={co}")
+    ref = nno.conv3d(x, w, b.astype(np.float64))
+    y32 = torch.zeros(shape + (co,), dtype=torch.float32, device="cuda")
+    y16 = torch.zeros(shape + (co,), dtype=torch.bfloat16, device="cuda")
+    nn.conv3d_fwd(to_bf16_dev(x), to_bf16_dev(w), torch.from_numpy(b).cuda(), act=False,
+                  out16=y16, out32=y32)
+    # FP32 accumulation: error within 1e-5 of the sum of |products| at each output
+    absref = nno.conv3d(np.abs(x), np.abs(w), None) + np.abs(b)
+    err32 = np.abs(y32.cpu().numpy() - ref)
+    log(f"  fp32 out max err {err32.max():.3e} (max |ref| {np.abs(ref).max():.3e})")
+    assert np.all(err32 <= 1e-5 * absref + 1e-30)
+    y16n = y16.float().cpu().numpy()
+    assert np.all(np.abs(y16n - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+    # activation
+    y16a = torch.zeros_like(y16)
+    nn.conv3d_fwd(to_bf16_dev(x), to_bf16_dev(w), torch.from_numpy(b).cuda(), alpha=0.1, act=True,
+                  out16=y16a)
+    refa = nno.lrelu(ref, 0.1)
+    assert np.all(np.abs(y16a.float().cpu().numpy() - refa) <= 2.0 ** -8 * np.abs(refa)
+                  + 1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape,ci,co", [((2, 6, 5, 7), 16, 16), ((1, 5, 4, 6), 48, 32),
+                                         ((1, 3, 4, 5), 192, 64), ((1, 4, 4, 4), 128, 128),
+                                         ((2, 8, 8, 9), 16, 48)])
+def test_conv3d_backward(shape, ci, co):
+    import torch
+    from paper_2511_03115_amd import nn
+    rng = np.random.default_rng(ci * 7 + co)
+    x = bf16_round(rng.normal(size=shape + (ci,)))
+    w = bf16_round(rng.normal(scale=0.2, size=(co, 27, ci)))
+    dz = bf16_round(rng.normal(size=shape + (co,)))
+    log(f"conv bwd shape={shape} ci={ci} co={co}")
+    dx_ref, dw_ref, db_ref = nno.conv3d_backward(dz, x, w)
+    dx = torch.zeros(shape + (ci,), dtype=torch.float32, device="cuda")
+    nn.conv3d_dgrad(to_bf16_dev(dz), to_bf16_dev(w), dx)
+    dw = torch.zeros((co, 27, ci), dtype=torch.float32, device="cuda")
+    db = torch.zeros(co, dtype=torch.float32, device="cuda")
+    nn.conv3d_wgrad(to_bf16_dev(dz), to_bf16_dev(x), dw, db)
+    for name, got, ref in (("dx", dx, dx_ref), ("dw", dw, dw_ref), ("db", db, db_ref)):
+        e = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+        log(f"  {name} rel err {e:.3e}")
+        assert e <= 1e-5, name
+
+
+def _net_inputs(B, D, H, W, seed):
+    rng = np.random.default_rng(seed)
+    z = np.arange(D)[None, :, None, None]
+    y = np.arange(H)[None, None, :, None]
+    x = np.arange(W)[None, None, None, :]
+    base = np.exp(-((y - H / 2) ** 2 + (x - W / 2) ** 2) / (0.1 * H * W)) * (0.3 + z / D)
+    dose = np.clip(base + 0.05 * rng.normal(size=(B, D, H, W)), 0, None)
+    dose = (dose / dose.max()).astype(np.float32)
+    rho = rng.uniform(0.2, 2.0, size=(B, D, H, W)).astype(np.float32)
+    tgt = np.ascontiguousarray(np.broadcast_to(base / base.max(), (B, D, H, W)), dtype=np.float32)
+    wgt = rng.uniform(0.5, 2.0, size=(B, D, H, W)).astype(np.float32)
+    return dose, rho, tgt, wgt
+
+
+def _oracle_input(dose, rho, cin):
+    x = np.zeros(dose.shape + (cin,))
+    x[..., 0] = dose
+    x[..., 1] = rho
+    return x
+
+
+def _oracle_net(p, levels, c0, cin, alpha, bf16_storage=True):
+    q = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    return nno.UNet(q, levels, c0, cin, alpha, bf16_storage=bf16_storage)
+
+
+@pytest.mark.parametrize("levels,B,D,H,W", [(4, 2, 16, 16, 24), (4, 1, 8, 8, 8), (2, 1, 6, 10, 4),
+                                             (3, 1, 12, 4, 20)])
+def test_network_forward_and_gradients(levels, B, D, H, W):
+    import torch
+    from paper_2511_03115_amd import nn
+    c0, cin, alpha = 16, 16, 0.01
+    p = he_params(levels, c0, cin, seed=11)
+    dose, rho, tgt, wgt = _net_inputs(B, D, H, W, seed=12)
+    log(f"net L={levels} dims={(B, D, H, W)}")
+    net = nn.Net(levels, c0, cin, alpha, max_batch=B, max_dims=(D, H, W), train=True)
+    assert net.n_params == sum(int(np.prod(s)) for _, s in nno.param_shapes(levels, c0, cin))
+    flat = nno.flatten(p, levels, c0, cin).astype(np.float32)
+    net.set_params(flat)
+    assert np.array_equal(net.get_params(), flat)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    out = torch.zeros((B, D, H, W), dtype=torch.float32, device="cuda")
+    net.forward(dev(dose), dev(rho), out)
+    x = _oracle_input(dose, rho, cin)
+    T, Tm = tgt.astype(np.float64), wgt.astype(np.float64)
+    onet = _oracle_net(p, levels, c0, cin, alpha)
+    loss_ref, grads_ref, ref = onet.loss_and_grads(x, T, Tm)
+    loss64, grads64, ref64 = _oracle_net(p, levels, c0, cin, alpha, False).loss_and_grads(x, T, Tm)
+    got = out.cpu().numpy()
+    head = np.abs(ref - dose).max()
+    e = np.abs(got - ref).max() / head
+    d_fwd = np.abs(ref - ref64).max() / head
+    log(f"  forward err / head scale {e:.3e} (rounding noise {d_fwd:.3e})")
+    assert e <= max(5e-3, 0.75 * d_fwd)
+    loss = net.loss_grad(dev(dose), dev(rho), dev(tgt), dev(wgt))
+    log(f"  loss gpu {loss:.6e} oracle {loss_ref:.6e} unrounded {loss64:.6e}")
+    assert abs(loss - loss_ref) <= 1e-3 * loss_ref
+    g = nno.unflatten(net.get_grads().astype(np.float64), levels, c0, cin)
+    rel = lambda a, b: np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+    for k, r in grads_ref.items():
+        gk, r64 = g[k], grads64[k]
+        if k == "enc0a.w":                # input channels 2.. are zero: so are their gradients
+            assert np.all(gk[:, :, 2:] == 0.0)
+            gk, r, r64 = gk[:, :, :2], r[:, :, :2], r64[:, :, :2]
+        e_b, e_64, d = rel(gk, r), rel(gk, r64), rel(r, r64)
+        log(f"  {k:8s} vs bf16 oracle {e_b:.2e}  vs unrounded {e_64:.2e}  noise {d:.2e}")
+        assert e_b <= max(1e-2, 0.75 * d), k
+        assert e_64 <= 2 * d + 1e-2, k
+    net.close()
+
+
+def test_adam_update_matches_oracle():
+    import torch
+    from paper_2511_03115_amd import nn
+    levels, c0, cin = 2, 16, 16
+    B, D, H, W = 1, 8, 8, 8
+    p = nno.flatten(he_params(levels, c0, cin, seed=13), levels, c0, cin).astype(np.float32)
+    dose, rho, tgt, wgt = _net_inputs(B, D, H, W, seed=14)
+    net = nn.Net(levels, c0, cin, 0.01, B, (D, H, W), train=True)
+    net.set_params(p)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    m = np.zeros(p.size)
+    v = np.zeros(p.size)
+    pr = p.astype(np.float64)
+    for step in range(1, 4):
+        net.loss_grad(dev(dose), dev(rho), dev(tgt), dev(wgt))
+        g = net.get_grads().astype(np.float64)
+        net.adam_step(1e-3)
+        pr, m, v = nno.adam(pr, g, m, v, step, 1e-3)
+        got = net.get_params()
+        e = np.abs(got - pr).max()
+        log(f"adam step {step} max |dp| err {e:.3e}")
+        assert e <= 1e-6 + 1e-5 * np.abs(pr).max()
+        pr = got.astype(np.float64)      # follow the FP32 trajectory
+    mm, vv, st = net.get_adam_state()
+    assert st == 3 and np.all(np.isfinite(mm)) and np.all(vv >= 0)
+    net.close()
+
+
+def test_training_reduces_loss_and_is_reproducible():
+    import torch
+    from paper_2511_03115_amd import nn
+    levels, c0, cin = 3, 16, 16
+    B, D, H, W = 2, 16, 16, 16
+    p = nno.flatten(he_params(levels, c0, cin, seed=15, head_scale=0.0), levels, c0, cin)
+    dose, rho, tgt, wgt = _net_inputs(B, D, H, W, seed=16)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    finals = []
+    for rep in range(2):
+        net = nn.Net(levels, c0, cin, 0.01, B, (D, H, W), train=True)
+        net.set_params(p.astype(np.float32))
+        losses = []
+        for it in range(150):
+            losses.append(net.loss_grad(dev(dose), dev(rho), dev(tgt), None))
+            net.adam_step(5e-3)
+        log(f"train rep {rep}: loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+        assert losses[-1] < 0.8 * losses[0]
+        finals.append(net.get_params())
+        net.close()
+    assert np.array_equal(finals[0], finals[1])
+
+
+def test_denoise_grid_pipeline():
+    """Normalise by the maximum, pad to multiples of 8, run, clamp, crop, rescale."""
+    import torch
+    from paper_2511_03115_amd import nn
+    levels, c0, cin = 4, 16, 16
+    nz, ny, nx = 13, 11, 9
+    p = he_params(levels, c0, cin, seed=17, head_scale=0.3)
+    rng = np.random.default_rng(18)
+    dose = rng.gamma(2.0, 1e-3, size=(nz, ny, nx))
+    rho = rng.uniform(0.2, 2.0, size=(nz, ny, nx)).astype(np.float32)
+    net = nn.Net(levels, c0, cin, 0.01, 1, (16, 16, 16), train=False)
+    net.set_params(nno.flatten(p, levels, c0, cin).astype(np.float32))
+    out = torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda")
+    net.denoise(torch.from_numpy(dose).cuda(), torch.from_numpy(rho).cuda(), out)
+    mx = dose.max()
+    dn = np.zeros((1, 16, 16, 16), np.float32)
+    dn[0, :nz, :ny, :nx] = (dose / mx).astype(np.float32)
+    rp = np.zeros((1, 16, 16, 16), np.float32)
+    rp[0, :nz, :ny, :nx] = rho
+    onet = _oracle_net(p, levels, c0, cin, 0.01)
+    ref, _ = onet.forward(_oracle_input(dn, rp, cin))
+    ref = np.maximum(ref[0, :nz, :ny, :nx], 0.0) * mx
+    got = out.cpu().numpy()
+    e = np.abs(got - ref).max() / np.abs(ref).max()
+    log(f"denoise grid err {e:.3e}")
+    assert e <= 5e-3
+    assert np.all(got >= 0)
+    # in place
+    d2 = torch.from_numpy(dose).cuda()
+    net.denoise(d2, torch.from_numpy(rho).cuda(), d2)
+    assert torch.equal(d2, out)
+    net.close()

@@ -204,3 +204,34 @@ def test_unet_identity_wiring_closed_form():
     np.testing.assert_allclose(out_skip, 2 * x[..., 0], atol=1e-14)
     out_up, _ = nn.UNet(params(2), levels, c0, cin, alpha=1.0).forward(x)
     np.testing.assert_allclose(out_up, x[..., 0] + nn.up2(nn.pool2(x))[..., 0], atol=1e-14)
+
+
+def test_bf16_rounding_matches_torch():
+    """The storage rounding is round-to-nearest-even to bf16 (torch's cast)."""
+    rng = np.random.default_rng(10)
+    a = np.concatenate([rng.normal(scale=10.0 ** rng.uniform(-20, 20, 4000)),
+                        [0.0, -0.0, 1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 65504.0]])
+    a = a.astype(np.float32)
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(nn.bf16(a), ref)
+    # ties: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7 and rounds to the even 1
+    assert nn.bf16(np.array([1.0 + 2 ** -8]))[0] == 1.0
+    assert nn.bf16(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6
+
+
+def test_bf16_storage_is_a_small_perturbation_off_the_residual():
+    """bf16 storage moves the output by a small fraction of the head's
+    contribution, and never touches the residual path."""
+    levels, c0, cin = 2, 2, 2
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=(1, 4, 4, 4, cin))
+    p = {n: rng.normal(scale=0.3, size=s) for n, s in nn.param_shapes(levels, c0, cin)}
+    o1, _ = nn.UNet(p, levels, c0, cin, 0.01, bf16_storage=True).forward(x)
+    o0, _ = nn.UNet(p, levels, c0, cin, 0.01).forward(x)
+    assert 0 < np.abs(o1 - o0).max() < 0.05 * np.abs(o0 - x[..., 0]).max()
+    # the residual is never rounded
+    q = dict(p)
+    q["head.w"] = np.zeros(c0)
+    q["head.b"] = np.zeros(1)
+    o2, _ = nn.UNet(q, levels, c0, cin, 0.01, bf16_storage=True).forward(x)
+    np.testing.assert_array_equal(o2, x[..., 0])
