@@ -50,6 +50,8 @@ def parse():
                     help="skip the batched-plan leg (1000 spots, hipGraph replay)")
     ap.add_argument("--launch", type=str, default="auto",
                     help="'auto' (autotuner), 'default', or a JSON launch configuration")
+    ap.add_argument("--no-gamma", action="store_true",
+                    help="skip the time-to-gamma leg (plain SDE vs denoised, plan at 2 mm)")
     return ap.parse_args()
 
 
@@ -132,6 +134,38 @@ def plan_leg(steps: int, stream) -> dict:
             "steps_per_execution": int(led[sde.LEDGER_STEPS]), "launch": launch}
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2511_03115_amd", "weights", "denoiser_plan2mm.npz")
+GAMMA_LADDER = [1000 * 2 ** k for k in range(9)]        # histories per spot
+GAMMA_REFERENCE = 2_000_000                              # histories per spot
+
+
+def gamma_leg() -> dict:
+    """Wall time to a dose with gamma >= 95 % (local 2 %/0.5 mm, 1 % threshold)
+    against a 2e6-histories-per-spot reference, on the batched plan (1000
+    spots, 2 mm): plain SDE on a doubling ladder of histories per spot vs
+    the denoised 1e3-per-spot run with the plain fallback."""
+    from dataclasses import replace
+    import workloads
+    from workloads import configs
+    from paper_2511_03115_amd import denoiser, judge, sde
+    wl = configs.plan_uniform(1000)
+    sde.init_materials(wl.phantom.materials, wl.params,
+                       workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
+    dph = sde.DevicePhantom.from_host(wl.phantom)
+    dn = denoiser.Denoiser(WEIGHTS, wl.phantom.material_id.shape)
+    log = lambda m: print(m, flush=True)
+    res = judge.time_to_gamma(lambda n: [replace(sp, n_histories=n) for sp in wl.spots], dph,
+                              wl.seed, GAMMA_LADDER, GAMMA_REFERENCE, denoise=dn,
+                              name="plan", log=log)
+    dn.close()
+    out = res.as_dict()
+    out["workload"] = ("plan: 1000 spots 70-230 MeV, lognormal weights, equal histories per "
+                       "spot, 256x256x200 at 2 mm, random density + bone/lung ellipsoids")
+    out["gamma"] = {"dd": judge.DD, "dta_cm": judge.DTA_CM, "threshold": judge.THRESH,
+                    "local": True, "target": judge.TARGET}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -204,6 +238,10 @@ def main():
     plan.close()
     if not a.no_plan:
         out["plan"] = plan_leg(a.steps, stream)
+    if not a.no_gamma:
+        print("[bench] time to gamma >= 95% (plain vs denoised)", flush=True)
+        sde.set_stream(None)
+        out["time_to_gamma"] = gamma_leg()
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)

@@ -93,6 +93,16 @@ int sde_nn_adam_step(sde_nn* net, float lr);
 int sde_nn_denoise(sde_nn* net, const double* dose, const float* rho, int nx, int ny, int nz,
                    double* out);
 
+/* Training pair from two dose grids of the same beam (device FP64, n
+ * voxels): m = max |low|; low_out = low / m, high_out = high / m (high
+ * nullable) and the loss weight weight_out (nullable): with h =
+ * max(high_out, 0), 1 / (h + eps)^2 where h >= thr (relative error with a
+ * floor of eps) and (h / thr) / (thr + eps)^2 below thr (fading out where a
+ * gamma test with threshold thr does not look).  Outputs are device FP32.
+ * Uses the network's scratch for m. */
+int sde_nn_prepare_pair(sde_nn* net, const double* low, const double* high, int64_t n, float eps,
+                        float thr, float* low_out, float* high_out, float* weight_out);
+
 /* Single layers, for tests of the kernels.  x, w, y16, dz: (device) bf16
  * bit patterns (uint16); bias, y32, dx, dw, db: (device) FP32.
  * Volumes [B][D][H][W][C]; weights [Co][27][Ci].  Ci % 16 == 0 and

@@ -447,6 +447,21 @@ int sde_nn_denoise(sde_nn* net, const double* dose, const float* rho, int nx, in
     return SDE_OK;
 }
 
+int sde_nn_prepare_pair(sde_nn* net, const double* low, const double* high, int64_t n, float eps,
+                        float thr, float* low_out, float* high_out, float* weight_out) {
+    NN_CHECK(net && low && low_out, "null argument");
+    NN_CHECK(n >= 1, "size must be positive");
+    NN_CHECK(!high || high_out, "high needs high_out");
+    NN_CHECK(!weight_out || (high && eps > 0.0f && thr > 0.0f),
+             "weight needs high, eps > 0 and thr > 0");
+    hipStream_t s = library_stream();
+    NN_TRY(fill_u32((uint32_t*)net->maxbits, 2, 0u, s));
+    NN_TRY(max_abs(low, n, net->maxbits, s));
+    NN_TRY(prepare_pair(low, high, n, (const double*)net->maxbits, eps, thr, low_out, high_out,
+                        weight_out, s));
+    return SDE_OK;
+}
+
 int sde_nn_conv3d_fwd(const uint16_t* x, const uint16_t* w, const float* bias, int B, int D,
                       int H, int W, int Ci, int Co, float alpha, int act, uint16_t* y16,
                       float* y32) {

@@ -46,6 +46,10 @@ hipError_t assemble_grid(const double* dose, const float* rho, const int* src, c
 // out (FP64 [nz][ny][nx]) = max(0, net[D][H][W] cropped) * (*maxp)
 hipError_t finish_grid(const float* net, const int* src, const int* dst, const double* maxp,
                        double* out, hipStream_t s);
+// lo = low / *maxp, hi = high / *maxp (high nullable); wt = 1 / (h + eps)^2 for
+// h = max(hi, 0) >= thr, else (h / thr) / (thr + eps)^2
+hipError_t prepare_pair(const double* low, const double* high, long long n, const double* maxp,
+                        float eps, float thr, float* lo, float* hi, float* wt, hipStream_t s);
 hipError_t max_abs(const double* a, long long n, unsigned long long* out_bits, hipStream_t s);
 hipError_t head_fwd(const uint16_t* x, const float* w, const float* b, const float* resid,
                     long long nv, int C, float* out, hipStream_t s);

@@ -366,6 +366,32 @@ __global__ void k_finish_grid(const float* net, int nx, int ny, int nz, int W, i
     }
 }
 
+// Training pair: low / m, high / m with m = *maxp (the low map's maximum),
+// and the loss weight: relative error with a floor eps above the threshold
+// thr, 1 / (h + eps)^2, tapering linearly to zero below it, (h / thr) /
+// (thr + eps)^2, so that voxels the gamma test ignores (and their stray
+// single-history deposits) do not drive the fit.
+__global__ void k_prepare_pair(const double* low, const double* high, long long n,
+                               const double* maxp, float eps, float thr, float* lo, float* hi,
+                               float* wt) {
+    const double m = *maxp;
+    const double inv = m > 0.0 ? 1.0 / m : 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        lo[i] = (float)(low[i] * inv);
+        if (high) {
+            const float h = (float)(high[i] * inv);
+            hi[i] = h;
+            if (wt) {
+                const float hp = fmaxf(h, 0.0f);
+                const float d = hp >= thr ? hp + eps : thr + eps;
+                const float r = 1.0f / (d * d);
+                wt[i] = hp >= thr ? r : (hp / thr) * r;
+            }
+        }
+    }
+}
+
 // Maximum of |a| as the bit pattern of a non-negative double (out zeroed first).
 __global__ void k_max_abs(const double* a, long long n, unsigned long long* out) {
     double m = 0.0;
@@ -636,6 +662,13 @@ hipError_t finish_grid(const float* net, const int* src, const int* dst, const d
     const long long n = (long long)src[0] * src[1] * src[2];
     hipLaunchKernelGGL(k_finish_grid, dim3(blocks_for(n)), dim3(256), 0, s, net, src[2], src[1],
                        src[0], dst[2], dst[1], maxp, out);
+    return hipGetLastError();
+}
+
+hipError_t prepare_pair(const double* low, const double* high, long long n, const double* maxp,
+                        float eps, float thr, float* lo, float* hi, float* wt, hipStream_t s) {
+    hipLaunchKernelGGL(k_prepare_pair, dim3(blocks_for(n)), dim3(256), 0, s, low, high, n, maxp, eps,
+                       thr, lo, hi, wt);
     return hipGetLastError();
 }
 

@@ -1,0 +1,148 @@
+"""The plain SDE as judge and fallback of the denoiser, and the wall time to
+a dose whose gamma pass rate reaches 95 %.
+
+Gamma (section 2.2): local dose difference 2 %, distance to agreement
+0.5 mm, voxels below 1 % of the reference maximum excluded, search at
+DTA/10 with trilinear interpolation of the evaluated map (``sde.gamma``,
+a HIP kernel).  The reference is a high-history SDE run of the same plan
+with an independent seed.
+
+* plain: the smallest history count on a doubling ladder whose map passes;
+  its time is that one run's time.
+* denoised, first rung only: one run at the lowest rung, denoised; if its
+  map passes, its time is that run plus the inference; otherwise the map is
+  rerun plain (fallback) at the plain ladder's passing rung, and that run's
+  time is added.
+* denoised ladder: every rung up to the plain passing one is also denoised;
+  the smallest rung whose denoised map passes gives run plus inference; if
+  none does, the plain run is the fallback.
+Both also report the cumulative time of walking the ladder up to the
+passing rung (every run, inference and nothing else), for plain and
+denoised alike.
+All times are GPU wall times of the execution (stream-synchronised), with
+tables, phantom and plan set up beforehand; set-up times are reported
+beside them.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import asdict, dataclass, field
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+from . import sde
+
+DD, DTA_CM, THRESH, INTERP, TARGET = 0.02, 0.05, 0.01, 10, 0.95
+
+
+def gamma_pass(ref, ev, voxel_cm, dd: float = DD, dta_cm: float = DTA_CM,
+               thresh: float = THRESH, local: bool = True) -> float:
+    frac, _, _ = sde.gamma(ref, ev, voxel_cm, dd, dta_cm, thresh, INTERP, local)
+    return float(frac)
+
+
+def _timed(fn) -> float:
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+@dataclass
+class Rung:
+    n_per_spot: int
+    histories: int
+    setup_s: float
+    run_s: float
+    gamma_plain: float
+    denoise_s: Optional[float] = None
+    gamma_denoised: Optional[float] = None
+
+
+@dataclass
+class TimeToGamma:
+    workload: str
+    reference_histories: int
+    reference_s: float
+    rungs: List[Rung] = field(default_factory=list)
+    plain_n_per_spot: Optional[int] = None
+    plain_s: Optional[float] = None
+    plain_cumulative_s: Optional[float] = None
+    first_rung_denoised_s: Optional[float] = None
+    first_rung_passed: Optional[bool] = None
+    denoised_n_per_spot: Optional[int] = None
+    denoised_s: Optional[float] = None
+    denoised_cumulative_s: Optional[float] = None
+    fallback: Optional[bool] = None
+
+    def as_dict(self) -> dict:
+        d = asdict(self)
+        d["speedup"] = (self.plain_s / self.denoised_s
+                        if self.plain_s and self.denoised_s else None)
+        d["speedup_first_rung"] = (self.plain_s / self.first_rung_denoised_s
+                                   if self.plain_s and self.first_rung_denoised_s else None)
+        return d
+
+
+def time_to_gamma(spots_for: Callable[[int], list], phantom, seed: int, ladder: Sequence[int],
+                  n_reference: int, denoise=None, name: str = "", launch=None,
+                  log=print) -> TimeToGamma:
+    """``spots_for(n)``: the plan's spots with n histories per spot;
+    ``phantom``: a sde.DevicePhantom (materials already initialised);
+    ``denoise(dose, rho, out)``: the trained network (or None)."""
+    import torch
+    shape = tuple(phantom.material_id.shape)
+    vcm = tuple(phantom.voxel_cm)
+    ref = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    plan = sde.Plan(spots_for(n_reference), phantom, seed + 999_983, launch=launch)
+    t_ref = _timed(lambda: plan.execute(ref))
+    n_ref_total = plan.n_histories
+    plan.close()
+    log(f"[judge] {name} reference {n_ref_total} histories in {t_ref:.2f} s")
+    res = TimeToGamma(name, n_ref_total, t_ref)
+    dose = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    den = torch.zeros_like(dose)
+    cum_plain = cum_den = 0.0
+    for k, n in enumerate(ladder):
+        t0 = time.perf_counter()
+        plan = sde.Plan(spots_for(n), phantom, seed + k, launch=launch)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        t_run = _timed(lambda: plan.execute(dose))
+        rung = Rung(n, plan.n_histories, t_setup, t_run, gamma_pass(ref, dose, vcm))
+        plan.close()
+        cum_plain += t_run
+        if denoise is not None and res.denoised_s is None:
+            rung.denoise_s = _timed(lambda: denoise(dose, phantom.density, den))
+            rung.gamma_denoised = gamma_pass(ref, den, vcm)
+            cum_den += t_run + rung.denoise_s
+            if rung.gamma_denoised >= TARGET:
+                res.denoised_n_per_spot = n
+                res.denoised_s = t_run + rung.denoise_s
+                res.denoised_cumulative_s = cum_den
+            if k == 0:
+                res.first_rung_passed = rung.gamma_denoised >= TARGET
+                res.first_rung_denoised_s = t_run + rung.denoise_s
+        res.rungs.append(rung)
+        log(f"[judge] {name} {n}/spot: {rung.histories} histories {t_run * 1e3:.1f} ms, "
+            f"gamma plain {rung.gamma_plain:.4f}"
+            + (f", denoised {rung.gamma_denoised:.4f} (+{rung.denoise_s * 1e3:.1f} ms)"
+               if rung.gamma_denoised is not None else ""))
+        if rung.gamma_plain >= TARGET:
+            res.plain_n_per_spot, res.plain_s = n, t_run
+            res.plain_cumulative_s = cum_plain
+            break
+    if denoise is not None:
+        if res.first_rung_passed is False and res.first_rung_denoised_s is not None:
+            res.first_rung_denoised_s = (res.first_rung_denoised_s + res.plain_s
+                                         if res.plain_s is not None else None)
+        res.fallback = res.denoised_s is None
+        if res.fallback and res.plain_s is not None:
+            res.denoised_n_per_spot = res.plain_n_per_spot
+            res.denoised_s = res.plain_s
+            res.denoised_cumulative_s = cum_den + res.plain_s
+    return res

@@ -20,7 +20,7 @@ from .sde import _check, lib
 EXPORTS = ("sde_nn_create", "sde_nn_destroy", "sde_nn_param_count", "sde_nn_set_params",
            "sde_nn_get_params", "sde_nn_set_adam_state", "sde_nn_get_adam_state",
            "sde_nn_get_grads", "sde_nn_forward", "sde_nn_loss_grad", "sde_nn_adam_step",
-           "sde_nn_denoise", "sde_nn_conv3d_fwd", "sde_nn_conv3d_workspace",
+           "sde_nn_denoise", "sde_nn_prepare_pair", "sde_nn_conv3d_fwd", "sde_nn_conv3d_workspace",
            "sde_nn_conv3d_dgrad", "sde_nn_conv3d_wgrad")
 
 
@@ -46,6 +46,7 @@ def _setup():
     lib.sde_nn_loss_grad.argtypes = [V, V, V, V, V, I, I, I, I, P(F)]
     lib.sde_nn_adam_step.argtypes = [V, F]
     lib.sde_nn_denoise.argtypes = [V, V, V, I, I, I, V]
+    lib.sde_nn_prepare_pair.argtypes = [V, V, V, i64, F, F, V, V, V]
     lib.sde_nn_conv3d_fwd.argtypes = [V, V, V, I, I, I, I, I, I, F, I, V, V]
     lib.sde_nn_conv3d_workspace.argtypes = [I, I, I, I, I, I, P(C.c_size_t)]
     lib.sde_nn_conv3d_dgrad.argtypes = [V, V, I, I, I, I, I, I, V, V, C.c_size_t]
@@ -139,6 +140,12 @@ class Net:
         """dose, out: float64 device tensors (nz, ny, nx); rho float32 or None."""
         nz, ny, nx = dose.shape
         _check(lib.sde_nn_denoise(self._h, _p(dose), _p(rho), nx, ny, nz, _p(out)))
+
+    def prepare_pair(self, low, high, low_out, high_out=None, weight_out=None,
+                     eps: float = 0.02, thr: float = 0.01):
+        """Normalise a (low, high) pair of FP64 device dose grids by max |low|."""
+        _check(lib.sde_nn_prepare_pair(self._h, _p(low), _p(high), low.numel(), eps, thr,
+                                       _p(low_out), _p(high_out), _p(weight_out)))
 
 
 # single layers (kernel tests) --------------------------------------------

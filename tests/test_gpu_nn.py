@@ -261,3 +261,27 @@ def test_denoise_grid_pipeline():
     net.denoise(d2, torch.from_numpy(rho).cuda(), d2)
     assert torch.equal(d2, out)
     net.close()
+
+
+def test_prepare_pair_definition():
+    """lo = low / max|low|, hi = high / max|low|, weight = relative error
+    (floor eps) above thr, fading linearly to zero below thr."""
+    import torch
+    from paper_2511_03115_amd import nn
+    rng = np.random.default_rng(19)
+    low = rng.gamma(1.5, 1e-4, size=(7, 9, 11))
+    high = np.clip(low * rng.uniform(0.8, 1.2, low.shape) - 3e-5, 0, None)
+    high[0, 0, :3] = [0.0, 1e-9, -0.0]
+    net = nn.Net(1, 16, 16, 0.01, 1, (1, 1, 1), train=False)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    f = lambda: torch.zeros(low.shape, dtype=torch.float32, device="cuda")
+    lo, hi, wt = f(), f(), f()
+    eps, thr = 0.02, 0.01
+    net.prepare_pair(dev(low), dev(high), lo, hi, wt, eps=eps, thr=thr)
+    m = np.abs(low).max()
+    np.testing.assert_allclose(lo.cpu().numpy(), low / m, rtol=1e-6)
+    h = high / m
+    np.testing.assert_allclose(hi.cpu().numpy(), h, rtol=1e-6, atol=1e-12)
+    w_ref = np.where(h >= thr, 1.0 / (h + eps) ** 2, (h / thr) / (thr + eps) ** 2)
+    np.testing.assert_allclose(wt.cpu().numpy(), w_ref, rtol=2e-6)
+    net.close()

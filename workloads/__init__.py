@@ -11,5 +11,5 @@ from .materials import ELEMENTS, material, water, bone, lung  # noqa: F401
 from .nuclear import placeholder_nuclear_tables, nuclear_for_phantom, EnergyLattice  # noqa: F401
 from .phantoms import (Phantom, water_box, slab_phantom, insert_phantom,  # noqa: F401
                        grf_phantom)
-from .beams import Spot, single_spot, plan_spots  # noqa: F401
+from .beams import Spot, single_spot, plan_spots, patch_spots, with_histories  # noqa: F401
 from . import configs  # noqa: F401

@@ -57,3 +57,34 @@ def plan_spots(n_spots: int = 1000, pitch_cm: float = 0.5, e_lo: float = 70.0,
         spots.append(Spot(float(E[k]), sigmaE_rel, float(x), float(y), sigma_xy_cm,
                           float(w[k]), int(n[k])))
     return spots
+
+
+def with_histories(spots: List[Spot], total: int) -> List[Spot]:
+    """The same spots (energies, positions, weights) with ``total`` histories
+    shared in proportion to the weights (at least one each).  The expected
+    dose does not change: each history carries weight/n_histories."""
+    w = np.array([s.weight for s in spots], dtype=np.float64)
+    n = np.maximum(1, np.rint(total * w / w.sum())).astype(np.int64)
+    return [Spot(s.E_MeV, s.sigmaE_rel, s.x_cm, s.y_cm, s.sigma_xy_cm, s.weight, int(k))
+            for s, k in zip(spots, n)]
+
+
+def patch_spots(seed: int, n_max: int = 64, pitch_cm: float = 0.5, half_cm: float = 4.0,
+                e_lo: float = 70.0, e_hi: float = 230.0, w_sigma: float = 0.5,
+                sigmaE_rel: float = 0.01, sigma_xy_cm: float = 0.3) -> List[Spot]:
+    """Spots for one denoiser training patch, drawn like the batched plan's:
+    between 1 and ``n_max`` distinct positions of a ``pitch_cm`` lateral grid
+    within +-``half_cm`` of the axis, energies U(e_lo, e_hi), weights
+    LogNormal(0, w_sigma); history counts are set by ``with_histories``."""
+    rng = np.random.default_rng(seed)
+    side = int(2 * half_cm / pitch_cm) + 1
+    k = int(rng.integers(1, n_max + 1))
+    cells = rng.choice(side * side, size=k, replace=False)
+    E = rng.uniform(e_lo, e_hi, k)
+    w = rng.lognormal(0.0, w_sigma, k)
+    out = []
+    for j in range(k):
+        iy, ix = divmod(int(cells[j]), side)
+        out.append(Spot(float(E[j]), sigmaE_rel, -half_cm + ix * pitch_cm, -half_cm + iy * pitch_cm,
+                        sigma_xy_cm, float(w[j]), 1))
+    return out

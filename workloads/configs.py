@@ -8,7 +8,11 @@
 * ``slab``/``insert``: 100 or 150 MeV with the water150 beam model,
   200 x 200 x 200 mm at 1 mm.
 * ``plan``: 1000 spots, 70-230 MeV, lognormal weights, 1e3-1e5 histories per
-  spot, 256 x 256 x 200 voxels of 2 mm with a random density field.
+  spot, 256 x 256 x 200 voxels of 2 mm with a random density field;
+  ``plan_uniform``: the same spots with one history count for every spot.
+* ``denoiser_patch``: training patches of the denoiser, 64 x 64 x 128 voxels
+  of 2 mm with a random density field and inclusions and 1-64 spots, all
+  drawn like the plan's (index i seeds everything).
 
 Physics parameters are the paper's run settings (section 2.2, "Test cases",
 and section 2.1): step 0.5 mm, Lynch-Dahl path length 0.05 cm, F = 0.98,
@@ -20,7 +24,9 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List
 
-from .beams import Spot, single_spot, plan_spots
+import numpy as np
+
+from .beams import Spot, single_spot, plan_spots, patch_spots, with_histories
 from .nuclear import EnergyLattice
 from .phantoms import Phantom, water_box, slab_phantom, insert_phantom, grf_phantom
 
@@ -91,3 +97,26 @@ def plan(n_spots: int = 1000, n_scale: float = 1.0, seed: int = 6,
     nx, ny, nz = shape
     return Workload("plan", grf_phantom(nx, ny, nz, 0.2),
                     plan_spots(n_spots, n_scale=n_scale), seed)
+
+
+def plan_uniform(n_per_spot: int, n_spots: int = 1000, seed: int = 6,
+                 shape=(256, 256, 200)) -> Workload:
+    """The batched plan with ``n_per_spot`` histories in every spot (same
+    energies, positions and weights as ``plan``)."""
+    nx, ny, nz = shape
+    e = float(np.log10(n_per_spot))
+    return Workload(f"plan_{n_per_spot}", grf_phantom(nx, ny, nz, 0.2),
+                    plan_spots(n_spots, logn_lo=e, logn_hi=e), seed)
+
+
+def denoiser_patch(i: int, n_histories: int = 100_000, shape=(64, 64, 128)) -> Workload:
+    """Training patch i: a 2 mm random-density phantom (correlation 1 cm,
+    0-3 bone and 0-2 lung ellipsoids) and 1-64 plan-like spots sharing
+    ``n_histories`` histories.  Seeds: field 1000+i, inclusions 5000+i,
+    spots 9000+i, transport 20000+i."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(13000 + i)
+    ph = grf_phantom(nx, ny, nz, 0.2, n_bone=int(rng.integers(0, 4)),
+                     n_lung=int(rng.integers(0, 3)), seed_field=1000 + i, seed_incl=5000 + i)
+    spots = with_histories(patch_spots(9000 + i, half_cm=min(4.0, 0.2 * nx / 2 - 1.0)), n_histories)
+    return Workload(f"denoiser_patch{i}", ph, spots, 20000 + i)
