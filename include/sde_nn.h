@@ -116,7 +116,8 @@ int sde_nn_conv3d_workspace(int B, int D, int H, int W, int Ci, int Co, size_t* 
 /* dx[v][ci] = sum_t sum_co dz[v - off(t)][co] w[co][t][ci] (FP32 out). */
 int sde_nn_conv3d_dgrad(const uint16_t* dz, const uint16_t* w, int B, int D, int H, int W, int Ci,
                         int Co, float* dx, void* workspace, size_t workspace_bytes);
-/* dw[co][t][ci] = sum_v dz[v][co] x[v + off(t)][ci]; db[co] = sum_v dz[v][co] (nullable). */
+/* dw[co][t][ci] = sum_v dz[v][co] x[v + off(t)][ci]; db[co] = sum_v dz[v][co] (nullable).
+ * Also needs (Co / 16) * (Ci / 16) <= 64. */
 int sde_nn_conv3d_wgrad(const uint16_t* dz, const uint16_t* x, int B, int D, int H, int W, int Ci,
                         int Co, float* dw, float* db, void* workspace, size_t workspace_bytes);
 

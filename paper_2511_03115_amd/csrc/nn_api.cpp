@@ -134,7 +134,7 @@ int run_forward(sde_nn* n, const int* d0) {
         (void)dc;
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
-        NN_TRY(copy_channels(v.eb, nvox(d), n->c[l], Cf, 0, v.cat, s));
+        NN_TRY(copy_channels(v.eb, d, n->c[l], Cf, 0, v.cat, s));
         NN_TRY(up_fwd(top, d, n->c[l + 1], Cf, n->c[l], v.cat, s));
         if (int r = conv_act(n, v.cat, n->dec_a[l], d, v.da)) return r;
         if (int r = conv_act(n, v.da, n->dec_b[l], d, v.db)) return r;
@@ -176,7 +176,7 @@ int run_backward(sde_nn* n, const int* d0) {
         const int Cf = n->c[l] + n->c[l + 1];
         if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa)) return r;
         if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, v.gCat)) return r;
-        NN_TRY(slice_copy(v.gCat, nvox(d), n->c[l], Cf, 0, v.gE, s));
+        NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
         float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
         NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s));
     }
@@ -301,7 +301,7 @@ int sde_nn_create(const sde_nn_config* cfg, sde_nn** out) {
     bool ok = true;
     for (auto* vec : {&n->enc_a, &n->enc_b, &n->dec_a, &n->dec_b})
         for (const ConvP& cp : *vec)
-            ok = ok && nt_ok(cp.co) && nt_ok(cp.ci) && (cp.co / 16) * (cp.ci / 16) <= 128;
+            ok = ok && nt_ok(cp.co) && nt_ok(cp.ci) && (cp.co / 16) * (cp.ci / 16) <= 64;
     if (!ok) {
         delete n;
         return report_error(SDE_E_INVALID, "channel counts outside the kernels' tile set");
@@ -480,7 +480,7 @@ int sde_nn_conv3d_workspace(int B, int D, int H, int W, int Ci, int Co, size_t* 
     const int d[4] = {B, D, H, W};
     const long long wfl = 27LL * Ci * Co;
     const int chunk = wgrad_chunk_for(d, Ci, Co, kMaxPartFloats);
-    const long long part = wgrad_chunks(d, chunk) * wfl * (long long)sizeof(float);
+    const long long part = wgrad_part_floats(d, Ci, Co, chunk) * (long long)sizeof(float);
     *bytes = (size_t)std::max<long long>(part, wfl * (long long)sizeof(uint16_t));
     return SDE_OK;
 }
@@ -504,7 +504,7 @@ int sde_nn_conv3d_wgrad(const uint16_t* dz, const uint16_t* x, int B, int D, int
     NN_CHECK(dz && x && dw && workspace, "null argument");
     NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
     NN_CHECK(Ci >= 16 && Ci % 16 == 0 && Co >= 16 && Co % 16 == 0 &&
-                 (Co / 16) * (Ci / 16) <= 128,
+                 (Co / 16) * (Ci / 16) <= 64,
              "unsupported channel counts");
     size_t need = 0;
     if (int r = sde_nn_conv3d_workspace(B, D, H, W, Ci, Co, &need)) return r;

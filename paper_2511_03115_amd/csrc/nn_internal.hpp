@@ -17,10 +17,12 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
                     int accumulate, hipStream_t s);
 // wt[ci][26 - t][co] = w[co][t][ci] (weights of the input-gradient conv)
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
-// weight gradient: part needs wgrad_chunks * 27 * Co * Ci floats; dw [Co][27][Ci],
-// db [Co] (nullable).  Ci % 16 == 0, Co % 16 == 0, chunk % 32 == 0.
+// weight gradient: part needs wgrad_part_floats floats; dw [Co][27][Ci], db [Co]
+// (nullable).  Ci % 16 == 0, Co % 16 == 0, (Co/16)(Ci/16) <= 64, chunk from
+// wgrad_chunk_for (a multiple of 64).
 long long wgrad_chunks(const int* dims, int chunk);
 int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats);
+long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk);
 hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
                  float* part, float* dw, float* db, hipStream_t s);
 hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n, uint16_t* dz,
@@ -31,9 +33,9 @@ hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0
                   hipStream_t s);
 hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
                   hipStream_t s);
-hipError_t copy_channels(const uint16_t* x, long long nv, int C, int Cf, int c0, uint16_t* y,
+hipError_t copy_channels(const uint16_t* x, const int* dims, int C, int Cf, int c0, uint16_t* y,
                          hipStream_t s);
-hipError_t slice_copy(const float* dy, long long nv, int C, int Cf, int c0, float* dx,
+hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, float* dx,
                       hipStream_t s);
 // network input from normalised FP32 maps (rho nullable): channel 0 dose,
 // channel 1 density, the rest zero; resid = dose

@@ -47,47 +47,95 @@ __device__ __forceinline__ long long shifted(const Geo& g, long long v, int t) {
 
 // ---------------------------------------------------------------------------
 // conv3d 3x3x3, zero padding 1, stride 1: y[v][co] = act(bias[co] +
-//   sum_{t, ci} x[shift(v, t)][ci] w[co][t][ci]).
-// Implicit GEMM: M = voxels, N = Co, K = 27 Ci (k = t*Ci + ci).  One wave owns
-// 16 voxels and all Co (Co/16 accumulator tiles); a workgroup has 4 waves.
-// Outputs: bf16 (optional) and/or FP32 (optional, added to when accumulate).
+//   sum_{t, ci} x[shift(v, t)][ci] w[co][t][ci]), as an implicit GEMM with
+// M = voxels, N = Co, K = 27 Ci (k = t*Ci + ci), outputs bf16 (optional)
+// and/or FP32 (optional, added to when accumulate).  The K dimension
+// (k = t*Ci + ci) is walked in slabs of kSlab: the workgroup copies
+// W[:, slab] into LDS ([co][kSlab + 8] bf16; the 16-byte row pad puts the 16
+// rows a quarter-wave reads on distinct banks), then every wave multiplies
+// MT 16-voxel row tiles by all NT 16-channel column tiles, so each weight
+// fragment read from LDS feeds MT matrix-core ops and each gathered input
+// fragment feeds NT.  Voxel coordinates are decoded once per kernel and
+// the (tap, channel) position of each lane advances incrementally.
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ void __launch_bounds__(256) k_conv_fwd(const uint16_t* __restrict__ x,
-                                                  const uint16_t* __restrict__ w,
-                                                  const float* __restrict__ bias, Geo g, int Ci,
-                                                  int Co, float alpha, int act,
-                                                  uint16_t* __restrict__ y16,
-                                                  float* __restrict__ y32, int accumulate) {
+constexpr int kSlab = 128;
+constexpr int kSlabRow = kSlab + 8;
+
+template <int NT, int MT>
+__global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict__ x,
+                                                      const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias, Geo g,
+                                                      int Ci, int Co, float alpha, int act,
+                                                      uint16_t* __restrict__ y16,
+                                                      float* __restrict__ y32, int accumulate) {
+    extern __shared__ __align__(16) uint16_t wl[];   // [NT*16][kSlabRow]
     const int lane = threadIdx.x & 63;
-    const long long base = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     const long long nv = g.nvox();
-    if (base >= nv) return;
-    f32x4 acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const long long vrow = base + (lane & 15);   // A row of this lane
+    const long long base = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * MT);
     const int K = 27 * Ci;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const int kk = k0 + (lane >> 4) * 8;      // first k of this lane's 8
-        uint4 av = make_uint4(0, 0, 0, 0);
-        int t = 0, ci = 0;
-        const bool kin = kk < K;
-        if (kin) {
-            t = kk / Ci;
-            ci = kk - t * Ci;
-            if (vrow < nv) {
-                const long long s = shifted(g, vrow, t);
-                if (s >= 0) av = *reinterpret_cast<const uint4*>(x + s * Ci + ci);
-            }
-        }
-        const bf16x8 a = as_bf16x8(av);
+    // this lane's A rows: voxel coordinates, decoded once
+    int vx[MT], vy[MT], vz[MT];
+    bool ok[MT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int co = j * 16 + (lane & 15);
-            uint4 bv = make_uint4(0, 0, 0, 0);
-            if (kin && co < Co) bv = *reinterpret_cast<const uint4*>(w + ((size_t)co * 27 + t) * Ci + ci);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(bv), acc[j], 0, 0, 0);
+    for (int m = 0; m < MT; ++m) {
+        const long long v = base + m * 16 + (lane & 15);
+        ok[m] = v < nv;
+        const long long vv = ok[m] ? v : 0;
+        vx[m] = (int)(vv % g.W);
+        vy[m] = (int)((vv / g.W) % g.H);
+        vz[m] = (int)((vv / ((long long)g.W * g.H)) % g.D);
+    }
+    const long long plane = (long long)g.W * g.H;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // (tap, channel) of this lane's first k: k = (lane / 16) * 8
+    int t = ((lane >> 4) * 8) / Ci;
+    int ci = ((lane >> 4) * 8) - t * Ci;
+    const int rows = NT * 16;
+    for (int k0 = 0; k0 < K; k0 += kSlab) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < rows * (kSlab / 8); i += blockDim.x) {
+            const int r = i / (kSlab / 8), c = (i - r * (kSlab / 8)) * 8;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (r < Co && k0 + c < K)
+                val = *reinterpret_cast<const uint4*>(w + (size_t)r * K + k0 + c);
+            *reinterpret_cast<uint4*>(wl + r * kSlabRow + c) = val;
+        }
+        __syncthreads();
+        for (int kc = 0; kc < kSlab && k0 + kc < K; kc += 32) {
+            const int kk = kc + (lane >> 4) * 8;
+            const bool kin = k0 + kk < K;
+            bf16x8 a[MT];
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                uint4 av = make_uint4(0, 0, 0, 0);
+                const int xs = vx[m] + dx, ys = vy[m] + dy, zs = vz[m] + dz;
+                if (kin && ok[m] && xs >= 0 && ys >= 0 && zs >= 0 && xs < g.W && ys < g.H &&
+                    zs < g.D) {
+                    const long long sv = base + m * 16 + (lane & 15) + dx + (long long)dy * g.W +
+                                         dz * plane;
+                    av = *reinterpret_cast<const uint4*>(x + sv * Ci + ci);
+                }
+                a[m] = as_bf16x8(av);
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const uint4 bv =
+                    *reinterpret_cast<const uint4*>(wl + (j * 16 + (lane & 15)) * kSlabRow + kk);
+                const bf16x8 b = as_bf16x8(bv);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][j], 0, 0, 0);
+            }
+            ci += 32;
+            while (ci >= Ci) {
+                ci -= Ci;
+                ++t;
+            }
         }
     }
 #pragma unroll
@@ -96,13 +144,16 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const uint16_t* __restrict__ x
         if (co >= Co) continue;
         const float b = bias ? bias[co] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long long v = base + (lane >> 4) * 4 + i;
-            if (v >= nv) continue;
-            float r = acc[j][i] + b;
-            if (act) r = r > 0.0f ? r : alpha * r;
-            if (y16) y16[v * Co + co] = f2bf(r);
-            if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + r : r;
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long v = base + m * 16 + (lane >> 4) * 4 + i;
+                if (v >= nv) continue;
+                float r = acc[m][j][i] + b;
+                if (act) r = r > 0.0f ? r : alpha * r;
+                if (y16) y16[v * Co + co] = f2bf(r);
+                if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + r : r;
+            }
         }
     }
 }
@@ -117,73 +168,139 @@ __global__ void k_flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient, split over voxel chunks: part[c][t][co][ci] =
-//   sum_{v in chunk c} dz[v][co] x[shift(v, t)][ci].  Workgroup = (chunk, tap).
-// 32-voxel slices of dz and of the shifted x are staged transposed in LDS
-// ([channel][voxel], rows padded to 40 elements so that the 16 rows a
-// quarter-wave reads fall on distinct banks); each lane reads its 8
-// consecutive voxels in one 16-byte load.  Waves own 16x16 (co, ci) tiles.
+// Weight and bias gradients, split over voxel chunks:
+//   part[c][t][co][ci] = sum_{v in chunk c} dz[v][co] x[shift(v, t)][ci],
+//   part_b[c][co]      = sum_{v in chunk c} dz[v][co].
+// Workgroup = (chunk, group of tg taps).  64-voxel slices of dz and of the
+// tg shifted copies of x are staged transposed in LDS ([channel][voxel],
+// rows padded to 72 elements = an odd number of 16-byte units, so the 16
+// rows a quarter-wave reads fall on distinct banks); the dz slice is staged
+// once for all taps of the group and the slice's voxel coordinates are
+// decoded once.  The block's tg x (Co/16) x (Ci/16) output tiles (at most
+// 64) are spread over its 4 waves; each lane reads 8 consecutive voxels in
+// one 16-byte load per operand.
 // ---------------------------------------------------------------------------
-constexpr int kWgMaxTiles = 16;
-constexpr int kWgRow = 40;
+constexpr int kWgSlice = 64;
+constexpr int kWgRow = kWgSlice + 8;
+constexpr int kWgWaves = 4;
+constexpr int kWgMaxTiles = 16;          // per wave
+constexpr int kWgLdsMax = 65536;         // bytes of LDS per workgroup
 
-__global__ void __launch_bounds__(512) k_wgrad_partial(const uint16_t* __restrict__ dz,
+int wgrad_taps_per_group(int Ci, int Co) {
+    const int ntiles = (Co / 16) * (Ci / 16);
+    int tg = (kWgWaves * kWgMaxTiles) / ntiles;
+    if (tg > 27) tg = 27;
+    if (tg < 1) tg = 1;
+    while (tg > 1 && (size_t)(Co + tg * Ci) * kWgRow * sizeof(uint16_t) > (size_t)kWgLdsMax) --tg;
+    return tg;
+}
+
+__global__ void __launch_bounds__(256) k_wgrad_partial(const uint16_t* __restrict__ dz,
                                                        const uint16_t* __restrict__ x, Geo g,
-                                                       int Ci, int Co, int chunk,
-                                                       float* __restrict__ part) {
-    extern __shared__ __align__(16) uint16_t lds[];   // [Co][kWgRow] then [Ci][kWgRow]
+                                                       int Ci, int Co, int chunk, int tg,
+                                                       float* __restrict__ part,
+                                                       float* __restrict__ part_b) {
+    extern __shared__ __align__(16) uint16_t lds[];   // [Co][kWgRow], then [tg][Ci][kWgRow]
+    __shared__ int cx[kWgSlice], cy[kWgSlice], cz[kWgSlice];
     uint16_t* dzT = lds;
     uint16_t* xT = lds + Co * kWgRow;
-    const int t = blockIdx.y;
+    const int t0 = blockIdx.y * tg;
+    const int ntap = min(tg, 27 - t0);
     const long long c = blockIdx.x;
     const long long v0 = c * chunk;
     const long long nv = g.nvox();
     const long long v1 = v0 + chunk < nv ? v0 + chunk : nv;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int tci = Ci / 16, ntiles = (Co / 16) * tci;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tci = Ci / 16, ntiles = (Co / 16) * tci, total = ntap * ntiles;
+    const bool do_bias = blockIdx.y == 0 && tid < Co;
+    const long long plane = (long long)g.W * g.H;
     f32x4 acc[kWgMaxTiles];
 #pragma unroll
     for (int j = 0; j < kWgMaxTiles; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long long s0 = v0; s0 < v1; s0 += 32) {
+    float bsum = 0.0f;
+    for (long long s0 = v0; s0 < v1; s0 += kWgSlice) {
         __syncthreads();
-        for (int i = threadIdx.x; i < 32 * Co; i += blockDim.x) {
-            const int vv = i / Co, ch = i - vv * Co;
-            const long long v = s0 + vv;
-            dzT[ch * kWgRow + vv] = v < v1 ? dz[v * Co + ch] : (uint16_t)0;
-        }
-        for (int i = threadIdx.x; i < 32 * Ci; i += blockDim.x) {
-            const int vv = i / Ci, ch = i - vv * Ci;
-            const long long v = s0 + vv;
-            uint16_t val = 0;
+        if (tid < kWgSlice) {
+            const long long v = s0 + tid;
             if (v < v1) {
-                const long long sv = shifted(g, v, t);
-                if (sv >= 0) val = x[sv * Ci + ch];
+                cx[tid] = (int)(v % g.W);
+                cy[tid] = (int)((v / g.W) % g.H);
+                cz[tid] = (int)((v / plane) % g.D);
+            } else {
+                cx[tid] = -4;   // every shift leaves the volume
+                cy[tid] = -4;
+                cz[tid] = -4;
             }
-            xT[ch * kWgRow + vv] = val;
         }
+        // dz slice: one 16-byte load (8 channels of one voxel) per item
+        const int gco = Co / 8, gci = Ci / 8;
+        for (int i = tid; i < kWgSlice * gco; i += blockDim.x) {
+            const int vv = i / gco, ch = (i - vv * gco) * 8;
+            const long long v = s0 + vv;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (v < v1) val = *reinterpret_cast<const uint4*>(dz + v * Co + ch);
+            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                dzT[(ch + 2 * k) * kWgRow + vv] = (uint16_t)(w4[k] & 0xFFFFu);
+                dzT[(ch + 2 * k + 1) * kWgRow + vv] = (uint16_t)(w4[k] >> 16);
+            }
+        }
+        __syncthreads();
+        // shifted x slices of the group's taps, 8 channels per item
+        for (int i = tid; i < ntap * kWgSlice * gci; i += blockDim.x) {
+            const int tl = i / (kWgSlice * gci);
+            const int r = i - tl * (kWgSlice * gci);
+            const int vv = r / gci, ch = (r - vv * gci) * 8;
+            const int t = t0 + tl;
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dzz = t / 9 - 1;
+            const int xs = cx[vv] + dx, ys = cy[vv] + dy, zs = cz[vv] + dzz;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (xs >= 0 && ys >= 0 && zs >= 0 && xs < g.W && ys < g.H && zs < g.D) {
+                const long long sv = s0 + vv + dx + (long long)dy * g.W + dzz * plane;
+                val = *reinterpret_cast<const uint4*>(x + sv * Ci + ch);
+            }
+            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+            uint16_t* row = xT + (tl * Ci + ch) * kWgRow + vv;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                row[(2 * k) * kWgRow] = (uint16_t)(w4[k] & 0xFFFFu);
+                row[(2 * k + 1) * kWgRow] = (uint16_t)(w4[k] >> 16);
+            }
+        }
+        if (do_bias)
+            for (int vv = 0; vv < kWgSlice; ++vv) bsum += bf2f(dzT[tid * kWgRow + vv]);
         __syncthreads();
         const int koff = (lane >> 4) * 8;
 #pragma unroll
         for (int j = 0; j < kWgMaxTiles; ++j) {
-            const int tile = wave + j * nwaves;
-            if (tile >= ntiles) break;
-            const int co0 = (tile / tci) * 16, ci0 = (tile % tci) * 16;
-            const uint4 av = *reinterpret_cast<const uint4*>(dzT + (co0 + (lane & 15)) * kWgRow + koff);
-            const uint4 bv = *reinterpret_cast<const uint4*>(xT + (ci0 + (lane & 15)) * kWgRow + koff);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc[j],
-                                                             0, 0, 0);
+            const int tile = wave + j * kWgWaves;
+            if (tile >= total) break;
+            const int tl = tile / ntiles, r = tile - tl * ntiles;
+            const int co0 = (r / tci) * 16, ci0 = (r % tci) * 16;
+#pragma unroll
+            for (int kh = 0; kh < kWgSlice; kh += 32) {
+                const uint4 av = *reinterpret_cast<const uint4*>(
+                    dzT + (co0 + (lane & 15)) * kWgRow + kh + koff);
+                const uint4 bv = *reinterpret_cast<const uint4*>(
+                    xT + (tl * Ci + ci0 + (lane & 15)) * kWgRow + kh + koff);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv),
+                                                                 acc[j], 0, 0, 0);
+            }
         }
     }
-    float* out = part + ((size_t)c * 27 + t) * Co * Ci;
 #pragma unroll
     for (int j = 0; j < kWgMaxTiles; ++j) {
-        const int tile = wave + j * nwaves;
-        if (tile >= ntiles) break;
-        const int co0 = (tile / tci) * 16, ci0 = (tile % tci) * 16;
+        const int tile = wave + j * kWgWaves;
+        if (tile >= total) break;
+        const int tl = tile / ntiles, r = tile - tl * ntiles;
+        const int co0 = (r / tci) * 16, ci0 = (r % tci) * 16;
+        float* out = part + ((size_t)c * 27 + t0 + tl) * Co * Ci;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             out[(size_t)(co0 + (lane >> 4) * 4 + i) * Ci + ci0 + (lane & 15)] = acc[j][i];
     }
+    if (do_bias) part_b[c * Co + tid] = bsum;
 }
 
 // dW[co][t][ci] = sum_c part[c][t][co][ci] (fixed order: deterministic).
@@ -197,22 +314,6 @@ __global__ void k_wgrad_reduce(const float* part, int nchunk, int Ci, int Co, fl
     }
 }
 
-// db[co] = sum_v dz[v][co], one block per channel (fixed order within the block).
-__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* dz, long long nv, int Co,
-                                                   float* db) {
-    const int co = blockIdx.x;
-    float s = 0.0f;
-    for (long long v = threadIdx.x; v < nv; v += blockDim.x) s += bf2f(dz[v * Co + co]);
-    __shared__ float red[256];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[co] = red[0];
-}
-
 // dz = dy * (y > 0 ? 1 : alpha), in bf16 (LeakyReLU backward from the output sign).
 __global__ void k_lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n,
                             uint16_t* dz) {
@@ -223,97 +324,132 @@ __global__ void k_lrelu_bwd(const float* dy, const uint16_t* y, float alpha, lon
     }
 }
 
-// 2x2x2 average pooling (dims even): y[b][z][y][x][c] = mean of the 8 children.
-__global__ void k_pool_fwd(const uint16_t* x, Geo go, int C, uint16_t* y) {
-    const long long n = go.nvox() * C;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long v = i / C;
-        const int xo = (int)(v % go.W), yo = (int)((v / go.W) % go.H);
-        const int zo = (int)((v / ((long long)go.W * go.H)) % go.D);
-        const long long b = v / ((long long)go.W * go.H * go.D);
-        const int Wi = go.W * 2, Hi = go.H * 2, Di = go.D * 2;
-        float s = 0.0f;
-        for (int d = 0; d < 8; ++d) {
-            const long long vi = (((b * Di + 2 * zo + (d >> 2)) * Hi + 2 * yo + ((d >> 1) & 1)) * Wi +
-                                  2 * xo + (d & 1));
-            s += bf2f(x[vi * C + c]);
-        }
-        y[i] = f2bf(0.125f * s);
+// Layout kernels.  Launched on a (ceil(W*G/256), H, D*B) grid over a
+// volume's voxels: the x dimension enumerates (x, group) with G channel
+// groups per voxel (8 bf16 or 4 FP32 channels per group, one 16-byte
+// access), y and z come from the block index, so no thread divides by a
+// runtime size except the small G.
+struct VoxG {
+    int x, grp;
+    long long v;   // linear voxel index
+    int y, z, b;
+};
+
+__device__ __forceinline__ bool vox_of(const Geo& g, int G, VoxG& o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.W * G) return false;
+    o.x = i / G;
+    o.grp = i - o.x * G;
+    o.y = blockIdx.y;
+    o.b = blockIdx.z / g.D;
+    o.z = blockIdx.z - o.b * g.D;
+    o.v = ((long long)blockIdx.z * g.H + o.y) * g.W + o.x;
+    return true;
+}
+
+inline dim3 vox_grid(const Geo& g, int G) {
+    return dim3((unsigned)((g.W * G + 255) / 256), (unsigned)g.H, (unsigned)(g.D * g.B));
+}
+
+__device__ __forceinline__ long long child(const Geo& gc, const VoxG& c, int d) {
+    // fine voxel d (0..7) of coarse voxel c; fine dims are twice gc's
+    const int Wf = gc.W * 2, Hf = gc.H * 2, Df = gc.D * 2;
+    return (((long long)c.b * Df + 2 * c.z + (d >> 2)) * Hf + 2 * c.y + ((d >> 1) & 1)) * Wf +
+           2 * c.x + (d & 1);
+}
+
+__device__ __forceinline__ long long parent(const Geo& gf, const VoxG& f) {
+    return (((long long)f.b * (gf.D / 2) + f.z / 2) * (gf.H / 2) + f.y / 2) * (gf.W / 2) + f.x / 2;
+}
+
+__device__ __forceinline__ void bf16x8_to_f32(uint4 u, float* f) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(w[k] << 16);
+        f[2 * k + 1] = __uint_as_float(w[k] & 0xFFFF0000u);
     }
 }
 
-// Pooling backward: dx (FP32, fine grid) += dy(parent) / 8.
-__global__ void k_pool_bwd(const float* dy, Geo gi, int C, float* dx) {
-    const long long n = gi.nvox() * C;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long v = i / C;
-        const int xi = (int)(v % gi.W), yi = (int)((v / gi.W) % gi.H);
-        const int zi = (int)((v / ((long long)gi.W * gi.H)) % gi.D);
-        const long long b = v / ((long long)gi.W * gi.H * gi.D);
-        const int Wo = gi.W / 2, Ho = gi.H / 2, Do = gi.D / 2;
-        const long long vo = ((b * Do + zi / 2) * Ho + yi / 2) * Wo + xi / 2;
-        dx[i] += 0.125f * dy[vo * C + c];
+__device__ __forceinline__ uint4 f32_to_bf16x8(const float* f) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// 2x2x2 average pooling (dims even): y[b][z][y][x][c] = mean of the 8 children.
+// Grid over the coarse (output) volume go, 8 channels per thread.
+__global__ void k_pool_fwd(const uint16_t* x, Geo go, int C, uint16_t* y) {
+    VoxG o;
+    if (!vox_of(go, C / 8, o)) return;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < 8; ++d) {
+        float f[8];
+        bf16x8_to_f32(*reinterpret_cast<const uint4*>(x + child(go, o, d) * C + o.grp * 8), f);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += f[k];
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] *= 0.125f;
+    *reinterpret_cast<uint4*>(y + o.v * C + o.grp * 8) = f32_to_bf16x8(s);
+}
+
+// Pooling backward: dx (FP32, fine grid gi) += dy(parent) / 8, 4 channels per thread.
+__global__ void k_pool_bwd(const float* dy, Geo gi, int C, float* dx) {
+    VoxG f;
+    if (!vox_of(gi, C / 4, f)) return;
+    const float4 p = *reinterpret_cast<const float4*>(dy + parent(gi, f) * C + f.grp * 4);
+    float4* q = reinterpret_cast<float4*>(dx + f.v * C + f.grp * 4);
+    float4 r = *q;
+    r.x += 0.125f * p.x;
+    r.y += 0.125f * p.y;
+    r.z += 0.125f * p.z;
+    r.w += 0.125f * p.w;
+    *q = r;
 }
 
 // Nearest x2 upsampling of a coarse tensor into channels [c0, c0+C) of a fine
-// tensor with Cf channels (the up half of a concatenation).
+// tensor with Cf channels (the up half of a concatenation); grid over the
+// fine volume gf, 8 channels per thread.
 __global__ void k_up_fwd(const uint16_t* x, Geo gf, int C, int Cf, int c0, uint16_t* y) {
-    const long long n = gf.nvox() * C;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long v = i / C;
-        const int xf = (int)(v % gf.W), yf = (int)((v / gf.W) % gf.H);
-        const int zf = (int)((v / ((long long)gf.W * gf.H)) % gf.D);
-        const long long b = v / ((long long)gf.W * gf.H * gf.D);
-        const long long vc = ((b * (gf.D / 2) + zf / 2) * (gf.H / 2) + yf / 2) * (gf.W / 2) + xf / 2;
-        y[v * Cf + c0 + c] = x[vc * C + c];
-    }
+    VoxG f;
+    if (!vox_of(gf, C / 8, f)) return;
+    *reinterpret_cast<uint4*>(y + f.v * Cf + c0 + f.grp * 8) =
+        *reinterpret_cast<const uint4*>(x + parent(gf, f) * C + f.grp * 8);
 }
 
-// Upsampling backward: dx(coarse) = sum over the 8 children of dy[.][c0 + c].
+// Upsampling backward: dx(coarse) = sum over the 8 children of dy[.][c0 + c];
+// grid over the coarse volume gc, 4 channels per thread.
 __global__ void k_up_bwd(const float* dy, Geo gc, int C, int Cf, int c0, float* dx) {
-    const long long n = gc.nvox() * C;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long v = i / C;
-        const int xc = (int)(v % gc.W), yc = (int)((v / gc.W) % gc.H);
-        const int zc = (int)((v / ((long long)gc.W * gc.H)) % gc.D);
-        const long long b = v / ((long long)gc.W * gc.H * gc.D);
-        const int Wf = gc.W * 2, Hf = gc.H * 2, Df = gc.D * 2;
-        float s = 0.0f;
-        for (int d = 0; d < 8; ++d) {
-            const long long vf = (((b * Df + 2 * zc + (d >> 2)) * Hf + 2 * yc + ((d >> 1) & 1)) * Wf +
-                                  2 * xc + (d & 1));
-            s += dy[vf * Cf + c0 + c];
-        }
-        dx[i] = s;
+    VoxG o;
+    if (!vox_of(gc, C / 4, o)) return;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int d = 0; d < 8; ++d) {
+        const float4 p = *reinterpret_cast<const float4*>(dy + child(gc, o, d) * Cf + c0 + o.grp * 4);
+        s.x += p.x;
+        s.y += p.y;
+        s.z += p.z;
+        s.w += p.w;
     }
+    *reinterpret_cast<float4*>(dx + o.v * C + o.grp * 4) = s;
 }
 
 // Copy channels [0, C) of x into channels [c0, c0+C) of y (Cf channels): the
-// skip half of a concatenation; and its backward (dx += dy slice).
-__global__ void k_copy_channels(const uint16_t* x, long long nv, int C, int Cf, int c0, uint16_t* y) {
-    const long long n = nv * C;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long v = i / C;
-        y[v * Cf + c0 + (i % C)] = x[i];
-    }
+// skip half of a concatenation (8 bf16 per thread); and its backward, the
+// slice dx = dy[:, c0:c0+C] (4 FP32 per thread).
+__global__ void k_copy_channels(const uint16_t* x, Geo g, int C, int Cf, int c0, uint16_t* y) {
+    VoxG o;
+    if (!vox_of(g, C / 8, o)) return;
+    *reinterpret_cast<uint4*>(y + o.v * Cf + c0 + o.grp * 8) =
+        *reinterpret_cast<const uint4*>(x + o.v * C + o.grp * 8);
 }
-__global__ void k_slice_copy(const float* dy, long long nv, int C, int Cf, int c0, float* dx) {
-    const long long n = nv * C;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long v = i / C;
-        dx[i] = dy[v * Cf + c0 + (i % C)];
-    }
+
+__global__ void k_slice_copy(const float* dy, Geo g, int C, int Cf, int c0, float* dx) {
+    VoxG o;
+    if (!vox_of(g, C / 4, o)) return;
+    *reinterpret_cast<float4*>(dx + o.v * C + o.grp * 4) =
+        *reinterpret_cast<const float4*>(dy + o.v * Cf + c0 + o.grp * 4);
 }
 
 // Network input from normalised maps: x[v] = {dose, rho, 0, ...} (Cx channels).
@@ -534,19 +670,19 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
                     int accumulate, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     const long long nv = g.nvox();
-    const int grid = (int)((nv + 63) / 64);
     const int nt = (Co + 15) / 16;
-#define LAUNCH(NT)                                                                           \
-    hipLaunchKernelGGL(k_conv_fwd<NT>, dim3(grid), dim3(256), 0, s, x, w, bias, g, Ci, Co, \
-                       alpha, act, y16, y32, accumulate)
+    const size_t lds = (size_t)nt * 16 * kSlabRow * sizeof(uint16_t);
+#define LAUNCH(NT, MT)                                                                        \
+    hipLaunchKernelGGL((k_conv_fwd_lds<NT, MT>), dim3((unsigned)((nv + 64 * MT - 1) / (64 * MT))), \
+                       dim3(256), lds, s, x, w, bias, g, Ci, Co, alpha, act, y16, y32, accumulate)
     switch (nt) {
-        case 1: LAUNCH(1); break;
-        case 2: LAUNCH(2); break;
-        case 3: LAUNCH(3); break;
-        case 4: LAUNCH(4); break;
-        case 6: LAUNCH(6); break;
-        case 8: LAUNCH(8); break;
-        case 12: LAUNCH(12); break;
+        case 1: LAUNCH(1, 4); break;
+        case 2: LAUNCH(2, 4); break;
+        case 3: LAUNCH(3, 4); break;
+        case 4: LAUNCH(4, 4); break;
+        case 6: LAUNCH(6, 2); break;
+        case 8: LAUNCH(8, 2); break;
+        case 12: LAUNCH(12, 2); break;
         default: return hipErrorInvalidValue;
     }
 #undef LAUNCH
@@ -564,35 +700,45 @@ long long wgrad_chunks(const int* dims, int chunk) {
     return (nv + chunk - 1) / chunk;
 }
 
+// Chunk length (a multiple of the 64-voxel slice) giving about 1024
+// workgroups in all, within max_part_floats of partial sums.
 int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats) {
     const long long nv = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-    long long target = max_part_floats / (27LL * Ci * Co);
-    if (target > 128) target = 128;
+    const int tg = wgrad_taps_per_group(Ci, Co);
+    const long long groups = (27 + tg - 1) / tg;
+    long long target = (1024 + groups - 1) / groups;
+    const long long cap = max_part_floats / (27LL * Ci * Co + Co);
+    if (target > cap) target = cap;
     if (target < 1) target = 1;
     long long chunk = (nv + target - 1) / target;
-    if (chunk < 256) chunk = 256;
-    chunk = (chunk + 31) / 32 * 32;
+    chunk = (chunk + kWgSlice - 1) / kWgSlice * kWgSlice;
+    if (chunk < kWgSlice) chunk = kWgSlice;
     return (int)chunk;
+}
+
+long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk) {
+    return wgrad_chunks(dims, chunk) * (27LL * Ci * Co + Co);
 }
 
 hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
                  float* part, float* dw, float* db, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     const long long nchunk = wgrad_chunks(dims, chunk);
-    const int ntiles = (Co / 16) * (Ci / 16);
-    int waves = (ntiles + kWgMaxTiles - 1) / kWgMaxTiles;
-    if (waves < 4) waves = 4;
-    if (waves > 8) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(Co + Ci) * kWgRow * sizeof(uint16_t);
-    hipLaunchKernelGGL(k_wgrad_partial, dim3((unsigned)nchunk, 27), dim3(64 * waves), lds, s, dz, x,
-                       g, Ci, Co, chunk, part);
+    const int tg = wgrad_taps_per_group(Ci, Co);
+    const int groups = (27 + tg - 1) / tg;
+    if (tg * (Co / 16) * (Ci / 16) > kWgWaves * kWgMaxTiles && tg > 1) return hipErrorInvalidValue;
+    if ((Co / 16) * (Ci / 16) > kWgWaves * kWgMaxTiles) return hipErrorInvalidValue;
+    const size_t lds = (size_t)(Co + tg * Ci) * kWgRow * sizeof(uint16_t);
+    float* part_b = part + nchunk * 27LL * Co * Ci;
+    hipLaunchKernelGGL(k_wgrad_partial, dim3((unsigned)nchunk, groups), dim3(64 * kWgWaves), lds, s,
+                       dz, x, g, Ci, Co, chunk, tg, part, part_b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(27LL * Co * Ci)), dim3(256), 0, s, part,
                        (int)nchunk, Ci, Co, dw);
     e = hipGetLastError();
     if (e != hipSuccess || !db) return e;
-    hipLaunchKernelGGL(k_bias_grad, dim3(Co), dim3(256), 0, s, dz, g.nvox(), Co, db);
+    hipLaunchKernelGGL(k_sum_rows, dim3(blocks_for(Co)), dim3(256), 0, s, part_b, (int)nchunk, Co, db);
     return hipGetLastError();
 }
 
@@ -604,39 +750,47 @@ hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long 
 
 hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, hipStream_t s) {
     Geo g{dims_out[0], dims_out[1], dims_out[2], dims_out[3]};
-    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, x, g, C, y);
+    if (C % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pool_fwd, vox_grid(g, C / 8), dim3(256), 0, s, x, g, C, y);
     return hipGetLastError();
 }
 
 hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s) {
     Geo g{dims_in[0], dims_in[1], dims_in[2], dims_in[3]};
-    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, dy, g, C, dx);
+    if (C % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pool_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, dx);
     return hipGetLastError();
 }
 
 hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0, uint16_t* y,
                   hipStream_t s) {
     Geo g{dims_fine[0], dims_fine[1], dims_fine[2], dims_fine[3]};
-    hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, x, g, C, Cf, c0, y);
+    if (C % 8 || Cf % 8 || c0 % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_up_fwd, vox_grid(g, C / 8), dim3(256), 0, s, x, g, C, Cf, c0, y);
     return hipGetLastError();
 }
 
 hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
                   hipStream_t s) {
     Geo g{dims_coarse[0], dims_coarse[1], dims_coarse[2], dims_coarse[3]};
-    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(g.nvox() * C)), dim3(256), 0, s, dy, g, C, Cf, c0, dx);
+    if (C % 4 || Cf % 4 || c0 % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_up_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, Cf, c0, dx);
     return hipGetLastError();
 }
 
-hipError_t copy_channels(const uint16_t* x, long long nv, int C, int Cf, int c0, uint16_t* y,
+hipError_t copy_channels(const uint16_t* x, const int* dims, int C, int Cf, int c0, uint16_t* y,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_channels, dim3(blocks_for(nv * C)), dim3(256), 0, s, x, nv, C, Cf, c0, y);
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (C % 8 || Cf % 8 || c0 % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy_channels, vox_grid(g, C / 8), dim3(256), 0, s, x, g, C, Cf, c0, y);
     return hipGetLastError();
 }
 
-hipError_t slice_copy(const float* dy, long long nv, int C, int Cf, int c0, float* dx,
+hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, float* dx,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_slice_copy, dim3(blocks_for(nv * C)), dim3(256), 0, s, dy, nv, C, Cf, c0, dx);
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (C % 4 || Cf % 4 || c0 % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_slice_copy, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, Cf, c0, dx);
     return hipGetLastError();
 }
 
@@ -673,7 +827,7 @@ hipError_t prepare_pair(const double* low, const double* high, long long n, cons
 }
 
 hipError_t max_abs(const double* a, long long n, unsigned long long* out_bits, hipStream_t s) {
-    hipLaunchKernelGGL(k_max_abs, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, a, n, out_bits);
+    hipLaunchKernelGGL(k_max_abs, dim3(blocks_for(n, 256, 1024)), dim3(256), 0, s, a, n, out_bits);
     return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ __device__ __forceinline__ void polar_cs(float th2, float& c, float& s) {
 __device__ __forceinline__ void turn(float& dx, float& dy, float& dz, float ct, float st,
                                      float cp, float sp) {
     const float sg = copysignf(1.0f, dz);
-    const float a = -1.0f / (sg + dz);
+    const float a = -frcp(sg + dz);   // |sg + dz| >= 1
     const float b = dx * dy * a;
     const float b1x = 1.0f + sg * dx * dx * a, b1y = sg * b, b1z = -sg * dx;
     const float b2x = b, b2y = sg + dy * dy * a, b2z = -dy;
@@ -114,29 +114,29 @@ __device__ __forceinline__ long long fixp(float e, float wsc) {
     return (long long)rintf(e * wsc);
 }
 
-// Add q to voxel v: the workgroup's LDS tile if v lies in it, else this
-// XCD's replica of the global tally (hot lines then stay in one L2).
-__device__ __forceinline__ void tally_add(const KParams& P, unsigned long long* tile,
-                                          unsigned long long* rep, int v, long long q) {
-    const int ix = v % P.nx, iy = (v / P.nx) % P.ny, iz = v / (P.nx * P.ny);
-    const unsigned tx = (unsigned)(ix - P.tile_x0), ty = (unsigned)(iy - P.tile_y0),
-                   tz = (unsigned)(iz - P.tile_z0);
-    if (tx < (unsigned)P.tile_nx && ty < (unsigned)P.tile_ny && tz < (unsigned)P.tile_nz)
-        atomicAdd(&tile[(tz * P.tile_ny + ty) * P.tile_nx + tx], (unsigned long long)q);
-    else
-        atomicAdd(&rep[v], (unsigned long long)q);
-}
-
 // Per-lane deposit accumulator: consecutive deposits into the same voxel are
-// summed in registers and written once when the voxel changes.
+// summed in registers and written once when the voxel changes.  The voxel's
+// coordinates are kept beside its linear index so that the tile test needs
+// no division.
 struct Acc {
     int v;
+    int ix, iy, iz;
     long long q;
 };
 
+// Add the accumulated q: into the workgroup's LDS tile if the voxel lies in
+// it, else into this XCD's replica of the global tally (hot lines then stay
+// in one L2).
 __device__ __forceinline__ void acc_flush(const KParams& P, unsigned long long* tile,
                                           unsigned long long* rep, Acc& a) {
-    if (a.v >= 0 && a.q != 0) tally_add(P, tile, rep, a.v, a.q);
+    if (a.v >= 0 && a.q != 0) {
+        const unsigned tx = (unsigned)(a.ix - P.tile_x0), ty = (unsigned)(a.iy - P.tile_y0),
+                       tz = (unsigned)(a.iz - P.tile_z0);
+        if (tx < (unsigned)P.tile_nx && ty < (unsigned)P.tile_ny && tz < (unsigned)P.tile_nz)
+            atomicAdd(&tile[(tz * P.tile_ny + ty) * P.tile_nx + tx], (unsigned long long)a.q);
+        else
+            atomicAdd(&rep[a.v], (unsigned long long)a.q);
+    }
     a.v = -1;
     a.q = 0;
 }
@@ -159,6 +159,9 @@ __device__ __forceinline__ void score(const KParams& P, unsigned long long* tile
     } else {
         acc_flush(P, tile, rep, a);
         a.v = v;
+        a.ix = ix;
+        a.iy = iy;
+        a.iz = iz;
         a.q = q;
     }
 }
@@ -383,7 +386,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     // lines in one L2)
     const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;   // HW_REG_XCC_ID
     unsigned long long* rep = P.tally + (size_t)(xcc % (unsigned)P.n_rep) * P.rep_stride;
-    Acc acc{-1, 0};
+    Acc acc{-1, 0, 0, 0, 0};
     int state = kDead;
     bool more = true;   // wave-uniform: the work counter may still hold histories
     unsigned long long q_next = 0, q_end = 0;   // wave-local range of history indices
@@ -554,11 +557,11 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // straggling, Eq. (energystraggling), B_n ~ N(0, Delta).
         const float p2 = E * (E + 2.0f * kMpF);
         const float g = E + kMpF;
-        const float b2 = p2 / (g * g);
+        const float b2 = p2 * frcp(g * g);
         float s1 = 0.0f;
         if (P.flags & kLoss) {
             const float L = mc.y + flog(p2) - b2;
-            s1 = rho * P.c_bethe * mc.x * L * (g * g) / p2;
+            s1 = rho * P.c_bethe * mc.x * L * frcp(b2);
         }
         const float a = s1 * P.step;
         float X = 0.0f;
@@ -881,7 +884,9 @@ hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int
 }
 
 hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s) {
-    hipLaunchKernelGGL(k_max, dim3(grid_for(n, 256)), dim3(256), 0, s, a, n, out_bits);
+    // a grid-stride pass over few blocks: one same-address atomic per wave
+    const int grid = grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024;
+    hipLaunchKernelGGL(k_max, dim3(grid), dim3(256), 0, s, a, n, out_bits);
     return hipGetLastError();
 }
 

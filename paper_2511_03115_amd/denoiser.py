@@ -126,6 +126,109 @@ class PairSet:
     rho: object           # float32 (n_in, D, H, W) density
     n_in: np.ndarray      # histories of each input
 
+    def sample(self, rng, batch: int):
+        """A random mini-batch (lo, rho, hi, wt) of whole pairs."""
+        import torch
+        idx = torch.from_numpy(rng.choice(self.lo.shape[0], size=batch, replace=False)).cuda()
+        return tuple(t.index_select(0, idx) for t in (self.lo, self.rho, self.hi, self.wt))
+
+    def batches(self, batch: int):
+        """The whole set in order, as (lo, rho, hi, wt) mini-batches."""
+        for s in range(0, self.lo.shape[0], batch):
+            e = min(s + batch, self.lo.shape[0])
+            yield self.lo[s:e], self.rho[s:e], self.hi[s:e], self.wt[s:e]
+
+
+@dataclass
+class PlanPairs:
+    """Normalised pairs on whole plan grids (N, nz, ny, nx) resident on the
+    device, sampled as random crops of ``crop`` = (D, H, W) voxels that
+    overlap the field (``lo_zyx``..``hi_zyx`` bounds the crops' origins)."""
+    lo: object
+    hi: object
+    wt: object
+    rho: object
+    n_in: np.ndarray
+    crop: Tuple[int, int, int]
+    lo_zyx: Tuple[int, int, int]
+    hi_zyx: Tuple[int, int, int]
+
+    def _crop(self, k: int, z: int, y: int, x: int):
+        D, H, W = self.crop
+        sl = (k, slice(z, z + D), slice(y, y + H), slice(x, x + W))
+        return [t[sl] for t in (self.lo, self.rho, self.hi, self.wt)]
+
+    def sample(self, rng, batch: int):
+        import torch
+        parts = [[], [], [], []]
+        for _ in range(batch):
+            k = int(rng.integers(0, self.lo.shape[0]))
+            z, y, x = (int(rng.integers(a, b + 1)) for a, b in zip(self.lo_zyx, self.hi_zyx))
+            for p, t in zip(parts, self._crop(k, z, y, x)):
+                p.append(t)
+        return tuple(torch.stack(p).contiguous() for p in parts)
+
+    def batches(self, batch: int, per_map: int = 4, seed: int = 12345):
+        """Fixed crops (``per_map`` per map, seeded) for validation."""
+        rng = np.random.default_rng(seed)
+        crops = []
+        for k in range(self.lo.shape[0]):
+            for _ in range(per_map):
+                crops.append((k,) + tuple(int(rng.integers(a, b + 1))
+                                          for a, b in zip(self.lo_zyx, self.hi_zyx)))
+        import torch
+        for s in range(0, len(crops), batch):
+            parts = [[], [], [], []]
+            for c in crops[s:s + batch]:
+                for p, t in zip(parts, self._crop(*c)):
+                    p.append(t)
+            yield tuple(torch.stack(p).contiguous() for p in parts)
+
+
+def generate_plan_pairs(variants: Sequence[int], n_low: Sequence[int], n_high: int,
+                        crop=(128, 64, 64), eps: float = 0.02, thr: float = 0.01, launch=None,
+                        log=print) -> PlanPairs:
+    """For each plan variant k (``workloads.configs.plan_variant``): one run
+    at ``n_high`` histories per spot and one at each of ``n_low`` per spot
+    (independent seeds), each low map normalised with its high map."""
+    import torch
+    import workloads
+    from dataclasses import replace
+    from workloads import configs
+    t0 = time.time()
+    wl0 = configs.plan_variant(int(variants[0]), 1)
+    sde.init_materials(wl0.phantom.materials, wl0.params,
+                       workloads.nuclear_for_phantom(wl0.phantom, wl0.params.lattice()))
+    nz, ny, nx = wl0.phantom.material_id.shape
+    n = len(variants) * len(n_low)
+    f32 = dict(dtype=torch.float32, device="cuda")
+    lo, hi, wt, rho = (torch.empty((n, nz, ny, nx), **f32) for _ in range(4))
+    nin = np.zeros(n, np.int64)
+    prep = nn.Net(1, 16, 16, 0.01, 1, (1, 1, 1), train=False)
+    d_hi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    d_lo = torch.empty_like(d_hi)
+    k = 0
+    for j, v in enumerate(variants):
+        wl = configs.plan_variant(int(v), int(n_high))
+        dph = sde.DevicePhantom.from_host(wl.phantom)
+        sde.transport(wl.spots, dph, wl.seed, dose_out=d_hi, launch=launch)
+        for r, nl in enumerate(n_low):
+            spots = [replace(sp, n_histories=int(nl)) for sp in wl.spots]
+            sde.transport(spots, dph, wl.seed + 7_000_003 * (r + 1), dose_out=d_lo, launch=launch)
+            prep.prepare_pair(d_lo, d_hi, lo[k], hi[k], wt[k], eps=eps, thr=thr)
+            rho[k].copy_(dph.density)
+            nin[k] = int(nl)
+            k += 1
+        torch.cuda.synchronize()
+        log(f"[pairs] plan variant {v}: {j + 1}/{len(variants)} ({time.time() - t0:.1f} s)")
+    prep.close()
+    D, H, W = crop
+    # crop origins: depth from the entrance, laterally over the spot raster
+    cy, cx = ny // 2, nx // 2
+    lo_zyx = (0, max(0, cy - 24 - H // 2), max(0, cx - 24 - W // 2))
+    hi_zyx = (nz - D, min(ny - H, cy + 24 - H // 2), min(nx - W, cx + 24 - W // 2))
+    return PlanPairs(lo, hi, wt, rho, nin, (D, H, W), lo_zyx, hi_zyx)
+
 
 def generate_pairs(indices: Sequence[int], inputs_per_target: int = 4,
                    n_in_choices: Sequence[int] = (30_000, 100_000, 300_000),
@@ -186,47 +289,44 @@ def cosine_lr(step: int, total: int, lr_max: float, lr_min: float, warmup: int) 
     return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * min(1.0, t)))
 
 
-def evaluate(net: nn.Net, ps: PairSet, batch: int) -> float:
-    """Mean weighted loss of the network on a pair set (a network with zero
-    parameters gives the loss of the input itself, i.e. of no network)."""
-    losses = []
-    for s in range(0, ps.lo.shape[0], batch):
-        e = min(s + batch, ps.lo.shape[0])
-        losses.append(net.loss_grad(ps.lo[s:e], ps.rho[s:e], ps.hi[s:e], ps.wt[s:e]) * (e - s))
-    return float(np.sum(losses) / ps.lo.shape[0])
+def evaluate(net: nn.Net, ps, batch: int) -> float:
+    """Mean weighted loss of the network on a pair set's fixed batches (a
+    network with zero parameters gives the loss of the input itself, i.e.
+    of no network)."""
+    tot, n = 0.0, 0
+    for lo, rho, hi, wt in ps.batches(batch):
+        tot += net.loss_grad(lo, rho, hi, wt) * lo.shape[0]
+        n += lo.shape[0]
+    return tot / max(n, 1)
 
 
-def relative_errors(net: nn.Net, ps: PairSet, thr: float = 0.01) -> Tuple[float, float]:
+def relative_errors(net: nn.Net, ps, thr: float = 0.01) -> Tuple[float, float]:
     """Root-mean-square relative error against the target, over voxels with
     target >= thr, of the inputs and of the network's outputs (a metric of
     the evaluation, computed with torch on the device)."""
     import torch
     e_in, e_out = [], []
-    out = torch.empty_like(ps.lo[:1])
-    for k in range(ps.lo.shape[0]):
-        net.forward(ps.lo[k:k + 1], ps.rho[k:k + 1], out)
-        h = ps.hi[k:k + 1]
-        m = h >= thr
-        e_in.append(torch.sqrt((((ps.lo[k:k + 1] - h) / h)[m] ** 2).mean()).item())
-        e_out.append(torch.sqrt((((out - h) / h)[m] ** 2).mean()).item())
+    for lo, rho, hi, _ in ps.batches(1):
+        out = torch.empty_like(lo)
+        net.forward(lo, rho, out)
+        m = hi >= thr
+        e_in.append(torch.sqrt((((lo - hi) / hi)[m] ** 2).mean()).item())
+        e_out.append(torch.sqrt((((out - hi) / hi)[m] ** 2).mean()).item())
     return float(np.mean(e_in)), float(np.mean(e_out))
 
 
-def train(net: nn.Net, ps: PairSet, steps: int, batch: int = 4, lr_max: float = 3e-4,
+def train(net: nn.Net, ps, steps: int, batch: int = 4, lr_max: float = 3e-4,
           lr_min: float = 1e-5, warmup: int = 200, seed: int = 0, log=print,
-          log_every: int = 50, val: Optional[PairSet] = None, checkpoint: Optional[str] = None,
+          log_every: int = 50, val=None, checkpoint: Optional[str] = None,
           checkpoint_every: int = 500) -> List[Tuple[int, float]]:
-    """Adam on random mini-batches of the resident pairs; returns the loss curve."""
-    import torch
+    """Adam on random mini-batches of the resident pairs (``ps.sample``);
+    returns the loss curve."""
     rng = np.random.default_rng(seed)
-    n = ps.lo.shape[0]
     curve = []
     t0 = time.time()
     run = []
     for it in range(steps):
-        idx = torch.from_numpy(rng.choice(n, size=batch, replace=False)).cuda()
-        loss = net.loss_grad(ps.lo.index_select(0, idx), ps.rho.index_select(0, idx),
-                             ps.hi.index_select(0, idx), ps.wt.index_select(0, idx))
+        loss = net.loss_grad(*ps.sample(rng, batch))
         net.adam_step(cosine_lr(it, steps, lr_max, lr_min, warmup))
         run.append(loss)
         if (it + 1) % log_every == 0 or it + 1 == steps:

@@ -9,7 +9,8 @@
   200 x 200 x 200 mm at 1 mm.
 * ``plan``: 1000 spots, 70-230 MeV, lognormal weights, 1e3-1e5 histories per
   spot, 256 x 256 x 200 voxels of 2 mm with a random density field;
-  ``plan_uniform``: the same spots with one history count for every spot.
+  ``plan_uniform``: the same spots with one history count for every spot;
+  ``plan_variant``: the family of such plans with other seeds.
 * ``denoiser_patch``: training patches of the denoiser, 64 x 64 x 128 voxels
   of 2 mm with a random density field and inclusions and 1-64 spots, all
   drawn like the plan's (index i seeds everything).
@@ -107,6 +108,20 @@ def plan_uniform(n_per_spot: int, n_spots: int = 1000, seed: int = 6,
     e = float(np.log10(n_per_spot))
     return Workload(f"plan_{n_per_spot}", grf_phantom(nx, ny, nz, 0.2),
                     plan_spots(n_spots, logn_lo=e, logn_hi=e), seed)
+
+
+def plan_variant(k: int, n_per_spot: int, n_spots: int = 1000,
+                 shape=(256, 256, 200)) -> Workload:
+    """Plan k of a family drawn like ``plan`` (k = 0 is ``plan_uniform``
+    itself): density field seed 100 + 1000k, inclusions 101 + 1000k, spots
+    102 + 1000k, transport seed 6 + 1000k; ``n_per_spot`` histories in every
+    spot."""
+    nx, ny, nz = shape
+    e = float(np.log10(n_per_spot))
+    return Workload(f"plan_variant{k}_{n_per_spot}",
+                    grf_phantom(nx, ny, nz, 0.2, seed_field=100 + 1000 * k,
+                                seed_incl=101 + 1000 * k),
+                    plan_spots(n_spots, logn_lo=e, logn_hi=e, seed=102 + 1000 * k), 6 + 1000 * k)
 
 
 def denoiser_patch(i: int, n_histories: int = 100_000, shape=(64, 64, 128)) -> Workload:
