@@ -135,6 +135,7 @@ def plan_leg(steps: int, stream) -> dict:
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2511_03115_amd", "weights", "denoiser_plan2mm.npz")
+BF16_PEAK = 2.5e15       # MI355X dense bf16 matrix-core peak, FLOP/s
 GAMMA_LADDER = [1000 * 2 ** k for k in range(9)]        # histories per spot
 GAMMA_REFERENCE = 2_000_000                              # histories per spot
 
@@ -145,6 +146,7 @@ def gamma_leg() -> dict:
     spots, 2 mm): plain SDE on a doubling ladder of histories per spot vs
     the denoised 1e3-per-spot run with the plain fallback."""
     from dataclasses import replace
+    import numpy as np
     import workloads
     from workloads import configs
     from paper_2511_03115_amd import denoiser, judge, sde
@@ -159,6 +161,19 @@ def gamma_leg() -> dict:
                               name="plan", log=log)
     dn.close()
     out = res.as_dict()
+    # the denoiser's forward pass against the dense bf16 matrix-core peak
+    m = 1 << (denoiser.LEVELS - 1)
+    padded = [-(-n // m) * m for n in wl.phantom.material_id.shape]
+    flops = denoiser.forward_flops(padded)
+    t_dn = [r.denoise_s for r in res.rungs if r.denoise_s]
+    if t_dn:
+        t = sum(t_dn) / len(t_dn)
+        out["denoiser_roofline"] = {
+            "bound": "mfma", "achieved": flops / t, "peak": BF16_PEAK, "unit": "FLOP/s",
+            "frac": flops / t / BF16_PEAK, "traffic": None,
+            "kernel": "denoiser forward (14 bf16 MFMA convs + layout kernels, whole pass)",
+            "ms": t * 1e3, "work_per_unit": "142560 FLOP per voxel",
+            "units_per_launch": int(np.prod(padded))}
     out["workload"] = ("plan: 1000 spots 70-230 MeV, lognormal weights, equal histories per "
                        "spot, 256x256x200 at 2 mm, random density + bone/lung ellipsoids")
     out["gamma"] = {"dd": judge.DD, "dta_cm": judge.DTA_CM, "threshold": judge.THRESH,

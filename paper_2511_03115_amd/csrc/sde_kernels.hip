@@ -142,11 +142,14 @@ __device__ __forceinline__ void acc_flush(const KParams& P, unsigned long long* 
 }
 
 // Score energy e at point (x,y,z): into the accumulator, or escaped.
+// check = false skips the inside test where the caller knows the point is
+// inside (a midpoint between two inside points of the box, with the
+// monotonic rounding of fmaf).
 __device__ __forceinline__ void score(const KParams& P, unsigned long long* tile,
                                       unsigned long long* rep, Acc& a, float x, float y, float z,
-                                      float e, float wsc, long long& esc) {
+                                      float e, float wsc, long long& esc, bool check = true) {
     const long long q = fixp(e, wsc);
-    if (!inside(P, x, y, z)) {
+    if (check && !inside(P, x, y, z)) {
         esc += q;
         return;
     }
@@ -169,35 +172,40 @@ __device__ __forceinline__ void score(const KParams& P, unsigned long long* tile
 // Hydrogen (Mott) antiderivative in units of (eta/k)^2, Appendix A.2 with
 // sin(eta ln((1+mu)/(1-mu))), and its derivative (the Mott cross section of
 // section 2.1.4 in the same units).
-__device__ __forceinline__ void mott_G_dG(float eta, float mu, float& G, float& dG) {
+__device__ __forceinline__ void mott_G_dG(float eta, float inv_2eta, float mu, float& G,
+                                          float& dG) {
     const float omm = (1.0f - mu) * (1.0f + mu);
-    const float L = logf((1.0f + mu) / (1.0f - mu));
+    const float iomm = frcp(omm);
+    const float L = logf((1.0f + mu) * frcp(1.0f - mu));
     const float r = eta * L * 0.15915494309189535f;   // revolutions, |r| < 1 for E >= e_min
     const float sn = sin_rev(r), cs = cos_rev(r);
-    G = 2.0f * mu / omm - sn / (2.0f * eta);
-    dG = 2.0f / omm * ((1.0f + mu * mu) / omm - 0.5f * cs);
+    G = 2.0f * mu * iomm - sn * inv_2eta;
+    dG = 2.0f * iomm * ((1.0f + mu * mu) * iomm - 0.5f * cs);
 }
 
 // Invert the hydrogen elastic CDF, (G(mu) - G(lo)) / (G(hi) - G(lo)) = U, by
 // Newton's method kept inside a shrinking bracket.  First guess: the
 // interference term dropped, 2 mu / (1 - mu^2) = target.
 __device__ __forceinline__ float mott_invert(const KParams& P, float eta, float U) {
+    const float inv_2eta = 0.5f * frcp(eta);
     float a = P.mott_lo, b = P.mott_hi, G0, G1, d;
-    mott_G_dG(eta, a, G0, d);
-    mott_G_dG(eta, b, G1, d);
+    mott_G_dG(eta, inv_2eta, a, G0, d);
+    mott_G_dG(eta, inv_2eta, b, G1, d);
     const float tgt = fmaf(U, G1 - G0, G0);
-    float mu = tgt / (1.0f + sqrtf(1.0f + tgt * tgt));
+    float mu = tgt * frcp(1.0f + sqrtf(1.0f + tgt * tgt));
     mu = fminf(fmaxf(mu, a), b);
     for (int it = 0; it < 24; ++it) {
         float G, dG;
-        mott_G_dG(eta, mu, G, dG);
+        mott_G_dG(eta, inv_2eta, mu, G, dG);
         const float g = G - tgt;
         if (g < 0.0f) a = mu; else b = mu;
-        float nx = mu - g / dG;
+        float nx = mu - g * frcp(dG);
         if (!(nx > a && nx < b)) nx = 0.5f * (a + b);
         const float step = fabsf(nx - mu);
         mu = nx;
-        if (step <= 1e-7f * fmaxf(1.0f - fabsf(mu), 1e-3f) || !(b > a)) break;
+        // converged to a few ulps of mu (FP32 Newton can cycle between
+        // neighbouring floats), or the bracket has closed
+        if (step <= 2.5e-7f * fmaxf(fabsf(mu), 1e-3f) || !(b > a)) break;
     }
     return mu;
 }
@@ -590,12 +598,15 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         }
 
         // Deposit E_n - E' at the step midpoint (pre-step direction), move.
+        // Both R_n and, when in_next, R_{n+1} lie in the box, and so does the
+        // midpoint: its inside test is needed only when R_{n+1} left.
+        const float nx = fmaf(ox, P.step, rx), ny = fmaf(oy, P.step, ry), nz = fmaf(oz, P.step, rz);
+        const bool in_next = inside(P, nx, ny, nz);
         score(P, tile, rep, acc, fmaf(ox, P.half_step, rx), fmaf(oy, P.half_step, ry),
-              fmaf(oz, P.half_step, rz), E - Ep, wsc, l_esc);
-        rx = fmaf(ox, P.step, rx);
-        ry = fmaf(oy, P.step, ry);
-        rz = fmaf(oz, P.step, rz);
-        const bool in_next = inside(P, rx, ry, rz);
+              fmaf(oz, P.half_step, rz), E - Ep, wsc, l_esc, !in_next);
+        rx = nx;
+        ry = ny;
+        rz = nz;
         uint2 pk_next = make_uint2(0u, 0u);
         int v_next = vcache;
         if (in_next) {   // prefetch the next voxel while the direction is updated

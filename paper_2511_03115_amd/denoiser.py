@@ -41,6 +41,20 @@ def param_layout(levels: int = LEVELS, c0: int = C0, cin: int = CIN) -> List[Tup
     return out
 
 
+def forward_flops(dims_zyx: Sequence[int], batch: int = 1, levels: int = LEVELS, c0: int = C0,
+                  cin: int = CIN) -> int:
+    """Algorithmic FLOPs of one forward pass: 2 * 27 * Ci * Co per output
+    voxel of every conv, at each level's resolution (D, H, W as the network
+    sees them, i.e. already padded to multiples of 2^(levels-1))."""
+    nv0 = batch * int(np.prod(dims_zyx))
+    total = 0
+    for name, shp in param_layout(levels, c0, cin):
+        if name.endswith(".w") and len(shp) == 3:
+            lvl = int(name[3])
+            total += 2 * 27 * shp[0] * shp[2] * (nv0 >> (3 * lvl))
+    return total
+
+
 def init_params(seed: int = 0, levels: int = LEVELS, c0: int = C0, cin: int = CIN,
                 alpha: float = ALPHA) -> np.ndarray:
     """He initialisation for LeakyReLU convs, zero biases and a zero head: the
