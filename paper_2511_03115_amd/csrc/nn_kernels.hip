@@ -158,6 +158,130 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same convolution for few input channels (Ci <= 48) and outputs (NT <=
+// 2 column tiles), where the input gathers dominate: a workgroup computes a
+// 4 x 8 x 8 brick of output voxels and first stages the 6 x 10 x 10 input
+// brick with its one-voxel halo in LDS ([voxel][Ci + 8]; the 16-byte pad
+// puts the 16 voxels a quarter-wave reads on distinct banks), so each input
+// voxel is read from memory about 2.3 times instead of 27.  Wave w owns
+// z-slice w of the brick as 4 row tiles of 16 voxels (two 8-voxel rows
+// each).  Weights are staged in slabs as in k_conv_fwd_lds.
+// ---------------------------------------------------------------------------
+constexpr int kHZ = 4, kHY = 8, kHX = 8;
+constexpr int kHVox = (kHZ + 2) * (kHY + 2) * (kHX + 2);
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, Geo g,
+                                                       int Ci, int Co, float alpha, int act,
+                                                       uint16_t* __restrict__ y16,
+                                                       float* __restrict__ y32, int accumulate) {
+    constexpr int MT = 4;
+    extern __shared__ __align__(16) uint16_t sm[];
+    const int row = Ci + 8;
+    uint16_t* hx = sm;                           // [kHVox][row]
+    uint16_t* wl = sm + kHVox * row;             // [NT*16][kSlabRow]
+    const int K = 27 * Ci;
+    const int nbx = (g.W + kHX - 1) / kHX, nby = (g.H + kHY - 1) / kHY, nbz = (g.D + kHZ - 1) / kHZ;
+    int bid = blockIdx.x;
+    const int bx = bid % nbx;
+    bid /= nbx;
+    const int by = bid % nby;
+    bid /= nby;
+    const int bz = bid % nbz;
+    const int b = bid / nbz;
+    const int x0 = bx * kHX, y0 = by * kHY, z0 = bz * kHZ;
+    const int gv = Ci / 8;
+    for (int i = threadIdx.x; i < kHVox * gv; i += blockDim.x) {
+        const int hv = i / gv, c = (i - hv * gv) * 8;
+        const int hxx = hv % (kHX + 2), hyy = (hv / (kHX + 2)) % (kHY + 2),
+                  hzz = hv / ((kHX + 2) * (kHY + 2));
+        const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D) {
+            const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+            val = *reinterpret_cast<const uint4*>(x + v * Ci + c);
+        }
+        *reinterpret_cast<uint4*>(hx + hv * row + c) = val;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int hb[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int ly = 2 * m + ((lane & 15) >> 3), lx = lane & 7;
+        hb[m] = ((wave + 1) * (kHY + 2) + (ly + 1)) * (kHX + 2) + (lx + 1);
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int t = ((lane >> 4) * 8) / Ci;
+    int ci = ((lane >> 4) * 8) - t * Ci;
+    const int rows = NT * 16;
+    for (int k0 = 0; k0 < K; k0 += kSlab) {
+        __syncthreads();   // (first pass: also orders the halo stores)
+        for (int i = threadIdx.x; i < rows * (kSlab / 8); i += blockDim.x) {
+            const int r = i / (kSlab / 8), c = (i - r * (kSlab / 8)) * 8;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (r < Co && k0 + c < K)
+                val = *reinterpret_cast<const uint4*>(w + (size_t)r * K + k0 + c);
+            *reinterpret_cast<uint4*>(wl + r * kSlabRow + c) = val;
+        }
+        __syncthreads();
+        for (int kc = 0; kc < kSlab && k0 + kc < K; kc += 32) {
+            const int kk = kc + (lane >> 4) * 8;
+            const bool kin = k0 + kk < K;
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            const int off = (dz * (kHY + 2) + dy) * (kHX + 2) + dx;
+            bf16x8 a[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                uint4 av = make_uint4(0, 0, 0, 0);
+                if (kin) av = *reinterpret_cast<const uint4*>(hx + (hb[m] + off) * row + ci);
+                a[m] = as_bf16x8(av);
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const uint4 bv =
+                    *reinterpret_cast<const uint4*>(wl + (j * 16 + (lane & 15)) * kSlabRow + kk);
+                const bf16x8 bb = as_bf16x8(bv);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb, acc[m][j], 0, 0, 0);
+            }
+            ci += 32;
+            while (ci >= Ci) {
+                ci -= Ci;
+                ++t;
+            }
+        }
+    }
+    const int zz = z0 + wave;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = j * 16 + (lane & 15);
+        if (co >= Co) continue;
+        const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = (lane >> 4) * 4 + i;           // row of the 16-voxel tile
+                const int yy = y0 + 2 * m + (r >> 3), xx = x0 + (r & 7);
+                if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
+                const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                float rr = acc[m][j][i] + bb;
+                if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                if (y16) y16[v * Co + co] = f2bf(rr);
+                if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
+            }
+        }
+    }
+}
+
 // wt[ci][26 - t][co] = w[co][t][ci]: the weights of the input-gradient conv.
 __global__ void k_flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co) {
     const int n = Co * 27 * Ci;
@@ -671,6 +795,29 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     const long long nv = g.nvox();
     const int nt = (Co + 15) / 16;
+    // the halo kernel may use more than the default 64 KB of dynamic LDS
+    static const hipError_t attr = [] {
+        hipError_t e = hipFuncSetAttribute((const void*)k_conv_fwd_halo<1>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_conv_fwd_halo<2>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+        return e;
+    }();
+    if (attr != hipSuccess) return attr;
+    if (nt <= 2 && Ci <= 48) {   // few channels: input brick with halo in LDS
+        const size_t lds_h =
+            ((size_t)kHVox * (Ci + 8) + (size_t)nt * 16 * kSlabRow) * sizeof(uint16_t);
+        const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
+                              ((g.D + kHZ - 1) / kHZ) * g.B;
+        if (nt == 1)
+            hipLaunchKernelGGL(k_conv_fwd_halo<1>, dim3((unsigned)nbk), dim3(256), lds_h, s, x, w,
+                               bias, g, Ci, Co, alpha, act, y16, y32, accumulate);
+        else
+            hipLaunchKernelGGL(k_conv_fwd_halo<2>, dim3((unsigned)nbk), dim3(256), lds_h, s, x, w,
+                               bias, g, Ci, Co, alpha, act, y16, y32, accumulate);
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)nt * 16 * kSlabRow * sizeof(uint16_t);
 #define LAUNCH(NT, MT)                                                                        \
     hipLaunchKernelGGL((k_conv_fwd_lds<NT, MT>), dim3((unsigned)((nv + 64 * MT - 1) / (64 * MT))), \

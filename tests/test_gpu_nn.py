@@ -54,7 +54,8 @@ def he_params(levels, c0, cin, seed, head_scale=0.1):
 @pytest.mark.parametrize("shape,ci,co", [((2, 6, 5, 7), 16, 16), ((1, 5, 9, 4), 48, 32),
                                          ((2, 4, 4, 6), 32, 64), ((1, 3, 4, 5), 64, 128),
                                          ((1, 4, 3, 5), 16, 48), ((1, 3, 3, 3), 128, 192),
-                                         ((1, 1, 1, 1), 16, 16)])
+                                         ((1, 1, 1, 1), 16, 16), ((2, 9, 17, 11), 16, 16),
+                                         ((1, 10, 8, 19), 32, 32), ((1, 5, 12, 9), 48, 16)])
 def test_conv3d_fwd(shape, ci, co):
     import torch
     from paper_2511_03115_amd import nn
