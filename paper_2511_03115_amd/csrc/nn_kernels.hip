@@ -428,13 +428,32 @@ __global__ void __launch_bounds__(256) k_wgrad_partial(const uint16_t* __restric
 }
 
 // dW[co][t][ci] = sum_c part[c][t][co][ci] (fixed order: deterministic).
-__global__ void k_wgrad_reduce(const float* part, int nchunk, int Ci, int Co, float* dw) {
-    const int n = 27 * Co * Ci;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int ci = i % Ci, co = (i / Ci) % Co, t = i / (Ci * Co);
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
-        dw[((size_t)co * 27 + t) * Ci + ci] = s;
+// Deterministic column sums out[c] = sum_r part[r * ncol + c]: a workgroup
+// of 64 x 16 threads owns 64 consecutive columns; row-group g sums rows
+// g, g + 16, ... (coalesced across the 64 columns) and the 16 partial sums
+// are added in a fixed order.  With ci_co > 0 the columns are the weight
+// gradient (t, co, ci) and are written to dW[co][t][ci] (ci_co = Ci * 65536 + Co).
+__global__ void __launch_bounds__(1024) k_colsum(const float* part, int nrow, int ncol,
+                                                 float* out, int ci_co) {
+    __shared__ float red[16][64];
+    const int o = threadIdx.x & 63, gr = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + o;
+    float s = 0.0f;
+    if (c < ncol)
+        for (int r = gr; r < nrow; r += 16) s += part[(size_t)r * ncol + c];
+    red[gr][o] = s;
+    __syncthreads();
+    if (gr == 0 && c < ncol) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][o];
+        if (ci_co > 0) {
+            const int Ci = ci_co >> 16, Co = ci_co & 0xFFFF;
+            const int ci = c % Ci, co = (c / Ci) % Co, tap = c / (Ci * Co);
+            out[((size_t)co * 27 + tap) * Ci + ci] = t;
+        } else {
+            out[c] = t;
+        }
     }
 }
 
@@ -722,13 +741,6 @@ __global__ void __launch_bounds__(256) k_head_bwd(const float* dout, const uint1
 }
 
 // out[c] = sum_r part[r * ncol + c] (fixed order: deterministic)
-__global__ void k_sum_rows(const float* part, int nrow, int ncol, float* out) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int r = 0; r < nrow; ++r) s += part[(size_t)r * ncol + c];
-        out[c] = s;
-    }
-}
 
 __global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -881,11 +893,13 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                        dz, x, g, Ci, Co, chunk, tg, part, part_b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(27LL * Co * Ci)), dim3(256), 0, s, part,
-                       (int)nchunk, Ci, Co, dw);
+    const int n = 27 * Co * Ci;
+    hipLaunchKernelGGL(k_colsum, dim3((n + 63) / 64), dim3(1024), 0, s, part, (int)nchunk, n, dw,
+                       (Ci << 16) | Co);
     e = hipGetLastError();
     if (e != hipSuccess || !db) return e;
-    hipLaunchKernelGGL(k_sum_rows, dim3(blocks_for(Co)), dim3(256), 0, s, part_b, (int)nchunk, Co, db);
+    hipLaunchKernelGGL(k_colsum, dim3((Co + 63) / 64), dim3(1024), 0, s, part_b, (int)nchunk, Co, db,
+                       0);
     return hipGetLastError();
 }
 
@@ -1004,7 +1018,7 @@ hipError_t head_bwd(const float* dout, const uint16_t* x, const float* w, long l
 }
 
 hipError_t sum_rows(const float* part, int nrow, int ncol, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_rows, dim3(blocks_for(ncol)), dim3(256), 0, s, part, nrow, ncol, out);
+    hipLaunchKernelGGL(k_colsum, dim3((ncol + 63) / 64), dim3(1024), 0, s, part, nrow, ncol, out, 0);
     return hipGetLastError();
 }
 
