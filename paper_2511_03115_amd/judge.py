@@ -88,12 +88,49 @@ class TimeToGamma:
         return d
 
 
+def decide(res: TimeToGamma) -> TimeToGamma:
+    """Fill the plain, denoised-ladder and first-rung results of ``res`` from
+    its rungs (each with its run time, plain gamma and, where denoised, the
+    inference time and denoised gamma), by the rules in the module text."""
+    res.plain_n_per_spot = res.plain_s = res.plain_cumulative_s = None
+    res.denoised_n_per_spot = res.denoised_s = res.denoised_cumulative_s = None
+    res.first_rung_denoised_s = res.first_rung_passed = res.fallback = None
+    cum_plain = cum_den = 0.0
+    any_denoised = any(r.gamma_denoised is not None for r in res.rungs)
+    for k, r in enumerate(res.rungs):
+        cum_plain += r.run_s
+        if r.gamma_denoised is not None and res.denoised_s is None:
+            cum_den += r.run_s + r.denoise_s
+            if r.gamma_denoised >= TARGET:
+                res.denoised_n_per_spot = r.n_per_spot
+                res.denoised_s = r.run_s + r.denoise_s
+                res.denoised_cumulative_s = cum_den
+            if k == 0:
+                res.first_rung_passed = r.gamma_denoised >= TARGET
+                res.first_rung_denoised_s = r.run_s + r.denoise_s
+        if r.gamma_plain >= TARGET and res.plain_s is None:
+            res.plain_n_per_spot, res.plain_s = r.n_per_spot, r.run_s
+            res.plain_cumulative_s = cum_plain
+    if any_denoised:
+        if res.first_rung_passed is False and res.first_rung_denoised_s is not None:
+            res.first_rung_denoised_s = (res.first_rung_denoised_s + res.plain_s
+                                         if res.plain_s is not None else None)
+        res.fallback = res.denoised_s is None
+        if res.fallback and res.plain_s is not None:
+            res.denoised_n_per_spot = res.plain_n_per_spot
+            res.denoised_s = res.plain_s
+            res.denoised_cumulative_s = cum_den + res.plain_s
+    return res
+
+
 def time_to_gamma(spots_for: Callable[[int], list], phantom, seed: int, ladder: Sequence[int],
                   n_reference: int, denoise=None, name: str = "", launch=None,
                   log=print) -> TimeToGamma:
     """``spots_for(n)``: the plan's spots with n histories per spot;
     ``phantom``: a sde.DevicePhantom (materials already initialised);
-    ``denoise(dose, rho, out)``: the trained network (or None)."""
+    ``denoise(dose, rho, out)``: the trained network (or None).  Walks the
+    ladder until the plain map passes, denoising every rung until a
+    denoised map passes, then applies ``decide``."""
     import torch
     shape = tuple(phantom.material_id.shape)
     vcm = tuple(phantom.voxel_cm)
@@ -106,7 +143,7 @@ def time_to_gamma(spots_for: Callable[[int], list], phantom, seed: int, ladder: 
     res = TimeToGamma(name, n_ref_total, t_ref)
     dose = torch.zeros(shape, dtype=torch.float64, device="cuda")
     den = torch.zeros_like(dose)
-    cum_plain = cum_den = 0.0
+    denoised_passed = False
     for k, n in enumerate(ladder):
         t0 = time.perf_counter()
         plan = sde.Plan(spots_for(n), phantom, seed + k, launch=launch)
@@ -115,34 +152,15 @@ def time_to_gamma(spots_for: Callable[[int], list], phantom, seed: int, ladder: 
         t_run = _timed(lambda: plan.execute(dose))
         rung = Rung(n, plan.n_histories, t_setup, t_run, gamma_pass(ref, dose, vcm))
         plan.close()
-        cum_plain += t_run
-        if denoise is not None and res.denoised_s is None:
+        if denoise is not None and not denoised_passed:
             rung.denoise_s = _timed(lambda: denoise(dose, phantom.density, den))
             rung.gamma_denoised = gamma_pass(ref, den, vcm)
-            cum_den += t_run + rung.denoise_s
-            if rung.gamma_denoised >= TARGET:
-                res.denoised_n_per_spot = n
-                res.denoised_s = t_run + rung.denoise_s
-                res.denoised_cumulative_s = cum_den
-            if k == 0:
-                res.first_rung_passed = rung.gamma_denoised >= TARGET
-                res.first_rung_denoised_s = t_run + rung.denoise_s
+            denoised_passed = rung.gamma_denoised >= TARGET
         res.rungs.append(rung)
         log(f"[judge] {name} {n}/spot: {rung.histories} histories {t_run * 1e3:.1f} ms, "
             f"gamma plain {rung.gamma_plain:.4f}"
             + (f", denoised {rung.gamma_denoised:.4f} (+{rung.denoise_s * 1e3:.1f} ms)"
                if rung.gamma_denoised is not None else ""))
         if rung.gamma_plain >= TARGET:
-            res.plain_n_per_spot, res.plain_s = n, t_run
-            res.plain_cumulative_s = cum_plain
             break
-    if denoise is not None:
-        if res.first_rung_passed is False and res.first_rung_denoised_s is not None:
-            res.first_rung_denoised_s = (res.first_rung_denoised_s + res.plain_s
-                                         if res.plain_s is not None else None)
-        res.fallback = res.denoised_s is None
-        if res.fallback and res.plain_s is not None:
-            res.denoised_n_per_spot = res.plain_n_per_spot
-            res.denoised_s = res.plain_s
-            res.denoised_cumulative_s = cum_den + res.plain_s
-    return res
+    return decide(res)
