@@ -21,7 +21,7 @@ namespace sde {
 namespace {
 
 constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelastic = 16u,
-                   kEor = 32u;
+                   kEor = 32u, kAllPhysics = 63u;
 
 constexpr float kMpF = (float)kMp;
 constexpr float kAlphaF = (float)kAlpha;
@@ -31,6 +31,11 @@ constexpr float kLn2 = 0.69314718055994530942f;
 // 32x32->64 products, key bumped by the Weyl constants between rounds.
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
+    // An empty barrier on the (wave-uniform) key: without it the compiler
+    // hoists all twenty round keys out of the caller's loop, where they
+    // occupy scalar registers for the whole kernel and are spilled; with it
+    // they are rebuilt here by scalar adds.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
@@ -240,13 +245,13 @@ __device__ __forceinline__ float channel_rate(const KParams& P, const ElemDev& d
 // Eq. (cm_to_lab).  Outputs the loss fraction u (0 for elastic), the lab
 // polar (cos, sin) and the azimuth (cos, sin).
 __device__ void jump(const KParams& P, const MatDev* md, float E, float rho, uint4 q,
-                     float& u_loss, float& jc, float& js, float& jcp, float& jsp) {
+                     float& u_loss, float& jc, float& js, float& jcp, float& jsp, unsigned flags) {
     const float tl = (flog(E) - P.ln_e_lo) * P.inv_dln;
     const int li = max(0, min((int)tl, P.n_e - 2));
     const float lf = tl - (float)li;
     const float inv_e2 = 1.0f / (E * E);
     const float eta = P.eta_pre * __builtin_amdgcn_rsqf(E);
-    const bool el = (P.flags & kElastic) != 0, ne = (P.flags & kInelastic) != 0;
+    const bool el = (flags & kElastic) != 0, ne = (flags & kInelastic) != 0;
     const int nel = md->n_elem;
     float mott = 0.0f;
     if (el && md->c_mott != 0.0f) {
@@ -374,7 +379,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 
 enum : int { kDead = 0, kStep = 1, kJump = 2 };
 
+// kFixed != 0: the physics switches are that compile-time constant (the
+// full method), so their tests fold away; 0: read them from P.flags.
+template <unsigned kFixed>
 __global__ void __launch_bounds__(1024) k_transport(KParams P) {
+    const unsigned flags = kFixed ? kFixed : P.flags;
     extern __shared__ __align__(16) unsigned char smem[];
     float4* tab = reinterpret_cast<float4*>(smem);
     const int ntab = P.n_mat * P.n_e;
@@ -499,7 +508,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
             if (state == kJump) {
                 const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), nj, 1u, k0, k1);
                 float u_loss, jc, js, jcp, jsp;
-                jump(P, P.mats + matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp);
+                jump(P, P.mats + matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp, flags);
                 // E holds E' (after continuous loss); the jump removes u E'
                 const float En = E * (1.0f - u_loss);
                 l_nuc += fixp(E, wsc) - fixp(En, wsc);
@@ -539,7 +548,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // End of range: residual range within one step, decided in FP64; the
         // FP32 screen E <= ec(material) is exact-safe (ec bounds the energy
         // whose range fits a step at the densest voxel of that material).
-        if ((P.flags & kEor) && E <= mc.z) {
+        if ((flags & kEor) && E <= mc.z) {
             const double rres = range_g64(P, mat, E) / (double)rho;
             if (rres <= P.step_d) {
                 const float hr = (float)(0.5 * rres);
@@ -567,13 +576,13 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         const float g = E + kMpF;
         const float b2 = p2 * frcp(g * g);
         float s1 = 0.0f;
-        if (P.flags & kLoss) {
+        if (flags & kLoss) {
             const float L = mc.y + flog(p2) - b2;
             s1 = rho * P.c_bethe * mc.x * L * frcp(b2);
         }
         const float a = s1 * P.step;
         float X = 0.0f;
-        if (P.flags & kStraggle) {
+        if (flags & kStraggle) {
             const float gm = g * (1.0f / kMpF);
             const float var = rho * P.c_strag * mc.x * gm * gm * (1.0f - 0.5f * b2);
             const float zE = fsqrt(-2.0f * flog(u_hi(w.x))) * cos_rev(u_hi(w.y));
@@ -585,11 +594,11 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // (Rutherford + Mott) = el_E2 / E^2 with el_E2 smooth in ln E;
         // inelastic rate linear on the lattice.
         bool jumped = false;
-        if (P.flags & (kElastic | kInelastic)) {
+        if (flags & (kElastic | kInelastic)) {
             const float el_e2 = fmaf(lf, tb.w - ta.w, ta.w);
             const float ne_rate = fmaf(lf, tb.z - ta.z, ta.z);
-            const float rate = ((P.flags & kElastic) ? el_e2 * frcp(E * E) : 0.0f) +
-                               ((P.flags & kInelastic) ? ne_rate : 0.0f);
+            const float rate = ((flags & kElastic) ? el_e2 * frcp(E * E) : 0.0f) +
+                               ((flags & kInelastic) ? ne_rate : 0.0f);
             const float lam = P.step * rho * rate;
             const float pj = lam < 0.05f
                 ? lam * fmaf(-0.5f * lam, fmaf(-lam * (1.0f / 3.0f), fmaf(-0.25f, lam, 1.0f), 1.0f), 1.0f)
@@ -619,7 +628,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
 
         // Small-angle diffusion: geodesic Gaussian step of per-axis variance
         // sigma^2 Delta / z, sigma the Lynch-Dahl width.
-        if (P.flags & kMcs) {
+        if (flags & kMcs) {
             const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
             const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
             const float nu = rho * A2;
@@ -863,13 +872,19 @@ hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long lo
 }
 
 hipError_t transport_kernel_attributes(size_t lds_bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<kAllPhysics>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<0u>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
 hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_transport, dim3(grid), dim3(block), lds_bytes, s, p);
+    if (p.flags == kAllPhysics)
+        hipLaunchKernelGGL(k_transport<kAllPhysics>, dim3(grid), dim3(block), lds_bytes, s, p);
+    else
+        hipLaunchKernelGGL(k_transport<0u>, dim3(grid), dim3(block), lds_bytes, s, p);
     return hipGetLastError();
 }
 
