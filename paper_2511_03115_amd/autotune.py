@@ -73,7 +73,7 @@ def tile_candidates(spots, phantom, budget_bytes: int) -> List[dict]:
 
 def candidates(spots, phantom) -> List[dict]:
     n_cu, max_lds, table = sde.launch_limits()
-    cands = [{"block": 512, "grid": 2 * n_cu, "refill": r} for r in (1, 8)]
+    cands = [{"block": 512, "grid": 2 * n_cu, "refill": r} for r in (1, 4, 8)]
     spread = max(s.sigma_xy_cm for s in spots)
     xs = [s.x_cm for s in spots]
     ys = [s.y_cm for s in spots]

@@ -286,3 +286,28 @@ def test_prepare_pair_definition():
     w_ref = np.where(h >= thr, 1.0 / (h + eps) ** 2, (h / thr) / (thr + eps) ** 2)
     np.testing.assert_allclose(wt.cpu().numpy(), w_ref, rtol=2e-6)
     net.close()
+
+
+def test_nn_errors_are_reported():
+    """Bad sizes and calls out of order come back as error codes, before any kernel runs."""
+    import torch
+    from paper_2511_03115_amd import nn, sde
+    net = nn.Net(2, 16, 16, 0.01, 1, (8, 8, 8), train=False)
+    f = lambda *s: torch.zeros(s, dtype=torch.float32, device="cuda")
+    with pytest.raises(sde.SdeError) as e:
+        net.forward(f(1, 8, 8, 7), None, f(1, 8, 8, 7))        # W not a multiple of 2
+    assert e.value.code == sde.E_INVALID
+    with pytest.raises(sde.SdeError) as e:
+        net.forward(f(1, 16, 8, 8), None, f(1, 16, 8, 8))      # exceeds the buffers
+    assert e.value.code == sde.E_INVALID
+    with pytest.raises(sde.SdeError) as e:
+        net.loss_grad(f(1, 8, 8, 8), None, f(1, 8, 8, 8))      # inference-only network
+    assert e.value.code == sde.E_INVALID
+    with pytest.raises(sde.SdeError):
+        net.set_params(np.zeros(net.n_params + 1, np.float32))  # wrong count
+    net.close()
+    tr = nn.Net(2, 16, 16, 0.01, 1, (8, 8, 8), train=True)
+    with pytest.raises(sde.SdeError) as e:
+        tr.adam_step(1e-3)                                     # no gradient yet
+    assert e.value.code == sde.E_INVALID
+    tr.close()
