@@ -141,7 +141,7 @@ typedef struct {
 typedef struct {
     int block;        /* threads per workgroup, multiple of 64, <= 1024 (512) */
     int grid;         /* workgroups (0: 2 per compute unit) */
-    int refill;       /* refill when at least this many lanes of a wave are idle, 1..64 (1) */
+    int refill;       /* refill when at least this many lanes of a wave are idle, 1..64 (8) */
     int jump_batch;   /* finish deferred jumps when this many lanes of a wave wait, 1..64 (8) */
     int tally_replicas; /* global tally copies, chosen per XCD and summed at the end, 1..16 (8) */
     int claim_chunk;  /* history indices a wave takes from the work counter at once, >= 64 (64) */

@@ -267,7 +267,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     }
     int grid = L.grid ? L.grid : 2 * std::max(1, g.n_cu);
     if (grid < 1) grid = 1;
-    int refill = L.refill ? L.refill : 1;
+    int refill = L.refill ? L.refill : 8;
     if (refill < 1 || refill > 64) {
         plan_free(p);
         return fail(SDE_E_INVALID, "refill must be in 1..64");

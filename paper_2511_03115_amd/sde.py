@@ -78,6 +78,11 @@ class Launch(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes libsde bind to that one, so the process has a single HIP
+    # runtime (loading libsde first would bring a second one, and torch's
+    # would then find no device)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, V = C.POINTER, C.c_void_p
     L.sde_init_materials.argtypes = [P(MaterialDesc), C.c_int, P(PhysicsParams), P(NuclearTables)]

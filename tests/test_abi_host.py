@@ -18,6 +18,7 @@ def lib():
     if not os.path.exists(LIB):
         from paper_2511_03115_amd import build
         build.build()
+    import torch  # noqa: F401  (one HIP runtime per process: torch's, loaded first)
     return C.CDLL(LIB)
 
 
