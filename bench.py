@@ -52,6 +52,8 @@ def parse():
                     help="'auto' (autotuner), 'default', or a JSON launch configuration")
     ap.add_argument("--no-gamma", action="store_true",
                     help="skip the time-to-gamma leg (plain SDE vs denoised, plan at 2 mm)")
+    ap.add_argument("--no-hetero", action="store_true",
+                    help="skip the heterogeneous-phantom leg (slab and insert, 100/150 MeV)")
     return ap.parse_args()
 
 
@@ -184,6 +186,39 @@ def gamma_leg() -> dict:
     return out
 
 
+def hetero_leg(steps: int) -> list:
+    """Throughput on the heterogeneous phantoms: water/bone/lung slabs and the
+    lateral bone insert, 200 mm cubes at 1 mm, 1e7 histories at 100 and
+    150 MeV (the same beam model as the water workload)."""
+    import numpy as np
+    import workloads
+    from workloads import configs
+    from paper_2511_03115_amd import autotune, sde
+    out = []
+    for kind in ("slab", "insert"):
+        for E in (100.0, 150.0):
+            wl = configs.slab(E) if kind == "slab" else configs.insert(E)
+            sde.init_materials(wl.phantom.materials, wl.params,
+                               workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
+            dph = sde.DevicePhantom.from_host(wl.phantom)
+            launch = autotune.tune(wl.spots, dph, wl.seed)
+            plan = sde.Plan(wl.spots, dph, wl.seed, launch=launch)
+            plan.execute(None)
+            ms = []
+            for _ in range(max(1, steps)):
+                plan.execute(None)
+                ms.append(plan.kernel_ms())
+            led, _ = plan.results()
+            plan.close()
+            k = float(np.mean(ms))
+            print(f"[bench] {wl.name}: {k:.2f} ms per launch", flush=True)
+            out.append({"workload": f"{kind} {E:.0f} MeV, 1e7 histories, 200 mm cube at 1 mm",
+                        "kernel_ms": k, "histories_per_s": wl.n_histories / (k * 1e-3),
+                        "steps_per_launch": int(led[sde.LEDGER_STEPS]),
+                        "jumps_per_launch": int(led[sde.LEDGER_JUMPS]), "launch": launch})
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -256,6 +291,8 @@ def main():
     plan.close()
     if not a.no_plan:
         out["plan"] = plan_leg(a.steps, stream)
+    if not a.no_hetero:
+        out["heterogeneous"] = hetero_leg(min(a.steps, 3))
     if not a.no_gamma:
         print("[bench] time to gamma >= 95% (plain vs denoised)", flush=True)
         sde.set_stream(None)
