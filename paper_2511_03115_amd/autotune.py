@@ -31,13 +31,28 @@ def device_arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
+def _fingerprint(phantom) -> list:
+    """Content of a phantom in a few numbers: the density sum (0.1 g/cm^3
+    voxels resolution) and the voxel count of each material id 0..7."""
+    d, m = phantom.density, phantom.material_id
+    if hasattr(d, "is_cuda"):          # device phantom (torch tensors)
+        import torch
+        total = float(d.double().sum().item())
+        counts = torch.bincount(m.flatten().long(), minlength=8)[:8].tolist()
+    else:
+        import numpy as np
+        total = float(np.asarray(d, dtype=np.float64).sum())
+        counts = np.bincount(np.asarray(m).ravel().astype(np.int64), minlength=8)[:8].tolist()
+    return [round(total, 1), [int(c) for c in counts]]
+
+
 def _key(spots, phantom, arch: Optional[str] = None) -> str:
     name = arch or device_arch()
     E = max(s.E_MeV for s in spots)
     cx = sum(s.x_cm * s.weight for s in spots) / max(sum(s.weight for s in spots), 1e-30)
     cy = sum(s.y_cm * s.weight for s in spots) / max(sum(s.weight for s in spots), 1e-30)
     return json.dumps([name, list(phantom.shape), [round(v, 4) for v in phantom.voxel_cm],
-                       len(spots), round(E, 1), round(cx, 2), round(cy, 2)])
+                       len(spots), round(E, 1), round(cx, 2), round(cy, 2), _fingerprint(phantom)])
 
 
 def _water_range_cm(E: float) -> float:
