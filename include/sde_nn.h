@@ -106,7 +106,8 @@ int sde_nn_prepare_pair(sde_nn* net, const double* low, const double* high, int6
 /* Single layers, for tests of the kernels.  x, w, y16, dz: (device) bf16
  * bit patterns (uint16); bias, y32, dx, dw, db: (device) FP32.
  * Volumes [B][D][H][W][C]; weights [Co][27][Ci].  Ci % 16 == 0 and
- * Co / 16 in {1, 2, 3, 4, 6, 8, 12}. */
+ * Co / 16 in {1, 2, 3, 4, 6, 8, 12}.  bf16 arrays and workspaces must be
+ * 16-byte aligned (SDE_E_INVALID otherwise). */
 /* y = act(conv3(x, w) + bias) into y16 and/or y32 (either nullable); act 0/1. */
 int sde_nn_conv3d_fwd(const uint16_t* x, const uint16_t* w, const float* bias, int B, int D,
                       int H, int W, int Ci, int Co, float alpha, int act, uint16_t* y16,

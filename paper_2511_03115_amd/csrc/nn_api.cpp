@@ -31,6 +31,8 @@ namespace {
 // largest wgrad split-K partial buffer (floats)
 constexpr long long kMaxPartFloats = 32LL << 20;
 
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 bool nt_ok(int co) {
     if (co % 16) return false;
     const int nt = co / 16;
@@ -134,9 +136,17 @@ int run_forward(sde_nn* n, const int* d0) {
         (void)dc;
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
-        NN_TRY(copy_channels(v.eb, d, n->c[l], Cf, 0, v.cat, s));
-        NN_TRY(up_fwd(top, d, n->c[l + 1], Cf, n->c[l], v.cat, s));
-        if (int r = conv_act(n, v.cat, n->dec_a[l], d, v.da)) return r;
+        const ConvP& cp = n->dec_a[l];
+        if (!n->cfg.train && conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co)) {
+            // inference: the concatenation is read in place (training keeps it
+            // for the weight gradient)
+            NN_TRY(conv_cat_fwd(v.eb, top, n->P16 + cp.w, n->P + cp.b, d, n->c[l], n->c[l + 1],
+                                cp.co, n->cfg.leaky_alpha, 1, v.da, s));
+        } else {
+            NN_TRY(copy_channels(v.eb, d, n->c[l], Cf, 0, v.cat, s));
+            NN_TRY(up_fwd(top, d, n->c[l + 1], Cf, n->c[l], v.cat, s));
+            if (int r = conv_act(n, v.cat, cp, d, v.da)) return r;
+        }
         if (int r = conv_act(n, v.da, n->dec_b[l], d, v.db)) return r;
         top = v.db;
     }
@@ -215,7 +225,8 @@ int alloc_all(sde_nn* n) {
         NN_TRY(dalloc(n, &v.eb, nv * n->c[l]));
         if (l > 0) NN_TRY(dalloc(n, &v.pin, nv * n->c[l - 1]));
         if (l <= L - 2) {
-            NN_TRY(dalloc(n, &v.cat, nv * (n->c[l] + n->c[l + 1])));
+            if (c.train || !conv_cat_fwd_supported(n->c[l], n->c[l + 1], n->c[l]))
+                NN_TRY(dalloc(n, &v.cat, nv * (n->c[l] + n->c[l + 1])));
             NN_TRY(dalloc(n, &v.da, nv * n->c[l]));
             NN_TRY(dalloc(n, &v.db, nv * n->c[l]));
         }
@@ -466,6 +477,7 @@ int sde_nn_conv3d_fwd(const uint16_t* x, const uint16_t* w, const float* bias, i
                       int H, int W, int Ci, int Co, float alpha, int act, uint16_t* y16,
                       float* y32) {
     NN_CHECK(x && w && (y16 || y32), "null argument");
+    NN_CHECK(aligned16(x) && aligned16(w) && aligned16(y16), "bf16 arrays must be 16-byte aligned");
     NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
     NN_CHECK(Ci >= 16 && Ci % 16 == 0 && nt_ok(Co), "unsupported channel counts");
     const int d[4] = {B, D, H, W};
@@ -488,6 +500,8 @@ int sde_nn_conv3d_workspace(int B, int D, int H, int W, int Ci, int Co, size_t* 
 int sde_nn_conv3d_dgrad(const uint16_t* dz, const uint16_t* w, int B, int D, int H, int W, int Ci,
                         int Co, float* dx, void* workspace, size_t workspace_bytes) {
     NN_CHECK(dz && w && dx && workspace, "null argument");
+    NN_CHECK(aligned16(dz) && aligned16(w) && aligned16(workspace),
+             "bf16 arrays and the workspace must be 16-byte aligned");
     NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
     NN_CHECK(Co >= 16 && Co % 16 == 0 && nt_ok(Ci), "unsupported channel counts");
     NN_CHECK(workspace_bytes >= 27ULL * Ci * Co * sizeof(uint16_t), "workspace too small");
@@ -502,6 +516,8 @@ int sde_nn_conv3d_dgrad(const uint16_t* dz, const uint16_t* w, int B, int D, int
 int sde_nn_conv3d_wgrad(const uint16_t* dz, const uint16_t* x, int B, int D, int H, int W, int Ci,
                         int Co, float* dw, float* db, void* workspace, size_t workspace_bytes) {
     NN_CHECK(dz && x && dw && workspace, "null argument");
+    NN_CHECK(aligned16(dz) && aligned16(x) && aligned16(workspace),
+             "bf16 arrays and the workspace must be 16-byte aligned");
     NN_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1, "volume sizes must be positive");
     NN_CHECK(Ci >= 16 && Ci % 16 == 0 && Co >= 16 && Co % 16 == 0 &&
                  (Co / 16) * (Ci / 16) <= 64,

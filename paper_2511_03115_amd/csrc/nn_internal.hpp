@@ -15,6 +15,13 @@ namespace nn {
 hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
                     int Ci, int Co, float alpha, int act, uint16_t* y16, float* y32,
                     int accumulate, hipStream_t s);
+// conv_fwd (bf16 output) of the decoder input concat[skip (Cs channels),
+// nearest-up(low) (Cu channels, half size)] without storing the
+// concatenation; only the shapes conv_cat_fwd_supported accepts.
+bool conv_cat_fwd_supported(int Cs, int Cu, int Co);
+hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_t* w,
+                        const float* bias, const int* dims, int Cs, int Cu, int Co, float alpha,
+                        int act, uint16_t* y16, hipStream_t s);
 // wt[ci][26 - t][co] = w[co][t][ci] (weights of the input-gradient conv)
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
 // weight gradient: part needs wgrad_part_floats floats; dw [Co][27][Ci], db [Co]

@@ -282,6 +282,201 @@ __global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// The halo-brick convolution with the input channel count fixed at compile
+// time, for the few-channel layers (Ci in {16, 32, 48} with 16 outputs,
+// Ci = 16 with 32): the B fragments (weights) of the K steps live in
+// registers, read from memory in chunks of CH steps, the next chunk in
+// flight while the current one feeds the matrix cores, and the whole
+// 6 x 10 x 10 input brick is fetched with every load issued before the
+// first LDS store, so a workgroup waits for one memory round trip before
+// its matrix-core work rather than one per staging pass.  The LDS offset of
+// a lane's (tap, channel) pair at K step s (k = 32 s + 8 (l / 16)) is a
+// compile-time constant picked by the lane's quarter.  Consecutive
+// workgroups are dealt round-robin to the 8 XCDs, so the brick order is
+// permuted to give each XCD one contiguous range of bricks: neighbouring
+// bricks, which share halo voxels, then meet in the same L2.
+// ---------------------------------------------------------------------------
+template <int CI>
+__host__ __device__ constexpr int halo_elem(int k) {
+    // element offset of k = t CI + ci from the output voxel's own LDS slot
+    return k >= 27 * CI ? 0
+                        : ((((k / CI) / 9 - 1) * (kHY + 2) + ((k / CI) / 3) % 3 - 1) * (kHX + 2) +
+                           (k / CI) % 3 - 1) * (CI + 8) + k % CI;
+}
+
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int bid, int nblocks) {
+    const int q = nblocks / kXcds, r = nblocks % kXcds;
+    const int xcd = bid % kXcds, idx = bid / kXcds;
+    return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+// With CS < CI the input is the decoder's concatenation, never stored:
+// channels [0, CS) come from x (CS channels per voxel) and [CS, CI) from
+// the coarser level xl (CI - CS channels, half the size along each axis,
+// nearest-neighbour upsampled), read straight into the brick.
+template <int CI, int NT, int CH, int CS = CI>
+__global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict__ x,
+                                                      const uint16_t* __restrict__ xl,
+                                                      const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias, Geo g,
+                                                      int Co, float alpha, int act,
+                                                      uint16_t* __restrict__ y16,
+                                                      float* __restrict__ y32, int accumulate) {
+    constexpr int MT = 4;
+    constexpr int K = 27 * CI;
+    constexpr int KS = (K + 31) / 32;
+    constexpr int NCH = (KS + CH - 1) / CH;
+    constexpr int ROW = CI + 8;
+    constexpr int GV = CI / 8;
+    constexpr int U = kHVox * GV;
+    constexpr int NU = (U + 255) / 256;
+    extern __shared__ __align__(16) uint16_t hx[];   // [kHVox][ROW]
+    const int nbx = (g.W + kHX - 1) / kHX, nby = (g.H + kHY - 1) / kHY, nbz = (g.D + kHZ - 1) / kHZ;
+    int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int bx = bid % nbx;
+    bid /= nbx;
+    const int by = bid % nby;
+    bid /= nby;
+    const int bz = bid % nbz;
+    const int b = bid / nbz;
+    const int x0 = bx * kHX, y0 = by * kHY, z0 = bz * kHZ;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+    bf16x8 wb[2][CH][NT];   // B[k][n] = w[n][k], two chunks of K steps
+    auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int c) {
+#pragma unroll
+        for (int s2 = 0; s2 < CH; ++s2)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int k = (c * CH + s2) * 32 + q * 8, co = j * 16 + (lane & 15);
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (k < K && co < Co) v = *reinterpret_cast<const uint4*>(w + (size_t)co * K + k);
+                dst[s2][j] = as_bf16x8(v);
+            }
+    };
+    uint4 st[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int i = threadIdx.x + u * 256;
+        st[u] = make_uint4(0, 0, 0, 0);
+        if (i < U) {
+            const int hv = i / GV, c = (i - hv * GV) * 8;
+            const int hxx = hv % (kHX + 2), hyy = (hv / (kHX + 2)) % (kHY + 2),
+                      hzz = hv / ((kHX + 2) * (kHY + 2));
+            const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
+            if (xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D) {
+                if (CS == CI || c < CS) {
+                    const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                    st[u] = *reinterpret_cast<const uint4*>(x + v * CS + c);
+                } else {
+                    const long long v =
+                        (((long long)b * (g.D >> 1) + (zz >> 1)) * (g.H >> 1) + (yy >> 1)) *
+                            (g.W >> 1) + (xx >> 1);
+                    st[u] = *reinterpret_cast<const uint4*>(xl + v * (CI - CS) + (c - CS));
+                }
+            }
+        }
+    }
+    load_chunk(wb[0], 0);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int i = threadIdx.x + u * 256;
+        if (i < U) {
+            const int hv = i / GV, c = (i - hv * GV) * 8;
+            *reinterpret_cast<uint4*>(hx + hv * ROW + c) = st[u];
+        }
+    }
+    __syncthreads();
+    // wave w owns z-slice w; row tile m covers rows 2m and 2m + 1
+    const int base =
+        (((wave + 1) * (kHY + 2) + ((lane & 15) >> 3) + 1) * (kHX + 2) + (lane & 7) + 1) * ROW;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (c + 1 < NCH) load_chunk(wb[(c + 1) & 1], c + 1);
+#pragma unroll
+        for (int s2 = 0; s2 < CH; ++s2) {
+            const int s = c * CH + s2;
+            if (s >= KS) break;
+            constexpr int kTail = K % 32;
+            const int o0 = halo_elem<CI>(s * 32), o1 = halo_elem<CI>(s * 32 + 8),
+                      o2 = halo_elem<CI>(s * 32 + 16), o3 = halo_elem<CI>(s * 32 + 24);
+            const int o = (q & 2) ? ((q & 1) ? o3 : o2) : ((q & 1) ? o1 : o0);
+            const bool kin = kTail == 0 || s < KS - 1 || q * 8 < kTail;
+            bf16x8 a[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                uint4 av = *reinterpret_cast<const uint4*>(hx + base + o + m * 2 * (kHX + 2) * ROW);
+                if (!kin) av = make_uint4(0, 0, 0, 0);
+                a[m] = as_bf16x8(av);
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], wb[c & 1][s2][j],
+                                                                        acc[m][j], 0, 0, 0);
+        }
+    }
+    const int zz = z0 + wave;
+    if (!y32) {
+        // bf16 output only: the wave's 8 x 8 slice goes through LDS ([voxel][Co],
+        // voxels row-major, which is the tile order) so that every lane stores
+        // 16 contiguous bytes
+        __syncthreads();   // every wave is done with the input brick
+        uint16_t* ot = hx + wave * (64 * NT * 16);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const float bb = bias ? bias[j * 16 + (lane & 15)] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float rr = acc[m][j][i] + bb;
+                    if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                    ot[(m * 16 + q * 4 + i) * (NT * 16) + j * 16 + (lane & 15)] = f2bf(rr);
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u0 = 0; u0 < 64 * 2 * NT; u0 += 64) {
+            const int u = u0 + lane, p = u / (2 * NT), c = (u % (2 * NT)) * 8;
+            const int yy = y0 + (p >> 3), xx = x0 + (p & 7);
+            if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
+            const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+            *reinterpret_cast<uint4*>(y16 + v * Co + c) =
+                *reinterpret_cast<const uint4*>(ot + p * (NT * 16) + c);
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = j * 16 + (lane & 15);
+        if (co >= Co) continue;
+        const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = q * 4 + i;           // row of the 16-voxel tile
+                const int yy = y0 + 2 * m + (r >> 3), xx = x0 + (r & 7);
+                if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
+                const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                float rr = acc[m][j][i] + bb;
+                if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                if (y16) y16[v * Co + co] = f2bf(rr);
+                if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
+            }
+        }
+    }
+}
+
 // wt[ci][26 - t][co] = w[co][t][ci]: the weights of the input-gradient conv.
 __global__ void k_flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co) {
     const int n = Co * 27 * Ci;
@@ -814,9 +1009,29 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_conv_fwd_halo<2>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_conv_fwd_reg<48, 1, 14>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         return e;
     }();
     if (attr != hipSuccess) return attr;
+    {   // few channels, weights in registers
+        const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
+                              ((g.D + kHZ - 1) / kHZ) * g.B;
+        const size_t lds_r = (size_t)kHVox * (Ci + 8) * sizeof(uint16_t);
+#define LAUNCH_REG(CI, NT, CH)                                                                \
+    hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk), dim3(256), lds_r, s, x, \
+                       nullptr, w, bias, g, Co, alpha, act, y16, y32, accumulate)
+        bool done = true;
+        if (Ci == 16 && nt == 1) LAUNCH_REG(16, 1, 14);
+        else if (Ci == 16 && nt == 2) LAUNCH_REG(16, 2, 14);
+        else if (Ci == 32 && nt == 1) LAUNCH_REG(32, 1, 14);
+        else if (Ci == 32 && nt == 2) LAUNCH_REG(32, 2, 7);
+        else if (Ci == 48 && nt == 1) LAUNCH_REG(48, 1, 14);
+        else done = false;
+#undef LAUNCH_REG
+        if (done) return hipGetLastError();
+    }
     if (nt <= 2 && Ci <= 48) {   // few channels: input brick with halo in LDS
         const size_t lds_h =
             ((size_t)kHVox * (Ci + 8) + (size_t)nt * 16 * kSlabRow) * sizeof(uint16_t);
@@ -845,6 +1060,26 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         default: return hipErrorInvalidValue;
     }
 #undef LAUNCH
+    return hipGetLastError();
+}
+
+bool conv_cat_fwd_supported(int Cs, int Cu, int Co) { return Cs == 16 && Cu == 32 && Co == 16; }
+
+hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_t* w,
+                        const float* bias, const int* dims, int Cs, int Cu, int Co, float alpha,
+                        int act, uint16_t* y16, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (!conv_cat_fwd_supported(Cs, Cu, Co) || (g.D | g.H | g.W) & 1 || !y16)
+        return hipErrorInvalidValue;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)k_conv_fwd_reg<48, 1, 14, 16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (attr != hipSuccess) return attr;
+    const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
+                          ((g.D + kHZ - 1) / kHZ) * g.B;
+    const size_t lds = (size_t)kHVox * (Cs + Cu + 8) * sizeof(uint16_t);
+    hipLaunchKernelGGL((k_conv_fwd_reg<48, 1, 14, 16>), dim3((unsigned)nbk), dim3(256), lds, s,
+                       skip, low, w, bias, g, Co, alpha, act, y16, nullptr, 0);
     return hipGetLastError();
 }
 

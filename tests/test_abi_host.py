@@ -110,3 +110,21 @@ def test_nn_config_validation_without_gpu(lib):
     assert lib.sde_nn_conv3d_workspace(1, 4, 4, 4, 8, 16, C.byref(n)) == sde.E_INVALID
     assert lib.sde_nn_conv3d_workspace(2, 4, 4, 4, 32, 64, C.byref(n)) == sde.OK
     assert n.value >= 27 * 32 * 64 * 4
+
+
+def test_nn_layer_alignment_is_checked_without_gpu(lib):
+    """The layer entry points read bf16 operands 16 bytes at a time: a
+    misaligned pointer is refused before any device call (the fake addresses
+    below are never dereferenced)."""
+    from paper_2511_03115_amd import sde
+    V, F, Z = C.c_void_p, C.c_float, C.c_size_t
+    ok, bad = V(0x10000), V(0x10002)
+    assert lib.sde_nn_conv3d_fwd(bad, ok, None, 1, 2, 2, 2, 16, 16, F(0.01), 1, ok, None) == \
+        sde.E_INVALID
+    assert b"aligned" in C.string_at(lib.sde_last_error())
+    assert lib.sde_nn_conv3d_fwd(ok, ok, None, 1, 2, 2, 2, 16, 16, F(0.01), 1, bad, None) == \
+        sde.E_INVALID
+    assert lib.sde_nn_conv3d_dgrad(ok, bad, 1, 2, 2, 2, 16, 16, ok, ok, Z(1 << 20)) == \
+        sde.E_INVALID
+    assert lib.sde_nn_conv3d_wgrad(ok, ok, 1, 2, 2, 2, 16, 16, ok, None, bad, Z(1 << 20)) == \
+        sde.E_INVALID

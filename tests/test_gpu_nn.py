@@ -55,7 +55,8 @@ def he_params(levels, c0, cin, seed, head_scale=0.1):
                                          ((2, 4, 4, 6), 32, 64), ((1, 3, 4, 5), 64, 128),
                                          ((1, 4, 3, 5), 16, 48), ((1, 3, 3, 3), 128, 192),
                                          ((1, 1, 1, 1), 16, 16), ((2, 9, 17, 11), 16, 16),
-                                         ((1, 10, 8, 19), 32, 32), ((1, 5, 12, 9), 48, 16)])
+                                         ((1, 10, 8, 19), 32, 32), ((1, 5, 12, 9), 48, 16),
+                                         ((1, 6, 9, 10), 16, 32), ((2, 5, 7, 9), 32, 16)])
 def test_conv3d_fwd(shape, ci, co):
     import torch
     from paper_2511_03115_amd import nn
@@ -177,6 +178,31 @@ def test_network_forward_and_gradients(levels, B, D, H, W):
         assert e_b <= max(1e-2, 0.75 * d), k
         assert e_64 <= 2 * d + 1e-2, k
     net.close()
+
+
+@pytest.mark.parametrize("levels,B,D,H,W", [(4, 1, 16, 24, 40), (2, 2, 6, 10, 14)])
+def test_inference_reads_the_concatenation_in_place(levels, B, D, H, W):
+    """An inference network reads the decoder input concat[skip, up(lower)]
+    straight from the two levels; a training network stores it first.  The
+    sums are the same in the same order, so the outputs are bit-identical
+    (sizes with ragged 4 x 8 x 8 bricks)."""
+    import torch
+    from paper_2511_03115_amd import nn
+    c0, cin, alpha = 16, 16, 0.01
+    flat = nno.flatten(he_params(levels, c0, cin, seed=21), levels, c0, cin).astype(np.float32)
+    dose, rho, _, _ = _net_inputs(B, D, H, W, seed=22)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    outs = []
+    for train in (False, True):
+        log(f"case fused concat L={levels} dims={(B, D, H, W)} train={train}")
+        net = nn.Net(levels, c0, cin, alpha, max_batch=B, max_dims=(D, H, W), train=train)
+        net.set_params(flat)
+        out = torch.zeros((B, D, H, W), dtype=torch.float32, device="cuda")
+        net.forward(dev(dose), dev(rho), out)
+        outs.append(out.cpu().numpy())
+        net.close()
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_adam_update_matches_oracle():
