@@ -477,6 +477,202 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// The halo-brick convolution for wide inputs (Ci a multiple of 32, at least
+// 64) with 32 or 64 outputs: the input channels are taken 32 at a time
+// (one pass each), so the brick of one pass (6 x 10 x 10 voxels x 32
+// channels, 48 KB of LDS) leaves room for two workgroups per CU.  Within a
+// pass each K step is one tap over the pass's 32 channels, so the LDS
+// offset of a step is the tap's, uniform over the wave.  The next pass's
+// brick is fetched with every load in flight before the first store, and
+// the weight fragments stream through registers in chunks of CH taps, the
+// next chunk in flight.  Channels [0, cs) come from x (cs per voxel) and
+// [cs, Ci) from the half-size level xl, nearest-neighbour upsampled (the
+// decoder's concatenation; cs = Ci for a plain input).  K order: pass,
+// tap, channel.
+// ---------------------------------------------------------------------------
+template <int NT, int CH>
+__global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ xl,
+                                                       const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, Geo g,
+                                                       int Ci, int cs, int Co, float alpha,
+                                                       int act, uint16_t* __restrict__ y16,
+                                                       float* __restrict__ y32, int accumulate) {
+    constexpr int MT = 4;
+    constexpr int CP = 32;
+    constexpr int ROW = CP + 8;
+    constexpr int GV = CP / 8;
+    constexpr int U = kHVox * GV;
+    constexpr int NU = (U + 255) / 256;
+    constexpr int NCH = (27 + CH - 1) / CH;
+    static_assert(NCH % 2 == 0, "every pass must start on weight buffer 0");
+    extern __shared__ __align__(16) uint16_t hx[];   // [kHVox][ROW]
+    const int nbx = (g.W + kHX - 1) / kHX, nby = (g.H + kHY - 1) / kHY, nbz = (g.D + kHZ - 1) / kHZ;
+    int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int bx = bid % nbx;
+    bid /= nbx;
+    const int by = bid % nby;
+    bid /= nby;
+    const int bz = bid % nbz;
+    const int b = bid / nbz;
+    const int x0 = bx * kHX, y0 = by * kHY, z0 = bz * kHZ;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+    const int K = 27 * Ci, P = Ci / CP, cu = Ci - cs;
+    auto load_brick = [&](uint4 (&st)[NU], int p) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int i = threadIdx.x + u * 256;
+            st[u] = make_uint4(0, 0, 0, 0);
+            if (i < U) {
+                const int hv = i / GV, c = p * CP + (i - hv * GV) * 8;
+                const int hxx = hv % (kHX + 2), hyy = (hv / (kHX + 2)) % (kHY + 2),
+                          hzz = hv / ((kHX + 2) * (kHY + 2));
+                const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
+                if (xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D) {
+                    if (c < cs) {
+                        const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                        st[u] = *reinterpret_cast<const uint4*>(x + v * cs + c);
+                    } else {
+                        const long long v =
+                            (((long long)b * (g.D >> 1) + (zz >> 1)) * (g.H >> 1) + (yy >> 1)) *
+                                (g.W >> 1) + (xx >> 1);
+                        st[u] = *reinterpret_cast<const uint4*>(xl + v * cu + (c - cs));
+                    }
+                }
+            }
+        }
+    };
+    auto store_brick = [&](const uint4 (&st)[NU]) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int i = threadIdx.x + u * 256;
+            if (i < U) {
+                const int hv = i / GV, c = (i - hv * GV) * 8;
+                *reinterpret_cast<uint4*>(hx + hv * ROW + c) = st[u];
+            }
+        }
+    };
+    // chunk c of pass p: taps [c CH, c CH + CH) over channels [p CP, p CP + CP).
+    // Buffer loads: the lane's part of the offset in a VGPR, the uniform
+    // part (tap, pass, column tile) in an SGPR.
+    // descriptor word 3 of gfx9: 32-bit data format (a zero format reads zeros)
+    const __amdgpu_buffer_rsrc_t wres =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(w), 0, Co * K * 2, 0x00020000);
+    const int wlane = ((lane & 15) * K + q * 8) * 2;
+    // The uniform offset advances by one tap at a time behind an empty asm,
+    // so the compiler computes it where it is used instead of keeping the
+    // offsets of all 27 taps live in scalar registers.
+    auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int p, int c) {
+        int so = (c * CH * Ci + p * CP) * 2;
+        asm volatile("" : "+s"(so));
+#pragma unroll
+        for (int s2 = 0; s2 < CH; ++s2) {
+            const int t = c * CH + s2;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (t < 27)
+                    v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                      wres, wlane, so + j * 32 * K, 0));
+                dst[s2][j] = as_bf16x8(v);
+            }
+            so += 2 * Ci;
+            asm volatile("" : "+s"(so));
+        }
+    };
+    bf16x8 wb[2][CH][NT];
+    uint4 st[NU];
+    load_brick(st, 0);
+    load_chunk(wb[0], 0, 0);
+    store_brick(st);
+    __syncthreads();
+    const int base =
+        (((wave + 1) * (kHY + 2) + ((lane & 15) >> 3) + 1) * (kHX + 2) + (lane & 7) + 1) * ROW + q * 8;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c + 1 < NCH) load_chunk(wb[(c + 1) & 1], p, c + 1);
+            else if (p + 1 < P) load_chunk(wb[0], p + 1, 0);
+#pragma unroll
+            for (int s2 = 0; s2 < CH; ++s2) {
+                const int t = c * CH + s2;
+                if (t >= 27) break;
+                const int off = ((t / 9 - 1) * (kHY + 2) + (t / 3) % 3 - 1) * (kHX + 2) + t % 3 - 1;
+                bf16x8 a[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    a[m] = as_bf16x8(*reinterpret_cast<const uint4*>(
+                        hx + base + off * ROW + m * 2 * (kHX + 2) * ROW));
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], wb[c & 1][s2][j],
+                                                                            acc[m][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // every wave is done with this pass's brick
+        if (p + 1 < P) {
+            load_brick(st, p + 1);
+            store_brick(st);
+            __syncthreads();
+        }
+    }
+    const int zz = z0 + wave;
+    if (!y32) {
+        // bf16 output only: stage the wave's 8 x 8 slice in LDS, 16-byte stores
+        uint16_t* ot = hx + wave * (64 * NT * 16);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const float bb = bias ? bias[j * 16 + (lane & 15)] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float rr = acc[m][j][i] + bb;
+                    if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                    ot[(m * 16 + q * 4 + i) * (NT * 16) + j * 16 + (lane & 15)] = f2bf(rr);
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u0 = 0; u0 < 64 * 2 * NT; u0 += 64) {
+            const int u = u0 + lane, p = u / (2 * NT), c = (u % (2 * NT)) * 8;
+            const int yy = y0 + (p >> 3), xx = x0 + (p & 7);
+            if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
+            const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+            *reinterpret_cast<uint4*>(y16 + v * Co + c) =
+                *reinterpret_cast<const uint4*>(ot + p * (NT * 16) + c);
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = j * 16 + (lane & 15);
+        const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = q * 4 + i;
+                const int yy = y0 + 2 * m + (r >> 3), xx = x0 + (r & 7);
+                if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
+                const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                float rr = acc[m][j][i] + bb;
+                if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                if (y16) y16[v * Co + co] = f2bf(rr);
+                y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
+            }
+        }
+    }
+}
+
 // wt[ci][26 - t][co] = w[co][t][ci]: the weights of the input-gradient conv.
 __global__ void k_flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co) {
     const int n = Co * 27 * Ci;
@@ -1032,6 +1228,20 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
     }
+    if (Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4)) {   // wide input, channel passes
+        const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
+                              ((g.D + kHZ - 1) / kHZ) * g.B;
+        const size_t lds_p = (size_t)kHVox * 40 * sizeof(uint16_t);
+        if (nt == 2)
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk), dim3(256), lds_p, s,
+                               x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
+                               accumulate);
+        else
+            hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256), lds_p, s,
+                               x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
+                               accumulate);
+        return hipGetLastError();
+    }
     if (nt <= 2 && Ci <= 48) {   // few channels: input brick with halo in LDS
         const size_t lds_h =
             ((size_t)kHVox * (Ci + 8) + (size_t)nt * 16 * kSlabRow) * sizeof(uint16_t);
@@ -1063,7 +1273,11 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
     return hipGetLastError();
 }
 
-bool conv_cat_fwd_supported(int Cs, int Cu, int Co) { return Cs == 16 && Cu == 32 && Co == 16; }
+bool conv_cat_fwd_supported(int Cs, int Cu, int Co) {
+    if (Cs == 16 && Cu == 32 && Co == 16) return true;
+    return Cs % 8 == 0 && Cu % 8 == 0 && (Cs + Cu) % 32 == 0 && Cs + Cu >= 64 &&
+           (Co == 32 || Co == 64);
+}
 
 hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_t* w,
                         const float* bias, const int* dims, int Cs, int Cu, int Co, float alpha,
@@ -1071,12 +1285,24 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     if (!conv_cat_fwd_supported(Cs, Cu, Co) || (g.D | g.H | g.W) & 1 || !y16)
         return hipErrorInvalidValue;
+    const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
+                          ((g.D + kHZ - 1) / kHZ) * g.B;
+    if (Co == 32 || Co == 64) {
+        const size_t lds_p = (size_t)kHVox * 40 * sizeof(uint16_t);
+        if (Co == 32)
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk), dim3(256), lds_p, s,
+                               skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16, nullptr,
+                               0);
+        else
+            hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256), lds_p, s,
+                               skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16, nullptr,
+                               0);
+        return hipGetLastError();
+    }
     static const hipError_t attr =
         hipFuncSetAttribute((const void*)k_conv_fwd_reg<48, 1, 14, 16>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (attr != hipSuccess) return attr;
-    const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
-                          ((g.D + kHZ - 1) / kHZ) * g.B;
     const size_t lds = (size_t)kHVox * (Cs + Cu + 8) * sizeof(uint16_t);
     hipLaunchKernelGGL((k_conv_fwd_reg<48, 1, 14, 16>), dim3((unsigned)nbk), dim3(256), lds, s,
                        skip, low, w, bias, g, Co, alpha, act, y16, nullptr, 0);

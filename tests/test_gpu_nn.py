@@ -56,7 +56,9 @@ def he_params(levels, c0, cin, seed, head_scale=0.1):
                                          ((1, 4, 3, 5), 16, 48), ((1, 3, 3, 3), 128, 192),
                                          ((1, 1, 1, 1), 16, 16), ((2, 9, 17, 11), 16, 16),
                                          ((1, 10, 8, 19), 32, 32), ((1, 5, 12, 9), 48, 16),
-                                         ((1, 6, 9, 10), 16, 32), ((2, 5, 7, 9), 32, 16)])
+                                         ((1, 6, 9, 10), 16, 32), ((2, 5, 7, 9), 32, 16),
+                                         ((1, 6, 9, 10), 96, 32), ((2, 5, 8, 11), 64, 64),
+                                         ((1, 4, 10, 9), 192, 64)])
 def test_conv3d_fwd(shape, ci, co):
     import torch
     from paper_2511_03115_amd import nn
@@ -88,7 +90,8 @@ def test_conv3d_fwd(shape, ci, co):
 
 @pytest.mark.parametrize("shape,ci,co", [((2, 6, 5, 7), 16, 16), ((1, 5, 4, 6), 48, 32),
                                          ((1, 3, 4, 5), 192, 64), ((1, 4, 4, 4), 128, 128),
-                                         ((2, 8, 8, 9), 16, 48)])
+                                         ((2, 8, 8, 9), 16, 48), ((1, 5, 9, 7), 32, 64),
+                                         ((1, 4, 6, 10), 64, 64)])
 def test_conv3d_backward(shape, ci, co):
     import torch
     from paper_2511_03115_amd import nn
