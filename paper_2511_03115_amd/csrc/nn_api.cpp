@@ -137,7 +137,7 @@ int run_forward(sde_nn* n, const int* d0) {
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
         const ConvP& cp = n->dec_a[l];
-        if (!n->cfg.train && conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co)) {
+        if (!n->cfg.train && conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co, nvox(d))) {
             // inference: the concatenation is read in place (training keeps it
             // for the weight gradient)
             NN_TRY(conv_cat_fwd(v.eb, top, n->P16 + cp.w, n->P + cp.b, d, n->c[l], n->c[l + 1],
@@ -225,7 +225,7 @@ int alloc_all(sde_nn* n) {
         NN_TRY(dalloc(n, &v.eb, nv * n->c[l]));
         if (l > 0) NN_TRY(dalloc(n, &v.pin, nv * n->c[l - 1]));
         if (l <= L - 2) {
-            if (c.train || !conv_cat_fwd_supported(n->c[l], n->c[l + 1], n->c[l]))
+            if (c.train || !conv_cat_fwd_supported(n->c[l], n->c[l + 1], n->c[l], nv))
                 NN_TRY(dalloc(n, &v.cat, nv * (n->c[l] + n->c[l + 1])));
             NN_TRY(dalloc(n, &v.da, nv * n->c[l]));
             NN_TRY(dalloc(n, &v.db, nv * n->c[l]));

@@ -17,8 +17,9 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
                     int accumulate, hipStream_t s);
 // conv_fwd (bf16 output) of the decoder input concat[skip (Cs channels),
 // nearest-up(low) (Cu channels, half size)] without storing the
-// concatenation; only the shapes conv_cat_fwd_supported accepts.
-bool conv_cat_fwd_supported(int Cs, int Cu, int Co);
+// concatenation; only the shapes and sizes (nvox voxels at the skip level)
+// conv_cat_fwd_supported accepts.
+bool conv_cat_fwd_supported(int Cs, int Cu, int Co, long long nvox);
 hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_t* w,
                         const float* bias, const int* dims, int Cs, int Cu, int Co, float alpha,
                         int act, uint16_t* y16, hipStream_t s);

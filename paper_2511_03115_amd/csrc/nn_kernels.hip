@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "nn_internal.hpp"
 
 namespace sde {
@@ -22,14 +24,29 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// float -> bf16, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// float -> bf16, round to nearest even (the hardware conversion)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// LeakyReLU; for a slope in (0, 1] it is max(r, alpha r)
+__device__ __forceinline__ float lrelu(float r, float alpha) {
+    return alpha <= 1.0f ? fmaxf(r, alpha * r) : (r > 0.0f ? r : alpha * r);
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Raw buffer resource over n bf16 elements (gfx9 descriptor word 3: 32-bit
+// data format; a zero format reads zeros).  n * 2 must stay below 2^31.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc16(const uint16_t* p, long long n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(p), 0, (int)(n * 2), 0x00020000);
+}
+
+// 16-byte buffer load at byte offset off, or zeros when !ok (then offset 0
+// is read, which is always in range, and discarded).
+__device__ __forceinline__ uint4 ld16(__amdgpu_buffer_rsrc_t r, int off, bool ok) {
+    const uint4 v =
+        __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, ok ? off : 0, 0, 0));
+    return ok ? v : make_uint4(0, 0, 0, 0);
+}
 
 struct Geo {
     int B, D, H, W;
@@ -171,6 +188,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
 constexpr int kHZ = 4, kHY = 8, kHX = 8;
 constexpr int kHVox = (kHZ + 2) * (kHY + 2) * (kHX + 2);
 
+// Brick of the register and channel-pass kernels below: 4 x 4 x 16 output
+// voxels, so a 16-voxel matrix row is one run along x; with the odd number
+// of 16-byte units per LDS voxel slot (Ci + 8 elements) the 16 slots a
+// quarter-wave reads then fall on distinct banks.
+constexpr int kRZ = 4, kRY = 4, kRX = 16;
+constexpr int kRVox = (kRZ + 2) * (kRY + 2) * (kRX + 2);
+
 template <int NT>
 __global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restrict__ x,
                                                        const uint16_t* __restrict__ w,
@@ -274,7 +298,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restric
                 if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
                 const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
                 float rr = acc[m][j][i] + bb;
-                if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                if (act) rr = lrelu(rr, alpha);
                 if (y16) y16[v * Co + co] = f2bf(rr);
                 if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
             }
@@ -288,7 +312,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restric
 // Ci = 16 with 32): the B fragments (weights) of the K steps live in
 // registers, read from memory in chunks of CH steps, the next chunk in
 // flight while the current one feeds the matrix cores, and the whole
-// 6 x 10 x 10 input brick is fetched with every load issued before the
+// 6 x 6 x 18 input brick is fetched with every load issued before the
 // first LDS store, so a workgroup waits for one memory round trip before
 // its matrix-core work rather than one per staging pass.  The LDS offset of
 // a lane's (tap, channel) pair at K step s (k = 32 s + 8 (l / 16)) is a
@@ -301,7 +325,7 @@ template <int CI>
 __host__ __device__ constexpr int halo_elem(int k) {
     // element offset of k = t CI + ci from the output voxel's own LDS slot
     return k >= 27 * CI ? 0
-                        : ((((k / CI) / 9 - 1) * (kHY + 2) + ((k / CI) / 3) % 3 - 1) * (kHX + 2) +
+                        : ((((k / CI) / 9 - 1) * (kRY + 2) + ((k / CI) / 3) % 3 - 1) * (kRX + 2) +
                            (k / CI) % 3 - 1) * (CI + 8) + k % CI;
 }
 
@@ -331,10 +355,10 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     constexpr int NCH = (KS + CH - 1) / CH;
     constexpr int ROW = CI + 8;
     constexpr int GV = CI / 8;
-    constexpr int U = kHVox * GV;
+    constexpr int U = kRVox * GV;
     constexpr int NU = (U + 255) / 256;
-    extern __shared__ __align__(16) uint16_t hx[];   // [kHVox][ROW]
-    const int nbx = (g.W + kHX - 1) / kHX, nby = (g.H + kHY - 1) / kHY, nbz = (g.D + kHZ - 1) / kHZ;
+    extern __shared__ __align__(16) uint16_t hx[];   // [kRVox][ROW]
+    const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
     int bid = xcd_contiguous(blockIdx.x, gridDim.x);
     const int bx = bid % nbx;
     bid /= nbx;
@@ -342,41 +366,47 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     bid /= nby;
     const int bz = bid % nbz;
     const int b = bid / nbz;
-    const int x0 = bx * kHX, y0 = by * kHY, z0 = bz * kHZ;
+    const int x0 = bx * kRX, y0 = by * kRY, z0 = bz * kRZ;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
-    bf16x8 wb[2][CH][NT];   // B[k][n] = w[n][k], two chunks of K steps
+    // Loads go through buffer resources with 32-bit offsets (the host keeps
+    // every operand below 2 GiB); a load that must give zeros (outside the
+    // volume, past the last K step) reads offset 0 and is replaced by zero,
+    // so no load sits behind a branch.
+    const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CS);
+    const __amdgpu_buffer_rsrc_t xlr = rsrc16(xl, CS == CI ? 0 : g.nvox() / 8 * (CI - CS));
+    const __amdgpu_buffer_rsrc_t wr = rsrc16(w, (long long)NT * 16 * K);
+    bf16x8 wb[2][CH][NT];   // B[k][n] = w[n][k], two chunks of K steps (Co = 16 NT)
     auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int c) {
 #pragma unroll
         for (int s2 = 0; s2 < CH; ++s2)
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
-                const int k = (c * CH + s2) * 32 + q * 8, co = j * 16 + (lane & 15);
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (k < K && co < Co) v = *reinterpret_cast<const uint4*>(w + (size_t)co * K + k);
-                dst[s2][j] = as_bf16x8(v);
+                const int k = (c * CH + s2) * 32 + q * 8;
+                const bool kin = (c * CH + s2 + 1) * 32 <= K || k < K;
+                dst[s2][j] = as_bf16x8(ld16(wr, ((j * 16 + (lane & 15)) * K + k) * 2, kin));
             }
     };
     uint4 st[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int i = threadIdx.x + u * 256;
-        st[u] = make_uint4(0, 0, 0, 0);
-        if (i < U) {
-            const int hv = i / GV, c = (i - hv * GV) * 8;
-            const int hxx = hv % (kHX + 2), hyy = (hv / (kHX + 2)) % (kHY + 2),
-                      hzz = hv / ((kHX + 2) * (kHY + 2));
-            const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
-            if (xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D) {
-                if (CS == CI || c < CS) {
-                    const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
-                    st[u] = *reinterpret_cast<const uint4*>(x + v * CS + c);
-                } else {
-                    const long long v =
-                        (((long long)b * (g.D >> 1) + (zz >> 1)) * (g.H >> 1) + (yy >> 1)) *
-                            (g.W >> 1) + (xx >> 1);
-                    st[u] = *reinterpret_cast<const uint4*>(xl + v * (CI - CS) + (c - CS));
-                }
-            }
+        const int hv = i / GV, c = (i - hv * GV) * 8;
+        const int hxx = hv % (kRX + 2), hyy = (hv / (kRX + 2)) % (kRY + 2),
+                  hzz = hv / ((kRX + 2) * (kRY + 2));
+        const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
+        const bool in = (U % 256 == 0 || u < NU - 1 || i < U) && xx >= 0 && yy >= 0 && zz >= 0 &&
+                        xx < g.W && yy < g.H && zz < g.D;
+        if (CS == CI) {
+            st[u] = ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2, in);
+        } else {
+            // skip channels from x, the rest from the parent voxel of xl
+            const uint4 vs =
+                ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2, in && c < CS);
+            const uint4 vl = ld16(xlr,
+                                  (((b * (g.D >> 1) + (zz >> 1)) * (g.H >> 1) + (yy >> 1)) *
+                                       (g.W >> 1) + (xx >> 1)) * ((CI - CS) * 2) + (c - CS) * 2,
+                                  in && c >= CS);
+            st[u] = make_uint4(vs.x | vl.x, vs.y | vl.y, vs.z | vl.z, vs.w | vl.w);
         }
     }
     load_chunk(wb[0], 0);
@@ -389,9 +419,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
         }
     }
     __syncthreads();
-    // wave w owns z-slice w; row tile m covers rows 2m and 2m + 1
-    const int base =
-        (((wave + 1) * (kHY + 2) + ((lane & 15) >> 3) + 1) * (kHX + 2) + (lane & 7) + 1) * ROW;
+    // wave w owns z-slice w; row tile m is row m (16 voxels along x)
+    const int base = (((wave + 1) * (kRY + 2) + 1) * (kRX + 2) + (lane & 15) + 1) * ROW;
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -412,7 +441,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
             bf16x8 a[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                uint4 av = *reinterpret_cast<const uint4*>(hx + base + o + m * 2 * (kHX + 2) * ROW);
+                uint4 av = *reinterpret_cast<const uint4*>(hx + base + o + m * (kRX + 2) * ROW);
                 if (!kin) av = make_uint4(0, 0, 0, 0);
                 a[m] = as_bf16x8(av);
             }
@@ -426,7 +455,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     }
     const int zz = z0 + wave;
     if (!y32) {
-        // bf16 output only: the wave's 8 x 8 slice goes through LDS ([voxel][Co],
+        // bf16 output only: the wave's 4 x 16 slice goes through LDS ([voxel][Co],
         // voxels row-major, which is the tile order) so that every lane stores
         // 16 contiguous bytes
         __syncthreads();   // every wave is done with the input brick
@@ -439,7 +468,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float rr = acc[m][j][i] + bb;
-                    if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                    if (act) rr = lrelu(rr, alpha);
                     ot[(m * 16 + q * 4 + i) * (NT * 16) + j * 16 + (lane & 15)] = f2bf(rr);
                 }
         }
@@ -447,7 +476,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
 #pragma unroll
         for (int u0 = 0; u0 < 64 * 2 * NT; u0 += 64) {
             const int u = u0 + lane, p = u / (2 * NT), c = (u % (2 * NT)) * 8;
-            const int yy = y0 + (p >> 3), xx = x0 + (p & 7);
+            const int yy = y0 + (p >> 4), xx = x0 + (p & 15);
             if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
             const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
             *reinterpret_cast<uint4*>(y16 + v * Co + c) =
@@ -465,11 +494,11 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = q * 4 + i;           // row of the 16-voxel tile
-                const int yy = y0 + 2 * m + (r >> 3), xx = x0 + (r & 7);
+                const int yy = y0 + m, xx = x0 + r;
                 if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
                 const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
                 float rr = acc[m][j][i] + bb;
-                if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                if (act) rr = lrelu(rr, alpha);
                 if (y16) y16[v * Co + co] = f2bf(rr);
                 if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
             }
@@ -480,7 +509,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
 // ---------------------------------------------------------------------------
 // The halo-brick convolution for wide inputs (Ci a multiple of 32, at least
 // 64) with 32 or 64 outputs: the input channels are taken 32 at a time
-// (one pass each), so the brick of one pass (6 x 10 x 10 voxels x 32
+// (one pass each), so the brick of one pass (6 x 6 x 18 voxels x 32
 // channels, 48 KB of LDS) leaves room for two workgroups per CU.  Within a
 // pass each K step is one tap over the pass's 32 channels, so the LDS
 // offset of a step is the tap's, uniform over the wave.  The next pass's
@@ -503,12 +532,12 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
     constexpr int CP = 32;
     constexpr int ROW = CP + 8;
     constexpr int GV = CP / 8;
-    constexpr int U = kHVox * GV;
+    constexpr int U = kRVox * GV;
     constexpr int NU = (U + 255) / 256;
     constexpr int NCH = (27 + CH - 1) / CH;
     static_assert(NCH % 2 == 0, "every pass must start on weight buffer 0");
-    extern __shared__ __align__(16) uint16_t hx[];   // [kHVox][ROW]
-    const int nbx = (g.W + kHX - 1) / kHX, nby = (g.H + kHY - 1) / kHY, nbz = (g.D + kHZ - 1) / kHZ;
+    extern __shared__ __align__(16) uint16_t hx[];   // [kRVox][ROW]
+    const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
     int bid = xcd_contiguous(blockIdx.x, gridDim.x);
     const int bx = bid % nbx;
     bid /= nbx;
@@ -516,7 +545,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
     bid /= nby;
     const int bz = bid % nbz;
     const int b = bid / nbz;
-    const int x0 = bx * kHX, y0 = by * kHY, z0 = bz * kHZ;
+    const int x0 = bx * kRX, y0 = by * kRY, z0 = bz * kRZ;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
     const int K = 27 * Ci, P = Ci / CP, cu = Ci - cs;
     auto load_brick = [&](uint4 (&st)[NU], int p) {
@@ -526,8 +555,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
             st[u] = make_uint4(0, 0, 0, 0);
             if (i < U) {
                 const int hv = i / GV, c = p * CP + (i - hv * GV) * 8;
-                const int hxx = hv % (kHX + 2), hyy = (hv / (kHX + 2)) % (kHY + 2),
-                          hzz = hv / ((kHX + 2) * (kHY + 2));
+                const int hxx = hv % (kRX + 2), hyy = (hv / (kRX + 2)) % (kRY + 2),
+                          hzz = hv / ((kRX + 2) * (kRY + 2));
                 const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
                 if (xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D) {
                     if (c < cs) {
@@ -587,8 +616,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
     load_chunk(wb[0], 0, 0);
     store_brick(st);
     __syncthreads();
-    const int base =
-        (((wave + 1) * (kHY + 2) + ((lane & 15) >> 3) + 1) * (kHX + 2) + (lane & 7) + 1) * ROW + q * 8;
+    const int base = (((wave + 1) * (kRY + 2) + 1) * (kRX + 2) + (lane & 15) + 1) * ROW + q * 8;
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -603,12 +631,12 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
             for (int s2 = 0; s2 < CH; ++s2) {
                 const int t = c * CH + s2;
                 if (t >= 27) break;
-                const int off = ((t / 9 - 1) * (kHY + 2) + (t / 3) % 3 - 1) * (kHX + 2) + t % 3 - 1;
+                const int off = ((t / 9 - 1) * (kRY + 2) + (t / 3) % 3 - 1) * (kRX + 2) + t % 3 - 1;
                 bf16x8 a[MT];
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
                     a[m] = as_bf16x8(*reinterpret_cast<const uint4*>(
-                        hx + base + off * ROW + m * 2 * (kHX + 2) * ROW));
+                        hx + base + off * ROW + m * (kRX + 2) * ROW));
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
 #pragma unroll
@@ -626,7 +654,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
     }
     const int zz = z0 + wave;
     if (!y32) {
-        // bf16 output only: stage the wave's 8 x 8 slice in LDS, 16-byte stores
+        // bf16 output only: stage the wave's 4 x 16 slice in LDS, 16-byte stores
         uint16_t* ot = hx + wave * (64 * NT * 16);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
@@ -636,7 +664,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float rr = acc[m][j][i] + bb;
-                    if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                    if (act) rr = lrelu(rr, alpha);
                     ot[(m * 16 + q * 4 + i) * (NT * 16) + j * 16 + (lane & 15)] = f2bf(rr);
                 }
         }
@@ -644,7 +672,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
 #pragma unroll
         for (int u0 = 0; u0 < 64 * 2 * NT; u0 += 64) {
             const int u = u0 + lane, p = u / (2 * NT), c = (u % (2 * NT)) * 8;
-            const int yy = y0 + (p >> 3), xx = x0 + (p & 7);
+            const int yy = y0 + (p >> 4), xx = x0 + (p & 15);
             if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
             const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
             *reinterpret_cast<uint4*>(y16 + v * Co + c) =
@@ -661,11 +689,11 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = q * 4 + i;
-                const int yy = y0 + 2 * m + (r >> 3), xx = x0 + (r & 7);
+                const int yy = y0 + m, xx = x0 + r;
                 if (zz >= g.D || yy >= g.H || xx >= g.W) continue;
                 const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
                 float rr = acc[m][j][i] + bb;
-                if (act) rr = rr > 0.0f ? rr : alpha * rr;
+                if (act) rr = lrelu(rr, alpha);
                 if (y16) y16[v * Co + co] = f2bf(rr);
                 y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
             }
@@ -1211,10 +1239,10 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         return e;
     }();
     if (attr != hipSuccess) return attr;
-    {   // few channels, weights in registers
-        const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
-                              ((g.D + kHZ - 1) / kHZ) * g.B;
-        const size_t lds_r = (size_t)kHVox * (Ci + 8) * sizeof(uint16_t);
+    if (nv * std::max(Ci, Co) * 2 < (1LL << 31)) {   // few channels, weights in registers
+        const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                              ((g.D + kRZ - 1) / kRZ) * g.B;
+        const size_t lds_r = (size_t)kRVox * (Ci + 8) * sizeof(uint16_t);
 #define LAUNCH_REG(CI, NT, CH)                                                                \
     hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk), dim3(256), lds_r, s, x, \
                        nullptr, w, bias, g, Co, alpha, act, y16, y32, accumulate)
@@ -1229,9 +1257,9 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         if (done) return hipGetLastError();
     }
     if (Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4)) {   // wide input, channel passes
-        const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
-                              ((g.D + kHZ - 1) / kHZ) * g.B;
-        const size_t lds_p = (size_t)kHVox * 40 * sizeof(uint16_t);
+        const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                              ((g.D + kRZ - 1) / kRZ) * g.B;
+        const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
         if (nt == 2)
             hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk), dim3(256), lds_p, s,
                                x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
@@ -1273,7 +1301,8 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
     return hipGetLastError();
 }
 
-bool conv_cat_fwd_supported(int Cs, int Cu, int Co) {
+bool conv_cat_fwd_supported(int Cs, int Cu, int Co, long long nvox) {
+    if (nvox * (Cs + Cu) * 2 >= (1LL << 31)) return false;   // 32-bit buffer offsets
     if (Cs == 16 && Cu == 32 && Co == 16) return true;
     return Cs % 8 == 0 && Cu % 8 == 0 && (Cs + Cu) % 32 == 0 && Cs + Cu >= 64 &&
            (Co == 32 || Co == 64);
@@ -1283,12 +1312,12 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
                         const float* bias, const int* dims, int Cs, int Cu, int Co, float alpha,
                         int act, uint16_t* y16, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
-    if (!conv_cat_fwd_supported(Cs, Cu, Co) || (g.D | g.H | g.W) & 1 || !y16)
+    if (!conv_cat_fwd_supported(Cs, Cu, Co, g.nvox()) || (g.D | g.H | g.W) & 1 || !y16)
         return hipErrorInvalidValue;
-    const long long nbk = (long long)((g.W + kHX - 1) / kHX) * ((g.H + kHY - 1) / kHY) *
-                          ((g.D + kHZ - 1) / kHZ) * g.B;
+    const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                          ((g.D + kRZ - 1) / kRZ) * g.B;
     if (Co == 32 || Co == 64) {
-        const size_t lds_p = (size_t)kHVox * 40 * sizeof(uint16_t);
+        const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
         if (Co == 32)
             hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk), dim3(256), lds_p, s,
                                skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16, nullptr,
@@ -1303,7 +1332,7 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
         hipFuncSetAttribute((const void*)k_conv_fwd_reg<48, 1, 14, 16>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (attr != hipSuccess) return attr;
-    const size_t lds = (size_t)kHVox * (Cs + Cu + 8) * sizeof(uint16_t);
+    const size_t lds = (size_t)kRVox * (Cs + Cu + 8) * sizeof(uint16_t);
     hipLaunchKernelGGL((k_conv_fwd_reg<48, 1, 14, 16>), dim3((unsigned)nbk), dim3(256), lds, s,
                        skip, low, w, bias, g, Co, alpha, act, y16, nullptr, 0);
     return hipGetLastError();
