@@ -719,10 +719,33 @@ __global__ void k_flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co
 // rows padded to 72 elements = an odd number of 16-byte units, so the 16
 // rows a quarter-wave reads fall on distinct banks); the dz slice is staged
 // once for all taps of the group and the slice's voxel coordinates are
-// decoded once.  The block's tg x (Co/16) x (Ci/16) output tiles (at most
-// 64) are spread over its 4 waves; each lane reads 8 consecutive voxels in
-// one 16-byte load per operand.
+// decoded once.  The transpose is done in registers, 8 voxels x 8 channels
+// per thread (8 16-byte loads in, 8 16-byte LDS stores out).  The block's
+// tg x (Co/16) x (Ci/16) output tiles (at most 64) are spread over its 4
+// waves; each lane reads 8 consecutive voxels in one 16-byte load per
+// operand.
 // ---------------------------------------------------------------------------
+// out[c] = bf16 column c of in (8 rows of 8 bf16): element (r, c) -> (c, r)
+__device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[8]) {
+    uint32_t a[8][4], b[8][4];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        a[r][0] = in[r].x;
+        a[r][1] = in[r].y;
+        a[r][2] = in[r].z;
+        a[r][3] = in[r].w;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t lo = a[2 * j][c >> 1], hi = a[2 * j + 1][c >> 1];
+            b[c][j] = (c & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
+        }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out[c] = make_uint4(b[c][0], b[c][1], b[c][2], b[c][3]);
+}
+
 constexpr int kWgSlice = 64;
 constexpr int kWgRow = kWgSlice + 8;
 constexpr int kWgWaves = 4;
@@ -775,41 +798,45 @@ __global__ void __launch_bounds__(256) k_wgrad_partial(const uint16_t* __restric
                 cz[tid] = -4;
             }
         }
-        // dz slice: one 16-byte load (8 channels of one voxel) per item
+        // dz slice: an item is 8 voxels x 8 channels, loaded as 8 16-byte
+        // rows, transposed in registers and stored as 8 16-byte rows
         const int gco = Co / 8, gci = Ci / 8;
-        for (int i = tid; i < kWgSlice * gco; i += blockDim.x) {
-            const int vv = i / gco, ch = (i - vv * gco) * 8;
-            const long long v = s0 + vv;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (v < v1) val = *reinterpret_cast<const uint4*>(dz + v * Co + ch);
-            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+        for (int i = tid; i < (kWgSlice / 8) * gco; i += blockDim.x) {
+            const int vb = (i / gco) * 8, ch = (i % gco) * 8;
+            uint4 in[8], out[8];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                dzT[(ch + 2 * k) * kWgRow + vv] = (uint16_t)(w4[k] & 0xFFFFu);
-                dzT[(ch + 2 * k + 1) * kWgRow + vv] = (uint16_t)(w4[k] >> 16);
+            for (int r = 0; r < 8; ++r) {
+                const long long v = s0 + vb + r;
+                in[r] = v < v1 ? *reinterpret_cast<const uint4*>(dz + v * Co + ch)
+                               : make_uint4(0, 0, 0, 0);
             }
+            transpose8x8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<uint4*>(dzT + (ch + c) * kWgRow + vb) = out[c];
         }
         __syncthreads();
-        // shifted x slices of the group's taps, 8 channels per item
-        for (int i = tid; i < ntap * kWgSlice * gci; i += blockDim.x) {
-            const int tl = i / (kWgSlice * gci);
-            const int r = i - tl * (kWgSlice * gci);
-            const int vv = r / gci, ch = (r - vv * gci) * 8;
+        // shifted x slices of the group's taps, the same 8 x 8 items
+        for (int i = tid; i < ntap * (kWgSlice / 8) * gci; i += blockDim.x) {
+            const int tl = i / ((kWgSlice / 8) * gci);
+            const int r8 = i - tl * ((kWgSlice / 8) * gci);
+            const int vb = (r8 / gci) * 8, ch = (r8 % gci) * 8;
             const int t = t0 + tl;
             const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dzz = t / 9 - 1;
-            const int xs = cx[vv] + dx, ys = cy[vv] + dy, zs = cz[vv] + dzz;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (xs >= 0 && ys >= 0 && zs >= 0 && xs < g.W && ys < g.H && zs < g.D) {
-                const long long sv = s0 + vv + dx + (long long)dy * g.W + dzz * plane;
-                val = *reinterpret_cast<const uint4*>(x + sv * Ci + ch);
-            }
-            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
-            uint16_t* row = xT + (tl * Ci + ch) * kWgRow + vv;
+            const long long shift = dx + (long long)dy * g.W + dzz * plane;
+            uint4 in[8], out[8];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                row[(2 * k) * kWgRow] = (uint16_t)(w4[k] & 0xFFFFu);
-                row[(2 * k + 1) * kWgRow] = (uint16_t)(w4[k] >> 16);
+            for (int r = 0; r < 8; ++r) {
+                const int vv = vb + r;
+                const int xs = cx[vv] + dx, ys = cy[vv] + dy, zs = cz[vv] + dzz;
+                in[r] = make_uint4(0, 0, 0, 0);
+                if (xs >= 0 && ys >= 0 && zs >= 0 && xs < g.W && ys < g.H && zs < g.D)
+                    in[r] = *reinterpret_cast<const uint4*>(x + (s0 + vv + shift) * Ci + ch);
             }
+            transpose8x8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<uint4*>(xT + (tl * Ci + ch + c) * kWgRow + vb) = out[c];
         }
         if (do_bias)
             for (int vv = 0; vv < kWgSlice; ++vv) bsum += bf2f(dzT[tid * kWgRow + vv]);
