@@ -873,6 +873,144 @@ __global__ void __launch_bounds__(256) k_wgrad_partial(const uint16_t* __restric
     if (do_bias) part_b[c * Co + tid] = bsum;
 }
 
+// ---------------------------------------------------------------------------
+// Weight and bias gradients of the layers with 16 or 32 outputs, by bricks:
+// the same partial sums part[c][t][co][ci] as k_wgrad_partial, with chunk c
+// a run of 4 x 4 x 16 voxel bricks (the bricks of k_conv_fwd_reg) and one
+// workgroup per (chunk, 16 input channels).  Per brick the dz values are
+// staged transposed in LDS ([co][voxel]) and the input brick with its halo
+// is staged once, transposed, in three copies shifted by dx = -1, 0, +1
+// ([dx][ci][6 x 6 rows][16]); every tap (dz, dy, dx) then reads aligned
+// 16-byte runs of 8 voxels from copy dx at rows shifted by (dz, dy), where
+// k_wgrad_partial stages a shifted copy per tap.  The dz fragments (A
+// operand) of the brick's 8 K-steps stay in registers for all taps; wave w
+// owns taps w, w + 4, ...  Transposes go through registers (8 x 8 bf16 per
+// thread).  Row pads keep the 16 rows a quarter-wave reads on distinct
+// banks.
+// ---------------------------------------------------------------------------
+constexpr int kWbXRow = 36 * 16 + 8;   // per input channel: 6 x 6 halo rows of 16
+constexpr int kWbDRow = 256 + 8;       // per output channel: the brick's voxels
+constexpr int kWbTaps = 7;             // taps per wave: w, w + 4, ..., < 27
+
+int wgrad_brick_lds_bytes(int Co) { return (3 * 16 * kWbXRow + Co * kWbDRow) * 2; }
+
+template <int NCO>
+__global__ void __launch_bounds__(256) k_wgrad_brick(const uint16_t* __restrict__ dz,
+                                                     const uint16_t* __restrict__ x, Geo g, int Ci,
+                                                     int bpc, int nbk, float* __restrict__ part,
+                                                     float* __restrict__ part_b) {
+    constexpr int Co = NCO * 16;
+    extern __shared__ __align__(16) uint16_t lds[];
+    uint16_t* xT = lds;                          // [3][16][kWbXRow]
+    uint16_t* dzT = lds + 3 * 16 * kWbXRow;      // [Co][kWbDRow]
+    __shared__ float bred[256];
+    const int c = blockIdx.x, ci0 = blockIdx.y * 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4;
+    const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
+    f32x4 acc[kWbTaps][NCO];
+#pragma unroll
+    for (int i = 0; i < kWbTaps; ++i)
+#pragma unroll
+        for (int j = 0; j < NCO; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    const int bk1 = min(nbk, (c + 1) * bpc);
+    for (int bk = c * bpc; bk < bk1; ++bk) {
+        int r = bk;
+        const int x0 = (r % nbx) * kRX;
+        r /= nbx;
+        const int y0 = (r % nby) * kRY;
+        r /= nby;
+        const int z0 = (r % nbz) * kRZ;
+        const int b = r / nbz;
+        __syncthreads();   // the previous brick's LDS reads are done
+        // dz: item = 8 voxels along x x 8 channels
+        for (int i = tid; i < 32 * (Co / 8); i += 256) {
+            const int vg = i / (Co / 8), ch = (i % (Co / 8)) * 8;
+            const int rr = vg >> 1, zz = z0 + (rr >> 2), yy = y0 + (rr & 3), xs = x0 + (vg & 1) * 8;
+            uint4 in[8], out[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                in[k] = make_uint4(0, 0, 0, 0);
+                if (zz < g.D && yy < g.H && xs + k < g.W)
+                    in[k] = *reinterpret_cast<const uint4*>(
+                        dz + ((((long long)b * g.D + zz) * g.H + yy) * g.W + xs + k) * Co + ch);
+            }
+            transpose8x8(in, out);
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc)
+                *reinterpret_cast<uint4*>(dzT + (ch + cc) * kWbDRow + vg * 8) = out[cc];
+        }
+        // input brick: copy d (dx = d - 1) x 36 halo rows x 2 halves x 2 channel groups
+        for (int i = tid; i < 3 * 36 * 4; i += 256) {
+            const int d = i / 144, rem = i % 144, row = rem >> 2, hh = (rem >> 1) & 1, cg = rem & 1;
+            const int zz = z0 - 1 + row / 6, yy = y0 - 1 + row % 6, xs = x0 + d - 1 + hh * 8;
+            const bool rin = zz >= 0 && yy >= 0 && zz < g.D && yy < g.H;
+            const long long rbase = (((long long)b * g.D + zz) * g.H + yy) * g.W;
+            uint4 in[8], out[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                in[k] = make_uint4(0, 0, 0, 0);
+                if (rin && xs + k >= 0 && xs + k < g.W)
+                    in[k] = *reinterpret_cast<const uint4*>(x + (rbase + xs + k) * Ci + ci0 + cg * 8);
+            }
+            transpose8x8(in, out);
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc)
+                *reinterpret_cast<uint4*>(xT + (d * 16 + cg * 8 + cc) * kWbXRow + row * 16 + hh * 8) =
+                    out[cc];
+        }
+        __syncthreads();
+        if (blockIdx.y == 0) {   // bias: thread (co = tid % Co) sums voxels tid / Co + k (256 / Co)
+#pragma unroll 4
+            for (int v = tid / Co; v < 256; v += 256 / Co) bsum += bf2f(dzT[(tid % Co) * kWbDRow + v]);
+        }
+        bf16x8 a[NCO][8];   // A[m = co][k = voxel] of the brick's 8 K-steps
+#pragma unroll
+        for (int j = 0; j < NCO; ++j)
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                a[j][s] = as_bf16x8(*reinterpret_cast<const uint4*>(
+                    dzT + (j * 16 + (lane & 15)) * kWbDRow + s * 32 + q * 8));
+#pragma unroll
+        for (int i = 0; i < kWbTaps; ++i) {
+            const int t = wave + 4 * i;
+            if (t >= 27) break;
+            const int tx = t % 3, ty = (t / 3) % 3, tz = t / 9;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                // voxels 32 s + 8 q + [0, 8): brick row 2 s + q / 2, x from 8 (q % 2)
+                const int rr = 2 * s + (q >> 1);
+                const int hrow = ((rr >> 2) + tz) * 6 + (rr & 3) + ty;
+                const bf16x8 bv = as_bf16x8(*reinterpret_cast<const uint4*>(
+                    xT + (tx * 16 + (lane & 15)) * kWbXRow + hrow * 16 + (q & 1) * 8));
+#pragma unroll
+                for (int j = 0; j < NCO; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j][s], bv, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kWbTaps; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= 27) break;
+        float* out = part + ((size_t)c * 27 + t) * Co * Ci;
+#pragma unroll
+        for (int j = 0; j < NCO; ++j)
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+                out[(size_t)(j * 16 + q * 4 + ii) * Ci + ci0 + (lane & 15)] = acc[i][j][ii];
+    }
+    if (blockIdx.y == 0) {   // fixed-order sum of the 256 / Co partial bias sums per channel
+        bred[tid] = bsum;
+        __syncthreads();
+        if (tid < Co) {
+            float sum = 0.0f;
+            for (int p = 0; p < 256 / Co; ++p) sum += bred[p * Co + tid];
+            part_b[(size_t)c * Co + tid] = sum;
+        }
+    }
+}
+
 // dW[co][t][ci] = sum_c part[c][t][co][ci] (fixed order: deterministic).
 // Deterministic column sums out[c] = sum_r part[r * ncol + c]: a workgroup
 // of 64 x 16 threads owns 64 consecutive columns; row-group g sums rows
@@ -1399,7 +1537,42 @@ long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk) {
 hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
                  float* part, float* dw, float* db, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
-    const long long nchunk = wgrad_chunks(dims, chunk);
+    long long nchunk = wgrad_chunks(dims, chunk);
+    if (Co == 16 || Co == 32) {   // by bricks, within the same partial-sum buffer
+        static const hipError_t attr = [] {
+            hipError_t e = hipFuncSetAttribute((const void*)k_wgrad_brick<1>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void*)k_wgrad_brick<2>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+            return e;
+        }();
+        if (attr != hipSuccess) return attr;
+        const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                              ((g.D + kRZ - 1) / kRZ) * g.B;
+        if (nbk > (1LL << 30)) return hipErrorInvalidValue;
+        const long long want = std::min(nchunk, nbk);
+        const int bpc = (int)((nbk + want - 1) / want);
+        const long long used = (nbk + bpc - 1) / bpc;   // <= nchunk
+        float* part_b = part + used * 27LL * Co * Ci;
+        const size_t lds = (size_t)wgrad_brick_lds_bytes(Co);
+        if (Co == 16)
+            hipLaunchKernelGGL(k_wgrad_brick<1>, dim3((unsigned)used, Ci / 16), dim3(256), lds, s,
+                               dz, x, g, Ci, bpc, (int)nbk, part, part_b);
+        else
+            hipLaunchKernelGGL(k_wgrad_brick<2>, dim3((unsigned)used, Ci / 16), dim3(256), lds, s,
+                               dz, x, g, Ci, bpc, (int)nbk, part, part_b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int n = 27 * Co * Ci;
+        hipLaunchKernelGGL(k_colsum, dim3((n + 63) / 64), dim3(1024), 0, s, part, (int)used, n, dw,
+                           (Ci << 16) | Co);
+        e = hipGetLastError();
+        if (e != hipSuccess || !db) return e;
+        hipLaunchKernelGGL(k_colsum, dim3((Co + 63) / 64), dim3(1024), 0, s, part_b, (int)used, Co,
+                           db, 0);
+        return hipGetLastError();
+    }
     const int tg = wgrad_taps_per_group(Ci, Co);
     const int groups = (27 + tg - 1) / tg;
     if (tg * (Co / 16) * (Ci / 16) > kWgWaves * kWgMaxTiles && tg > 1) return hipErrorInvalidValue;

@@ -91,7 +91,8 @@ def test_conv3d_fwd(shape, ci, co):
 @pytest.mark.parametrize("shape,ci,co", [((2, 6, 5, 7), 16, 16), ((1, 5, 4, 6), 48, 32),
                                          ((1, 3, 4, 5), 192, 64), ((1, 4, 4, 4), 128, 128),
                                          ((2, 8, 8, 9), 16, 48), ((1, 5, 9, 7), 32, 64),
-                                         ((1, 4, 6, 10), 64, 64)])
+                                         ((1, 4, 6, 10), 64, 64), ((2, 9, 10, 35), 16, 16),
+                                         ((1, 7, 9, 20), 96, 32), ((1, 5, 6, 17), 32, 16)])
 def test_conv3d_backward(shape, ci, co):
     import torch
     from paper_2511_03115_amd import nn
