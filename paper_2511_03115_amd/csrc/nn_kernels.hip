@@ -74,6 +74,9 @@ __device__ __forceinline__ long long shifted(const Geo& g, long long v, int t) {
 // fragment read from LDS feeds MT matrix-core ops and each gathered input
 // fragment feeds NT.  Voxel coordinates are decoded once per kernel and
 // the (tap, channel) position of each lane advances incrementally.
+// blockIdx.y selects the group of NT column tiles (output channels from
+// 16 NT blockIdx.y), so a small volume can spread its columns over several
+// workgroups.
 // ---------------------------------------------------------------------------
 constexpr int kSlab = 128;
 constexpr int kSlabRow = kSlab + 8;
@@ -87,6 +90,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
                                                       float* __restrict__ y32, int accumulate) {
     extern __shared__ __align__(16) uint16_t wl[];   // [NT*16][kSlabRow]
     const int lane = threadIdx.x & 63;
+    const int cob = blockIdx.y * NT * 16;             // first output channel of this block
     const long long nv = g.nvox();
     const long long base = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * MT);
     const int K = 27 * Ci;
@@ -117,8 +121,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
         for (int i = threadIdx.x; i < rows * (kSlab / 8); i += blockDim.x) {
             const int r = i / (kSlab / 8), c = (i - r * (kSlab / 8)) * 8;
             uint4 val = make_uint4(0, 0, 0, 0);
-            if (r < Co && k0 + c < K)
-                val = *reinterpret_cast<const uint4*>(w + (size_t)r * K + k0 + c);
+            if (cob + r < Co && k0 + c < K)
+                val = *reinterpret_cast<const uint4*>(w + (size_t)(cob + r) * K + k0 + c);
             *reinterpret_cast<uint4*>(wl + r * kSlabRow + c) = val;
         }
         __syncthreads();
@@ -157,7 +161,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
     }
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int co = j * 16 + (lane & 15);
+        const int co = cob + j * 16 + (lane & 15);
         if (co >= Co) continue;
         const float b = bias ? bias[co] : 0.0f;
 #pragma unroll
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
                 const long long v = base + m * 16 + (lane >> 4) * 4 + i;
                 if (v >= nv) continue;
                 float r = acc[m][j][i] + b;
-                if (act) r = r > 0.0f ? r : alpha * r;
+                if (act) r = lrelu(r, alpha);
                 if (y16) y16[v * Co + co] = f2bf(r);
                 if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + r : r;
             }
@@ -1452,6 +1456,14 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
 #define LAUNCH(NT, MT)                                                                        \
     hipLaunchKernelGGL((k_conv_fwd_lds<NT, MT>), dim3((unsigned)((nv + 64 * MT - 1) / (64 * MT))), \
                        dim3(256), lds, s, x, w, bias, g, Ci, Co, alpha, act, y16, y32, accumulate)
+    if (nt % 2 == 0 && nt > 2 && (nv + 127) / 128 < 512) {
+        // few voxels (the coarsest level): split the output channels over
+        // blockIdx.y so the launch still fills the device
+        hipLaunchKernelGGL((k_conv_fwd_lds<2, 2>), dim3((unsigned)((nv + 127) / 128), nt / 2),
+                           dim3(256), (size_t)2 * 16 * kSlabRow * sizeof(uint16_t), s, x, w, bias,
+                           g, Ci, Co, alpha, act, y16, y32, accumulate);
+        return hipGetLastError();
+    }
     switch (nt) {
         case 1: LAUNCH(1, 4); break;
         case 2: LAUNCH(2, 4); break;
