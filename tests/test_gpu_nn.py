@@ -113,6 +113,27 @@ def test_conv3d_backward(shape, ci, co):
         assert e <= 1e-5, name
 
 
+@pytest.mark.parametrize("shape,ci,co", [((1, 64, 64, 80), 16, 16), ((1, 32, 64, 80), 32, 32)])
+def test_wgrad_many_bricks_per_workgroup(shape, ci, co):
+    """Volumes with more bricks than split-K chunks (2 and 2 bricks per
+    workgroup here, 8 in training), so each workgroup sums several bricks."""
+    import torch
+    from paper_2511_03115_amd import nn
+    rng = np.random.default_rng(ci * 31 + co)
+    x = bf16_round(rng.normal(size=shape + (ci,)))
+    dz = bf16_round(rng.normal(size=shape + (co,)))
+    w = np.zeros((co, 27, ci))
+    log(f"wgrad shape={shape} ci={ci} co={co}")
+    _, dw_ref, db_ref = nno.conv3d_backward(dz, x, w)
+    dw = torch.zeros((co, 27, ci), dtype=torch.float32, device="cuda")
+    db = torch.zeros(co, dtype=torch.float32, device="cuda")
+    nn.conv3d_wgrad(to_bf16_dev(dz), to_bf16_dev(x), dw, db)
+    for name, got, ref in (("dw", dw, dw_ref), ("db", db, db_ref)):
+        e = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+        log(f"  {name} rel err {e:.3e}")
+        assert e <= 1e-5, name
+
+
 def _net_inputs(B, D, H, W, seed):
     rng = np.random.default_rng(seed)
     z = np.arange(D)[None, :, None, None]
