@@ -1184,15 +1184,21 @@ __global__ void k_slice_copy(const float* dy, Geo g, int C, int Cf, int c0, floa
 }
 
 // Network input from normalised maps: x[v] = {dose, rho, 0, ...} (Cx channels).
+// One voxel's input channels (Cx, a multiple of 8): dose, density, zeros,
+// in 16-byte stores.
+__device__ __forceinline__ void store_input_row(uint16_t* row, int Cx, float d, float r) {
+    uint4* q = reinterpret_cast<uint4*>(row);
+    q[0] = make_uint4((uint32_t)f2bf(d) | ((uint32_t)f2bf(r) << 16), 0u, 0u, 0u);
+    for (int c = 1; c < Cx / 8; ++c) q[c] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 __global__ void k_assemble_f32(const float* dose, const float* rho, long long nv, int Cx,
                                uint16_t* x, float* resid) {
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
          v += (long long)gridDim.x * blockDim.x) {
         const float d = dose[v];
         resid[v] = d;
-        x[v * Cx] = f2bf(d);
-        x[v * Cx + 1] = f2bf(rho ? rho[v] : 0.0f);
-        for (int c = 2; c < Cx; ++c) x[v * Cx + c] = 0;
+        store_input_row(x + v * Cx, Cx, d, rho ? rho[v] : 0.0f);
     }
 }
 
@@ -1214,9 +1220,7 @@ __global__ void k_assemble_grid(const double* dose, const float* rho, int nx, in
             r = rho ? rho[u] : 0.0f;
         }
         resid[v] = d;
-        x[v * Cx] = f2bf(d);
-        x[v * Cx + 1] = f2bf(r);
-        for (int c = 2; c < Cx; ++c) x[v * Cx + c] = 0;
+        store_input_row(x + v * Cx, Cx, d, r);
     }
 }
 
@@ -1285,8 +1289,17 @@ __global__ void k_head_fwd(const uint16_t* x, const float* w, const float* b, co
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
          v += (long long)gridDim.x * blockDim.x) {
         float s = bb + resid[v];
+        const uint4* xv = reinterpret_cast<const uint4*>(x + v * C);
 #pragma unroll
-        for (int c = 0; c < C; ++c) s += wr[c] * bf2f(x[v * C + c]);
+        for (int g8 = 0; g8 < C / 8; ++g8) {
+            const uint4 u = xv[g8];
+            const uint32_t h[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s += wr[g8 * 8 + 2 * k] * __uint_as_float(h[k] << 16);
+                s += wr[g8 * 8 + 2 * k + 1] * __uint_as_float(h[k] & 0xFFFF0000u);
+            }
+        }
         out[v] = s;
     }
 }
