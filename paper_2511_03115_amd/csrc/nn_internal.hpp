@@ -10,8 +10,11 @@ namespace sde {
 namespace nn {
 
 // 3x3x3 conv, zero padding 1; y = act(conv(x, w) + bias) to bf16 y16 and/or
-// FP32 y32 (y32 += result when accumulate).  Ci % 8 == 0, Co % 16 == 0 and
+// FP32 y32 (y32 += result when accumulate).  Ci % 16 == 0, Co % 16 == 0 and
 // Co / 16 in {1, 2, 3, 4, 6, 8, 12}.  bias may be null; act = LeakyReLU(alpha).
+// The kernel is chosen by the channel counts: registers-held weights for
+// Ci <= 48 with 16 or 32 outputs, 32-channel passes for Ci >= 64 with 32 or
+// 64, LDS weight slabs otherwise.
 hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
                     int Ci, int Co, float alpha, int act, uint16_t* y16, float* y32,
                     int accumulate, hipStream_t s);
@@ -27,7 +30,9 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
 // weight gradient: part needs wgrad_part_floats floats; dw [Co][27][Ci], db [Co]
 // (nullable).  Ci % 16 == 0, Co % 16 == 0, (Co/16)(Ci/16) <= 64, chunk from
-// wgrad_chunk_for (a multiple of 64).
+// wgrad_chunk_for (a multiple of 64).  16 or 32 outputs go by 4 x 4 x 16
+// bricks (at most as many split-K chunks as the chunk length gives), wider
+// layers by 64-voxel slices and tap groups.
 long long wgrad_chunks(const int* dims, int chunk);
 int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats);
 long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk);

@@ -187,7 +187,10 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
 // puts the 16 voxels a quarter-wave reads on distinct banks), so each input
 // voxel is read from memory about 2.3 times instead of 27.  Wave w owns
 // z-slice w of the brick as 4 row tiles of 16 voxels (two 8-voxel rows
-// each).  Weights are staged in slabs as in k_conv_fwd_lds.
+// each).  Weights are staged in slabs as in k_conv_fwd_lds.  The register
+// and channel-pass kernels below replace it where they apply; it remains
+// for the other few-channel shapes (e.g. 48 inputs with 32 outputs) and for
+// operands of 2 GiB or more, beyond their 32-bit buffer offsets.
 // ---------------------------------------------------------------------------
 constexpr int kHZ = 4, kHY = 8, kHX = 8;
 constexpr int kHVox = (kHZ + 2) * (kHY + 2) * (kHX + 2);
