@@ -546,29 +546,36 @@ int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, doubl
         !(dy_cm > 0) || !(dz_cm > 0) || !(dd > 0) || !(dta_cm > 0) || !(thresh >= 0) ||
         interp < 1 || interp > 50)
         return fail(SDE_E_INVALID, "invalid gamma arguments");
-    // integer offsets on the dta/interp lattice within dta, nearest first
-    std::vector<int4> off;
+    // offsets on the dta/interp lattice within dta, nearest first, in voxel
+    // units, with their squared length over dta^2
+    std::vector<int4> lat;
     const double st = dta_cm / interp;
     for (int a = -interp; a <= interp; ++a)
         for (int b = -interp; b <= interp; ++b)
             for (int c = -interp; c <= interp; ++c) {
                 const double ox = a * st, oy = b * st, oz = c * st;
                 if (ox * ox + oy * oy + oz * oz <= dta_cm * dta_cm * (1.0 + 1e-12))
-                    off.push_back(make_int4(a, b, c, a * a + b * b + c * c));
+                    lat.push_back(make_int4(a, b, c, a * a + b * b + c * c));
             }
-    std::stable_sort(off.begin(), off.end(),
+    std::stable_sort(lat.begin(), lat.end(),
                      [](const int4& u, const int4& v) { return u.w < v.w; });
+    std::vector<double4> off(lat.size());
+    for (size_t k = 0; k < lat.size(); ++k) {
+        const double ox = lat[k].x * st, oy = lat[k].y * st, oz = lat[k].z * st;
+        off[k] = make_double4(ox / dx_cm, oy / dy_cm, oz / dz_cm,
+                              (ox * ox + oy * oy + oz * oz) / (dta_cm * dta_cm));
+    }
     const size_t nvox = (size_t)nx * ny * nz;
     hipStream_t s = cur_stream();
-    int4* doff = nullptr;
+    double4* doff = nullptr;
     unsigned long long* buf = nullptr;
-    HIP_TRY(hipMalloc((void**)&doff, sizeof(int4) * off.size()));
+    HIP_TRY(hipMalloc((void**)&doff, sizeof(double4) * off.size()));
     HIP_TRY(hipMalloc((void**)&buf, sizeof(unsigned long long) * 3));
     int rc = SDE_OK;
     unsigned long long host[3] = {0, 0, 0};
     do {
         hipError_t e;
-        if ((e = hipMemcpyAsync(doff, off.data(), sizeof(int4) * off.size(),
+        if ((e = hipMemcpyAsync(doff, off.data(), sizeof(double4) * off.size(),
                                 hipMemcpyHostToDevice, s)) != hipSuccess ||
             (e = hipMemsetAsync(buf, 0, sizeof(unsigned long long) * 3, s)) != hipSuccess ||
             (e = launch_max(ref, nvox, buf + 2, s)) != hipSuccess ||
@@ -579,9 +586,8 @@ int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, doubl
         }
         double mx;
         std::memcpy(&mx, &host[2], sizeof mx);
-        const double dvec[3] = {dx_cm, dy_cm, dz_cm};
-        if ((e = launch_gamma(ref, ev, nx, ny, nz, doff, (int)off.size(), st, dd, dta_cm,
-                              thresh * mx, mx, local, dvec, buf, s)) != hipSuccess ||
+        if ((e = launch_gamma(ref, ev, nx, ny, nz, doff, (int)off.size(), dd, thresh * mx, mx,
+                              local, buf, s)) != hipSuccess ||
             (e = hipMemcpyAsync(host, buf, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
                                 s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess) {

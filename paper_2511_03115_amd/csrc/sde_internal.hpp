@@ -108,10 +108,10 @@ hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_by
 hipError_t launch_convert(unsigned long long* tally, int n_rep, const uint2* vox, size_t nvox,
                           double inv_scale, double voxel_cm3, double* dose,
                           unsigned long long* ledger, hipStream_t s);
+// gamma_kernels.hip: offsets[k] = (ox / dx, oy / dy, oz / dz, |o|^2 / dta^2)
 hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
-                        const int4* offsets, int n_off, double step, double dd, double dta,
-                        double thr_abs, double max_ref, int local, const double* d,
-                        unsigned long long* counts, hipStream_t s);
+                        const double4* offsets, int n_off, double dd, double thr_abs,
+                        double max_ref, int local, unsigned long long* counts, hipStream_t s);
 hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s);
 hipError_t transport_kernel_attributes(size_t lds_bytes);
 

@@ -778,74 +778,6 @@ __global__ void __launch_bounds__(256) k_convert(unsigned long long* tally, int 
     }
 }
 
-// Gamma index, one thread per reference voxel.  Offsets are integer lattice
-// vectors (a, b, c, a^2+b^2+c^2) of spacing step = dta/interp within dta,
-// sorted by length so a passing voxel stops early.  counts[0] evaluated,
-// counts[1] passed.
-__global__ void __launch_bounds__(256) k_gamma(const double* ref, const double* ev, int nx,
-                                               int ny, int nz, const int4* off, int n_off,
-                                               double step, double dd, double dta, double thr_abs,
-                                               double max_ref, int local, double dx, double dy,
-                                               double dz, unsigned long long* counts) {
-    const size_t nvox = (size_t)nx * ny * nz;
-    unsigned long long ne = 0, np = 0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double dr = ref[i];
-        if (!(dr >= thr_abs) || dr <= 0.0) continue;
-        ne++;
-        const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((size_t)nx * ny));
-        const double norm = dd * (local ? dr : max_ref);
-        bool pass = false;
-        for (int k = 0; k < n_off && !pass; ++k) {
-            const int4 o = off[k];
-            const double ox = o.x * step, oy = o.y * step, oz = o.z * step;
-            const double fx = ix + ox / dx, fy = iy + oy / dy, fz = iz + oz / dz;
-            if (fx < 0.0 || fy < 0.0 || fz < 0.0 || fx > nx - 1 || fy > ny - 1 || fz > nz - 1)
-                continue;
-            int x0 = (int)floor(fx), y0 = (int)floor(fy), z0 = (int)floor(fz);
-            if (x0 > nx - 2) x0 = nx > 1 ? nx - 2 : 0;
-            if (y0 > ny - 2) y0 = ny > 1 ? ny - 2 : 0;
-            if (z0 > nz - 2) z0 = nz > 1 ? nz - 2 : 0;
-            const double tx = fx - x0, ty = fy - y0, tz = fz - z0;
-            const int x1 = nx > 1 ? x0 + 1 : x0, y1 = ny > 1 ? y0 + 1 : y0, z1 = nz > 1 ? z0 + 1 : z0;
-#define EV(a, b, c) ev[((size_t)(c) * ny + (b)) * nx + (a)]
-            const double c00 = EV(x0, y0, z0) * (1 - tx) + EV(x1, y0, z0) * tx;
-            const double c10 = EV(x0, y1, z0) * (1 - tx) + EV(x1, y1, z0) * tx;
-            const double c01 = EV(x0, y0, z1) * (1 - tx) + EV(x1, y0, z1) * tx;
-            const double c11 = EV(x0, y1, z1) * (1 - tx) + EV(x1, y1, z1) * tx;
-#undef EV
-            const double c0 = c00 * (1 - ty) + c10 * ty, c1 = c01 * (1 - ty) + c11 * ty;
-            const double de = c0 * (1 - tz) + c1 * tz;
-            const double r2 = ox * ox + oy * oy + oz * oz;
-            const double g2 = r2 / (dta * dta) + (de - dr) * (de - dr) / (norm * norm);
-            if (g2 <= 1.0) pass = true;
-        }
-        np += pass ? 1ull : 0ull;
-    }
-    ne = wave_sum(ne);
-    np = wave_sum(np);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&counts[0], ne);
-        atomicAdd(&counts[1], np);
-    }
-}
-
-// Maximum of a non-negative double array via its bit pattern.
-__global__ void k_max(const double* a, size_t n, unsigned long long* out) {
-    double m = 0.0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        m = fmax(m, a[i]);
-    unsigned long long b = (unsigned long long)__double_as_longlong(m);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long c = __shfl_xor(b, o);
-        b = c > b ? c : b;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(out, b);
-}
-
 int grid_for(size_t n, int block) {
     size_t g = (n + block - 1) / block;
     if (g > 65536) g = 65536;
@@ -895,24 +827,6 @@ hipError_t launch_convert(unsigned long long* tally, int n_rep, const uint2* vox
     const int grid = std::min(grid_for(nvox, 256), 2048);
     hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, s, tally, n_rep, vox, nvox,
                        inv_scale, voxel_cm3, dose, ledger);
-    return hipGetLastError();
-}
-
-hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
-                        const int4* offsets, int n_off, double step, double dd, double dta,
-                        double thr_abs, double max_ref, int local, const double* d,
-                        unsigned long long* counts, hipStream_t s) {
-    const size_t nvox = (size_t)nx * ny * nz;
-    hipLaunchKernelGGL(k_gamma, dim3(grid_for(nvox, 256)), dim3(256), 0, s, ref, ev, nx, ny, nz,
-                       offsets, n_off, step, dd, dta, thr_abs, max_ref, local, d[0], d[1], d[2],
-                       counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s) {
-    // a grid-stride pass over few blocks: one same-address atomic per wave
-    const int grid = grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024;
-    hipLaunchKernelGGL(k_max, dim3(grid), dim3(256), 0, s, a, n, out_bits);
     return hipGetLastError();
 }
 
