@@ -78,9 +78,28 @@ def cpu_baseline(wl, target_s: float) -> dict:
     oracle.transport(wl.phantom, wl.spots, wl.params, nuc, seed=wl.seed, h_begin=0, h_end=n2,
                      n_threads=threads)
     dt2 = time.perf_counter() - t0
+    # one thread, as the paper times its own implementation: a smaller prefix
+    n1 = int(min(n2, max(1000, 3.0 / (per_h * threads))))
+    t0 = time.perf_counter()
+    oracle.transport(wl.phantom, wl.spots, wl.params, nuc, seed=wl.seed, h_begin=0, h_end=n1,
+                     n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n2 / dt2, "unit": "histories/s", "cores": threads, "kind": "oracle",
             "sample": f"histories 0..{n2} of the same workload (FP64, {threads} threads, "
-                      f"{dt2:.1f} s)"}
+                      f"{dt2:.1f} s)",
+            "value_1thread": n1 / dt1,
+            "sample_1thread": f"histories 0..{n1} (FP64, 1 thread, {dt1:.1f} s)",
+            "cpu": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def measured_traffic(launch, histories):
