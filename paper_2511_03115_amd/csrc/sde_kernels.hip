@@ -115,8 +115,10 @@ __device__ __forceinline__ void voxel3(const KParams& P, float x, float y, float
     iz = min((int)((z - P.lo[2]) * P.inv_d[2]), P.nz - 1);
 }
 
+// Fixed-point energy, round to nearest even; e >= 0 always (deposits,
+// energies), so the conversion is the unsigned one, without a sign fix-up.
 __device__ __forceinline__ long long fixp(float e, float wsc) {
-    return (long long)rintf(e * wsc);
+    return (long long)(unsigned long long)rintf(e * wsc);
 }
 
 // Per-lane deposit accumulator: consecutive deposits into the same voxel are
