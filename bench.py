@@ -74,9 +74,11 @@ def cpu_baseline(wl, target_s: float) -> dict:
     per_h = max((times[1] - times[0]) / 18000.0, 1e-7)
     fixed = max(times[0] - 2000 * per_h, 0.0)
     n2 = int(min(wl.n_histories, max(20000, (target_s - fixed) / per_h)))
+    # the first n2 histories as a workload of their own (same Philox words,
+    # weights per n2), so the GPU can run exactly the same sample
+    spots2 = workloads.with_histories(wl.spots, n2)
     t0 = time.perf_counter()
-    oracle.transport(wl.phantom, wl.spots, wl.params, nuc, seed=wl.seed, h_begin=0, h_end=n2,
-                     n_threads=threads)
+    r2 = oracle.transport(wl.phantom, spots2, wl.params, nuc, seed=wl.seed, n_threads=threads)
     dt2 = time.perf_counter() - t0
     # one thread, as the paper times its own implementation: a smaller prefix
     n1 = int(min(n2, max(1000, 3.0 / (per_h * threads))))
@@ -89,7 +91,32 @@ def cpu_baseline(wl, target_s: float) -> dict:
                       f"{dt2:.1f} s)",
             "value_1thread": n1 / dt1,
             "sample_1thread": f"histories 0..{n1} (FP64, 1 thread, {dt1:.1f} s)",
-            "cpu": cpu_model()}
+            "cpu": cpu_model(),
+            "parity": oracle_parity(wl, spots2, n2, oracle.dose(r2.edep, wl.phantom))}
+
+
+def oracle_parity(wl, spots, n, d_ref) -> dict:
+    """The GPU path on the oracle's sample (the same n histories): per-voxel
+    difference over the maximum, gamma 1 %/0.5 mm (local, 1 % threshold) and
+    the R80 difference, the workloads' parity measures."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    from paper_2511_03115_amd import sde
+    sde.init_materials(wl.phantom.materials, wl.params,
+                       workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
+    dph = sde.DevicePhantom.from_host(wl.phantom)
+    dose = torch.zeros(wl.phantom.material_id.shape, dtype=torch.float64, device="cuda")
+    sde.transport(spots, dph, wl.seed, dose_out=dose)
+    torch.cuda.synchronize()
+    d = dose.cpu().numpy()
+    g, _, _ = sde.gamma(torch.from_numpy(np.ascontiguousarray(d_ref)).cuda(), dose,
+                        wl.phantom.voxel_cm, 0.01, 0.05, 0.01, 10, True)
+    dz = wl.phantom.voxel_cm[2]
+    return {"histories": int(n), "max_rel_diff": float(np.abs(d - d_ref).max() / d_ref.max()),
+            "gamma_1pct_05mm": float(g),
+            "dr80_mm": float(abs(oracle.range_rx(d_ref, dz) - oracle.range_rx(d, dz)) * 10)}
 
 
 def cpu_model() -> str:
