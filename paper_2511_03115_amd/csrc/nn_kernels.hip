@@ -362,8 +362,6 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     constexpr int NCH = (KS + CH - 1) / CH;
     constexpr int ROW = CI + 8;
     constexpr int GV = CI / 8;
-    constexpr int U = kRVox * GV;
-    constexpr int NU = (U + 255) / 256;
     extern __shared__ __align__(16) uint16_t hx[];   // [kRVox][ROW]
     const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
     int bid = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -393,37 +391,75 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
                 dst[s2][j] = as_bf16x8(ld16(wr, ((j * 16 + (lane & 15)) * K + k) * 2, kin));
             }
     };
-    uint4 st[NU];
+    // Staging: a thread owns one 16-byte column of the halo rows (voxel hxx
+    // of the row, channel group c) and walks the 6 x 6 rows RP at a time, so
+    // the x part of its index and bounds test is worked out once.
+    constexpr int RU = (kRX + 2) * GV;           // 16-byte units per halo row
+    constexpr int NROW = (kRZ + 2) * (kRY + 2);  // halo rows
+    constexpr int RP = 256 / RU;                 // rows per pass
+    constexpr int NUR = (NROW + RP - 1) / RP;
+    const int col = threadIdx.x % RU, r0 = threadIdx.x / RU;
+    const int hxx = col / GV, c = (col - hxx * GV) * 8;
+    const int xx = x0 - 1 + hxx;
+    const bool xin = r0 < RP && xx >= 0 && xx < g.W;
+    uint4 st[NUR];
+    constexpr int kMaxR0 = 255 / RU;   // largest r0, idle threads included
+    const bool interior = CS == CI && x0 >= 1 && x0 + kRX < g.W && y0 >= 1 && y0 + kRY < g.H &&
+                          z0 >= 1 && z0 + kRZ < g.D;   // uniform over the workgroup
+    if (interior) {
+        // the whole halo is inside the volume: no bounds tests, and the offset
+        // advances by RP rows per pass (DZ slices and DY rows, wrapping at 6)
+        constexpr int DZ = RP / (kRY + 2), DY = RP % (kRY + 2);
+        const int rowb = g.W * (CS * 2), plane = g.H * rowb;
+        int hyy = r0 % (kRY + 2);
+        int off = (((b * g.D + z0 - 1 + r0 / (kRY + 2)) * g.H + y0 - 1 + hyy) * g.W + xx) *
+                      (CS * 2) + c * 2;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int i = threadIdx.x + u * 256;
-        const int hv = i / GV, c = (i - hv * GV) * 8;
-        const int hxx = hv % (kRX + 2), hyy = (hv / (kRX + 2)) % (kRY + 2),
-                  hzz = hv / ((kRX + 2) * (kRY + 2));
-        const int xx = x0 - 1 + hxx, yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
-        const bool in = (U % 256 == 0 || u < NU - 1 || i < U) && xx >= 0 && yy >= 0 && zz >= 0 &&
-                        xx < g.W && yy < g.H && zz < g.D;
-        if (CS == CI) {
-            st[u] = ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2, in);
-        } else {
-            // skip channels from x, the rest from the parent voxel of xl
-            const uint4 vs =
-                ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2, in && c < CS);
-            const uint4 vl = ld16(xlr,
-                                  (((b * (g.D >> 1) + (zz >> 1)) * (g.H >> 1) + (yy >> 1)) *
-                                       (g.W >> 1) + (xx >> 1)) * ((CI - CS) * 2) + (c - CS) * 2,
-                                  in && c >= CS);
-            st[u] = make_uint4(vs.x | vl.x, vs.y | vl.y, vs.z | vl.z, vs.w | vl.w);
+        for (int u = 0; u < NUR; ++u) {
+            if (kMaxR0 + RP * u < NROW) {
+                st[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+            } else {
+                const int row = r0 + RP * u;
+                st[u] = ld16(xr, off, r0 < RP && row < NROW);
+            }
+            off += DZ * plane + DY * rowb;
+            hyy += DY;
+            if (hyy >= kRY + 2) {
+                hyy -= kRY + 2;
+                off += plane - (kRY + 2) * rowb;
+            }
+        }
+    } else {
+        // channels [0, CS) from x, [CS, CI) from the parent voxel in xl: each
+        // thread reads one source (c is fixed per thread)
+        const bool sk = CS == CI || c < CS;
+        const int sh = sk ? 0 : 1;
+        const int Dd = g.D >> sh, Hd = g.H >> sh, Wd = g.W >> sh;
+        const uint16_t* src = sk ? x + c : xl + (c - CS);
+        const int cstride = sk ? CS : CI - CS;
+#pragma unroll
+        for (int u = 0; u < NUR; ++u) {
+            const int row = r0 + RP * u;
+            const int hzz = row / (kRY + 2), hyy = row - hzz * (kRY + 2);
+            const int yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
+            const bool in = xin && (NROW % RP == 0 || u < NUR - 1 || row < NROW) && yy >= 0 &&
+                            zz >= 0 && yy < g.H && zz < g.D;
+            if (CS == CI) {
+                st[u] = ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2, in);
+            } else {
+                const long long vox =
+                    (((long long)b * Dd + (zz >> sh)) * Hd + (yy >> sh)) * Wd + (xx >> sh);
+                st[u] = in ? *reinterpret_cast<const uint4*>(src + (in ? vox : 0) * cstride)
+                           : make_uint4(0, 0, 0, 0);
+            }
         }
     }
     load_chunk(wb[0], 0);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int i = threadIdx.x + u * 256;
-        if (i < U) {
-            const int hv = i / GV, c = (i - hv * GV) * 8;
-            *reinterpret_cast<uint4*>(hx + hv * ROW + c) = st[u];
-        }
+    for (int u = 0; u < NUR; ++u) {
+        const int row = r0 + RP * u;
+        if (r0 < RP && (NROW % RP == 0 || u < NUR - 1 || row < NROW))
+            *reinterpret_cast<uint4*>(hx + (row * (kRX + 2) + hxx) * ROW + c) = st[u];
     }
     __syncthreads();
     // wave w owns z-slice w; row tile m is row m (16 voxels along x)

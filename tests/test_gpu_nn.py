@@ -58,7 +58,11 @@ def he_params(levels, c0, cin, seed, head_scale=0.1):
                                          ((1, 10, 8, 19), 32, 32), ((1, 5, 12, 9), 48, 16),
                                          ((1, 6, 9, 10), 16, 32), ((2, 5, 7, 9), 32, 16),
                                          ((1, 6, 9, 10), 96, 32), ((2, 5, 8, 11), 64, 64),
-                                         ((1, 4, 10, 9), 192, 64)])
+                                         ((1, 4, 10, 9), 192, 64),
+                                         # volumes with interior bricks (halo inside)
+                                         ((1, 12, 12, 50), 16, 16), ((1, 12, 12, 50), 48, 16),
+                                         ((1, 10, 12, 40), 32, 32), ((1, 10, 12, 40), 16, 32),
+                                         ((1, 10, 12, 40), 32, 16)])
 def test_conv3d_fwd(shape, ci, co):
     import torch
     from paper_2511_03115_amd import nn
