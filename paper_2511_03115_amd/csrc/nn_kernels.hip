@@ -53,15 +53,6 @@ struct Geo {
     __host__ __device__ __forceinline__ long long nvox() const { return (long long)B * D * H * W; }
 };
 
-// Voxel v shifted by tap t (t = (dz+1)*9 + (dy+1)*3 + (dx+1)) or -1 outside.
-__device__ __forceinline__ long long shifted(const Geo& g, long long v, int t) {
-    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-    const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)((v / ((long long)g.W * g.H)) % g.D);
-    const int xs = x + dx, ys = y + dy, zs = z + dz;
-    if (xs < 0 || ys < 0 || zs < 0 || xs >= g.W || ys >= g.H || zs >= g.D) return -1;
-    return v + dx + (long long)dy * g.W + (long long)dz * g.W * g.H;
-}
-
 // ---------------------------------------------------------------------------
 // conv3d 3x3x3, zero padding 1, stride 1: y[v][co] = act(bias[co] +
 //   sum_{t, ci} x[shift(v, t)][ci] w[co][t][ci]), as an implicit GEMM with
@@ -376,9 +367,9 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     // Loads go through buffer resources with 32-bit offsets (the host keeps
     // every operand below 2 GiB); a load that must give zeros (outside the
     // volume, past the last K step) reads offset 0 and is replaced by zero,
-    // so no load sits behind a branch.
+    // so no load sits behind a branch.  (The decoder concatenation, whose
+    // two sources differ from lane to lane, reads through plain pointers.)
     const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CS);
-    const __amdgpu_buffer_rsrc_t xlr = rsrc16(xl, CS == CI ? 0 : g.nvox() / 8 * (CI - CS));
     const __amdgpu_buffer_rsrc_t wr = rsrc16(w, (long long)NT * 16 * K);
     bf16x8 wb[2][CH][NT];   // B[k][n] = w[n][k], two chunks of K steps (Co = 16 NT)
     auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int c) {

@@ -24,7 +24,6 @@ constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelas
                    kEor = 32u, kAllPhysics = 63u;
 
 constexpr float kMpF = (float)kMp;
-constexpr float kAlphaF = (float)kAlpha;
 constexpr float kLn2 = 0.69314718055994530942f;
 
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
@@ -506,7 +505,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // ---------------- finish pending jumps, a batch at a time ----------------
         const unsigned long long pend = __ballot(state == kJump);
         const unsigned long long stepping = __ballot(state == kStep);
-        if (pend && (__popcll(pend) >= P.jump_batch || stepping == 0ull)) {
+        if (pend && ((int)__popcll(pend) >= P.jump_batch || stepping == 0ull)) {
             if (state == kJump) {
                 const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), nj, 1u, k0, k1);
                 float u_loss, jc, js, jcp, jsp;
