@@ -26,7 +26,9 @@
  *  - Results are a pure function of (materials, params, nuclear tables,
  *    beam, phantom, history count, seed): bit-identical across runs and
  *    launch configurations (integer tally, counter-based RNG keyed by
- *    (seed, history, step)).
+ *    (seed, history, step)).  History h is the h-th history in the order
+ *    of the beam's spots (spot i owns the n_i indices after those of spots
+ *    0..i-1), whatever order the kernel runs them in.
  */
 #ifndef SDE_H
 #define SDE_H

@@ -213,14 +213,27 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     p->scale = scale;
     p->voxel_cm3 = ph->dx_cm * ph->dy_cm * ph->dz_cm;
 
+    // The kernel claims the spots' histories highest energy first (the
+    // longest histories), so the last histories of a launch are short ones
+    // and the lanes run out of work together.  Every history keeps its index
+    // in the caller's spot order (h0 + offset), which keys its random
+    // numbers: the result does not depend on this order.
+    std::vector<unsigned long long> h0(ns + 1, 0);
+    for (int i = 0; i < ns; ++i) h0[i + 1] = h0[i] + counts[i];
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return beam->spots[a].E_MeV > beam->spots[b].E_MeV;
+    });
     std::vector<SpotDev> sd(ns);
-    std::vector<unsigned long long> pre(ns + 1, 0);
-    for (int i = 0; i < ns; ++i) {
+    std::vector<unsigned long long> pre(ns + 1, 0);   // prefix in claim order
+    for (int k = 0; k < ns; ++k) {
+        const int i = order[k];
         const sde_spot& s = beam->spots[i];
-        sd[i] = SpotDev{(float)s.E_MeV, (float)s.sigmaE_rel, (float)s.x_cm, (float)s.y_cm,
+        sd[k] = SpotDev{(float)s.E_MeV, (float)s.sigmaE_rel, (float)s.x_cm, (float)s.y_cm,
                         (float)s.sigma_xy_cm,
-                        counts[i] ? (float)(s.weight / (double)counts[i] * scale) : 0.f, 0.f, 0.f};
-        pre[i + 1] = pre[i] + counts[i];
+                        counts[i] ? (float)(s.weight / (double)counts[i] * scale) : 0.f, h0[i]};
+        pre[k + 1] = pre[k] + counts[i];
     }
     auto bail = [&](int rc) {
         plan_free(p);

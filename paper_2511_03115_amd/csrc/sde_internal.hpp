@@ -45,7 +45,8 @@ struct MatDev {
 
 // Per-spot source data on the device.  wscale = weight / n * 2^k.
 struct SpotDev {
-    float E, sigmaE, x, y, sxy, wscale, pad0, pad1;
+    float E, sigmaE, x, y, sxy, wscale;
+    unsigned long long h0;   // index of the spot's first history in the caller's order
 };
 
 // Everything the transport kernel reads; passed by value.
@@ -79,7 +80,7 @@ struct KParams {
     float lo[3], hi[3], inv_d[3], pad2;
     // beam
     const SpotDev* spots;
-    const unsigned long long* prefix;   // [n_spots + 1] cumulative history counts
+    const unsigned long long* prefix;   // [n_spots + 1] cumulative history counts, claim order
     int n_spots, pad3;
     unsigned long long n_hist;
     unsigned long long seed;

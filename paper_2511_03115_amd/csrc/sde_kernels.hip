@@ -445,9 +445,10 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 const unsigned long long rank = __popcll(dead & ((1ull << lane) - 1ull));
                 const unsigned long long hh = rank < avail ? q_next + rank : base + (rank - avail);
                 if (hh < P.n_hist) {
-                    // Source: spot by cumulative count; Box-Muller pairs from
-                    // block (h, 2^32-1, 0): (w0, w1) lateral, (w2, w3) energy.
-                    h = hh;
+                    // Source: spot by cumulative count in claim order; the
+                    // history's index h is its index in the caller's spot
+                    // order.  Box-Muller pairs from block (h, 2^32-1, 0):
+                    // (w0, w1) lateral, (w2, w3) energy.
                     n = 0;
                     int lo = 0, hi = P.n_spots - 1;
                     while (lo < hi) {
@@ -455,6 +456,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                         if (P.prefix[mid] <= hh) lo = mid; else hi = mid - 1;
                     }
                     const SpotDev sp = P.spots[lo];
+                    h = sp.h0 + (hh - P.prefix[lo]);
                     const uint4 w = philox((uint32_t)h, (uint32_t)(h >> 32), 0xFFFFFFFFu, 0u, k0, k1);
                     const float rr = fsqrt(-2.0f * flog(u_hi(w.x)));
                     const float a1 = u_hi(w.y);
