@@ -34,6 +34,7 @@ MAX_MAT = 16
 # physics switches
 LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, EOR = 1, 2, 4, 8, 16, 32
 ALL = 63
+SBM = 64   # small-angle diffusion by the spherical Brownian motion law
 
 # ledger slots and record fields (mirror the enums of sde_oracle.c)
 L_DEP, L_ESC, L_NUC, L_E0, L_TRUNC, L_STEPS, L_HIST, L_JUMPS = range(8)
@@ -119,6 +120,15 @@ def lib():
         L.or_cm_to_lab.restype = d
         L.or_turn.argtypes = [P(d), d, d, d]
         L.or_turn.restype = None
+        for f in ("or_sbm_lineage_mean", "or_sbm_lineage_var"):
+            getattr(L, f).argtypes = [d]
+            getattr(L, f).restype = d
+        L.or_sbm_upper_tail.argtypes = [d, d]
+        L.or_sbm_upper_tail.restype = d
+        L.or_sbm_t_switch.argtypes = []
+        L.or_sbm_t_switch.restype = d
+        L.or_sbm_polar_n.argtypes = [C.c_size_t, d, P(d), P(d), P(d), P(d)]
+        L.or_sbm_polar_n.restype = None
         L.or_channel_total_rate.argtypes = [P(Material), P(Nuclear), P(Params), d, d]
         L.or_channel_total_rate.restype = d
         L.or_rng_block.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -310,6 +320,36 @@ def csda_range_g(m, E: float, e_min: float = 0.05) -> float:
 def ld_sigma(m, rho: float, E: float, z: float = 0.05, F: float = 0.98) -> float:
     s = material_struct(m)
     return lib().or_ld_sigma(C.byref(s), float(rho), float(E), float(z), float(F))
+
+
+def sbm_lineage_mean(t: float) -> float:
+    return lib().or_sbm_lineage_mean(float(t))
+
+
+def sbm_lineage_var(t: float) -> float:
+    return lib().or_sbm_lineage_var(float(t))
+
+
+def sbm_upper_tail(t: float, c: float) -> float:
+    """P(cos(angle) > c) of spherical Brownian motion on S^2 at time t."""
+    return lib().or_sbm_upper_tail(float(t), float(c))
+
+
+def sbm_t_switch() -> float:
+    return lib().or_sbm_t_switch()
+
+
+def sbm_polar(t: float, z: np.ndarray, u: np.ndarray):
+    """(cos, sin) of the polar angle of the spherical Brownian motion step at
+    time t for normal deviates z and uniforms u (arrays of one length)."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert z.shape == u.shape
+    ct = np.empty_like(z)
+    st = np.empty_like(z)
+    d = C.c_double
+    lib().or_sbm_polar_n(z.size, float(t), _ptr(z, d), _ptr(u, d), _ptr(ct, d), _ptr(st, d))
+    return ct, st
 
 
 def philox4x32(ctr: Sequence[int], key: Sequence[int]) -> List[int]:

@@ -16,8 +16,11 @@
  * Units: MeV, cm, g/cm^3, barn (1e-24 cm^2), radians.
  *
  * Parity unpinned (no independent value to compare with): the placeholder
- * nuclear inelastic data, and the geodesic Gaussian step used in place of
- * the exact spherical Brownian motion sampler (see sbm_step).
+ * nuclear inelastic data.  The small-angle diffusion has two samplers: the
+ * spherical Brownian motion law (switch OR_SBM, see sbm_polar; pinned by
+ * its heat-kernel moments) and the geodesic Gaussian step (geodesic_step),
+ * which approximates it to O(t) in the angle and is pinned by the thin-slab
+ * laws only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -38,6 +41,7 @@
 #define OR_ELASTIC 8
 #define OR_INELASTIC 16
 #define OR_EOR 32
+#define OR_SBM 64   /* small-angle diffusion by the spherical Brownian motion law */
 
 /* CODATA 2018 values (the paper does not print them) */
 static const double MASS_P = 938.27208816;     /* proton rest energy, MeV */
@@ -406,17 +410,98 @@ static void turn(double d[3], double ct, double st, double phi) {
     d[0] = r[0]; d[1] = r[1]; d[2] = r[2];
 }
 
-/* Aggregated small-angle scattering over one step.  The paper samples the
+/* Aggregated small-angle scattering over one step (section 2.2.2): the
  * time-Delta increment of spherical Brownian motion with volatility
- * m = sigma(E)/sqrt(z) by Algorithm 1 of Mijatovic et al., which is not
- * reproduced in the paper.  Substitute: the geodesic (exponential-map)
- * Gaussian step, whose tangent displacement has per-axis variance
- * m^2 Delta = sigma^2 Delta/z, i.e. polar angle sigma sqrt(-2 ln U1)
- * (Rayleigh) and uniform azimuth 2 pi U2.  Parity unpinned against the
- * exact sampler. */
-static void sbm_step(double d[3], double sigma_step, double U1, double U2) {
+ * m = sigma(E)/sqrt(z), i.e. run for time t = m^2 Delta = sigma^2 Delta/z
+ * under the generator (1/2) Laplace-Beltrami on S^2, so that for small t the
+ * tangent displacement has per-axis variance t.
+ *
+ * Geodesic (exponential-map) Gaussian step: polar angle sqrt(t) sqrt(-2 ln U1)
+ * (Rayleigh), uniform azimuth 2 pi U2.  Its law differs from the spherical
+ * Brownian motion at O(t) in the angle (E[cos] = 1 - t + t^2/3 - ... against
+ * e^{-t}). */
+static void geodesic_step(double d[3], double sigma_step, double U1, double U2) {
     double th = sigma_step * sqrt(-2.0 * log(U1));
     turn(d, cos(th), sin(th), TWO_PI * U2);
+}
+
+/* Spherical Brownian motion on S^2 (d = 3) at time t from the north pole,
+ * the sampler the paper cites (Mijatovic, Mramor and Uribe Bravo 2020,
+ * Algorithm 1), in two regimes split at SBM_T_SWITCH.
+ *
+ * Algorithm 1: M = A(t), the number of lineages left at time t of Kingman's
+ * coalescent with mutation parameter theta = d - 1 = 2 started from
+ * infinitely many (each of k lineages is lost at rate k (k + theta - 1) / 2);
+ * X ~ Beta((d-1)/2, (d-1)/2 + M) = Beta(1, 1 + M); cos(angle) = 1 - 2 X,
+ * azimuth uniform.  For small t the count M is drawn from Griffiths' (1984)
+ * normal law with mean sbm_lineage_mean(t) and variance sbm_lineage_var(t),
+ * rounded to the nearest integer and floored at 0, which is how the cited
+ * method treats small t: its exact series for P(A(t) = m) cancels
+ * catastrophically there (terms ~1e11 at t = 0.05 for values ~0.1).
+ *
+ * For t >= SBM_T_SWITCH, where that series is still out of reach in double
+ * precision but the heat kernel's Legendre series converges within
+ * SBM_LEGENDRE_L terms, cos(angle) is drawn exactly by inverting the
+ * distribution function of that series (sbm_upper_tail) by bisection.
+ *
+ * Random inputs: z a standard normal (the lineage count, small t only), u a
+ * uniform on (0, 1), oriented so that u -> 1 gives the angle -> 0 in both
+ * regimes.  The azimuth is the caller's. */
+#define SBM_T_SWITCH 0.02
+#define SBM_LEGENDRE_L 64
+
+/* Griffiths' mean of A(t): 2 eta / t with beta = (theta - 1) t / 2 = t / 2 and
+ * eta = beta / (e^beta - 1), i.e. 1 / expm1(t / 2). */
+static double sbm_lineage_mean(double t) { return 1.0 / expm1(0.5 * t); }
+
+/* Griffiths' variance of A(t): (2 eta / t) (eta + beta)^2
+ * (1 + eta / (eta + beta) - 2 eta) / beta^2.  The bracket is ~beta^2 / 3 and
+ * cancels in double precision for small t, so below t = 1e-2 its Taylor
+ * series (derived from the same expression) is used: 2 / (3 t) times
+ * (1 - 7 t^2 / 240 + 41 t^4 / 80640), truncation O(t^6). */
+static double sbm_lineage_var(double t) {
+    if (t < 1e-2) {
+        double t2 = t * t;
+        return 2.0 / (3.0 * t) * (1.0 - 7.0 * t2 / 240.0 + 41.0 * t2 * t2 / 80640.0);
+    }
+    double beta = 0.5 * t, eta = beta / expm1(beta);
+    return (2.0 * eta / t) * (eta + beta) * (eta + beta) *
+           (1.0 + eta / (eta + beta) - 2.0 * eta) / (beta * beta);
+}
+
+/* P(cos(angle) > c) for spherical Brownian motion at time t: the heat kernel
+ * on S^2 is sum_l (2l+1)/2 e^{-l(l+1)t/2} P_l(c) in c, and the integral of
+ * P_l from c to 1 is (P_{l-1}(c) - P_{l+1}(c)) / (2l+1) for l >= 1. */
+static double sbm_upper_tail(double t, double c) {
+    double g = 0.5 * (1.0 - c);
+    double pm = 1.0, p = c;                  /* P_{l-1}, P_l at l = 1 */
+    for (int l = 1; l <= SBM_LEGENDRE_L; ++l) {
+        double pn = ((2.0 * l + 1.0) * c * p - l * pm) / (l + 1.0);   /* P_{l+1} */
+        g += 0.5 * exp(-0.5 * l * (l + 1.0) * t) * (pm - pn);
+        pm = p;
+        p = pn;
+    }
+    return g;
+}
+
+static void sbm_polar(double t, double z, double u, double* ct, double* st) {
+    if (t < SBM_T_SWITCH) {
+        double M = floor(sbm_lineage_mean(t) + sqrt(sbm_lineage_var(t)) * z + 0.5);
+        if (M < 0.0) M = 0.0;
+        double X = -expm1(log(u) / (1.0 + M));          /* Beta(1, 1 + M) by inversion */
+        *ct = 1.0 - 2.0 * X;
+        *st = 2.0 * sqrt(X * (1.0 - X));
+        return;
+    }
+    /* P(cos(angle) <= c) = u, i.e. sbm_upper_tail(t, c) = 1 - u */
+    double lo = -1.0, hi = 1.0;
+    for (int i = 0; i < 60; ++i) {
+        double c = 0.5 * (lo + hi);
+        if (sbm_upper_tail(t, c) > 1.0 - u) lo = c; else hi = c;
+    }
+    double c = 0.5 * (lo + hi);
+    *ct = c;
+    *st = sqrt((1.0 - c) * (1.0 + c));
 }
 
 static void normalize(double d[3]) {
@@ -526,6 +611,13 @@ double or_cm_to_lab(double K, double A, double c, double s, double u) {
     return cm_to_lab(K, A, c, s, u);
 }
 void or_turn(double* d, double ct, double st, double phi) { turn(d, ct, st, phi); }
+double or_sbm_lineage_mean(double t) { return sbm_lineage_mean(t); }
+double or_sbm_lineage_var(double t) { return sbm_lineage_var(t); }
+double or_sbm_upper_tail(double t, double c) { return sbm_upper_tail(t, c); }
+double or_sbm_t_switch(void) { return SBM_T_SWITCH; }
+void or_sbm_polar_n(size_t n, double t, const double* z, const double* u, double* ct, double* st) {
+    for (size_t i = 0; i < n; ++i) sbm_polar(t, z[i], u[i], &ct[i], &st[i]);
+}
 double or_channel_total_rate(const or_material* m, const or_nuclear* nu, const or_params* p,
                              double rho, double E) {
     channels c;
@@ -728,7 +820,15 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
         /* Direction: small-angle diffusion, then the jump, then renormalise. */
         if (p->flags & OR_MCS) {
             double sig = lynch_dahl_sigma(m, rho, E, p->ld_z_cm, p->ld_F) * sqrt(D / p->ld_z_cm);
-            sbm_step(O, sig, u_hi(w[2]), u_hi(w[3]));
+            if (p->flags & OR_SBM) {
+                /* the lineage count's normal: the sine partner of Z_E's Box-Muller pair */
+                double zM = sqrt(-2.0 * log(u_hi(w[0]))) * sin(TWO_PI * u_hi(w[1]));
+                double ct, st;
+                sbm_polar(sig * sig, zM, u_hi(w[2]), &ct, &st);
+                turn(O, ct, st, TWO_PI * u_hi(w[3]));
+            } else {
+                geodesic_step(O, sig, u_hi(w[2]), u_hi(w[3]));
+            }
         }
         if (jumped) turn(O, jc, js, jphi);
         normalize(O);

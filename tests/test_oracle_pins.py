@@ -190,6 +190,171 @@ def test_mcs_thin_slab_invariant_and_highland(water, E):
     assert abs(math.sqrt(20) * sig / hl - 1) < 0.12
 
 
+# Spherical Brownian motion on S^2 (generator half the Laplace-Beltrami
+# operator): E[P_l(cos angle)] = exp(-l (l + 1) t / 2) for every l, the
+# heat kernel's eigenvalues.  X = (1 - cos) / 2, so E[X] = (1 - e^-t) / 2 and
+# E[X^2] = (1 - 2 e^-t + (1 + 2 e^-3t) / 3) / 4.
+
+def _sbm_exact_moments(t):
+    ex = (1 - math.exp(-t)) / 2
+    ex2 = (1 - 2 * math.exp(-t) + (1 + 2 * math.exp(-3 * t)) / 3) / 4
+    return ex, ex2
+
+
+def _griffiths_mpmath(t):
+    import mpmath as mp
+    mp.mp.dps = 40
+    b = mp.mpf(t) / 2
+    eta = b / mp.expm1(b)
+    mean = 2 * eta / mp.mpf(t)
+    var = mean * (eta + b) ** 2 * (1 + eta / (eta + b) - 2 * eta) / b ** 2
+    return float(mean), float(var)
+
+
+@pytest.mark.parametrize("t", [1e-6, 1e-4, 3e-3, 0.0099, 0.01, 0.0199])
+def test_sbm_griffiths_moments_high_precision(t):
+    """The oracle's lineage-count mean and variance (a Taylor series below
+    t = 1e-2, the closed form above) against a 40-digit evaluation of
+    Griffiths' closed forms, and the variance's t -> 0 limit 2 / (3 t)."""
+    mean, var = _griffiths_mpmath(t)
+    assert abs(oracle.sbm_lineage_mean(t) / mean - 1) < 1e-12
+    assert abs(oracle.sbm_lineage_var(t) / var - 1) < 1e-9
+    assert abs(var * 1.5 * t - 1) < 2e-5
+
+
+def test_sbm_griffiths_vs_exact_lineage_law():
+    """Griffiths' normal law against the exact law of the number of lineages
+    A(t) of Kingman's coalescent with mutation parameter 2, computed here from
+    its alternating series (Tavare 1984) at 50 digits, t = 0.02:
+    P(A = m) = sum_{k >= m} (-1)^(k-m) (2k+1) (m+2)_(k-1) / (m! (k-m)!)
+    exp(-k (k+1) t / 2).  The exact law gives E[cos] = e^-t (checked), and
+    Griffiths' mean is within 0.2 of its mean, the variance within 0.5 %."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    t = 0.02
+    q = {}
+    for m in range(40, 175):
+        s = mp.mpf(0)
+        for k in range(m, 700):
+            term = ((2 * k + 1) * mp.rf(m + 2, k - 1) / (mp.factorial(m) * mp.factorial(k - m))
+                    * mp.exp(-k * (k + 1) * mp.mpf(t) / 2))
+            s += term if (k - m) % 2 == 0 else -term
+            if k > m + 20 and term < mp.mpf(10) ** -30:
+                break
+        q[m] = float(s)
+    assert abs(sum(q.values()) - 1) < 1e-9
+    assert abs(sum(p * m / (m + 2) for m, p in q.items()) - math.exp(-t)) < 1e-10
+    em = sum(p * m for m, p in q.items())
+    vm = sum(p * m * m for m, p in q.items()) - em ** 2
+    assert abs(oracle.sbm_lineage_mean(t) - em) < 0.2
+    assert abs(oracle.sbm_lineage_var(t) / vm - 1) < 5e-3
+
+
+def _stratified(n_z, n_u):
+    """Product grid of normal quantiles z (equal-mass cells) and uniforms u
+    at the midpoints of cells graded cubically towards 0, where X's log tail
+    lives; returns (z, u, w) with w the probability of each cell."""
+    from scipy.special import ndtri
+    z = ndtri((np.arange(n_z) + 0.5) / n_z)
+    edges = (np.arange(n_u + 1) / n_u) ** 3
+    u = 0.5 * (edges[1:] + edges[:-1])
+    wu = np.diff(edges)
+    return np.repeat(z, n_u), np.tile(u, n_z), np.tile(wu, n_z) / n_z
+
+
+@pytest.mark.parametrize("t", [0.005, 0.01, 0.019])
+def test_sbm_small_t_moments(t):
+    """Algorithm 1 with the normal lineage count (t below the switch), on a
+    stratified grid of (z, u): E[X] and E[X^2] of X = sin^2(angle / 2)
+    against the exact spherical Brownian motion.  The normal law's own error
+    (from the exact lineage law) is -8.3e-4 relative in E[X] and -1.7e-3 in
+    E[X^2] at t = 0.01, growing like t; the bars 0.12 t and 0.25 t reject
+    the geodesic step (+0.17 t), a count without its spread (-0.49 t and
+    -1.15 t), Beta(1, M) (+0.5 t) and the mean without its -1/2 (-0.25 t)."""
+    assert t < oracle.sbm_t_switch()
+    z, u, w = _stratified(2048, 2048)
+    ct, st = oracle.sbm_polar(t, z, u)
+    assert np.allclose(ct * ct + st * st, 1.0, atol=1e-12)
+    x = 0.5 * (1 - ct)
+    ex, ex2 = _sbm_exact_moments(t)
+    m1, m2 = np.dot(w, x), np.dot(w, x * x)
+    assert abs(m1 / ex - 1) < 0.12 * t, m1 / ex - 1
+    assert abs(m2 / ex2 - 1) < 0.25 * t, m2 / ex2 - 1
+
+
+@pytest.mark.parametrize("t", [0.02, 0.1, 0.5, 2.0])
+def test_sbm_heat_kernel_inversion_moments(t):
+    """Exact regime (t at or above the switch): cos(angle) from inverting the
+    heat kernel's distribution function, on a stratified grid of u, has the
+    moments E[P_l] = exp(-l (l + 1) t / 2), l = 1, 2, 3, and is increasing in u."""
+    assert t >= oracle.sbm_t_switch()
+    n = 40_000
+    u = (np.arange(n) + 0.5) / n
+    ct, st = oracle.sbm_polar(t, np.zeros(n), u)
+    assert np.all(np.diff(ct) > 0) and ct.min() >= -1 and ct.max() <= 1
+    assert np.allclose(ct * ct + st * st, 1.0, atol=1e-12)
+    legendre = [ct, 0.5 * (3 * ct ** 2 - 1), 0.5 * (5 * ct ** 3 - 3 * ct)]
+    for l, pl in enumerate(legendre, start=1):
+        assert abs(pl.mean() - math.exp(-0.5 * l * (l + 1) * t)) < 2e-5, (l, pl.mean())
+
+
+def test_sbm_upper_tail_limits_and_density():
+    """P(cos > c) is 1 at c = -1, 0 at c = 1, tends to the uniform law's
+    (1 - c) / 2 for large t, and its derivative integrates the density
+    sum_l (2l+1)/2 e^{-l(l+1)t/2} P_l (scipy's Legendre values)."""
+    from scipy.special import eval_legendre
+    for t in (0.02, 0.3, 3.0):
+        assert abs(oracle.sbm_upper_tail(t, -1.0) - 1) < 1e-12
+        assert abs(oracle.sbm_upper_tail(t, 1.0)) < 1e-12
+    assert abs(oracle.sbm_upper_tail(40.0, 0.3) - 0.35) < 1e-12
+    t = 0.05
+    c = np.linspace(-0.9, 0.99, 7)
+    l = np.arange(0, 200)
+    dens = lambda x: np.sum((2 * l + 1) / 2 * np.exp(-0.5 * l * (l + 1) * t) * eval_legendre(l, x))
+    for a, b in zip(c[:-1], c[1:]):
+        want, _ = integrate.quad(dens, a, b, limit=200)
+        got = oracle.sbm_upper_tail(t, a) - oracle.sbm_upper_tail(t, b)
+        assert abs(got - want) < 1e-9 * max(1.0, abs(want)), (a, b, got, want)
+
+
+def test_sbm_regimes_meet_at_the_switch():
+    """Just below and at the switch the two regimes give the same E[X] to
+    within the normal law's error there (about -1.6e-3 relative)."""
+    ts = oracle.sbm_t_switch()
+    z, u, w = _stratified(1024, 2048)
+    ex, _ = _sbm_exact_moments(ts)
+    below = np.dot(w, 0.5 * (1 - oracle.sbm_polar(ts * (1 - 1e-9), z, u)[0]))
+    # the exact regime does not read z: one row of the grid suffices
+    at = np.dot(w[:2048] * 1024, 0.5 * (1 - oracle.sbm_polar(ts, z[:2048], u[:2048])[0]))
+    assert abs(at / ex - 1) < 2e-5
+    assert abs(below / at - 1) < 2.5e-3
+
+
+@pytest.mark.parametrize("E,n_steps", [(3.0, 21), (1.0, 5)])
+def test_mcs_sbm_slab_direction_law(water, E, n_steps):
+    """Transport with the spherical Brownian motion sampler only (no loss, so
+    E and t = sigma_LD^2 stay fixed), stopped after n steps by max_steps: the
+    direction is then the motion at time n t, so E[cos] = exp(-n t) and
+    E[P_2] = exp(-3 n t), within 4 standard errors.  3 MeV runs the normal
+    regime (t = 5.8e-3), 1 MeV the exact one (t = 5.4e-2)."""
+    from dataclasses import replace
+    n_h = 20_000
+    ph = slab(4.0, water)
+    p = replace(PhysicsParams(), max_steps=n_steps)
+    r = oracle.transport(ph, workloads.single_spot(E, n_h), p, None, seed=10,
+                         flags=oracle.MCS | oracle.SBM, tally=False, records=True)
+    rec = r.records
+    assert np.all(rec[:, oracle.R_END] == oracle.END_MAXSTEPS)
+    assert np.all(rec[:, oracle.R_STEPS] == n_steps)
+    t = oracle.ld_sigma(water, 1.0, E) ** 2
+    assert (t < oracle.sbm_t_switch()) == (E > 2.0)
+    oz = rec[:, oracle.R_OZ]
+    for vals, want in ((oz, math.exp(-n_steps * t)),
+                       (0.5 * (3 * oz ** 2 - 1), math.exp(-3 * n_steps * t))):
+        se = vals.std() / math.sqrt(n_h)
+        assert abs(vals.mean() - want) < 4 * se + 1e-12, (vals.mean(), want, se)
+
+
 # --------------------------------------------------------------------------
 # Large-angle elastic and inelastic jumps
 # --------------------------------------------------------------------------
