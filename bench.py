@@ -54,6 +54,8 @@ def parse():
                     help="skip the time-to-gamma leg (plain SDE vs denoised, plan at 2 mm)")
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-phantom leg (slab and insert, 100/150 MeV)")
+    ap.add_argument("--no-sbm", action="store_true",
+                    help="skip the leg timing the spherical Brownian motion sampler")
     return ap.parse_args()
 
 
@@ -265,6 +267,36 @@ def hetero_leg(steps: int) -> list:
     return out
 
 
+def sbm_leg(wl, launch, steps: int, kms_geodesic: float) -> dict:
+    """The water workload with the small-angle diffusion drawn from the
+    spherical Brownian motion law (switch SBM) instead of the geodesic
+    Gaussian step, same launch, timed per launch like the main leg."""
+    from dataclasses import replace
+    import numpy as np
+    import workloads
+    from paper_2511_03115_amd import sde
+    params = replace(wl.params, flags=sde.ALL | sde.SBM)
+    sde.init_materials(wl.phantom.materials, params,
+                       workloads.nuclear_for_phantom(wl.phantom, params.lattice()))
+    dph = sde.DevicePhantom.from_host(wl.phantom)
+    plan = sde.Plan(wl.spots, dph, wl.seed, launch=launch)
+    plan.execute(None)
+    ms = []
+    for _ in range(max(1, steps)):
+        plan.execute(None)
+        ms.append(plan.kernel_ms())
+    led, _ = plan.results()
+    plan.close()
+    k = float(np.mean(ms))
+    print(f"[bench] water150 with the spherical Brownian motion sampler: {k:.2f} ms per launch",
+          flush=True)
+    return {"workload": "water150 (the main workload), small-angle diffusion by the spherical "
+                        "Brownian motion law", "flags": int(params.flags), "kernel_ms": k,
+            "histories_per_s": wl.n_histories / (k * 1e-3),
+            "steps_per_launch": int(led[sde.LEDGER_STEPS]),
+            "time_vs_geodesic_step": k / kms_geodesic}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -335,6 +367,8 @@ def main():
                      "units_per_launch": steps_per_launch},
     }
     plan.close()
+    if not a.no_sbm:
+        out["sbm"] = sbm_leg(wl, launch, min(a.steps, 3), kms)
     if not a.no_plan:
         out["plan"] = plan_leg(a.steps, stream)
     if not a.no_hetero:

@@ -60,6 +60,12 @@ typedef enum {
 #define SDE_INELASTIC 16u    /* inelastic nuclear jumps */
 #define SDE_END_OF_RANGE 32u /* residual-range final step near the Bragg peak */
 #define SDE_ALL 63u
+/* With SDE_MCS: draw the small-angle diffusion from the spherical Brownian
+ * motion law at time t = sigma^2 Delta / z (section 2.2.2; the cited
+ * Algorithm 1 of Mijatovic et al. with Griffiths' normal lineage count for
+ * t < 0.02, exact inversion of the heat kernel's Legendre series above)
+ * instead of the geodesic Gaussian step.  Other bits are rejected. */
+#define SDE_SBM 64u
 
 /* Ledger slots (sde_transport_ex ledger_out) */
 #define SDE_LEDGER_DEPOSITED 0   /* energy scored inside the phantom (fixed point) */

@@ -485,6 +485,7 @@ static double sbm_upper_tail(double t, double c) {
 }
 
 static void sbm_polar(double t, double z, double u, double* ct, double* st) {
+    if (t <= 0.0) { *ct = 1.0; *st = 0.0; return; }    /* no motion */
     if (t < SBM_T_SWITCH) {
         double M = floor(sbm_lineage_mean(t) + sqrt(sbm_lineage_var(t)) * z + 0.5);
         if (M < 0.0) M = 0.0;

@@ -21,7 +21,7 @@ namespace sde {
 namespace {
 
 constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelastic = 16u,
-                   kEor = 32u, kAllPhysics = 63u;
+                   kEor = 32u, kAllPhysics = 63u, kSbm = 64u;
 
 constexpr float kMpF = (float)kMp;
 constexpr float kLn2 = 0.69314718055994530942f;
@@ -84,6 +84,98 @@ __device__ __forceinline__ void polar_cs(float th2, float& c, float& s) {
         s = sin_rev(r);
         c = cos_rev(r);
     }
+}
+
+// Spherical Brownian motion on S^2 (generator half the Laplace-Beltrami
+// operator) at time t = sigma^2 Delta / z, the law of the small-angle
+// diffusion over one step (section 2.2.2), by the sampler the paper cites
+// (Mijatovic, Mramor and Uribe Bravo 2020, Algorithm 1): M = the number of
+// lineages left at time t of Kingman's coalescent with mutation parameter
+// d - 1 = 2 started from infinitely many, X ~ Beta(1, 1 + M),
+// cos = 1 - 2 X.  u -> 1 gives the angle -> 0 in both regimes.
+constexpr float kSbmSwitch = 0.02f;
+constexpr int kSbmL = 64;   // Legendre terms: e^{-l(l+1)t/2} < 1e-18 beyond, t >= kSbmSwitch
+
+// t < kSbmSwitch: M from Griffiths' normal law, mean 2/t - 1/2 + t/24
+// (series of 1/expm1(t/2), error t^3/5760) and standard deviation
+// sqrt(2/(3t)) (1 - 7t^2/480), rounded to the nearest integer; then X by
+// inversion, -expm1(ln u / (1 + M)) as a degree-7 polynomial: here
+// 1 + M >= 67 (|z| <= 5.77) and -ln u <= 16.7, so |ln u / (1 + M)| <= 0.25
+// and the truncation is below 2e-9 relative.
+__device__ __forceinline__ void sbm_small(float t, float z, float u, float& ct, float& st) {
+    t = fmaxf(t, 1e-30f);
+    const float r = __builtin_amdgcn_rsqf(t);
+    const float mu = fmaf(2.0f * r, r, fmaf(t, 1.0f / 24.0f, -0.5f));
+    const float sd = 0.81649658f * r * fmaf(-7.0f / 480.0f * t, t, 1.0f);
+    const float M = fmaxf(rintf(fmaf(sd, z, mu)), 0.0f);
+    const float y = flog(u) * frcp(M + 1.0f);
+    const float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, 1.0f / 5040.0f, 1.0f / 720.0f),
+                                                         1.0f / 120.0f), 1.0f / 24.0f),
+                                         1.0f / 6.0f), 0.5f), 1.0f);
+    const float X = -y * p;
+    ct = fmaf(-2.0f, X, 1.0f);
+    st = 2.0f * fsqrt(X * (1.0f - X));
+}
+
+// Legendre recurrence coefficients (l+1) P_{l+1} = (2l+1) c P_l - l P_{l-1}
+// as (2l+1)/(l+1) and l/(l+1), read with a wave-uniform index.
+struct LegendreCoef {
+    double a[kSbmL + 1], b[kSbmL + 1];
+};
+constexpr LegendreCoef legendre_coef() {
+    LegendreCoef k{};
+    for (int l = 0; l <= kSbmL; ++l) {
+        k.a[l] = (2.0 * l + 1.0) / (l + 1.0);
+        k.b[l] = (double)l / (l + 1.0);
+    }
+    return k;
+}
+__constant__ LegendreCoef kLegendre = legendre_coef();
+
+// P(cos > c) at time t and its density in c, from the heat kernel on S^2,
+// sum_l (2l+1)/2 e^{-l(l+1)t/2} P_l(c), whose integral from c to 1 has the
+// terms (P_{l-1} - P_{l+1}) / 2 for l >= 1.  Weights by
+// e^{-l(l+1)t/2} = e^{-(l-1)l t/2} (e^{-t})^l.  The loop stays rolled: its
+// constants unrolled would crowd out the step's scalar registers.
+__device__ __forceinline__ void sbm_tail(double q, double c, double& g, double& f) {
+    double ql = 1.0, w = 1.0, pm = 1.0, p = c;
+    g = 0.5 * (1.0 - c);
+    f = 0.5;
+#pragma unroll 1
+    for (int l = 1; l <= kSbmL; ++l) {
+        ql *= q;
+        w *= ql;
+        const double pn = kLegendre.a[l] * c * p - kLegendre.b[l] * pm;
+        g = fma(0.5 * w, pm - pn, g);
+        f = fma((l + 0.5) * w, p, f);
+        pm = p;
+        p = pn;
+    }
+}
+
+// t >= kSbmSwitch: cos drawn exactly, P(cos <= c) = u, by Newton steps on
+// the series kept inside a shrinking bisection bracket (at most 40 steps;
+// a step that leaves the bracket or is NaN bisects instead); returns
+// (cos, sin).  Rare: with the residual-range step on, t stays below ~2e-2
+// on every full step.  Out of line, so that its double-precision registers
+// never add to the step's: registers live across the call are saved only
+// when it runs.
+__device__ __noinline__ float2 sbm_large(float t, float u) {
+    const double td = t, target = 1.0 - (double)u, q = exp(-td);
+    double lo = -1.0, hi = 1.0;
+    double c = fmin(fmax(fmax(1.0 + td * log((double)u), 2.0 * (double)u - 1.0), -1.0), 1.0);
+#pragma unroll 1
+    for (int it = 0; it < 40; ++it) {
+        double g, f;
+        sbm_tail(q, c, g, f);
+        if (g > target) lo = c; else hi = c;
+        double cn = c + (g - target) / f;
+        if (!(cn > lo && cn < hi)) cn = 0.5 * (lo + hi);
+        const bool done = fabs(cn - c) <= 1e-14;
+        c = cn;
+        if (done) break;
+    }
+    return make_float2((float)c, (float)sqrt(fmax((1.0 - c) * (1.0 + c), 0.0)));
 }
 
 // Turn unit d by (ct, st) about itself, azimuth (cp, sp) from b1 of the
@@ -423,9 +515,28 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     int j1 = -1, j2 = -1;
     long long l_esc = 0, l_nuc = 0, l_e0 = 0;
     unsigned l_steps = 0, l_jumps = 0, l_hist = 0;
+    // small-angle turn of the last step still to draw (exact regime): time,
+    // uniform, azimuth
+    bool sbm_pend = false;
+    float sbm_t = 0.0f, sbm_u = 0.0f, sbm_ph = 0.0f;
 
     for (;;) {
         if (state == kDead) acc_flush(P, tile, rep, acc);
+        // ---------------- small-angle turns in the exact regime ----------------
+        // Drawn here, where little is live, before the lane's pending jump
+        // (if any) turns it and before its next step moves it.  A history that
+        // ended in that step needs no direction.
+        if ((flags & kSbm) && sbm_pend) {
+            if (state != kDead) {
+                const float2 cs = sbm_large(sbm_t, sbm_u);
+                turn(ox, oy, oz, cs.x, cs.y, cos_rev(sbm_ph), sin_rev(sbm_ph));
+                const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+                ox *= inv;
+                oy *= inv;
+                oz *= inv;
+            }
+            sbm_pend = false;
+        }
         // ---------------- refill idle lanes ----------------
         // History indices come from a wave-local range [q_next, q_end) that is
         // refilled a chunk at a time from the global counter (one atomic per
@@ -630,19 +741,37 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
             if (v_next != vcache) pk_next = P.vox[v_next];
         }
 
-        // Small-angle diffusion: geodesic Gaussian step of per-axis variance
-        // sigma^2 Delta / z, sigma the Lynch-Dahl width.
+        // Small-angle diffusion over time t = sigma^2 Delta / z, sigma the
+        // Lynch-Dahl width: the spherical Brownian motion law (switch kSbm;
+        // the lineage count's normal is the sine partner of Z_E's
+        // Box-Muller pair) or the geodesic Gaussian step of per-axis
+        // variance t.
         if (flags & kMcs) {
             const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
             const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
             const float nu = rho * A2;
             const float br = (1.0f + frcp(nu)) * flog(1.0f + nu) - 1.0f;
             const float sig2 = rho * A1 * br;
-            const float th2 = -2.0f * sig2 * flog(u_hi(w.z));
-            float ct, st;
-            polar_cs(th2, ct, st);
-            const float ph = u_hi(w.w);
-            turn(ox, oy, oz, ct, st, cos_rev(ph), sin_rev(ph));
+            float ct = 1.0f, st = 0.0f;
+            bool now = true;
+            if (flags & kSbm) {
+                if (sig2 < kSbmSwitch) {
+                    const float zM = fsqrt(-2.0f * flog(u_hi(w.x))) * sin_rev(u_hi(w.y));
+                    sbm_small(sig2, zM, u_hi(w.z), ct, st);
+                } else {   // exact regime: drawn at the top of the loop
+                    now = false;
+                    sbm_pend = true;
+                    sbm_t = sig2;
+                    sbm_u = u_hi(w.z);
+                    sbm_ph = u_hi(w.w);
+                }
+            } else {
+                polar_cs(-2.0f * sig2 * flog(u_hi(w.z)), ct, st);
+            }
+            if (now) {
+                const float ph = u_hi(w.w);
+                turn(ox, oy, oz, ct, st, cos_rev(ph), sin_rev(ph));
+            }
         }
         l_steps++;
         if (jumped) {
@@ -808,17 +937,24 @@ hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long lo
 }
 
 hipError_t transport_kernel_attributes(size_t lds_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<kAllPhysics>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<0u>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<kAllPhysics>),
+                         reinterpret_cast<const void*>(&k_transport<kAllPhysics | kSbm>),
+                         reinterpret_cast<const void*>(&k_transport<0u>)};
+    for (const void* f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
                             hipStream_t s) {
     if (p.flags == kAllPhysics)
         hipLaunchKernelGGL(k_transport<kAllPhysics>, dim3(grid), dim3(block), lds_bytes, s, p);
+    else if (p.flags == (kAllPhysics | kSbm))
+        hipLaunchKernelGGL(k_transport<kAllPhysics | kSbm>, dim3(grid), dim3(block), lds_bytes,
+                           s, p);
     else
         hipLaunchKernelGGL(k_transport<0u>, dim3(grid), dim3(block), lds_bytes, s, p);
     return hipGetLastError();

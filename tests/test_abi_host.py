@@ -75,6 +75,10 @@ def test_host_validation_without_gpu(lib):
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(bad), None) == sde.E_INVALID
     lib.sde_last_error.restype = C.c_char_p
     assert b"invalid physics parameters" in lib.sde_last_error()
+    # physics switch bits other than SDE_ALL | SDE_SBM
+    unk = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63 | 128, 65536)
+    assert lib.sde_init_materials(C.byref(m), 1, C.byref(unk), None) == sde.E_INVALID
+    assert b"unknown physics switch" in lib.sde_last_error()
     # a medium whose Bethe stopping power is negative at e_min (I far too large)
     m.I_eV = 5000.0
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(pp), None) == sde.E_INVALID

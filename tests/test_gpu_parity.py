@@ -8,6 +8,8 @@ where a rounding difference flips a discrete decision (a voxel boundary, the
 jump test, the end-of-range test), which is rare.
 """
 
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -48,15 +50,61 @@ def test_parity_water100_small_full_physics():
     oracle.LOSS | oracle.MCS | oracle.EOR,
     oracle.LOSS | oracle.ELASTIC | oracle.EOR,
     oracle.LOSS | oracle.INELASTIC | oracle.EOR,
+    oracle.LOSS | oracle.MCS | oracle.SBM | oracle.EOR,
+    # no residual-range step: the last steps before e_min run the exact regime
+    oracle.LOSS | oracle.STRAGGLE | oracle.MCS | oracle.SBM,
 ])
 def test_parity_physics_subsets(flags):
-    wl = configs.water100_small(n=3000)
+    # 1e4 histories: the residual-range step deposits up to ~6 MeV at one
+    # midpoint, and one such deposit put in the neighbouring voxel (a midpoint
+    # within ~1e-5 cm of a face, FP32 vs FP64 positions) is ~8e-4 of the peak
+    # voxel here; at 3e3 histories it alone would be ~2.5e-3, above the bar.
+    wl = configs.water100_small(n=10_000)
     log(f"case subset flags={flags}")
     d_gpu, _, _, _ = run_gpu(wl, flags=flags)
     d_ref, _ = run_oracle(wl, flags=flags)
     m = parity_metrics(d_ref, d_gpu, wl.phantom)
     log(f"metrics {m}")
     _bar(m)
+
+
+def test_parity_full_physics_spherical_brownian_motion():
+    """The full method with the spherical Brownian motion sampler (its own
+    compiled instance) against the oracle with the same switch.  3e4
+    histories: about one history in 3e3 takes another path after a jump (a
+    rounding difference flips a discrete decision), and one such history
+    moves ~1e-3 of the peak voxel's dose at 1e4 histories, ~4e-4 here."""
+    wl = configs.water100_small(n=30_000)
+    flags = oracle.ALL | oracle.SBM
+    log(f"case water100_small sbm flags={flags}")
+    d_gpu, tal, led, scale = run_gpu(wl, flags=flags)
+    d_ref, led_ref = run_oracle(wl, flags=flags)
+    m = parity_metrics(d_ref, d_gpu, wl.phantom)
+    log(f"metrics {m}")
+    assert led[6] == wl.n_histories
+    assert abs(led[0] / scale - led_ref[oracle.L_DEP]) <= 1e-4 * led_ref[oracle.L_E0]
+    _bar(m)
+
+
+@pytest.mark.parametrize("flags", [oracle.ALL | oracle.SBM,
+                                   oracle.LOSS | oracle.STRAGGLE | oracle.MCS | oracle.SBM])
+def test_history_agreement_spherical_brownian_motion(flags):
+    """History by history under the spherical Brownian motion sampler, with
+    and without the residual-range step (without it, the exact regime runs
+    near e_min): the same discrete paths and end points as the oracle."""
+    wl = configs.water100_small(n=4000)
+    log(f"case history agreement sbm flags={flags}")
+    g, _ = run_gpu_records(wl, flags=flags)
+    params = replace(wl.params, flags=flags)
+    r = oracle.transport(wl.phantom, wl.spots, params,
+                         workloads.nuclear_for_phantom(wl.phantom, params.lattice()),
+                         seed=wl.seed, records=True, tally=False)
+    a = history_agreement(g, r.records)
+    log(f"agreement {a}")
+    assert a["e0_equal"] == 1.0
+    assert a["same_frac"] >= 0.995
+    assert a["pos_close_frac"] >= 0.995 and a["pos_p99"] < 2.5e-4
+    assert a["dE_p99"] < 1e-2
 
 
 def test_history_by_history_agreement():

@@ -39,6 +39,7 @@ F_ELASTIC = 8
 F_INELASTIC = 16
 F_END_OF_RANGE = 32
 F_ALL = 63
+F_SBM = 64
 
 
 @dataclass(frozen=True)
