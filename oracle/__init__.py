@@ -33,8 +33,8 @@ MAX_MAT = 16
 
 # physics switches
 LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, EOR = 1, 2, 4, 8, 16, 32
-ALL = 63
-SBM = 64   # small-angle diffusion by the spherical Brownian motion law
+SBM = 64   # small-angle diffusion by the spherical Brownian motion law (else geodesic step)
+ALL = 127  # the method
 
 # ledger slots and record fields (mirror the enums of sde_oracle.c)
 L_DEP, L_ESC, L_NUC, L_E0, L_TRUNC, L_STEPS, L_HIST, L_JUMPS = range(8)

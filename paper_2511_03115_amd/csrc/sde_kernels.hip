@@ -21,7 +21,11 @@ namespace sde {
 namespace {
 
 constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelastic = 16u,
-                   kEor = 32u, kAllPhysics = 63u, kSbm = 64u;
+                   kEor = 32u, kSbm = 64u;
+// the method (every switch) and the method with the geodesic Gaussian step:
+// each its own compiled instance, the rest share k_transport<0> (switches
+// read at run time)
+constexpr unsigned kMethod = 127u, kMethodGeodesic = 63u;
 
 constexpr float kMpF = (float)kMp;
 constexpr float kLn2 = 0.69314718055994530942f;
@@ -474,7 +478,8 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 enum : int { kDead = 0, kStep = 1, kJump = 2 };
 
 // kFixed != 0: the physics switches are that compile-time constant (the
-// full method), so their tests fold away; 0: read them from P.flags.
+// method, with either small-angle sampler), so their tests fold away; 0:
+// read them from P.flags.
 template <unsigned kFixed>
 __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     const unsigned flags = kFixed ? kFixed : P.flags;
@@ -937,8 +942,8 @@ hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long lo
 }
 
 hipError_t transport_kernel_attributes(size_t lds_bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<kAllPhysics>),
-                         reinterpret_cast<const void*>(&k_transport<kAllPhysics | kSbm>),
+    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<kMethod>),
+                         reinterpret_cast<const void*>(&k_transport<kMethodGeodesic>),
                          reinterpret_cast<const void*>(&k_transport<0u>)};
     for (const void* f : fns) {
         const hipError_t e =
@@ -950,11 +955,11 @@ hipError_t transport_kernel_attributes(size_t lds_bytes) {
 
 hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
                             hipStream_t s) {
-    if (p.flags == kAllPhysics)
-        hipLaunchKernelGGL(k_transport<kAllPhysics>, dim3(grid), dim3(block), lds_bytes, s, p);
-    else if (p.flags == (kAllPhysics | kSbm))
-        hipLaunchKernelGGL(k_transport<kAllPhysics | kSbm>, dim3(grid), dim3(block), lds_bytes,
-                           s, p);
+    if (p.flags == kMethod)
+        hipLaunchKernelGGL(k_transport<kMethod>, dim3(grid), dim3(block), lds_bytes, s, p);
+    else if (p.flags == kMethodGeodesic)
+        hipLaunchKernelGGL(k_transport<kMethodGeodesic>, dim3(grid), dim3(block), lds_bytes, s,
+                           p);
     else
         hipLaunchKernelGGL(k_transport<0u>, dim3(grid), dim3(block), lds_bytes, s, p);
     return hipGetLastError();

@@ -119,7 +119,7 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         *err = "invalid physics parameters";
         return SDE_E_INVALID;
     }
-    if (p->flags & ~(unsigned)(SDE_ALL | SDE_SBM)) {
+    if (p->flags & ~(unsigned)SDE_ALL) {
         *err = "unknown physics switch bits";
         return SDE_E_INVALID;
     }

@@ -19,8 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsde.so")
 
 OK, E_INVALID, E_HIP, E_RANGE, E_OVERFLOW, E_STATE, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
-LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, END_OF_RANGE, ALL = 1, 2, 4, 8, 16, 32, 63
-SBM = 64   # small-angle diffusion by the spherical Brownian motion law
+LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, END_OF_RANGE = 1, 2, 4, 8, 16, 32
+SBM = 64   # small-angle diffusion by the spherical Brownian motion law (else geodesic step)
+ALL = 127  # the method
 (LEDGER_DEPOSITED, LEDGER_ESCAPED, LEDGER_NUCLEAR, LEDGER_INITIAL, LEDGER_TRUNCATED,
  LEDGER_STEPS, LEDGER_HISTORIES, LEDGER_JUMPS) = range(8)
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",

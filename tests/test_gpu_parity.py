@@ -29,7 +29,10 @@ def _bar(m):
 
 
 def test_parity_water100_small_full_physics():
-    wl = configs.water100_small()
+    # 3e4 histories: about one history in 3e3 takes another path after a
+    # jump (a rounding difference flips a discrete decision), and one such
+    # history moves ~1e-3 of the peak voxel's dose at 1e4 histories, ~4e-4 here.
+    wl = configs.water100_small(n=30_000)
     log(f"case water100_small seed={wl.seed} n={wl.n_histories}")
     d_gpu, tal, led, scale = run_gpu(wl)
     d_ref, led_ref = run_oracle(wl)
@@ -68,15 +71,13 @@ def test_parity_physics_subsets(flags):
     _bar(m)
 
 
-def test_parity_full_physics_spherical_brownian_motion():
-    """The full method with the spherical Brownian motion sampler (its own
-    compiled instance) against the oracle with the same switch.  3e4
-    histories: about one history in 3e3 takes another path after a jump (a
-    rounding difference flips a discrete decision), and one such history
-    moves ~1e-3 of the peak voxel's dose at 1e4 histories, ~4e-4 here."""
+def test_parity_full_physics_geodesic_step():
+    """The method with the geodesic Gaussian step for the small-angle
+    diffusion (its own compiled instance) against the oracle with the same
+    switches; 3e4 histories as for the method."""
     wl = configs.water100_small(n=30_000)
-    flags = oracle.ALL | oracle.SBM
-    log(f"case water100_small sbm flags={flags}")
+    flags = oracle.ALL & ~oracle.SBM
+    log(f"case water100_small geodesic flags={flags}")
     d_gpu, tal, led, scale = run_gpu(wl, flags=flags)
     d_ref, led_ref = run_oracle(wl, flags=flags)
     m = parity_metrics(d_ref, d_gpu, wl.phantom)
@@ -86,11 +87,11 @@ def test_parity_full_physics_spherical_brownian_motion():
     _bar(m)
 
 
-@pytest.mark.parametrize("flags", [oracle.ALL | oracle.SBM,
+@pytest.mark.parametrize("flags", [oracle.ALL,
                                    oracle.LOSS | oracle.STRAGGLE | oracle.MCS | oracle.SBM])
 def test_history_agreement_spherical_brownian_motion(flags):
-    """History by history under the spherical Brownian motion sampler, with
-    and without the residual-range step (without it, the exact regime runs
+    """History by history under the spherical Brownian motion sampler (the
+    method, and without the residual-range step, where the exact regime runs
     near e_min): the same discrete paths and end points as the oracle."""
     wl = configs.water100_small(n=4000)
     log(f"case history agreement sbm flags={flags}")
@@ -109,12 +110,15 @@ def test_history_agreement_spherical_brownian_motion(flags):
 
 def test_history_by_history_agreement():
     """Same seeded words on both sides: almost every history takes the same
-    discrete path (steps, jumps, end event) and ends at the same place."""
+    discrete path (steps, jumps, end event) and ends at the same place
+    (the method with the geodesic step)."""
     wl = configs.water100_small()
-    log("case history agreement water100_small")
-    g, _ = run_gpu_records(wl)
-    r = oracle.transport(wl.phantom, wl.spots, wl.params,
-                         workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()),
+    flags = oracle.ALL & ~oracle.SBM
+    log("case history agreement water100_small geodesic")
+    g, _ = run_gpu_records(wl, flags=flags)
+    params = replace(wl.params, flags=flags)
+    r = oracle.transport(wl.phantom, wl.spots, params,
+                         workloads.nuclear_for_phantom(wl.phantom, params.lattice()),
                          seed=wl.seed, records=True, tally=False)
     a = history_agreement(g, r.records)
     log(f"agreement {a}")

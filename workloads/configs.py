@@ -38,8 +38,8 @@ F_MCS = 4
 F_ELASTIC = 8
 F_INELASTIC = 16
 F_END_OF_RANGE = 32
-F_ALL = 63
 F_SBM = 64
+F_ALL = 127
 
 
 @dataclass(frozen=True)
