@@ -146,7 +146,13 @@ def test_parity_heterogeneous(kind, E):
     _bar(m)
 
 
-def test_launch_shape_invariance():
+@pytest.mark.parametrize("flags", [
+    None,
+    # no residual-range step: the exact-regime small-angle draws (deferred to
+    # the top of the loop) interleave with refills and jump batches
+    oracle.LOSS | oracle.STRAGGLE | oracle.MCS | oracle.SBM | oracle.ELASTIC | oracle.INELASTIC,
+])
+def test_launch_shape_invariance(flags):
     """The tally is bit-identical across block, grid, refill and LDS tile."""
     wl = configs.water100_small(n=4000)
     ref = None
@@ -154,8 +160,8 @@ def test_launch_shape_invariance():
                    {"block": 1024, "grid": 300, "refill": 64, "jump_batch": 64},
                    {"block": 512, "tile_nx": 8, "tile_ny": 8, "tile_nz": 60,
                     "tile_x0": 16, "tile_y0": 16, "tile_z0": 10}):
-        log(f"case launch {launch}")
-        _, tal, led, _ = run_gpu(wl, launch=launch)
+        log(f"case launch {launch} flags {flags}")
+        _, tal, led, _ = run_gpu(wl, flags=flags, launch=launch)
         if ref is None:
             ref = (tal, led)
         else:
