@@ -395,9 +395,44 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     const bool xin = r0 < RP && xx >= 0 && xx < g.W;
     uint4 st[NUR];
     constexpr int kMaxR0 = 255 / RU;   // largest r0, idle threads included
-    const bool interior = CS == CI && x0 >= 1 && x0 + kRX < g.W && y0 >= 1 && y0 + kRY < g.H &&
-                          z0 >= 1 && z0 + kRZ < g.D;   // uniform over the workgroup
-    if (interior) {
+    const bool inner = x0 >= 1 && x0 + kRX < g.W && y0 >= 1 && y0 + kRY < g.H && z0 >= 1 &&
+                       z0 + kRZ < g.D;   // the halo lies inside the volume; uniform
+    const bool interior = CS == CI && inner;
+    if (CS < CI && inner) {
+        if constexpr (CS < CI) {
+            // The concatenation over an interior brick.  With 2 halo rows per
+            // pass and 6 rows per z (asserted), pass u = 3k + j covers the rows
+            // at hzz = k, hyy = r0 + 2j; z0 and y0 are multiples of 4, so the
+            // parent voxel in xl sits at coarse z = z0/2 + ((k - 1) >> 1) and
+            // coarse y = y0/2 - 1 + r0 + j.  Offsets are compile-time multiples
+            // of two strides from a per-thread base: no bounds tests.
+            static_assert(RP == 2 && kRY + 2 == 6 && NROW == 36 && NUR == 18,
+                          "interior concatenation staging assumes 2 halo rows per pass");
+            const bool sk = c < CS;
+            const int rr0 = r0 < RP ? r0 : 0;   // idle threads load nothing
+            const uint16_t* p;
+            int dy, dz;   // element strides of one step in j and in the z term
+            if (sk) {
+                p = x + ((long long)((b * g.D + z0 - 1) * g.H + y0 - 1 + rr0) * g.W + xx) * CS +
+                    c;
+                dy = 2 * g.W * CS;
+                dz = g.H * g.W * CS;
+            } else {
+                const int Dd = g.D >> 1, Hd = g.H >> 1, Wd = g.W >> 1;
+                p = xl + ((long long)((b * Dd + (z0 >> 1)) * Hd + (y0 >> 1) - 1 + rr0) * Wd +
+                          (xx >> 1)) * (CI - CS) + (c - CS);
+                dy = Wd * (CI - CS);
+                dz = Hd * Wd * (CI - CS);
+            }
+#pragma unroll
+            for (int u = 0; u < NUR; ++u) {
+                const int k = u / 3, j = u % 3;
+                const int off = (sk ? k : ((k - 1) >> 1)) * dz + j * dy;
+                st[u] = r0 < RP ? *reinterpret_cast<const uint4*>(p + off)
+                                : make_uint4(0, 0, 0, 0);
+            }
+        }
+    } else if (interior) {
         // the whole halo is inside the volume: no bounds tests, and the offset
         // advances by RP rows per pass (DZ slices and DY rows, wrapping at 6)
         constexpr int DZ = RP / (kRY + 2), DY = RP % (kRY + 2);

@@ -209,12 +209,14 @@ def test_network_forward_and_gradients(levels, B, D, H, W):
     net.close()
 
 
-@pytest.mark.parametrize("levels,B,D,H,W", [(4, 1, 16, 24, 40), (2, 2, 6, 10, 14)])
+@pytest.mark.parametrize("levels,B,D,H,W", [(4, 1, 16, 24, 40), (2, 2, 6, 10, 14),
+                                             (2, 2, 14, 18, 50)])
 def test_inference_reads_the_concatenation_in_place(levels, B, D, H, W):
     """An inference network reads the decoder input concat[skip, up(lower)]
     straight from the two levels; a training network stores it first.  The
     sums are the same in the same order, so the outputs are bit-identical
-    (sizes with ragged 4 x 8 x 8 bricks)."""
+    (sizes with ragged bricks, and with bricks whose halo lies inside the
+    volume, which take the staging path without bounds tests, in a batch of 2)."""
     import torch
     from paper_2511_03115_amd import nn
     c0, cin, alpha = 16, 16, 0.01
