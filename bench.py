@@ -236,17 +236,19 @@ def gamma_leg() -> dict:
 
 
 def hetero_leg(steps: int) -> list:
-    """Throughput on the heterogeneous phantoms: water/bone/lung slabs and the
-    lateral bone insert, 200 mm cubes at 1 mm, 1e7 histories at 100 and
-    150 MeV (the same beam model as the water workload)."""
+    """Throughput on the heterogeneous phantoms: water/bone/lung slabs, the
+    lateral bone insert and the CT-like head (air, bone shell, air cavity),
+    200 mm cubes at 1 mm, 1e7 histories at 100 and 150 MeV (the same beam
+    model as the water workload)."""
     import numpy as np
     import workloads
     from workloads import configs
     from paper_2511_03115_amd import autotune, sde
     out = []
-    for kind in ("slab", "insert"):
+    make = {"slab": configs.slab, "insert": configs.insert, "ct": configs.ct_like}
+    for kind in ("slab", "insert", "ct"):
         for E in (100.0, 150.0):
-            wl = configs.slab(E) if kind == "slab" else configs.insert(E)
+            wl = make[kind](E)
             sde.init_materials(wl.phantom.materials, wl.params,
                                workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
             dph = sde.DevicePhantom.from_host(wl.phantom)

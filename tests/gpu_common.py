@@ -37,14 +37,16 @@ def run_gpu(wl, flags=None, launch=None, n=None, tally=True):
     return (dose.cpu().numpy(), tal.cpu().numpy() if tally else None, res.ledger, res.scale)
 
 
-def run_oracle(wl, flags=None, n=None):
+def run_oracle(wl, flags=None, n=None, energy=False):
+    """(dose, ledger) from the oracle; with energy=True (energy, ledger), the
+    deposited energy per voxel in MeV (weighted like the tally)."""
     params = wl.params if flags is None else replace(wl.params, flags=flags)
     nuc = nuclear_for(wl.phantom, params)
     spots = wl.spots
     if n:
         spots = [replace(spots[0], n_histories=n)]
     r = oracle.transport(wl.phantom, spots, params, nuc, seed=wl.seed)
-    return oracle.dose(r.edep, wl.phantom), r.ledger
+    return (r.edep if energy else oracle.dose(r.edep, wl.phantom)), r.ledger
 
 
 def parity_metrics(d_ref, d_gpu, phantom):

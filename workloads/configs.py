@@ -29,7 +29,7 @@ import numpy as np
 
 from .beams import Spot, single_spot, plan_spots, patch_spots, with_histories
 from .nuclear import EnergyLattice
-from .phantoms import Phantom, water_box, slab_phantom, insert_phantom, grf_phantom
+from .phantoms import Phantom, ct_like_phantom, grf_phantom, insert_phantom, slab_phantom, water_box
 
 # physics switches (bit values shared by both implementations' interfaces)
 F_LOSS = 1
@@ -91,6 +91,12 @@ def slab(E: float = 150.0, n: int = 10_000_000, seed: int = 2, size: int = 200,
 def insert(E: float = 150.0, n: int = 10_000_000, seed: int = 4, size: int = 200,
            depth: int = 200) -> Workload:
     return Workload(f"insert{int(E)}", insert_phantom(size, 0.1, nz=depth),
+                    single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
+
+
+def ct_like(E: float = 150.0, n: int = 10_000_000, seed: int = 7, size: int = 200,
+            depth: int = 200) -> Workload:
+    return Workload(f"ct{int(E)}", ct_like_phantom(size, 0.1, nz=depth),
                     single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
 
 

@@ -9,7 +9,10 @@ below are built from stoichiometry only:
 * water: exact H2O;
 * bone: a 50/50 mass mixture of water and hydroxyapatite Ca10(PO4)6(OH)2,
   a synthetic stand-in (elements H, O, P, Ca), not a database record;
-* lung: H2O composition at lung density.
+* lung: H2O composition at lung density;
+* air: dry air near sea level by mass (N 0.755267, O 0.231781,
+  Ar 0.012827, C 0.000124), 0.001205 g/cm3, I = 85.7 eV (the usual
+  dosimetry values), for the cavities of the CT-like phantom.
 
 Densities and I values are the ones the workloads fix (water 1.0 g/cm3 and
 75 eV, bone 1.85 g/cm3 and 92 eV, lung 0.26 g/cm3 and 75 eV).  Atomic weights
@@ -28,6 +31,7 @@ ELEMENTS: Dict[int, Tuple[str, float]] = {
     7: ("N", 14.007),
     8: ("O", 15.999),
     15: ("P", 30.974),
+    18: ("Ar", 39.948),
     20: ("Ca", 40.078),
 }
 
@@ -84,3 +88,8 @@ def bone() -> Material:
 
 def lung() -> Material:
     return material("lung", _H2O, 75.0, 0.26)
+
+
+def air() -> Material:
+    return material("air", {7: 0.755267, 8: 0.231781, 18: 0.012827, 6: 0.000124}, 85.7,
+                    0.001205)

@@ -17,7 +17,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .materials import Material, water, bone, lung
+from .materials import Material, air, bone, lung, water
 
 
 @dataclass
@@ -84,6 +84,44 @@ def insert_phantom(n: int = 200, d_cm: float = 0.1, z_lo: float = 3.0,
     sel = np.broadcast_to(sel, ph.material_id.shape)
     ph.material_id[sel] = 1
     ph.density[sel] = ph.materials[1].rho_nominal
+    return ph
+
+
+def ct_like_phantom(n: int = 200, d_cm: float = 0.1, nz: int | None = None) -> Phantom:
+    """A CT-like head geometry with sharp density contrasts, the setting the
+    paper names for its next step (voxelised materials, air cavities).
+
+    Materials [water (soft tissue, 1.0), bone (1.85), air (0.001205)].  With
+    L the lateral half-width and the beam along +z on the axis: soft tissue
+    everywhere (the beam enters tissue, as in the paper's phantoms), with an
+    ellipsoid of lateral semi-axes 0.8 L (x) and 0.9 L (y) and depth
+    semi-axis 9 cm centred at z = 10 cm whose outer 0.6 cm is bone (a skull
+    shell); inside it an air cavity (a sinus: semi-axes 0.15 L, 0.12 L,
+    2 cm) centred at (0.05 L, 0, 4.5 cm) lies on the beam path, and a bone
+    block (side 0.1 L) at (-0.12 L, 0.08 L, 7 cm) sits beside it.  Voxel
+    centres decide membership.
+    """
+    ph = _box(n, n, nz or n, d_cm, [water(), bone(), air()])
+    L = 0.5 * n * d_cm
+    xc, yc, zc = ph.centers(0), ph.centers(1), ph.centers(2)
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+
+    def ell(cx, cy, cz, ax, ay, az):
+        return ((X - cx) / ax) ** 2 + ((Y - cy) / ay) ** 2 + ((Z - cz) / az) ** 2 <= 1.0
+
+    mid = np.zeros(ph.material_id.shape, dtype=np.uint8)             # soft tissue
+    head = ell(0.0, 0.0, 10.0, 0.8 * L, 0.9 * L, 9.0)
+    brain = ell(0.0, 0.0, 10.0, 0.8 * L - 0.6, 0.9 * L - 0.6, 9.0 - 0.6)
+    mid[head] = 1                                                     # bone shell
+    mid[brain] = 0                                                    # soft tissue
+    mid[ell(0.05 * L, 0.0, 4.5, 0.15 * L, 0.12 * L, 2.0)] = 2         # sinus
+    h = 0.05 * L
+    block = ((np.abs(X + 0.12 * L) <= h) & (np.abs(Y - 0.08 * L) <= h) &
+             (np.abs(Z - 7.0) <= h))
+    mid[block] = 1
+    ph.material_id[...] = mid
+    ph.density[...] = np.array([m.rho_nominal for m in ph.materials],
+                               dtype=np.float32)[mid]
     return ph
 
 
