@@ -237,9 +237,9 @@ def gamma_leg() -> dict:
 
 def hetero_leg(steps: int) -> list:
     """Throughput on the heterogeneous phantoms: water/bone/lung slabs, the
-    lateral bone insert and the CT-like head (air, bone shell, air cavity),
-    200 mm cubes at 1 mm, 1e7 histories at 100 and 150 MeV (the same beam
-    model as the water workload)."""
+    lateral bone insert and the CT-like head (bone shell, air cavity), 200
+    mm cubes at 1 mm, 1e7 histories at 100 and 150 MeV (the same beam model
+    as the water workload); and a spread-out Bragg peak plan in water."""
     import numpy as np
     import workloads
     from workloads import configs
@@ -267,6 +267,27 @@ def hetero_leg(steps: int) -> list:
                         "kernel_ms": k, "histories_per_s": wl.n_histories / (k * 1e-3),
                         "steps_per_launch": int(led[sde.LEDGER_STEPS]),
                         "jumps_per_launch": int(led[sde.LEDGER_JUMPS]), "launch": launch})
+    # a spread-out Bragg peak plan: 11 layers (87-117 MeV) x 25 spots, 5.5e6 histories
+    wl = configs.sobp(n=5_500_000)
+    sde.init_materials(wl.phantom.materials, wl.params,
+                       workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()))
+    dph = sde.DevicePhantom.from_host(wl.phantom)
+    launch = autotune.tune(wl.spots, dph, wl.seed)
+    plan = sde.Plan(wl.spots, dph, wl.seed, launch=launch)
+    plan.execute(None)
+    ms = []
+    for _ in range(max(1, steps)):
+        plan.execute(None)
+        ms.append(plan.kernel_ms())
+    led, _ = plan.results()
+    plan.close()
+    k = float(np.mean(ms))
+    print(f"[bench] sobp: {k:.2f} ms per launch", flush=True)
+    out.append({"workload": "sobp: 11 layers (6-10 cm peaks, 87-117 MeV) x 5x5 spots, 5.5e6 "
+                            "histories shared like the layer weights, water 80x80x150 mm at 1 mm",
+                "kernel_ms": k, "histories_per_s": wl.n_histories / (k * 1e-3),
+                "steps_per_launch": int(led[sde.LEDGER_STEPS]),
+                "jumps_per_launch": int(led[sde.LEDGER_JUMPS]), "launch": launch})
     return out
 
 

@@ -155,6 +155,23 @@ def test_parity_heterogeneous(kind, E):
     _bar(m)
 
 
+def test_parity_sobp_plan():
+    """A spread-out Bragg peak (11 energy layers of 5 x 5 spots, layer
+    weights for a flat plateau, histories shared like the weights) through
+    the C ABI against the oracle, on deposited energy.  8e6 histories: the
+    field spreads them over ~400 voxel columns, and one history that takes
+    another path after a jump moves its Bragg-peak deposits (10-20 MeV) into
+    other voxels, 3.3e-3 of the peak voxel at 1.4e6 histories, ~6e-4 here."""
+    wl = configs.sobp(n=8_000_000)
+    log(f"case sobp n={wl.n_histories} spots={len(wl.spots)}")
+    d_gpu, tal, led, scale = run_gpu(wl)
+    e_ref, led_ref = run_oracle(wl, energy=True)
+    m = parity_metrics(e_ref, tal.astype(np.float64) / scale, wl.phantom)
+    log(f"metrics {m}")
+    assert abs(led[0] / scale - led_ref[oracle.L_DEP]) <= 1e-4 * led_ref[oracle.L_E0]
+    _bar(m)
+
+
 @pytest.mark.parametrize("flags", [
     None,
     # no residual-range step: the exact-regime small-angle draws (deferred to

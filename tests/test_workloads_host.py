@@ -38,3 +38,51 @@ def test_ct_like_phantom_geometry():
     assert cavity.min() >= 2.5 and cavity.max() <= 6.5
     assert abs((cavity.max() - cavity.min() + 0.1) - 3.87) <= 0.1
     assert (ph.material_id == 1).sum() > 0 and (ph.material_id == 0).sum() > 0
+
+
+def test_sobp_weights_closed_form():
+    """Two peaks: the density (1 - x)^(-1/p) integrated over [0, 1/2] and
+    [1/2, 1] gives 1 - 2^-q and 2^-q (q = 1 - 1/p); eleven peaks: positive,
+    summing to 1, rising from the second to the deepest."""
+    from workloads import beams
+    q = 1 - 1 / 1.77
+    w2 = beams.sobp_weights(2)
+    assert np.allclose(w2, [1 - 0.5 ** q, 0.5 ** q], rtol=0, atol=1e-12)
+    w = beams.sobp_weights(11)
+    assert abs(w.sum() - 1) < 1e-12 and np.all(w > 0) and np.all(np.diff(w[1:]) > 0)
+
+
+def test_sobp_layer_energies_bragg_kleeman():
+    """Layer ranges span [r0 - mod, r0] evenly; each energy gives back its
+    range by R = 0.0022 E^1.77."""
+    from workloads import beams
+    sp = beams.sobp_spots(10.0, 4.0, 11, 5, 0.5, 100_000)
+    e = np.array(sorted({s.E_MeV for s in sp}))
+    assert len(e) == 11 and len(sp) == 11 * 25
+    assert np.allclose(0.0022 * e ** 1.77, np.linspace(6.0, 10.0, 11), rtol=1e-12)
+    assert abs(sum(s.weight for s in sp) - 1.0) < 1e-12
+    # histories shared like the weights: per-history weights within 2 %
+    ph = np.array([s.weight / s.n_histories for s in sp])
+    assert ph.max() / ph.min() < 1.02 and abs(sum(s.n_histories for s in sp) - 100_000) < 300
+
+
+def test_sobp_plateau_flat_with_oracle():
+    """The oracle's central-axis energy deposit (1 cm^2 around the axis,
+    2 mm depth bins) of the SOBP plan is flat within 4 % of its mean over
+    6.5-9 cm (the Bragg-Kleeman energies put the method's peaks slightly
+    deeper, so the last half centimetre falls off); it is about 0.6 of that
+    at 2 cm."""
+    import oracle
+    import workloads
+    wl = configs.sobp(n=275_000)
+    r = oracle.transport(wl.phantom, wl.spots, wl.params,
+                         workloads.nuclear_for_phantom(wl.phantom, wl.params.lattice()),
+                         seed=wl.seed)
+    e = r.edep
+    nz, ny, nx = e.shape
+    c = e[:, ny // 2 - 5:ny // 2 + 5, nx // 2 - 5:nx // 2 + 5].sum(axis=(1, 2))
+    c = c[: nz // 2 * 2].reshape(-1, 2).sum(1)             # 2 mm bins
+    z = (np.arange(len(c)) + 0.5) * 0.2
+    plat = c[(z >= 6.5) & (z <= 9.0)]
+    assert plat.max() / plat.mean() < 1.04 and plat.min() / plat.mean() > 0.96, plat / plat.mean()
+    assert 0.45 < c[int(2.0 / 0.2)] / plat.mean() < 0.75

@@ -88,3 +88,51 @@ def patch_spots(seed: int, n_max: int = 64, pitch_cm: float = 0.5, half_cm: floa
         out.append(Spot(float(E[j]), sigmaE_rel, -half_cm + ix * pitch_cm, -half_cm + iy * pitch_cm,
                         sigma_xy_cm, float(w[j]), 1))
     return out
+
+
+def sobp_weights(n_layers: int, p: float = 1.77) -> np.ndarray:
+    """Relative weights of the Bragg peaks of a spread-out Bragg peak, from
+    the shallowest (index 0) to the deepest (index n_layers - 1).
+
+    With ranges R = alpha E^p (Bragg-Kleeman), a flat dose over the modulated
+    depths needs a continuous weight density proportional to (R0 - r)^(-1/p)
+    in the peak range r (Bortfeld and Schlegel 1996).  Peak k at the
+    normalised position x_k = k / n (n = n_layers - 1) takes that density's
+    integral over [x_k - 1/(2n), x_k + 1/(2n)] clipped to [0, 1] (the
+    discrete form of Jette and Chen 2011); the weights sum to 1.
+    """
+    n = n_layers - 1
+    if n < 1:
+        return np.ones(1)
+    q = 1.0 - 1.0 / p
+    lo = np.clip((np.arange(n_layers) - 0.5) / n, 0.0, 1.0)
+    hi = np.clip((np.arange(n_layers) + 0.5) / n, 0.0, 1.0)
+    w = (1.0 - lo) ** q - (1.0 - hi) ** q
+    return w / w.sum()
+
+
+def sobp_spots(r0_cm: float = 10.0, mod_cm: float = 4.0, n_layers: int = 11,
+               grid: int = 5, pitch_cm: float = 0.5, n_total: int = 550_000,
+               sigmaE_rel: float = 0.01, sigma_xy_cm: float = 0.3,
+               alpha: float = 0.0022, p: float = 1.77) -> List[Spot]:
+    """A spread-out Bragg peak in water: n_layers energy layers whose peaks
+    span ranges [r0 - mod, r0] evenly, each a grid x grid raster of spots
+    (pitch ``pitch_cm``, centred on the axis).  Layer energies from the
+    ranges by Bragg-Kleeman, E = (R / alpha)^(1/p) (water, R in cm); each
+    spot's weight is its layer's ``sobp_weights`` share split evenly over the
+    raster, and its history count the same share of ``n_total``, so that
+    every history carries (about) the same weight.
+    """
+    w = sobp_weights(n_layers, p)
+    ranges = r0_cm - mod_cm + mod_cm * np.arange(n_layers) / max(n_layers - 1, 1)
+    energies = (ranges / alpha) ** (1.0 / p)
+    c = (np.arange(grid) - 0.5 * (grid - 1)) * pitch_cm
+    spots: List[Spot] = []
+    for k in range(n_layers):
+        for y in c:
+            for x in c:
+                share = float(w[k]) / (grid * grid)
+                spots.append(Spot(float(energies[k]), sigmaE_rel, float(x), float(y), sigma_xy_cm,
+                                  share, max(1, int(round(share * n_total)))))
+    return spots
+

@@ -27,7 +27,7 @@ from typing import List
 
 import numpy as np
 
-from .beams import Spot, single_spot, plan_spots, patch_spots, with_histories
+from .beams import Spot, single_spot, plan_spots, patch_spots, sobp_spots, with_histories
 from .nuclear import EnergyLattice
 from .phantoms import Phantom, ct_like_phantom, grf_phantom, insert_phantom, slab_phantom, water_box
 
@@ -98,6 +98,14 @@ def ct_like(E: float = 150.0, n: int = 10_000_000, seed: int = 7, size: int = 20
             depth: int = 200) -> Workload:
     return Workload(f"ct{int(E)}", ct_like_phantom(size, 0.1, nz=depth),
                     single_spot(E, n, sigmaE_rel=0.01, sigma_xy_cm=0.3), seed)
+
+
+def sobp(n: int = 550_000, seed: int = 8, size: int = 80, depth: int = 150) -> Workload:
+    """Spread-out Bragg peak plan in water: 11 energy layers with peaks from 6
+    to 10 cm (about 87-117 MeV), each a 5 x 5 raster at 5 mm, n histories in
+    all shared like the weights, 1 mm voxels."""
+    return Workload("sobp", water_box(size, size, depth, 0.1),
+                    sobp_spots(10.0, 4.0, 11, 5, 0.5, n), seed)
 
 
 def plan(n_spots: int = 1000, n_scale: float = 1.0, seed: int = 6,
