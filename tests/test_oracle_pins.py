@@ -282,7 +282,7 @@ def test_sbm_small_t_moments(t):
     assert abs(m2 / ex2 - 1) < 0.25 * t, m2 / ex2 - 1
 
 
-@pytest.mark.parametrize("t", [0.02, 0.1, 0.5, 2.0])
+@pytest.mark.parametrize("t", [0.02, 0.1, 0.5, 2.0, 20.0])
 def test_sbm_heat_kernel_inversion_moments(t):
     """Exact regime (t at or above the switch): cos(angle) from inverting the
     heat kernel's distribution function, on a stratified grid of u, has the
