@@ -307,6 +307,9 @@ def test_sbm_upper_tail_limits_and_density():
         assert abs(oracle.sbm_upper_tail(t, -1.0) - 1) < 1e-12
         assert abs(oracle.sbm_upper_tail(t, 1.0)) < 1e-12
     assert abs(oracle.sbm_upper_tail(40.0, 0.3) - 0.35) < 1e-12
+    # no time, no motion (either regime's input)
+    ct, st = oracle.sbm_polar(0.0, np.array([-3.0, 0.0, 3.0]), np.array([1e-7, 0.5, 1 - 1e-7]))
+    assert np.all(ct == 1.0) and np.all(st == 0.0)
     t = 0.05
     c = np.linspace(-0.9, 0.99, 7)
     l = np.arange(0, 200)
