@@ -229,6 +229,18 @@ int sde_gamma(const double* ref, const double* eval, int nx, int ny, int nz, dou
               double dy_cm, double dz_cm, double dd, double dta_cm, double thresh,
               int interp, int local, int64_t* counts_out);
 
+/* Kernel test entry point: the polar angle of the small-angle step as the
+ * transport draws it with SDE_SBM (section 2.2.2; spherical Brownian motion
+ * on S^2 at time t[i]: for t < 0.02 Algorithm 1 of Mijatovic et al. with
+ * the lineage count Griffiths' normal rounded, mean + sd * z[i], and
+ * X ~ Beta(1, 1 + M) by inversion of u[i]; else the exact inversion
+ * P(cos <= c) = u[i] of the heat kernel's Legendre series).  t, u, z,
+ * cos_out, sin_out: (device) float arrays of n; u in (0, 1), t >= 0.
+ * Synchronises the stream.  SDE_E_INVALID for n < 0, n > 2^30 or a NULL
+ * pointer with n > 0. */
+int sde_sbm_polar(const float* t, const float* u, const float* z, int64_t n, float* cos_out,
+                  float* sin_out);
+
 /* Launch limits for choosing a configuration: compute units, LDS bytes per
  * workgroup, and LDS bytes the current tables take (0 before
  * sde_init_materials).  Any pointer may be NULL. */

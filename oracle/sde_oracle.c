@@ -447,7 +447,9 @@ static void geodesic_step(double d[3], double sigma_step, double U1, double U2) 
  * Random inputs: z a standard normal (the lineage count, small t only), u a
  * uniform on (0, 1), oriented so that u -> 1 gives the angle -> 0 in both
  * regimes.  The azimuth is the caller's. */
-#define SBM_T_SWITCH 0.02
+/* The regime is a discrete decision: it is taken in single precision, as
+ * the GPU takes it, so that the same t selects the same regime on both sides. */
+#define SBM_T_SWITCH 0.02f
 #define SBM_LEGENDRE_L 64
 
 /* Griffiths' mean of A(t): 2 eta / t with beta = (theta - 1) t / 2 = t / 2 and
@@ -486,7 +488,7 @@ static double sbm_upper_tail(double t, double c) {
 
 static void sbm_polar(double t, double z, double u, double* ct, double* st) {
     if (t <= 0.0) { *ct = 1.0; *st = 0.0; return; }    /* no motion */
-    if (t < SBM_T_SWITCH) {
+    if ((float)t < SBM_T_SWITCH) {
         double M = floor(sbm_lineage_mean(t) + sqrt(sbm_lineage_var(t)) * z + 0.5);
         if (M < 0.0) M = 0.0;
         double X = -expm1(log(u) / (1.0 + M));          /* Beta(1, 1 + M) by inversion */
@@ -615,7 +617,7 @@ void or_turn(double* d, double ct, double st, double phi) { turn(d, ct, st, phi)
 double or_sbm_lineage_mean(double t) { return sbm_lineage_mean(t); }
 double or_sbm_lineage_var(double t) { return sbm_lineage_var(t); }
 double or_sbm_upper_tail(double t, double c) { return sbm_upper_tail(t, c); }
-double or_sbm_t_switch(void) { return SBM_T_SWITCH; }
+double or_sbm_t_switch(void) { return (double)SBM_T_SWITCH; }
 void or_sbm_polar_n(size_t n, double t, const double* z, const double* u, double* ct, double* st) {
     for (size_t i = 0; i < n; ++i) sbm_polar(t, z[i], u[i], &ct[i], &st[i]);
 }

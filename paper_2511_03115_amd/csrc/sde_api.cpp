@@ -551,6 +551,18 @@ int sde_transport(const sde_beam* beam, const sde_phantom* phantom, uint64_t n_h
                             nullptr);
 }
 
+int sde_sbm_polar(const float* t, const float* u, const float* z, int64_t n, float* cos_out,
+                  float* sin_out) {
+    g_err.clear();
+    if (n < 0 || n > (1ll << 30) || (n > 0 && (!t || !u || !z || !cos_out || !sin_out)))
+        return fail(SDE_E_INVALID, "invalid sbm_polar arguments");
+    if (n == 0) return SDE_OK;
+    hipStream_t s = cur_stream();
+    hipError_t e = launch_sbm_polar(t, u, z, (int)n, cos_out, sin_out, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? SDE_OK : fail(SDE_E_HIP, hipGetErrorString(e));
+}
+
 int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
               double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int interp,
               int local, int64_t* counts_out) {

@@ -114,6 +114,8 @@ hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int
                         const double4* offsets, int n_off, double dd, double thr_abs,
                         double max_ref, int local, unsigned long long* counts, hipStream_t s);
 hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s);
+hipError_t launch_sbm_polar(const float* t, const float* u, const float* z, int n, float* c,
+                            float* s_out, hipStream_t s);
 hipError_t transport_kernel_attributes(size_t lds_bytes);
 
 }  // namespace sde

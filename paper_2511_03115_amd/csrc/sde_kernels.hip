@@ -923,6 +923,26 @@ int grid_for(size_t n, int block) {
     return (int)g;
 }
 
+// The small-angle step's polar angle alone, for given times, uniforms and
+// lineage normals (the same device functions as the transport), so that the
+// sampler can be compared with another implementation value by value.
+__global__ void k_sbm_polar(const float* __restrict__ t, const float* __restrict__ u,
+                            const float* __restrict__ z, int n, float* __restrict__ c,
+                            float* __restrict__ s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float ct, st;
+    if (t[i] < kSbmSwitch) {
+        sbm_small(t[i], z[i], u[i], ct, st);
+    } else {
+        const float2 cs = sbm_large(t[i], u[i]);
+        ct = cs.x;
+        st = cs.y;
+    }
+    c[i] = ct;
+    s[i] = st;
+}
+
 }  // namespace
 
 hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox,
@@ -931,6 +951,13 @@ hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox,
     hipLaunchKernelGGL(k_pack, dim3(std::min(grid_for(nvox, 256), 4096)), dim3(256), 0, s, mat,
                        rho, vox, nvox,
                        n_mat, bad, rho_max_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_sbm_polar(const float* t, const float* u, const float* z, int n, float* c,
+                            float* s_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sbm_polar, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, u, z,
+                       n, c, s_out);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ ALL = 127  # the method
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",
            "sde_plan_create", "sde_plan_execute", "sde_plan_results", "sde_plan_destroy",
            "sde_plan_kernel_ms", "sde_plan_set_records", "sde_gamma", "sde_launch_limits",
-           "sde_free", "sde_last_error")
+           "sde_sbm_polar", "sde_free", "sde_last_error")
 
 
 class SdeError(RuntimeError):
@@ -101,6 +101,7 @@ def _load():
     L.sde_gamma.argtypes = [V, V, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                             C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, P(C.c_int64)]
     L.sde_launch_limits.argtypes = [P(C.c_int), P(C.c_int), P(C.c_int)]
+    L.sde_sbm_polar.argtypes = [V, V, V, C.c_int64, V, V]
     L.sde_free.argtypes = []
     L.sde_free.restype = None
     L.sde_last_error.argtypes = []
@@ -304,6 +305,21 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def sbm_polar(t, u, z):
+    """(cos, sin) of the small-angle step's polar angle as the transport draws
+    it with SBM, for float32 device tensors t, u, z of one length."""
+    import torch
+    n = t.numel()
+    assert u.numel() == n and z.numel() == n
+    for a in (t, u, z):
+        assert a.dtype == torch.float32 and a.is_cuda and a.is_contiguous()
+    c = torch.empty_like(t)
+    s = torch.empty_like(t)
+    _check(lib.sde_sbm_polar(C.c_void_p(_dptr(t)), C.c_void_p(_dptr(u)), C.c_void_p(_dptr(z)),
+                             int(n), C.c_void_p(_dptr(c)), C.c_void_p(_dptr(s))))
+    return c, s
 
 
 def gamma(ref, ev, voxel_cm, dd: float = 0.02, dta_cm: float = 0.05, thresh: float = 0.01,

@@ -155,6 +155,44 @@ def test_parity_heterogeneous(kind, E):
     _bar(m)
 
 
+def test_sbm_sampler_matches_oracle():
+    """The small-angle step's polar angle through the C ABI (the transport's
+    device functions) against the oracle's sampler, value by value, on the
+    23-bit uniform grid the transport draws from.  Below t = 0.02 (FP32,
+    Algorithm 1): cos within 2.4e-7 and sin within 5e-6 relative for 99.9 %
+    of the values, every value within one step of the rounded lineage count
+    (sin within 1e-2 relative).  From 0.02 (FP64 inversion of the heat
+    kernel's series, Newton vs the oracle's bisection, rounded to FP32): cos
+    within 2.4e-7 and sin within 1e-4 relative or 1e-6."""
+    import torch
+    from paper_2511_03115_amd import sde
+    rng = np.random.default_rng(31)
+    m = 8000
+    for ts, exact in ((np.geomspace(1e-6, 0.0199, 12), False), (np.geomspace(0.02, 30.0, 12), True)):
+        bad = 0
+        for t in ts:
+            u = (rng.integers(0, 2 ** 23, m) + 0.5) / 2 ** 23
+            z = np.clip(rng.standard_normal(m), -5.77, 5.77)
+            t32 = np.full(m, t, dtype=np.float32)
+            tt = float(t32[0])                      # the oracle sees the same t
+            dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+            c_gpu, s_gpu = sde.sbm_polar(dev(t32), dev(u), dev(z))
+            c_gpu = c_gpu.cpu().numpy().astype(np.float64)
+            s_gpu = s_gpu.cpu().numpy().astype(np.float64)
+            c_ref, s_ref = oracle.sbm_polar(tt, z.astype(np.float32).astype(np.float64),
+                                            u.astype(np.float32).astype(np.float64))
+            dc = np.abs(c_gpu - c_ref)
+            ds = np.abs(s_gpu - s_ref) / np.maximum(s_ref, 1e-30)
+            if exact:
+                assert dc.max() <= 2.4e-7, (t, dc.max())
+                assert np.all((ds <= 1e-4) | (np.abs(s_gpu - s_ref) <= 1e-6)), (t, ds.max())
+            else:
+                bad += int(np.sum((dc > 2.4e-7) | (ds > 5e-6)))
+                assert ds.max() <= 1e-2, (t, ds.max())
+        log(f"sbm sampler {'exact' if exact else 'small-t'}: {bad} of {len(ts) * m} outside")
+        assert bad <= 1e-3 * len(ts) * m
+
+
 def test_parity_sobp_plan():
     """A spread-out Bragg peak (11 energy layers of 5 x 5 spots, layer
     weights for a flat plateau, histories shared like the weights) through

@@ -321,12 +321,13 @@ def test_sbm_upper_tail_limits_and_density():
 
 
 def test_sbm_regimes_meet_at_the_switch():
-    """Just below and at the switch the two regimes give the same E[X] to
-    within the normal law's error there (about -1.6e-3 relative)."""
+    """Just below and at the switch (0.02 in single precision, where the
+    regime is decided) the two regimes give the same E[X] to within the
+    normal law's error there (about -1.6e-3 relative)."""
     ts = oracle.sbm_t_switch()
     z, u, w = _stratified(1024, 2048)
     ex, _ = _sbm_exact_moments(ts)
-    below = np.dot(w, 0.5 * (1 - oracle.sbm_polar(ts * (1 - 1e-9), z, u)[0]))
+    below = np.dot(w, 0.5 * (1 - oracle.sbm_polar(ts * (1 - 1e-6), z, u)[0]))
     # the exact regime does not read z: one row of the grid suffices
     at = np.dot(w[:2048] * 1024, 0.5 * (1 - oracle.sbm_polar(ts, z[:2048], u[:2048])[0]))
     assert abs(at / ex - 1) < 2e-5
