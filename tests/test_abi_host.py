@@ -75,6 +75,11 @@ def test_host_validation_without_gpu(lib):
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(bad), None) == sde.E_INVALID
     lib.sde_last_error.restype = C.c_char_p
     assert b"invalid physics parameters" in lib.sde_last_error()
+    # the sampler's test entry point checks its arguments before any device call
+    lib.sde_sbm_polar.argtypes = [C.c_void_p] * 3 + [C.c_int64] + [C.c_void_p] * 2
+    assert lib.sde_sbm_polar(None, None, None, 5, None, None) == sde.E_INVALID
+    assert lib.sde_sbm_polar(None, None, None, -1, None, None) == sde.E_INVALID
+    assert lib.sde_sbm_polar(None, None, None, 0, None, None) == sde.OK
     # physics switch bits other than SDE_ALL | SDE_SBM
     unk = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63 | 128, 65536)
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(unk), None) == sde.E_INVALID
