@@ -138,6 +138,16 @@ def lib():
         L.or_philox4x32_10.restype = None
         L.or_philox4x64_10.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
         L.or_philox4x64_10.restype = None
+        L.or_source_n.argtypes = [P(SpotS), d, C.c_uint64, C.c_uint64, C.c_size_t, P(d)]
+        L.or_source_n.restype = None
+        L.or_lattice_pos.argtypes = [P(Nuclear), d, P(C.c_int), P(d)]
+        L.or_lattice_pos.restype = None
+        L.or_inelastic_sigma_barn.argtypes = [P(Nuclear), C.c_int, d]
+        L.or_inelastic_sigma_barn.restype = d
+        L.or_table_eu.argtypes = [P(Nuclear), C.c_int, C.c_int, d, d]
+        L.or_table_eu.restype = d
+        L.or_inelastic_draw.argtypes = [P(Nuclear), C.c_int, d, d, d, P(d), P(d)]
+        L.or_inelastic_draw.restype = None
         L.or_transport.argtypes = [P(Material), C.c_int, P(Params), P(Nuclear), P(PhantomS),
                                    P(SpotS), C.c_int, C.c_uint64, C.c_uint64, C.c_uint64,
                                    C.c_int, P(d), P(d), P(d)]
@@ -372,6 +382,40 @@ def rng_block(seed: int, h: int, n: int, b: int) -> List[int]:
     o = (C.c_uint32 * 4)()
     lib().or_rng_block(C.c_uint64(seed), C.c_uint64(h), C.c_uint32(n), C.c_uint32(b), o)
     return list(o)
+
+
+def source(spot, z0_cm: float, seed: int, h0: int, n: int) -> np.ndarray:
+    """Source (E, x, y, z) of histories [h0, h0 + n) of one spot, (n, 4)."""
+    out = np.zeros((int(n), 4), dtype=np.float64)
+    sp = spots_struct([spot])
+    lib().or_source_n(sp, float(z0_cm), C.c_uint64(seed), C.c_uint64(h0), int(n),
+                      _ptr(out, C.c_double))
+    return out
+
+
+class NuclearView:
+    """The oracle's view of a workloads NuclearTables, for the inelastic pins."""
+
+    def __init__(self, nt):
+        self.s, self._keep = nuclear_struct(nt)
+
+    def lattice_pos(self, E: float):
+        i, f = C.c_int(0), C.c_double(0.0)
+        lib().or_lattice_pos(C.byref(self.s), float(E), C.byref(i), C.byref(f))
+        return i.value, f.value
+
+    def sigma_barn(self, t: int, E: float) -> float:
+        return lib().or_inelastic_sigma_barn(C.byref(self.s), int(t), float(E))
+
+    def table(self, t: int, which: str, E: float, x: float) -> float:
+        k = {"u": 0, "r": 1, "a": 2}[which]
+        return lib().or_table_eu(C.byref(self.s), int(t), k, float(E), float(x))
+
+    def draw(self, t: int, E: float, U1: float, U3: float):
+        u, c = C.c_double(0.0), C.c_double(0.0)
+        lib().or_inelastic_draw(C.byref(self.s), int(t), float(E), float(U1), float(U3),
+                                C.byref(u), C.byref(c))
+        return u.value, c.value
 
 
 def channel_total_rate(m, params, rho: float, E: float, nuclear=None, flags=None) -> float:

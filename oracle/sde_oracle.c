@@ -369,6 +369,22 @@ static double kalbach_mu(double a, double r, double U) {
     return mu;
 }
 
+/* Inelastic event of element table t at E (section 2.1, inelastic
+ * proton-nucleus interactions): the loss fraction u from the pi_ne inverse
+ * CDF at U1 (linear in E on the lattice and in U), then the CM cosine from
+ * the Kalbach-Mann law with r(E, u) and a(E, u) at U3. */
+static void inelastic_draw(const or_nuclear* nu, int t, double E, double U1, double U3,
+                           double* u_loss, double* cos_cm) {
+    size_t off = (size_t)t * nu->n_e * nu->n_u;
+    double u = table_eu(nu, nu->u_icdf + off, E, U1);
+    if (u < 0.0) u = 0.0;
+    if (u > 1.0) u = 1.0;
+    double a = table_eu(nu, nu->ka + off, E, u);
+    double r = table_eu(nu, nu->kr + off, E, u);
+    *u_loss = u;
+    *cos_cm = kalbach_mu(a, r, U3);
+}
+
 /* CM -> lab polar angle, Appendix A.1, Eq. (cm_to_lab):
  *   tan(theta_L) = sin(theta_CM) / (gamma_u (cos(theta_CM) + u / v'_1C)),
  * taken with atan2.  m1 = m_p, m2 = A amu, K = E_n, outgoing lab energy
@@ -447,9 +463,9 @@ static void geodesic_step(double d[3], double sigma_step, double U1, double U2) 
  * Random inputs: z a standard normal (the lineage count, small t only), u a
  * uniform on (0, 1), oriented so that u -> 1 gives the angle -> 0 in both
  * regimes.  The azimuth is the caller's. */
-/* The regime is a discrete decision: it is taken in single precision, as
- * the GPU takes it, so that the same t selects the same regime on both sides. */
-#define SBM_T_SWITCH 0.02f
+/* The regime switch is the implementation's choice (the paper cites the
+ * sampler, not a switch); the decision is taken on t in double precision. */
+#define SBM_T_SWITCH 0.02
 #define SBM_LEGENDRE_L 64
 
 /* Griffiths' mean of A(t): 2 eta / t with beta = (theta - 1) t / 2 = t / 2 and
@@ -488,7 +504,7 @@ static double sbm_upper_tail(double t, double c) {
 
 static void sbm_polar(double t, double z, double u, double* ct, double* st) {
     if (t <= 0.0) { *ct = 1.0; *st = 0.0; return; }    /* no motion */
-    if ((float)t < SBM_T_SWITCH) {
+    if (t < SBM_T_SWITCH) {
         double M = floor(sbm_lineage_mean(t) + sqrt(sbm_lineage_var(t)) * z + 0.5);
         if (M < 0.0) M = 0.0;
         double X = -expm1(log(u) / (1.0 + M));          /* Beta(1, 1 + M) by inversion */
@@ -617,9 +633,23 @@ void or_turn(double* d, double ct, double st, double phi) { turn(d, ct, st, phi)
 double or_sbm_lineage_mean(double t) { return sbm_lineage_mean(t); }
 double or_sbm_lineage_var(double t) { return sbm_lineage_var(t); }
 double or_sbm_upper_tail(double t, double c) { return sbm_upper_tail(t, c); }
-double or_sbm_t_switch(void) { return (double)SBM_T_SWITCH; }
+double or_sbm_t_switch(void) { return SBM_T_SWITCH; }
 void or_sbm_polar_n(size_t n, double t, const double* z, const double* u, double* ct, double* st) {
     for (size_t i = 0; i < n; ++i) sbm_polar(t, z[i], u[i], &ct[i], &st[i]);
+}
+/* Inelastic-branch pieces, exported for the pins. */
+void or_lattice_pos(const or_nuclear* nu, double E, int* i, double* f) { lattice_pos(nu, E, i, f); }
+double or_inelastic_sigma_barn(const or_nuclear* nu, int t, double E) {
+    return inelastic_sigma_barn(nu, t, E);
+}
+void or_inelastic_draw(const or_nuclear* nu, int t, double E, double U1, double U3,
+                       double* u_loss, double* cos_cm) {
+    inelastic_draw(nu, t, E, U1, U3, u_loss, cos_cm);
+}
+/* which: 0 = loss-fraction inverse CDF, 1 = Kalbach r, 2 = Kalbach a */
+double or_table_eu(const or_nuclear* nu, int t, int which, double E, double x) {
+    const double* base = which == 0 ? nu->u_icdf : which == 1 ? nu->kr : nu->ka;
+    return table_eu(nu, base + (size_t)t * nu->n_e * nu->n_u, E, x);
 }
 double or_channel_total_rate(const or_material* m, const or_nuclear* nu, const or_params* p,
                              double rho, double E) {
@@ -684,6 +714,32 @@ static void deposit(const or_phantom* ph, score_ctx* sc, const double at[3], dou
     }
 }
 
+/* Source of history h (the workloads' Gaussian pencil beam; the paper's
+ * own beam is a monoenergetic nozzle, section 2.2.2): energy
+ * E_s (1 + sigma_E Z3) and lateral position (x_s, y_s) + sigma_xy (Z1, Z2)
+ * on the entrance face z0, direction +z.  Block (h, 2^32-1, 0): the
+ * Box-Muller pair (cos, sin) of (w0, w1) gives Z1, Z2, and (w2, w3) gives
+ * Z3 by its cosine. */
+static void source(const or_spot* sp, double z0, uint64_t seed, uint64_t h, double* E,
+                   double R[3]) {
+    uint32_t w[4];
+    rng_block(seed, h, 0xFFFFFFFFu, 0, w);
+    double rr = sqrt(-2.0 * log(u_hi(w[0])));
+    double z1 = rr * cos(TWO_PI * u_hi(w[1])), z2 = rr * sin(TWO_PI * u_hi(w[1]));
+    double z3 = sqrt(-2.0 * log(u_hi(w[2]))) * cos(TWO_PI * u_hi(w[3]));
+    *E = sp->E * (1.0 + sp->sigmaE * z3);
+    R[0] = sp->x + sp->sigma_xy * z1;
+    R[1] = sp->y + sp->sigma_xy * z2;
+    R[2] = z0;
+}
+
+/* Exported for the pins: source energy and position of histories
+ * [h0, h0 + n) of one spot; out is n x 4 (E, x, y, z). */
+void or_source_n(const or_spot* sp, double z0, uint64_t seed, uint64_t h0, size_t n,
+                 double* out) {
+    for (size_t i = 0; i < n; ++i) source(sp, z0, seed, h0 + i, &out[4 * i], &out[4 * i + 1]);
+}
+
 /* One sequential proton track, Eq. (VSDE) with the jump law of Eq. (Npi),
  * until it leaves D, falls below e_min, or ends its range.  Coefficients
  * are taken at Y_n: the material and density of the voxel holding R_n and
@@ -694,15 +750,8 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
     const double D = p->step_cm;
     uint32_t w[4];
 
-    /* Source: Gaussian energy and lateral position on the entrance face,
-     * direction +z.  Block (h, 2^32-1, 0): Box-Muller pairs from (w0, w1)
-     * for x, y and from (w2, w3) for the energy. */
-    rng_block(seed, h, 0xFFFFFFFFu, 0, w);
-    double rr = sqrt(-2.0 * log(u_hi(w[0])));
-    double z1 = rr * cos(TWO_PI * u_hi(w[1])), z2 = rr * sin(TWO_PI * u_hi(w[1]));
-    double z3 = sqrt(-2.0 * log(u_hi(w[2]))) * cos(TWO_PI * u_hi(w[3]));
-    double E = sp->E * (1.0 + sp->sigmaE * z3);
-    double R[3] = {sp->x + sp->sigma_xy * z1, sp->y + sp->sigma_xy * z2, ph->origin[2]};
+    double E, R[3];
+    source(sp, ph->origin[2], seed, h, &E, R);
     double O[3] = {0.0, 0.0, 1.0};
     sc->hist[R_E0] = E;
 
@@ -790,14 +839,7 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
                     }
                     sc->hist[R_NEL] += 1.0;
                 } else {
-                    int tb = ch.tab[c];
-                    size_t off = (size_t)tb * nu->n_e * nu->n_u;
-                    u_loss = table_eu(nu, nu->u_icdf + off, E, u_hi(q[1]));
-                    if (u_loss < 0.0) u_loss = 0.0;
-                    if (u_loss > 1.0) u_loss = 1.0;
-                    double a = table_eu(nu, nu->ka + off, E, u_loss);
-                    double r = table_eu(nu, nu->kr + off, E, u_loss);
-                    cos_cm = kalbach_mu(a, r, u_hi(q[3]));
+                    inelastic_draw(nu, ch.tab[c], E, u_hi(q[1]), u_hi(q[3]), &u_loss, &cos_cm);
                     sin_cm = sqrt(fmax(0.0, 1.0 - cos_cm * cos_cm));
                     sc->hist[R_NNE] += 1.0;
                 }

@@ -321,9 +321,9 @@ def test_sbm_upper_tail_limits_and_density():
 
 
 def test_sbm_regimes_meet_at_the_switch():
-    """Just below and at the switch (0.02 in single precision, where the
-    regime is decided) the two regimes give the same E[X] to within the
-    normal law's error there (about -1.6e-3 relative)."""
+    """Just below and at the switch (t = 0.02, decided in double precision)
+    the two regimes give the same E[X] to within the normal law's error
+    there (about -1.6e-3 relative)."""
     ts = oracle.sbm_t_switch()
     z, u, w = _stratified(1024, 2048)
     ex, _ = _sbm_exact_moments(ts)
