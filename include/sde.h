@@ -53,7 +53,7 @@ typedef enum {
 #define SDE_MAX_MAT 8     /* materials per phantom (LDS table budget) */
 
 /* Physics switches (sde_physics_params.flags).  SDE_ALL is the method;
- * other bits are rejected. */
+ * bits other than these and SDE_FP64 are rejected. */
 #define SDE_LOSS 1u          /* continuous loss, Eq. (bethbloch) */
 #define SDE_STRAGGLE 2u      /* straggling noise, Eq. (energystraggling) */
 #define SDE_MCS 4u           /* small-angle diffusion on S^2 */
@@ -68,6 +68,14 @@ typedef enum {
  * from that law in the angle; ~2 % less time on a 150 MeV water beam). */
 #define SDE_SBM 64u
 #define SDE_ALL 127u
+/* Not a physics switch: step in double precision.  The same kernel source
+ * instantiated on double, with the Lynch-Dahl width and the elastic jump
+ * rate evaluated from their formulas at each step instead of interpolated
+ * from the FP32 lattice tables (section 2.1.4), so that histories follow a
+ * double-precision reference step by step; for checks against such a
+ * reference, several times slower than the default single-precision
+ * stepping.  Combines with any set of the switches above. */
+#define SDE_FP64 128u
 
 /* Ledger slots (sde_transport_ex ledger_out) */
 #define SDE_LEDGER_DEPOSITED 0   /* energy scored inside the phantom (fixed point) */
@@ -240,6 +248,17 @@ int sde_gamma(const double* ref, const double* eval, int nx, int ny, int nz, dou
  * pointer with n > 0. */
 int sde_sbm_polar(const float* t, const float* u, const float* z, int64_t n, float* cos_out,
                   float* sin_out);
+
+/* Kernel test entry point: the transport's random numbers.  For i < count,
+ * words_out[4i..4i+3] (device, 16-byte aligned) receives the Philox4x32-10
+ * block (Salmon et al., SC'11; ten rounds) with key (seed low, seed high)
+ * and counter (h[i] low, h[i] high, n[i], b[i]), the stream the transport
+ * reads for history h, step n and block b (the source uses n = 2^32 - 1).
+ * h, n, b: (device) arrays of count.  Synchronises the stream.
+ * SDE_E_INVALID for count < 0, count > 2^30, a NULL or misaligned array
+ * with count > 0. */
+int sde_philox_words(uint64_t seed, const uint64_t* h, const uint32_t* n, const uint32_t* b,
+                     int64_t count, uint32_t* words_out);
 
 /* Launch limits for choosing a configuration: compute units, LDS bytes per
  * workgroup, and LDS bytes the current tables take (0 before

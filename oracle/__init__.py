@@ -134,6 +134,9 @@ def lib():
         L.or_rng_block.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
                                    P(C.c_uint32)]
         L.or_rng_block.restype = None
+        L.or_rng_blocks.argtypes = [C.c_uint64, C.c_size_t, P(C.c_uint64), P(C.c_uint32),
+                                    P(C.c_uint32), P(C.c_uint32)]
+        L.or_rng_blocks.restype = None
         L.or_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         L.or_philox4x32_10.restype = None
         L.or_philox4x64_10.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
@@ -194,7 +197,8 @@ def params_struct(p, flags: Optional[int] = None) -> Params:
     s.e_min, s.e_max = p.e_min_MeV, p.e_max_MeV
     s.ld_F, s.theta_cut, s.theta_bs = p.ld_F, p.theta_cut_rad, p.backscatter_cut_rad
     s.max_steps = int(p.max_steps)
-    s.flags = int(p.flags if flags is None else flags)
+    # the oracle always steps in double precision: only the physics switches count
+    s.flags = int(p.flags if flags is None else flags) & ALL
     return s
 
 
@@ -416,6 +420,17 @@ class NuclearView:
         lib().or_inelastic_draw(C.byref(self.s), int(t), float(E), float(U1), float(U3),
                                 C.byref(u), C.byref(c))
         return u.value, c.value
+
+
+def rng_blocks(seed: int, h: np.ndarray, n: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 blocks (count, 4) uint32 for counters (h, n, b)."""
+    h = np.ascontiguousarray(h, dtype=np.uint64)
+    n = np.ascontiguousarray(n, dtype=np.uint32)
+    b = np.ascontiguousarray(b, dtype=np.uint32)
+    out = np.zeros((h.size, 4), dtype=np.uint32)
+    lib().or_rng_blocks(C.c_uint64(seed), h.size, _ptr(h, C.c_uint64), _ptr(n, C.c_uint32),
+                        _ptr(b, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
 
 
 def channel_total_rate(m, params, rho: float, E: float, nuclear=None, flags=None) -> float:

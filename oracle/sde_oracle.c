@@ -145,6 +145,10 @@ static double u_lo(uint32_t w0, uint32_t w1, uint32_t w2) {
 void or_rng_block(uint64_t seed, uint64_t h, uint32_t n, uint32_t b, uint32_t* w) {
     rng_block(seed, h, n, b, w);
 }
+void or_rng_blocks(uint64_t seed, size_t count, const uint64_t* h, const uint32_t* n,
+                   const uint32_t* b, uint32_t* w) {
+    for (size_t i = 0; i < count; ++i) rng_block(seed, h[i], n[i], b[i], w + 4 * i);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Kinematics                                                               */

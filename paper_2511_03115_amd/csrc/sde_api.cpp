@@ -19,6 +19,14 @@ namespace {
 
 thread_local std::string g_err;
 
+struct GammaKey {
+    int interp = 0;
+    double dta = 0, dx = 0, dy = 0, dz = 0;
+    bool operator==(const GammaKey& o) const {
+        return interp == o.interp && dta == o.dta && dx == o.dx && dy == o.dy && dz == o.dz;
+    }
+};
+
 struct State {
     bool ready = false;
     HostTables host;
@@ -26,6 +34,14 @@ struct State {
     double2* rg64 = nullptr;
     MatDev* mats = nullptr;
     float *nuc_sigma = nullptr, *nuc_u = nullptr, *nuc_r = nullptr, *nuc_a = nullptr;
+    MatDev64* mats64 = nullptr;
+    double2* hot64 = nullptr;
+    double *nuc_sigma64 = nullptr, *nuc_u64 = nullptr, *nuc_r64 = nullptr, *nuc_a64 = nullptr;
+    // gamma: offsets of the last lattice and the counters
+    double4* gam_off = nullptr;
+    int gam_cap = 0, gam_n = 0;
+    GammaKey gam_key{};
+    unsigned long long* gam_buf = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t own = nullptr;   // for graph capture when the caller uses the null stream
     int n_cu = 0;
@@ -60,6 +76,12 @@ void release_tables() {
     dfree(g.nuc_u);
     dfree(g.nuc_r);
     dfree(g.nuc_a);
+    dfree(g.mats64);
+    dfree(g.hot64);
+    dfree(g.nuc_sigma64);
+    dfree(g.nuc_u64);
+    dfree(g.nuc_r64);
+    dfree(g.nuc_a64);
     g.ready = false;
 }
 
@@ -101,6 +123,7 @@ struct sde_plan {
     unsigned long long* counter = nullptr;
     unsigned int* bad = nullptr;    // [1 + kMaxMat]: invalid-voxel count, per-material max density
     SpotDev* spots = nullptr;
+    SpotDev64* spots64 = nullptr;
     unsigned long long* prefix = nullptr;
     size_t nvox = 0;
     int n_rep = 1;
@@ -128,6 +151,7 @@ void plan_free(sde_plan* p) {
     dfree(p->counter);
     dfree(p->bad);
     dfree(p->spots);
+    dfree(p->spots64);
     dfree(p->prefix);
     delete p;
 }
@@ -226,13 +250,15 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
         return beam->spots[a].E_MeV > beam->spots[b].E_MeV;
     });
     std::vector<SpotDev> sd(ns);
+    std::vector<SpotDev64> sd64(ns);
     std::vector<unsigned long long> pre(ns + 1, 0);   // prefix in claim order
     for (int k = 0; k < ns; ++k) {
         const int i = order[k];
         const sde_spot& s = beam->spots[i];
+        const double wsc = counts[i] ? s.weight / (double)counts[i] * scale : 0.0;
         sd[k] = SpotDev{(float)s.E_MeV, (float)s.sigmaE_rel, (float)s.x_cm, (float)s.y_cm,
-                        (float)s.sigma_xy_cm,
-                        counts[i] ? (float)(s.weight / (double)counts[i] * scale) : 0.f, h0[i]};
+                        (float)s.sigma_xy_cm, (float)wsc, h0[i]};
+        sd64[k] = SpotDev64{s.E_MeV, s.sigmaE_rel, s.x_cm, s.y_cm, s.sigma_xy_cm, wsc, h0[i]};
         pre[k + 1] = pre[k] + counts[i];
     }
     auto bail = [&](int rc) {
@@ -241,6 +267,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     };
     int rc;
     if ((rc = upload(&p->spots, sd)) != SDE_OK) return bail(rc);
+    if ((rc = upload(&p->spots64, sd64)) != SDE_OK) return bail(rc);
     if ((rc = upload(&p->prefix, pre)) != SDE_OK) return bail(rc);
     hipError_t e;
     if ((e = hipMalloc((void**)&p->vox, sizeof(uint2) * nvox)) != hipSuccess ||
@@ -328,38 +355,72 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     kp.n_e = T.n_e;
     kp.n_u = T.n_u;
     kp.n_tab = T.n_tab;
-    kp.ln_e_lo = (float)T.ln_e_lo;
-    kp.inv_dln = (float)(1.0 / T.dln);
-    kp.ln_e_lo_d = T.ln_e_lo;
-    kp.inv_dln_d = 1.0 / T.dln;
-    kp.step_d = pp.step_cm;
-    kp.step = (float)pp.step_cm;
-    kp.half_step = (float)(0.5 * pp.step_cm);
-    kp.sqrt_step = (float)std::sqrt(pp.step_cm);
-    kp.e_min = (float)pp.e_min_MeV;
-    kp.c_bethe = (float)kBethe;
-    kp.c_strag = (float)T.c_strag;
-    kp.ruth_T = (float)T.ruth_T;
-    kp.mott_lo = (float)T.mott_lo;
-    kp.mott_hi = (float)T.mott_hi;
-    kp.mott_D0 = (float)T.mott_D0;
-    kp.mott_Lhi = (float)T.mott_Lhi;
-    kp.mott_Llo = (float)T.mott_Llo;
-    kp.eta_pre = (float)(kAlpha * std::sqrt(0.5 * kMp));
-    kp.flags = pp.flags;
+    kp.mats64 = g.mats64;
+    kp.hot64 = g.hot64;
+    kp.nuc_sigma64 = g.nuc_sigma64;
+    kp.nuc_u64 = g.nuc_u64;
+    kp.nuc_r64 = g.nuc_r64;
+    kp.nuc_a64 = g.nuc_a64;
+    // scheme and geometry scalars, in double and rounded to float
+    KScal<double>& S = kp.sd;
+    S.step = pp.step_cm;
+    S.half_step = 0.5 * pp.step_cm;
+    S.sqrt_step = std::sqrt(pp.step_cm);
+    S.e_min = pp.e_min_MeV;
+    S.c_bethe = kBethe;
+    S.c_strag = T.c_strag;
+    S.ruth_T = T.ruth_T;
+    S.mott_lo = T.mott_lo;
+    S.mott_hi = T.mott_hi;
+    S.mott_D0 = T.mott_D0;
+    S.mott_Lhi = T.mott_Lhi;
+    S.mott_Llo = T.mott_Llo;
+    S.eta_pre = kAlpha * std::sqrt(0.5 * kMp);
+    S.ln_e_lo = T.ln_e_lo;
+    S.inv_dln = 1.0 / T.dln;
+    S.ld_z = pp.ld_z_cm;
+    S.ld_F = pp.ld_F;
+    const double d[3] = {ph->dx_cm, ph->dy_cm, ph->dz_cm};
+    const int nn[3] = {ph->nx, ph->ny, ph->nz};
+    for (int a = 0; a < 3; ++a) {
+        S.lo[a] = ph->origin_cm[a];
+        S.hi[a] = ph->origin_cm[a] + nn[a] * d[a];
+        S.d[a] = d[a];
+        S.inv_d[a] = 1.0 / d[a];
+    }
+    KScal<float>& F = kp.sf;
+    F.step = (float)S.step;
+    F.half_step = (float)S.half_step;
+    F.sqrt_step = (float)S.sqrt_step;
+    F.e_min = (float)S.e_min;
+    F.c_bethe = (float)S.c_bethe;
+    F.c_strag = (float)S.c_strag;
+    F.ruth_T = (float)S.ruth_T;
+    F.mott_lo = (float)S.mott_lo;
+    F.mott_hi = (float)S.mott_hi;
+    F.mott_D0 = (float)S.mott_D0;
+    F.mott_Lhi = (float)S.mott_Lhi;
+    F.mott_Llo = (float)S.mott_Llo;
+    F.eta_pre = (float)S.eta_pre;
+    F.ln_e_lo = (float)S.ln_e_lo;
+    F.inv_dln = (float)S.inv_dln;
+    F.ld_z = (float)S.ld_z;
+    F.ld_F = (float)S.ld_F;
+    for (int a = 0; a < 3; ++a) {
+        F.lo[a] = (float)S.lo[a];
+        F.hi[a] = (float)S.hi[a];
+        F.d[a] = (float)S.d[a];
+        F.inv_d[a] = (float)S.inv_d[a];
+    }
+    kp.flags = pp.flags & SDE_ALL;
+    kp.fp64 = (pp.flags & SDE_FP64) ? 1 : 0;
     kp.max_steps = pp.max_steps;
     kp.vox = p->vox;
     kp.nx = ph->nx;
     kp.ny = ph->ny;
     kp.nz = ph->nz;
-    const double d[3] = {ph->dx_cm, ph->dy_cm, ph->dz_cm};
-    const int nn[3] = {ph->nx, ph->ny, ph->nz};
-    for (int a = 0; a < 3; ++a) {
-        kp.lo[a] = (float)ph->origin_cm[a];
-        kp.hi[a] = (float)(ph->origin_cm[a] + nn[a] * d[a]);
-        kp.inv_d[a] = (float)(1.0 / d[a]);
-    }
     kp.spots = p->spots;
+    kp.spots64 = p->spots64;
     kp.prefix = p->prefix;
     kp.n_spots = ns;
     kp.n_hist = total;
@@ -401,6 +462,87 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     return SDE_OK;
 }
 
+// Gamma index: argument checks, the offset lattice, and the launch sequence
+// shared by sde_gamma and sde_gamma_noalloc.
+int gamma_check(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
+                double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int interp,
+                const int64_t* counts_out) {
+    if (!ref || !ev || !counts_out || nx < 1 || ny < 1 || nz < 1 || !(dx_cm > 0) ||
+        !(dy_cm > 0) || !(dz_cm > 0) || !(dd > 0) || !(dta_cm > 0) || !(thresh >= 0) ||
+        interp < 1 || interp > 50 || (double)nx * ny * nz >= 9.0e15)
+        return fail(SDE_E_INVALID, "invalid gamma arguments");
+    return SDE_OK;
+}
+
+// Lattice offsets (a, b, c) of spacing dta/interp within dta (the squared
+// length tested in double precision, as the definition evaluates it), with
+// w = a^2 + b^2 + c^2, sorted by (w, a, b, c): nearest first, a fixed order.
+// Writes at most cap entries and returns the count (> cap: out is partial).
+int gamma_lattice(int interp, double dta_cm, int4* out, int cap) {
+    const double st = dta_cm / interp;
+    int n = 0;
+    for (int a = -interp; a <= interp; ++a)
+        for (int b = -interp; b <= interp; ++b)
+            for (int c = -interp; c <= interp; ++c) {
+                const double ox = a * st, oy = b * st, oz = c * st;
+                if (ox * ox + oy * oy + oz * oz <= dta_cm * dta_cm * (1.0 + 1e-12)) {
+                    if (n < cap) out[n] = make_int4(a, b, c, a * a + b * b + c * c);
+                    ++n;
+                }
+            }
+    if (n <= cap)
+        std::sort(out, out + n, [](const int4& u, const int4& v) {
+            if (u.w != v.w) return u.w < v.w;
+            if (u.x != v.x) return u.x < v.x;
+            if (u.y != v.y) return u.y < v.y;
+            return u.z < v.z;
+        });
+    return n;
+}
+
+// (ox / dx, oy / dy, oz / dz, |o|^2 / dta^2) per lattice offset, each in the
+// operations of the definition (so a kernel adding them to a voxel index
+// evaluates the same points).
+void gamma_offsets(const int4* lat, int n, int interp, double dta_cm, double dx_cm, double dy_cm,
+                   double dz_cm, double4* out) {
+    const double st = dta_cm / interp;
+    for (int k = 0; k < n; ++k) {
+        const double ox = lat[k].x * st, oy = lat[k].y * st, oz = lat[k].z * st;
+        out[k] = make_double4(ox / dx_cm, oy / dy_cm, oz / dz_cm,
+                              (ox * ox + oy * oy + oz * oz) / (dta_cm * dta_cm));
+    }
+}
+
+// Counters and maximum into buf[0..2], then the gamma kernel; reads the
+// counts back (synchronises the stream).
+int gamma_run(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
+              double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int local,
+              const double4* doff, int n_off, unsigned long long* buf, int64_t* counts_out) {
+    const size_t nvox = (size_t)nx * ny * nz;
+    hipStream_t s = cur_stream();
+    unsigned long long host[3] = {0, 0, 0};
+    hipError_t e;
+    if ((e = launch_zero_u64(buf, 3, s)) != hipSuccess ||
+        (e = launch_max(ref, nvox, buf + 2, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(host, buf, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(SDE_E_HIP, hipGetErrorString(e));
+    double mx;
+    std::memcpy(&mx, &host[2], sizeof mx);
+    // the bound needs the search box inside the 8 cells around a voxel
+    const double rx = dta_cm / dx_cm, ry = dta_cm / dy_cm, rz = dta_cm / dz_cm;
+    const int use_bound = (rx <= 1.0 && ry <= 1.0 && rz <= 1.0) ? 1 : 0;
+    if ((e = launch_gamma(ref, ev, nx, ny, nz, doff, n_off, dd, thresh * mx, mx, local, rx, ry,
+                          rz, use_bound, buf, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(host, buf, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(SDE_E_HIP, hipGetErrorString(e));
+    counts_out[0] = (int64_t)host[0];
+    counts_out[1] = (int64_t)host[1];
+    return SDE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -418,7 +560,10 @@ int sde_init_materials(const sde_material_desc* mats, int n_mats, const sde_phys
     if ((r = upload(&g.hot, T.hot)) || (r = upload(&g.rg64, T.rg64)) ||
         (r = upload(&g.mats, T.mats)) || (r = upload(&g.nuc_sigma, T.nuc_sigma)) ||
         (r = upload(&g.nuc_u, T.nuc_u)) || (r = upload(&g.nuc_r, T.nuc_r)) ||
-        (r = upload(&g.nuc_a, T.nuc_a))) {
+        (r = upload(&g.nuc_a, T.nuc_a)) || (r = upload(&g.mats64, T.mats64)) ||
+        (r = upload(&g.hot64, T.hot64)) || (r = upload(&g.nuc_sigma64, T.nuc_sigma64)) ||
+        (r = upload(&g.nuc_u64, T.nuc_u64)) || (r = upload(&g.nuc_r64, T.nuc_r64)) ||
+        (r = upload(&g.nuc_a64, T.nuc_a64))) {
         release_tables();
         return r;
     }
@@ -563,68 +708,52 @@ int sde_sbm_polar(const float* t, const float* u, const float* z, int64_t n, flo
     return e == hipSuccess ? SDE_OK : fail(SDE_E_HIP, hipGetErrorString(e));
 }
 
+int sde_philox_words(uint64_t seed, const uint64_t* h, const uint32_t* n, const uint32_t* b,
+                     int64_t count, uint32_t* words_out) {
+    g_err.clear();
+    if (count < 0 || count > (1ll << 30) || (count > 0 && (!h || !n || !b || !words_out)))
+        return fail(SDE_E_INVALID, "invalid philox_words arguments");
+    if ((uintptr_t)words_out % 16 != 0 || (uintptr_t)h % 8 != 0 || (uintptr_t)n % 4 != 0 ||
+        (uintptr_t)b % 4 != 0)
+        return fail(SDE_E_INVALID, "philox_words: misaligned array (words_out needs 16 bytes)");
+    if (count == 0) return SDE_OK;
+    hipStream_t s = cur_stream();
+    hipError_t e = launch_philox_words(seed, (const unsigned long long*)h, n, b, (int)count,
+                                       (uint4*)words_out, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? SDE_OK : fail(SDE_E_HIP, hipGetErrorString(e));
+}
+
 int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
               double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int interp,
               int local, int64_t* counts_out) {
     g_err.clear();
-    if (!ref || !ev || !counts_out || nx < 1 || ny < 1 || nz < 1 || !(dx_cm > 0) ||
-        !(dy_cm > 0) || !(dz_cm > 0) || !(dd > 0) || !(dta_cm > 0) || !(thresh >= 0) ||
-        interp < 1 || interp > 50)
-        return fail(SDE_E_INVALID, "invalid gamma arguments");
-    // offsets on the dta/interp lattice within dta, nearest first, in voxel
-    // units, with their squared length over dta^2
-    std::vector<int4> lat;
-    const double st = dta_cm / interp;
-    for (int a = -interp; a <= interp; ++a)
-        for (int b = -interp; b <= interp; ++b)
-            for (int c = -interp; c <= interp; ++c) {
-                const double ox = a * st, oy = b * st, oz = c * st;
-                if (ox * ox + oy * oy + oz * oz <= dta_cm * dta_cm * (1.0 + 1e-12))
-                    lat.push_back(make_int4(a, b, c, a * a + b * b + c * c));
-            }
-    std::stable_sort(lat.begin(), lat.end(),
-                     [](const int4& u, const int4& v) { return u.w < v.w; });
-    std::vector<double4> off(lat.size());
-    for (size_t k = 0; k < lat.size(); ++k) {
-        const double ox = lat[k].x * st, oy = lat[k].y * st, oz = lat[k].z * st;
-        off[k] = make_double4(ox / dx_cm, oy / dy_cm, oz / dz_cm,
-                              (ox * ox + oy * oy + oz * oz) / (dta_cm * dta_cm));
+    if (int rc = gamma_check(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, interp,
+                             counts_out))
+        return rc;
+    // offsets (cached in the library for the last lattice) and counters
+    const GammaKey key{interp, dta_cm, dx_cm, dy_cm, dz_cm};
+    if (!g.gam_off || !(g.gam_key == key)) {
+        std::vector<int4> lat((size_t)(2 * interp + 1) * (2 * interp + 1) * (2 * interp + 1));
+        const int n = gamma_lattice(interp, dta_cm, lat.data(), (int)lat.size());
+        std::vector<double4> off(n);
+        gamma_offsets(lat.data(), n, interp, dta_cm, dx_cm, dy_cm, dz_cm, off.data());
+        if (n > g.gam_cap) {
+            dfree(g.gam_off);
+            g.gam_cap = 0;
+            HIP_TRY(hipMalloc((void**)&g.gam_off, sizeof(double4) * n));
+            g.gam_cap = n;
+        }
+        if (!g.gam_buf) HIP_TRY(hipMalloc((void**)&g.gam_buf, sizeof(unsigned long long) * 4));
+        g.gam_n = 0;
+        HIP_TRY(hipMemcpyAsync(g.gam_off, off.data(), sizeof(double4) * n, hipMemcpyHostToDevice,
+                               cur_stream()));
+        HIP_TRY(hipStreamSynchronize(cur_stream()));
+        g.gam_key = key;
+        g.gam_n = n;
     }
-    const size_t nvox = (size_t)nx * ny * nz;
-    hipStream_t s = cur_stream();
-    double4* doff = nullptr;
-    unsigned long long* buf = nullptr;
-    HIP_TRY(hipMalloc((void**)&doff, sizeof(double4) * off.size()));
-    HIP_TRY(hipMalloc((void**)&buf, sizeof(unsigned long long) * 3));
-    int rc = SDE_OK;
-    unsigned long long host[3] = {0, 0, 0};
-    do {
-        hipError_t e;
-        if ((e = hipMemcpyAsync(doff, off.data(), sizeof(double4) * off.size(),
-                                hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemsetAsync(buf, 0, sizeof(unsigned long long) * 3, s)) != hipSuccess ||
-            (e = launch_max(ref, nvox, buf + 2, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(host, buf, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess) {
-            rc = fail(SDE_E_HIP, hipGetErrorString(e));
-            break;
-        }
-        double mx;
-        std::memcpy(&mx, &host[2], sizeof mx);
-        if ((e = launch_gamma(ref, ev, nx, ny, nz, doff, (int)off.size(), dd, thresh * mx, mx,
-                              local, buf, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(host, buf, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
-                                s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess) {
-            rc = fail(SDE_E_HIP, hipGetErrorString(e));
-            break;
-        }
-        counts_out[0] = (int64_t)host[0];
-        counts_out[1] = (int64_t)host[1];
-    } while (0);
-    (void)hipFree(doff);
-    (void)hipFree(buf);
-    return rc;
+    return gamma_run(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, local, g.gam_off,
+                     g.gam_n, g.gam_buf, counts_out);
 }
 
 int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes) {
@@ -642,6 +771,10 @@ int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes) {
 
 void sde_free(void) {
     release_tables();
+    dfree(g.gam_off);
+    dfree(g.gam_buf);
+    g.gam_cap = g.gam_n = 0;
+    g.gam_key = GammaKey{};
     if (g.own) {
         (void)hipStreamDestroy(g.own);
         g.own = nullptr;

@@ -16,6 +16,10 @@ struct HostTables {
     std::vector<double2> rg64;
     std::vector<MatDev> mats;
     std::vector<float> nuc_sigma, nuc_u, nuc_r, nuc_a;
+    // the FP64 instance's copies
+    std::vector<MatDev64> mats64;
+    std::vector<double2> hot64;
+    std::vector<double> nuc_sigma64, nuc_u64, nuc_r64, nuc_a64;
     double ruth_T = 0, mott_lo = 0, mott_hi = 0, mott_D0 = 0, mott_Lhi = 0, mott_Llo = 0;
     double c_strag = 0;
     sde_physics_params params{};

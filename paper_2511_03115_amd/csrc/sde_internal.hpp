@@ -43,10 +43,43 @@ struct MatDev {
     ElemDev el[kMaxElem];
 };
 
-// Per-spot source data on the device.  wscale = weight / n * 2^k.
-struct SpotDev {
-    float E, sigmaE, x, y, sxy, wscale;
+// The same medium in double precision, for the FP64 instance of the
+// transport: Bethe and Lynch-Dahl constants per element (the small-angle
+// width is evaluated from its formula there, not from the lattice table)
+// and the jump constants.
+struct MatDev64 {
+    double zoa, log_pre;   // as in MatDev
+    double c_ruth, c_mott; // as in MatDev
+    int n_elem, pad[3];
+    double wz[kMaxElem];      // w_i Z_i (Z_i + 1) / A_i
+    double ln_ca[kMaxElem];   // ln(2.007e-5 Z_i^(2/3))
+    double za2[kMaxElem];     // 3.34 (Z_i alpha)^2
+    double el_coef[kMaxElem], ne_coef[kMaxElem], m2[kMaxElem];
+    int is_h[kMaxElem], tab[kMaxElem];
+};
+
+// Per-spot source data on the device in the stepping precision R.
+// wscale = weight / n * 2^k.
+template <class R>
+struct SpotT {
+    R E, sigmaE, x, y, sxy, wscale;
     unsigned long long h0;   // index of the spot's first history in the caller's order
+};
+using SpotDev = SpotT<float>;
+using SpotDev64 = SpotT<double>;
+
+// Scheme and geometry scalars in the stepping precision R.
+template <class R>
+struct KScal {
+    R step, half_step, sqrt_step, e_min;
+    R c_bethe, c_strag;              // 0.3072, 4 pi N_A (alpha hbar c)^2
+    R ruth_T;                        // 1 / (1 - cos theta_cut)
+    R mott_lo, mott_hi;              // CM cosine limits of hydrogen elastic
+    R mott_D0, mott_Lhi, mott_Llo;
+    R eta_pre;                       // alpha sqrt(m_p / 2): eta = eta_pre / sqrt(E)
+    R ln_e_lo, inv_dln;              // lattice: t = (ln E - ln_e_lo) inv_dln
+    R ld_z, ld_F;                    // Lynch-Dahl path length and central fraction
+    R lo[3], hi[3], inv_d[3], d[3];  // phantom box and voxel size
 };
 
 // Everything the transport kernel reads; passed by value.
@@ -60,26 +93,25 @@ struct KParams {
     const float* nuc_r;
     const float* nuc_a;
     int n_mat, n_e, n_u, n_tab;
-    float ln_e_lo, inv_dln;
-    int pad5;
-    double ln_e_lo_d, inv_dln_d;
-    // scheme
-    double step_d;
-    float step, half_step, sqrt_step, e_min;
-    float c_bethe, c_strag;          // 0.3072, 4 pi N_A (alpha hbar c)^2
-    float ruth_T;                    // 1 / (1 - cos theta_cut)
-    float mott_lo, mott_hi;          // CM cosine limits of hydrogen elastic
-    float mott_D0, mott_Lhi, mott_Llo;
-    float eta_pre;                   // alpha sqrt(m_p / 2): eta = eta_pre / sqrt(E)
-    unsigned flags;
-    int pad0;
+    // tables of the FP64 instance
+    const MatDev64* mats64;          // [n_mat]
+    const double2* hot64;            // [n_mat][n_e] {inelastic rate/rho, elastic rate E^2/rho}
+    const double* nuc_sigma64;       // the nuclear tables unrounded
+    const double* nuc_u64;
+    const double* nuc_r64;
+    const double* nuc_a64;
+    // scheme and geometry scalars per precision
+    KScal<float> sf;
+    KScal<double> sd;
+    unsigned flags;                  // physics switches (SDE_ALL bits)
+    int fp64;                        // step in double precision
     long long max_steps;
     // phantom
     const uint2* vox;                // [nz][ny][nx] {density bits, material}
     int nx, ny, nz, pad1;
-    float lo[3], hi[3], inv_d[3], pad2;
     // beam
     const SpotDev* spots;
+    const SpotDev64* spots64;        // the same spots in double precision
     const unsigned long long* prefix;   // [n_spots + 1] cumulative history counts, claim order
     int n_spots, pad3;
     unsigned long long n_hist;
@@ -109,13 +141,19 @@ hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_by
 hipError_t launch_convert(unsigned long long* tally, int n_rep, const uint2* vox, size_t nvox,
                           double inv_scale, double voxel_cm3, double* dose,
                           unsigned long long* ledger, hipStream_t s);
-// gamma_kernels.hip: offsets[k] = (ox / dx, oy / dy, oz / dz, |o|^2 / dta^2)
+// gamma_kernels.hip: offsets[k] = (ox / dx, oy / dy, oz / dz, |o|^2 / dta^2),
+// nearest first; r = dta / d per axis (the bound needs r <= 1: use_bound)
 hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
                         const double4* offsets, int n_off, double dd, double thr_abs,
-                        double max_ref, int local, unsigned long long* counts, hipStream_t s);
+                        double max_ref, int local, double rx, double ry, double rz, int use_bound,
+                        unsigned long long* counts, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s);
 hipError_t launch_sbm_polar(const float* t, const float* u, const float* z, int n, float* c,
                             float* s_out, hipStream_t s);
 hipError_t transport_kernel_attributes(size_t lds_bytes);
+hipError_t launch_philox_words(unsigned long long seed, const unsigned long long* h,
+                               const unsigned* n, const unsigned* b, int count, uint4* out,
+                               hipStream_t s);
 
 }  // namespace sde

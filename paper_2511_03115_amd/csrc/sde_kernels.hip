@@ -11,9 +11,17 @@
 // lane, wave or launch runs it.  Energy is scored as int64 fixed point with
 // integer atomics (an LDS tile first when one is configured), so the tally
 // is the same for every launch shape.
+//
+// The stepping is written once over its real type R.  R = float is the
+// production instance (hardware transcendentals, FP32 lattice tables in LDS,
+// FP64 only for the end-of-range decision).  R = double evaluates every
+// coefficient in double precision (the Lynch-Dahl width and the elastic rate
+// from their formulas instead of the FP32 lattice), for runs that must agree
+// with a double-precision reference history by history.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sde_internal.hpp"
 
@@ -23,12 +31,60 @@ namespace {
 constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelastic = 16u,
                    kEor = 32u, kSbm = 64u;
 // the method (every switch) and the method with the geodesic Gaussian step:
-// each its own compiled instance, the rest share k_transport<0> (switches
+// each its own compiled instance, the rest share k_transport<float, 0> (switches
 // read at run time)
 constexpr unsigned kMethod = 127u, kMethodGeodesic = 63u;
 
 constexpr float kMpF = (float)kMp;
 constexpr float kLn2 = 0.69314718055994530942f;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Arithmetic of one precision.  float: the gfx950 hardware log2, sqrt,
+// reciprocal, reciprocal square root and sin/cos in revolutions; double: the
+// correctly rounded (or nearly) library functions.
+template <class R>
+struct RM;
+
+template <>
+struct RM<float> {
+    static constexpr bool f64 = false;
+    static __device__ __forceinline__ float lg(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+    static __device__ __forceinline__ float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    // sin and cos of 2 pi u: the hardware takes revolutions
+    static __device__ __forceinline__ float sinr(float u) { return __builtin_amdgcn_sinf(u); }
+    static __device__ __forceinline__ float cosr(float u) { return __builtin_amdgcn_cosf(u); }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return fmaf(a, b, c); }
+    // IEEE library forms where the hardware approximations were not enough
+    static __device__ __forceinline__ float lgx(float x) { return logf(x); }
+    static __device__ __forceinline__ float sqx(float x) { return sqrtf(x); }
+    static __device__ __forceinline__ float sinh(float x) { return sinhf(x); }
+    static __device__ __forceinline__ float cosh(float x) { return coshf(x); }
+};
+
+template <>
+struct RM<double> {
+    static constexpr bool f64 = true;
+    static __device__ __forceinline__ double lg(double x) { return ::log(x); }
+    static __device__ __forceinline__ double sq(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsq(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double sinr(double u) { return ::sin(kTwoPi * u); }
+    static __device__ __forceinline__ double cosr(double u) { return ::cos(kTwoPi * u); }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
+    static __device__ __forceinline__ double lgx(double x) { return ::log(x); }
+    static __device__ __forceinline__ double sqx(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double sinh(double x) { return ::sinh(x); }
+    static __device__ __forceinline__ double cosh(double x) { return ::cosh(x); }
+};
+
+template <class R>
+__device__ __forceinline__ const KScal<R>& scal(const KParams& P);
+template <>
+__device__ __forceinline__ const KScal<float>& scal<float>(const KParams& P) { return P.sf; }
+template <>
+__device__ __forceinline__ const KScal<double>& scal<double>(const KParams& P) { return P.sd; }
 
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
 // 32x32->64 products, key bumped by the Weyl constants between rounds.
@@ -56,69 +112,96 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
-// (2k+1) 2^-24 from the top 23 bits: exact in FP32, never 0 or 1.
-__device__ __forceinline__ float u_hi(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+// (2k+1) 2^-24 from the top 23 bits: exact in FP32 and FP64, never 0 or 1.
+template <class R>
+__device__ __forceinline__ R u_hi(uint32_t w) { return ((R)(w >> 9) + R(0.5)) * R(0x1p-23); }
 // Same from the 23 low bits that u_hi leaves unused in three words.
-__device__ __forceinline__ float u_lo(uint32_t a, uint32_t b, uint32_t c) {
+template <class R>
+__device__ __forceinline__ R u_lo(uint32_t a, uint32_t b, uint32_t c) {
     const uint32_t k = (a & 0x1FFu) | ((b & 0x1FFu) << 9) | ((c & 0x1Fu) << 18);
-    return ((float)k + 0.5f) * 0x1p-23f;
+    return ((R)k + R(0.5)) * R(0x1p-23);
 }
 
-__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-// sin and cos of 2 pi u for u in (0, 1): the hardware takes revolutions.
-__device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf(u); }
-__device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
-
-// cos and sin of a polar angle given its square: Taylor in theta^2 for small
-// angles (where the hardware sine would lose relative accuracy), the hardware
-// sine and cosine (absolute error ~1e-7) otherwise.
-__device__ __forceinline__ void polar_cs(float th2, float& c, float& s) {
-    if (th2 < 0.25f) {
-        const float x = th2;
-        c = fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, -2.7557319e-7f, 2.4801587e-5f),
-                                         -1.3888889e-3f), 4.1666667e-2f), -0.5f), 1.0f);
-        const float sc = fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, -2.5052108e-8f, 2.7557319e-6f),
-                                              -1.9841270e-4f), 8.3333333e-3f),
-                                      -1.6666667e-1f), 1.0f);
-        s = fsqrt(x) * sc;
+// cos and sin of a polar angle given its square.  float: Taylor in theta^2
+// for small angles (where the hardware sine would lose relative accuracy),
+// the hardware sine and cosine (absolute error ~1e-7) otherwise.
+template <class R>
+__device__ __forceinline__ void polar_cs(R th2, R& c, R& s) {
+    if constexpr (RM<R>::f64) {
+        const double th = ::sqrt(th2);
+        c = ::cos(th);
+        s = ::sin(th);
     } else {
-        const float r = sqrtf(th2) * 0.15915494309189535f;   // revolutions
-        s = sin_rev(r);
-        c = cos_rev(r);
+        if (th2 < 0.25f) {
+            const float x = th2;
+            c = fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, -2.7557319e-7f, 2.4801587e-5f),
+                                             -1.3888889e-3f), 4.1666667e-2f), -0.5f), 1.0f);
+            const float sc = fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, -2.5052108e-8f, 2.7557319e-6f),
+                                                  -1.9841270e-4f), 8.3333333e-3f),
+                                          -1.6666667e-1f), 1.0f);
+            s = RM<float>::sq(x) * sc;
+        } else {
+            const float r = sqrtf(th2) * 0.15915494309189535f;   // revolutions
+            s = RM<float>::sinr(r);
+            c = RM<float>::cosr(r);
+        }
     }
 }
 
 // Spherical Brownian motion on S^2 (generator half the Laplace-Beltrami
 // operator) at time t = sigma^2 Delta / z, the law of the small-angle
-// diffusion over one step (section 2.2.2), by the sampler the paper cites
+// diffusion over one step (section 2.1.4), by the sampler the paper cites
 // (Mijatovic, Mramor and Uribe Bravo 2020, Algorithm 1): M = the number of
 // lineages left at time t of Kingman's coalescent with mutation parameter
 // d - 1 = 2 started from infinitely many, X ~ Beta(1, 1 + M),
 // cos = 1 - 2 X.  u -> 1 gives the angle -> 0 in both regimes.
-constexpr float kSbmSwitch = 0.02f;
-constexpr int kSbmL = 64;   // Legendre terms: e^{-l(l+1)t/2} < 1e-18 beyond, t >= kSbmSwitch
+template <class R>
+struct SbmSwitch;
+template <>
+struct SbmSwitch<float> { static constexpr float t = 0.02f; };
+template <>
+struct SbmSwitch<double> { static constexpr double t = 0.02; };
+constexpr int kSbmL = 64;   // Legendre terms: e^{-l(l+1)t/2} < 1e-18 beyond, t >= 0.02
 
-// t < kSbmSwitch: M from Griffiths' normal law, mean 2/t - 1/2 + t/24
-// (series of 1/expm1(t/2), error t^3/5760) and standard deviation
-// sqrt(2/(3t)) (1 - 7t^2/480), rounded to the nearest integer; then X by
-// inversion, -expm1(ln u / (1 + M)) as a degree-7 polynomial: here
-// 1 + M >= 67 (|z| <= 5.77) and -ln u <= 16.7, so |ln u / (1 + M)| <= 0.25
-// and the truncation is below 2e-9 relative.
-__device__ __forceinline__ void sbm_small(float t, float z, float u, float& ct, float& st) {
-    t = fmaxf(t, 1e-30f);
-    const float r = __builtin_amdgcn_rsqf(t);
-    const float mu = fmaf(2.0f * r, r, fmaf(t, 1.0f / 24.0f, -0.5f));
-    const float sd = 0.81649658f * r * fmaf(-7.0f / 480.0f * t, t, 1.0f);
-    const float M = fmaxf(rintf(fmaf(sd, z, mu)), 0.0f);
-    const float y = flog(u) * frcp(M + 1.0f);
-    const float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, 1.0f / 5040.0f, 1.0f / 720.0f),
-                                                         1.0f / 120.0f), 1.0f / 24.0f),
-                                         1.0f / 6.0f), 0.5f), 1.0f);
-    const float X = -y * p;
-    ct = fmaf(-2.0f, X, 1.0f);
-    st = 2.0f * fsqrt(X * (1.0f - X));
+// t below the switch: M from Griffiths' normal law with mean 1/expm1(t/2)
+// and its variance, rounded to the nearest integer and floored at 0; then
+// X by inversion, X = -expm1(ln u / (1 + M)).
+// float: mean 2/t - 1/2 + t/24 (series of 1/expm1(t/2), error t^3/5760),
+// standard deviation sqrt(2/(3t)) (1 - 7t^2/480), and -expm1 as a degree-7
+// polynomial: here 1 + M >= 67 (|z| <= 5.77) and -ln u <= 16.7, so
+// |ln u / (1 + M)| <= 0.25 and the truncation is below 2e-9 relative.
+// double: the mean and variance from their closed forms (the variance's
+// bracket by its Taylor series below t = 1e-2, where it cancels).
+template <class R>
+__device__ __forceinline__ void sbm_small(R t, R z, R u, R& ct, R& st) {
+    if constexpr (RM<R>::f64) {
+        double var;
+        if (t < 1e-2) {
+            const double t2 = t * t;
+            var = 2.0 / (3.0 * t) * (1.0 - 7.0 * t2 / 240.0 + 41.0 * t2 * t2 / 80640.0);
+        } else {
+            const double beta = 0.5 * t, eta = beta / ::expm1(beta);
+            var = (2.0 * eta / t) * (eta + beta) * (eta + beta) *
+                  (1.0 + eta / (eta + beta) - 2.0 * eta) / (beta * beta);
+        }
+        const double M = ::fmax(::floor(1.0 / ::expm1(0.5 * t) + ::sqrt(var) * z + 0.5), 0.0);
+        const double X = -::expm1(::log(u) / (1.0 + M));
+        ct = 1.0 - 2.0 * X;
+        st = 2.0 * ::sqrt(X * (1.0 - X));
+    } else {
+        t = fmaxf(t, 1e-30f);
+        const float r = __builtin_amdgcn_rsqf(t);
+        const float mu = fmaf(2.0f * r, r, fmaf(t, 1.0f / 24.0f, -0.5f));
+        const float sd = 0.81649658f * r * fmaf(-7.0f / 480.0f * t, t, 1.0f);
+        const float M = fmaxf(rintf(fmaf(sd, z, mu)), 0.0f);
+        const float y = RM<float>::lg(u) * RM<float>::rcp(M + 1.0f);
+        const float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, 1.0f / 5040.0f, 1.0f / 720.0f),
+                                                             1.0f / 120.0f), 1.0f / 24.0f),
+                                             1.0f / 6.0f), 0.5f), 1.0f);
+        const float X = -y * p;
+        ct = fmaf(-2.0f, X, 1.0f);
+        st = 2.0f * RM<float>::sq(X * (1.0f - X));
+    }
 }
 
 // Legendre recurrence coefficients (l+1) P_{l+1} = (2l+1) c P_l - l P_{l-1}
@@ -157,17 +240,23 @@ __device__ __forceinline__ void sbm_tail(double q, double c, double& g, double& 
     }
 }
 
-// t >= kSbmSwitch: cos drawn exactly, P(cos <= c) = u, by Newton steps on
-// the series kept inside a shrinking bisection bracket (at most 40 steps;
-// a step that leaves the bracket or is NaN bisects instead); returns
+template <class R>
+struct CosSin {
+    R c, s;
+};
+
+// t at or above the switch: cos drawn exactly, P(cos <= c) = u, by Newton
+// steps on the series kept inside a shrinking bisection bracket (at most 40
+// steps; a step that leaves the bracket or is NaN bisects instead); returns
 // (cos, sin).  Rare: with the residual-range step on, t stays below ~2e-2
 // on every full step.  Out of line, so that its double-precision registers
 // never add to the step's: registers live across the call are saved only
 // when it runs.
-__device__ __noinline__ float2 sbm_large(float t, float u) {
-    const double td = t, target = 1.0 - (double)u, q = exp(-td);
+template <class R>
+__device__ __noinline__ CosSin<R> sbm_large(double td, double ud) {
+    const double target = 1.0 - ud, q = exp(-td);
     double lo = -1.0, hi = 1.0;
-    double c = fmin(fmax(fmax(1.0 + td * log((double)u), 2.0 * (double)u - 1.0), -1.0), 1.0);
+    double c = fmin(fmax(fmax(1.0 + td * log(ud), 2.0 * ud - 1.0), -1.0), 1.0);
 #pragma unroll 1
     for (int it = 0; it < 40; ++it) {
         double g, f;
@@ -179,42 +268,55 @@ __device__ __noinline__ float2 sbm_large(float t, float u) {
         c = cn;
         if (done) break;
     }
-    return make_float2((float)c, (float)sqrt(fmax((1.0 - c) * (1.0 + c), 0.0)));
+    return CosSin<R>{(R)c, (R)sqrt(fmax((1.0 - c) * (1.0 + c), 0.0))};
 }
 
 // Turn unit d by (ct, st) about itself, azimuth (cp, sp) from b1 of the
 // Duff et al. (JCGT 2017) orthonormal basis of d.
-__device__ __forceinline__ void turn(float& dx, float& dy, float& dz, float ct, float st,
-                                     float cp, float sp) {
-    const float sg = copysignf(1.0f, dz);
-    const float a = -frcp(sg + dz);   // |sg + dz| >= 1
-    const float b = dx * dy * a;
-    const float b1x = 1.0f + sg * dx * dx * a, b1y = sg * b, b1z = -sg * dx;
-    const float b2x = b, b2y = sg + dy * dy * a, b2z = -dy;
-    const float ex = cp * b1x + sp * b2x, ey = cp * b1y + sp * b2y, ez = cp * b1z + sp * b2z;
-    const float nx = ct * dx + st * ex, ny = ct * dy + st * ey, nz = ct * dz + st * ez;
+template <class R>
+__device__ __forceinline__ void turn(R& dx, R& dy, R& dz, R ct, R st, R cp, R sp) {
+    const R sg = copysign(R(1), dz);
+    const R a = -RM<R>::rcp(sg + dz);   // |sg + dz| >= 1
+    const R b = dx * dy * a;
+    const R b1x = R(1) + sg * dx * dx * a, b1y = sg * b, b1z = -sg * dx;
+    const R b2x = b, b2y = sg + dy * dy * a, b2z = -dy;
+    const R ex = cp * b1x + sp * b2x, ey = cp * b1y + sp * b2y, ez = cp * b1z + sp * b2z;
+    const R nx = ct * dx + st * ex, ny = ct * dy + st * ey, nz = ct * dz + st * ez;
     dx = nx;
     dy = ny;
     dz = nz;
 }
 
-__device__ __forceinline__ bool inside(const KParams& P, float x, float y, float z) {
-    return x >= P.lo[0] && x <= P.hi[0] && y >= P.lo[1] && y <= P.hi[1] && z >= P.lo[2] &&
-           z <= P.hi[2];
+template <class R>
+__device__ __forceinline__ bool inside(const KScal<R>& S, R x, R y, R z) {
+    return x >= S.lo[0] && x <= S.hi[0] && y >= S.lo[1] && y <= S.hi[1] && z >= S.lo[2] &&
+           z <= S.hi[2];
 }
 
 // Voxel of an inside point; the upper face belongs to the last voxel.
-__device__ __forceinline__ void voxel3(const KParams& P, float x, float y, float z, int& ix,
-                                       int& iy, int& iz) {
-    ix = min((int)((x - P.lo[0]) * P.inv_d[0]), P.nx - 1);
-    iy = min((int)((y - P.lo[1]) * P.inv_d[1]), P.ny - 1);
-    iz = min((int)((z - P.lo[2]) * P.inv_d[2]), P.nz - 1);
+// float multiplies by the reciprocal voxel size; double divides, as the
+// definition floor((x - origin) / d) reads.
+template <class R>
+__device__ __forceinline__ void voxel3(const KParams& P, const KScal<R>& S, R x, R y, R z,
+                                       int& ix, int& iy, int& iz) {
+    if constexpr (RM<R>::f64) {
+        ix = min((int)((x - S.lo[0]) / S.d[0]), P.nx - 1);
+        iy = min((int)((y - S.lo[1]) / S.d[1]), P.ny - 1);
+        iz = min((int)((z - S.lo[2]) / S.d[2]), P.nz - 1);
+    } else {
+        ix = min((int)((x - S.lo[0]) * S.inv_d[0]), P.nx - 1);
+        iy = min((int)((y - S.lo[1]) * S.inv_d[1]), P.ny - 1);
+        iz = min((int)((z - S.lo[2]) * S.inv_d[2]), P.nz - 1);
+    }
 }
 
 // Fixed-point energy, round to nearest even; e >= 0 always (deposits,
 // energies), so the conversion is the unsigned one, without a sign fix-up.
 __device__ __forceinline__ long long fixp(float e, float wsc) {
     return (long long)(unsigned long long)rintf(e * wsc);
+}
+__device__ __forceinline__ long long fixp(double e, double wsc) {
+    return (long long)(unsigned long long)rint(e * wsc);
 }
 
 // Per-lane deposit accumulator: consecutive deposits into the same voxel are
@@ -247,17 +349,19 @@ __device__ __forceinline__ void acc_flush(const KParams& P, unsigned long long* 
 // Score energy e at point (x,y,z): into the accumulator, or escaped.
 // check = false skips the inside test where the caller knows the point is
 // inside (a midpoint between two inside points of the box, with the
-// monotonic rounding of fmaf).
-__device__ __forceinline__ void score(const KParams& P, unsigned long long* tile,
-                                      unsigned long long* rep, Acc& a, float x, float y, float z,
-                                      float e, float wsc, long long& esc, bool check = true) {
+// monotonic rounding of fma).
+template <class R>
+__device__ __forceinline__ void score(const KParams& P, const KScal<R>& S,
+                                      unsigned long long* tile, unsigned long long* rep, Acc& a,
+                                      R x, R y, R z, R e, R wsc, long long& esc,
+                                      bool check = true) {
     const long long q = fixp(e, wsc);
-    if (check && !inside(P, x, y, z)) {
+    if (check && !inside(S, x, y, z)) {
         esc += q;
         return;
     }
     int ix, iy, iz;
-    voxel3(P, x, y, z, ix, iy, iz);
+    voxel3(P, S, x, y, z, ix, iy, iz);
     const int v = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx +
                         (unsigned)ix);
     if (v == a.v) {
@@ -275,167 +379,209 @@ __device__ __forceinline__ void score(const KParams& P, unsigned long long* tile
 // Hydrogen (Mott) antiderivative in units of (eta/k)^2, Appendix A.2 with
 // sin(eta ln((1+mu)/(1-mu))), and its derivative (the Mott cross section of
 // section 2.1.4 in the same units).
-__device__ __forceinline__ void mott_G_dG(float eta, float inv_2eta, float mu, float& G,
-                                          float& dG) {
-    const float omm = (1.0f - mu) * (1.0f + mu);
-    const float iomm = frcp(omm);
-    const float L = logf((1.0f + mu) * frcp(1.0f - mu));
-    const float r = eta * L * 0.15915494309189535f;   // revolutions, |r| < 1 for E >= e_min
-    const float sn = sin_rev(r), cs = cos_rev(r);
-    G = 2.0f * mu * iomm - sn * inv_2eta;
-    dG = 2.0f * iomm * ((1.0f + mu * mu) * iomm - 0.5f * cs);
+template <class R>
+__device__ __forceinline__ void mott_G_dG(R eta, R inv_2eta, R mu, R& G, R& dG) {
+    using M = RM<R>;
+    const R omm = (R(1) - mu) * (R(1) + mu);
+    const R iomm = M::rcp(omm);
+    const R L = M::lgx((R(1) + mu) * M::rcp(R(1) - mu));
+    const R r = eta * L * R(0.15915494309189535);   // revolutions, |r| < 1 for E >= e_min
+    const R sn = M::sinr(r), cs = M::cosr(r);
+    G = R(2) * mu * iomm - sn * inv_2eta;
+    dG = R(2) * iomm * ((R(1) + mu * mu) * iomm - R(0.5) * cs);
 }
 
 // Invert the hydrogen elastic CDF, (G(mu) - G(lo)) / (G(hi) - G(lo)) = U, by
 // Newton's method kept inside a shrinking bracket.  First guess: the
 // interference term dropped, 2 mu / (1 - mu^2) = target.
-__device__ __forceinline__ float mott_invert(const KParams& P, float eta, float U) {
-    const float inv_2eta = 0.5f * frcp(eta);
-    float a = P.mott_lo, b = P.mott_hi, G0, G1, d;
+template <class R>
+__device__ __forceinline__ R mott_invert(const KScal<R>& S, R eta, R U) {
+    using M = RM<R>;
+    // float: a few ulps of mu (FP32 Newton can cycle between neighbouring
+    // floats); double: 1e-15 of mu
+    constexpr R tol = M::f64 ? R(1e-15) : R(2.5e-7);
+    constexpr int max_it = M::f64 ? 60 : 24;
+    const R inv_2eta = R(0.5) * M::rcp(eta);
+    R a = S.mott_lo, b = S.mott_hi, G0, G1, d;
     mott_G_dG(eta, inv_2eta, a, G0, d);
     mott_G_dG(eta, inv_2eta, b, G1, d);
-    const float tgt = fmaf(U, G1 - G0, G0);
-    float mu = tgt * frcp(1.0f + sqrtf(1.0f + tgt * tgt));
-    mu = fminf(fmaxf(mu, a), b);
-    for (int it = 0; it < 24; ++it) {
-        float G, dG;
+    const R tgt = M::fma(U, G1 - G0, G0);
+    R mu = tgt * M::rcp(R(1) + M::sqx(R(1) + tgt * tgt));
+    mu = fmin(fmax(mu, a), b);
+    for (int it = 0; it < max_it; ++it) {
+        R G, dG;
         mott_G_dG(eta, inv_2eta, mu, G, dG);
-        const float g = G - tgt;
-        if (g < 0.0f) a = mu; else b = mu;
-        float nx = mu - g * frcp(dG);
-        if (!(nx > a && nx < b)) nx = 0.5f * (a + b);
-        const float step = fabsf(nx - mu);
+        const R g = G - tgt;
+        if (g < R(0)) a = mu; else b = mu;
+        R nx = mu - g * M::rcp(dG);
+        if (!(nx > a && nx < b)) nx = R(0.5) * (a + b);
+        const R step = fabs(nx - mu);
         mu = nx;
-        // converged to a few ulps of mu (FP32 Newton can cycle between
-        // neighbouring floats), or the bracket has closed
-        if (step <= 2.5e-7f * fmaxf(fabsf(mu), 1e-3f) || !(b > a)) break;
+        // converged, or the bracket has closed
+        if (step <= tol * fmax(fabs(mu), R(1e-3)) || !(b > a)) break;
     }
     return mu;
 }
 
-__device__ __forceinline__ float lerp_row(const float* row, int i, float f) {
-    return fmaf(f, row[i + 1] - row[i], row[i]);
+template <class R>
+__device__ __forceinline__ R lerp_row(const R* row, int i, R f) {
+    return RM<R>::fma(f, row[i + 1] - row[i], row[i]);
 }
 
 // Bilinear value of a [n_e][n_u] table at lattice (i, f) and x in [0, 1].
-__device__ __forceinline__ float table_eu(const float* tab, int n_u, int i, float f, float x) {
-    float tu = fminf(fmaxf(x * (float)(n_u - 1), 0.0f), (float)(n_u - 1));
+template <class R>
+__device__ __forceinline__ R table_eu(const R* tab, int n_u, int i, R f, R x) {
+    using M = RM<R>;
+    R tu = fmin(fmax(x * (R)(n_u - 1), R(0)), (R)(n_u - 1));
     int j = min((int)tu, n_u - 2);
-    const float g = tu - (float)j;
-    const float* r0 = tab + (size_t)i * n_u;
-    const float* r1 = r0 + n_u;
-    const float a = fmaf(g, r0[j + 1] - r0[j], r0[j]);
-    const float b = fmaf(g, r1[j + 1] - r1[j], r1[j]);
-    return fmaf(f, b - a, a);
+    const R g = tu - (R)j;
+    const R* r0 = tab + (size_t)i * n_u;
+    const R* r1 = r0 + n_u;
+    const R a = M::fma(g, r0[j + 1] - r0[j], r0[j]);
+    const R b = M::fma(g, r1[j + 1] - r1[j], r1[j]);
+    return M::fma(f, b - a, a);
+}
+
+// Per-precision views of a medium's jump constants and of the nuclear tables.
+__device__ __forceinline__ int n_elem(const MatDev& m) { return m.n_elem; }
+__device__ __forceinline__ int n_elem(const MatDev64& m) { return m.n_elem; }
+__device__ __forceinline__ float el_coef(const MatDev& m, int e) { return m.el[e].el_coef; }
+__device__ __forceinline__ double el_coef(const MatDev64& m, int e) { return m.el_coef[e]; }
+__device__ __forceinline__ float ne_coef(const MatDev& m, int e) { return m.el[e].ne_coef; }
+__device__ __forceinline__ double ne_coef(const MatDev64& m, int e) { return m.ne_coef[e]; }
+__device__ __forceinline__ float m2_of(const MatDev& m, int e) { return m.el[e].m2; }
+__device__ __forceinline__ double m2_of(const MatDev64& m, int e) { return m.m2[e]; }
+__device__ __forceinline__ int is_h(const MatDev& m, int e) { return m.el[e].is_h; }
+__device__ __forceinline__ int is_h(const MatDev64& m, int e) { return m.is_h[e]; }
+__device__ __forceinline__ int tab_of(const MatDev& m, int e) { return m.el[e].tab; }
+__device__ __forceinline__ int tab_of(const MatDev64& m, int e) { return m.tab[e]; }
+__device__ __forceinline__ float c_mott(const MatDev& m) { return m.c_mott; }
+__device__ __forceinline__ double c_mott(const MatDev64& m) { return m.c_mott; }
+
+template <class R>
+struct Nuc {
+    const R *sigma, *u, *r, *a;
+};
+__device__ __forceinline__ Nuc<float> nuc_of(const KParams& P, float) {
+    return Nuc<float>{P.nuc_sigma, P.nuc_u, P.nuc_r, P.nuc_a};
+}
+__device__ __forceinline__ Nuc<double> nuc_of(const KParams& P, double) {
+    return Nuc<double>{P.nuc_sigma64, P.nuc_u64, P.nuc_r64, P.nuc_a64};
 }
 
 // Rate of channel (element e, elastic or inelastic) per cm at E.
-__device__ __forceinline__ float channel_rate(const KParams& P, const ElemDev& d, bool inel,
-                                              float rho, float inv_e2, float mott, int li,
-                                              float lf) {
-    if (!inel) return rho * d.el_coef * inv_e2 * (d.is_h ? mott : 1.0f);
-    return rho * d.ne_coef * lerp_row(P.nuc_sigma + (size_t)d.tab * P.n_e, li, lf);
+template <class R, class Mat>
+__device__ __forceinline__ R channel_rate(const KParams& P, const Nuc<R>& nu, const Mat& m, int e,
+                                          bool inel, R rho, R inv_e2, R mott, int li, R lf) {
+    if (!inel) return rho * el_coef(m, e) * inv_e2 * (is_h(m, e) ? mott : R(1));
+    return rho * ne_coef(m, e) * lerp_row(nu.sigma + (size_t)tab_of(m, e) * P.n_e, li, lf);
 }
 
-// One large-angle jump at energy E (the state energy E_n) in material md,
+// The bracket of the hydrogen elastic rate: G(hi) - G(lo) of the Mott
+// antiderivative in units of (eta/k)^2.
+template <class R>
+__device__ __forceinline__ R mott_bracket(const KScal<R>& S, R eta) {
+    const R k = R(0.15915494309189535);   // revolutions per radian
+    return S.mott_D0 -
+           (RM<R>::sinr(eta * S.mott_Lhi * k) - RM<R>::sinr(eta * S.mott_Llo * k)) / (R(2) * eta);
+}
+
+// One large-angle jump at energy E (the state energy E_n) in medium md,
 // Eq. (Npi): channel by its rate, CM cosine from its law (closed-form
 // Rutherford inverse, Mott by Newton, Kalbach-Mann inverse), CM -> lab by
 // Eq. (cm_to_lab).  Outputs the loss fraction u (0 for elastic), the lab
 // polar (cos, sin) and the azimuth (cos, sin).
-__device__ void jump(const KParams& P, const MatDev* md, float E, float rho, uint4 q,
-                     float& u_loss, float& jc, float& js, float& jcp, float& jsp, unsigned flags) {
-    const float tl = (flog(E) - P.ln_e_lo) * P.inv_dln;
+template <class R, class Mat>
+__device__ void jump(const KParams& P, const KScal<R>& S, const Mat& md, R E, R rho, uint4 q,
+                     R& u_loss, R& jc, R& js, R& jcp, R& jsp, unsigned flags) {
+    using M = RM<R>;
+    const Nuc<R> nu = nuc_of(P, R(0));
+    const R tl = (M::lg(E) - S.ln_e_lo) * S.inv_dln;
     const int li = max(0, min((int)tl, P.n_e - 2));
-    const float lf = tl - (float)li;
-    const float inv_e2 = 1.0f / (E * E);
-    const float eta = P.eta_pre * __builtin_amdgcn_rsqf(E);
+    const R lf = tl - (R)li;
+    const R inv_e2 = R(1) / (E * E);
+    const R eta = S.eta_pre * M::rsq(E);
     const bool el = (flags & kElastic) != 0, ne = (flags & kInelastic) != 0;
-    const int nel = md->n_elem;
-    float mott = 0.0f;
-    if (el && md->c_mott != 0.0f) {
-        const float k = 0.15915494309189535f;   // revolutions per radian
-        mott = P.mott_D0 -
-               (sin_rev(eta * P.mott_Lhi * k) - sin_rev(eta * P.mott_Llo * k)) / (2.0f * eta);
-    }
-    float tot = 0.0f;
+    const int nel = n_elem(md);
+    R mott = R(0);
+    if (el && c_mott(md) != R(0)) mott = mott_bracket(S, eta);
+    R tot = R(0);
     for (int e = 0; e < nel; ++e) {
-        const ElemDev& d = md->el[e];
-        if (el) tot += channel_rate(P, d, false, rho, inv_e2, mott, li, lf);
-        if (ne && d.tab >= 0) tot += channel_rate(P, d, true, rho, inv_e2, mott, li, lf);
+        if (el) tot += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf);
+        if (ne && tab_of(md, e) >= 0)
+            tot += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf);
     }
-    const float target = u_hi(q.x) * tot;
-    float acc = 0.0f;
+    const R target = u_hi<R>(q.x) * tot;
+    R acc = R(0);
     int ce = -1, cin = 0;
     for (int e = 0; e < nel && ce < 0; ++e) {
-        const ElemDev& d = md->el[e];
         if (el) {
-            acc += channel_rate(P, d, false, rho, inv_e2, mott, li, lf);
+            acc += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf);
             if (target < acc) { ce = e; cin = 0; break; }
         }
-        if (ne && d.tab >= 0) {
-            acc += channel_rate(P, d, true, rho, inv_e2, mott, li, lf);
+        if (ne && tab_of(md, e) >= 0) {
+            acc += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf);
             if (target < acc) { ce = e; cin = 1; break; }
         }
     }
     if (ce < 0) {   // rounding at the top end: the last channel with a rate
         ce = nel - 1;
-        cin = (ne && md->el[ce].tab >= 0) ? 1 : 0;
+        cin = (ne && tab_of(md, ce) >= 0) ? 1 : 0;
     }
-    const ElemDev& d = md->el[ce];
-    float cmc, cms;
-    u_loss = 0.0f;
+    R cmc, cms;
+    u_loss = R(0);
     if (!cin) {
-        const float U = u_hi(q.y);
-        if (d.is_h) {
-            cmc = mott_invert(P, eta, U);
-            cms = sqrtf(fmaxf(0.0f, (1.0f - cmc) * (1.0f + cmc)));
+        const R U = u_hi<R>(q.y);
+        if (is_h(md, ce)) {
+            cmc = mott_invert(S, eta, U);
+            cms = M::sqx(fmax(R(0), (R(1) - cmc) * (R(1) + cmc)));
         } else {
-            const float om = 1.0f / fmaf(U, P.ruth_T - 0.5f, 0.5f);   // 1 - mu
-            cmc = 1.0f - om;
-            cms = sqrtf(om * (2.0f - om));
+            const R om = R(1) / M::fma(U, S.ruth_T - R(0.5), R(0.5));   // 1 - mu
+            cmc = R(1) - om;
+            cms = M::sqx(om * (R(2) - om));
         }
     } else {
-        const size_t off = (size_t)d.tab * P.n_e * P.n_u;
-        float u = table_eu(P.nuc_u + off, P.n_u, li, lf, u_hi(q.y));
-        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        const size_t off = (size_t)tab_of(md, ce) * P.n_e * P.n_u;
+        R u = table_eu(nu.u + off, P.n_u, li, lf, u_hi<R>(q.y));
+        u = fmin(fmax(u, R(0)), R(1));
         u_loss = u;
-        const float a = table_eu(P.nuc_a + off, P.n_u, li, lf, u);
-        const float r = table_eu(P.nuc_r + off, P.n_u, li, lf, u);
-        const float U = u_hi(q.w);
-        float mu;
-        if (a < 1e-6f) {
-            mu = 2.0f * U - 1.0f;
+        const R a = table_eu(nu.a + off, P.n_u, li, lf, u);
+        const R r = table_eu(nu.r + off, P.n_u, li, lf, u);
+        const R U = u_hi<R>(q.w);
+        R mu;
+        if (a < R(1e-6)) {
+            mu = R(2) * U - R(1);
         } else {
-            const float sh = sinhf(a), ch = coshf(a);
-            const float C = 2.0f * sh * U + r * ch - sh;
-            mu = logf((C + sqrtf(C * C - r * r + 1.0f)) / (1.0f + r)) / a;
-            mu = fminf(fmaxf(mu, -1.0f), 1.0f);
+            const R sh = M::sinh(a), ch = M::cosh(a);
+            const R C = R(2) * sh * U + r * ch - sh;
+            mu = M::lgx((C + M::sqx(C * C - r * r + R(1))) / (R(1) + r)) / a;
+            mu = fmin(fmax(mu, R(-1)), R(1));
         }
         cmc = mu;
-        cms = sqrtf(fmaxf(0.0f, (1.0f - mu) * (1.0f + mu)));
+        cms = M::sqx(fmax(R(0), (R(1) - mu) * (R(1) + mu)));
     }
     // CM -> lab (Appendix A.1): K = E, m1 = m_p, outgoing lab energy E - u E
-    const float m1 = kMpF, m2 = d.m2;
-    const float E1 = E + m1;
-    const float p1 = sqrtf(E * (E + 2.0f * m1));
-    const float ucm = p1 / (E1 + m2);
-    const float gu = 1.0f / sqrtf((1.0f - ucm) * (1.0f + ucm));
-    const float K2 = E * (1.0f - u_loss);
-    const float E1p = K2 + m1;
-    const float p1p = sqrtf(K2 * (K2 + 2.0f * m1));
-    const float v1c = (p1p - ucm * E1p) / (E1p - ucm * p1p);
-    const float X = gu * (cmc + ucm / v1c), Y = cms;
-    const float rn = 1.0f / sqrtf(X * X + Y * Y);
+    const R m1 = (R)kMp, m2 = m2_of(md, ce);
+    const R E1 = E + m1;
+    const R p1 = M::sqx(E * (E + R(2) * m1));
+    const R ucm = p1 / (E1 + m2);
+    const R gu = R(1) / M::sqx((R(1) - ucm) * (R(1) + ucm));
+    const R K2 = E * (R(1) - u_loss);
+    const R E1p = K2 + m1;
+    const R p1p = M::sqx(K2 * (K2 + R(2) * m1));
+    const R v1c = (p1p - ucm * E1p) / (E1p - ucm * p1p);
+    const R X = gu * (cmc + ucm / v1c), Y = cms;
+    const R rn = R(1) / M::sqx(X * X + Y * Y);
     jc = X * rn;
     js = Y * rn;
-    const float phi = u_hi(q.z);
-    jcp = cos_rev(phi);
-    jsp = sin_rev(phi);
+    const R phi = u_hi<R>(q.z);
+    jcp = M::cosr(phi);
+    jsp = M::sinr(phi);
 }
 
 // FP64 residual range R_g(E) (g/cm^2) by cubic Hermite on the lattice.
-__device__ __forceinline__ double range_g64(const KParams& P, int mat, float E) {
-    const double t = (log((double)E) - P.ln_e_lo_d) * P.inv_dln_d;
+__device__ __forceinline__ double range_g64(const KParams& P, int mat, double E) {
+    const double t = (log(E) - P.sd.ln_e_lo) * P.sd.inv_dln;
     int i = (int)floor(t);
     i = max(0, min(i, P.n_e - 2));
     const double s = t - (double)i;
@@ -444,6 +590,26 @@ __device__ __forceinline__ double range_g64(const KParams& P, int mat, float E) 
     const double s2 = s * s, s3 = s2 * s;
     return (2.0 * s3 - 3.0 * s2 + 1.0) * a.x + (s3 - 2.0 * s2 + s) * a.y +
            (-2.0 * s3 + 3.0 * s2) * b.x + (s3 - s2) * b.y;
+}
+
+// Lynch-Dahl width of section 2.1.4 for the medium at density rho and
+// energy E, scaled to the step: t = sigma^2 Delta / z (double instance).
+__device__ __forceinline__ double ld_time64(const MatDev64& m, const KScal<double>& S, double rho,
+                                            double E) {
+    const double p2 = E * E + 2.0 * E * kMp;
+    const double pb = p2 / (E + kMp);
+    const double b2 = p2 / ((E + kMp) * (E + kMp));
+    const double lp2 = ::log(p2);
+    double wz = 0.0, num = 0.0;
+    for (int i = 0; i < m.n_elem; ++i) {
+        wz += m.wz[i];
+        num += m.wz[i] * (m.ln_ca[i] + ::log1p(m.za2[i] / b2) - lp2);
+    }
+    const double chic2 = 0.157 * wz * rho * S.ld_z / (pb * pb);
+    const double chia2 = ::exp(num / wz);
+    const double nu = chic2 / (2.0 * chia2 * (1.0 - S.ld_F));
+    const double s2 = chic2 / (1.0 + S.ld_F * S.ld_F) * ((1.0 + nu) / nu * ::log1p(nu) - 1.0);
+    return s2 * (S.step / S.ld_z);
 }
 
 // Per-history record {E0, steps, jumps, end, x, y, z, E, first jump step,
@@ -477,11 +643,20 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 
 enum : int { kDead = 0, kStep = 1, kJump = 2 };
 
+__device__ __forceinline__ const SpotDev& spot_at(const KParams& P, int i, float) {
+    return P.spots[i];
+}
+__device__ __forceinline__ const SpotDev64& spot_at(const KParams& P, int i, double) {
+    return P.spots64[i];
+}
+
 // kFixed != 0: the physics switches are that compile-time constant (the
 // method, with either small-angle sampler), so their tests fold away; 0:
 // read them from P.flags.
-template <unsigned kFixed>
+template <class R, unsigned kFixed>
 __global__ void __launch_bounds__(1024) k_transport(KParams P) {
+    using M = RM<R>;
+    const KScal<R>& S = scal<R>(P);
     const unsigned flags = kFixed ? kFixed : P.flags;
     extern __shared__ __align__(16) unsigned char smem[];
     float4* tab = reinterpret_cast<float4*>(smem);
@@ -509,11 +684,11 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
 
     unsigned long long h = 0;
     unsigned n = 0;
-    float E = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f, ox = 0.0f, oy = 0.0f, oz = 1.0f, wsc = 0.0f;
+    R E = R(0), rx = R(0), ry = R(0), rz = R(0), ox = R(0), oy = R(0), oz = R(1), wsc = R(0);
     int vcache = -1, mat = 0;
-    float rho = 1.0f, e0 = 0.0f;
+    R rho = R(1), e0 = R(0);
     // pending jump: state energy, material, density and step index at the jump
-    float ej = 0.0f, rhoj = 1.0f;
+    R ej = R(0), rhoj = R(1);
     int matj = 0;
     unsigned nj = 0;
     unsigned hj = 0;
@@ -523,7 +698,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     // small-angle turn of the last step still to draw (exact regime): time,
     // uniform, azimuth
     bool sbm_pend = false;
-    float sbm_t = 0.0f, sbm_u = 0.0f, sbm_ph = 0.0f;
+    R sbm_t = R(0), sbm_u = R(0), sbm_ph = R(0);
 
     for (;;) {
         if (state == kDead) acc_flush(P, tile, rep, acc);
@@ -533,9 +708,9 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // ended in that step needs no direction.
         if ((flags & kSbm) && sbm_pend) {
             if (state != kDead) {
-                const float2 cs = sbm_large(sbm_t, sbm_u);
-                turn(ox, oy, oz, cs.x, cs.y, cos_rev(sbm_ph), sin_rev(sbm_ph));
-                const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+                const CosSin<R> cs = sbm_large<R>((double)sbm_t, (double)sbm_u);
+                turn(ox, oy, oz, cs.c, cs.s, M::cosr(sbm_ph), M::sinr(sbm_ph));
+                const R inv = M::rsq(ox * ox + oy * oy + oz * oz);
                 ox *= inv;
                 oy *= inv;
                 oz *= inv;
@@ -572,20 +747,20 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                         const int mid = (lo + hi + 1) >> 1;
                         if (P.prefix[mid] <= hh) lo = mid; else hi = mid - 1;
                     }
-                    const SpotDev sp = P.spots[lo];
+                    const SpotT<R> sp = spot_at(P, lo, R(0));
                     h = sp.h0 + (hh - P.prefix[lo]);
                     const uint4 w = philox((uint32_t)h, (uint32_t)(h >> 32), 0xFFFFFFFFu, 0u, k0, k1);
-                    const float rr = fsqrt(-2.0f * flog(u_hi(w.x)));
-                    const float a1 = u_hi(w.y);
-                    const float z1 = rr * cos_rev(a1), z2 = rr * sin_rev(a1);
-                    const float z3 = fsqrt(-2.0f * flog(u_hi(w.z))) * cos_rev(u_hi(w.w));
-                    E = sp.E * (1.0f + sp.sigmaE * z3);
+                    const R rr = M::sq(R(-2) * M::lg(u_hi<R>(w.x)));
+                    const R a1 = u_hi<R>(w.y);
+                    const R z1 = rr * M::cosr(a1), z2 = rr * M::sinr(a1);
+                    const R z3 = M::sq(R(-2) * M::lg(u_hi<R>(w.z))) * M::cosr(u_hi<R>(w.w));
+                    E = sp.E * (R(1) + sp.sigmaE * z3);
                     rx = sp.x + sp.sxy * z1;
                     ry = sp.y + sp.sxy * z2;
-                    rz = P.lo[2];
-                    ox = 0.0f;
-                    oy = 0.0f;
-                    oz = 1.0f;
+                    rz = S.lo[2];
+                    ox = R(0);
+                    oy = R(0);
+                    oz = R(1);
                     wsc = sp.wscale;
                     e0 = E;
                     hj = 0;
@@ -593,19 +768,21 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                     j2 = -1;
                     l_hist++;
                     l_e0 += fixp(E, wsc);
-                    if (!inside(P, rx, ry, rz)) {
+                    if (!inside(S, rx, ry, rz)) {
                         l_esc += fixp(E, wsc);
-                        record(P, h, e0, 0, 0, 5, rx, ry, rz, E, -1, -1);
-                    } else if (E < P.e_min) {
-                        score(P, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
-                        record(P, h, e0, 0, 0, 5, rx, ry, rz, E, -1, -1);
+                        record(P, h, (float)e0, 0, 0, 5, (float)rx, (float)ry, (float)rz, (float)E,
+                               -1, -1);
+                    } else if (E < S.e_min) {
+                        score(P, S, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                        record(P, h, (float)e0, 0, 0, 5, (float)rx, (float)ry, (float)rz, (float)E,
+                               -1, -1);
                     } else {
                         int ix, iy, iz;
-                        voxel3(P, rx, ry, rz, ix, iy, iz);
+                        voxel3(P, S, rx, ry, rz, ix, iy, iz);
                         vcache = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) *
                                            (unsigned)P.nx + (unsigned)ix);
                         const uint2 pk = P.vox[vcache];
-                        rho = __uint_as_float(pk.x);
+                        rho = (R)__uint_as_float(pk.x);
                         mat = (int)pk.y;
                         state = kStep;
                     }
@@ -627,14 +804,17 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         if (pend && ((int)__popcll(pend) >= P.jump_batch || stepping == 0ull)) {
             if (state == kJump) {
                 const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), nj, 1u, k0, k1);
-                float u_loss, jc, js, jcp, jsp;
-                jump(P, P.mats + matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp, flags);
+                R u_loss, jc, js, jcp, jsp;
+                if constexpr (M::f64)
+                    jump(P, S, P.mats64[matj], ej, rhoj, q, u_loss, jc, js, jcp, jsp, flags);
+                else
+                    jump(P, S, P.mats[matj], ej, rhoj, q, u_loss, jc, js, jcp, jsp, flags);
                 // E holds E' (after continuous loss); the jump removes u E'
-                const float En = E * (1.0f - u_loss);
+                const R En = E * (R(1) - u_loss);
                 l_nuc += fixp(E, wsc) - fixp(En, wsc);
                 E = En;
                 turn(ox, oy, oz, jc, js, jcp, jsp);
-                const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+                const R inv = M::rsq(ox * ox + oy * oy + oz * oz);
                 ox *= inv;
                 oy *= inv;
                 oz *= inv;
@@ -643,13 +823,15 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 if (j1 < 0) j1 = (int)nj;
                 j2 = (int)nj;
                 state = kStep;
-                if (!inside(P, rx, ry, rz)) {
+                if (!inside(S, rx, ry, rz)) {
                     l_esc += fixp(E, wsc);
-                    record(P, h, e0, n, hj, 2, rx, ry, rz, E, j1, j2);
+                    record(P, h, (float)e0, n, hj, 2, (float)rx, (float)ry, (float)rz, (float)E,
+                           j1, j2);
                     state = kDead;
-                } else if (E < P.e_min) {
-                    score(P, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
-                    record(P, h, e0, n, hj, 3, rx, ry, rz, E, j1, j2);
+                } else if (E < S.e_min) {
+                    score(P, S, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                    record(P, h, (float)e0, n, hj, 3, (float)rx, (float)ry, (float)rz, (float)E,
+                           j1, j2);
                     state = kDead;
                 }
             }
@@ -659,7 +841,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // ---------------- one step of Eq. (VSDE) ----------------
         if ((long long)n >= P.max_steps) {
             atomicAdd(&P.ledger[4], (unsigned long long)fixp(E, wsc));
-            record(P, h, e0, n, hj, 4, rx, ry, rz, E, j1, j2);
+            record(P, h, (float)e0, n, hj, 4, (float)rx, (float)ry, (float)rz, (float)E, j1, j2);
             state = kDead;
             continue;
         }
@@ -668,71 +850,102 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // End of range: residual range within one step, decided in FP64; the
         // FP32 screen E <= ec(material) is exact-safe (ec bounds the energy
         // whose range fits a step at the densest voxel of that material).
-        if ((flags & kEor) && E <= mc.z) {
-            const double rres = range_g64(P, mat, E) / (double)rho;
-            if (rres <= P.step_d) {
-                const float hr = (float)(0.5 * rres);
-                score(P, tile, rep, acc, fmaf(ox, hr, rx), fmaf(oy, hr, ry), fmaf(oz, hr, rz), E, wsc,
-                      l_esc);
+        if ((flags & kEor) && E <= (R)mc.z) {
+            const double rres = range_g64(P, mat, (double)E) / (double)rho;
+            if (rres <= P.sd.step) {
+                const R hr = (R)(0.5 * rres);
+                score(P, S, tile, rep, acc, M::fma(ox, hr, rx), M::fma(oy, hr, ry),
+                      M::fma(oz, hr, rz), E, wsc, l_esc);
                 l_steps++;
-                const float fr = (float)rres;
-                record(P, h, e0, n + 1, hj, 1, fmaf(ox, fr, rx), fmaf(oy, fr, ry),
-                       fmaf(oz, fr, rz), E, j1, j2);
+                const R fr = (R)rres;
+                record(P, h, (float)e0, n + 1, hj, 1, (float)M::fma(ox, fr, rx),
+                       (float)M::fma(oy, fr, ry), (float)M::fma(oz, fr, rz), (float)E, j1, j2);
                 state = kDead;
                 continue;
             }
         }
 
-        const float lnE = flog(E);
-        const float tl = (lnE - P.ln_e_lo) * P.inv_dln;
+        const R lnE = M::lg(E);
+        const R tl = (lnE - S.ln_e_lo) * S.inv_dln;
         const int li = max(0, min((int)tl, P.n_e - 2));
-        const float lf = tl - (float)li;
-        const float4 ta = tab[mat * P.n_e + li], tb = tab[mat * P.n_e + li + 1];
+        const R lf = tl - (R)li;
+        float4 ta, tb;
+        if constexpr (!M::f64) {
+            ta = tab[mat * P.n_e + li];
+            tb = tab[mat * P.n_e + li + 1];
+        }
         const uint4 w = philox((uint32_t)h, (uint32_t)(h >> 32), n, 0u, k0, k1);
 
         // Continuous loss, Eq. (bethbloch) with Bragg additivity; clamped
         // straggling, Eq. (energystraggling), B_n ~ N(0, Delta).
-        const float p2 = E * (E + 2.0f * kMpF);
-        const float g = E + kMpF;
-        const float b2 = p2 * frcp(g * g);
-        float s1 = 0.0f;
+        R zoa, log_pre;
+        if constexpr (M::f64) {
+            zoa = P.mats64[mat].zoa;
+            log_pre = P.mats64[mat].log_pre;
+        } else {
+            zoa = mc.x;
+            log_pre = mc.y;
+        }
+        const R p2 = E * (E + R(2) * (R)kMp);
+        const R g = E + (R)kMp;
+        const R b2 = p2 * M::rcp(g * g);
+        R s1 = R(0);
         if (flags & kLoss) {
-            const float L = mc.y + flog(p2) - b2;
-            s1 = rho * P.c_bethe * mc.x * L * frcp(b2);
+            const R L = log_pre + M::lg(p2) - b2;
+            s1 = rho * S.c_bethe * zoa * L * M::rcp(b2);
         }
-        const float a = s1 * P.step;
-        float X = 0.0f;
+        const R a = s1 * S.step;
+        R X = R(0);
         if (flags & kStraggle) {
-            const float gm = g * (1.0f / kMpF);
-            const float var = rho * P.c_strag * mc.x * gm * gm * (1.0f - 0.5f * b2);
-            const float zE = fsqrt(-2.0f * flog(u_hi(w.x))) * cos_rev(u_hi(w.y));
-            X = fminf(fmaxf(fsqrt(var) * P.sqrt_step * zE, -a), a);
+            const R gm = g * (R(1) / (R)kMp);
+            const R var = rho * S.c_strag * zoa * gm * gm * (R(1) - R(0.5) * b2);
+            const R zE = M::sq(R(-2) * M::lg(u_hi<R>(w.x))) * M::cosr(u_hi<R>(w.y));
+            X = fmin(fmax(M::sq(var) * S.sqrt_step * zE, -a), a);
         }
-        const float Ep = fmaxf(E - a + X, 0.0f);
+        const R Ep = fmax(E - a + X, R(0));
 
-        // Jump test: none with probability exp(-Delta sigma).  Elastic rate
-        // (Rutherford + Mott) = el_E2 / E^2 with el_E2 smooth in ln E;
-        // inelastic rate linear on the lattice.
+        // Jump test: none with probability exp(-Delta sigma).  float: elastic
+        // rate (Rutherford + Mott) = el_E2 / E^2 with el_E2 smooth in ln E,
+        // inelastic rate linear on the lattice; double: the elastic rate from
+        // its closed form at E.
         bool jumped = false;
         if (flags & (kElastic | kInelastic)) {
-            const float el_e2 = fmaf(lf, tb.w - ta.w, ta.w);
-            const float ne_rate = fmaf(lf, tb.z - ta.z, ta.z);
-            const float rate = ((flags & kElastic) ? el_e2 * frcp(E * E) : 0.0f) +
-                               ((flags & kInelastic) ? ne_rate : 0.0f);
-            const float lam = P.step * rho * rate;
-            const float pj = lam < 0.05f
-                ? lam * fmaf(-0.5f * lam, fmaf(-lam * (1.0f / 3.0f), fmaf(-0.25f, lam, 1.0f), 1.0f), 1.0f)
-                : 1.0f - __expf(-lam);
-            jumped = u_lo(w.x, w.y, w.z) < pj;
+            R rate;
+            if constexpr (M::f64) {
+                const MatDev64& md = P.mats64[mat];
+                const double2 ha = P.hot64[(size_t)mat * P.n_e + li];
+                const double2 hb = P.hot64[(size_t)mat * P.n_e + li + 1];
+                rate = R(0);
+                if (flags & kElastic) {
+                    R el = md.c_ruth;
+                    if (md.c_mott != 0.0) el += md.c_mott * mott_bracket(S, S.eta_pre / ::sqrt(E));
+                    rate += el / (E * E);
+                }
+                if (flags & kInelastic) rate += ::fma(lf, hb.x - ha.x, ha.x);
+            } else {
+                const float el_e2 = fmaf(lf, tb.w - ta.w, ta.w);
+                const float ne_rate = fmaf(lf, tb.z - ta.z, ta.z);
+                rate = ((flags & kElastic) ? el_e2 * M::rcp(E * E) : 0.0f) +
+                       ((flags & kInelastic) ? ne_rate : 0.0f);
+            }
+            const R lam = S.step * rho * rate;
+            R pj;
+            if constexpr (M::f64)
+                pj = -::expm1(-lam);
+            else
+                pj = lam < 0.05f
+                    ? lam * fmaf(-0.5f * lam, fmaf(-lam * (1.0f / 3.0f), fmaf(-0.25f, lam, 1.0f), 1.0f), 1.0f)
+                    : 1.0f - __expf(-lam);
+            jumped = u_lo<R>(w.x, w.y, w.z) < pj;
         }
 
         // Deposit E_n - E' at the step midpoint (pre-step direction), move.
         // Both R_n and, when in_next, R_{n+1} lie in the box, and so does the
         // midpoint: its inside test is needed only when R_{n+1} left.
-        const float nx = fmaf(ox, P.step, rx), ny = fmaf(oy, P.step, ry), nz = fmaf(oz, P.step, rz);
-        const bool in_next = inside(P, nx, ny, nz);
-        score(P, tile, rep, acc, fmaf(ox, P.half_step, rx), fmaf(oy, P.half_step, ry),
-              fmaf(oz, P.half_step, rz), E - Ep, wsc, l_esc, !in_next);
+        const R nx = M::fma(ox, S.step, rx), ny = M::fma(oy, S.step, ry), nz = M::fma(oz, S.step, rz);
+        const bool in_next = inside(S, nx, ny, nz);
+        score(P, S, tile, rep, acc, M::fma(ox, S.half_step, rx), M::fma(oy, S.half_step, ry),
+              M::fma(oz, S.half_step, rz), E - Ep, wsc, l_esc, !in_next);
         rx = nx;
         ry = ny;
         rz = nz;
@@ -740,7 +953,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         int v_next = vcache;
         if (in_next) {   // prefetch the next voxel while the direction is updated
             int ix, iy, iz;
-            voxel3(P, rx, ry, rz, ix, iy, iz);
+            voxel3(P, S, rx, ry, rz, ix, iy, iz);
             v_next = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx +
                            (unsigned)ix);
             if (v_next != vcache) pk_next = P.vox[v_next];
@@ -752,30 +965,35 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         // Box-Muller pair) or the geodesic Gaussian step of per-axis
         // variance t.
         if (flags & kMcs) {
-            const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
-            const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
-            const float nu = rho * A2;
-            const float br = (1.0f + frcp(nu)) * flog(1.0f + nu) - 1.0f;
-            const float sig2 = rho * A1 * br;
-            float ct = 1.0f, st = 0.0f;
+            R sig2;
+            if constexpr (M::f64) {
+                sig2 = ld_time64(P.mats64[mat], S, rho, E);
+            } else {
+                const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
+                const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
+                const float nu = rho * A2;
+                const float br = (1.0f + M::rcp(nu)) * M::lg(1.0f + nu) - 1.0f;
+                sig2 = rho * A1 * br;
+            }
+            R ct = R(1), st = R(0);
             bool now = true;
             if (flags & kSbm) {
-                if (sig2 < kSbmSwitch) {
-                    const float zM = fsqrt(-2.0f * flog(u_hi(w.x))) * sin_rev(u_hi(w.y));
-                    sbm_small(sig2, zM, u_hi(w.z), ct, st);
+                if (sig2 < SbmSwitch<R>::t) {
+                    const R zM = M::sq(R(-2) * M::lg(u_hi<R>(w.x))) * M::sinr(u_hi<R>(w.y));
+                    sbm_small(sig2, zM, u_hi<R>(w.z), ct, st);
                 } else {   // exact regime: drawn at the top of the loop
                     now = false;
                     sbm_pend = true;
                     sbm_t = sig2;
-                    sbm_u = u_hi(w.z);
-                    sbm_ph = u_hi(w.w);
+                    sbm_u = u_hi<R>(w.z);
+                    sbm_ph = u_hi<R>(w.w);
                 }
             } else {
-                polar_cs(-2.0f * sig2 * flog(u_hi(w.z)), ct, st);
+                polar_cs(R(-2) * sig2 * M::lg(u_hi<R>(w.z)), ct, st);
             }
             if (now) {
-                const float ph = u_hi(w.w);
-                turn(ox, oy, oz, ct, st, cos_rev(ph), sin_rev(ph));
+                const R ph = u_hi<R>(w.w);
+                turn(ox, oy, oz, ct, st, M::cosr(ph), M::sinr(ph));
             }
         }
         l_steps++;
@@ -789,7 +1007,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
             n++;
             state = kJump;
         } else {
-            const float inv = __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+            const R inv = M::rsq(ox * ox + oy * oy + oz * oz);
             ox *= inv;
             oy *= inv;
             oz *= inv;
@@ -797,16 +1015,18 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
             n++;
             if (!in_next) {
                 l_esc += fixp(E, wsc);
-                record(P, h, e0, n, hj, 2, rx, ry, rz, E, j1, j2);
+                record(P, h, (float)e0, n, hj, 2, (float)rx, (float)ry, (float)rz, (float)E, j1,
+                       j2);
                 state = kDead;
-            } else if (E < P.e_min) {
-                score(P, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
-                record(P, h, e0, n, hj, 3, rx, ry, rz, E, j1, j2);
+            } else if (E < S.e_min) {
+                score(P, S, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                record(P, h, (float)e0, n, hj, 3, (float)rx, (float)ry, (float)rz, (float)E, j1,
+                       j2);
                 state = kDead;
             }
         }
         if (in_next && v_next != vcache) {
-            rho = __uint_as_float(pk_next.x);
+            rho = (R)__uint_as_float(pk_next.x);
             mat = (int)pk_next.y;
             vcache = v_next;
         }
@@ -932,18 +1152,38 @@ __global__ void k_sbm_polar(const float* __restrict__ t, const float* __restrict
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float ct, st;
-    if (t[i] < kSbmSwitch) {
+    if (t[i] < SbmSwitch<float>::t) {
         sbm_small(t[i], z[i], u[i], ct, st);
     } else {
-        const float2 cs = sbm_large(t[i], u[i]);
-        ct = cs.x;
-        st = cs.y;
+        const CosSin<float> cs = sbm_large<float>((double)t[i], (double)u[i]);
+        ct = cs.c;
+        st = cs.s;
     }
     c[i] = ct;
     s[i] = st;
 }
 
+// Raw Philox4x32-10 blocks for given counters (the transport's generator),
+// so that its words can be compared with another implementation bit for bit.
+__global__ void k_philox_words(unsigned long long seed, const unsigned long long* __restrict__ h,
+                               const unsigned* __restrict__ n, const unsigned* __restrict__ b,
+                               int count, uint4* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const unsigned long long hh = h[i];
+    out[i] = philox((uint32_t)hh, (uint32_t)(hh >> 32), n[i], b[i], (uint32_t)seed,
+                    (uint32_t)(seed >> 32));
+}
+
 }  // namespace
+
+hipError_t launch_philox_words(unsigned long long seed, const unsigned long long* h,
+                               const unsigned* n, const unsigned* b, int count, uint4* out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_philox_words, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       seed, h, n, b, count, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack_phantom(const uint8_t* mat, const float* rho, uint2* vox, size_t nvox,
                                int n_mat, unsigned int* bad, unsigned int* rho_max_bits,
@@ -969,9 +1209,10 @@ hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long lo
 }
 
 hipError_t transport_kernel_attributes(size_t lds_bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<kMethod>),
-                         reinterpret_cast<const void*>(&k_transport<kMethodGeodesic>),
-                         reinterpret_cast<const void*>(&k_transport<0u>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<float, kMethod>),
+                         reinterpret_cast<const void*>(&k_transport<float, kMethodGeodesic>),
+                         reinterpret_cast<const void*>(&k_transport<float, 0u>),
+                         reinterpret_cast<const void*>(&k_transport<double, 0u>)};
     for (const void* f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
@@ -982,13 +1223,16 @@ hipError_t transport_kernel_attributes(size_t lds_bytes) {
 
 hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
                             hipStream_t s) {
-    if (p.flags == kMethod)
-        hipLaunchKernelGGL(k_transport<kMethod>, dim3(grid), dim3(block), lds_bytes, s, p);
-    else if (p.flags == kMethodGeodesic)
-        hipLaunchKernelGGL(k_transport<kMethodGeodesic>, dim3(grid), dim3(block), lds_bytes, s,
+    if (p.fp64)
+        hipLaunchKernelGGL((k_transport<double, 0u>), dim3(grid), dim3(block), lds_bytes, s, p);
+    else if (p.flags == kMethod)
+        hipLaunchKernelGGL((k_transport<float, kMethod>), dim3(grid), dim3(block), lds_bytes, s,
                            p);
+    else if (p.flags == kMethodGeodesic)
+        hipLaunchKernelGGL((k_transport<float, kMethodGeodesic>), dim3(grid), dim3(block),
+                           lds_bytes, s, p);
     else
-        hipLaunchKernelGGL(k_transport<0u>, dim3(grid), dim3(block), lds_bytes, s, p);
+        hipLaunchKernelGGL((k_transport<float, 0u>), dim3(grid), dim3(block), lds_bytes, s, p);
     return hipGetLastError();
 }
 

@@ -12,7 +12,9 @@
 //     el = elastic jump rate per unit density times E^2: the Rutherford part
 //          is constant and the Mott part nearly so, so interpolating el and
 //          dividing by E^2 keeps the rate's 1/E^2 shape exact;
-//   rg64[i] = {Rg, dRg/dt} in FP64 for the cubic-Hermite end-of-range decision.
+//   rg64[i] = {Rg, dRg/dt} in FP64 for the cubic-Hermite end-of-range decision;
+//   hot64[i] = {ne, el} unrounded, and per medium the Lynch-Dahl, Bethe and
+//   jump constants in FP64 (MatDev64), for the double-precision instance.
 // Per element: the constants of the rate laws (section 2.1.4, Eq.
 // (large_elastic_cm) and Eq. (large_elastic_cm_hydrogen); section 2.1.5).
 #include <cmath>
@@ -119,7 +121,7 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         *err = "invalid physics parameters";
         return SDE_E_INVALID;
     }
-    if (p->flags & ~(unsigned)SDE_ALL) {
+    if (p->flags & ~(unsigned)(SDE_ALL | SDE_FP64)) {
         *err = "unknown physics switch bits";
         return SDE_E_INVALID;
     }
@@ -172,17 +174,27 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             T.nuc_r[i] = (float)nuc->kalbach_r[i];
             T.nuc_a[i] = (float)nuc->kalbach_a[i];
         }
+        T.nuc_sigma64.assign(nuc->sigma_barn, nuc->sigma_barn + ns);
+        T.nuc_u64.assign(nuc->u_icdf, nuc->u_icdf + nu);
+        T.nuc_r64.assign(nuc->kalbach_r, nuc->kalbach_r + nu);
+        T.nuc_a64.assign(nuc->kalbach_a, nuc->kalbach_a + nu);
     } else {
         T.nuc_sigma.assign(1, 0.f);
         T.nuc_u.assign(2, 0.f);
         T.nuc_r.assign(2, 0.f);
         T.nuc_a.assign(2, 0.f);
+        T.nuc_sigma64.assign(1, 0.0);
+        T.nuc_u64.assign(2, 0.0);
+        T.nuc_r64.assign(2, 0.0);
+        T.nuc_a64.assign(2, 0.0);
     }
 
     const Gauss G;
     T.hot.resize((size_t)n_mats * T.n_e);
+    T.hot64.resize((size_t)n_mats * T.n_e);
     T.rg64.resize((size_t)n_mats * T.n_e);
     T.mats.resize(n_mats);
+    T.mats64.resize(n_mats);
     std::vector<double> E(T.n_e);
     for (int i = 0; i < T.n_e; ++i) E[i] = std::exp(T.ln_e_lo + i * T.dln);
     E[0] = T.e_lo;
@@ -216,9 +228,13 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         }
 
         MatDev md{};
+        MatDev64 m64{};
         double c_ruth_d = 0, c_mott_d = 0;   // FP64 sums of the elastic coefficients
-        md.zoa = (float)zoa(m);
-        md.log_pre = (float)(std::log(2.0 * kMe / m.I_MeV) - 2.0 * std::log(kMp));
+        m64.zoa = zoa(m);
+        m64.log_pre = std::log(2.0 * kMe / m.I_MeV) - 2.0 * std::log(kMp);
+        m64.n_elem = m.n;
+        md.zoa = (float)m64.zoa;
+        md.log_pre = (float)m64.log_pre;
         md.n_elem = m.n;
         for (int i = 0; i < m.n; ++i) {
             ElemDev& e = md.el[i];
@@ -239,6 +255,14 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             if (e.is_h) e.tab = -1;
             const double coef = e.is_h ? pre : pre * (T.ruth_T - 0.5);
             if (e.is_h) c_mott_d += coef; else c_ruth_d += coef;
+            m64.wz[i] = m.w[i] * Z * (Z + 1.0) / A;
+            m64.ln_ca[i] = std::log(2.007e-5 * std::cbrt(Z * Z));
+            m64.za2[i] = 3.34 * (Z * kAlpha) * (Z * kAlpha);
+            m64.el_coef[i] = coef;
+            m64.ne_coef[i] = nd * 1e-24;
+            m64.m2[i] = A * kAmu;
+            m64.is_h[i] = e.is_h;
+            m64.tab[i] = e.tab;
         }
 
         // elastic rate per unit density times E^2 at En
@@ -272,6 +296,7 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             h.z = (float)ne_rate_at(i);
             h.w = (float)el_e2_at(E[i]);
             T.hot[(size_t)k * T.n_e + i] = h;
+            T.hot64[(size_t)k * T.n_e + i] = make_double2(ne_rate_at(i), el_e2_at(E[i]));
             double2 r;
             r.x = Rg;
             r.y = E[i] / stopping(m, E[i]) * T.dln;   // dRg / dt, t the lattice coordinate
@@ -280,6 +305,9 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         md.c_ruth = (float)c_ruth_d;
         md.c_mott = (float)c_mott_d;
         T.mats[k] = md;
+        m64.c_ruth = c_ruth_d;
+        m64.c_mott = c_mott_d;
+        T.mats64[k] = m64;
     }
     return SDE_OK;
 }

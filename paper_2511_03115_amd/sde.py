@@ -22,12 +22,13 @@ OK, E_INVALID, E_HIP, E_RANGE, E_OVERFLOW, E_STATE, E_NOMEM = 0, -1, -2, -3, -4,
 LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, END_OF_RANGE = 1, 2, 4, 8, 16, 32
 SBM = 64   # small-angle diffusion by the spherical Brownian motion law (else geodesic step)
 ALL = 127  # the method
+FP64 = 128  # step in double precision (not a physics switch)
 (LEDGER_DEPOSITED, LEDGER_ESCAPED, LEDGER_NUCLEAR, LEDGER_INITIAL, LEDGER_TRUNCATED,
  LEDGER_STEPS, LEDGER_HISTORIES, LEDGER_JUMPS) = range(8)
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",
            "sde_plan_create", "sde_plan_execute", "sde_plan_results", "sde_plan_destroy",
            "sde_plan_kernel_ms", "sde_plan_set_records", "sde_gamma", "sde_launch_limits",
-           "sde_sbm_polar", "sde_free", "sde_last_error")
+           "sde_sbm_polar", "sde_philox_words", "sde_free", "sde_last_error")
 
 
 class SdeError(RuntimeError):
@@ -102,6 +103,7 @@ def _load():
                             C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, P(C.c_int64)]
     L.sde_launch_limits.argtypes = [P(C.c_int), P(C.c_int), P(C.c_int)]
     L.sde_sbm_polar.argtypes = [V, V, V, C.c_int64, V, V]
+    L.sde_philox_words.argtypes = [C.c_uint64, V, V, V, C.c_int64, V]
     L.sde_free.argtypes = []
     L.sde_free.restype = None
     L.sde_last_error.argtypes = []
@@ -320,6 +322,21 @@ def sbm_polar(t, u, z):
     _check(lib.sde_sbm_polar(C.c_void_p(_dptr(t)), C.c_void_p(_dptr(u)), C.c_void_p(_dptr(z)),
                              int(n), C.c_void_p(_dptr(c)), C.c_void_p(_dptr(s))))
     return c, s
+
+
+def philox_words(seed: int, h, n, b):
+    """Philox4x32-10 blocks (count, 4) uint32 -> int32 tensor as the transport
+    draws them, for device tensors h (int64), n, b (int32) of one length."""
+    import torch
+    count = h.numel()
+    assert n.numel() == count and b.numel() == count
+    assert h.dtype == torch.int64 and n.dtype == torch.int32 and b.dtype == torch.int32
+    for a in (h, n, b):
+        assert a.is_cuda and a.is_contiguous()
+    out = torch.empty((count, 4), dtype=torch.int32, device=h.device)
+    _check(lib.sde_philox_words(C.c_uint64(seed), C.c_void_p(_dptr(h)), C.c_void_p(_dptr(n)),
+                                C.c_void_p(_dptr(b)), int(count), C.c_void_p(_dptr(out))))
+    return out
 
 
 def gamma(ref, ev, voxel_cm, dd: float = 0.02, dta_cm: float = 0.05, thresh: float = 0.01,

@@ -80,10 +80,20 @@ def test_host_validation_without_gpu(lib):
     assert lib.sde_sbm_polar(None, None, None, 5, None, None) == sde.E_INVALID
     assert lib.sde_sbm_polar(None, None, None, -1, None, None) == sde.E_INVALID
     assert lib.sde_sbm_polar(None, None, None, 0, None, None) == sde.OK
-    # physics switch bits other than SDE_ALL | SDE_SBM
-    unk = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63 | 128, 65536)
+    # bits other than the physics switches and SDE_FP64
+    unk = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63 | 256, 65536)
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(unk), None) == sde.E_INVALID
     assert b"unknown physics switch" in lib.sde_last_error()
+    # the random-number test entry point checks its arguments before any device call
+    lib.sde_philox_words.argtypes = [C.c_uint64] + [C.c_void_p] * 3 + [C.c_int64, C.c_void_p]
+    V = C.c_void_p
+    assert lib.sde_philox_words(0, None, None, None, 4, None) == sde.E_INVALID
+    assert lib.sde_philox_words(0, None, None, None, -1, None) == sde.E_INVALID
+    assert lib.sde_philox_words(0, None, None, None, 0, None) == sde.OK
+    # a misaligned output (the fake addresses are never dereferenced)
+    assert lib.sde_philox_words(0, V(0x10000), V(0x10000), V(0x10000), 4, V(0x10008)) == \
+        sde.E_INVALID
+    assert b"misaligned" in lib.sde_last_error()
     # a medium whose Bethe stopping power is negative at e_min (I far too large)
     m.I_eV = 5000.0
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(pp), None) == sde.E_INVALID

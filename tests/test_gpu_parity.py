@@ -268,7 +268,7 @@ def test_gamma_kernel_matches_oracle():
         f1, ne1, np1 = sde.gamma(torch.from_numpy(ref).cuda(), torch.from_numpy(ev).cuda(), d,
                                  0.02, 0.05, 0.01, 10, local)
         log(f"gamma local={local} oracle {ne0}/{np0} gpu {ne1}/{np1}")
-        assert ne0 == ne1 and abs(np0 - np1) <= 1
+        assert ne0 == ne1 and np0 == np1
 
 
 def test_errors_are_reported():

@@ -40,6 +40,7 @@ F_INELASTIC = 16
 F_END_OF_RANGE = 32
 F_SBM = 64
 F_ALL = 127
+F_FP64 = 128   # not a physics switch: the GPU path steps in double precision
 
 
 @dataclass(frozen=True)
