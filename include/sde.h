@@ -53,7 +53,7 @@ typedef enum {
 #define SDE_MAX_MAT 8     /* materials per phantom (LDS table budget) */
 
 /* Physics switches (sde_physics_params.flags).  SDE_ALL is the method;
- * bits other than these and SDE_FP64 are rejected. */
+ * bits other than these, SDE_FP64 and SDE_ECUT are rejected. */
 #define SDE_LOSS 1u          /* continuous loss, Eq. (bethbloch) */
 #define SDE_STRAGGLE 2u      /* straggling noise, Eq. (energystraggling) */
 #define SDE_MCS 4u           /* small-angle diffusion on S^2 */
@@ -76,6 +76,15 @@ typedef enum {
  * reference, several times slower than the default single-precision
  * stepping.  Combines with any set of the switches above. */
 #define SDE_FP64 128u
+/* Variant of the method: the large-angle elastic cut (the upper limit
+ * cos(2.5 sigma(E)) of Eq. (large_elastic_cm) and of the CM cosine drawn by
+ * Eq. (large_elastic_cdf)) is 2.5 sigma(E), sigma the Lynch-Dahl width of
+ * section 2.1.4 for the step's medium and density over the path ld_z_cm,
+ * instead of the fixed theta_cut_rad the paper's runs use (the paper names
+ * the energy-dependent cut, section 2.1.4, and leaves it for later,
+ * section 4).  Limited to pi (pi - backscatter_cut_rad for hydrogen), where
+ * the elastic rate vanishes.  Runs in the general instance. */
+#define SDE_ECUT 256u
 
 /* Ledger slots (sde_transport_ex ledger_out) */
 #define SDE_LEDGER_DEPOSITED 0   /* energy scored inside the phantom (fixed point) */

@@ -35,6 +35,8 @@ MAX_MAT = 16
 LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, EOR = 1, 2, 4, 8, 16, 32
 SBM = 64   # small-angle diffusion by the spherical Brownian motion law (else geodesic step)
 ALL = 127  # the method
+ECUT = 256  # variant: large-angle elastic cut 2.5 sigma(E) instead of the fixed 0.02 rad
+PHYSICS = ALL | ECUT   # every bit the oracle reads
 
 # ledger slots and record fields (mirror the enums of sde_oracle.c)
 L_DEP, L_ESC, L_NUC, L_E0, L_TRUNC, L_STEPS, L_HIST, L_JUMPS = range(8)
@@ -129,6 +131,8 @@ def lib():
         L.or_sbm_t_switch.restype = d
         L.or_sbm_polar_n.argtypes = [C.c_size_t, d, P(d), P(d), P(d), P(d)]
         L.or_sbm_polar_n.restype = None
+        L.or_elastic_cut.argtypes = [P(Material), P(Params), d, d]
+        L.or_elastic_cut.restype = d
         L.or_channel_total_rate.argtypes = [P(Material), P(Nuclear), P(Params), d, d]
         L.or_channel_total_rate.restype = d
         L.or_rng_block.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -198,7 +202,7 @@ def params_struct(p, flags: Optional[int] = None) -> Params:
     s.ld_F, s.theta_cut, s.theta_bs = p.ld_F, p.theta_cut_rad, p.backscatter_cut_rad
     s.max_steps = int(p.max_steps)
     # the oracle always steps in double precision: only the physics switches count
-    s.flags = int(p.flags if flags is None else flags) & ALL
+    s.flags = int(p.flags if flags is None else flags) & PHYSICS
     return s
 
 
@@ -431,6 +435,13 @@ def rng_blocks(seed: int, h: np.ndarray, n: np.ndarray, b: np.ndarray) -> np.nda
     lib().or_rng_blocks(C.c_uint64(seed), h.size, _ptr(h, C.c_uint64), _ptr(n, C.c_uint32),
                         _ptr(b, C.c_uint32), _ptr(out, C.c_uint32))
     return out
+
+
+def elastic_cut(m, params, rho: float, E: float, flags=None) -> float:
+    """The large-angle elastic cut (CM, rad) at E in medium m of density rho."""
+    s = material_struct(m)
+    ps = params_struct(params, flags)
+    return lib().or_elastic_cut(C.byref(s), C.byref(ps), float(rho), float(E))
 
 
 def channel_total_rate(m, params, rho: float, E: float, nuclear=None, flags=None) -> float:

@@ -42,6 +42,7 @@
 #define OR_INELASTIC 16
 #define OR_EOR 32
 #define OR_SBM 64   /* small-angle diffusion by the spherical Brownian motion law */
+#define OR_ECUT 256 /* large-angle elastic cut 2.5 sigma(E) instead of the fixed theta_cut */
 
 /* CODATA 2018 values (the paper does not print them) */
 static const double MASS_P = 938.27208816;     /* proton rest energy, MeV */
@@ -302,21 +303,42 @@ static double table_eu(const or_nuclear* nu, const double* tab, double E, double
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int n;
+    double theta_c;                /* the elastic cut (CM), rad */
     double rate[2 * OR_MAX_ELEM];  /* per cm */
     int elem[2 * OR_MAX_ELEM];
     int inel[2 * OR_MAX_ELEM];
     int tab[2 * OR_MAX_ELEM];
 } channels;
 
+/* The large-angle elastic cut at E in medium m of density rho.  Fixed:
+ * theta_cut, as the paper's runs take it.  With OR_ECUT: 2.5 sigma(E), sigma
+ * the Lynch-Dahl width of section 2.1.4 for this medium and density over the
+ * path z of that width (the cut the paper states and names as energy
+ * dependent), applied to the CM angle like the fixed cut. */
+static double elastic_cut(const or_material* m, const or_params* p, double rho, double E) {
+    if (!(p->flags & OR_ECUT)) return p->theta_cut;
+    return 2.5 * lynch_dahl_sigma(m, rho, E, p->ld_z_cm, p->ld_F);
+}
+
+/* The cut limited to the range where the law is defined: pi for Rutherford
+ * (the rate vanishes there), pi - theta_bs for hydrogen (the interval
+ * [-cos theta_bs, cos theta_c] closes there). */
+static double cut_for(int Z, double theta_c, double theta_bs) {
+    double top = (Z == 1) ? M_PI - theta_bs : M_PI;
+    return theta_c < top ? theta_c : top;
+}
+
 static void channel_rates(const or_material* m, const or_nuclear* nu, const or_params* p,
                           double rho, double E, channels* c) {
     c->n = 0;
+    c->theta_c = elastic_cut(m, p, rho, E);
     for (int i = 0; i < m->n_elem; ++i) {
         double nd = N_A * rho * m->w[i] / m->A[i];    /* atoms per cm^3 */
         if (p->flags & OR_ELASTIC) {
+            double tc = cut_for(m->Z[i], c->theta_c, p->theta_bs);
             double xs = (m->Z[i] == 1)
-                ? mott_integral_barn(m->A[i], E, p->theta_cut, p->theta_bs)
-                : rutherford_integral_barn(m->Z[i], m->A[i], E, p->theta_cut);
+                ? mott_integral_barn(m->A[i], E, tc, p->theta_bs)
+                : rutherford_integral_barn(m->Z[i], m->A[i], E, tc);
             /* 2 pi from the azimuth, 1e-24 cm^2 per barn (Eq. (large_elastic_cm)) */
             c->rate[c->n] = 2.0 * M_PI * nd * xs * 1e-24;
             c->elem[c->n] = i; c->inel[c->n] = 0; c->tab[c->n] = -1;
@@ -655,6 +677,9 @@ double or_table_eu(const or_nuclear* nu, int t, int which, double E, double x) {
     const double* base = which == 0 ? nu->u_icdf : which == 1 ? nu->kr : nu->ka;
     return table_eu(nu, base + (size_t)t * nu->n_e * nu->n_u, E, x);
 }
+double or_elastic_cut(const or_material* m, const or_params* p, double rho, double E) {
+    return elastic_cut(m, p, rho, E);
+}
 double or_channel_total_rate(const or_material* m, const or_nuclear* nu, const or_params* p,
                              double rho, double E) {
     channels c;
@@ -833,11 +858,12 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
                 int e = ch.elem[c];
                 double cos_cm, sin_cm;
                 if (!ch.inel[c]) {
+                    double tc = cut_for(m->Z[e], ch.theta_c, p->theta_bs);
                     if (m->Z[e] == 1) {
-                        cos_cm = mott_sample_mu(E, u_hi(q[1]), p->theta_cut, p->theta_bs);
+                        cos_cm = mott_sample_mu(E, u_hi(q[1]), tc, p->theta_bs);
                         sin_cm = sqrt(fmax(0.0, 1.0 - cos_cm * cos_cm));
                     } else {
-                        double om = rutherford_one_minus_mu(u_hi(q[1]), p->theta_cut);
+                        double om = rutherford_one_minus_mu(u_hi(q[1]), tc);
                         cos_cm = 1.0 - om;
                         sin_cm = sqrt(om * (2.0 - om));
                     }

@@ -44,106 +44,242 @@ __device__ __forceinline__ bool trilinear(const double* g, int nx, int ny, int n
     return true;
 }
 
-// Range [lo, hi] of the trilinear interpolant of g over the box
-// |x - node| <= r per axis around grid node (ix, iy, iz), clipped to the
-// grid, for r <= 1 voxel on every axis.  The box then lies in the 8 cells
-// around the node, the interpolant is multilinear in each, and so its
-// extremes over the box are at the 27 points node + {-r, 0, r}^3 (clipped),
-// evaluated here separably from the 27 node values around the node.
-__device__ __forceinline__ void box_range(const double* g, int nx, int ny, int nz, int ix, int iy,
-                                          int iz, double rx, double ry, double rz, double& lo,
-                                          double& hi) {
-    int xs[3] = {max(ix - 1, 0), ix, min(ix + 1, nx - 1)};
-    int ys[3] = {max(iy - 1, 0), iy, min(iy + 1, ny - 1)};
-    int zs[3] = {max(iz - 1, 0), iz, min(iz + 1, nz - 1)};
-    double a[3][3][3];   // [z node][y node][x point]
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double* row = g + ((size_t)zs[k] * ny + ys[j]) * nx;
-            const double v0 = row[xs[0]], v1 = row[xs[1]], v2 = row[xs[2]];
-            a[k][j][0] = v1 + rx * (v0 - v1);
-            a[k][j][1] = v1;
-            a[k][j][2] = v1 + rx * (v2 - v1);
-        }
-    double b[3][3][3];   // [z node][y point][x point]
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            const double v0 = a[k][0][p], v1 = a[k][1][p], v2 = a[k][2][p];
-            b[k][0][p] = v1 + ry * (v0 - v1);
-            b[k][1][p] = v1;
-            b[k][2][p] = v1 + ry * (v2 - v1);
-        }
-    lo = b[1][1][1];
-    hi = lo;
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            const double v0 = b[0][q][p], v1 = b[1][q][p], v2 = b[2][q][p];
-            const double m0 = v1 + rz * (v0 - v1), m2 = v1 + rz * (v2 - v1);
-            lo = fmin(lo, fmin(v1, fmin(m0, m2)));
-            hi = fmax(hi, fmax(v1, fmax(m0, m2)));
-        }
+constexpr int kMaxK = 50;   // largest interp (offsets per dta per axis)
+
+// Everything the two gamma kernels read.
+struct GammaArgs {
+    const double* ref;
+    const double* ev;
+    int nx, ny, nz, K;
+    double st, dta, dx, dy, dz;      // lattice spacing dta / K, dta, voxel size (cm)
+    double dd, thr_abs, max_ref;
+    int local, use_bound;
+};
+
+// Per axis and lattice index a in [-K, K]: a st (cm) and a st / d (voxels),
+// in LDS.
+struct GammaLattice {
+    double cm[3][2 * kMaxK + 1];
+    double vx[3][2 * kMaxK + 1];
+};
+
+__device__ __forceinline__ void fill_lattice(const GammaArgs& A, GammaLattice& L) {
+    const int nl = 2 * A.K + 1;
+    for (int t = threadIdx.x; t < 3 * nl; t += blockDim.x) {
+        const int ax = t / nl, a = t % nl - A.K;
+        const double v = a * A.st;
+        L.cm[ax][a + A.K] = v;
+        L.vx[ax][a + A.K] = v / (ax == 0 ? A.dx : ax == 1 ? A.dy : A.dz);
+    }
+    __syncthreads();
 }
 
-// Gamma index, one thread per reference voxel.  off[k] = (ox / dx, oy / dy,
-// oz / dz, |o|^2 / dta^2) for the lattice offsets o of spacing dta/interp
-// within dta, nearest first (off[0] = 0); a voxel passes when
-// |o|^2 / dta^2 + (de - dr)^2 / norm^2 <= 1 at some offset, de the trilinear
-// value of the evaluated map there.  Voxels failing at o = 0 take a bound
-// first (when dta is at most a voxel on every axis): every de reachable lies
-// in the range of the interpolant over the search box, so with d the
-// distance from dr to that range no offset passes once |o|^2 / dta^2 >
-// 1 - d^2 / norm^2, and none at all when d > norm.  The bound is loosened by
-// 1e-12 (relative in d, absolute in the limit) so that it never drops an
-// offset whose evaluated test would pass.  counts[0] evaluated, counts[1]
-// passed.
-__global__ void __launch_bounds__(256) k_gamma(const double* ref, const double* ev, int nx,
-                                               int ny, int nz, const double4* off, int n_off,
-                                               double dd, double thr_abs, double max_ref,
-                                               int local, double rx, double ry, double rz,
-                                               int use_bound, unsigned long long* counts) {
+// The gamma test of reference voxel (ix, iy, iz) with dose dr at every
+// offset but the zero one: the voxel passes when some offset o of the
+// lattice of spacing st = dta/K within dta (o = st (a, b, c),
+// a^2 + b^2 + c^2 <= K^2) has |o|^2 / dta^2 + (de - dr)^2 / norm^2 <= 1, de
+// the trilinear value of the evaluated map at the voxel plus o.
+//
+// The lattice is walked octant by octant: with dta below a voxel on every
+// axis, the offsets of one sign pattern all fall in one cell of the grid,
+// whose 8 corner values are then held in registers and the trilinear value
+// is formed factor by factor (the x factors once per a, the y factors once
+// per b), the same products and sums in the same order as the definition's
+// expression.  Per octant a bound first: the interpolant is multilinear in
+// the cell, so its range over the octant's box is that of the box's 8
+// corners; with d the distance from dr to the range, no offset with
+// |o|^2 / dta^2 > 1 - d^2 / norm^2 passes, which limits a^2 + b^2 + c^2
+// (loosened by 1e-9 so that no offset whose evaluated test would pass is
+// dropped).  Each offset's test is screened with multiplications by
+// reciprocals; within 1e-12 of the boundary it is decided by the
+// definition's divisions, so the decision is the same, bit for bit, as a
+// double-precision evaluation of the definition.  An offset whose cell is
+// not the octant's (dta at or above a voxel, or rounding at a face) takes the
+// general evaluation.
+__device__ bool gamma_search(const GammaArgs& A, const GammaLattice& L, int ix, int iy, int iz,
+                             double dr) {
 #pragma clang fp contract(off)
-    const size_t nvox = (size_t)nx * ny * nz;
-    unsigned long long ne = 0, np = 0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double dr = ref[i];
-        if (!(dr >= thr_abs) || dr <= 0.0) continue;
-        ne++;
-        const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((size_t)nx * ny));
-        const double norm = dd * (local ? dr : max_ref);
-        const double norm2 = norm * norm;
-        bool pass = false;
-        double de;
-        if (trilinear(ev, nx, ny, nz, ix + off[0].x, iy + off[0].y, iz + off[0].z, de))
-            pass = off[0].w + (de - dr) * (de - dr) / norm2 <= 1.0;
-        double wmax = 2.0;   // offsets with |o|^2 / dta^2 above this cannot pass
-        if (!pass && use_bound) {
-            double lo, hi;
-            box_range(ev, nx, ny, nz, ix, iy, iz, rx, ry, rz, lo, hi);
+    const int nx = A.nx, ny = A.ny, nz = A.nz, K = A.K, KK = K * K;
+    const double* ev = A.ev;
+    const double dta = A.dta, inv_dta2 = 1.0 / (dta * dta);
+    const double norm = A.dd * (A.local ? dr : A.max_ref);
+    const double norm2 = norm * norm, inv_n2 = 1.0 / norm2;
+    for (int oct = 0; oct < 8; ++oct) {
+        // sign pattern: s = 0 takes a >= 0 (cell [i, i+1]), s = 1 takes a < 0 (cell [i-1, i])
+        const int sx = oct & 1, sy = (oct >> 1) & 1, sz = oct >> 2;
+        if ((sx && ix == 0) || (sy && iy == 0) || (sz && iz == 0)) continue;   // outside
+        int x0 = ix - sx, y0 = iy - sy, z0 = iz - sz;
+        if (x0 > nx - 2) x0 = nx > 1 ? nx - 2 : 0;
+        if (y0 > ny - 2) y0 = ny > 1 ? ny - 2 : 0;
+        if (z0 > nz - 2) z0 = nz > 1 ? nz - 2 : 0;
+        const int x1 = nx > 1 ? x0 + 1 : x0, y1 = ny > 1 ? y0 + 1 : y0, z1 = nz > 1 ? z0 + 1 : z0;
+        const double* p00 = ev + ((size_t)z0 * ny + y0) * nx;
+        const double* p10 = ev + ((size_t)z0 * ny + y1) * nx;
+        const double* p01 = ev + ((size_t)z1 * ny + y0) * nx;
+        const double* p11 = ev + ((size_t)z1 * ny + y1) * nx;
+        const double v000 = p00[x0], v100 = p00[x1], v010 = p10[x0], v110 = p10[x1];
+        const double v001 = p01[x0], v101 = p01[x1], v011 = p11[x0], v111 = p11[x1];
+        int nmax = KK;
+        if (A.use_bound) {
+            // the octant's box in cell coordinates, its corners, the range
+            const double rx = L.vx[0][2 * K], ry = L.vx[1][2 * K], rz = L.vx[2][2 * K];
+            const double ax0 = sx ? 1.0 - rx : (double)(ix - x0),
+                         ax1 = sx ? 1.0 : fmin((double)(ix - x0) + rx, 1.0);
+            const double ay0 = sy ? 1.0 - ry : (double)(iy - y0),
+                         ay1 = sy ? 1.0 : fmin((double)(iy - y0) + ry, 1.0);
+            const double az0 = sz ? 1.0 - rz : (double)(iz - z0),
+                         az1 = sz ? 1.0 : fmin((double)(iz - z0) + rz, 1.0);
+            double lo = 1e300, hi = -1e300;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const double tx = (c & 1) ? ax1 : ax0, ty = (c & 2) ? ay1 : ay0,
+                             tz = (c & 4) ? az1 : az0;
+                const double e00 = v000 + tx * (v100 - v000), e10 = v010 + tx * (v110 - v010);
+                const double e01 = v001 + tx * (v101 - v001), e11 = v011 + tx * (v111 - v011);
+                const double e0 = e00 + ty * (e10 - e00), e1 = e01 + ty * (e11 - e01);
+                const double e = e0 + tz * (e1 - e0);
+                lo = fmin(lo, e);
+                hi = fmax(hi, e);
+            }
             const double d = dr < lo ? lo - dr : (dr > hi ? dr - hi : 0.0);
             const double ds = d - 1e-12 * fmax(fabs(dr), fmax(fabs(lo), fabs(hi)));
-            if (ds > 0.0) wmax = 1.0 + 1e-12 - (ds * ds / norm2) * (1.0 - 1e-12);
+            if (ds > 0.0) {
+                const double wmax = 1.0 - ds * ds * inv_n2;   // |o|^2 / dta^2 at most
+                if (wmax < 0.0) continue;                    // the octant cannot pass
+                nmax = min(KK, (int)(wmax * KK * (1.0 + 1e-9)) + 1);
+            }
         }
-        for (int k = 1; k < n_off && !pass; ++k) {
-            const double4 o = off[k];
-            if (o.w > wmax) break;
-            if (!trilinear(ev, nx, ny, nz, ix + o.x, iy + o.y, iz + o.z, de)) continue;
-            if (o.w + (de - dr) * (de - dr) / norm2 <= 1.0) pass = true;
+        // a in [0, K] (s = 0) or [-K, -1] (s = 1), walked outward
+        for (int ua = 0; ua + sx <= K; ++ua) {
+            const int a = sx ? -(ua + 1) : ua;
+            if (a * a > nmax) break;
+            const double fx = ix + L.vx[0][a + K];
+            if (fx < 0.0 || fx > nx - 1) continue;
+            int xf = (int)floor(fx);
+            if (xf > nx - 2) xf = nx > 1 ? nx - 2 : 0;
+            const bool xin = xf == x0;
+            const double tx = fx - x0;
+            const double c00 = v000 * (1 - tx) + v100 * tx, c10 = v010 * (1 - tx) + v110 * tx;
+            const double c01 = v001 * (1 - tx) + v101 * tx, c11 = v011 * (1 - tx) + v111 * tx;
+            const double oxx = L.cm[0][a + K] * L.cm[0][a + K];
+            for (int ub = 0; ub + sy <= K; ++ub) {
+                const int b = sy ? -(ub + 1) : ub;
+                if (a * a + b * b > nmax) break;
+                const double fy = iy + L.vx[1][b + K];
+                if (fy < 0.0 || fy > ny - 1) continue;
+                int yf = (int)floor(fy);
+                if (yf > ny - 2) yf = ny > 1 ? ny - 2 : 0;
+                const bool yin = yf == y0;
+                const double ty = fy - y0;
+                const double c0 = c00 * (1 - ty) + c10 * ty, c1 = c01 * (1 - ty) + c11 * ty;
+                const double sab = oxx + L.cm[1][b + K] * L.cm[1][b + K];
+                for (int uc = 0; uc + sz <= K; ++uc) {
+                    const int c = sz ? -(uc + 1) : uc;
+                    if (a * a + b * b + c * c > nmax) break;
+                    if (a == 0 && b == 0 && c == 0) continue;   // the zero offset: tested apart
+                    const double fz = iz + L.vx[2][c + K];
+                    if (fz < 0.0 || fz > nz - 1) continue;
+                    int zf = (int)floor(fz);
+                    if (zf > nz - 2) zf = nz > 1 ? nz - 2 : 0;
+                    double v;
+                    if (xin && yin && zf == z0) {
+                        const double tz = fz - z0;
+                        v = c0 * (1 - tz) + c1 * tz;
+                    } else if (!trilinear(ev, nx, ny, nz, fx, fy, fz, v)) {
+                        continue;
+                    }
+                    const double r2 = sab + L.cm[2][c + K] * L.cm[2][c + K];
+                    const double diff = v - dr;
+                    const double gf = r2 * inv_dta2 + diff * diff * inv_n2;
+                    if (gf > 1.0 + 1e-12) continue;
+                    if (gf < 1.0 - 1e-12 || r2 / (dta * dta) + diff * diff / norm2 <= 1.0)
+                        return true;
+                }
+            }
         }
-        np += pass ? 1ull : 0ull;
+    }
+    return false;
+}
+
+// Pass 1 of the gamma index, one thread per reference voxel: the
+// threshold, then the zero offset (|o|^2 / dta^2 = 0 / dta^2).  A voxel
+// failing there is appended to the list of voxels to search (one atomic
+// per wave); beyond the list's capacity it is searched at once.
+// counts = {evaluated, passed, (maximum), list length}.
+__global__ void __launch_bounds__(256) k_gamma_screen(GammaArgs A, unsigned long long* counts,
+                                                      unsigned* list, unsigned cap) {
+#pragma clang fp contract(off)
+    __shared__ GammaLattice L;
+    fill_lattice(A, L);
+    const int nx = A.nx, ny = A.ny, nz = A.nz, K = A.K;
+    const size_t nvox = (size_t)nx * ny * nz;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    unsigned long long ne = 0, np = 0;
+    // the loop runs a whole number of rounds per wave so the ballot sees every lane
+    for (size_t i0 = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~63u); i0 < nvox;
+         i0 += stride) {
+        const size_t i = i0 + lane;
+        bool hard = false;
+        int ix = 0, iy = 0, iz = 0;
+        double dr = 0.0;
+        if (i < nvox) {
+            dr = A.ref[i];
+            if (dr >= A.thr_abs && dr > 0.0) {
+                ne++;
+                ix = (int)(i % nx);
+                iy = (int)((i / nx) % ny);
+                iz = (int)(i / ((size_t)nx * ny));
+                const double norm = A.dd * (A.local ? dr : A.max_ref);
+                double de;
+                bool pass = false;
+                if (trilinear(A.ev, nx, ny, nz, ix + L.vx[0][K], iy + L.vx[1][K],
+                              iz + L.vx[2][K], de))
+                    pass = (L.cm[0][K] * L.cm[0][K] + L.cm[1][K] * L.cm[1][K] +
+                            L.cm[2][K] * L.cm[2][K]) / (A.dta * A.dta) +
+                               (de - dr) * (de - dr) / (norm * norm) <= 1.0;
+                if (pass) np++;
+                else hard = true;
+            }
+        }
+        const unsigned long long m = __ballot(hard);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&counts[3], (unsigned long long)__popcll(m));
+            base = __shfl(base, leader);
+            if (hard) {
+                const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (slot < cap) list[slot] = (unsigned)i;
+                else if (gamma_search(A, L, ix, iy, iz, dr)) np++;
+            }
+        }
     }
     ne = wave_sum64(ne);
     np = wave_sum64(np);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         atomicAdd(&counts[0], ne);
         atomicAdd(&counts[1], np);
     }
+}
+
+// Pass 2: the listed voxels, one thread each, so that the waves doing the
+// long searches are full.
+__global__ void __launch_bounds__(256) k_gamma_search(GammaArgs A, unsigned long long* counts,
+                                                      const unsigned* list, unsigned cap) {
+    __shared__ GammaLattice L;
+    fill_lattice(A, L);
+    const unsigned long long nl = counts[3] < cap ? counts[3] : cap;
+    unsigned long long np = 0;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nl;
+         k += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = list[k];
+        const int ix = (int)(i % A.nx), iy = (int)((i / A.nx) % A.ny),
+                  iz = (int)(i / ((size_t)A.nx * A.ny));
+        if (gamma_search(A, L, ix, iy, iz, A.ref[i])) np++;
+    }
+    np = wave_sum64(np);
+    if ((threadIdx.x & 63) == 0 && np) atomicAdd(&counts[1], np);
 }
 
 // Maximum of a non-negative double array via its bit pattern.
@@ -177,14 +313,22 @@ int blocks_for(size_t n, int block, int cap) {
 
 }  // namespace
 
-hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
-                        const double4* offsets, int n_off, double dd, double thr_abs,
-                        double max_ref, int local, double rx, double ry, double rz, int use_bound,
-                        unsigned long long* counts, hipStream_t s) {
+hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz, int interp,
+                        double dta, double dx, double dy, double dz, double dd, double thr_abs,
+                        double max_ref, int local, int use_bound, unsigned long long* counts,
+                        unsigned* list, unsigned cap, hipStream_t s) {
+    if (interp < 1 || interp > kMaxK) return hipErrorInvalidValue;
     const size_t nvox = (size_t)nx * ny * nz;
-    hipLaunchKernelGGL(k_gamma, dim3(blocks_for(nvox, 256, 65536)), dim3(256), 0, s, ref, ev, nx,
-                       ny, nz, offsets, n_off, dd, thr_abs, max_ref, local, rx, ry, rz, use_bound,
-                       counts);
+    GammaArgs A{ref, ev, nx, ny, nz, interp, dta / interp, dta, dx, dy, dz, dd, thr_abs, max_ref,
+                local, use_bound};
+    hipLaunchKernelGGL(k_gamma_screen, dim3(blocks_for(nvox, 256, 65536)), dim3(256), 0, s, A,
+                       counts, list, cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the list's length is on the device: a grid that covers a large list,
+    // grid-stride beyond
+    hipLaunchKernelGGL(k_gamma_search, dim3(blocks_for(cap, 256, 8192)), dim3(256), 0, s, A,
+                       counts, list, cap);
     return hipGetLastError();
 }
 

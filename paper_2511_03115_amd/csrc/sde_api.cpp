@@ -19,14 +19,6 @@ namespace {
 
 thread_local std::string g_err;
 
-struct GammaKey {
-    int interp = 0;
-    double dta = 0, dx = 0, dy = 0, dz = 0;
-    bool operator==(const GammaKey& o) const {
-        return interp == o.interp && dta == o.dta && dx == o.dx && dy == o.dy && dz == o.dz;
-    }
-};
-
 struct State {
     bool ready = false;
     HostTables host;
@@ -37,11 +29,10 @@ struct State {
     MatDev64* mats64 = nullptr;
     double2* hot64 = nullptr;
     double *nuc_sigma64 = nullptr, *nuc_u64 = nullptr, *nuc_r64 = nullptr, *nuc_a64 = nullptr;
-    // gamma: offsets of the last lattice and the counters
-    double4* gam_off = nullptr;
-    int gam_cap = 0, gam_n = 0;
-    GammaKey gam_key{};
+    // gamma: the counters and the list of voxels to search
     unsigned long long* gam_buf = nullptr;
+    unsigned* gam_list = nullptr;
+    unsigned gam_cap = 0;
     hipStream_t stream = nullptr;
     hipStream_t own = nullptr;   // for graph capture when the caller uses the null stream
     int n_cu = 0;
@@ -375,6 +366,10 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     S.mott_D0 = T.mott_D0;
     S.mott_Lhi = T.mott_Lhi;
     S.mott_Llo = T.mott_Llo;
+    S.mott_Dlo = T.mott_Dlo;
+    S.mott_shi = T.mott_shi;
+    S.mott_slo = T.mott_slo;
+    S.z_over_step = pp.ld_z_cm / pp.step_cm;
     S.eta_pre = kAlpha * std::sqrt(0.5 * kMp);
     S.ln_e_lo = T.ln_e_lo;
     S.inv_dln = 1.0 / T.dln;
@@ -401,6 +396,10 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     F.mott_D0 = (float)S.mott_D0;
     F.mott_Lhi = (float)S.mott_Lhi;
     F.mott_Llo = (float)S.mott_Llo;
+    F.mott_Dlo = (float)S.mott_Dlo;
+    F.mott_shi = (float)S.mott_shi;
+    F.mott_slo = (float)S.mott_slo;
+    F.z_over_step = (float)S.z_over_step;
     F.eta_pre = (float)S.eta_pre;
     F.ln_e_lo = (float)S.ln_e_lo;
     F.inv_dln = (float)S.inv_dln;
@@ -412,7 +411,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
         F.d[a] = (float)S.d[a];
         F.inv_d[a] = (float)S.inv_d[a];
     }
-    kp.flags = pp.flags & SDE_ALL;
+    kp.flags = pp.flags & (SDE_ALL | SDE_ECUT);
     kp.fp64 = (pp.flags & SDE_FP64) ? 1 : 0;
     kp.max_steps = pp.max_steps;
     kp.vox = p->vox;
@@ -462,8 +461,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     return SDE_OK;
 }
 
-// Gamma index: argument checks, the offset lattice, and the launch sequence
-// shared by sde_gamma and sde_gamma_noalloc.
+// Gamma index: argument checks and the launch sequence.
 int gamma_check(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
                 double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int interp,
                 const int64_t* counts_out) {
@@ -474,66 +472,30 @@ int gamma_check(const double* ref, const double* ev, int nx, int ny, int nz, dou
     return SDE_OK;
 }
 
-// Lattice offsets (a, b, c) of spacing dta/interp within dta (the squared
-// length tested in double precision, as the definition evaluates it), with
-// w = a^2 + b^2 + c^2, sorted by (w, a, b, c): nearest first, a fixed order.
-// Writes at most cap entries and returns the count (> cap: out is partial).
-int gamma_lattice(int interp, double dta_cm, int4* out, int cap) {
-    const double st = dta_cm / interp;
-    int n = 0;
-    for (int a = -interp; a <= interp; ++a)
-        for (int b = -interp; b <= interp; ++b)
-            for (int c = -interp; c <= interp; ++c) {
-                const double ox = a * st, oy = b * st, oz = c * st;
-                if (ox * ox + oy * oy + oz * oz <= dta_cm * dta_cm * (1.0 + 1e-12)) {
-                    if (n < cap) out[n] = make_int4(a, b, c, a * a + b * b + c * c);
-                    ++n;
-                }
-            }
-    if (n <= cap)
-        std::sort(out, out + n, [](const int4& u, const int4& v) {
-            if (u.w != v.w) return u.w < v.w;
-            if (u.x != v.x) return u.x < v.x;
-            if (u.y != v.y) return u.y < v.y;
-            return u.z < v.z;
-        });
-    return n;
-}
-
-// (ox / dx, oy / dy, oz / dz, |o|^2 / dta^2) per lattice offset, each in the
-// operations of the definition (so a kernel adding them to a voxel index
-// evaluates the same points).
-void gamma_offsets(const int4* lat, int n, int interp, double dta_cm, double dx_cm, double dy_cm,
-                   double dz_cm, double4* out) {
-    const double st = dta_cm / interp;
-    for (int k = 0; k < n; ++k) {
-        const double ox = lat[k].x * st, oy = lat[k].y * st, oz = lat[k].z * st;
-        out[k] = make_double4(ox / dx_cm, oy / dy_cm, oz / dz_cm,
-                              (ox * ox + oy * oy + oz * oz) / (dta_cm * dta_cm));
-    }
-}
-
-// Counters and maximum into buf[0..2], then the gamma kernel; reads the
-// counts back (synchronises the stream).
+// Counters and maximum into buf[0..3], then the two gamma passes with a
+// search list of cap voxel indices; reads the counts back (synchronises the
+// stream).
 int gamma_run(const double* ref, const double* ev, int nx, int ny, int nz, double dx_cm,
-              double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int local,
-              const double4* doff, int n_off, unsigned long long* buf, int64_t* counts_out) {
+              double dy_cm, double dz_cm, double dd, double dta_cm, double thresh, int interp,
+              int local, unsigned long long* buf, unsigned* list, unsigned cap,
+              int64_t* counts_out) {
     const size_t nvox = (size_t)nx * ny * nz;
     hipStream_t s = cur_stream();
     unsigned long long host[3] = {0, 0, 0};
     hipError_t e;
-    if ((e = launch_zero_u64(buf, 3, s)) != hipSuccess ||
+    if ((e = launch_zero_u64(buf, 4, s)) != hipSuccess ||
         (e = launch_max(ref, nvox, buf + 2, s)) != hipSuccess ||
         (e = hipMemcpyAsync(host, buf, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(SDE_E_HIP, hipGetErrorString(e));
     double mx;
     std::memcpy(&mx, &host[2], sizeof mx);
-    // the bound needs the search box inside the 8 cells around a voxel
-    const double rx = dta_cm / dx_cm, ry = dta_cm / dy_cm, rz = dta_cm / dz_cm;
-    const int use_bound = (rx <= 1.0 && ry <= 1.0 && rz <= 1.0) ? 1 : 0;
-    if ((e = launch_gamma(ref, ev, nx, ny, nz, doff, n_off, dd, thresh * mx, mx, local, rx, ry,
-                          rz, use_bound, buf, s)) != hipSuccess ||
+    // the per-octant cells and bounds need the search box inside the 8
+    // cells around a voxel
+    const int use_bound =
+        (dta_cm / dx_cm < 1.0 && dta_cm / dy_cm < 1.0 && dta_cm / dz_cm < 1.0) ? 1 : 0;
+    if ((e = launch_gamma(ref, ev, nx, ny, nz, interp, dta_cm, dx_cm, dy_cm, dz_cm, dd,
+                          thresh * mx, mx, local, use_bound, buf, list, cap, s)) != hipSuccess ||
         (e = hipMemcpyAsync(host, buf, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
                             s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -731,29 +693,19 @@ int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, doubl
     if (int rc = gamma_check(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, interp,
                              counts_out))
         return rc;
-    // offsets (cached in the library for the last lattice) and counters
-    const GammaKey key{interp, dta_cm, dx_cm, dy_cm, dz_cm};
-    if (!g.gam_off || !(g.gam_key == key)) {
-        std::vector<int4> lat((size_t)(2 * interp + 1) * (2 * interp + 1) * (2 * interp + 1));
-        const int n = gamma_lattice(interp, dta_cm, lat.data(), (int)lat.size());
-        std::vector<double4> off(n);
-        gamma_offsets(lat.data(), n, interp, dta_cm, dx_cm, dy_cm, dz_cm, off.data());
-        if (n > g.gam_cap) {
-            dfree(g.gam_off);
-            g.gam_cap = 0;
-            HIP_TRY(hipMalloc((void**)&g.gam_off, sizeof(double4) * n));
-            g.gam_cap = n;
-        }
-        if (!g.gam_buf) HIP_TRY(hipMalloc((void**)&g.gam_buf, sizeof(unsigned long long) * 4));
-        g.gam_n = 0;
-        HIP_TRY(hipMemcpyAsync(g.gam_off, off.data(), sizeof(double4) * n, hipMemcpyHostToDevice,
-                               cur_stream()));
-        HIP_TRY(hipStreamSynchronize(cur_stream()));
-        g.gam_key = key;
-        g.gam_n = n;
+    // the counters and the search list, held by the library across calls
+    // (the list grows to the largest grid seen, at most 2^24 entries;
+    // beyond it voxels are searched in the first pass)
+    if (!g.gam_buf) HIP_TRY(hipMalloc((void**)&g.gam_buf, sizeof(unsigned long long) * 4));
+    const unsigned want = (unsigned)std::min<size_t>((size_t)nx * ny * nz, (size_t)1 << 24);
+    if (want > g.gam_cap) {
+        dfree(g.gam_list);
+        g.gam_cap = 0;
+        HIP_TRY(hipMalloc((void**)&g.gam_list, sizeof(unsigned) * want));
+        g.gam_cap = want;
     }
-    return gamma_run(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, local, g.gam_off,
-                     g.gam_n, g.gam_buf, counts_out);
+    return gamma_run(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, interp, local,
+                     g.gam_buf, g.gam_list, g.gam_cap, counts_out);
 }
 
 int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes) {
@@ -771,10 +723,9 @@ int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes) {
 
 void sde_free(void) {
     release_tables();
-    dfree(g.gam_off);
     dfree(g.gam_buf);
-    g.gam_cap = g.gam_n = 0;
-    g.gam_key = GammaKey{};
+    dfree(g.gam_list);
+    g.gam_cap = 0;
     if (g.own) {
         (void)hipStreamDestroy(g.own);
         g.own = nullptr;

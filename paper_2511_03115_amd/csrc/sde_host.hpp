@@ -21,6 +21,7 @@ struct HostTables {
     std::vector<double2> hot64;
     std::vector<double> nuc_sigma64, nuc_u64, nuc_r64, nuc_a64;
     double ruth_T = 0, mott_lo = 0, mott_hi = 0, mott_D0 = 0, mott_Lhi = 0, mott_Llo = 0;
+    double mott_Dlo = 0, mott_shi = 0, mott_slo = 0;
     double c_strag = 0;
     sde_physics_params params{};
 };

@@ -29,7 +29,8 @@ struct ElemDev {
     float ne_coef;   // inelastic rate = rho * ne_coef * sigma_barn(E)
     int is_h;        // hydrogen: Mott (identical-particle) cross section
     int tab;         // row of the inelastic tables, -1 if none
-    int pad0, pad1;
+    float el_base;   // el_coef without the cut's factor (T - 1/2 for Rutherford; = el_coef for H)
+    int pad1;
 };
 
 struct MatDev {
@@ -39,7 +40,8 @@ struct MatDev {
     int pad;
     float c_ruth;          // sum of non-hydrogen el_coef: Rutherford rate = rho c_ruth / E^2
     float c_mott;          // hydrogen el_coef: Mott rate = rho c_mott / E^2 * bracket(E)
-    float pad1, pad2;
+    float c_ruth0;         // c_ruth without the cut's factor T - 1/2
+    float pad2;
     ElemDev el[kMaxElem];
 };
 
@@ -49,12 +51,12 @@ struct MatDev {
 // and the jump constants.
 struct MatDev64 {
     double zoa, log_pre;   // as in MatDev
-    double c_ruth, c_mott; // as in MatDev
+    double c_ruth, c_mott, c_ruth0;   // as in MatDev
     int n_elem, pad[3];
     double wz[kMaxElem];      // w_i Z_i (Z_i + 1) / A_i
     double ln_ca[kMaxElem];   // ln(2.007e-5 Z_i^(2/3))
     double za2[kMaxElem];     // 3.34 (Z_i alpha)^2
-    double el_coef[kMaxElem], ne_coef[kMaxElem], m2[kMaxElem];
+    double el_coef[kMaxElem], el_base[kMaxElem], ne_coef[kMaxElem], m2[kMaxElem];
     int is_h[kMaxElem], tab[kMaxElem];
 };
 
@@ -75,7 +77,10 @@ struct KScal {
     R c_bethe, c_strag;              // 0.3072, 4 pi N_A (alpha hbar c)^2
     R ruth_T;                        // 1 / (1 - cos theta_cut)
     R mott_lo, mott_hi;              // CM cosine limits of hydrogen elastic
-    R mott_D0, mott_Lhi, mott_Llo;
+    R mott_D0, mott_Lhi, mott_Llo;   // bracket terms at the fixed cut
+    R mott_Dlo;                      // 2 lo / (1 - lo^2), the bracket's lower rational term
+    R mott_shi, mott_slo;            // 1 - hi (fixed cut) and 1 - lo
+    R z_over_step;                   // ld_z / step
     R eta_pre;                       // alpha sqrt(m_p / 2): eta = eta_pre / sqrt(E)
     R ln_e_lo, inv_dln;              // lattice: t = (ln E - ln_e_lo) inv_dln
     R ld_z, ld_F;                    // Lynch-Dahl path length and central fraction
@@ -141,12 +146,14 @@ hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_by
 hipError_t launch_convert(unsigned long long* tally, int n_rep, const uint2* vox, size_t nvox,
                           double inv_scale, double voxel_cm3, double* dose,
                           unsigned long long* ledger, hipStream_t s);
-// gamma_kernels.hip: offsets[k] = (ox / dx, oy / dy, oz / dz, |o|^2 / dta^2),
-// nearest first; r = dta / d per axis (the bound needs r <= 1: use_bound)
-hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz,
-                        const double4* offsets, int n_off, double dd, double thr_abs,
-                        double max_ref, int local, double rx, double ry, double rz, int use_bound,
-                        unsigned long long* counts, hipStream_t s);
+// gamma_kernels.hip: offsets on the lattice of spacing dta / interp
+// (interp <= 50) within dta; use_bound needs dta below a voxel on every axis.
+// counts[4] = {evaluated, passed, maximum bits, list length} (counts[0], [1]
+// and [3] zero on entry); list: cap voxel indices of scratch.
+hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int nz, int interp,
+                        double dta, double dx, double dy, double dz, double dd, double thr_abs,
+                        double max_ref, int local, int use_bound, unsigned long long* counts,
+                        unsigned* list, unsigned cap, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_max(const double* a, size_t n, unsigned long long* out_bits, hipStream_t s);
 hipError_t launch_sbm_polar(const float* t, const float* u, const float* z, int n, float* c,

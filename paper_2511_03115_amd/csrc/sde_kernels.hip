@@ -29,7 +29,7 @@ namespace sde {
 namespace {
 
 constexpr unsigned kLoss = 1u, kStraggle = 2u, kMcs = 4u, kElastic = 8u, kInelastic = 16u,
-                   kEor = 32u, kSbm = 64u;
+                   kEor = 32u, kSbm = 64u, kEcut = 256u;
 // the method (every switch) and the method with the geodesic Gaussian step:
 // each its own compiled instance, the rest share k_transport<float, 0> (switches
 // read at run time)
@@ -377,50 +377,55 @@ __device__ __forceinline__ void score(const KParams& P, const KScal<R>& S,
 }
 
 // Hydrogen (Mott) antiderivative in units of (eta/k)^2, Appendix A.2 with
-// sin(eta ln((1+mu)/(1-mu))), and its derivative (the Mott cross section of
-// section 2.1.4 in the same units).
+// sin(eta ln((1+mu)/(1-mu))), written in s = 1 - mu (which keeps the forward
+// angles, s << 1, at full relative precision):
+//   G(s) = 2 (1 - s) / (s (2 - s)) - sin(eta ln((2 - s) / s)) / (2 eta),
+// and dG/ds, minus the Mott cross section of section 2.1.4 in the same units.
 template <class R>
-__device__ __forceinline__ void mott_G_dG(R eta, R inv_2eta, R mu, R& G, R& dG) {
+__device__ __forceinline__ void mott_G_dG(R eta, R inv_2eta, R s, R& G, R& dG) {
     using M = RM<R>;
-    const R omm = (R(1) - mu) * (R(1) + mu);
-    const R iomm = M::rcp(omm);
-    const R L = M::lgx((R(1) + mu) * M::rcp(R(1) - mu));
+    const R q = s * (R(2) - s);   // 1 - mu^2
+    const R iq = M::rcp(q);
+    const R L = M::lgx((R(2) - s) * M::rcp(s));
     const R r = eta * L * R(0.15915494309189535);   // revolutions, |r| < 1 for E >= e_min
     const R sn = M::sinr(r), cs = M::cosr(r);
-    G = R(2) * mu * iomm - sn * inv_2eta;
-    dG = R(2) * iomm * ((R(1) + mu * mu) * iomm - R(0.5) * cs);
+    const R om = R(1) - s;
+    G = R(2) * om * iq - sn * inv_2eta;
+    dG = -R(2) * iq * ((R(1) + om * om) * iq - R(0.5) * cs);
 }
 
-// Invert the hydrogen elastic CDF, (G(mu) - G(lo)) / (G(hi) - G(lo)) = U, by
-// Newton's method kept inside a shrinking bracket.  First guess: the
-// interference term dropped, 2 mu / (1 - mu^2) = target.
+// Invert the hydrogen elastic CDF in s: G(s) = G(s_lo) + U (G(s_hi) - G(s_lo))
+// over [s_hi, s_lo] = [1 - cos(cut), 1 + cos(backscatter cut)], by Newton's
+// method kept inside a shrinking bracket (G decreases in s).  First guess:
+// the interference term dropped, 2 (1 - s) / (s (2 - s)) = target.
+// Returns s = 1 - mu.
 template <class R>
-__device__ __forceinline__ R mott_invert(const KScal<R>& S, R eta, R U) {
+__device__ __forceinline__ R mott_invert(R s_hi, R s_lo, R eta, R U) {
     using M = RM<R>;
-    // float: a few ulps of mu (FP32 Newton can cycle between neighbouring
-    // floats); double: 1e-15 of mu
+    // float: a few ulps of s (FP32 Newton can cycle between neighbouring
+    // floats); double: 1e-15 of s
     constexpr R tol = M::f64 ? R(1e-15) : R(2.5e-7);
     constexpr int max_it = M::f64 ? 60 : 24;
     const R inv_2eta = R(0.5) * M::rcp(eta);
-    R a = S.mott_lo, b = S.mott_hi, G0, G1, d;
-    mott_G_dG(eta, inv_2eta, a, G0, d);
-    mott_G_dG(eta, inv_2eta, b, G1, d);
+    R a = s_hi, b = s_lo, G0, G1, d;
+    mott_G_dG(eta, inv_2eta, b, G0, d);
+    mott_G_dG(eta, inv_2eta, a, G1, d);
     const R tgt = M::fma(U, G1 - G0, G0);
-    R mu = tgt * M::rcp(R(1) + M::sqx(R(1) + tgt * tgt));
-    mu = fmin(fmax(mu, a), b);
+    R s = R(2) * M::rcp((tgt + R(1)) + M::sqx(tgt * tgt + R(1)));
+    s = fmin(fmax(s, a), b);
     for (int it = 0; it < max_it; ++it) {
         R G, dG;
-        mott_G_dG(eta, inv_2eta, mu, G, dG);
+        mott_G_dG(eta, inv_2eta, s, G, dG);
         const R g = G - tgt;
-        if (g < R(0)) a = mu; else b = mu;
-        R nx = mu - g * M::rcp(dG);
+        if (g > R(0)) a = s; else b = s;
+        R nx = s - g * M::rcp(dG);
         if (!(nx > a && nx < b)) nx = R(0.5) * (a + b);
-        const R step = fabs(nx - mu);
-        mu = nx;
+        const R step = fabs(nx - s);
+        s = nx;
         // converged, or the bracket has closed
-        if (step <= tol * fmax(fabs(mu), R(1e-3)) || !(b > a)) break;
+        if (step <= tol * s || !(b > a)) break;
     }
-    return mu;
+    return s;
 }
 
 template <class R>
@@ -447,6 +452,8 @@ __device__ __forceinline__ int n_elem(const MatDev& m) { return m.n_elem; }
 __device__ __forceinline__ int n_elem(const MatDev64& m) { return m.n_elem; }
 __device__ __forceinline__ float el_coef(const MatDev& m, int e) { return m.el[e].el_coef; }
 __device__ __forceinline__ double el_coef(const MatDev64& m, int e) { return m.el_coef[e]; }
+__device__ __forceinline__ float el_base(const MatDev& m, int e) { return m.el[e].el_base; }
+__device__ __forceinline__ double el_base(const MatDev64& m, int e) { return m.el_base[e]; }
 __device__ __forceinline__ float ne_coef(const MatDev& m, int e) { return m.el[e].ne_coef; }
 __device__ __forceinline__ double ne_coef(const MatDev64& m, int e) { return m.ne_coef[e]; }
 __device__ __forceinline__ float m2_of(const MatDev& m, int e) { return m.el[e].m2; }
@@ -469,21 +476,99 @@ __device__ __forceinline__ Nuc<double> nuc_of(const KParams& P, double) {
     return Nuc<double>{P.nuc_sigma64, P.nuc_u64, P.nuc_r64, P.nuc_a64};
 }
 
-// Rate of channel (element e, elastic or inelastic) per cm at E.
-template <class R, class Mat>
-__device__ __forceinline__ R channel_rate(const KParams& P, const Nuc<R>& nu, const Mat& m, int e,
-                                          bool inel, R rho, R inv_e2, R mott, int li, R lf) {
-    if (!inel) return rho * el_coef(m, e) * inv_e2 * (is_h(m, e) ? mott : R(1));
-    return rho * ne_coef(m, e) * lerp_row(nu.sigma + (size_t)tab_of(m, e) * P.n_e, li, lf);
+// Lynch-Dahl width of section 2.1.4 for the medium at density rho and
+// energy E, scaled to the step: t = sigma^2 Delta / z (double instance).
+__device__ __forceinline__ double ld_time64(const MatDev64& m, const KScal<double>& S, double rho,
+                                            double E) {
+    const double p2 = E * E + 2.0 * E * kMp;
+    const double pb = p2 / (E + kMp);
+    const double b2 = p2 / ((E + kMp) * (E + kMp));
+    const double lp2 = ::log(p2);
+    double wz = 0.0, num = 0.0;
+    for (int i = 0; i < m.n_elem; ++i) {
+        wz += m.wz[i];
+        num += m.wz[i] * (m.ln_ca[i] + ::log1p(m.za2[i] / b2) - lp2);
+    }
+    const double chic2 = 0.157 * wz * rho * S.ld_z / (pb * pb);
+    const double chia2 = ::exp(num / wz);
+    const double nu = chic2 / (2.0 * chia2 * (1.0 - S.ld_F));
+    const double s2 = chic2 / (1.0 + S.ld_F * S.ld_F) * ((1.0 + nu) / nu * ::log1p(nu) - 1.0);
+    return s2 * (S.step / S.ld_z);
+}
+
+// The large-angle elastic cut in the forms the rates and samplers use:
+// Rutherford T = 1 / (1 - cos), hydrogen's s_hi = 1 - cos, the rational and
+// logarithmic terms of the Mott antiderivative at cos (D0 already less its
+// value at the backscatter limit), and the cut itself.
+template <class R>
+struct Cut {
+    R T, s_hi, D0, Lhi;
+};
+
+template <class R>
+__device__ __forceinline__ Cut<R> fixed_cut(const KScal<R>& S) {
+    return Cut<R>{S.ruth_T, S.mott_shi, S.mott_D0, S.mott_Lhi};
+}
+
+// The cut 2.5 sigma for a Lynch-Dahl variance sig2z = sigma^2 at the width's
+// path z, limited to pi (Rutherford) and pi - backscatter cut (hydrogen,
+// where its interval closes); the half-angle forms keep small cuts exact.
+template <class R>
+__device__ __forceinline__ Cut<R> energy_cut(const KScal<R>& S, R sig2z) {
+    using M = RM<R>;
+    const R pi = R(3.14159265358979323846);
+    const R th = fmin(R(2.5) * M::sq(sig2z), pi);
+    const R th_h = fmin(th, pi - acos(-S.mott_lo));
+    R hc, hs;
+    polar_cs(R(0.25) * th * th, hc, hs);            // cos, sin of th / 2
+    Cut<R> c;
+    c.T = R(0.5) * M::rcp(hs * hs);                  // 1 / (1 - cos th)
+    polar_cs(R(0.25) * th_h * th_h, hc, hs);
+    const R hs2 = hs * hs, hc2 = hc * hc;
+    c.s_hi = R(2) * hs2;                             // 1 - cos th_h
+    c.D0 = (hc2 - hs2) * M::rcp(R(2) * hs2 * hc2) - S.mott_Dlo;   // 2 cos / sin^2 - D(lo)
+    c.Lhi = M::lgx(hc2 * M::rcp(hs2));               // ln((1 + cos) / (1 - cos))
+    return c;
 }
 
 // The bracket of the hydrogen elastic rate: G(hi) - G(lo) of the Mott
 // antiderivative in units of (eta/k)^2.
 template <class R>
-__device__ __forceinline__ R mott_bracket(const KScal<R>& S, R eta) {
+__device__ __forceinline__ R mott_bracket(const KScal<R>& S, const Cut<R>& c, R eta) {
     const R k = R(0.15915494309189535);   // revolutions per radian
-    return S.mott_D0 -
-           (RM<R>::sinr(eta * S.mott_Lhi * k) - RM<R>::sinr(eta * S.mott_Llo * k)) / (R(2) * eta);
+    return c.D0 -
+           (RM<R>::sinr(eta * c.Lhi * k) - RM<R>::sinr(eta * S.mott_Llo * k)) / (R(2) * eta);
+}
+
+// Lynch-Dahl variance sigma^2 at the width's path z for medium mat at
+// density rho and energy E (lattice position li, lf): float from the FP32
+// lattice rows, double from the formula.
+template <class R>
+__device__ __forceinline__ R ld_sig2z(const KParams& P, const KScal<R>& S, const float4* tab,
+                                      int mat, R rho, R E, int li, R lf) {
+    if constexpr (RM<R>::f64) {
+        return ld_time64(P.mats64[mat], S, rho, E) * S.z_over_step;
+    } else {
+        const float4 ta = tab[mat * P.n_e + li], tb = tab[mat * P.n_e + li + 1];
+        const float A1 = fmaf(lf, tb.x - ta.x, ta.x);
+        const float A2 = fmaf(lf, tb.y - ta.y, ta.y);
+        const float nu = rho * A2;
+        const float br = (1.0f + RM<float>::rcp(nu)) * RM<float>::lg(1.0f + nu) - 1.0f;
+        return rho * A1 * br * S.z_over_step;
+    }
+}
+
+// Rate of channel (element e, elastic or inelastic) per cm at E; ecut: the
+// elastic coefficient at the cut c instead of the fixed one.
+template <class R, class Mat>
+__device__ __forceinline__ R channel_rate(const KParams& P, const Nuc<R>& nu, const Mat& m, int e,
+                                          bool inel, R rho, R inv_e2, R mott, int li, R lf,
+                                          bool ecut, const Cut<R>& c) {
+    if (!inel) {
+        if (is_h(m, e)) return rho * el_coef(m, e) * inv_e2 * mott;
+        return rho * (ecut ? el_base(m, e) * (c.T - R(0.5)) : el_coef(m, e)) * inv_e2;
+    }
+    return rho * ne_coef(m, e) * lerp_row(nu.sigma + (size_t)tab_of(m, e) * P.n_e, li, lf);
 }
 
 // One large-angle jump at energy E (the state energy E_n) in medium md,
@@ -492,8 +577,9 @@ __device__ __forceinline__ R mott_bracket(const KScal<R>& S, R eta) {
 // Eq. (cm_to_lab).  Outputs the loss fraction u (0 for elastic), the lab
 // polar (cos, sin) and the azimuth (cos, sin).
 template <class R, class Mat>
-__device__ void jump(const KParams& P, const KScal<R>& S, const Mat& md, R E, R rho, uint4 q,
-                     R& u_loss, R& jc, R& js, R& jcp, R& jsp, unsigned flags) {
+__device__ void jump(const KParams& P, const KScal<R>& S, const float4* tab, const Mat& md,
+                     int mat, R E, R rho, uint4 q, R& u_loss, R& jc, R& js, R& jcp, R& jsp,
+                     unsigned flags) {
     using M = RM<R>;
     const Nuc<R> nu = nuc_of(P, R(0));
     const R tl = (M::lg(E) - S.ln_e_lo) * S.inv_dln;
@@ -502,25 +588,28 @@ __device__ void jump(const KParams& P, const KScal<R>& S, const Mat& md, R E, R 
     const R inv_e2 = R(1) / (E * E);
     const R eta = S.eta_pre * M::rsq(E);
     const bool el = (flags & kElastic) != 0, ne = (flags & kInelastic) != 0;
+    const bool ecut = (flags & kEcut) != 0;
+    const Cut<R> cut = (el && ecut) ? energy_cut(S, ld_sig2z(P, S, tab, mat, rho, E, li, lf))
+                                    : fixed_cut(S);
     const int nel = n_elem(md);
     R mott = R(0);
-    if (el && c_mott(md) != R(0)) mott = mott_bracket(S, eta);
+    if (el && c_mott(md) != R(0)) mott = mott_bracket(S, cut, eta);
     R tot = R(0);
     for (int e = 0; e < nel; ++e) {
-        if (el) tot += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf);
+        if (el) tot += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf, ecut, cut);
         if (ne && tab_of(md, e) >= 0)
-            tot += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf);
+            tot += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf, ecut, cut);
     }
     const R target = u_hi<R>(q.x) * tot;
     R acc = R(0);
     int ce = -1, cin = 0;
     for (int e = 0; e < nel && ce < 0; ++e) {
         if (el) {
-            acc += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf);
+            acc += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf, ecut, cut);
             if (target < acc) { ce = e; cin = 0; break; }
         }
         if (ne && tab_of(md, e) >= 0) {
-            acc += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf);
+            acc += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf, ecut, cut);
             if (target < acc) { ce = e; cin = 1; break; }
         }
     }
@@ -533,10 +622,11 @@ __device__ void jump(const KParams& P, const KScal<R>& S, const Mat& md, R E, R 
     if (!cin) {
         const R U = u_hi<R>(q.y);
         if (is_h(md, ce)) {
-            cmc = mott_invert(S, eta, U);
-            cms = M::sqx(fmax(R(0), (R(1) - cmc) * (R(1) + cmc)));
+            const R sm = mott_invert(cut.s_hi, S.mott_slo, eta, U);   // 1 - mu
+            cmc = R(1) - sm;
+            cms = M::sqx(fmax(R(0), sm * (R(2) - sm)));
         } else {
-            const R om = R(1) / M::fma(U, S.ruth_T - R(0.5), R(0.5));   // 1 - mu
+            const R om = R(1) / M::fma(U, cut.T - R(0.5), R(0.5));   // 1 - mu
             cmc = R(1) - om;
             cms = M::sqx(om * (R(2) - om));
         }
@@ -590,26 +680,6 @@ __device__ __forceinline__ double range_g64(const KParams& P, int mat, double E)
     const double s2 = s * s, s3 = s2 * s;
     return (2.0 * s3 - 3.0 * s2 + 1.0) * a.x + (s3 - 2.0 * s2 + s) * a.y +
            (-2.0 * s3 + 3.0 * s2) * b.x + (s3 - s2) * b.y;
-}
-
-// Lynch-Dahl width of section 2.1.4 for the medium at density rho and
-// energy E, scaled to the step: t = sigma^2 Delta / z (double instance).
-__device__ __forceinline__ double ld_time64(const MatDev64& m, const KScal<double>& S, double rho,
-                                            double E) {
-    const double p2 = E * E + 2.0 * E * kMp;
-    const double pb = p2 / (E + kMp);
-    const double b2 = p2 / ((E + kMp) * (E + kMp));
-    const double lp2 = ::log(p2);
-    double wz = 0.0, num = 0.0;
-    for (int i = 0; i < m.n_elem; ++i) {
-        wz += m.wz[i];
-        num += m.wz[i] * (m.ln_ca[i] + ::log1p(m.za2[i] / b2) - lp2);
-    }
-    const double chic2 = 0.157 * wz * rho * S.ld_z / (pb * pb);
-    const double chia2 = ::exp(num / wz);
-    const double nu = chic2 / (2.0 * chia2 * (1.0 - S.ld_F));
-    const double s2 = chic2 / (1.0 + S.ld_F * S.ld_F) * ((1.0 + nu) / nu * ::log1p(nu) - 1.0);
-    return s2 * (S.step / S.ld_z);
 }
 
 // Per-history record {E0, steps, jumps, end, x, y, z, E, first jump step,
@@ -806,9 +876,11 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), nj, 1u, k0, k1);
                 R u_loss, jc, js, jcp, jsp;
                 if constexpr (M::f64)
-                    jump(P, S, P.mats64[matj], ej, rhoj, q, u_loss, jc, js, jcp, jsp, flags);
+                    jump(P, S, tab, P.mats64[matj], matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp,
+                         flags);
                 else
-                    jump(P, S, P.mats[matj], ej, rhoj, q, u_loss, jc, js, jcp, jsp, flags);
+                    jump(P, S, tab, P.mats[matj], matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp,
+                         flags);
                 // E holds E' (after continuous loss); the jump removes u E'
                 const R En = E * (R(1) - u_loss);
                 l_nuc += fixp(E, wsc) - fixp(En, wsc);
@@ -911,14 +983,35 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         bool jumped = false;
         if (flags & (kElastic | kInelastic)) {
             R rate;
-            if constexpr (M::f64) {
+            if ((flags & kEcut) && (flags & kElastic)) {
+                // the cut 2.5 sigma(E) at this step's medium and density
+                const Cut<R> cut = energy_cut(S, ld_sig2z(P, S, tab, mat, rho, E, li, lf));
+                R el, ne_rate;
+                if constexpr (M::f64) {
+                    const MatDev64& md = P.mats64[mat];
+                    el = md.c_ruth0 * (cut.T - 0.5);
+                    if (md.c_mott != 0.0)
+                        el += md.c_mott * mott_bracket(S, cut, S.eta_pre / ::sqrt(E));
+                    const double2 ha = P.hot64[(size_t)mat * P.n_e + li];
+                    const double2 hb = P.hot64[(size_t)mat * P.n_e + li + 1];
+                    ne_rate = ::fma(lf, hb.x - ha.x, ha.x);
+                } else {
+                    const MatDev& md = P.mats[mat];
+                    el = md.c_ruth0 * (cut.T - 0.5f);
+                    if (md.c_mott != 0.0f)
+                        el += md.c_mott * mott_bracket(S, cut, S.eta_pre * M::rsq(E));
+                    ne_rate = fmaf(lf, tb.z - ta.z, ta.z);
+                }
+                rate = el / (E * E) + ((flags & kInelastic) ? ne_rate : R(0));
+            } else if constexpr (M::f64) {
                 const MatDev64& md = P.mats64[mat];
                 const double2 ha = P.hot64[(size_t)mat * P.n_e + li];
                 const double2 hb = P.hot64[(size_t)mat * P.n_e + li + 1];
                 rate = R(0);
                 if (flags & kElastic) {
                     R el = md.c_ruth;
-                    if (md.c_mott != 0.0) el += md.c_mott * mott_bracket(S, S.eta_pre / ::sqrt(E));
+                    if (md.c_mott != 0.0)
+                        el += md.c_mott * mott_bracket(S, fixed_cut(S), S.eta_pre / ::sqrt(E));
                     rate += el / (E * E);
                 }
                 if (flags & kInelastic) rate += ::fma(lf, hb.x - ha.x, ha.x);

@@ -121,7 +121,7 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         *err = "invalid physics parameters";
         return SDE_E_INVALID;
     }
-    if (p->flags & ~(unsigned)(SDE_ALL | SDE_FP64)) {
+    if (p->flags & ~(unsigned)(SDE_ALL | SDE_FP64 | SDE_ECUT)) {
         *err = "unknown physics switch bits";
         return SDE_E_INVALID;
     }
@@ -145,6 +145,9 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
     {
         const double s_hi = std::sin(p->theta_cut_rad), s_lo = std::sin(p->backscatter_cut_rad);
         T.mott_D0 = 2.0 * T.mott_hi / (s_hi * s_hi) - 2.0 * T.mott_lo / (s_lo * s_lo);
+        T.mott_Dlo = 2.0 * T.mott_lo / (s_lo * s_lo);
+        T.mott_shi = omc;
+        T.mott_slo = 1.0 + std::cos(p->backscatter_cut_rad);
         T.mott_Lhi = std::log((1.0 + T.mott_hi) / omc);
         const double omb = 2.0 * std::pow(std::sin(0.5 * p->backscatter_cut_rad), 2);
         T.mott_Llo = std::log(omb / (1.0 - T.mott_lo));
@@ -229,7 +232,7 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
 
         MatDev md{};
         MatDev64 m64{};
-        double c_ruth_d = 0, c_mott_d = 0;   // FP64 sums of the elastic coefficients
+        double c_ruth_d = 0, c_mott_d = 0, c_ruth0_d = 0;   // FP64 sums of the elastic coefficients
         m64.zoa = zoa(m);
         m64.log_pre = std::log(2.0 * kMe / m.I_MeV) - 2.0 * std::log(kMp);
         m64.n_elem = m.n;
@@ -247,6 +250,8 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             // 2 pi (azimuth) x atoms/g x 1e-24 cm^2/barn x 0.01 barn/fm^2
             const double pre = 2.0 * M_PI * nd * 1e-24 * 0.01 * ek * ek;
             e.el_coef = (float)(e.is_h ? pre : pre * (T.ruth_T - 0.5));
+            e.el_base = (float)pre;
+            if (!e.is_h) c_ruth0_d += pre;
             e.ne_coef = (float)(nd * 1e-24);
             e.tab = -1;
             if (use_ne)
@@ -259,6 +264,7 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             m64.ln_ca[i] = std::log(2.007e-5 * std::cbrt(Z * Z));
             m64.za2[i] = 3.34 * (Z * kAlpha) * (Z * kAlpha);
             m64.el_coef[i] = coef;
+            m64.el_base[i] = pre;
             m64.ne_coef[i] = nd * 1e-24;
             m64.m2[i] = A * kAmu;
             m64.is_h[i] = e.is_h;
@@ -304,9 +310,11 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         }
         md.c_ruth = (float)c_ruth_d;
         md.c_mott = (float)c_mott_d;
+        md.c_ruth0 = (float)c_ruth0_d;
         T.mats[k] = md;
         m64.c_ruth = c_ruth_d;
         m64.c_mott = c_mott_d;
+        m64.c_ruth0 = c_ruth0_d;
         T.mats64[k] = m64;
     }
     return SDE_OK;

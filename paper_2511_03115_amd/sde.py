@@ -23,6 +23,7 @@ LOSS, STRAGGLE, MCS, ELASTIC, INELASTIC, END_OF_RANGE = 1, 2, 4, 8, 16, 32
 SBM = 64   # small-angle diffusion by the spherical Brownian motion law (else geodesic step)
 ALL = 127  # the method
 FP64 = 128  # step in double precision (not a physics switch)
+ECUT = 256  # variant: large-angle elastic cut 2.5 sigma(E) instead of the fixed cut
 (LEDGER_DEPOSITED, LEDGER_ESCAPED, LEDGER_NUCLEAR, LEDGER_INITIAL, LEDGER_TRUNCATED,
  LEDGER_STEPS, LEDGER_HISTORIES, LEDGER_JUMPS) = range(8)
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",

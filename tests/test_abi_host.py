@@ -80,8 +80,8 @@ def test_host_validation_without_gpu(lib):
     assert lib.sde_sbm_polar(None, None, None, 5, None, None) == sde.E_INVALID
     assert lib.sde_sbm_polar(None, None, None, -1, None, None) == sde.E_INVALID
     assert lib.sde_sbm_polar(None, None, None, 0, None, None) == sde.OK
-    # bits other than the physics switches and SDE_FP64
-    unk = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63 | 256, 65536)
+    # bits other than the physics switches, SDE_FP64 and SDE_ECUT
+    unk = sde.PhysicsParams(0.05, 0.05, 0.05, 260.0, 0.98, 0.02, 0.04, 1024, 63 | 512, 65536)
     assert lib.sde_init_materials(C.byref(m), 1, C.byref(unk), None) == sde.E_INVALID
     assert b"unknown physics switch" in lib.sde_last_error()
     # the random-number test entry point checks its arguments before any device call

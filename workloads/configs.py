@@ -41,6 +41,7 @@ F_END_OF_RANGE = 32
 F_SBM = 64
 F_ALL = 127
 F_FP64 = 128   # not a physics switch: the GPU path steps in double precision
+F_ECUT = 256   # variant: large-angle elastic cut 2.5 sigma(E) instead of theta_cut_rad
 
 
 @dataclass(frozen=True)
