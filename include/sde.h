@@ -246,6 +246,20 @@ int sde_gamma(const double* ref, const double* eval, int nx, int ny, int nz, dou
               double dy_cm, double dz_cm, double dd, double dta_cm, double thresh,
               int interp, int local, int64_t* counts_out);
 
+/* sde_gamma for callers that cannot allocate device memory (code under
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same counts, with the counters and the search list in a
+ * fixed scratch array of 4 MiB + 256 bytes that every GPU the library runs on
+ * holds until the process ends; it calls no hipMalloc or hipFree.  Voxels
+ * failing at the zero offset beyond 2^20 are searched in the first pass
+ * (same counts, slower).  Calls on one GPU share its scratch array: calls
+ * that overlap on one GPU (several host threads or streams) race.
+ * Arguments, synchronisation and errors as sde_gamma; also SDE_E_INVALID for
+ * more than 2^31 voxels. */
+int sde_gamma_noalloc(const double* ref, const double* eval, int nx, int ny, int nz,
+                      double dx_cm, double dy_cm, double dz_cm, double dd, double dta_cm,
+                      double thresh, int interp, int local, int64_t* counts_out);
+
 /* Kernel test entry point: the polar angle of the small-angle step as the
  * transport draws it with SDE_SBM (section 2.2.2; spherical Brownian motion
  * on S^2 at time t[i]: for t < 0.02 Algorithm 1 of Mijatovic et al. with

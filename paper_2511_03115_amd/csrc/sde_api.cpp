@@ -505,6 +505,32 @@ int gamma_run(const double* ref, const double* ev, int nx, int ny, int nz, doubl
     return SDE_OK;
 }
 
+// Scratch of sde_gamma_noalloc on each GPU: the four counters, then a
+// search list of kNoallocList voxel indices (voxels beyond it are searched in
+// the first pass).  In host code `scratch` is only a symbol: its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr unsigned kNoallocList = 1u << 20;
+constexpr size_t kNoallocCounters = 256;   // bytes before the list
+static __device__ __align__(256) unsigned char scratch[kNoallocCounters +
+                                                       sizeof(unsigned) * kNoallocList];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// This device's copy of the scratch array (its address looked up on the
+// first call with that device current).
+int noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SDE_E_INVALID, "device index out of range");
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char*)g_scratch_ptr[dev];
+    return SDE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -706,6 +732,22 @@ int sde_gamma(const double* ref, const double* ev, int nx, int ny, int nz, doubl
     }
     return gamma_run(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, interp, local,
                      g.gam_buf, g.gam_list, g.gam_cap, counts_out);
+}
+
+int sde_gamma_noalloc(const double* ref, const double* ev, int nx, int ny, int nz,
+                      double dx_cm, double dy_cm, double dz_cm, double dd, double dta_cm,
+                      double thresh, int interp, int local, int64_t* counts_out) {
+    g_err.clear();
+    if (int rc = gamma_check(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, interp,
+                             counts_out))
+        return rc;
+    if ((size_t)nx * ny * nz > ((size_t)1 << 31))
+        return fail(SDE_E_INVALID, "sde_gamma_noalloc: more than 2^31 voxels");
+    unsigned char* sc = nullptr;
+    if (int rc = noalloc_scratch(&sc)) return rc;
+    return gamma_run(ref, ev, nx, ny, nz, dx_cm, dy_cm, dz_cm, dd, dta_cm, thresh, interp, local,
+                     (unsigned long long*)sc, (unsigned*)(sc + kNoallocCounters), kNoallocList,
+                     counts_out);
 }
 
 int sde_launch_limits(int* n_cu, int* max_lds_bytes, int* table_lds_bytes) {

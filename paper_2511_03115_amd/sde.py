@@ -29,7 +29,8 @@ ECUT = 256  # variant: large-angle elastic cut 2.5 sigma(E) instead of the fixed
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",
            "sde_plan_create", "sde_plan_execute", "sde_plan_results", "sde_plan_destroy",
            "sde_plan_kernel_ms", "sde_plan_set_records", "sde_gamma", "sde_launch_limits",
-           "sde_sbm_polar", "sde_philox_words", "sde_free", "sde_last_error")
+           "sde_sbm_polar", "sde_philox_words", "sde_gamma_noalloc", "sde_free",
+           "sde_last_error")
 
 
 class SdeError(RuntimeError):
@@ -104,6 +105,7 @@ def _load():
                             C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, P(C.c_int64)]
     L.sde_launch_limits.argtypes = [P(C.c_int), P(C.c_int), P(C.c_int)]
     L.sde_sbm_polar.argtypes = [V, V, V, C.c_int64, V, V]
+    L.sde_gamma_noalloc.argtypes = L.sde_gamma.argtypes
     L.sde_philox_words.argtypes = [C.c_uint64, V, V, V, C.c_int64, V]
     L.sde_free.argtypes = []
     L.sde_free.restype = None
@@ -350,6 +352,21 @@ def gamma(ref, ev, voxel_cm, dd: float = 0.02, dta_cm: float = 0.05, thresh: flo
     _check(lib.sde_gamma(C.c_void_p(_dptr(ref)), C.c_void_p(_dptr(ev)), nx, ny, nz,
                          voxel_cm[0], voxel_cm[1], voxel_cm[2], dd, dta_cm, thresh, int(interp),
                          int(local), cnt.ctypes.data_as(C.POINTER(C.c_int64))))
+    ne, npass = int(cnt[0]), int(cnt[1])
+    return (npass / ne if ne else 1.0), ne, npass
+
+
+def gamma_noalloc(ref, ev, voxel_cm, dd: float = 0.02, dta_cm: float = 0.05,
+                  thresh: float = 0.01, interp: int = 10, local: bool = True):
+    """As ``gamma``, through the entry point that allocates no device memory."""
+    if ref.shape != ev.shape or ref.dtype != ev.dtype:
+        raise ValueError("ref and ev must have the same shape and dtype")
+    nz, ny, nx = ref.shape
+    cnt = np.zeros(2, dtype=np.int64)
+    _check(lib.sde_gamma_noalloc(C.c_void_p(_dptr(ref)), C.c_void_p(_dptr(ev)), nx, ny, nz,
+                                 voxel_cm[0], voxel_cm[1], voxel_cm[2], dd, dta_cm, thresh,
+                                 int(interp), int(local),
+                                 cnt.ctypes.data_as(C.POINTER(C.c_int64))))
     ne, npass = int(cnt[0]), int(cnt[1])
     return (npass / ne if ne else 1.0), ne, npass
 
