@@ -72,7 +72,11 @@ class Nuclear(C.Structure):
     _fields_ = [("n_tab", C.c_int), ("n_e", C.c_int), ("n_u", C.c_int), ("pad", C.c_int),
                 ("e_lo", C.c_double), ("e_hi", C.c_double), ("Z", C.POINTER(C.c_int)),
                 ("sigma", C.POINTER(C.c_double)), ("u_icdf", C.POINTER(C.c_double)),
-                ("kr", C.POINTER(C.c_double)), ("ka", C.POINTER(C.c_double))]
+                ("kr", C.POINTER(C.c_double)), ("ka", C.POINTER(C.c_double)),
+                ("n_ni", C.c_int), ("n_mu", C.c_int), ("ni_Z", C.POINTER(C.c_int)),
+                ("ni_sigma", C.POINTER(C.c_double)), ("ni_p", C.POINTER(C.c_double)),
+                ("n_l", C.c_int), ("pad2", C.c_int), ("h_are", C.POINTER(C.c_double)),
+                ("h_aim", C.POINTER(C.c_double)), ("h_b", C.POINTER(C.c_double))]
 
 
 class PhantomS(C.Structure):
@@ -131,6 +135,21 @@ def lib():
         L.or_sbm_t_switch.restype = d
         L.or_sbm_polar_n.argtypes = [C.c_size_t, d, P(d), P(d), P(d), P(d)]
         L.or_sbm_polar_n.restype = None
+        L.or_bspline3.argtypes = [P(d), C.c_int, d, d, d]
+        L.or_bspline3.restype = d
+        for f in ("or_p_ni_integral",):
+            getattr(L, f).argtypes = [P(Nuclear), C.c_int, C.c_int, d]
+            getattr(L, f).restype = d
+        for f in ("or_ni_density", "or_ni_integral"):
+            getattr(L, f).argtypes = [P(Nuclear), C.c_int, d, d]
+            getattr(L, f).restype = d
+        for f in ("or_h_nuclear_density", "or_h_nuclear_antiderivative"):
+            getattr(L, f).argtypes = [P(Nuclear), d, d]
+            getattr(L, f).restype = d
+        L.or_elastic_sample_mu.argtypes = [P(Nuclear), C.c_int, d, d, d, d, d]
+        L.or_elastic_sample_mu.restype = d
+        L.or_elastic_cum_barn.argtypes = [P(Nuclear), C.c_int, d, d, d, d]
+        L.or_elastic_cum_barn.restype = d
         L.or_elastic_cut.argtypes = [P(Material), P(Params), d, d]
         L.or_elastic_cut.restype = d
         L.or_channel_total_rate.argtypes = [P(Material), P(Nuclear), P(Params), d, d]
@@ -225,7 +244,21 @@ def nuclear_struct(nt) -> tuple:
     s.e_lo, s.e_hi = nt.lattice.e_lo, nt.lattice.e_hi
     s.Z, s.sigma, s.u_icdf = _ptr(Z, C.c_int), _ptr(sg, C.c_double), _ptr(ui, C.c_double)
     s.kr, s.ka = _ptr(kr, C.c_double), _ptr(ka, C.c_double)
-    return s, [Z, sg, ui, kr, ka]
+    keep = [Z, sg, ui, kr, ka]
+    el = getattr(nt, "elastic", None)
+    if el is not None:
+        nZ = np.ascontiguousarray(el.ni_Z, dtype=np.int32)
+        ns = np.ascontiguousarray(el.ni_sigma, dtype=np.float64)
+        npp = np.ascontiguousarray(el.ni_p, dtype=np.float64)
+        ha = np.ascontiguousarray(el.h_are, dtype=np.float64)
+        hi = np.ascontiguousarray(el.h_aim, dtype=np.float64)
+        hb = np.ascontiguousarray(el.h_b, dtype=np.float64)
+        s.n_ni, s.n_mu = len(nZ), int(npp.shape[-1]) if npp.size else 0
+        s.ni_Z, s.ni_sigma, s.ni_p = _ptr(nZ, C.c_int), _ptr(ns, C.c_double), _ptr(npp, C.c_double)
+        s.n_l = int(ha.shape[0])
+        s.h_are, s.h_aim, s.h_b = _ptr(ha, C.c_double), _ptr(hi, C.c_double), _ptr(hb, C.c_double)
+        keep += [nZ, ns, npp, ha, hi, hb]
+    return s, keep
 
 
 def phantom_struct(ph) -> tuple:
@@ -419,6 +452,30 @@ class NuclearView:
         k = {"u": 0, "r": 1, "a": 2}[which]
         return lib().or_table_eu(C.byref(self.s), int(t), k, float(E), float(x))
 
+    def p_ni_integral(self, t: int, i: int, x: float) -> float:
+        return lib().or_p_ni_integral(C.byref(self.s), int(t), int(i), float(x))
+
+    def ni_density(self, t: int, E: float, mu: float) -> float:
+        return lib().or_ni_density(C.byref(self.s), int(t), float(E), float(mu))
+
+    def ni_integral(self, t: int, E: float, x: float) -> float:
+        return lib().or_ni_integral(C.byref(self.s), int(t), float(E), float(x))
+
+    def h_nuclear_density(self, E: float, mu: float) -> float:
+        return lib().or_h_nuclear_density(C.byref(self.s), float(E), float(mu))
+
+    def h_nuclear_antiderivative(self, E: float, mu: float) -> float:
+        return lib().or_h_nuclear_antiderivative(C.byref(self.s), float(E), float(mu))
+
+    def elastic_sample_mu(self, Z: int, A: float, E: float, U: float, tc: float = 0.02,
+                          tb: float = 0.04) -> float:
+        return lib().or_elastic_sample_mu(C.byref(self.s), int(Z), float(A), float(E),
+                                          float(U), float(tc), float(tb))
+
+    def elastic_cum_barn(self, Z: int, A: float, E: float, lo: float, x: float) -> float:
+        return lib().or_elastic_cum_barn(C.byref(self.s), int(Z), float(A), float(E),
+                                         float(lo), float(x))
+
     def draw(self, t: int, E: float, U1: float, U3: float):
         u, c = C.c_double(0.0), C.c_double(0.0)
         lib().or_inelastic_draw(C.byref(self.s), int(t), float(E), float(U1), float(U3),
@@ -442,6 +499,11 @@ def elastic_cut(m, params, rho: float, E: float, flags=None) -> float:
     s = material_struct(m)
     ps = params_struct(params, flags)
     return lib().or_elastic_cut(C.byref(s), C.byref(ps), float(rho), float(E))
+
+
+def bspline3(c: np.ndarray, m: int, x0: float, h: float, x: float) -> float:
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    return lib().or_bspline3(_ptr(c, C.c_double), int(m), float(x0), float(h), float(x))
 
 
 def channel_total_rate(m, params, rho: float, E: float, nuclear=None, flags=None) -> float:

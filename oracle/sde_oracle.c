@@ -22,6 +22,8 @@
  * which approximates it to O(t) in the angle and is pinned by the thin-slab
  * laws only.
  */
+#include <complex.h>
+#undef I   /* the imaginary unit is written _Complex_I below; I is a variable name */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -85,6 +87,21 @@ typedef struct {
     const double* u_icdf;    /* [n_tab][n_e][n_u] */
     const double* kr;        /* [n_tab][n_e][n_u] */
     const double* ka;        /* [n_tab][n_e][n_u] */
+    /* Elastic nuclear data (section 2.1.4).  Elements other than hydrogen:
+     * sigma_NI(E_i) in barn and the cubic B-spline coefficients of
+     * P_NI(mu, E_i) on uniform knots over [-1, 1] (n_mu >= 4; knot j at
+     * -1 + (j - 3) h, h = 2 / (n_mu - 3)).  Hydrogen: partial waves
+     * l = 0..n_l-1 (n_l <= 8), the cubic B-spline coefficients in the
+     * lattice coordinate (n_e + 2 per l, uniform knots at the lattice
+     * points) of Re a_l, Im a_l and b_l (barn). */
+    int n_ni, n_mu;
+    const int* ni_Z;         /* [n_ni] */
+    const double* ni_sigma;  /* [n_ni][n_e] barn */
+    const double* ni_p;      /* [n_ni][n_e][n_mu] */
+    int n_l, pad2;
+    const double* h_are;     /* [n_l][n_e + 2] */
+    const double* h_aim;
+    const double* h_b;
 } or_nuclear;
 
 typedef struct {
@@ -298,6 +315,211 @@ static double table_eu(const or_nuclear* nu, const double* tab, double E, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Elastic nuclear terms (section 2.1.4)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* The uniform cubic B-spline basis on one knot interval, at local u in [0, 1]:
+ * the four pieces (1-u)^3/6, (3u^3 - 6u^2 + 4)/6, (-3u^3 + 3u^2 + 3u + 1)/6,
+ * u^3/6 of the cardinal cubic B-spline. */
+static void bspline3_basis(double u, double B[4]) {
+    double v = 1.0 - u;
+    B[0] = v * v * v / 6.0;
+    B[1] = (3.0 * u * u * u - 6.0 * u * u + 4.0) / 6.0;
+    B[2] = (-3.0 * u * u * u + 3.0 * u * u + 3.0 * u + 1.0) / 6.0;
+    B[3] = u * u * u / 6.0;
+}
+
+/* Value at x of the cubic spline with coefficients c[0..m+2] on the uniform
+ * knots x0 + (j - 3) h (m intervals covering [x0, x0 + m h]); x is clamped
+ * to that range. */
+static double bspline3(const double* c, int m, double x0, double h, double x) {
+    double t = (x - x0) / h;
+    if (t < 0.0) t = 0.0;
+    if (t > m) t = m;
+    int k = (int)floor(t);
+    if (k > m - 1) k = m - 1;
+    double B[4];
+    bspline3_basis(t - k, B);
+    return c[k] * B[0] + c[k + 1] * B[1] + c[k + 2] * B[2] + c[k + 3] * B[3];
+}
+
+/* P_NI of element row t at lattice energy i and cosine mu. */
+static double p_ni(const or_nuclear* nu, int t, int i, double mu) {
+    int m = nu->n_mu - 3;
+    const double* c = nu->ni_p + ((size_t)t * nu->n_e + i) * nu->n_mu;
+    return bspline3(c, m, -1.0, 2.0 / m, mu);
+}
+
+/* int_{-1}^{x} P_NI(mu, E_i) dmu: 4-point Gauss-Legendre on every knot
+ * interval (exact for the cubic pieces). */
+static double p_ni_integral(const or_nuclear* nu, int t, int i, double x) {
+    static const double gx[4] = {-0.86113631159405257522, -0.33998104358485626480,
+                                 0.33998104358485626480, 0.86113631159405257522};
+    static const double gw[4] = {0.34785484513745385737, 0.65214515486254614263,
+                                 0.65214515486254614263, 0.34785484513745385737};
+    int m = nu->n_mu - 3;
+    double h = 2.0 / m, s = 0.0;
+    if (x <= -1.0) return 0.0;
+    if (x > 1.0) x = 1.0;
+    for (int k = 0; k < m; ++k) {
+        double a = -1.0 + k * h, b = a + h;
+        if (a >= x) break;
+        if (b > x) b = x;
+        double c = 0.5 * (a + b), r = 0.5 * (b - a);
+        for (int q = 0; q < 4; ++q) s += gw[q] * r * p_ni(nu, t, i, c + r * gx[q]);
+    }
+    return s;
+}
+
+static int ni_row(const or_nuclear* nu, int Z) {
+    if (!nu || nu->n_ni <= 0) return -1;
+    for (int t = 0; t < nu->n_ni; ++t) if (nu->ni_Z[t] == Z) return t;
+    return -1;
+}
+
+/* The nuclear-plus-interference term sigma_NI(E) P_NI(mu, E) of Eq.
+ * (elastic_large_barns) at energy E, linear in the lattice coordinate
+ * between the two neighbouring lattice energies (the paper extends its
+ * lattice quantities linearly): its density in mu (barn/sr) and its
+ * integral from -1 to x (barn). */
+static double ni_density(const or_nuclear* nu, int t, double E, double mu) {
+    int i; double f;
+    lattice_pos(nu, E, &i, &f);
+    const double* sg = nu->ni_sigma + (size_t)t * nu->n_e;
+    return (1.0 - f) * sg[i] * p_ni(nu, t, i, mu) + f * sg[i + 1] * p_ni(nu, t, i + 1, mu);
+}
+static double ni_integral(const or_nuclear* nu, int t, double E, double x) {
+    int i; double f;
+    lattice_pos(nu, E, &i, &f);
+    const double* sg = nu->ni_sigma + (size_t)t * nu->n_e;
+    return (1.0 - f) * sg[i] * p_ni_integral(nu, t, i, x) +
+           f * sg[i + 1] * p_ni_integral(nu, t, i + 1, x);
+}
+
+/* Hydrogen partial-wave amplitudes at E: the cubic B-splines in the lattice
+ * coordinate (section 2.1.4: a_l(E), b_l(E) extended by a cubic B-spline). */
+static void h_amplitudes(const or_nuclear* nu, double E, double complex* a, double* b) {
+    double t = (log(E) - log(nu->e_lo)) / (log(nu->e_hi) - log(nu->e_lo)) * (nu->n_e - 1);
+    int m = nu->n_e - 1;
+    for (int l = 0; l < nu->n_l; ++l) {
+        const double* cr = nu->h_are + (size_t)l * (nu->n_e + 2);
+        const double* ci = nu->h_aim + (size_t)l * (nu->n_e + 2);
+        const double* cb = nu->h_b + (size_t)l * (nu->n_e + 2);
+        a[l] = bspline3(cr, m, 0.0, 1.0, t) + _Complex_I * bspline3(ci, m, 0.0, 1.0, t);
+        b[l] = bspline3(cb, m, 0.0, 1.0, t);
+    }
+}
+
+/* Legendre polynomial P_n(x) by the three-term recurrence. */
+static double legendre(int n, double x) {
+    double pm = 1.0, p = x;
+    if (n == 0) return 1.0;
+    for (int k = 1; k < n; ++k) {
+        double pn = ((2.0 * k + 1.0) * x * p - k * pm) / (k + 1.0);
+        pm = p;
+        p = pn;
+    }
+    return p;
+}
+
+/* The hydrogen nuclear term sigma_N^c(mu, E) of Eq. (hydrogen_not_ruther),
+ * barn/sr, evaluated literally (eta = alpha sqrt(m_p / 2E)). */
+static double h_nuclear_density(const or_nuclear* nu, double E, double mu) {
+    double complex a[8];
+    double b[8];
+    h_amplitudes(nu, E, a, b);
+    double eta = mott_eta(E);
+    double s1 = 0.0;
+    double complex s2 = 0.0;
+    double complex em = cexp(_Complex_I * eta * log((1.0 - mu) / 2.0));
+    double complex ep = cexp(_Complex_I * eta * log((1.0 + mu) / 2.0));
+    for (int l = 0; l < nu->n_l; ++l) {
+        s1 += (4.0 * l + 1.0) / 2.0 * b[l] * legendre(2 * l, mu);
+        double sgn = (l % 2) ? -1.0 : 1.0;
+        s2 += ((1.0 + mu) * em + sgn * (1.0 - mu) * ep) * (2.0 * l + 1.0) / 2.0 * a[l] *
+              legendre(l, mu);
+    }
+    return s1 - 2.0 * eta / (1.0 - mu * mu) * creal(s2);
+}
+
+/* Coefficients of P_l(x) = sum_n p[n] x^n, l <= 15, by the recurrence on
+ * coefficient vectors. */
+static void legendre_monomials(int l, double* p) {
+    double pm[16] = {0}, pc[16] = {0}, pn[16];
+    pm[0] = 1.0;          /* P_0 */
+    pc[1] = 1.0;          /* P_1 */
+    if (l == 0) { memcpy(p, pm, sizeof pm); return; }
+    for (int k = 1; k < l; ++k) {
+        for (int n = 0; n < 16; ++n) {
+            double up = n > 0 ? pc[n - 1] : 0.0;
+            pn[n] = ((2.0 * k + 1.0) * up - k * pm[n]) / (k + 1.0);
+        }
+        memcpy(pm, pc, sizeof pc);
+        memcpy(pc, pn, sizeof pn);
+    }
+    memcpy(p, pc, sizeof pc);
+}
+
+/* Antiderivative (Appendix A.2) of mu^n f(mu), f(mu) = (c1 cos(phi) +
+ * c2 sin(phi)) / (1 + sg mu), phi = eta ln((1 + sg mu) / 2), sg = +1 or -1:
+ * the k-th antiderivative of f is (1 + sg mu)^(k-1) (cc_k cos(phi) +
+ * cs_k sin(phi)) with cc_0 = c1, cs_0 = c2 and
+ *   cc_{k+1} = sg (k cc_k - eta cs_k) / (k^2 + eta^2),
+ *   cs_{k+1} = sg (eta cc_k + k cs_k) / (k^2 + eta^2),
+ * and by repeated integration by parts
+ *   int mu^n f = sum_{i=0}^{n} (-1)^i n! / (n-i)! f^(i+1)(mu) mu^(n-i)
+ * up to a constant (it cancels in every definite integral taken here). */
+static double h_mono_antiderivative(int n, double sg, double c1, double c2, double eta,
+                                    double mu) {
+    double cc[17], cs[17];
+    cc[0] = c1;
+    cs[0] = c2;
+    for (int k = 0; k <= n; ++k) {
+        double d = k * k + eta * eta;
+        cc[k + 1] = sg * (k * cc[k] - eta * cs[k]) / d;
+        cs[k + 1] = sg * (eta * cc[k] + k * cs[k]) / d;
+    }
+    double y = 1.0 + sg * mu;
+    double phi = eta * log(y / 2.0), cp = cos(phi), sp = sin(phi);
+    double s = 0.0, fact = 1.0;   /* n! / (n - i)! */
+    for (int i = 0; i <= n; ++i) {
+        if (i > 0) fact *= (n - i + 1);
+        double fi = pow(y, i) * (cc[i + 1] * cp + cs[i + 1] * sp);   /* f^(i+1) */
+        s += ((i % 2) ? -1.0 : 1.0) * fact * fi * pow(mu, n - i);
+    }
+    return s;
+}
+
+/* Antiderivative in mu of sigma_N^c(mu, E) (barn): the b_l terms through
+ * int P_n = (P_{n+1} - P_{n-1}) / (2n + 1) (x for n = 0), the a_l terms
+ * through h_mono_antiderivative with c1 = Re a_l, c2 = -Im a_l (so that
+ * c1 cos + c2 sin = Re(a_l e^{i phi})) for the (1 - mu) and (1 + mu)
+ * denominators. */
+static double h_nuclear_antiderivative(const or_nuclear* nu, double E, double mu) {
+    double complex a[8];
+    double b[8];
+    h_amplitudes(nu, E, a, b);
+    double eta = mott_eta(E);
+    double s1 = 0.0, s2 = 0.0;
+    for (int l = 0; l < nu->n_l; ++l) {
+        int n2 = 2 * l;
+        double ip = n2 == 0 ? mu : (legendre(n2 + 1, mu) - legendre(n2 - 1, mu)) / (2.0 * n2 + 1.0);
+        s1 += (4.0 * l + 1.0) / 2.0 * b[l] * ip;
+        double p[16];
+        legendre_monomials(l, p);
+        double c1 = creal(a[l]), c2 = -cimag(a[l]), sgn = (l % 2) ? -1.0 : 1.0;
+        double acc = 0.0;
+        for (int n = 0; n <= l; ++n) {
+            if (p[n] == 0.0) continue;
+            acc += p[n] * (h_mono_antiderivative(n, -1.0, c1, c2, eta, mu) +
+                           sgn * h_mono_antiderivative(n, +1.0, c1, c2, eta, mu));
+        }
+        s2 += (2.0 * l + 1.0) / 2.0 * acc;
+    }
+    return s1 - 2.0 * eta * s2;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Jump channels (Eq. (Npi)): for compounds each element is an independent  */
 /* point process (section 2.1), elastic and inelastic per element.          */
 /* ------------------------------------------------------------------------ */
@@ -328,6 +550,23 @@ static double cut_for(int Z, double theta_c, double theta_bs) {
     return theta_c < top ? theta_c : top;
 }
 
+/* The elastic nuclear terms' integral (barn) over the CM cosines of the
+ * large-angle law: sigma_NI P_NI from -1 to cos(cut) for elements with
+ * such data, sigma_N from -cos(theta_bs) to cos(cut) for hydrogen with
+ * partial waves; 0 without data. */
+static double elastic_nuclear_integral_barn(const or_nuclear* nu, int Z, double E, double tc,
+                                            double theta_bs) {
+    if (!nu) return 0.0;
+    if (Z == 1) {
+        if (nu->n_l <= 0) return 0.0;
+        double hi = cos(tc), lo = -cos(theta_bs);
+        if (hi <= lo) return 0.0;
+        return h_nuclear_antiderivative(nu, E, hi) - h_nuclear_antiderivative(nu, E, lo);
+    }
+    int t = ni_row(nu, Z);
+    return t < 0 ? 0.0 : ni_integral(nu, t, E, cos(tc));
+}
+
 static void channel_rates(const or_material* m, const or_nuclear* nu, const or_params* p,
                           double rho, double E, channels* c) {
     c->n = 0;
@@ -339,6 +578,7 @@ static void channel_rates(const or_material* m, const or_nuclear* nu, const or_p
             double xs = (m->Z[i] == 1)
                 ? mott_integral_barn(m->A[i], E, tc, p->theta_bs)
                 : rutherford_integral_barn(m->Z[i], m->A[i], E, tc);
+            xs += elastic_nuclear_integral_barn(nu, m->Z[i], E, tc, p->theta_bs);
             /* 2 pi from the azimuth, 1e-24 cm^2 per barn (Eq. (large_elastic_cm)) */
             c->rate[c->n] = 2.0 * M_PI * nd * xs * 1e-24;
             c->elem[c->n] = i; c->inel[c->n] = 0; c->tab[c->n] = -1;
@@ -377,6 +617,38 @@ static double mott_sample_mu(double E, double U, double theta_cut, double theta_
         double mid = 0.5 * (a + b);
         if (mid <= a || mid >= b) break;
         if (mott_G(eta, mid) < target) a = mid; else b = mid;
+    }
+    return 0.5 * (a + b);
+}
+
+/* The CM cosine of an elastic jump with nuclear data: solve
+ * Pi_e(E; nu) = U for the distribution function Eq. (large_elastic_cdf) of
+ * the summed cross section (Coulomb + nuclear) by bisection, the numerator
+ * the integral from the lower limit (-1, or -cos(theta_bs) for hydrogen). */
+static double elastic_cum_barn(const or_nuclear* nu, int Z, double A, double E, double lo,
+                               double x) {
+    if (Z == 1) {
+        double ek2 = eta2_over_k2_fm2(1.0, A, E) * 0.01, eta = mott_eta(E);
+        double s = ek2 * (mott_G(eta, x) - mott_G(eta, lo));
+        if (nu && nu->n_l > 0)
+            s += h_nuclear_antiderivative(nu, E, x) - h_nuclear_antiderivative(nu, E, lo);
+        return s;
+    }
+    double ek2 = eta2_over_k2_fm2(Z, A, E) * 0.01;
+    double s = ek2 * (1.0 / (1.0 - x) - 0.5);   /* int_{-1}^{x} (eta/k)^2 / (1 - mu)^2 */
+    int t = ni_row(nu, Z);
+    if (t >= 0) s += ni_integral(nu, t, E, x);
+    return s;
+}
+static double elastic_sample_mu(const or_nuclear* nu, int Z, double A, double E, double U,
+                                double tc, double theta_bs) {
+    double lo = (Z == 1) ? -cos(theta_bs) : -1.0, hi = cos(tc);
+    double target = U * elastic_cum_barn(nu, Z, A, E, lo, hi);
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (a + b);
+        if (mid <= a || mid >= b) break;
+        if (elastic_cum_barn(nu, Z, A, E, lo, mid) < target) a = mid; else b = mid;
     }
     return 0.5 * (a + b);
 }
@@ -677,6 +949,31 @@ double or_table_eu(const or_nuclear* nu, int t, int which, double E, double x) {
     const double* base = which == 0 ? nu->u_icdf : which == 1 ? nu->kr : nu->ka;
     return table_eu(nu, base + (size_t)t * nu->n_e * nu->n_u, E, x);
 }
+double or_bspline3(const double* c, int m, double x0, double h, double x) {
+    return bspline3(c, m, x0, h, x);
+}
+double or_p_ni_integral(const or_nuclear* nu, int t, int i, double x) {
+    return p_ni_integral(nu, t, i, x);
+}
+double or_ni_density(const or_nuclear* nu, int t, double E, double mu) {
+    return ni_density(nu, t, E, mu);
+}
+double or_ni_integral(const or_nuclear* nu, int t, double E, double x) {
+    return ni_integral(nu, t, E, x);
+}
+double or_h_nuclear_density(const or_nuclear* nu, double E, double mu) {
+    return h_nuclear_density(nu, E, mu);
+}
+double or_h_nuclear_antiderivative(const or_nuclear* nu, double E, double mu) {
+    return h_nuclear_antiderivative(nu, E, mu);
+}
+double or_elastic_sample_mu(const or_nuclear* nu, int Z, double A, double E, double U,
+                            double tc, double tb) {
+    return elastic_sample_mu(nu, Z, A, E, U, tc, tb);
+}
+double or_elastic_cum_barn(const or_nuclear* nu, int Z, double A, double E, double lo, double x) {
+    return elastic_cum_barn(nu, Z, A, E, lo, x);
+}
 double or_elastic_cut(const or_material* m, const or_params* p, double rho, double E) {
     return elastic_cut(m, p, rho, E);
 }
@@ -859,7 +1156,11 @@ static void track(const or_material* mats, const range_cache* rcs, const or_para
                 double cos_cm, sin_cm;
                 if (!ch.inel[c]) {
                     double tc = cut_for(m->Z[e], ch.theta_c, p->theta_bs);
-                    if (m->Z[e] == 1) {
+                    if (elastic_nuclear_integral_barn(nu, m->Z[e], E, tc, p->theta_bs) != 0.0) {
+                        cos_cm = elastic_sample_mu(nu, m->Z[e], m->A[e], E, u_hi(q[1]), tc,
+                                                   p->theta_bs);
+                        sin_cm = sqrt(fmax(0.0, 1.0 - cos_cm * cos_cm));
+                    } else if (m->Z[e] == 1) {
                         cos_cm = mott_sample_mu(E, u_hi(q[1]), tc, p->theta_bs);
                         sin_cm = sqrt(fmax(0.0, 1.0 - cos_cm * cos_cm));
                     } else {

@@ -47,6 +47,26 @@ class EnergyLattice:
 
 
 @dataclass
+class ElasticNuclear:
+    """Elastic nuclear data of section 2.1.4 in the layout both sides read.
+
+    * ``ni_Z``, ``ni_sigma[t, i]`` (barn) and ``ni_p[t, i, j]``: for elements
+      other than hydrogen, sigma_NI(E_i) and the cubic B-spline coefficients
+      of P_NI(mu, E_i) on uniform knots over mu in [-1, 1] (knot j at
+      -1 + (j - 3) h, h = 2 / (n_mu - 3));
+    * ``h_are[l, k]``, ``h_aim[l, k]``, ``h_b[l, k]`` (barn): for hydrogen,
+      l = 0..n_l-1, the cubic B-spline coefficients in the lattice
+      coordinate of Re a_l(E), Im a_l(E) and b_l(E) (n_e + 2 per l).
+    """
+    ni_Z: np.ndarray
+    ni_sigma: np.ndarray
+    ni_p: np.ndarray
+    h_are: np.ndarray
+    h_aim: np.ndarray
+    h_b: np.ndarray
+
+
+@dataclass
 class NuclearTables:
     lattice: EnergyLattice
     n_u: int
@@ -56,6 +76,7 @@ class NuclearTables:
     u_icdf: np.ndarray     # float64 [n_tab, n_e, n_u]
     kalbach_r: np.ndarray  # float64 [n_tab, n_e, n_u]
     kalbach_a: np.ndarray  # float64 [n_tab, n_e, n_u]
+    elastic: "ElasticNuclear | None" = None
 
 
 def placeholder_nuclear_tables(elements: Sequence[int], atomic_weights: Sequence[float],
@@ -101,3 +122,63 @@ def nuclear_for_phantom(phantom, lattice: EnergyLattice) -> NuclearTables:
     zs = [z for m in phantom.materials for z in m.Z]
     As = [a for m in phantom.materials for a in m.A]
     return placeholder_nuclear_tables(zs, As, lattice)
+
+
+def synthetic_elastic_nuclear(elements: Sequence[int], atomic_weights: Sequence[float],
+                              lattice: EnergyLattice = EnergyLattice(), n_mu: int = 24,
+                              n_l: int = 8, seed: int = 0) -> ElasticNuclear:
+    """Synthetic elastic nuclear data of the ENDF shapes (no library values):
+    every element heavier than hydrogen gets sigma_NI(E) = 0.3 A^(2/3)
+    (1 - exp(-E / 20 MeV)) barn and a P_NI(mu, E) that rises towards forward
+    angles, exp(k (mu - 1)) with k = 1 + E / 40 MeV, normalised to integrate
+    to 1 over [-1, 1] (its B-spline coefficients are those values at the
+    knots' Greville points, a smooth shape, not an interpolation);
+    hydrogen gets seeded smooth amplitudes: b_0(E) around 0.012 barn with
+    higher b_l falling as 0.1^l, and complex a_l of modulus <= 5e-4 barn,
+    small enough that the summed hydrogen cross section stays positive (the
+    tests check it)."""
+    rng = np.random.default_rng(seed)
+    m = n_mu - 3
+    h = 2.0 / m
+    greville = -1.0 + (np.arange(n_mu) - 1.0) * h      # centres of the basis functions
+    E = lattice.energies()
+    zs, As = [], []
+    for z, a in zip(elements, atomic_weights):
+        if int(z) > 1 and int(z) not in zs:
+            zs.append(int(z))
+            As.append(float(a))
+    ni_sigma = np.zeros((len(zs), lattice.n))
+    ni_p = np.zeros((len(zs), lattice.n, n_mu))
+    for t, a in enumerate(As):
+        ni_sigma[t] = 0.3 * a ** (2.0 / 3.0) * (1.0 - np.exp(-E / 20.0))
+        k = 1.0 + E / 40.0
+        c = np.exp(k[:, None] * (np.clip(greville, -1.0, 1.0)[None, :] - 1.0))
+        # normalise each energy's spline to unit integral: the integral of a
+        # uniform cubic spline is h times the sum of its coefficients, less
+        # the parts of the three boundary basis functions outside [-1, 1]
+        w = np.ones(n_mu)
+        w[0] = w[-1] = 1.0 / 24.0
+        w[1] = w[-2] = 0.5
+        w[2] = w[-3] = 23.0 / 24.0
+        ni_p[t] = c / (h * (c * w[None, :]).sum(axis=1))[:, None]
+    n_c = lattice.n + 2
+    tt = np.arange(n_c) - 1.0                          # lattice coordinate of coefficient k
+    x = tt / max(lattice.n - 1, 1)
+    h_b = np.zeros((n_l, n_c))
+    h_are = np.zeros((n_l, n_c))
+    h_aim = np.zeros((n_l, n_c))
+    for l in range(n_l):
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        h_b[l] = 0.012 * 0.1 ** l * (1.0 + 0.2 * np.sin(np.pi * x * (l + 2) + ph[0]))
+        amp = 5e-4 / (l + 1)
+        h_are[l] = amp * np.cos(np.pi * x * 1.5 + ph[1])
+        h_aim[l] = amp * np.sin(np.pi * x * 2.5 + ph[2])
+    return ElasticNuclear(ni_Z=np.array(zs, dtype=np.int32), ni_sigma=ni_sigma, ni_p=ni_p,
+                          h_are=h_are, h_aim=h_aim, h_b=h_b)
+
+
+def with_elastic_nuclear(nt: NuclearTables, el: ElasticNuclear) -> NuclearTables:
+    """The same inelastic tables with elastic nuclear data attached."""
+    return NuclearTables(lattice=nt.lattice, n_u=nt.n_u, Z=nt.Z, A=nt.A, sigma=nt.sigma,
+                         u_icdf=nt.u_icdf, kalbach_r=nt.kalbach_r, kalbach_a=nt.kalbach_a,
+                         elastic=el)
