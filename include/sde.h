@@ -122,12 +122,28 @@ typedef struct {
     int64_t max_steps;           /* histories still alive after this many steps stop */
 } sde_physics_params;
 
-/* Inelastic proton-nucleus data on the energy lattice of the physics params
- * (n_energy points uniform in ln E over [e_min, e_max]); section 2.1.5.
- * Values between lattice points are linear in the lattice coordinate.
- * sigma_barn[t][i] total cross section of element Z[t] at E_i (barn);
- * u_icdf[t][i][j] inverse CDF of the loss fraction u at U = j/(n_u-1);
- * kalbach_r/kalbach_a[t][i][j] Kalbach-Mann r and a at u = j/(n_u-1).  (host) */
+/* Nuclear data on the energy lattice of the physics params (n_energy
+ * points uniform in ln E over [e_min, e_max]).  (host)
+ *
+ * Inelastic proton-nucleus interactions (section 2.1.5); values between
+ * lattice points are linear in the lattice coordinate.  sigma_barn[t][i]
+ * total cross section of element Z[t] at E_i (barn); u_icdf[t][i][j] inverse
+ * CDF of the loss fraction u at U = j/(n_u-1); kalbach_r/kalbach_a[t][i][j]
+ * Kalbach-Mann r and a at u = j/(n_u-1).
+ *
+ * Elastic nuclear terms (section 2.1.4), optional (counts 0 = none):
+ *  - elements other than hydrogen, the nuclear-plus-interference term
+ *    sigma_NI(E) P_NI(mu, E) of Eq. (elastic_large_barns): ni_sigma_barn[t][i]
+ *    (barn) and ni_p[t][i][j], the cubic B-spline coefficients of
+ *    P_NI(mu, E_i) (barn/sr per barn) on uniform knots over mu in [-1, 1]
+ *    (knot j at -1 + (j - 3) 2/(n_mu - 3); n_mu in 7..256); the term is
+ *    linear in the lattice coordinate between lattice energies;
+ *  - hydrogen, the nuclear term of Eq. (hydrogen_not_ruther) for
+ *    l = 0..n_l-1 (n_l <= 8): h_a_re, h_a_im, h_b [l][n_energy + 2], the
+ *    cubic B-spline coefficients in the lattice coordinate (uniform knots at
+ *    the lattice points, knot k at k - 3) of Re a_l(E), Im a_l(E) and b_l(E)
+ *    (barn).
+ *  The summed cross sections must be positive over the sampled range. */
 typedef struct {
     int n_tab;
     int n_u;                     /* >= 2 */
@@ -136,6 +152,15 @@ typedef struct {
     const double* u_icdf;        /* [n_tab][n_energy][n_u] */
     const double* kalbach_r;     /* [n_tab][n_energy][n_u] */
     const double* kalbach_a;     /* [n_tab][n_energy][n_u] */
+    int n_ni;                    /* elements with sigma_NI P_NI (Z > 1), <= 64 */
+    int n_mu;
+    const int* ni_Z;             /* [n_ni] */
+    const double* ni_sigma_barn; /* [n_ni][n_energy] */
+    const double* ni_p;          /* [n_ni][n_energy][n_mu] */
+    int n_l;                     /* hydrogen partial waves, 0..8 */
+    const double* h_a_re;        /* [n_l][n_energy + 2] */
+    const double* h_a_im;
+    const double* h_b;
 } sde_nuclear_tables;
 
 /* Gaussian pencil beam along +z starting on the entrance face.  Each of its

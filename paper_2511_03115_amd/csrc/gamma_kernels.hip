@@ -255,11 +255,13 @@ __global__ void __launch_bounds__(256) k_gamma_screen(GammaArgs A, unsigned long
             }
         }
     }
+    // same-address atomics serialise in L2: one per wave, and none for a
+    // wave that evaluated nothing (most of a dose map is below threshold)
     ne = wave_sum64(ne);
     np = wave_sum64(np);
-    if (lane == 0) {
+    if (lane == 0 && ne) {
         atomicAdd(&counts[0], ne);
-        atomicAdd(&counts[1], np);
+        if (np) atomicAdd(&counts[1], np);
     }
 }
 
@@ -321,7 +323,9 @@ hipError_t launch_gamma(const double* ref, const double* ev, int nx, int ny, int
     const size_t nvox = (size_t)nx * ny * nz;
     GammaArgs A{ref, ev, nx, ny, nz, interp, dta / interp, dta, dx, dy, dz, dd, thr_abs, max_ref,
                 local, use_bound};
-    hipLaunchKernelGGL(k_gamma_screen, dim3(blocks_for(nvox, 256, 65536)), dim3(256), 0, s, A,
+    // a grid-stride pass over at most 4096 workgroups keeps the counter
+    // atomics few (one per wave that evaluated something)
+    hipLaunchKernelGGL(k_gamma_screen, dim3(blocks_for(nvox, 256, 4096)), dim3(256), 0, s, A,
                        counts, list, cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -29,6 +29,8 @@ struct State {
     MatDev64* mats64 = nullptr;
     double2* hot64 = nullptr;
     double *nuc_sigma64 = nullptr, *nuc_u64 = nullptr, *nuc_r64 = nullptr, *nuc_a64 = nullptr;
+    float *ni_p = nullptr, *ni_cum = nullptr, *ni_sig = nullptr;
+    double *ni_p64 = nullptr, *ni_cum64 = nullptr, *ni_sig64 = nullptr, *h_coef = nullptr;
     // gamma: the counters and the list of voxels to search
     unsigned long long* gam_buf = nullptr;
     unsigned* gam_list = nullptr;
@@ -73,6 +75,13 @@ void release_tables() {
     dfree(g.nuc_u64);
     dfree(g.nuc_r64);
     dfree(g.nuc_a64);
+    dfree(g.ni_p);
+    dfree(g.ni_cum);
+    dfree(g.ni_sig);
+    dfree(g.ni_p64);
+    dfree(g.ni_cum64);
+    dfree(g.ni_sig64);
+    dfree(g.h_coef);
     g.ready = false;
 }
 
@@ -352,6 +361,16 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     kp.nuc_u64 = g.nuc_u64;
     kp.nuc_r64 = g.nuc_r64;
     kp.nuc_a64 = g.nuc_a64;
+    kp.n_ni = T.n_ni;
+    kp.n_mu = T.n_mu;
+    kp.n_l = T.n_l;
+    kp.ni_p = g.ni_p;
+    kp.ni_cum = g.ni_cum;
+    kp.ni_sig = g.ni_sig;
+    kp.ni_p64 = g.ni_p64;
+    kp.ni_cum64 = g.ni_cum64;
+    kp.ni_sig64 = g.ni_sig64;
+    kp.h_coef = g.h_coef;
     // scheme and geometry scalars, in double and rounded to float
     KScal<double>& S = kp.sd;
     S.step = pp.step_cm;
@@ -551,7 +570,10 @@ int sde_init_materials(const sde_material_desc* mats, int n_mats, const sde_phys
         (r = upload(&g.nuc_a, T.nuc_a)) || (r = upload(&g.mats64, T.mats64)) ||
         (r = upload(&g.hot64, T.hot64)) || (r = upload(&g.nuc_sigma64, T.nuc_sigma64)) ||
         (r = upload(&g.nuc_u64, T.nuc_u64)) || (r = upload(&g.nuc_r64, T.nuc_r64)) ||
-        (r = upload(&g.nuc_a64, T.nuc_a64))) {
+        (r = upload(&g.nuc_a64, T.nuc_a64)) || (r = upload(&g.ni_p, T.ni_p)) ||
+        (r = upload(&g.ni_cum, T.ni_cum)) || (r = upload(&g.ni_sig, T.ni_sig)) ||
+        (r = upload(&g.ni_p64, T.ni_p64)) || (r = upload(&g.ni_cum64, T.ni_cum64)) ||
+        (r = upload(&g.ni_sig64, T.ni_sig64)) || (r = upload(&g.h_coef, T.h_coef))) {
         release_tables();
         return r;
     }

@@ -20,6 +20,10 @@ struct HostTables {
     std::vector<MatDev64> mats64;
     std::vector<double2> hot64;
     std::vector<double> nuc_sigma64, nuc_u64, nuc_r64, nuc_a64;
+    // elastic nuclear data
+    int n_ni = 0, n_mu = 0, n_l = 0;
+    std::vector<float> ni_p, ni_cum, ni_sig;
+    std::vector<double> ni_p64, ni_cum64, ni_sig64, h_coef;
     double ruth_T = 0, mott_lo = 0, mott_hi = 0, mott_D0 = 0, mott_Lhi = 0, mott_Llo = 0;
     double mott_Dlo = 0, mott_shi = 0, mott_slo = 0;
     double c_strag = 0;

@@ -30,7 +30,10 @@ struct ElemDev {
     int is_h;        // hydrogen: Mott (identical-particle) cross section
     int tab;         // row of the inelastic tables, -1 if none
     float el_base;   // el_coef without the cut's factor (T - 1/2 for Rutherford; = el_coef for H)
-    int pad1;
+    int ni;          // row of the sigma_NI P_NI tables, -1 if none (hydrogen: -1)
+    float nuc_coef;  // 2 pi N_A w / A 1e-24: nuclear elastic rate / rho per barn of integral
+    int hn;          // hydrogen with partial-wave amplitudes
+    int pad2, pad3;
 };
 
 struct MatDev {
@@ -57,7 +60,8 @@ struct MatDev64 {
     double ln_ca[kMaxElem];   // ln(2.007e-5 Z_i^(2/3))
     double za2[kMaxElem];     // 3.34 (Z_i alpha)^2
     double el_coef[kMaxElem], el_base[kMaxElem], ne_coef[kMaxElem], m2[kMaxElem];
-    int is_h[kMaxElem], tab[kMaxElem];
+    double nuc_coef[kMaxElem];
+    int is_h[kMaxElem], tab[kMaxElem], ni[kMaxElem], hn[kMaxElem];
 };
 
 // Per-spot source data on the device in the stepping precision R.
@@ -105,6 +109,18 @@ struct KParams {
     const double* nuc_u64;
     const double* nuc_r64;
     const double* nuc_a64;
+    // elastic nuclear data (section 2.1.4): sigma_NI P_NI splines in mu per
+    // lattice energy, with their cumulative integrals at the knots
+    // ([n_ni][n_e][n_mu - 2]), and hydrogen's amplitude splines in the
+    // lattice coordinate ([3][n_l][n_e + 2]: Re a_l, Im a_l, b_l)
+    int n_ni, n_mu, n_l, pad7;
+    const float* ni_p;
+    const float* ni_cum;
+    const float* ni_sig;
+    const double* ni_p64;
+    const double* ni_cum64;
+    const double* ni_sig64;
+    const double* h_coef;
     // scheme and geometry scalars per precision
     KScal<float> sf;
     KScal<double> sd;

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "sde_elastic.hpp"
 #include "sde_internal.hpp"
 
 namespace sde {
@@ -503,11 +504,12 @@ __device__ __forceinline__ double ld_time64(const MatDev64& m, const KScal<doubl
 template <class R>
 struct Cut {
     R T, s_hi, D0, Lhi;
+    R cos_r;   // cos of the cut for elements other than hydrogen (nuclear integrals)
 };
 
 template <class R>
 __device__ __forceinline__ Cut<R> fixed_cut(const KScal<R>& S) {
-    return Cut<R>{S.ruth_T, S.mott_shi, S.mott_D0, S.mott_Lhi};
+    return Cut<R>{S.ruth_T, S.mott_shi, S.mott_D0, S.mott_Lhi, S.mott_hi};
 }
 
 // The cut 2.5 sigma for a Lynch-Dahl variance sig2z = sigma^2 at the width's
@@ -523,6 +525,7 @@ __device__ __forceinline__ Cut<R> energy_cut(const KScal<R>& S, R sig2z) {
     polar_cs(R(0.25) * th * th, hc, hs);            // cos, sin of th / 2
     Cut<R> c;
     c.T = R(0.5) * M::rcp(hs * hs);                  // 1 / (1 - cos th)
+    c.cos_r = hc * hc - hs * hs;
     polar_cs(R(0.25) * th_h * th_h, hc, hs);
     const R hs2 = hs * hs, hc2 = hc * hc;
     c.s_hi = R(2) * hs2;                             // 1 - cos th_h
@@ -558,15 +561,194 @@ __device__ __forceinline__ R ld_sig2z(const KParams& P, const KScal<R>& S, const
     }
 }
 
+// ---- elastic nuclear terms (section 2.1.4) ----
+__device__ __forceinline__ int ni_row(const MatDev& m, int e) { return m.el[e].ni; }
+__device__ __forceinline__ int ni_row(const MatDev64& m, int e) { return m.ni[e]; }
+__device__ __forceinline__ int h_nuc(const MatDev& m, int e) { return m.el[e].hn; }
+__device__ __forceinline__ int h_nuc(const MatDev64& m, int e) { return m.hn[e]; }
+__device__ __forceinline__ float nuc_coef(const MatDev& m, int e) { return m.el[e].nuc_coef; }
+__device__ __forceinline__ double nuc_coef(const MatDev64& m, int e) { return m.nuc_coef[e]; }
+
+template <class R>
+struct NiTab {
+    const R *p, *cum, *sig;
+};
+__device__ __forceinline__ NiTab<float> ni_of(const KParams& P, float) {
+    return NiTab<float>{P.ni_p, P.ni_cum, P.ni_sig};
+}
+__device__ __forceinline__ NiTab<double> ni_of(const KParams& P, double) {
+    return NiTab<double>{P.ni_p64, P.ni_cum64, P.ni_sig64};
+}
+
+// sigma_NI P_NI of table row t at lattice position (li, lf) and cosine x:
+// its density and its integral from -1 to x, linear in the lattice
+// coordinate between the two lattice energies.
+template <class R>
+__device__ __forceinline__ void ni_term(const KParams& P, int t, int li, R lf, R x, R& dens,
+                                        R& integ) {
+    const NiTab<R> T = ni_of(P, R(0));
+    const int m = P.n_mu - 3;
+    const size_t r0 = (size_t)t * P.n_e + li;
+    R d0, i0, d1, i1;
+    ni_spline(T.p + r0 * P.n_mu, T.cum + r0 * (P.n_mu - 2), m, x, d0, i0);
+    ni_spline(T.p + (r0 + 1) * P.n_mu, T.cum + (r0 + 1) * (P.n_mu - 2), m, x, d1, i1);
+    const R s0 = T.sig[r0], s1 = T.sig[r0 + 1];
+    dens = (R(1) - lf) * s0 * d0 + lf * s1 * d1;
+    integ = (R(1) - lf) * s0 * i0 + lf * s1 * i1;
+}
+
+// What the out-of-line hydrogen functions read, passed by value (a reference
+// to the kernel's argument block cannot leave the kernel).
+struct HTab {
+    const double* coef;   // [3][n_l][n_e + 2]
+    int n_l, n_e;
+    double ln_e_lo, inv_dln, eta_pre;
+};
+__device__ __forceinline__ HTab h_tab(const KParams& P) {
+    return HTab{P.h_coef, P.n_l, P.n_e, P.sd.ln_e_lo, P.sd.inv_dln, P.sd.eta_pre};
+}
+
+// Hydrogen's amplitudes at lattice coordinate tl (cubic B-splines, knots at
+// the lattice points).
+__device__ __forceinline__ HAmp h_amp(const HTab& P, double tl) {
+    HAmp a;
+    a.n_l = P.n_l;
+    const int m = P.n_e - 1;
+    double t = fmin(fmax(tl, 0.0), (double)m);
+    int k = (int)floor(t);
+    if (k > m - 1) k = m - 1;
+    const double u = t - k, v = 1.0 - u;
+    const double B0 = v * v * v / 6.0, B1 = (3.0 * u * u * u - 6.0 * u * u + 4.0) / 6.0,
+                 B2 = (-3.0 * u * u * u + 3.0 * u * u + 3.0 * u + 1.0) / 6.0, B3 = u * u * u / 6.0;
+    const size_t nc = (size_t)P.n_l * (P.n_e + 2);
+    for (int l = 0; l < P.n_l; ++l) {
+        const double* c = P.coef + (size_t)l * (P.n_e + 2) + k;
+        a.are[l] = c[0] * B0 + c[1] * B1 + c[2] * B2 + c[3] * B3;
+        a.aim[l] = c[nc] * B0 + c[nc + 1] * B1 + c[nc + 2] * B2 + c[nc + 3] * B3;
+        a.b[l] = c[2 * nc] * B0 + c[2 * nc + 1] * B1 + c[2 * nc + 2] * B2 + c[2 * nc + 3] * B3;
+    }
+    return a;
+}
+
+// Integral (barn) of hydrogen's nuclear term over [lo, hi] at energy E,
+// in double precision (its antiderivative cancels strongly); out of line.
+__device__ __noinline__ double h_bracket64(HTab P, double E, double hi, double lo) {
+    if (!(hi > lo)) return 0.0;
+    const double tl = (log(E) - P.ln_e_lo) * P.inv_dln;
+    const HAmp a = h_amp(P, tl);
+    const double eta = P.eta_pre / sqrt(E);
+    double d, g1, g0;
+    h_nuclear(a, eta, hi, d, g1);
+    h_nuclear(a, eta, lo, d, g0);
+    return g1 - g0;
+}
+
+// The CM cosine's s = 1 - mu of a hydrogen elastic jump with the nuclear
+// term: the distribution function of the summed cross section,
+// ab G_mott(s) + nc G_N(1 - s) (ab = the Mott coefficient / E^2, nc = the
+// nuclear coefficient), inverted over [s_hi, s_lo] by Newton's method in
+// double precision kept inside a shrinking bracket; out of line.
+__device__ __noinline__ double h_invert64(HTab P, double E, double ab, double nc, double s_hi,
+                                          double s_lo, double U) {
+    const double tl = (log(E) - P.ln_e_lo) * P.inv_dln;
+    const HAmp A = h_amp(P, tl);
+    const double eta = P.eta_pre / sqrt(E), inv_2eta = 0.5 / eta;
+    auto G = [&](double s, double& dG) {
+        double gm, dgm, dn, gn;
+        mott_G_dG(eta, inv_2eta, s, gm, dgm);
+        h_nuclear(A, eta, 1.0 - s, dn, gn);
+        dG = ab * dgm - nc * dn;
+        return ab * gm + nc * gn;
+    };
+    double d;
+    const double G0 = G(s_lo, d), G1 = G(s_hi, d);
+    const double tgt = G0 + U * (G1 - G0);
+    double a = s_hi, b = s_lo, s = 0.5 * (s_hi + s_lo);
+    for (int it = 0; it < 80; ++it) {
+        double dG;
+        const double g = G(s, dG) - tgt;
+        if (g > 0.0) a = s; else b = s;
+        double nx = s - g / dG;
+        if (!(nx > a && nx < b)) nx = 0.5 * (a + b);
+        const double step = fabs(nx - s);
+        s = nx;
+        if (step <= 1e-15 * s || !(b > a)) break;
+    }
+    return s;
+}
+
+// The same for an element other than hydrogen with sigma_NI P_NI:
+// ab (1/s - 1/2) + nc NI(1 - s) over [s_c, 2], in the stepping precision.
+template <class R>
+__device__ R ni_invert(const KParams& P, int t, int li, R lf, R ab, R nc, R s_c, R U) {
+    using M = RM<R>;
+    constexpr R tol = M::f64 ? R(1e-15) : R(2.5e-7);
+    constexpr int max_it = M::f64 ? 80 : 40;
+    auto G = [&](R s, R& dG) {
+        R dn, in;
+        ni_term(P, t, li, lf, R(1) - s, dn, in);
+        dG = -(ab * M::rcp(s * s) + nc * dn);
+        return ab * (M::rcp(s) - R(0.5)) + nc * in;
+    };
+    R d;
+    const R tgt = U * G(s_c, d);
+    R a = s_c, b = R(2), s = fmin(s_c * R(2), R(1));
+    for (int it = 0; it < max_it; ++it) {
+        R dG;
+        const R g = G(s, dG) - tgt;
+        if (g > R(0)) a = s; else b = s;
+        R nx = s - g / dG;
+        if (!(nx > a && nx < b)) nx = R(0.5) * (a + b);
+        const R step = fabs(nx - s);
+        s = nx;
+        if (step <= tol * s || !(b > a)) break;
+    }
+    return s;
+}
+
+// Nuclear elastic rate / rho of element e at E with the cut c: nc times the
+// integral of its nuclear term over the law's range; hbr: hydrogen's
+// bracket, computed once per medium by the caller.
+template <class R, class Mat>
+__device__ __forceinline__ R nuclear_rate(const KParams& P, const Mat& md, int e, int li, R lf,
+                                          const Cut<R>& c, R hbr) {
+    const int t = ni_row(md, e);
+    if (t >= 0) {
+        R d, in;
+        ni_term(P, t, li, lf, c.cos_r, d, in);
+        return nuc_coef(md, e) * in;
+    }
+    if (h_nuc(md, e)) return nuc_coef(md, e) * hbr;
+    return R(0);
+}
+
+// Sum over the medium's elements of the nuclear elastic rates / rho at E
+// with the cut c (0 without nuclear data).
+template <class R, class Mat>
+__device__ __forceinline__ R nuclear_sum(const KParams& P, const KScal<R>& S, const Mat& md, R E,
+                                         int li, R lf, const Cut<R>& c) {
+    R sum = R(0);
+    if (P.n_ni == 0 && P.n_l == 0) return sum;
+    for (int e = 0; e < n_elem(md); ++e) {
+        R hbr = R(0);
+        if (h_nuc(md, e))
+            hbr = (R)h_bracket64(h_tab(P), (double)E, 1.0 - (double)c.s_hi, (double)S.mott_lo);
+        sum += nuclear_rate(P, md, e, li, lf, c, hbr);
+    }
+    return sum;
+}
+
 // Rate of channel (element e, elastic or inelastic) per cm at E; ecut: the
 // elastic coefficient at the cut c instead of the fixed one.
-template <class R, class Mat>
+template <bool NUC, class R, class Mat>
 __device__ __forceinline__ R channel_rate(const KParams& P, const Nuc<R>& nu, const Mat& m, int e,
                                           bool inel, R rho, R inv_e2, R mott, int li, R lf,
-                                          bool ecut, const Cut<R>& c) {
+                                          bool ecut, const Cut<R>& c, R hbr) {
     if (!inel) {
-        if (is_h(m, e)) return rho * el_coef(m, e) * inv_e2 * mott;
-        return rho * (ecut ? el_base(m, e) * (c.T - R(0.5)) : el_coef(m, e)) * inv_e2;
+        R nuc = R(0);
+        if constexpr (NUC) nuc = nuclear_rate(P, m, e, li, lf, c, hbr);
+        if (is_h(m, e)) return rho * (el_coef(m, e) * inv_e2 * mott + nuc);
+        return rho * ((ecut ? el_base(m, e) * (c.T - R(0.5)) : el_coef(m, e)) * inv_e2 + nuc);
     }
     return rho * ne_coef(m, e) * lerp_row(nu.sigma + (size_t)tab_of(m, e) * P.n_e, li, lf);
 }
@@ -575,8 +757,10 @@ __device__ __forceinline__ R channel_rate(const KParams& P, const Nuc<R>& nu, co
 // Eq. (Npi): channel by its rate, CM cosine from its law (closed-form
 // Rutherford inverse, Mott by Newton, Kalbach-Mann inverse), CM -> lab by
 // Eq. (cm_to_lab).  Outputs the loss fraction u (0 for elastic), the lab
-// polar (cos, sin) and the azimuth (cos, sin).
-template <class R, class Mat>
+// polar (cos, sin) and the azimuth (cos, sin).  NUC: the instance carries the
+// elastic nuclear terms (the general and FP64 instances; the method's own
+// instances are launched only without such data).
+template <bool NUC, class R, class Mat>
 __device__ void jump(const KParams& P, const KScal<R>& S, const float4* tab, const Mat& md,
                      int mat, R E, R rho, uint4 q, R& u_loss, R& jc, R& js, R& jcp, R& jsp,
                      unsigned flags) {
@@ -592,24 +776,31 @@ __device__ void jump(const KParams& P, const KScal<R>& S, const float4* tab, con
     const Cut<R> cut = (el && ecut) ? energy_cut(S, ld_sig2z(P, S, tab, mat, rho, E, li, lf))
                                     : fixed_cut(S);
     const int nel = n_elem(md);
-    R mott = R(0);
+    R mott = R(0), hbr = R(0);
     if (el && c_mott(md) != R(0)) mott = mott_bracket(S, cut, eta);
+    if constexpr (NUC)
+        if (el && P.n_l > 0)   // hydrogen's nuclear bracket, once
+            for (int e = 0; e < nel; ++e)
+                if (h_nuc(md, e))
+                    hbr = (R)h_bracket64(h_tab(P), (double)E, 1.0 - (double)cut.s_hi,
+                                     (double)S.mott_lo);
     R tot = R(0);
     for (int e = 0; e < nel; ++e) {
-        if (el) tot += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf, ecut, cut);
+        if (el)
+            tot += channel_rate<NUC>(P, nu, md, e, false, rho, inv_e2, mott, li, lf, ecut, cut, hbr);
         if (ne && tab_of(md, e) >= 0)
-            tot += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf, ecut, cut);
+            tot += channel_rate<NUC>(P, nu, md, e, true, rho, inv_e2, mott, li, lf, ecut, cut, hbr);
     }
     const R target = u_hi<R>(q.x) * tot;
     R acc = R(0);
     int ce = -1, cin = 0;
     for (int e = 0; e < nel && ce < 0; ++e) {
         if (el) {
-            acc += channel_rate(P, nu, md, e, false, rho, inv_e2, mott, li, lf, ecut, cut);
+            acc += channel_rate<NUC>(P, nu, md, e, false, rho, inv_e2, mott, li, lf, ecut, cut, hbr);
             if (target < acc) { ce = e; cin = 0; break; }
         }
         if (ne && tab_of(md, e) >= 0) {
-            acc += channel_rate(P, nu, md, e, true, rho, inv_e2, mott, li, lf, ecut, cut);
+            acc += channel_rate<NUC>(P, nu, md, e, true, rho, inv_e2, mott, li, lf, ecut, cut, hbr);
             if (target < acc) { ce = e; cin = 1; break; }
         }
     }
@@ -621,8 +812,24 @@ __device__ void jump(const KParams& P, const KScal<R>& S, const float4* tab, con
     u_loss = R(0);
     if (!cin) {
         const R U = u_hi<R>(q.y);
-        if (is_h(md, ce)) {
+        if (NUC && is_h(md, ce) && h_nuc(md, ce)) {
+            // Mott + nuclear term: the summed law in double precision
+            double sm = 0.0;
+            if constexpr (NUC) sm = h_invert64(h_tab(P), (double)E, (double)(el_coef(md, ce) * inv_e2),
+                                         (double)nuc_coef(md, ce), (double)cut.s_hi,
+                                         (double)S.mott_slo, (double)U);
+            cmc = (R)(1.0 - sm);
+            cms = (R)sqrt(fmax(0.0, sm * (2.0 - sm)));
+        } else if (is_h(md, ce)) {
             const R sm = mott_invert(cut.s_hi, S.mott_slo, eta, U);   // 1 - mu
+            cmc = R(1) - sm;
+            cms = M::sqx(fmax(R(0), sm * (R(2) - sm)));
+        } else if (NUC && ni_row(md, ce) >= 0) {
+            // Rutherford + sigma_NI P_NI: the summed law
+            const R ab = el_base(md, ce) * inv_e2;
+            R sm = R(1);
+            if constexpr (NUC)
+                sm = ni_invert(P, ni_row(md, ce), li, lf, ab, nuc_coef(md, ce), R(1) / cut.T, U);
             cmc = R(1) - sm;
             cms = M::sqx(fmax(R(0), sm * (R(2) - sm)));
         } else {
@@ -722,8 +929,10 @@ __device__ __forceinline__ const SpotDev64& spot_at(const KParams& P, int i, dou
 
 // kFixed != 0: the physics switches are that compile-time constant (the
 // method, with either small-angle sampler), so their tests fold away; 0:
-// read them from P.flags.
-template <class R, unsigned kFixed>
+// read them from P.flags.  kNuc: the elastic nuclear terms are compiled in
+// (their double-precision hydrogen functions are out of line, and the calls
+// cost registers, so only the instances launched with such data have them).
+template <class R, unsigned kFixed, bool kNuc>
 __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     using M = RM<R>;
     const KScal<R>& S = scal<R>(P);
@@ -876,11 +1085,11 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 const uint4 q = philox((uint32_t)h, (uint32_t)(h >> 32), nj, 1u, k0, k1);
                 R u_loss, jc, js, jcp, jsp;
                 if constexpr (M::f64)
-                    jump(P, S, tab, P.mats64[matj], matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp,
-                         flags);
+                    jump<kNuc>(P, S, tab, P.mats64[matj], matj, ej, rhoj, q, u_loss, jc,
+                                       js, jcp, jsp, flags);
                 else
-                    jump(P, S, tab, P.mats[matj], matj, ej, rhoj, q, u_loss, jc, js, jcp, jsp,
-                         flags);
+                    jump<kNuc>(P, S, tab, P.mats[matj], matj, ej, rhoj, q, u_loss, jc,
+                                       js, jcp, jsp, flags);
                 // E holds E' (after continuous loss); the jump removes u E'
                 const R En = E * (R(1) - u_loss);
                 l_nuc += fixp(E, wsc) - fixp(En, wsc);
@@ -987,6 +1196,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 // the cut 2.5 sigma(E) at this step's medium and density
                 const Cut<R> cut = energy_cut(S, ld_sig2z(P, S, tab, mat, rho, E, li, lf));
                 R el, ne_rate;
+                R nucl;
                 if constexpr (M::f64) {
                     const MatDev64& md = P.mats64[mat];
                     el = md.c_ruth0 * (cut.T - 0.5);
@@ -995,14 +1205,17 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                     const double2 ha = P.hot64[(size_t)mat * P.n_e + li];
                     const double2 hb = P.hot64[(size_t)mat * P.n_e + li + 1];
                     ne_rate = ::fma(lf, hb.x - ha.x, ha.x);
+                    nucl = nuclear_sum(P, S, md, E, li, lf, cut);
                 } else {
                     const MatDev& md = P.mats[mat];
                     el = md.c_ruth0 * (cut.T - 0.5f);
                     if (md.c_mott != 0.0f)
                         el += md.c_mott * mott_bracket(S, cut, S.eta_pre * M::rsq(E));
                     ne_rate = fmaf(lf, tb.z - ta.z, ta.z);
+                    nucl = R(0);
+                    if constexpr (kNuc) nucl = nuclear_sum(P, S, md, E, li, lf, cut);
                 }
-                rate = el / (E * E) + ((flags & kInelastic) ? ne_rate : R(0));
+                rate = el / (E * E) + nucl + ((flags & kInelastic) ? ne_rate : R(0));
             } else if constexpr (M::f64) {
                 const MatDev64& md = P.mats64[mat];
                 const double2 ha = P.hot64[(size_t)mat * P.n_e + li];
@@ -1012,7 +1225,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                     R el = md.c_ruth;
                     if (md.c_mott != 0.0)
                         el += md.c_mott * mott_bracket(S, fixed_cut(S), S.eta_pre / ::sqrt(E));
-                    rate += el / (E * E);
+                    rate += el / (E * E) + nuclear_sum(P, S, md, E, li, lf, fixed_cut(S));
                 }
                 if (flags & kInelastic) rate += ::fma(lf, hb.x - ha.x, ha.x);
             } else {
@@ -1302,10 +1515,11 @@ hipError_t launch_reset(unsigned long long* tally, size_t nvox, unsigned long lo
 }
 
 hipError_t transport_kernel_attributes(size_t lds_bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<float, kMethod>),
-                         reinterpret_cast<const void*>(&k_transport<float, kMethodGeodesic>),
-                         reinterpret_cast<const void*>(&k_transport<float, 0u>),
-                         reinterpret_cast<const void*>(&k_transport<double, 0u>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&k_transport<float, kMethod, false>),
+                         reinterpret_cast<const void*>(&k_transport<float, kMethodGeodesic, false>),
+                         reinterpret_cast<const void*>(&k_transport<float, 0u, false>),
+                         reinterpret_cast<const void*>(&k_transport<float, 0u, true>),
+                         reinterpret_cast<const void*>(&k_transport<double, 0u, true>)};
     for (const void* f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
@@ -1317,15 +1531,20 @@ hipError_t transport_kernel_attributes(size_t lds_bytes) {
 hipError_t launch_transport(const KParams& p, int grid, int block, size_t lds_bytes,
                             hipStream_t s) {
     if (p.fp64)
-        hipLaunchKernelGGL((k_transport<double, 0u>), dim3(grid), dim3(block), lds_bytes, s, p);
-    else if (p.flags == kMethod)
-        hipLaunchKernelGGL((k_transport<float, kMethod>), dim3(grid), dim3(block), lds_bytes, s,
+        hipLaunchKernelGGL((k_transport<double, 0u, true>), dim3(grid), dim3(block), lds_bytes, s,
                            p);
+    else if (p.n_ni > 0 || p.n_l > 0)   // elastic nuclear data
+        hipLaunchKernelGGL((k_transport<float, 0u, true>), dim3(grid), dim3(block), lds_bytes, s,
+                           p);
+    else if (p.flags == kMethod)
+        hipLaunchKernelGGL((k_transport<float, kMethod, false>), dim3(grid), dim3(block),
+                           lds_bytes, s, p);
     else if (p.flags == kMethodGeodesic)
-        hipLaunchKernelGGL((k_transport<float, kMethodGeodesic>), dim3(grid), dim3(block),
+        hipLaunchKernelGGL((k_transport<float, kMethodGeodesic, false>), dim3(grid), dim3(block),
                            lds_bytes, s, p);
     else
-        hipLaunchKernelGGL((k_transport<float, 0u>), dim3(grid), dim3(block), lds_bytes, s, p);
+        hipLaunchKernelGGL((k_transport<float, 0u, false>), dim3(grid), dim3(block), lds_bytes, s,
+                           p);
     return hipGetLastError();
 }
 

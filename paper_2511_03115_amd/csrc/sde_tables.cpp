@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "sde.h"
+#include "sde_elastic.hpp"
 #include "sde_host.hpp"
 #include "sde_internal.hpp"
 
@@ -192,6 +193,67 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         T.nuc_a64.assign(2, 0.0);
     }
 
+    // elastic nuclear data (section 2.1.4)
+    const bool use_ni = nuc && nuc->n_ni > 0, use_h = nuc && nuc->n_l > 0;
+    if (nuc && (nuc->n_ni < 0 || nuc->n_ni > 64 || nuc->n_l < 0 || nuc->n_l > kMaxL ||
+                (use_ni && (!nuc->ni_Z || !nuc->ni_sigma_barn || !nuc->ni_p || nuc->n_mu < 7 ||
+                            nuc->n_mu > 256)) ||
+                (use_h && (!nuc->h_a_re || !nuc->h_a_im || !nuc->h_b)))) {
+        *err = "invalid elastic nuclear tables";
+        return SDE_E_INVALID;
+    }
+    if (use_ni) {
+        T.n_ni = nuc->n_ni;
+        T.n_mu = nuc->n_mu;
+        const int m = T.n_mu - 3;
+        const double hk = 2.0 / m;
+        const size_t nrow = (size_t)T.n_ni * T.n_e;
+        T.ni_p64.assign(nuc->ni_p, nuc->ni_p + nrow * T.n_mu);
+        T.ni_sig64.assign(nuc->ni_sigma_barn, nuc->ni_sigma_barn + nrow);
+        T.ni_cum64.assign(nrow * (m + 1), 0.0);
+        for (size_t r = 0; r < nrow; ++r) {
+            if (!(T.ni_sig64[r] >= 0)) { *err = "negative sigma_NI"; return SDE_E_INVALID; }
+            const double* c = &T.ni_p64[r * T.n_mu];
+            double* cum = &T.ni_cum64[r * (m + 1)];
+            for (int k = 0; k < m; ++k)   // a full knot interval: h (c_k + 11 c_k+1 + 11 c_k+2 + c_k+3) / 24
+                cum[k + 1] = cum[k] + hk * (c[k] + 11.0 * c[k + 1] + 11.0 * c[k + 2] + c[k + 3]) / 24.0;
+        }
+        T.ni_p.assign(T.ni_p64.begin(), T.ni_p64.end());
+        T.ni_cum.assign(T.ni_cum64.begin(), T.ni_cum64.end());
+        T.ni_sig.assign(T.ni_sig64.begin(), T.ni_sig64.end());
+    } else {
+        T.ni_p.assign(1, 0.f);
+        T.ni_cum.assign(1, 0.f);
+        T.ni_sig.assign(1, 0.f);
+        T.ni_p64.assign(1, 0.0);
+        T.ni_cum64.assign(1, 0.0);
+        T.ni_sig64.assign(1, 0.0);
+    }
+    if (use_h) {
+        T.n_l = nuc->n_l;
+        const size_t nc = (size_t)T.n_l * (T.n_e + 2);
+        T.h_coef.resize(3 * nc);
+        std::copy(nuc->h_a_re, nuc->h_a_re + nc, T.h_coef.begin());
+        std::copy(nuc->h_a_im, nuc->h_a_im + nc, T.h_coef.begin() + nc);
+        std::copy(nuc->h_b, nuc->h_b + nc, T.h_coef.begin() + 2 * nc);
+    } else {
+        T.h_coef.assign(1, 0.0);
+    }
+    // hydrogen amplitudes at lattice point i (the spline at an integer
+    // lattice coordinate: (c_i + 4 c_i+1 + c_i+2) / 6)
+    auto h_amp_at = [&](int i) {
+        HAmp a{};
+        a.n_l = T.n_l;
+        const size_t nc = (size_t)T.n_l * (T.n_e + 2);
+        for (int l = 0; l < T.n_l; ++l) {
+            const double* c = &T.h_coef[(size_t)l * (T.n_e + 2) + i];
+            a.are[l] = (c[0] + 4.0 * c[1] + c[2]) / 6.0;
+            a.aim[l] = (c[nc] + 4.0 * c[nc + 1] + c[nc + 2]) / 6.0;
+            a.b[l] = (c[2 * nc] + 4.0 * c[2 * nc + 1] + c[2 * nc + 2]) / 6.0;
+        }
+        return a;
+    };
+
     const Gauss G;
     T.hot.resize((size_t)n_mats * T.n_e);
     T.hot64.resize((size_t)n_mats * T.n_e);
@@ -269,14 +331,45 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             m64.m2[i] = A * kAmu;
             m64.is_h[i] = e.is_h;
             m64.tab[i] = e.tab;
+            // elastic nuclear terms: rate / rho per barn of CM integral
+            const double nuc_coef = 2.0 * M_PI * nd * 1e-24;
+            e.nuc_coef = (float)nuc_coef;
+            m64.nuc_coef[i] = nuc_coef;
+            e.ni = -1;
+            if (use_ni && !e.is_h)
+                for (int t = 0; t < nuc->n_ni; ++t)
+                    if (nuc->ni_Z[t] == d.Z[i]) e.ni = t;
+            e.hn = (e.is_h && use_h) ? 1 : 0;
+            m64.ni[i] = e.ni;
+            m64.hn[i] = e.hn;
         }
 
-        // elastic rate per unit density times E^2 at En
-        auto el_e2_at = [&](double En) {
+        // elastic rate per unit density times E^2 at lattice point li (the
+        // Coulomb parts, and the nuclear terms at the fixed cut)
+        auto el_e2_at = [&](int li) {
+            const double En = E[li];
             const double eta = kAlpha * std::sqrt(kMp / (2.0 * En));
             const double mott = T.mott_D0 - (std::sin(eta * T.mott_Lhi) -
                                              std::sin(eta * T.mott_Llo)) / (2.0 * eta);
-            return (p->flags & SDE_ELASTIC) ? c_ruth_d + c_mott_d * mott : 0.0;
+            if (!(p->flags & SDE_ELASTIC)) return 0.0;
+            double r = c_ruth_d + c_mott_d * mott, nucl = 0.0;
+            for (int i = 0; i < m.n; ++i) {
+                const ElemDev& e = md.el[i];
+                if (e.ni >= 0) {
+                    const size_t row = (size_t)e.ni * T.n_e + li;
+                    double dens, integ;
+                    ni_spline(&T.ni_p64[row * T.n_mu], &T.ni_cum64[row * (T.n_mu - 2)],
+                              T.n_mu - 3, T.mott_hi, dens, integ);
+                    nucl += m64.nuc_coef[i] * T.ni_sig64[row] * integ;
+                } else if (e.hn) {
+                    const HAmp a = h_amp_at(li);
+                    double d0, d1, g0, g1;
+                    h_nuclear(a, eta, T.mott_hi, d1, g1);
+                    h_nuclear(a, eta, T.mott_lo, d0, g0);
+                    nucl += m64.nuc_coef[i] * (g1 - g0);
+                }
+            }
+            return r + nucl * En * En;
         };
         // inelastic rate per unit density at lattice point li
         auto ne_rate_at = [&](int li) {
@@ -300,9 +393,10 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
             h.x = (float)(c2 / (1.0 + Fp * Fp) * p->step_cm / p->ld_z_cm);
             h.y = (float)(c2 / (2.0 * ca2 * (1.0 - Fp)));
             h.z = (float)ne_rate_at(i);
-            h.w = (float)el_e2_at(E[i]);
+            const double el_e2 = el_e2_at(i);
+            h.w = (float)el_e2;
             T.hot[(size_t)k * T.n_e + i] = h;
-            T.hot64[(size_t)k * T.n_e + i] = make_double2(ne_rate_at(i), el_e2_at(E[i]));
+            T.hot64[(size_t)k * T.n_e + i] = make_double2(ne_rate_at(i), el_e2);
             double2 r;
             r.x = Rg;
             r.y = E[i] / stopping(m, E[i]) * T.dln;   // dRg / dt, t the lattice coordinate

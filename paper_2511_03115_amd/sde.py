@@ -54,7 +54,11 @@ class PhysicsParams(C.Structure):
 class NuclearTables(C.Structure):
     _fields_ = [("n_tab", C.c_int), ("n_u", C.c_int), ("Z", C.POINTER(C.c_int)),
                 ("sigma_barn", C.POINTER(C.c_double)), ("u_icdf", C.POINTER(C.c_double)),
-                ("kalbach_r", C.POINTER(C.c_double)), ("kalbach_a", C.POINTER(C.c_double))]
+                ("kalbach_r", C.POINTER(C.c_double)), ("kalbach_a", C.POINTER(C.c_double)),
+                ("n_ni", C.c_int), ("n_mu", C.c_int), ("ni_Z", C.POINTER(C.c_int)),
+                ("ni_sigma_barn", C.POINTER(C.c_double)), ("ni_p", C.POINTER(C.c_double)),
+                ("n_l", C.c_int), ("h_a_re", C.POINTER(C.c_double)),
+                ("h_a_im", C.POINTER(C.c_double)), ("h_b", C.POINTER(C.c_double))]
 
 
 class SpotS(C.Structure):
@@ -172,6 +176,21 @@ def init_materials(materials: Sequence, params, nuclear=None) -> None:
         nt = NuclearTables(len(Z), int(nuclear.n_u), Z.ctypes.data_as(C.POINTER(C.c_int)),
                            sg.ctypes.data_as(d), ui.ctypes.data_as(d), kr.ctypes.data_as(d),
                            ka.ctypes.data_as(d))
+        el = getattr(nuclear, "elastic", None)
+        if el is not None:
+            nZ = np.ascontiguousarray(el.ni_Z, dtype=np.int32)
+            ns = np.ascontiguousarray(el.ni_sigma, dtype=np.float64)
+            npp = np.ascontiguousarray(el.ni_p, dtype=np.float64)
+            ha = np.ascontiguousarray(el.h_are, dtype=np.float64)
+            hi = np.ascontiguousarray(el.h_aim, dtype=np.float64)
+            hb = np.ascontiguousarray(el.h_b, dtype=np.float64)
+            keep += [nZ, ns, npp, ha, hi, hb]
+            nt.n_ni, nt.n_mu = len(nZ), int(npp.shape[-1]) if len(nZ) else 0
+            nt.ni_Z = nZ.ctypes.data_as(C.POINTER(C.c_int))
+            nt.ni_sigma_barn, nt.ni_p = ns.ctypes.data_as(d), npp.ctypes.data_as(d)
+            nt.n_l = int(ha.shape[0])
+            nt.h_a_re, nt.h_a_im, nt.h_b = ha.ctypes.data_as(d), hi.ctypes.data_as(d), \
+                hb.ctypes.data_as(d)
     _check(lib.sde_init_materials(arr, len(materials), C.byref(pp),
                                   C.byref(nt) if nt is not None else None))
 

@@ -19,7 +19,9 @@ def lib():
         from paper_2511_03115_amd import build
         build.build()
     import torch  # noqa: F401  (one HIP runtime per process: torch's, loaded first)
-    return C.CDLL(LIB)
+    lib = C.CDLL(LIB)
+    lib.sde_last_error.restype = C.c_char_p
+    return lib
 
 
 def declared_functions():
@@ -140,7 +142,7 @@ def test_nn_layer_alignment_is_checked_without_gpu(lib):
     ok, bad = V(0x10000), V(0x10002)
     assert lib.sde_nn_conv3d_fwd(bad, ok, None, 1, 2, 2, 2, 16, 16, F(0.01), 1, ok, None) == \
         sde.E_INVALID
-    assert b"aligned" in C.string_at(lib.sde_last_error())
+    assert b"aligned" in lib.sde_last_error()
     assert lib.sde_nn_conv3d_fwd(ok, ok, None, 1, 2, 2, 2, 16, 16, F(0.01), 1, bad, None) == \
         sde.E_INVALID
     assert lib.sde_nn_conv3d_dgrad(ok, bad, 1, 2, 2, 2, 16, 16, ok, ok, Z(1 << 20)) == \
