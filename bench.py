@@ -23,17 +23,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "proton histories/s @150 MeV water; time-to-gamma≥95% denoised vs plain"
-# MI355X issue capacity for non-packed 32-bit VALU work: 256 CUs x 4 SIMDs x
+# MI355X issue capacity for full-rate 32-bit VALU work: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz, in lane-operations per second.
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
-# Algorithmic work of one Euler-Maruyama step in VALU issue slots: the
-# straight path of a step (voxel and table lookup, one Philox4x32-10 block,
-# Bethe loss, straggling, jump test, midpoint deposit, move, Lynch-Dahl
-# width and the spherical Brownian motion turn at small t, renormalisation),
-# counted operation by operation with quarter-rate operations
-# (transcendentals, 32x32->64 products) weighted by 4.  The breakdown is in
-# the design notes.
-STEP_SLOTS = 396
+# Algorithmic work of one Euler-Maruyama step in full-rate VALU issue slots:
+# the straight path of a step (voxel and table lookup, one Philox4x32-10
+# block, Bethe loss, straggling, jump test, midpoint deposit, move,
+# Lynch-Dahl width and the spherical Brownian motion turn at small t,
+# renormalisation), counted operation by operation: 244 full-rate
+# operations, 18 transcendentals (log, rcp, rsq, sqrt, sin, cos), weighted 2
+# (gfx950's transcendental unit issues 8 lanes per SIMD per clock), and the
+# Philox round's 20 32x32->64 products, weighted 1 (v_mad_u64_u32 issues at
+# the full rate).  The microbenchmarks below measure both weights.  The
+# breakdown is in the design notes.
+STEP_FULL, STEP_TRANS, STEP_MUL64 = 244, 18, 20
+TRANS_WEIGHT, MUL64_WEIGHT = 2, 1
+STEP_SLOTS = STEP_FULL + TRANS_WEIGHT * STEP_TRANS + MUL64_WEIGHT * STEP_MUL64   # 300
+# global int64 atomics per launch of the water workload (rocprofv3
+# TCC_ATOMIC_sum of the committed counter summary), for the atomic roof
+ATOMICS_FILE = os.path.join(ROOT, "profiles", "k_transport_water150_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2511_03115_amd", "csrc", "sde_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_transport_water150_traffic.json")
 
@@ -55,6 +63,8 @@ def parse():
                     help="skip the time-to-gamma leg (plain SDE vs denoised, plan at 2 mm)")
     ap.add_argument("--no-hetero", action="store_true",
                     help="skip the heterogeneous-phantom leg (slab and insert, 100/150 MeV)")
+    ap.add_argument("--no-roofs", action="store_true",
+                    help="skip the microbenchmarks of the transport's ingredients")
     ap.add_argument("--no-geodesic", action="store_true",
                     help="skip the leg timing the geodesic Gaussian small-angle step")
     return ap.parse_args()
@@ -145,6 +155,22 @@ def measured_traffic(launch, histories):
             t.get("launch") != launch:
         return None
     return t.get("bytes_per_launch")
+
+
+def measured_atomics(launch, histories):
+    """Global int64 atomics per launch (rocprofv3 TCC_ATOMIC_sum) from the
+    committed counter summary, if taken on the current kernel source, launch
+    and size."""
+    import hashlib
+    try:
+        t = json.load(open(ATOMICS_FILE))
+    except (OSError, ValueError):
+        return None
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if t.get("kernel_sha256") != src or t.get("histories") != histories or \
+            t.get("launch") != launch:
+        return None
+    return t.get("tcc_atomic_per_launch")
 
 
 def plan_leg(steps: int, stream) -> dict:
@@ -390,6 +416,28 @@ def main():
                      "units_per_launch": steps_per_launch},
     }
     plan.close()
+    if not a.no_roofs:
+        # the transport's ingredients timed alone: the measured FMA issue
+        # rate beside the derived peak, the quarter-rate weights and the
+        # atomic and HBM ceilings
+        print("[bench] microbenchmarks (VALU, atomics, HBM)", flush=True)
+        from paper_2511_03115_amd import roofs
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        out["roofs"] = roofs.measure_roofs(n_cu)
+        pm = out["roofs"]["fma_lane_ops_s"]
+        out["roofline"]["peak_measured"] = pm
+        out["roofline"]["frac_measured"] = achieved / pm
+        out["roofline"]["weights_measured"] = {
+            "transcendental": min(out["roofs"][f"{k}_slots"] for k in roofs.TRANS_NAMES),
+            "mul64": out["roofs"]["mul64_slots"]}
+        # the second roof: the tally's global int64 atomics against the
+        # measured random-address atomic rate
+        atom = measured_atomics(launch, n)
+        if atom:
+            rate = atom / (kms * 1e-3)
+            top = out["roofs"]["global_atomic64_random_2MiB_per_s"]
+            out["roofline"]["atomics"] = {"per_launch": atom, "achieved": rate, "peak_measured": top,
+                                          "frac": rate / top, "unit": "atomic/s"}
     if not a.no_geodesic:
         out["geodesic_step"] = geodesic_leg(wl, launch, min(a.steps, 3), kms)
     if not a.no_plan:

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsde.so")
 
 SOURCES = ["sde_kernels.hip", "gamma_kernels.hip", "sde_tables.cpp", "sde_api.cpp", "nn_kernels.hip",
-           "nn_api.cpp"]
+           "nn_api.cpp", "roofs.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # packed FP32 VALU forms are switched off for device code

@@ -9,7 +9,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("sde.h", "sde_nn.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("sde.h", "sde_nn.h", "sde_roofs.h")]
 LIB = os.path.join(ROOT, "paper_2511_03115_amd", "libsde.so")
 
 
@@ -53,8 +53,10 @@ def test_binding_names_match_header():
     import importlib
     sde = importlib.import_module("paper_2511_03115_amd.sde")
     nn = importlib.import_module("paper_2511_03115_amd.nn")
+    roofs = importlib.import_module("paper_2511_03115_amd.roofs")
     assert not set(sde.EXPORTS) & set(nn.EXPORTS)
-    assert set(sde.EXPORTS) | set(nn.EXPORTS) == set(declared_functions())
+    assert not (set(sde.EXPORTS) | set(nn.EXPORTS)) & set(roofs.EXPORTS)
+    assert set(sde.EXPORTS) | set(nn.EXPORTS) | set(roofs.EXPORTS) == set(declared_functions())
 
 
 def test_host_validation_without_gpu(lib):
@@ -149,3 +151,30 @@ def test_nn_layer_alignment_is_checked_without_gpu(lib):
         sde.E_INVALID
     assert lib.sde_nn_conv3d_wgrad(ok, ok, 1, 2, 2, 2, 16, 16, ok, None, bad, Z(1 << 20)) == \
         sde.E_INVALID
+
+
+def test_microbench_arguments_are_checked_without_gpu(lib):
+    """The microbenchmark entry point refuses bad shapes, kinds, variants and
+    buffers before any device call."""
+    from paper_2511_03115_amd import roofs, sde
+    u, m = C.c_double(), C.c_double()
+    mb = lib.sde_microbench
+    mb.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int64,
+                   C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+
+    def call(kind, variant, buf=None, nbytes=0, grid=8, block=64, iters=4, reps=1):
+        return mb(kind, variant, buf, nbytes, grid, block, iters, reps, C.byref(u), C.byref(m))
+    assert call(roofs.FMA, 0, block=96) == sde.E_INVALID
+    assert call(roofs.FMA, 0, grid=0) == sde.E_INVALID
+    assert call(roofs.FMA, 0, reps=0) == sde.E_INVALID
+    assert call(roofs.FMA, 0, iters=0) == sde.E_INVALID
+    assert call(roofs.FMA, 5) == sde.E_INVALID
+    assert call(roofs.TRANS, 6) == sde.E_INVALID
+    assert call(roofs.MIX, 3) == sde.E_INVALID
+    assert call(roofs.LATOMIC, 1) == sde.E_INVALID
+    assert call(9, 0) == sde.E_INVALID
+    assert b"unknown" in lib.sde_last_error()
+    assert call(roofs.GATOMIC, 2) == sde.E_INVALID                     # no buffer
+    assert call(roofs.HBM, 0, C.c_void_p(0x10000), 4096) == sde.E_INVALID   # < 1 MiB
+    assert call(roofs.HBM, 0, C.c_void_p(0x10008), 1 << 20) == sde.E_INVALID  # misaligned
+    assert mb(0, 0, None, 0, 8, 64, 4, 1, None, None) == sde.E_INVALID
