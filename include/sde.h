@@ -95,7 +95,9 @@ typedef enum {
 #define SDE_LEDGER_STEPS 5       /* number of steps (count) */
 #define SDE_LEDGER_HISTORIES 6   /* number of histories (count) */
 #define SDE_LEDGER_JUMPS 7       /* number of large-angle jumps (count) */
-#define SDE_LEDGER_N 8
+#define SDE_LEDGER_BAD_LANES 8   /* energy of histories ended by the lane guard: a non-finite
+                                    energy or direction (fixed point; 0 in a sound run) */
+#define SDE_LEDGER_N 9
 
 /* A medium: element list with mass fractions and one mean excitation
  * energy (section 2.1.3, Bragg additivity).  (host) */
@@ -143,7 +145,10 @@ typedef struct {
  *    cubic B-spline coefficients in the lattice coordinate (uniform knots at
  *    the lattice points, knot k at k - 3) of Re a_l(E), Im a_l(E) and b_l(E)
  *    (barn).
- *  The summed cross sections must be positive over the sampled range. */
+ *  The summed cross sections must be positive over the sampled range.
+ * Refused with SDE_E_INVALID: negative or non-finite cross sections; an
+ * inverse CDF outside [0, 1] or decreasing in U; Kalbach r outside [0, 1]
+ * or a negative; non-finite B-spline coefficients; counts out of range. */
 typedef struct {
     int n_tab;
     int n_u;                     /* >= 2 */
@@ -199,6 +204,8 @@ typedef struct {
     int claim_chunk;  /* history indices a wave takes from the work counter at once, >= 64 (64) */
     int tile_nx, tile_ny, tile_nz;   /* LDS tally tile extent in voxels (0: none) */
     int tile_x0, tile_y0, tile_z0;   /* tile low corner in voxels */
+    uint64_t nan_history;  /* test hook: 0 none; else history nan_history - 1 starts with a
+                              NaN direction, which the lane guard must catch */
 } sde_launch;
 
 /* Build the per-material tables (FP64 on the host, FP32 hot fields staged in

@@ -47,7 +47,17 @@ END_EOR, END_EXIT, END_EMIN, END_MAXSTEPS, END_SOURCE = 1, 2, 3, 4, 5
 
 
 def build(force: bool = False) -> str:
-    """Compile sde_oracle.c with gcc into liboracle.so next to it."""
+    """Compile sde_oracle.c with gcc into liboracle.so next to it.  With
+    ORACLE_SANITIZE_LIB set, compile an AddressSanitizer + UndefinedBehavior-
+    Sanitizer build to that path instead (the process must preload libasan)."""
+    san = os.environ.get("ORACLE_SANITIZE_LIB")
+    if san:
+        if force or not os.path.exists(san) or os.path.getmtime(san) < os.path.getmtime(_SRC):
+            subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp",
+                                   "-fsanitize=address,undefined",
+                                   "-fno-sanitize-recover=undefined", "-shared", "-fPIC",
+                                   "-std=gnu11", "-o", san, _SRC, "-lm"])
+        return san
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11",

@@ -450,6 +450,7 @@ int make_plan(const sde_beam* beam, const sde_phantom* ph, uint64_t n_histories,
     kp.counter = p->counter;
     kp.refill = refill;
     kp.jump_batch = jump_batch;
+    kp.nan_h = L.nan_history ? L.nan_history - 1 : ~0ull;
     kp.claim_chunk = claim_chunk;
     // End-of-range screen: for E above ec[m] the residual range exceeds the
     // step at every voxel of material m (densest voxel, 0.1 % margin); below

@@ -8,7 +8,7 @@ namespace sde {
 
 constexpr int kMaxElem = 16;
 constexpr int kMaxMat = 8;
-constexpr int kLedgerN = 8;
+constexpr int kLedgerN = 9;
 
 // Physical constants (CODATA 2018), MeV based.
 constexpr double kMp = 938.27208816;       // proton rest energy
@@ -149,6 +149,7 @@ struct KParams {
     int claim_chunk;                 // history indices a wave takes from the counter at once
     int refill;
     int tile_nx, tile_ny, tile_nz, tile_x0, tile_y0, tile_z0, pad4;
+    unsigned long long nan_h;        // test hook: this history starts with a NaN direction
 };
 
 // Launchers (sde_kernels.hip)

@@ -24,6 +24,7 @@
 #include <type_traits>
 
 #include "sde_elastic.hpp"
+#include "sde_index.hpp"
 #include "sde_internal.hpp"
 
 namespace sde {
@@ -301,13 +302,13 @@ template <class R>
 __device__ __forceinline__ void voxel3(const KParams& P, const KScal<R>& S, R x, R y, R z,
                                        int& ix, int& iy, int& iz) {
     if constexpr (RM<R>::f64) {
-        ix = min((int)((x - S.lo[0]) / S.d[0]), P.nx - 1);
-        iy = min((int)((y - S.lo[1]) / S.d[1]), P.ny - 1);
-        iz = min((int)((z - S.lo[2]) / S.d[2]), P.nz - 1);
+        ix = axis_voxel(x, S.lo[0], 0.0, S.d[0], P.nx);
+        iy = axis_voxel(y, S.lo[1], 0.0, S.d[1], P.ny);
+        iz = axis_voxel(z, S.lo[2], 0.0, S.d[2], P.nz);
     } else {
-        ix = min((int)((x - S.lo[0]) * S.inv_d[0]), P.nx - 1);
-        iy = min((int)((y - S.lo[1]) * S.inv_d[1]), P.ny - 1);
-        iz = min((int)((z - S.lo[2]) * S.inv_d[2]), P.nz - 1);
+        ix = axis_voxel(x, S.lo[0], S.inv_d[0], 0.0f, P.nx);
+        iy = axis_voxel(y, S.lo[1], S.inv_d[1], 0.0f, P.ny);
+        iz = axis_voxel(z, S.lo[2], S.inv_d[2], 0.0f, P.nz);
     }
 }
 
@@ -336,10 +337,10 @@ struct Acc {
 __device__ __forceinline__ void acc_flush(const KParams& P, unsigned long long* tile,
                                           unsigned long long* rep, Acc& a) {
     if (a.v >= 0 && a.q != 0) {
-        const unsigned tx = (unsigned)(a.ix - P.tile_x0), ty = (unsigned)(a.iy - P.tile_y0),
-                       tz = (unsigned)(a.iz - P.tile_z0);
-        if (tx < (unsigned)P.tile_nx && ty < (unsigned)P.tile_ny && tz < (unsigned)P.tile_nz)
-            atomicAdd(&tile[(tz * P.tile_ny + ty) * P.tile_nx + tx], (unsigned long long)a.q);
+        const int slot = tile_slot(a.ix, a.iy, a.iz, P.tile_x0, P.tile_y0, P.tile_z0, P.tile_nx,
+                                   P.tile_ny, P.tile_nz);
+        if (slot >= 0)
+            atomicAdd(&tile[slot], (unsigned long long)a.q);
         else
             atomicAdd(&rep[a.v], (unsigned long long)a.q);
     }
@@ -363,8 +364,7 @@ __device__ __forceinline__ void score(const KParams& P, const KScal<R>& S,
     }
     int ix, iy, iz;
     voxel3(P, S, x, y, z, ix, iy, iz);
-    const int v = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx +
-                        (unsigned)ix);
+    const int v = voxel_index(ix, iy, iz, P.nx, P.ny, P.nz);
     if (v == a.v) {
         a.q += q;
     } else {
@@ -767,7 +767,7 @@ __device__ void jump(const KParams& P, const KScal<R>& S, const float4* tab, con
     using M = RM<R>;
     const Nuc<R> nu = nuc_of(P, R(0));
     const R tl = (M::lg(E) - S.ln_e_lo) * S.inv_dln;
-    const int li = max(0, min((int)tl, P.n_e - 2));
+    const int li = lattice_interval(tl, P.n_e);
     const R lf = tl - (R)li;
     const R inv_e2 = R(1) / (E * E);
     const R eta = S.eta_pre * M::rsq(E);
@@ -972,7 +972,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     unsigned nj = 0;
     unsigned hj = 0;
     int j1 = -1, j2 = -1;
-    long long l_esc = 0, l_nuc = 0, l_e0 = 0;
+    long long l_esc = 0, l_nuc = 0, l_e0 = 0, l_bad = 0;
     unsigned l_steps = 0, l_jumps = 0, l_hist = 0;
     // small-angle turn of the last step still to draw (exact regime): time,
     // uniform, azimuth
@@ -1040,6 +1040,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                     ox = R(0);
                     oy = R(0);
                     oz = R(1);
+                    if (h == P.nan_h) ox = (R)__builtin_nan("");   // host-set test hook
                     wsc = sp.wscale;
                     e0 = E;
                     hj = 0;
@@ -1058,8 +1059,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                     } else {
                         int ix, iy, iz;
                         voxel3(P, S, rx, ry, rz, ix, iy, iz);
-                        vcache = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) *
-                                           (unsigned)P.nx + (unsigned)ix);
+                        vcache = voxel_index(ix, iy, iz, P.nx, P.ny, P.nz);
                         const uint2 pk = P.vox[vcache];
                         rho = (R)__uint_as_float(pk.x);
                         mat = (int)pk.y;
@@ -1092,8 +1092,6 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                                        js, jcp, jsp, flags);
                 // E holds E' (after continuous loss); the jump removes u E'
                 const R En = E * (R(1) - u_loss);
-                l_nuc += fixp(E, wsc) - fixp(En, wsc);
-                E = En;
                 turn(ox, oy, oz, jc, js, jcp, jsp);
                 const R inv = M::rsq(ox * ox + oy * oy + oz * oz);
                 ox *= inv;
@@ -1104,16 +1102,25 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 if (j1 < 0) j1 = (int)nj;
                 j2 = (int)nj;
                 state = kStep;
-                if (!inside(S, rx, ry, rz)) {
-                    l_esc += fixp(E, wsc);
-                    record(P, h, (float)e0, n, hj, 2, (float)rx, (float)ry, (float)rz, (float)E,
+                if (!__builtin_isfinite(En * ox)) {   // the lane guard, as after a step
+                    l_bad += fixp(E, wsc);
+                    record(P, h, (float)e0, n, hj, 6, (float)rx, (float)ry, (float)rz, (float)E,
                            j1, j2);
                     state = kDead;
-                } else if (E < S.e_min) {
-                    score(P, S, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
-                    record(P, h, (float)e0, n, hj, 3, (float)rx, (float)ry, (float)rz, (float)E,
-                           j1, j2);
-                    state = kDead;
+                } else {
+                    l_nuc += fixp(E, wsc) - fixp(En, wsc);
+                    E = En;
+                    if (!inside(S, rx, ry, rz)) {
+                        l_esc += fixp(E, wsc);
+                        record(P, h, (float)e0, n, hj, 2, (float)rx, (float)ry, (float)rz,
+                               (float)E, j1, j2);
+                        state = kDead;
+                    } else if (E < S.e_min) {
+                        score(P, S, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
+                        record(P, h, (float)e0, n, hj, 3, (float)rx, (float)ry, (float)rz,
+                               (float)E, j1, j2);
+                        state = kDead;
+                    }
                 }
             }
         }
@@ -1148,7 +1155,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
 
         const R lnE = M::lg(E);
         const R tl = (lnE - S.ln_e_lo) * S.inv_dln;
-        const int li = max(0, min((int)tl, P.n_e - 2));
+        const int li = lattice_interval(tl, P.n_e);
         const R lf = tl - (R)li;
         float4 ta, tb;
         if constexpr (!M::f64) {
@@ -1260,8 +1267,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         if (in_next) {   // prefetch the next voxel while the direction is updated
             int ix, iy, iz;
             voxel3(P, S, rx, ry, rz, ix, iy, iz);
-            v_next = (int)(((unsigned)iz * (unsigned)P.ny + (unsigned)iy) * (unsigned)P.nx +
-                           (unsigned)ix);
+            v_next = voxel_index(ix, iy, iz, P.nx, P.ny, P.nz);
             if (v_next != vcache) pk_next = P.vox[v_next];
         }
 
@@ -1319,10 +1325,23 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
             oz *= inv;
             E = Ep;
             n++;
-            if (!in_next) {
-                l_esc += fixp(E, wsc);
-                record(P, h, (float)e0, n, hj, 2, (float)rx, (float)ry, (float)rz, (float)E, j1,
-                       j2);
+            // Lane guard, folded into the exit test: a non-finite energy or
+            // direction (one non-finite component reaches all three through
+            // the renormalisation, and the move then leaves the box, so this
+            // step's deposit was scored as escaped) ends the history; its
+            // energy goes to the bad-lane ledger slot, so the energy balance
+            // still closes, and its record ends with code 6.
+            const bool bad = !__builtin_isfinite(E * ox);
+            if (!in_next || bad) {
+                if (bad) {
+                    l_bad += __builtin_isfinite(E) ? fixp(E, wsc) : 0ll;
+                    record(P, h, (float)e0, n, hj, 6, (float)rx, (float)ry, (float)rz, (float)E,
+                           j1, j2);
+                } else {
+                    l_esc += fixp(E, wsc);
+                    record(P, h, (float)e0, n, hj, 2, (float)rx, (float)ry, (float)rz, (float)E,
+                           j1, j2);
+                }
                 state = kDead;
             } else if (E < S.e_min) {
                 score(P, S, tile, rep, acc, rx, ry, rz, E, wsc, l_esc);
@@ -1346,7 +1365,9 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     const unsigned long long s_st = wave_sum((unsigned long long)l_steps);
     const unsigned long long s_hi = wave_sum((unsigned long long)l_hist);
     const unsigned long long s_ju = wave_sum((unsigned long long)l_jumps);
+    const unsigned long long s_bad = wave_sum((unsigned long long)l_bad);
     if (lane == 0) {
+        if (s_bad) atomicAdd(&P.ledger[8], s_bad);
         atomicAdd(&P.ledger[1], s_esc);
         atomicAdd(&P.ledger[2], s_nuc);
         atomicAdd(&P.ledger[3], s_e0);

@@ -170,13 +170,27 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         T.nuc_r.resize(nu);
         T.nuc_a.resize(nu);
         for (size_t i = 0; i < ns; ++i) {
-            if (!(nuc->sigma_barn[i] >= 0)) { *err = "negative cross section"; return SDE_E_INVALID; }
+            if (!(nuc->sigma_barn[i] >= 0) || !std::isfinite(nuc->sigma_barn[i])) {
+                *err = "negative or non-finite cross section";
+                return SDE_E_INVALID;
+            }
             T.nuc_sigma[i] = (float)nuc->sigma_barn[i];
         }
         for (size_t i = 0; i < nu; ++i) {
-            T.nuc_u[i] = (float)nuc->u_icdf[i];
-            T.nuc_r[i] = (float)nuc->kalbach_r[i];
-            T.nuc_a[i] = (float)nuc->kalbach_a[i];
+            // the loss fraction's inverse CDF: in [0, 1], nondecreasing in U;
+            // Kalbach-Mann r in [0, 1], a >= 0 (NaN fails every test)
+            const double u = nuc->u_icdf[i], r = nuc->kalbach_r[i], a = nuc->kalbach_a[i];
+            if (!(u >= 0 && u <= 1) || (i % T.n_u && !(u >= nuc->u_icdf[i - 1]))) {
+                *err = "loss-fraction inverse CDF outside [0, 1] or decreasing";
+                return SDE_E_INVALID;
+            }
+            if (!(r >= 0 && r <= 1) || !(a >= 0 && std::isfinite(a))) {
+                *err = "Kalbach-Mann r outside [0, 1] or a negative";
+                return SDE_E_INVALID;
+            }
+            T.nuc_u[i] = (float)u;
+            T.nuc_r[i] = (float)r;
+            T.nuc_a[i] = (float)a;
         }
         T.nuc_sigma64.assign(nuc->sigma_barn, nuc->sigma_barn + ns);
         T.nuc_u64.assign(nuc->u_icdf, nuc->u_icdf + nu);
@@ -211,8 +225,13 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         T.ni_p64.assign(nuc->ni_p, nuc->ni_p + nrow * T.n_mu);
         T.ni_sig64.assign(nuc->ni_sigma_barn, nuc->ni_sigma_barn + nrow);
         T.ni_cum64.assign(nrow * (m + 1), 0.0);
+        for (size_t i = 0; i < nrow * T.n_mu; ++i)
+            if (!std::isfinite(T.ni_p64[i])) { *err = "non-finite P_NI coefficient"; return SDE_E_INVALID; }
         for (size_t r = 0; r < nrow; ++r) {
-            if (!(T.ni_sig64[r] >= 0)) { *err = "negative sigma_NI"; return SDE_E_INVALID; }
+            if (!(T.ni_sig64[r] >= 0) || !std::isfinite(T.ni_sig64[r])) {
+                *err = "negative or non-finite sigma_NI";
+                return SDE_E_INVALID;
+            }
             const double* c = &T.ni_p64[r * T.n_mu];
             double* cum = &T.ni_cum64[r * (m + 1)];
             for (int k = 0; k < m; ++k)   // a full knot interval: h (c_k + 11 c_k+1 + 11 c_k+2 + c_k+3) / 24
@@ -236,6 +255,8 @@ int build_host_tables(const sde_material_desc* mats, int n_mats, const sde_physi
         std::copy(nuc->h_a_re, nuc->h_a_re + nc, T.h_coef.begin());
         std::copy(nuc->h_a_im, nuc->h_a_im + nc, T.h_coef.begin() + nc);
         std::copy(nuc->h_b, nuc->h_b + nc, T.h_coef.begin() + 2 * nc);
+        for (double c : T.h_coef)
+            if (!std::isfinite(c)) { *err = "non-finite hydrogen amplitude"; return SDE_E_INVALID; }
     } else {
         T.h_coef.assign(1, 0.0);
     }

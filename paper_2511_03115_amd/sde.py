@@ -25,7 +25,8 @@ ALL = 127  # the method
 FP64 = 128  # step in double precision (not a physics switch)
 ECUT = 256  # variant: large-angle elastic cut 2.5 sigma(E) instead of the fixed cut
 (LEDGER_DEPOSITED, LEDGER_ESCAPED, LEDGER_NUCLEAR, LEDGER_INITIAL, LEDGER_TRUNCATED,
- LEDGER_STEPS, LEDGER_HISTORIES, LEDGER_JUMPS) = range(8)
+ LEDGER_STEPS, LEDGER_HISTORIES, LEDGER_JUMPS, LEDGER_BAD_LANES) = range(9)
+LEDGER_N = 9
 EXPORTS = ("sde_init_materials", "sde_set_stream", "sde_transport", "sde_transport_ex",
            "sde_plan_create", "sde_plan_execute", "sde_plan_results", "sde_plan_destroy",
            "sde_plan_kernel_ms", "sde_plan_set_records", "sde_gamma", "sde_launch_limits",
@@ -81,7 +82,8 @@ class Launch(C.Structure):
     _fields_ = [("block", C.c_int), ("grid", C.c_int), ("refill", C.c_int),
                 ("jump_batch", C.c_int), ("tally_replicas", C.c_int), ("claim_chunk", C.c_int),
                 ("tile_nx", C.c_int), ("tile_ny", C.c_int), ("tile_nz", C.c_int),
-                ("tile_x0", C.c_int), ("tile_y0", C.c_int), ("tile_z0", C.c_int)]
+                ("tile_x0", C.c_int), ("tile_y0", C.c_int), ("tile_z0", C.c_int),
+                ("nan_history", C.c_uint64)]
 
 
 def _load():
@@ -248,7 +250,7 @@ def launch_struct(launch: Optional[dict]):
 
 @dataclass
 class TransportResult:
-    ledger: np.ndarray      # int64 [8]
+    ledger: np.ndarray      # int64 [LEDGER_N]
     scale: float
 
 
@@ -258,7 +260,7 @@ def transport(spots, phantom: DevicePhantom, seed: int, dose_out=None, tally_out
     tally_out: int64 (nz,ny,nx) cuda tensor or None."""
     beam, keep = beam_struct(spots)
     ph = phantom.struct()
-    ledger = np.zeros(8, dtype=np.int64)
+    ledger = np.zeros(LEDGER_N, dtype=np.int64)
     scale = C.c_double(0.0)
     L = launch_struct(launch)
     rc = lib.sde_transport_ex(C.byref(beam), C.byref(ph), C.c_uint64(n_histories),
@@ -296,9 +298,9 @@ class Plan:
                                                         else None), int(use_graph)))
 
     def results(self, tally_out=None):
-        """(ledger int64[8], scale); copies the tally into tally_out (cuda int64
+        """(ledger int64[LEDGER_N], scale); copies the tally into tally_out (cuda int64
         (nz,ny,nx)) when given.  Synchronises the stream."""
-        ledger = np.zeros(8, dtype=np.int64)
+        ledger = np.zeros(LEDGER_N, dtype=np.int64)
         sc = C.c_double()
         _check(lib.sde_plan_results(self._h, C.c_void_p(_dptr(tally_out) if tally_out is not None
                                                         else None),

@@ -40,6 +40,7 @@ def test_parity_water100_small_full_physics():
     log(f"metrics {m}")
     # ledger: energy balance in fixed point and histories counted
     assert led[6] == wl.n_histories
+    assert led[8] == 0          # no lane ended by the guard
     bal = led[0] + led[1] + led[2] + led[4] - led[3]
     assert abs(bal) <= 2 * led[5] + 1e-6 * led[3], (bal, led)
     assert abs(led[0] / scale - led_ref[oracle.L_DEP]) <= 1e-4 * led_ref[oracle.L_E0]
@@ -83,6 +84,7 @@ def test_parity_full_physics_geodesic_step():
     m = parity_metrics(d_ref, d_gpu, wl.phantom)
     log(f"metrics {m}")
     assert led[6] == wl.n_histories
+    assert led[8] == 0          # no lane ended by the guard
     assert abs(led[0] / scale - led_ref[oracle.L_DEP]) <= 1e-4 * led_ref[oracle.L_E0]
     _bar(m)
 
