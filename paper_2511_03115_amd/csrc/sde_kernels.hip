@@ -323,26 +323,28 @@ __device__ __forceinline__ long long fixp(double e, double wsc) {
 
 // Per-lane deposit accumulator: consecutive deposits into the same voxel are
 // summed in registers and written once when the voxel changes.  The voxel's
-// coordinates are kept beside its linear index so that the tile test needs
-// no division.
+// slot in the workgroup's LDS tile (-1 outside it) is found when the voxel
+// is first scored, beside its linear index.
 struct Acc {
     int v;
-    int ix, iy, iz;
+    int slot;
     long long q;
 };
 
 // Add the accumulated q: into the workgroup's LDS tile if the voxel lies in
 // it, else into this XCD's replica of the global tally (hot lines then stay
-// in one L2).
-__device__ __forceinline__ void acc_flush(const KParams& P, unsigned long long* tile,
-                                          unsigned long long* rep, Acc& a) {
+// in one L2).  The two atomics carry different scopes, so that they stay an
+// LDS and a global instruction rather than one generic (flat) atomic on a
+// selected address.
+__device__ __forceinline__ void acc_flush(unsigned long long* tile, unsigned long long* rep,
+                                          Acc& a) {
     if (a.v >= 0 && a.q != 0) {
-        const int slot = tile_slot(a.ix, a.iy, a.iz, P.tile_x0, P.tile_y0, P.tile_z0, P.tile_nx,
-                                   P.tile_ny, P.tile_nz);
-        if (slot >= 0)
-            atomicAdd(&tile[slot], (unsigned long long)a.q);
+        if (a.slot >= 0)
+            __hip_atomic_fetch_add(&tile[a.slot], (unsigned long long)a.q, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-            atomicAdd(&rep[a.v], (unsigned long long)a.q);
+            __hip_atomic_fetch_add(&rep[a.v], (unsigned long long)a.q, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     a.v = -1;
     a.q = 0;
@@ -368,11 +370,10 @@ __device__ __forceinline__ void score(const KParams& P, const KScal<R>& S,
     if (v == a.v) {
         a.q += q;
     } else {
-        acc_flush(P, tile, rep, a);
+        acc_flush(tile, rep, a);
         a.v = v;
-        a.ix = ix;
-        a.iy = iy;
-        a.iz = iz;
+        a.slot = tile_slot(ix, iy, iz, P.tile_x0, P.tile_y0, P.tile_z0, P.tile_nx, P.tile_ny,
+                           P.tile_nz);
         a.q = q;
     }
 }
@@ -956,7 +957,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     // lines in one L2)
     const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;   // HW_REG_XCC_ID
     unsigned long long* rep = P.tally + (size_t)(xcc % (unsigned)P.n_rep) * P.rep_stride;
-    Acc acc{-1, 0, 0, 0, 0};
+    Acc acc{-1, -1, 0};
     int state = kDead;
     bool more = true;   // wave-uniform: the work counter may still hold histories
     unsigned long long q_next = 0, q_end = 0;   // wave-local range of history indices
@@ -980,7 +981,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     R sbm_t = R(0), sbm_u = R(0), sbm_ph = R(0);
 
     for (;;) {
-        if (state == kDead) acc_flush(P, tile, rep, acc);
+        if (state == kDead) acc_flush(tile, rep, acc);
         // ---------------- small-angle turns in the exact regime ----------------
         // Drawn here, where little is live, before the lane's pending jump
         // (if any) turns it and before its next step moves it.  A history that
@@ -1357,7 +1358,7 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         }
     }
 
-    acc_flush(P, tile, rep, acc);
+    acc_flush(tile, rep, acc);
     // ledger: wave sums, one atomic per slot per wave
     const unsigned long long s_esc = wave_sum((unsigned long long)l_esc);
     const unsigned long long s_nuc = wave_sum((unsigned long long)l_nuc);
