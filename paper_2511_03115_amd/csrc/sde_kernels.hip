@@ -322,32 +322,35 @@ __device__ __forceinline__ long long fixp(double e, double wsc) {
 }
 
 // Per-lane deposit accumulator: consecutive deposits into the same voxel are
-// summed in registers and written once when the voxel changes.  The voxel's
-// slot in the workgroup's LDS tile (-1 outside it) is found when the voxel
-// is first scored, beside its linear index.
+// summed in registers, as weighted energy in the stepping precision, and
+// written once, in fixed point, when the voxel changes.  The voxel's slot in
+// the workgroup's LDS tile (-1 outside it) is found when the voxel is first
+// scored, beside its linear index.
+template <class R>
 struct Acc {
     int v;
     int slot;
-    long long q;
+    R e;   // sum of e * wsc (fixed-point units)
 };
 
-// Add the accumulated q: into the workgroup's LDS tile if the voxel lies in
-// it, else into this XCD's replica of the global tally (hot lines then stay
-// in one L2).  The two atomics carry different scopes, so that they stay an
-// LDS and a global instruction rather than one generic (flat) atomic on a
-// selected address.
+// Add the accumulated energy, rounded to fixed point: into the workgroup's
+// LDS tile if the voxel lies in it, else into this XCD's replica of the
+// global tally (hot lines then stay in one L2).  The two atomics carry
+// different scopes, so that they stay an LDS and a global instruction
+// rather than one generic (flat) atomic on a selected address.
+template <class R>
 __device__ __forceinline__ void acc_flush(unsigned long long* tile, unsigned long long* rep,
-                                          Acc& a) {
-    if (a.v >= 0 && a.q != 0) {
+                                          Acc<R>& a) {
+    if (a.v >= 0 && a.e != R(0)) {
+        const unsigned long long q = (unsigned long long)fixp(a.e, R(1));
         if (a.slot >= 0)
-            __hip_atomic_fetch_add(&tile[a.slot], (unsigned long long)a.q, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&tile[a.slot], q, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-            __hip_atomic_fetch_add(&rep[a.v], (unsigned long long)a.q, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&rep[a.v], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     a.v = -1;
-    a.q = 0;
+    a.e = R(0);
 }
 
 // Score energy e at point (x,y,z): into the accumulator, or escaped.
@@ -356,25 +359,25 @@ __device__ __forceinline__ void acc_flush(unsigned long long* tile, unsigned lon
 // monotonic rounding of fma).
 template <class R>
 __device__ __forceinline__ void score(const KParams& P, const KScal<R>& S,
-                                      unsigned long long* tile, unsigned long long* rep, Acc& a,
+                                      unsigned long long* tile, unsigned long long* rep, Acc<R>& a,
                                       R x, R y, R z, R e, R wsc, long long& esc,
                                       bool check = true) {
-    const long long q = fixp(e, wsc);
     if (check && !inside(S, x, y, z)) {
-        esc += q;
+        esc += fixp(e, wsc);
         return;
     }
+    const R eq = e * wsc;
     int ix, iy, iz;
     voxel3(P, S, x, y, z, ix, iy, iz);
     const int v = voxel_index(ix, iy, iz, P.nx, P.ny, P.nz);
     if (v == a.v) {
-        a.q += q;
+        a.e += eq;
     } else {
         acc_flush(tile, rep, a);
         a.v = v;
         a.slot = tile_slot(ix, iy, iz, P.tile_x0, P.tile_y0, P.tile_z0, P.tile_nx, P.tile_ny,
                            P.tile_nz);
-        a.q = q;
+        a.e = eq;
     }
 }
 
@@ -919,7 +922,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-enum : int { kDead = 0, kStep = 1, kJump = 2 };
+enum : int { kDead = 0, kStep = 1, kJump = 2, kEnd = 3 };
 
 __device__ __forceinline__ const SpotDev& spot_at(const KParams& P, int i, float) {
     return P.spots[i];
@@ -957,8 +960,9 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
     // lines in one L2)
     const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;   // HW_REG_XCC_ID
     unsigned long long* rep = P.tally + (size_t)(xcc % (unsigned)P.n_rep) * P.rep_stride;
-    Acc acc{-1, -1, 0};
+    Acc<R> acc{-1, -1, R(0)};
     int state = kDead;
+    bool end_checked = false;   // the residual range exceeded the step: skip the screen once
     bool more = true;   // wave-uniform: the work counter may still hold histories
     unsigned long long q_next = 0, q_end = 0;   // wave-local range of history indices
 
@@ -1125,6 +1129,33 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
                 }
             }
         }
+        // ---------------- end-of-range steps, a batch at a time ----------------
+        // A lane whose energy passed the end-of-range screen waits here, so
+        // that the wave runs the FP64 residual-range step for several lanes
+        // at once instead of once per lane.  A lane whose residual range
+        // exceeds the step after all takes an ordinary step next.
+        if (flags & kEor) {
+            const unsigned long long ends = __ballot(state == kEnd);
+            if (ends && ((int)__popcll(ends) >= P.jump_batch || __ballot(state == kStep) == 0ull)) {
+                if (state == kEnd) {
+                    const double rres = range_g64(P, mat, (double)E) / (double)rho;
+                    if (rres <= P.sd.step) {
+                        const R hr = (R)(0.5 * rres);
+                        score(P, S, tile, rep, acc, M::fma(ox, hr, rx), M::fma(oy, hr, ry),
+                              M::fma(oz, hr, rz), E, wsc, l_esc);
+                        l_steps++;
+                        const R fr = (R)rres;
+                        record(P, h, (float)e0, n + 1, hj, 1, (float)M::fma(ox, fr, rx),
+                               (float)M::fma(oy, fr, ry), (float)M::fma(oz, fr, rz), (float)E,
+                               j1, j2);
+                        state = kDead;
+                    } else {
+                        state = kStep;
+                        end_checked = true;
+                    }
+                }
+            }
+        }
         if (state != kStep) continue;
 
         // ---------------- one step of Eq. (VSDE) ----------------
@@ -1136,23 +1167,15 @@ __global__ void __launch_bounds__(1024) k_transport(KParams P) {
         }
         const float4 mc = matc[mat];
 
-        // End of range: residual range within one step, decided in FP64; the
-        // FP32 screen E <= ec(material) is exact-safe (ec bounds the energy
-        // whose range fits a step at the densest voxel of that material).
-        if ((flags & kEor) && E <= (R)mc.z) {
-            const double rres = range_g64(P, mat, (double)E) / (double)rho;
-            if (rres <= P.sd.step) {
-                const R hr = (R)(0.5 * rres);
-                score(P, S, tile, rep, acc, M::fma(ox, hr, rx), M::fma(oy, hr, ry),
-                      M::fma(oz, hr, rz), E, wsc, l_esc);
-                l_steps++;
-                const R fr = (R)rres;
-                record(P, h, (float)e0, n + 1, hj, 1, (float)M::fma(ox, fr, rx),
-                       (float)M::fma(oy, fr, ry), (float)M::fma(oz, fr, rz), (float)E, j1, j2);
-                state = kDead;
-                continue;
-            }
+        // End of range: residual range within one step, decided in FP64 in the
+        // batch above; the FP32 screen E <= ec(material) is exact-safe (ec
+        // bounds the energy whose range fits a step at the densest voxel of
+        // that material).
+        if ((flags & kEor) && E <= (R)mc.z && !end_checked) {
+            state = kEnd;
+            continue;
         }
+        end_checked = false;
 
         const R lnE = M::lg(E);
         const R tl = (lnE - S.ln_e_lo) * S.inv_dln;
