@@ -173,6 +173,22 @@ __device__ bool gamma_search(const GammaArgs& A, const GammaLattice& L, int ix, 
                 const double ty = fy - y0;
                 const double c0 = c00 * (1 - ty) + c10 * ty, c1 = c01 * (1 - ty) + c11 * ty;
                 const double sab = oxx + L.cm[1][b + K] * L.cm[1][b + K];
+                if (A.use_bound && xin && yin) {
+                    // Along the row the offsets stay in the octant's cell, where
+                    // v - dr = al + be c is linear in c, so the test function
+                    // sab/dta^2 + c^2 st^2/dta^2 + (al + be c)^2/norm^2 is a
+                    // convex quadratic in c: its continuous minimum bounds every
+                    // offset of the row, and above 1 (by a margin far beyond
+                    // rounding) no offset of the row passes.
+                    const double t0 = (double)(iz - z0), h = L.vx[2][K + 1];
+                    const double al = (c0 + (c1 - c0) * t0) - dr, be = (c1 - c0) * h;
+                    const double qa = L.cm[2][K + 1] * L.cm[2][K + 1] * inv_dta2;
+                    const double qb = be * be * inv_n2;
+                    const double cs = -(al * be * inv_n2) / (qa + qb);
+                    const double lin = al + be * cs;
+                    const double fmin = sab * inv_dta2 + qa * cs * cs + lin * lin * inv_n2;
+                    if (fmin > 1.0 + 1e-9) continue;
+                }
                 for (int uc = 0; uc + sz <= K; ++uc) {
                     const int c = sz ? -(uc + 1) : uc;
                     if (a * a + b * b + c * c > nmax) break;
