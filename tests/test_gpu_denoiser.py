@@ -21,8 +21,8 @@ WEIGHTS = os.path.join(ROOT, "paper_2511_03115_amd", "weights", "denoiser_plan2m
 
 
 def _rel_err(d, ref, thr=0.01):
-    m = ref >= thr * ref.max()
-    return float(np.sqrt((((d - ref) / ref)[m] ** 2).mean()))
+    m = ref >= thr * ref.max()          # masked before dividing: no zero denominators
+    return float(np.sqrt((((d[m] - ref[m]) / ref[m]) ** 2).mean()))
 
 
 def test_trained_network_gains_over_no_network():
