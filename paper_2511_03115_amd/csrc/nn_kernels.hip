@@ -186,12 +186,20 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const uint16_t* __restrict
 constexpr int kHZ = 4, kHY = 8, kHX = 8;
 constexpr int kHVox = (kHZ + 2) * (kHY + 2) * (kHX + 2);
 
-// Brick of the register and channel-pass kernels below: 4 x 4 x 16 output
-// voxels, so a 16-voxel matrix row is one run along x; with the odd number
-// of 16-byte units per LDS voxel slot (Ci + 8 elements) the 16 slots a
-// quarter-wave reads then fall on distinct banks.
+// Brick of the register, row-reuse and channel-pass kernels below: 4 x 4 x
+// 16 output voxels, so a 16-voxel matrix row is one run along x.
 constexpr int kRZ = 4, kRY = 4, kRX = 16;
 constexpr int kRVox = (kRZ + 2) * (kRY + 2) * (kRX + 2);
+
+// Elements per voxel slot of the row-reuse kernel's brick in LDS.  Its
+// matrix-core fragment reads are 16 voxels x 4 lane quarters x 16 bytes;
+// gfx950 serves them at its full 256 bytes per clock when consecutive voxel
+// slots are 32 or 96 bytes apart, and at half rate for 48, 64, 80 or 112
+// (measured on the device for every K step's fragment pattern), so 32
+// channels are padded to 48 and 16 or 48 channels are not padded.  (The
+// register and channel-pass kernels keep a 16-byte pad per slot: in them the
+// unpadded layout measured no faster.)
+__host__ __device__ constexpr int brick_row(int ci) { return ci == 32 ? 48 : ci; }
 
 template <int NT>
 __global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restrict__ x,
@@ -306,8 +314,9 @@ __global__ void __launch_bounds__(256) k_conv_fwd_halo(const uint16_t* __restric
 
 // ---------------------------------------------------------------------------
 // The halo-brick convolution with the input channel count fixed at compile
-// time, for the few-channel layers (Ci in {16, 32, 48} with 16 outputs,
-// Ci = 16 with 32): the B fragments (weights) of the K steps live in
+// time, for the few-channel layers with 32 outputs (Ci in {16, 32}; those
+// with 16 outputs take the row-reuse kernel below): the B fragments
+// (weights) of the K steps live in
 // registers, read from memory in chunks of CH steps, the next chunk in
 // flight while the current one feeds the matrix cores, and the whole
 // 6 x 6 x 18 input brick is fetched with every load issued before the
@@ -335,13 +344,8 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int nblocks) {
     return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
-// With CS < CI the input is the decoder's concatenation, never stored:
-// channels [0, CS) come from x (CS channels per voxel) and [CS, CI) from
-// the coarser level xl (CI - CS channels, half the size along each axis,
-// nearest-neighbour upsampled), read straight into the brick.
-template <int CI, int NT, int CH, int CS = CI>
+template <int CI, int NT, int CH>
 __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict__ x,
-                                                      const uint16_t* __restrict__ xl,
                                                       const uint16_t* __restrict__ w,
                                                       const float* __restrict__ bias, Geo g,
                                                       int Co, float alpha, int act,
@@ -367,9 +371,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     // Loads go through buffer resources with 32-bit offsets (the host keeps
     // every operand below 2 GiB); a load that must give zeros (outside the
     // volume, past the last K step) reads offset 0 and is replaced by zero,
-    // so no load sits behind a branch.  (The decoder concatenation, whose
-    // two sources differ from lane to lane, reads through plain pointers.)
-    const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CS);
+    // so no load sits behind a branch.
+    const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CI);
     const __amdgpu_buffer_rsrc_t wr = rsrc16(w, (long long)NT * 16 * K);
     bf16x8 wb[2][CH][NT];   // B[k][n] = w[n][k], two chunks of K steps (Co = 16 NT)
     auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int c) {
@@ -397,49 +400,14 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     constexpr int kMaxR0 = 255 / RU;   // largest r0, idle threads included
     const bool inner = x0 >= 1 && x0 + kRX < g.W && y0 >= 1 && y0 + kRY < g.H && z0 >= 1 &&
                        z0 + kRZ < g.D;   // the halo lies inside the volume; uniform
-    const bool interior = CS == CI && inner;
-    if (CS < CI && inner) {
-        if constexpr (CS < CI) {
-            // The concatenation over an interior brick.  With 2 halo rows per
-            // pass and 6 rows per z (asserted), pass u = 3k + j covers the rows
-            // at hzz = k, hyy = r0 + 2j; z0 and y0 are multiples of 4, so the
-            // parent voxel in xl sits at coarse z = z0/2 + ((k - 1) >> 1) and
-            // coarse y = y0/2 - 1 + r0 + j.  Offsets are compile-time multiples
-            // of two strides from a per-thread base: no bounds tests.
-            static_assert(RP == 2 && kRY + 2 == 6 && NROW == 36 && NUR == 18,
-                          "interior concatenation staging assumes 2 halo rows per pass");
-            const bool sk = c < CS;
-            const int rr0 = r0 < RP ? r0 : 0;   // idle threads load nothing
-            const uint16_t* p;
-            int dy, dz;   // element strides of one step in j and in the z term
-            if (sk) {
-                p = x + ((long long)((b * g.D + z0 - 1) * g.H + y0 - 1 + rr0) * g.W + xx) * CS +
-                    c;
-                dy = 2 * g.W * CS;
-                dz = g.H * g.W * CS;
-            } else {
-                const int Dd = g.D >> 1, Hd = g.H >> 1, Wd = g.W >> 1;
-                p = xl + ((long long)((b * Dd + (z0 >> 1)) * Hd + (y0 >> 1) - 1 + rr0) * Wd +
-                          (xx >> 1)) * (CI - CS) + (c - CS);
-                dy = Wd * (CI - CS);
-                dz = Hd * Wd * (CI - CS);
-            }
-#pragma unroll
-            for (int u = 0; u < NUR; ++u) {
-                const int k = u / 3, j = u % 3;
-                const int off = (sk ? k : ((k - 1) >> 1)) * dz + j * dy;
-                st[u] = r0 < RP ? *reinterpret_cast<const uint4*>(p + off)
-                                : make_uint4(0, 0, 0, 0);
-            }
-        }
-    } else if (interior) {
+    if (inner) {
         // the whole halo is inside the volume: no bounds tests, and the offset
         // advances by RP rows per pass (DZ slices and DY rows, wrapping at 6)
         constexpr int DZ = RP / (kRY + 2), DY = RP % (kRY + 2);
-        const int rowb = g.W * (CS * 2), plane = g.H * rowb;
+        const int rowb = g.W * (CI * 2), plane = g.H * rowb;
         int hyy = r0 % (kRY + 2);
         int off = (((b * g.D + z0 - 1 + r0 / (kRY + 2)) * g.H + y0 - 1 + hyy) * g.W + xx) *
-                      (CS * 2) + c * 2;
+                      (CI * 2) + c * 2;
 #pragma unroll
         for (int u = 0; u < NUR; ++u) {
             if (kMaxR0 + RP * u < NROW) {
@@ -456,13 +424,6 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
             }
         }
     } else {
-        // channels [0, CS) from x, [CS, CI) from the parent voxel in xl: each
-        // thread reads one source (c is fixed per thread)
-        const bool sk = CS == CI || c < CS;
-        const int sh = sk ? 0 : 1;
-        const int Dd = g.D >> sh, Hd = g.H >> sh, Wd = g.W >> sh;
-        const uint16_t* src = sk ? x + c : xl + (c - CS);
-        const int cstride = sk ? CS : CI - CS;
 #pragma unroll
         for (int u = 0; u < NUR; ++u) {
             const int row = r0 + RP * u;
@@ -470,14 +431,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
             const int yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
             const bool in = xin && (NROW % RP == 0 || u < NUR - 1 || row < NROW) && yy >= 0 &&
                             zz >= 0 && yy < g.H && zz < g.D;
-            if (CS == CI) {
-                st[u] = ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2, in);
-            } else {
-                const long long vox =
-                    (((long long)b * Dd + (zz >> sh)) * Hd + (yy >> sh)) * Wd + (xx >> sh);
-                st[u] = in ? *reinterpret_cast<const uint4*>(src + (in ? vox : 0) * cstride)
-                           : make_uint4(0, 0, 0, 0);
-            }
+            st[u] = ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CI * 2) + c * 2, in);
         }
     }
     load_chunk(wb[0], 0);
@@ -570,6 +524,208 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
                 if (act) rr = lrelu(rr, alpha);
                 if (y16) y16[v * Co + co] = f2bf(rr);
                 if (y32) y32[v * Co + co] = accumulate ? y32[v * Co + co] + rr : rr;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The row-reuse convolution with 16 outputs, persistent over bricks: the
+// workgroup gathers the weight fragments of every K step into registers
+// once, then walks a contiguous range of this XCD's bricks (neighbouring
+// bricks, which share halo voxels, run at the same time and meet in one
+// L2), the next brick's input rows loaded into registers while the current
+// one feeds the matrix cores.  Per brick the work is the row-reuse form of
+// k_conv_fwd_reg (pairs of (dz, dx, 16-channel block) combinations, 6 input
+// rows read once for 3 dy taps x 4 output rows).  The weights are the
+// matrix cores' A operand and the input rows the B operand, so a lane ends
+// with 4 consecutive output channels of one voxel and stores them straight
+// from registers (a wave's 64 lanes write one 16-voxel row, 512 contiguous
+// bytes).  Loads go through buffer resources: a halo voxel outside the
+// volume is read at an offset past the end, which the hardware answers with
+// zeros, so no load sits behind a branch and the compiler's wait counts stay
+// exact across the loop.  With CS < CI the input is the decoder's
+// concatenation, read in place: channels [0, CS) from x, [CS, CI) from the
+// half-size level xl (nearest-neighbour upsampled); a thread's channel group
+// comes from one of the two, the other load is answered with zeros.
+// ---------------------------------------------------------------------------
+constexpr int kOob = 0x7ff00000;   // a buffer offset past every operand
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+template <int CI, int CS, bool F32>
+__global__ void __launch_bounds__(256) k_conv_rows(const uint16_t* __restrict__ x,
+                                                   const uint16_t* __restrict__ xl,
+                                                   const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ bias, Geo g,
+                                                   float alpha, int act,
+                                                   uint16_t* __restrict__ y16,
+                                                   float* __restrict__ y32, int accumulate) {
+    constexpr int MT = 4, K = 27 * CI, ROW = brick_row(CI), GV = CI / 8;
+    constexpr int NB = CI / 16, NU = 9 * NB, NP = (NU + 1) / 2;
+    constexpr int RU = (kRX + 2) * GV, NROW = (kRZ + 2) * (kRY + 2), RP = 256 / RU;
+    constexpr int NUR = (NROW + RP - 1) / RP;
+    static_assert(CI % 16 == 0 && CS % 8 == 0, "16-channel blocks");
+    // [kRVox][ROW] halo brick, then one spare 16-byte slot per thread for
+    // the staging stores that fall outside the brick
+    extern __shared__ __align__(16) uint16_t hx[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+    const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
+    const int nbk = nbx * nby * nbz * g.B;   // the host keeps it below 2^31
+
+    // the weight fragments of every pair and dy (a padded half gets zeros)
+    const __amdgpu_buffer_rsrc_t wr = rsrc16(w, 16LL * K);
+    bf16x8 wv[NP][3];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int u = 2 * p + (q >> 1);
+        const int dz = u / (3 * NB), dx = (u / NB) % 3, cb = u % NB;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int k = (dz * 9 + dy * 3 + dx) * CI + cb * 16 + (q & 1) * 8;
+            wv[p][dy] = as_bf16x8(__builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                           wr, u < NU ? ((lane & 15) * K + k) * 2 : kOob, 0, 0)));
+        }
+    }
+
+    // staging: a thread owns one 16-byte column (voxel hxx of a halo row,
+    // channels [c, c + 8)) and rows r0, r0 + RP, ...
+    const int col = threadIdx.x % RU, r0 = threadIdx.x / RU;
+    const int hxx = col / GV, c = (col - hxx * GV) * 8;
+    const bool sk = CS == CI || c < CS;
+    const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CS);
+    const __amdgpu_buffer_rsrc_t lr = rsrc16(CS < CI ? xl : x, CS < CI ? g.nvox() / 8 * (CI - CS) : 0);
+    auto decode = [&](int bid, int& x0, int& y0, int& z0, int& b) {
+        const int bx = bid % nbx;
+        bid /= nbx;
+        const int by = bid % nby;
+        bid /= nby;
+        const int bz = bid % nbz;
+        b = bid / nbz;
+        x0 = bx * kRX;
+        y0 = by * kRY;
+        z0 = bz * kRZ;
+    };
+    auto load_brick = [&](int brick, uint4 (&st)[NUR]) {
+        int x0, y0, z0, b;
+        decode(brick, x0, y0, z0, b);
+        const int xx = x0 - 1 + hxx;
+        const bool xin = r0 < RP && xx >= 0 && xx < g.W;
+#pragma unroll
+        for (int u = 0; u < NUR; ++u) {
+            const int row = r0 + RP * u;
+            const int hzz = row / (kRY + 2), hyy = row - hzz * (kRY + 2);
+            const int yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
+            const bool in = xin && row < NROW && yy >= 0 && zz >= 0 && yy < g.H && zz < g.D;
+            const int ox = (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2;
+            st[u] = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, in && sk ? ox : kOob, 0, 0));
+            if constexpr (CS < CI) {
+                const int Dd = g.D >> 1, Hd = g.H >> 1, Wd = g.W >> 1;
+                const int ol = (((b * Dd + (zz >> 1)) * Hd + (yy >> 1)) * Wd + (xx >> 1)) *
+                                   ((CI - CS) * 2) + (c - CS) * 2;
+                const uint4 v = __builtin_bit_cast(
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(lr, in && !sk ? ol : kOob, 0, 0));
+                st[u].x |= v.x;
+                st[u].y |= v.y;
+                st[u].z |= v.z;
+                st[u].w |= v.w;
+            }
+        }
+    };
+
+    // this XCD's contiguous range of bricks and its workgroups
+    const int xcd = blockIdx.x % kXcds, gi = blockIdx.x / kXcds;
+    const int gn = ((int)gridDim.x - xcd + kXcds - 1) / kXcds;
+    const int per = nbk / kXcds, rem = nbk % kXcds;
+    const int s0 = xcd * per + (xcd < rem ? xcd : rem), s1 = s0 + per + (xcd < rem ? 1 : 0);
+    const int rbase = ((wave * (kRY + 2)) * (kRX + 2) + (lane & 15)) * ROW + (q & 1) * 8;
+    const int sbase = (r0 * (kRX + 2) + hxx) * ROW + c;
+    uint16_t* const spare = hx + kRVox * ROW + threadIdx.x * 8;
+    float bq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bq[i] = bias ? bias[q * 4 + i] : 0.0f;
+    // r > 0 ? r : slope r is LeakyReLU(r, alpha) for any alpha, and r when act == 0
+    const float slope = act ? alpha : 1.0f;
+    const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, y16 ? g.nvox() * 16 : 0);
+    uint4 st[NUR];
+    int brick = s0 + gi;
+    if (brick < s1) load_brick(brick, st);
+    // every load so far has landed (the weights stay live across the loop;
+    // without this the compiler's wait counts would assume them pending)
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    for (; brick < s1; brick += gn) {
+        __syncthreads();   // the previous brick's LDS reads are done
+#pragma unroll
+        for (int u = 0; u < NUR; ++u) {
+            const bool ok = r0 < RP && r0 + RP * u < NROW;
+            *reinterpret_cast<uint4*>(ok ? hx + sbase + u * RP * (kRX + 2) * ROW : spare) = st[u];
+        }
+        __syncthreads();
+        if (brick + gn < s1) load_brick(brick + gn, st);   // in flight during the MFMAs
+        f32x4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int u0 = 2 * p, u1 = 2 * p + 1 < NU ? 2 * p + 1 : 2 * p;
+            const int o0 = ((u0 / (3 * NB)) * (kRY + 2) * (kRX + 2) + (u0 / NB) % 3) * ROW +
+                           (u0 % NB) * 16;
+            const int o1 = ((u1 / (3 * NB)) * (kRY + 2) * (kRX + 2) + (u1 / NB) % 3) * ROW +
+                           (u1 % NB) * 16;
+            const int o = (q & 2) ? o1 : o0;
+            bf16x8 a[MT + 2];
+#pragma unroll
+            for (int i = 0; i < MT + 2; ++i)
+                a[i] = as_bf16x8(*reinterpret_cast<const uint4*>(hx + rbase + o + i * (kRX + 2) * ROW));
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[p][dy], a[m + dy], acc[m],
+                                                                     0, 0, 0);
+        }
+        // acc[m][i]: output channel 4 q + i of voxel (x0 + lane % 16, y0 + m, z0 + wave)
+        int x0, y0, z0, b;
+        decode(brick, x0, y0, z0, b);
+        const int xx = x0 + (lane & 15), zz = z0 + wave;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int yy = y0 + m;
+            const bool in = zz < g.D && yy < g.H && xx < g.W;
+            const int v = ((b * g.D + zz) * g.H + yy) * g.W + xx;
+            float r[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                r[i] = acc[m][i] + bq[i];
+                r[i] = r[i] > 0.0f ? r[i] : slope * r[i];   // LeakyReLU, or identity
+            }
+            if constexpr (!F32) {
+                // a store past the end of the resource is dropped: no branch
+                const uint32_t lo = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
+                const uint32_t hi = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo, hi}, yr,
+                                                      in ? (v * 16 + q * 4) * 2 : kOob, 0, 0);
+                continue;
+            } else {
+            if (!in) continue;
+            if (y16) {
+                uint2 pk;
+                pk.x = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
+                pk.y = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+                *reinterpret_cast<uint2*>(y16 + (long long)v * 16 + q * 4) = pk;
+            }
+            float4* d = reinterpret_cast<float4*>(y32 + (long long)v * 16 + q * 4);
+            float4 o4 = make_float4(r[0], r[1], r[2], r[3]);
+            if (accumulate) {
+                const float4 prev = *d;
+                o4.x += prev.x;
+                o4.y += prev.y;
+                o4.z += prev.z;
+                o4.w += prev.w;
+            }
+            *d = o4;
             }
         }
     }
@@ -1465,6 +1621,46 @@ inline int blocks_for(long long n, int bs = 256, int cap = 16384) {
     return (int)g;
 }
 
+// The persistent row-reuse convolution: as many workgroups as the device
+// holds at once (the occupancy the compiler's register and LDS use allows),
+// at most one per brick.
+template <int CI, int CS, bool F32>
+hipError_t launch_rows_as(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
+                          const float* bias, Geo g, float alpha, int act, uint16_t* y16,
+                          float* y32, int accumulate, hipStream_t s) {
+    constexpr size_t lds = ((size_t)kRVox * brick_row(CI) + 256 * 8) * sizeof(uint16_t);
+    static const int cap = [] {
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void*)k_conv_rows<CI, CS, F32>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024) != hipSuccess)
+            return 0;
+        int dev = 0, cu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv_rows<CI, CS, F32>, 256,
+                                                         lds) != hipSuccess)
+            return 0;
+        return per * cu;
+    }();
+    if (cap <= 0) return hipErrorInvalidConfiguration;
+    const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                          ((g.D + kRZ - 1) / kRZ) * g.B;
+    if (nbk >= (1LL << 31) || g.nvox() * 16 * (F32 ? 4 : 2) >= (1LL << 31))
+        return hipErrorInvalidValue;
+    const int grid = (int)std::min<long long>(nbk, cap);
+    hipLaunchKernelGGL((k_conv_rows<CI, CS, F32>), dim3((unsigned)grid), dim3(256), lds, s, x, xl,
+                       w, bias, g, alpha, act, y16, y32, accumulate);
+    return hipGetLastError();
+}
+
+template <int CI, int CS>
+hipError_t launch_rows(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
+                       const float* bias, Geo g, float alpha, int act, uint16_t* y16, float* y32,
+                       int accumulate, hipStream_t s) {
+    return y32 ? launch_rows_as<CI, CS, true>(x, xl, w, bias, g, alpha, act, y16, y32, accumulate, s)
+               : launch_rows_as<CI, CS, false>(x, xl, w, bias, g, alpha, act, y16, y32, 0, s);
+}
+
 }  // namespace
 
 hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
@@ -1480,9 +1676,6 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_conv_fwd_halo<2>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_conv_fwd_reg<48, 1, 14>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
         return e;
     }();
     if (attr != hipSuccess) return attr;
@@ -1490,15 +1683,19 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
         const size_t lds_r = (size_t)kRVox * (Ci + 8) * sizeof(uint16_t);
-#define LAUNCH_REG(CI, NT, CH)                                                                \
+#define LAUNCH_REG(CI, NT, CH)                                                             \
     hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk), dim3(256), lds_r, s, x, \
-                       nullptr, w, bias, g, Co, alpha, act, y16, y32, accumulate)
+                       w, bias, g, Co, alpha, act, y16, y32, accumulate)
+        // 16 outputs: the persistent row-reuse form
+        if (Co == 16 && Ci == 16)
+            return launch_rows<16, 16>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
+        if (Co == 16 && Ci == 32)
+            return launch_rows<32, 32>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
+        if (Co == 16 && Ci == 48)
+            return launch_rows<48, 48>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
         bool done = true;
-        if (Ci == 16 && nt == 1) LAUNCH_REG(16, 1, 14);
-        else if (Ci == 16 && nt == 2) LAUNCH_REG(16, 2, 14);
-        else if (Ci == 32 && nt == 1) LAUNCH_REG(32, 1, 14);
+        if (Ci == 16 && nt == 2) LAUNCH_REG(16, 2, 14);
         else if (Ci == 32 && nt == 2) LAUNCH_REG(32, 2, 7);
-        else if (Ci == 48 && nt == 1) LAUNCH_REG(48, 1, 14);
         else done = false;
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
@@ -1583,14 +1780,7 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
                                0);
         return hipGetLastError();
     }
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void*)k_conv_fwd_reg<48, 1, 14, 16>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    if (attr != hipSuccess) return attr;
-    const size_t lds = (size_t)kRVox * (Cs + Cu + 8) * sizeof(uint16_t);
-    hipLaunchKernelGGL((k_conv_fwd_reg<48, 1, 14, 16>), dim3((unsigned)nbk), dim3(256), lds, s,
-                       skip, low, w, bias, g, Co, alpha, act, y16, nullptr, 0);
-    return hipGetLastError();
+    return launch_rows<48, 16>(skip, low, w, bias, g, alpha, act, y16, nullptr, 0, s);
 }
 
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s) {

@@ -265,6 +265,12 @@ def test_adam_update_matches_oracle():
 
 
 def test_training_reduces_loss_and_is_reproducible():
+    """150 Adam steps at lr 1e-3 on a small net: the loss equals the oracle's
+    at the evolved parameters, falls below half its start, and two runs end
+    bit-identical.  (At lr 5e-3 this net sits at the edge of stability: the
+    loss trace then depends on the summation order, spiking with one
+    kernel's rounding and not with another's, although both match the
+    oracle's loss along the way; at 1e-3 it descends smoothly either way.)"""
     import torch
     from paper_2511_03115_amd import nn
     levels, c0, cin = 3, 16, 16
@@ -272,16 +278,24 @@ def test_training_reduces_loss_and_is_reproducible():
     p = nno.flatten(he_params(levels, c0, cin, seed=15, head_scale=0.0), levels, c0, cin)
     dose, rho, tgt, wgt = _net_inputs(B, D, H, W, seed=16)
     dev = lambda a: torch.from_numpy(a).cuda()
+    x = _oracle_input(dose, rho, cin)
     finals = []
     for rep in range(2):
         net = nn.Net(levels, c0, cin, 0.01, B, (D, H, W), train=True)
         net.set_params(p.astype(np.float32))
         losses = []
         for it in range(150):
+            if rep == 0 and it == 75:
+                q = nno.unflatten(net.get_params().astype(np.float64), levels, c0, cin)
+                loss_ref, _, _ = _oracle_net(q, levels, c0, cin, 0.01).loss_and_grads(
+                    x, tgt.astype(np.float64), np.ones(tgt.shape))
             losses.append(net.loss_grad(dev(dose), dev(rho), dev(tgt), None))
-            net.adam_step(5e-3)
+            if rep == 0 and it == 75:
+                log(f"  loss at step 75: gpu {losses[-1]:.6e} oracle {loss_ref:.6e}")
+                assert abs(losses[-1] - loss_ref) <= 1e-3 * loss_ref
+            net.adam_step(1e-3)
         log(f"train rep {rep}: loss {losses[0]:.4e} -> {losses[-1]:.4e}")
-        assert losses[-1] < 0.8 * losses[0]
+        assert losses[-1] < 0.5 * losses[0]
         finals.append(net.get_params())
         net.close()
     assert np.array_equal(finals[0], finals[1])
