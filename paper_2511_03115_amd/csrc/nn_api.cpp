@@ -63,7 +63,8 @@ struct sde_nn {
     uint16_t* P16 = nullptr;
     long long step = 0;
     long long max_nv0 = 0;
-    uint16_t* x16 = nullptr;
+    uint16_t* x16 = nullptr;    // input rows (training: the first weight gradient reads them)
+    uint32_t* x2 = nullptr;     // the two used input channels as bf16 pairs
     float *resid = nullptr, *out = nullptr;
     std::vector<Level> lv;
     float *dout = nullptr, *loss_part = nullptr, *loss_dev = nullptr, *head_part = nullptr;
@@ -115,6 +116,14 @@ int conv_act(sde_nn* n, const uint16_t* x, const ConvP& cp, const int* d, uint16
     return SDE_OK;
 }
 
+// The first conv reads the input's two used channels as bf16 pairs (16
+// outputs); the Cx-channel rows are then needed only by training's weight
+// gradient.
+bool first_from_pairs(const sde_nn* n) { return n->enc_a[0].co == 16; }
+
+// The input rows x16 are written when a conv reads them.
+uint16_t* input_rows(sde_nn* n) { return n->cfg.train || !first_from_pairs(n) ? n->x16 : nullptr; }
+
 int run_forward(sde_nn* n, const int* d0) {
     hipStream_t s = library_stream();
     int d[4], dc[4];
@@ -126,7 +135,13 @@ int run_forward(sde_nn* n, const int* d0) {
             NN_TRY(pool_fwd(n->lv[l - 1].eb, d, n->c[l - 1], v.pin, s));
             in = v.pin;
         }
-        if (int r = conv_act(n, in, n->enc_a[l], d, v.ea)) return r;
+        if (l == 0 && first_from_pairs(n)) {
+            const ConvP& cp = n->enc_a[0];
+            NN_TRY(conv_in_fwd(n->x2, n->P16 + cp.w, n->cin, n->P + cp.b, d, n->cfg.leaky_alpha,
+                               v.ea, s));
+        } else if (int r = conv_act(n, in, n->enc_a[l], d, v.ea)) {
+            return r;
+        }
         if (int r = conv_act(n, v.ea, n->enc_b[l], d, v.eb)) return r;
     }
     const uint16_t* top = n->lv[n->L - 1].eb;
@@ -147,7 +162,16 @@ int run_forward(sde_nn* n, const int* d0) {
             NN_TRY(up_fwd(top, d, n->c[l + 1], Cf, n->c[l], v.cat, s));
             if (int r = conv_act(n, v.cat, cp, d, v.da)) return r;
         }
-        if (int r = conv_act(n, v.da, n->dec_b[l], d, v.db)) return r;
+        const ConvP& cb = n->dec_b[l];
+        if (l == 0 && cb.ci == 16 && cb.co == 16) {
+            // the head fused into the last conv; inference does not keep its
+            // activation
+            NN_TRY(conv_head_fwd(v.da, n->P16 + cb.w, n->P + cb.b, d, n->cfg.leaky_alpha,
+                                 n->cfg.train ? v.db : nullptr, n->P + n->head_w,
+                                 n->P + n->head_b, n->resid, n->out, s));
+            return SDE_OK;
+        }
+        if (int r = conv_act(n, v.da, cb, d, v.db)) return r;
         top = v.db;
     }
     NN_TRY(head_fwd(top, n->P + n->head_w, n->P + n->head_b, n->resid, nvox(d0), n->c0, n->out, s));
@@ -213,7 +237,8 @@ int alloc_all(sde_nn* n) {
     NN_TRY(dalloc(n, &n->P16, n->n_params));
     NN_TRY(hipMemset(n->P, 0, sizeof(float) * n->n_params));
     NN_TRY(hipMemset(n->P16, 0, sizeof(uint16_t) * n->n_params));
-    NN_TRY(dalloc(n, &n->x16, n->max_nv0 * n->cin));
+    if (c.train || !first_from_pairs(n)) NN_TRY(dalloc(n, &n->x16, n->max_nv0 * n->cin));
+    NN_TRY(dalloc(n, &n->x2, n->max_nv0));
     NN_TRY(dalloc(n, &n->resid, n->max_nv0));
     NN_TRY(dalloc(n, &n->out, n->max_nv0));
     NN_TRY(dalloc(n, &n->maxbits, 1));
@@ -401,7 +426,7 @@ int sde_nn_forward(sde_nn* net, const float* dose, const float* rho, int B, int 
     if (int r = check_dims(net, B, D, H, W)) return r;
     const int d0[4] = {B, D, H, W};
     hipStream_t s = library_stream();
-    NN_TRY(assemble_f32(dose, rho, nvox(d0), net->cin, net->x16, net->resid, s));
+    NN_TRY(assemble_f32(dose, rho, nvox(d0), net->cin, input_rows(net), net->x2, net->resid, s));
     if (int r = run_forward(net, d0)) return r;
     NN_TRY(hipMemcpyAsync(out, net->out, sizeof(float) * nvox(d0), hipMemcpyDeviceToDevice, s));
     return SDE_OK;
@@ -415,7 +440,7 @@ int sde_nn_loss_grad(sde_nn* net, const float* dose, const float* rho, const flo
     const int d0[4] = {B, D, H, W};
     const long long nv0 = nvox(d0);
     hipStream_t s = library_stream();
-    NN_TRY(assemble_f32(dose, rho, nv0, net->cin, net->x16, net->resid, s));
+    NN_TRY(assemble_f32(dose, rho, nv0, net->cin, input_rows(net), net->x2, net->resid, s));
     if (int r = run_forward(net, d0)) return r;
     // dL/dout overwrites the output buffer (the forward result is not kept)
     NN_TRY(mse(net->out, target, weight, nv0, net->out, net->loss_part, s));
@@ -452,7 +477,8 @@ int sde_nn_denoise(sde_nn* net, const double* dose, const float* rho, int nx, in
     NN_TRY(fill_u32((uint32_t*)net->maxbits, 2, 0u, s));
     NN_TRY(max_abs(dose, (long long)nx * ny * nz, net->maxbits, s));
     const double* maxp = (const double*)net->maxbits;
-    NN_TRY(assemble_grid(dose, rho, src, dst, maxp, net->cin, net->x16, net->resid, s));
+    NN_TRY(assemble_grid(dose, rho, src, dst, maxp, net->cin, input_rows(net), net->x2, net->resid,
+                         s));
     if (int r = run_forward(net, d0)) return r;
     NN_TRY(finish_grid(net->out, src, dst, maxp, out, s));
     return SDE_OK;

@@ -26,6 +26,17 @@ bool conv_cat_fwd_supported(int Cs, int Cu, int Co, long long nvox);
 hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_t* w,
                         const float* bias, const int* dims, int Cs, int Cu, int Co, float alpha,
                         int act, uint16_t* y16, hipStream_t s);
+// The last decoder conv (16 -> 16, LeakyReLU) with the head fused in: y16
+// (nullable) as conv_fwd stores it, and out[v] = head_b + resid[v] +
+// sum_c head_w[c] y16[v][c] summed per 4 channels, the four partial sums
+// added pairwise.
+hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
+                         float alpha, uint16_t* y16, const float* head_w, const float* head_b,
+                         const float* resid, float* out, hipStream_t s);
+// The first layer's conv_fwd (16 outputs, LeakyReLU, bf16 output) from the
+// input's two used channels as bf16 pairs x2 (weights [16][27][cin]).
+hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
+                       const int* dims, float alpha, uint16_t* y16, hipStream_t s);
 // wt[ci][26 - t][co] = w[co][t][ci] (weights of the input-gradient conv)
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
 // weight gradient: part needs wgrad_part_floats floats; dw [Co][27][Ci], db [Co]
@@ -51,13 +62,15 @@ hipError_t copy_channels(const uint16_t* x, const int* dims, int C, int Cf, int 
 hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, float* dx,
                       hipStream_t s);
 // network input from normalised FP32 maps (rho nullable): channel 0 dose,
-// channel 1 density, the rest zero; resid = dose
+// channel 1 density, the rest zero, as Cx-channel rows x (nullable) and as
+// bf16 pairs x2[v] = dose | density << 16 (nullable); resid = dose
 hipError_t assemble_f32(const float* dose, const float* rho, long long nv, int Cx, uint16_t* x,
-                        float* resid, hipStream_t s);
+                        uint32_t* x2, float* resid, hipStream_t s);
 // network input from a dose grid [nz][ny][nx] (FP64) divided by *maxp, zero
 // padded into [D][H][W]; rho (FP32, nullable) padded likewise
 hipError_t assemble_grid(const double* dose, const float* rho, const int* src, const int* dst,
-                         const double* maxp, int Cx, uint16_t* x, float* resid, hipStream_t s);
+                         const double* maxp, int Cx, uint16_t* x, uint32_t* x2, float* resid,
+                         hipStream_t s);
 // out (FP64 [nz][ny][nx]) = max(0, net[D][H][W] cropped) * (*maxp)
 hipError_t finish_grid(const float* net, const int* src, const int* dst, const double* maxp,
                        double* out, hipStream_t s);

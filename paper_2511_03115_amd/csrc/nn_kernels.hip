@@ -337,6 +337,11 @@ __host__ __device__ constexpr int halo_elem(int k) {
 }
 
 constexpr int kXcds = 8;
+// Below this many bricks a launch of one workgroup per brick leaves the
+// device partly idle (256 CUs, two or more workgroups each), so the brick
+// kernels split 64 output channels into two groups of 32, one per
+// blockIdx.y.
+constexpr long long kFewBricks = 2048;
 
 __device__ __forceinline__ int xcd_contiguous(int bid, int nblocks) {
     const int q = nblocks / kXcds, r = nblocks % kXcds;
@@ -368,6 +373,12 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     const int b = bid / nbz;
     const int x0 = bx * kRX, y0 = by * kRY, z0 = bz * kRZ;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+    // output channels [cg, cg + 16 NT) of Co (blockIdx.y picks the group)
+    const int cg = blockIdx.y * NT * 16;
+    w += (long long)cg * K;
+    if (bias) bias += cg;
+    if (y16) y16 += cg;
+    if (y32) y32 += cg;
     // Loads go through buffer resources with 32-bit offsets (the host keeps
     // every operand below 2 GiB); a load that must give zeros (outside the
     // volume, past the last K step) reads offset 0 and is replaced by zero,
@@ -553,21 +564,43 @@ constexpr int kOob = 0x7ff00000;   // a buffer offset past every operand
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-template <int CI, int CS, bool F32>
+// Output of the row-reuse kernel: bf16 only (y16), FP32 (y32, added to when
+// accumulate; y16 as well when non-null), or the network's head fused in
+// (bf16 y16 when non-null, and out[v] = b + resid[v] + sum_c w[c] y[v][c]
+// over the bf16-rounded outputs: each lane quarter sums its 4 channels in
+// order, the quarters are added pairwise, (0 + 1) + (2 + 3)).
+enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2 };
+struct HeadArgs {
+    const float* w;       // [16]
+    const float* b;       // [1]
+    const float* resid;   // per voxel
+    float* out;           // per voxel
+};
+
+template <int CI, int CS, int OUT>
 __global__ void __launch_bounds__(256) k_conv_rows(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ xl,
                                                    const uint16_t* __restrict__ w,
                                                    const float* __restrict__ bias, Geo g,
                                                    float alpha, int act,
                                                    uint16_t* __restrict__ y16,
-                                                   float* __restrict__ y32, int accumulate) {
-    constexpr int MT = 4, K = 27 * CI, ROW = brick_row(CI), GV = CI / 8;
+                                                   float* __restrict__ y32, int accumulate,
+                                                   HeadArgs head) {
+    constexpr bool F32 = OUT == kOutF32;
+    constexpr int MT = 4, K = 27 * CI, ROW = brick_row(CI);
     constexpr int NB = CI / 16, NU = 9 * NB, NP = (NU + 1) / 2;
-    constexpr int RU = (kRX + 2) * GV, NROW = (kRZ + 2) * (kRY + 2), RP = 256 / RU;
-    constexpr int NUR = (NROW + RP - 1) / RP;
+    constexpr int HX = kRX + 2, HY = kRY + 2, HZ = kRZ + 2;
+    // Staging: a "column" is one 16-byte unit of every halo plane, fixed
+    // (y, x, channel group); a thread owns columns t, t + 256, ... and loads
+    // them in all HZ planes, so its per-column offsets are worked out once
+    // and the planes differ by a scalar stride.  The columns of x (CS
+    // channels) come first, those of xl after them.
+    constexpr int GS = CS / 8, GL = (CI - CS) / 8;
+    constexpr int NCS = HY * HX * GS, NCOL = NCS + HY * HX * GL;
+    constexpr int NC = (NCOL + 255) / 256;
     static_assert(CI % 16 == 0 && CS % 8 == 0, "16-channel blocks");
     // [kRVox][ROW] halo brick, then one spare 16-byte slot per thread for
-    // the staging stores that fall outside the brick
+    // the staging stores of a thread's unused columns
     extern __shared__ __align__(16) uint16_t hx[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
     const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
@@ -589,96 +622,159 @@ __global__ void __launch_bounds__(256) k_conv_rows(const uint16_t* __restrict__ 
         }
     }
 
-    // staging: a thread owns one 16-byte column (voxel hxx of a halo row,
-    // channels [c, c + 8)) and rows r0, r0 + RP, ...
-    const int col = threadIdx.x % RU, r0 = threadIdx.x / RU;
-    const int hxx = col / GV, c = (col - hxx * GV) * 8;
-    const bool sk = CS == CI || c < CS;
+    // per column: halo (y, x), LDS slot, byte offset from the brick's corner
+    // voxel (fine for x; for xl the corner of the coarse parents)
+    const int Dd = g.D >> 1, Hd = g.H >> 1, Wd = g.W >> 1;
+    int cy[NC], cx[NC], lo[NC], ro[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int col = (int)threadIdx.x + 256 * k;
+        const bool used = col < NCOL, fine = col < NCS;
+        const int cc = !used ? 0 : fine ? col : col - NCS, gw = fine || GL == 0 ? GS : GL;
+        const int gg = cc % gw, xy = cc / gw, yv = xy / HX;
+        cx[k] = xy % HX;
+        cy[k] = used ? yv : -(1 << 20);   // unused columns never pass the y test
+        lo[k] = used ? (xy * ROW + (fine ? 0 : CS) + gg * 8) * 2
+                     : (kRVox * ROW + (int)threadIdx.x * 8) * 2;
+        ro[k] = fine || !used
+                    ? ((yv * g.W + cx[k]) * CS + gg * 8) * 2
+                    : ((((yv + 1) >> 1) * Wd + ((cx[k] + 1) >> 1)) * (CI - CS) + gg * 8) * 2;
+    }
     const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CS);
     const __amdgpu_buffer_rsrc_t lr = rsrc16(CS < CI ? xl : x, CS < CI ? g.nvox() / 8 * (CI - CS) : 0);
-    auto decode = [&](int bid, int& x0, int& y0, int& z0, int& b) {
-        const int bx = bid % nbx;
-        bid /= nbx;
-        const int by = bid % nby;
-        bid /= nby;
-        const int bz = bid % nbz;
-        b = bid / nbz;
-        x0 = bx * kRX;
-        y0 = by * kRY;
-        z0 = bz * kRZ;
-    };
-    auto load_brick = [&](int brick, uint4 (&st)[NUR]) {
-        int x0, y0, z0, b;
-        decode(brick, x0, y0, z0, b);
-        const int xx = x0 - 1 + hxx;
-        const bool xin = r0 < RP && xx >= 0 && xx < g.W;
-#pragma unroll
-        for (int u = 0; u < NUR; ++u) {
-            const int row = r0 + RP * u;
-            const int hzz = row / (kRY + 2), hyy = row - hzz * (kRY + 2);
-            const int yy = y0 - 1 + hyy, zz = z0 - 1 + hzz;
-            const bool in = xin && row < NROW && yy >= 0 && zz >= 0 && yy < g.H && zz < g.D;
-            const int ox = (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CS * 2) + c * 2;
-            st[u] = __builtin_bit_cast(
-                uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, in && sk ? ox : kOob, 0, 0));
-            if constexpr (CS < CI) {
-                const int Dd = g.D >> 1, Hd = g.H >> 1, Wd = g.W >> 1;
-                const int ol = (((b * Dd + (zz >> 1)) * Hd + (yy >> 1)) * Wd + (xx >> 1)) *
-                                   ((CI - CS) * 2) + (c - CS) * 2;
-                const uint4 v = __builtin_bit_cast(
-                    uint4, __builtin_amdgcn_raw_buffer_load_b128(lr, in && !sk ? ol : kOob, 0, 0));
-                st[u].x |= v.x;
-                st[u].y |= v.y;
-                st[u].z |= v.z;
-                st[u].w |= v.w;
-            }
-        }
-    };
+    const int planeb = g.H * g.W * CS * 2, planel = Hd * Wd * (CI - CS) * 2;
 
-    // this XCD's contiguous range of bricks and its workgroups
+    // bricks: this XCD's contiguous range; the brick coordinates advance by
+    // gn with mixed-radix carries (no divisions in the loop)
     const int xcd = blockIdx.x % kXcds, gi = blockIdx.x / kXcds;
     const int gn = ((int)gridDim.x - xcd + kXcds - 1) / kXcds;
     const int per = nbk / kXcds, rem = nbk % kXcds;
     const int s0 = xcd * per + (xcd < rem ? xcd : rem), s1 = s0 + per + (xcd < rem ? 1 : 0);
-    const int rbase = ((wave * (kRY + 2)) * (kRX + 2) + (lane & 15)) * ROW + (q & 1) * 8;
-    const int sbase = (r0 * (kRX + 2) + hxx) * ROW + c;
-    uint16_t* const spare = hx + kRVox * ROW + threadIdx.x * 8;
+    struct Bk { int x, y, z, b; };
+    auto split = [&](int bid) {
+        Bk r;
+        r.x = bid % nbx;
+        bid /= nbx;
+        r.y = bid % nby;
+        bid /= nby;
+        r.z = bid % nbz;
+        r.b = bid / nbz;
+        return r;
+    };
+    const Bk step = split(gn);
+    auto advance = [&](Bk r) {
+        r.x += step.x;
+        int c = r.x >= nbx;
+        r.x -= c ? nbx : 0;
+        r.y += step.y + c;
+        c = r.y >= nby;
+        r.y -= c ? nby : 0;
+        r.z += step.z + c;
+        c = r.z >= nbz;
+        r.z -= c ? nbz : 0;
+        r.b += step.b + c;
+        return r;
+    };
+    auto load_brick = [&](const Bk& bk, uint4 (&st)[NC][HZ]) {
+        const int x0 = bk.x * kRX, y0 = bk.y * kRY, z0 = bk.z * kRZ;
+        // corner voxel (x0 - 1, y0 - 1, z0 - 1) and its coarse parent's
+        // corner (x0 / 2 - 1, ...): scalar, possibly negative
+        const int cf = (((bk.b * g.D + z0 - 1) * g.H + y0 - 1) * g.W + x0 - 1) * (CS * 2);
+        const int cl = (((bk.b * Dd + (z0 >> 1) - 1) * Hd + (y0 >> 1) - 1) * Wd + (x0 >> 1) - 1) *
+                       ((CI - CS) * 2);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int xx = x0 - 1 + cx[k], yy = y0 - 1 + cy[k];
+            const bool cin = xx >= 0 && xx < g.W && yy >= 0 && yy < g.H;
+            const int col0 = 256 * k;   // this pass's first column: which sources it may hold
+#pragma unroll
+            for (int hz = 0; hz < HZ; ++hz) {
+                const int zz = z0 - 1 + hz;
+                const bool in = cin && zz >= 0 && zz < g.D;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (col0 < NCS) {
+                    const bool f = (int)threadIdx.x + col0 < NCS;
+                    v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                      xr, in && f ? cf + hz * planeb + ro[k] : kOob,
+                                                      0, 0));
+                }
+                if (CS < CI && col0 + 255 >= NCS) {
+                    const bool f = (int)threadIdx.x + col0 >= NCS;
+                    const uint4 u = __builtin_bit_cast(
+                        uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                   lr, in && f ? cl + ((hz + 1) >> 1) * planel + ro[k] : kOob, 0, 0));
+                    v.x |= u.x;
+                    v.y |= u.y;
+                    v.z |= u.z;
+                    v.w |= u.w;
+                }
+                st[k][hz] = v;
+            }
+        }
+    };
+
+    const int rbase = ((wave * HY) * HX + (lane & 15)) * ROW + (q & 1) * 8;
     float bq[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) bq[i] = bias ? bias[q * 4 + i] : 0.0f;
     // r > 0 ? r : slope r is LeakyReLU(r, alpha) for any alpha, and r when act == 0
     const float slope = act ? alpha : 1.0f;
     const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, y16 ? g.nvox() * 16 : 0);
-    uint4 st[NUR];
+    float hw[4] = {0.f, 0.f, 0.f, 0.f}, hb = 0.0f;
+    __amdgpu_buffer_rsrc_t rr_, or_;
+    if constexpr (OUT == kOutHead) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hw[i] = head.w[q * 4 + i];
+        hb = head.b[0];
+        rr_ = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(head.resid), 0,
+                                                (int)(g.nvox() * 4), 0x00020000);
+        or_ = __builtin_amdgcn_make_buffer_rsrc(head.out, 0, (int)(g.nvox() * 4), 0x00020000);
+    }
+    uint4 st[NC][HZ];
     int brick = s0 + gi;
-    if (brick < s1) load_brick(brick, st);
+    Bk cur = split(brick < s1 ? brick : 0);
+    if (brick < s1) load_brick(cur, st);
     // every load so far has landed (the weights stay live across the loop;
     // without this the compiler's wait counts would assume them pending)
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     for (; brick < s1; brick += gn) {
         __syncthreads();   // the previous brick's LDS reads are done
 #pragma unroll
-        for (int u = 0; u < NUR; ++u) {
-            const bool ok = r0 < RP && r0 + RP * u < NROW;
-            *reinterpret_cast<uint4*>(ok ? hx + sbase + u * RP * (kRX + 2) * ROW : spare) = st[u];
-        }
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int hz = 0; hz < HZ; ++hz)
+                *reinterpret_cast<uint4*>(reinterpret_cast<char*>(hx) + lo[k] +
+                                          (NC * 256 > NCOL && 256 * k + 255 >= NCOL
+                                               ? ((int)threadIdx.x + 256 * k < NCOL ? hz : 0)
+                                               : hz) * (HY * HX * ROW * 2)) = st[k][hz];
         __syncthreads();
-        if (brick + gn < s1) load_brick(brick + gn, st);   // in flight during the MFMAs
+        const Bk nxt = advance(cur);
+        if (brick + gn < s1) load_brick(nxt, st);   // in flight during the MFMAs
+        // output voxels of this lane: (x0 + lane % 16, y0 + m, z0 + wave)
+        const int xx = cur.x * kRX + (lane & 15), y0 = cur.y * kRY, zz = cur.z * kRZ + wave;
+        const bool xzin = zz < g.D && xx < g.W;
+        const int v0 = ((cur.b * g.D + zz) * g.H + y0) * g.W + xx;
+        float res[MT];   // the head's residual input, loaded during the MFMAs
+        if constexpr (OUT == kOutHead) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                res[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    rr_, xzin && y0 + m < g.H ? (v0 + m * g.W) * 4 : kOob, 0, 0));
+        }
+        // the accumulators start at the bias
         f32x4 acc[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < MT; ++m) acc[m] = f32x4{bq[0], bq[1], bq[2], bq[3]};
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int u0 = 2 * p, u1 = 2 * p + 1 < NU ? 2 * p + 1 : 2 * p;
-            const int o0 = ((u0 / (3 * NB)) * (kRY + 2) * (kRX + 2) + (u0 / NB) % 3) * ROW +
-                           (u0 % NB) * 16;
-            const int o1 = ((u1 / (3 * NB)) * (kRY + 2) * (kRX + 2) + (u1 / NB) % 3) * ROW +
-                           (u1 % NB) * 16;
+            const int o0 = ((u0 / (3 * NB)) * HY * HX + (u0 / NB) % 3) * ROW + (u0 % NB) * 16;
+            const int o1 = ((u1 / (3 * NB)) * HY * HX + (u1 / NB) % 3) * ROW + (u1 % NB) * 16;
             const int o = (q & 2) ? o1 : o0;
             bf16x8 a[MT + 2];
 #pragma unroll
             for (int i = 0; i < MT + 2; ++i)
-                a[i] = as_bf16x8(*reinterpret_cast<const uint4*>(hx + rbase + o + i * (kRX + 2) * ROW));
+                a[i] = as_bf16x8(*reinterpret_cast<const uint4*>(hx + rbase + o + i * HX * ROW));
 #pragma unroll
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -687,47 +783,193 @@ __global__ void __launch_bounds__(256) k_conv_rows(const uint16_t* __restrict__ 
                                                                      0, 0, 0);
         }
         // acc[m][i]: output channel 4 q + i of voxel (x0 + lane % 16, y0 + m, z0 + wave)
-        int x0, y0, z0, b;
-        decode(brick, x0, y0, z0, b);
-        const int xx = x0 + (lane & 15), zz = z0 + wave;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-            const int yy = y0 + m;
-            const bool in = zz < g.D && yy < g.H && xx < g.W;
-            const int v = ((b * g.D + zz) * g.H + yy) * g.W + xx;
+            const bool in = xzin && y0 + m < g.H;
+            const int v = v0 + m * g.W;
             float r[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                r[i] = acc[m][i] + bq[i];
-                r[i] = r[i] > 0.0f ? r[i] : slope * r[i];   // LeakyReLU, or identity
-            }
+            for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : slope * acc[m][i];
             if constexpr (!F32) {
                 // a store past the end of the resource is dropped: no branch
-                const uint32_t lo = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
-                const uint32_t hi = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
-                __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo, hi}, yr,
+                const uint32_t lo16 = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
+                const uint32_t hi16 = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
                                                       in ? (v * 16 + q * 4) * 2 : kOob, 0, 0);
-                continue;
+                if constexpr (OUT == kOutHead) {
+                    // the head on the stored (bf16) values
+                    float p = hw[0] * __uint_as_float(lo16 << 16);
+                    p = __builtin_fmaf(hw[1], __uint_as_float(lo16 & 0xFFFF0000u), p);
+                    p = __builtin_fmaf(hw[2], __uint_as_float(hi16 << 16), p);
+                    p = __builtin_fmaf(hw[3], __uint_as_float(hi16 & 0xFFFF0000u), p);
+                    p += __shfl_xor(p, 16);
+                    p += __shfl_xor(p, 32);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((hb + res[m]) + p), or_,
+                                                          in && q == 0 ? v * 4 : kOob, 0, 0);
+                }
             } else {
-            if (!in) continue;
-            if (y16) {
-                uint2 pk;
-                pk.x = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
-                pk.y = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
-                *reinterpret_cast<uint2*>(y16 + (long long)v * 16 + q * 4) = pk;
-            }
-            float4* d = reinterpret_cast<float4*>(y32 + (long long)v * 16 + q * 4);
-            float4 o4 = make_float4(r[0], r[1], r[2], r[3]);
-            if (accumulate) {
-                const float4 prev = *d;
-                o4.x += prev.x;
-                o4.y += prev.y;
-                o4.z += prev.z;
-                o4.w += prev.w;
-            }
-            *d = o4;
+                if (!in) continue;
+                if (y16) {
+                    uint2 pk;
+                    pk.x = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
+                    pk.y = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+                    *reinterpret_cast<uint2*>(y16 + (long long)v * 16 + q * 4) = pk;
+                }
+                float4* d = reinterpret_cast<float4*>(y32 + (long long)v * 16 + q * 4);
+                float4 o4 = make_float4(r[0], r[1], r[2], r[3]);
+                if (accumulate) {
+                    const float4 prev = *d;
+                    o4.x += prev.x;
+                    o4.y += prev.y;
+                    o4.z += prev.z;
+                    o4.w += prev.w;
+                }
+                *d = o4;
             }
         }
+        cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The first convolution (16 outputs) from the network input's two used
+// channels, normalised dose and density, packed as one 32-bit bf16 pair per
+// voxel (x2[v] = bf16(d) | bf16(rho) << 16); the other input channels are
+// zero and drop out of the sum.  K = 27 taps x 2 channels, k = 2 t + c,
+// padded to two K steps of 32 (taps 27..31 have zero weights).  Persistent
+// over 4 x 4 x 16 bricks like k_conv_rows: the weights are gathered into
+// registers once, the next brick's halo (6 x 6 x 18 pairs, 2.6 KB) is
+// loaded while the current one feeds the matrix cores, and a lane's input
+// fragment is its 4 taps x 2 channels, read as 4 pairs from the halo.
+// Weights [16][27][cin]: only channels 0 and 1 are read.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2,
+                                                 const uint16_t* __restrict__ w, int cin,
+                                                 const float* __restrict__ bias, Geo g,
+                                                 float alpha, uint16_t* __restrict__ y16) {
+    constexpr int MT = 4, HX = kRX + 2, HY = kRY + 2, HZ = kRZ + 2;
+    constexpr int NH = HZ * HY * HX, NL = (NH + 255) / 256;
+    __shared__ uint32_t hx[NH + 256];   // halo pairs, then a spare slot per thread
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+    const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
+    const int nbk = nbx * nby * nbz * g.B;
+
+    // A = W[co][k]: lane (co = lane % 16, quarter q) holds k = 32 s + 8 q + [0, 8),
+    // i.e. taps 16 s + 4 q + [0, 4), two channels each, as 4 32-bit words
+    const __amdgpu_buffer_rsrc_t wr = rsrc16(w, 16LL * 27 * cin);
+    bf16x8 wa[2];
+    int off[2][4];   // LDS word offset of each of the lane's taps from the row-0 slot
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+        uint32_t wd[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 16 * s2 + 4 * q + i;
+            wd[i] = __builtin_amdgcn_raw_buffer_load_b32(
+                wr, t < 27 ? (((lane & 15) * 27 + t) * cin) * 2 : kOob, 0, 0);
+            off[s2][i] = t < 27 ? ((t / 9) * HY + (t / 3) % 3) * HX + t % 3 : 0;
+        }
+        wa[s2] = as_bf16x8(make_uint4(wd[0], wd[1], wd[2], wd[3]));
+    }
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(x2), 0, (int)(g.nvox() * 4), 0x00020000);
+    const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, g.nvox() * 16);
+    // staging: thread t loads halo slots t, t + 256, t + 512 (< NH)
+    int sy[NL], sx[NL], sz[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int h = (int)threadIdx.x + 256 * k;
+        sx[k] = h % HX;
+        sy[k] = (h / HX) % HY;
+        sz[k] = h < NH ? h / (HX * HY) : -(1 << 20);
+    }
+    struct Bk { int x, y, z, b; };
+    auto split = [&](int bid) {
+        Bk r;
+        r.x = bid % nbx;
+        bid /= nbx;
+        r.y = bid % nby;
+        bid /= nby;
+        r.z = bid % nbz;
+        r.b = bid / nbz;
+        return r;
+    };
+    const int xcd = blockIdx.x % kXcds, gi = blockIdx.x / kXcds;
+    const int gn = ((int)gridDim.x - xcd + kXcds - 1) / kXcds;
+    const int per = nbk / kXcds, rem = nbk % kXcds;
+    const int s0 = xcd * per + (xcd < rem ? xcd : rem), s1 = s0 + per + (xcd < rem ? 1 : 0);
+    const Bk step = split(gn);
+    auto advance = [&](Bk r) {
+        r.x += step.x;
+        int c = r.x >= nbx;
+        r.x -= c ? nbx : 0;
+        r.y += step.y + c;
+        c = r.y >= nby;
+        r.y -= c ? nby : 0;
+        r.z += step.z + c;
+        c = r.z >= nbz;
+        r.z -= c ? nbz : 0;
+        r.b += step.b + c;
+        return r;
+    };
+    auto load_brick = [&](const Bk& bk, uint32_t (&st)[NL]) {
+        const int x0 = bk.x * kRX, y0 = bk.y * kRY, z0 = bk.z * kRZ;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int xx = x0 - 1 + sx[k], yy = y0 - 1 + sy[k], zz = z0 - 1 + sz[k];
+            const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D;
+            st[k] = __builtin_amdgcn_raw_buffer_load_b32(
+                xr, in ? (((bk.b * g.D + zz) * g.H + yy) * g.W + xx) * 4 : kOob, 0, 0);
+        }
+    };
+    float bq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bq[i] = bias ? bias[q * 4 + i] : 0.0f;
+    const int rbase = (wave * HY) * HX + (lane & 15);   // word offset of the lane's row-0 slot
+    uint32_t st[NL];
+    int brick = s0 + gi;
+    Bk cur = split(brick < s1 ? brick : 0);
+    if (brick < s1) load_brick(cur, st);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the weights have landed
+    for (; brick < s1; brick += gn) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int h = (int)threadIdx.x + 256 * k;
+            hx[h < NH ? h : NH + (int)threadIdx.x] = st[k];
+        }
+        __syncthreads();
+        const Bk nxt = advance(cur);
+        if (brick + gn < s1) load_brick(nxt, st);
+        f32x4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            acc[m] = f32x4{bq[0], bq[1], bq[2], bq[3]};
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int b0 = rbase + m * HX;
+                const uint4 bv = make_uint4(hx[b0 + off[s2][0]], hx[b0 + off[s2][1]],
+                                            hx[b0 + off[s2][2]], hx[b0 + off[s2][3]]);
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s2], as_bf16x8(bv), acc[m], 0,
+                                                                 0, 0);
+            }
+        }
+        const int xx = cur.x * kRX + (lane & 15), y0 = cur.y * kRY, zz = cur.z * kRZ + wave;
+        const bool xzin = zz < g.D && xx < g.W;
+        const int v0 = ((cur.b * g.D + zz) * g.H + y0) * g.W + xx;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const bool in = xzin && y0 + m < g.H;
+            float r[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : alpha * acc[m][i];
+            const uint32_t lo16 = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
+            const uint32_t hi16 = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
+                                                  in ? ((v0 + m * g.W) * 16 + q * 4) * 2 : kOob, 0,
+                                                  0);
+        }
+        cur = nxt;
     }
 }
 
@@ -773,6 +1015,12 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __rest
     const int x0 = bx * kRX, y0 = by * kRY, z0 = bz * kRZ;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
     const int K = 27 * Ci, P = Ci / CP, cu = Ci - cs;
+    // output channels [cg, cg + 16 NT) of Co (blockIdx.y picks the group)
+    const int cg = blockIdx.y * NT * 16;
+    w += (long long)cg * K;
+    if (bias) bias += cg;
+    if (y16) y16 += cg;
+    if (y32) y32 += cg;
     auto load_brick = [&](uint4 (&st)[NU], int p) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -1413,13 +1661,21 @@ __device__ __forceinline__ void store_input_row(uint16_t* row, int Cx, float d, 
     for (int c = 1; c < Cx / 8; ++c) q[c] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// The network input: the Cx-channel rows x (when non-null) and the two used
+// channels as one bf16 pair per voxel, x2 (when non-null).
+__device__ __forceinline__ void store_input(uint16_t* x, uint32_t* x2, long long v, int Cx, float d,
+                                            float r) {
+    if (x) store_input_row(x + v * Cx, Cx, d, r);
+    if (x2) x2[v] = (uint32_t)f2bf(d) | ((uint32_t)f2bf(r) << 16);
+}
+
 __global__ void k_assemble_f32(const float* dose, const float* rho, long long nv, int Cx,
-                               uint16_t* x, float* resid) {
+                               uint16_t* x, uint32_t* x2, float* resid) {
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
          v += (long long)gridDim.x * blockDim.x) {
         const float d = dose[v];
         resid[v] = d;
-        store_input_row(x + v * Cx, Cx, d, rho ? rho[v] : 0.0f);
+        store_input(x, x2, v, Cx, d, rho ? rho[v] : 0.0f);
     }
 }
 
@@ -1427,7 +1683,7 @@ __global__ void k_assemble_f32(const float* dose, const float* rho, long long nv
 // padded into [D][H][W] (batch 1).
 __global__ void k_assemble_grid(const double* dose, const float* rho, int nx, int ny, int nz,
                                 int W, int H, int D, const double* maxp, int Cx, uint16_t* x,
-                                float* resid) {
+                                uint32_t* x2, float* resid) {
     const long long nv = (long long)W * H * D;
     const double m = *maxp;
     const double inv = m > 0.0 ? 1.0 / m : 0.0;
@@ -1441,7 +1697,7 @@ __global__ void k_assemble_grid(const double* dose, const float* rho, int nx, in
             r = rho ? rho[u] : 0.0f;
         }
         resid[v] = d;
-        store_input_row(x + v * Cx, Cx, d, r);
+        store_input(x, x2, v, Cx, d, r);
     }
 }
 
@@ -1485,7 +1741,12 @@ __global__ void k_prepare_pair(const double* low, const double* high, long long 
 }
 
 // Maximum of |a| as the bit pattern of a non-negative double (out zeroed first).
-__global__ void k_max_abs(const double* a, long long n, unsigned long long* out) {
+// max |a| as the bit pattern of a non-negative double (ordered like the
+// value): a wave reduction, then the workgroup's 4 waves through LDS, then
+// one atomic per workgroup (same-address atomics serialise in L2).
+__global__ void __launch_bounds__(256) k_max_abs(const double* a, long long n,
+                                                 unsigned long long* out) {
+    __shared__ unsigned long long red[4];
     double m = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
@@ -1496,7 +1757,13 @@ __global__ void k_max_abs(const double* a, long long n, unsigned long long* out)
         const unsigned long long c = __shfl_xor(b, o);
         b = c > b ? c : b;
     }
-    if ((threadIdx.x & 63) == 0) atomicMax(out, b);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = red[0];
+        for (int k = 1; k < 4; ++k) t = red[k] > t ? red[k] : t;
+        atomicMax(out, t);
+    }
 }
 
 // Head: out[v] = resid[v] + b + sum_c w[c] x[v][c] (1x1x1 conv to one channel).
@@ -1624,20 +1891,21 @@ inline int blocks_for(long long n, int bs = 256, int cap = 16384) {
 // The persistent row-reuse convolution: as many workgroups as the device
 // holds at once (the occupancy the compiler's register and LDS use allows),
 // at most one per brick.
-template <int CI, int CS, bool F32>
+template <int CI, int CS, int OUT>
 hipError_t launch_rows_as(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
                           const float* bias, Geo g, float alpha, int act, uint16_t* y16,
-                          float* y32, int accumulate, hipStream_t s) {
+                          float* y32, int accumulate, hipStream_t s, HeadArgs head = {}) {
+    constexpr bool F32 = OUT == kOutF32;
     constexpr size_t lds = ((size_t)kRVox * brick_row(CI) + 256 * 8) * sizeof(uint16_t);
     static const int cap = [] {
         if (lds > 64 * 1024 &&
-            hipFuncSetAttribute((const void*)k_conv_rows<CI, CS, F32>,
+            hipFuncSetAttribute((const void*)k_conv_rows<CI, CS, OUT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024) != hipSuccess)
             return 0;
         int dev = 0, cu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv_rows<CI, CS, F32>, 256,
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv_rows<CI, CS, OUT>, 256,
                                                          lds) != hipSuccess)
             return 0;
         return per * cu;
@@ -1648,8 +1916,8 @@ hipError_t launch_rows_as(const uint16_t* x, const uint16_t* xl, const uint16_t*
     if (nbk >= (1LL << 31) || g.nvox() * 16 * (F32 ? 4 : 2) >= (1LL << 31))
         return hipErrorInvalidValue;
     const int grid = (int)std::min<long long>(nbk, cap);
-    hipLaunchKernelGGL((k_conv_rows<CI, CS, F32>), dim3((unsigned)grid), dim3(256), lds, s, x, xl,
-                       w, bias, g, alpha, act, y16, y32, accumulate);
+    hipLaunchKernelGGL((k_conv_rows<CI, CS, OUT>), dim3((unsigned)grid), dim3(256), lds, s, x, xl,
+                       w, bias, g, alpha, act, y16, y32, accumulate, head);
     return hipGetLastError();
 }
 
@@ -1657,8 +1925,9 @@ template <int CI, int CS>
 hipError_t launch_rows(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
                        const float* bias, Geo g, float alpha, int act, uint16_t* y16, float* y32,
                        int accumulate, hipStream_t s) {
-    return y32 ? launch_rows_as<CI, CS, true>(x, xl, w, bias, g, alpha, act, y16, y32, accumulate, s)
-               : launch_rows_as<CI, CS, false>(x, xl, w, bias, g, alpha, act, y16, y32, 0, s);
+    return y32 ? launch_rows_as<CI, CS, kOutF32>(x, xl, w, bias, g, alpha, act, y16, y32,
+                                                  accumulate, s)
+               : launch_rows_as<CI, CS, kOutBf16>(x, xl, w, bias, g, alpha, act, y16, y32, 0, s);
 }
 
 }  // namespace
@@ -1684,8 +1953,8 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
                               ((g.D + kRZ - 1) / kRZ) * g.B;
         const size_t lds_r = (size_t)kRVox * (Ci + 8) * sizeof(uint16_t);
 #define LAUNCH_REG(CI, NT, CH)                                                             \
-    hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk), dim3(256), lds_r, s, x, \
-                       w, bias, g, Co, alpha, act, y16, y32, accumulate)
+    hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk, nt / NT), dim3(256), \
+                       lds_r, s, x, w, bias, g, Co, alpha, act, y16, y32, accumulate)
         // 16 outputs: the persistent row-reuse form
         if (Co == 16 && Ci == 16)
             return launch_rows<16, 16>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
@@ -1694,8 +1963,11 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         if (Co == 16 && Ci == 48)
             return launch_rows<48, 48>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
         bool done = true;
-        if (Ci == 16 && nt == 2) LAUNCH_REG(16, 2, 14);
-        else if (Ci == 32 && nt == 2) LAUNCH_REG(32, 2, 7);
+        // 32 outputs, or 64 in two groups when the bricks are too few to fill
+        // the device
+        const bool few = nbk < kFewBricks;
+        if (Ci == 16 && (nt == 2 || (nt == 4 && few))) LAUNCH_REG(16, 2, 14);
+        else if (Ci == 32 && (nt == 2 || (nt == 4 && few))) LAUNCH_REG(32, 2, 7);
         else done = false;
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
@@ -1704,9 +1976,9 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
         const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
-        if (nt == 2)
-            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk), dim3(256), lds_p, s,
-                               x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
+        if (nt == 2 || nbk < kFewBricks)   // 64 outputs on few bricks: two groups of 32
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk, nt / 2), dim3(256),
+                               lds_p, s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
                                accumulate);
         else
             hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256), lds_p, s,
@@ -1770,10 +2042,10 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
                           ((g.D + kRZ - 1) / kRZ) * g.B;
     if (Co == 32 || Co == 64) {
         const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
-        if (Co == 32)
-            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk), dim3(256), lds_p, s,
-                               skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16, nullptr,
-                               0);
+        if (Co == 32 || nbk < kFewBricks)   // 64 outputs on few bricks: two groups of 32
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk, Co / 32), dim3(256),
+                               lds_p, s, skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16,
+                               nullptr, 0);
         else
             hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256), lds_p, s,
                                skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16, nullptr,
@@ -1781,6 +2053,36 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
         return hipGetLastError();
     }
     return launch_rows<48, 16>(skip, low, w, bias, g, alpha, act, y16, nullptr, 0, s);
+}
+
+hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
+                         float alpha, uint16_t* y16, const float* head_w, const float* head_b,
+                         const float* resid, float* out, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (g.nvox() * 16 * 2 >= (1LL << 31)) return hipErrorInvalidValue;
+    return launch_rows_as<16, 16, kOutHead>(x, nullptr, w, bias, g, alpha, 1, y16, nullptr, 0, s,
+                                            HeadArgs{head_w, head_b, resid, out});
+}
+
+hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
+                       const int* dims, float alpha, uint16_t* y16, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (cin < 2 || !y16 || g.nvox() * 16 * 2 >= (1LL << 31)) return hipErrorInvalidValue;
+    static const int cap = [] {
+        int dev = 0, cu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_conv_in, 256, 0) != hipSuccess)
+            return 0;
+        return per * cu;
+    }();
+    if (cap <= 0) return hipErrorInvalidConfiguration;
+    const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                          ((g.D + kRZ - 1) / kRZ) * g.B;
+    const int grid = (int)std::min<long long>(nbk, cap);
+    hipLaunchKernelGGL(k_conv_in, dim3((unsigned)grid), dim3(256), 0, s, x2, w, cin, bias, g, alpha,
+                       y16);
+    return hipGetLastError();
 }
 
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s) {
@@ -1926,19 +2228,20 @@ hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, f
 }
 
 hipError_t assemble_f32(const float* dose, const float* rho, long long nv, int Cx, uint16_t* x,
-                        float* resid, hipStream_t s) {
+                        uint32_t* x2, float* resid, hipStream_t s) {
     if (Cx < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_assemble_f32, dim3(blocks_for(nv)), dim3(256), 0, s, dose, rho, nv, Cx, x,
-                       resid);
+                       x2, resid);
     return hipGetLastError();
 }
 
 hipError_t assemble_grid(const double* dose, const float* rho, const int* src, const int* dst,
-                         const double* maxp, int Cx, uint16_t* x, float* resid, hipStream_t s) {
+                         const double* maxp, int Cx, uint16_t* x, uint32_t* x2, float* resid,
+                         hipStream_t s) {
     if (Cx < 2) return hipErrorInvalidValue;
     const long long nv = (long long)dst[0] * dst[1] * dst[2];
     hipLaunchKernelGGL(k_assemble_grid, dim3(blocks_for(nv)), dim3(256), 0, s, dose, rho, src[2],
-                       src[1], src[0], dst[2], dst[1], dst[0], maxp, Cx, x, resid);
+                       src[1], src[0], dst[2], dst[1], dst[0], maxp, Cx, x, x2, resid);
     return hipGetLastError();
 }
 
