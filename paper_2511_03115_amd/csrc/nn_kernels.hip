@@ -26,6 +26,12 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 // float -> bf16, round to nearest even (the hardware conversion)
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// two floats rounded to bf16 (as f2bf) in one conversion: a | b << 16
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
 
 // LeakyReLU; for a slope in (0, 1] it is max(r, alpha r)
 __device__ __forceinline__ float lrelu(float r, float alpha) {
@@ -578,7 +584,8 @@ struct HeadArgs {
 };
 
 template <int CI, int CS, int OUT>
-__global__ void __launch_bounds__(256) k_conv_rows(const uint16_t* __restrict__ x,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CI == 16 ? 3 : 1)))
+k_conv_rows(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ xl,
                                                    const uint16_t* __restrict__ w,
                                                    const float* __restrict__ bias, Geo g,
@@ -792,8 +799,7 @@ __global__ void __launch_bounds__(256) k_conv_rows(const uint16_t* __restrict__ 
             for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : slope * acc[m][i];
             if constexpr (!F32) {
                 // a store past the end of the resource is dropped: no branch
-                const uint32_t lo16 = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
-                const uint32_t hi16 = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+                const uint32_t lo16 = pk_bf16(r[0], r[1]), hi16 = pk_bf16(r[2], r[3]);
                 __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
                                                       in ? (v * 16 + q * 4) * 2 : kOob, 0, 0);
                 if constexpr (OUT == kOutHead) {
@@ -874,14 +880,16 @@ __global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t*>(x2), 0, (int)(g.nvox() * 4), 0x00020000);
     const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, g.nvox() * 16);
-    // staging: thread t loads halo slots t, t + 256, t + 512 (< NH)
-    int sy[NL], sx[NL], sz[NL];
+    // staging: thread t loads halo slots t, t + 256, t + 512 (< NH), at byte
+    // offsets rel from the brick's corner voxel (x0 - 1, y0 - 1, z0 - 1)
+    int sy[NL], sx[NL], sz[NL], rel[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int h = (int)threadIdx.x + 256 * k;
         sx[k] = h % HX;
         sy[k] = (h / HX) % HY;
         sz[k] = h < NH ? h / (HX * HY) : -(1 << 20);
+        rel[k] = h < NH ? (((h / (HX * HY)) * g.H + sy[k]) * g.W + sx[k]) * 4 : 0;
     }
     struct Bk { int x, y, z, b; };
     auto split = [&](int bid) {
@@ -914,12 +922,21 @@ __global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2
     };
     auto load_brick = [&](const Bk& bk, uint32_t (&st)[NL]) {
         const int x0 = bk.x * kRX, y0 = bk.y * kRY, z0 = bk.z * kRZ;
+        const int corner = (((bk.b * g.D + z0 - 1) * g.H + y0 - 1) * g.W + x0 - 1) * 4;
+        if (x0 >= 1 && x0 + kRX < g.W && y0 >= 1 && y0 + kRY < g.H && z0 >= 1 &&
+            z0 + kRZ < g.D) {
+            // the halo lies inside the volume (uniform): no bounds tests
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int xx = x0 - 1 + sx[k], yy = y0 - 1 + sy[k], zz = z0 - 1 + sz[k];
-            const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D;
-            st[k] = __builtin_amdgcn_raw_buffer_load_b32(
-                xr, in ? (((bk.b * g.D + zz) * g.H + yy) * g.W + xx) * 4 : kOob, 0, 0);
+            for (int k = 0; k < NL; ++k)
+                st[k] = __builtin_amdgcn_raw_buffer_load_b32(
+                    xr, (int)threadIdx.x + 256 * k < NH ? corner + rel[k] : kOob, 0, 0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int xx = x0 - 1 + sx[k], yy = y0 - 1 + sy[k], zz = z0 - 1 + sz[k];
+                const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < g.W && yy < g.H && zz < g.D;
+                st[k] = __builtin_amdgcn_raw_buffer_load_b32(xr, in ? corner + rel[k] : kOob, 0, 0);
+            }
         }
     };
     float bq[4];
@@ -963,8 +980,7 @@ __global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2
             float r[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : alpha * acc[m][i];
-            const uint32_t lo16 = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
-            const uint32_t hi16 = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+            const uint32_t lo16 = pk_bf16(r[0], r[1]), hi16 = pk_bf16(r[2], r[3]);
             __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
                                                   in ? ((v0 + m * g.W) * 16 + q * 4) * 2 : kOob, 0,
                                                   0);
