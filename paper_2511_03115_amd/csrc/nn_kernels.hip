@@ -345,7 +345,7 @@ __host__ __device__ constexpr int halo_elem(int k) {
 constexpr int kXcds = 8;
 // Below this many bricks a launch of one workgroup per brick leaves the
 // device partly idle (256 CUs, two or more workgroups each), so the brick
-// kernels split 64 output channels into two groups of 32, one per
+// kernels split 64 or 128 output channels into groups of 32, one per
 // blockIdx.y.
 constexpr long long kFewBricks = 2048;
 
@@ -1720,14 +1720,11 @@ __global__ void k_assemble_grid(const double* dose, const float* rho, int nx, in
 // out[nz][ny][nx] = max(0, net cropped) * (*maxp)
 __global__ void k_finish_grid(const float* net, int nx, int ny, int nz, int W, int H,
                               const double* maxp, double* out) {
-    const long long n = (long long)nx * ny * nz;
-    const double m = *maxp;
-    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < n;
-         u += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(u % nx), j = (int)((u / nx) % ny), k = (int)(u / ((long long)nx * ny));
-        const float y = net[((long long)k * H + j) * W + i];
-        out[u] = y > 0.0f ? (double)y * m : 0.0;
-    }
+    // thread: voxel (i, j = blockIdx.y, k = blockIdx.z) of the dose grid
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= nx) return;
+    const float y = net[((long long)k * H + j) * W + i];
+    out[((long long)k * ny + j) * nx + i] = y > 0.0f ? (double)y * *maxp : 0.0;
 }
 
 // Training pair: low / m, high / m with m = *maxp (the low map's maximum),
@@ -1764,9 +1761,19 @@ __global__ void __launch_bounds__(256) k_max_abs(const double* a, long long n,
                                                  unsigned long long* out) {
     __shared__ unsigned long long red[4];
     double m = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        m = fmax(m, fabs(a[i]));
+    // 16-byte loads from the first 16-byte boundary; the elements before it
+    // and after the last full pair are read singly
+    const long long head = (reinterpret_cast<uintptr_t>(a) & 8) && n > 0 ? 1 : 0;
+    const long long n2 = (n - head) / 2, stride = (long long)gridDim.x * blockDim.x;
+    const double2* a2 = reinterpret_cast<const double2*>(a + head);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += stride) {
+        const double2 v = a2[i];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (head) m = fmax(m, fabs(a[0]));
+        if (head + 2 * n2 < n) m = fmax(m, fabs(a[n - 1]));
+    }
     unsigned long long b = (unsigned long long)__double_as_longlong(m);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1988,11 +1995,14 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
     }
-    if (Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4)) {   // wide input, channel passes
+    const bool few = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                         ((g.D + kRZ - 1) / kRZ) * g.B < kFewBricks;
+    if (Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4 || (nt == 8 && few))) {
+        // wide input, channel passes (on few bricks in groups of 32 outputs)
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
         const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
-        if (nt == 2 || nbk < kFewBricks)   // 64 outputs on few bricks: two groups of 32
+        if (nt == 2 || few)
             hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk, nt / 2), dim3(256),
                                lds_p, s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
                                accumulate);
@@ -2263,9 +2273,9 @@ hipError_t assemble_grid(const double* dose, const float* rho, const int* src, c
 
 hipError_t finish_grid(const float* net, const int* src, const int* dst, const double* maxp,
                        double* out, hipStream_t s) {
-    const long long n = (long long)src[0] * src[1] * src[2];
-    hipLaunchKernelGGL(k_finish_grid, dim3(blocks_for(n)), dim3(256), 0, s, net, src[2], src[1],
-                       src[0], dst[2], dst[1], maxp, out);
+    if (src[0] > 65535 || src[1] > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_finish_grid, dim3((unsigned)((src[2] + 255) / 256), src[1], src[0]),
+                       dim3(256), 0, s, net, src[2], src[1], src[0], dst[2], dst[1], maxp, out);
     return hipGetLastError();
 }
 
