@@ -68,7 +68,9 @@ struct sde_nn {
     float *resid = nullptr, *out = nullptr;
     std::vector<Level> lv;
     float *dout = nullptr, *loss_part = nullptr, *loss_dev = nullptr, *head_part = nullptr;
-    uint16_t *dz = nullptr, *wt = nullptr;
+    uint16_t* dz = nullptr;
+    uint16_t* dz2 = nullptr;      // the second bf16 output gradient of a 16 -> 16 chain
+    uint16_t* wt_all = nullptr;   // every layer's flipped weights (offsets as in P16)
     float* wpart = nullptr;
     unsigned long long* maxbits = nullptr;
     std::vector<void*> allocs;
@@ -178,20 +180,33 @@ int run_forward(sde_nn* n, const int* d0) {
     return SDE_OK;
 }
 
-// backward through conv + LeakyReLU: weight/bias gradients into G, input
-// gradient (FP32) into dx when non-null
+// backward through conv + LeakyReLU: weight/bias gradients into G; the
+// gradient at the conv's output is dz_ready (bf16, already through the
+// LeakyReLU derivative) when non-null, else lrelu_bwd(dy, y).  The input
+// gradient goes (FP32) into dx when non-null, or, through the LeakyReLU
+// derivative of the input activation y_in, (bf16) into dz_next when that is
+// non-null (16 -> 16 convs).  The flipped weights are in n->wt_all (offset cp.w).
 int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, const ConvP& cp,
-             const int* d, float* dx) {
+             const int* d, float* dx, const uint16_t* dz_ready = nullptr,
+             const uint16_t* y_in = nullptr, uint16_t* dz_next = nullptr) {
     hipStream_t s = library_stream();
-    NN_TRY(lrelu_bwd(dy, y, n->cfg.leaky_alpha, nvox(d) * cp.co, n->dz, s));
-    const int chunk = wgrad_chunk_for(d, cp.ci, cp.co, kMaxPartFloats);
-    NN_TRY(wgrad(n->dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
-    if (dx) {
-        NN_TRY(flip_transpose(n->P16 + cp.w, n->wt, cp.ci, cp.co, s));
-        NN_TRY(conv_fwd(n->dz, n->wt, nullptr, d, cp.co, cp.ci, 0.0f, 0, nullptr, dx, 0, s));
+    const uint16_t* dz = dz_ready;
+    if (!dz) {
+        NN_TRY(lrelu_bwd(dy, y, n->cfg.leaky_alpha, nvox(d) * cp.co, n->dz, s));
+        dz = n->dz;
     }
+    const int chunk = wgrad_chunk_for(d, cp.ci, cp.co, kMaxPartFloats);
+    NN_TRY(wgrad(dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
+    if (dz_next)
+        NN_TRY(conv_dz_fwd(dz, n->wt_all + cp.w, d, y_in, n->cfg.leaky_alpha, dz_next, s));
+    else if (dx)
+        NN_TRY(conv_fwd(dz, n->wt_all + cp.w, nullptr, d, cp.co, cp.ci, 0.0f, 0, nullptr, dx, 0, s));
     return SDE_OK;
 }
+
+// A 16 -> 16 conv whose input gradient feeds only the LeakyReLU before it
+// hands that layer its bf16 gradient directly.
+bool dz_chain(const ConvP& cp) { return cp.ci == 16 && cp.co == 16; }
 
 int run_backward(sde_nn* n, const int* d0) {
     hipStream_t s = library_stream();
@@ -200,6 +215,22 @@ int run_backward(sde_nn* n, const int* d0) {
     const long long nv0 = nvox(d0);
     const uint16_t* top0 = L > 1 ? n->lv[0].db : n->lv[0].eb;
     float* gtop0 = L > 1 ? n->lv[0].gDb : n->lv[0].gE;
+    // every layer's flipped weights, in one launch
+    FlipJobs fj;
+    long long start = 0;
+    for (auto* vec : {&n->enc_a, &n->enc_b, &n->dec_a, &n->dec_b})
+        for (const ConvP& cp : *vec) {
+            if (fj.n == kMaxFlipJobs) return SDE_E_INVALID;
+            fj.w[fj.n] = n->P16 + cp.w;
+            fj.wt[fj.n] = n->wt_all + cp.w;
+            fj.ci[fj.n] = cp.ci;
+            fj.co[fj.n] = cp.co;
+            fj.start[fj.n] = start;
+            start += 27LL * cp.ci * cp.co;
+            ++fj.n;
+        }
+    fj.start[fj.n] = start;
+    NN_TRY(flip_transpose_all(fj, s));
     NN_TRY(head_bwd(n->out /* holds dL/dout */, top0, n->P + n->head_w, nv0, n->c0, gtop0,
                     n->head_part, s));
     NN_TRY(sum_rows(n->head_part, head_bwd_blocks(nv0), n->c0 + 1, n->G + n->head_w, s));
@@ -208,8 +239,16 @@ int run_backward(sde_nn* n, const int* d0) {
         dims_at(d0, l + 1, dc);
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
-        if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa)) return r;
-        if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, v.gCat)) return r;
+        if (dz_chain(n->dec_b[l])) {
+            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, nullptr, v.da,
+                                 n->dz2))
+                return r;
+            if (int r = conv_bwd(n, nullptr, nullptr, v.cat, n->dec_a[l], d, v.gCat, n->dz2))
+                return r;
+        } else {
+            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa)) return r;
+            if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, v.gCat)) return r;
+        }
         NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
         float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
         NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s));
@@ -217,9 +256,19 @@ int run_backward(sde_nn* n, const int* d0) {
     for (int l = L - 1; l >= 0; --l) {
         dims_at(d0, l, d);
         Level& v = n->lv[l];
-        if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, v.gEa)) return r;
         const uint16_t* in = l == 0 ? n->x16 : v.pin;
-        if (int r = conv_bwd(n, v.gEa, v.ea, in, n->enc_a[l], d, l > 0 ? v.gP : nullptr)) return r;
+        if (dz_chain(n->enc_b[l])) {
+            if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, nullptr, nullptr, v.ea,
+                                 n->dz2))
+                return r;
+            if (int r = conv_bwd(n, nullptr, nullptr, in, n->enc_a[l], d, l > 0 ? v.gP : nullptr,
+                                 n->dz2))
+                return r;
+        } else {
+            if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, v.gEa)) return r;
+            if (int r = conv_bwd(n, v.gEa, v.ea, in, n->enc_a[l], d, l > 0 ? v.gP : nullptr))
+                return r;
+        }
         if (l > 0) {
             int df[4];
             dims_at(d0, l - 1, df);
@@ -276,7 +325,8 @@ int alloc_all(sde_nn* n) {
     NN_TRY(hipMemset(n->M, 0, sizeof(float) * n->n_params));
     NN_TRY(hipMemset(n->V, 0, sizeof(float) * n->n_params));
     NN_TRY(dalloc(n, &n->dz, n->max_nv0 * n->c0));
-    NN_TRY(dalloc(n, &n->wt, max_w));
+    NN_TRY(dalloc(n, &n->dz2, n->max_nv0 * 16));
+    NN_TRY(dalloc(n, &n->wt_all, n->n_params));
     NN_TRY(dalloc(n, &n->wpart, std::max(kMaxPartFloats, max_w)));
     NN_TRY(dalloc(n, &n->dout, n->max_nv0));
     NN_TRY(dalloc(n, &n->loss_part, mse_blocks(n->max_nv0)));

@@ -37,6 +37,21 @@ hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias
 // input's two used channels as bf16 pairs x2 (weights [16][27][cin]).
 hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
                        const int* dims, float alpha, uint16_t* y16, hipStream_t s);
+// The input gradient of a LeakyReLU layer through the next conv (16 -> 16):
+// dz = bf16(ym > 0 ? r : alpha r), r = conv(x, w) in FP32 (no bias); the same
+// values as conv_fwd into FP32 followed by lrelu_bwd.
+hipError_t conv_dz_fwd(const uint16_t* x, const uint16_t* w, const int* dims, const uint16_t* ym,
+                       float alpha, uint16_t* dz, hipStream_t s);
+// flip_transpose of several layers in one launch
+constexpr int kMaxFlipJobs = 32;
+struct FlipJobs {
+    int n = 0;
+    const uint16_t* w[kMaxFlipJobs];
+    uint16_t* wt[kMaxFlipJobs];
+    int ci[kMaxFlipJobs], co[kMaxFlipJobs];
+    long long start[kMaxFlipJobs + 1];
+};
+hipError_t flip_transpose_all(const FlipJobs& jobs, hipStream_t s);
 // wt[ci][26 - t][co] = w[co][t][ci] (weights of the input-gradient conv)
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
 // weight gradient: part needs wgrad_part_floats floats; dw [Co][27][Ci], db [Co]

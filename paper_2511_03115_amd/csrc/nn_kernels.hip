@@ -575,12 +575,16 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 // (bf16 y16 when non-null, and out[v] = b + resid[v] + sum_c w[c] y[v][c]
 // over the bf16-rounded outputs: each lane quarter sums its 4 channels in
 // order, the quarters are added pairwise, (0 + 1) + (2 + 3)).
-enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2 };
+// Or the input gradient of a LeakyReLU layer (kOutDz): dz[v][c] =
+// bf16(ym[v][c] > 0 ? r : alpha r) with r the FP32 conv output (no bias),
+// what conv_fwd into FP32 followed by lrelu_bwd gives.
+enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2, kOutDz = 3 };
 struct HeadArgs {
     const float* w;       // [16]
     const float* b;       // [1]
     const float* resid;   // per voxel
     float* out;           // per voxel
+    const uint16_t* ym;   // kOutDz: the layer's output activation, [voxel][16]
 };
 
 template <int CI, int CS, int OUT>
@@ -592,7 +596,7 @@ k_conv_rows(const uint16_t* __restrict__ x,
                                                    float alpha, int act,
                                                    uint16_t* __restrict__ y16,
                                                    float* __restrict__ y32, int accumulate,
-                                                   HeadArgs head) {
+                                                   HeadArgs head, int ys) {
     constexpr bool F32 = OUT == kOutF32;
     constexpr int MT = 4, K = 27 * CI, ROW = brick_row(CI);
     constexpr int NB = CI / 16, NU = 9 * NB, NP = (NU + 1) / 2;
@@ -612,6 +616,12 @@ k_conv_rows(const uint16_t* __restrict__ x,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
     const int nbx = (g.W + kRX - 1) / kRX, nby = (g.H + kRY - 1) / kRY, nbz = (g.D + kRZ - 1) / kRZ;
     const int nbk = nbx * nby * nbz * g.B;   // the host keeps it below 2^31
+    // output channels [16 blockIdx.y, + 16) of ys per voxel
+    const int cg = blockIdx.y * 16;
+    w += (long long)cg * K;
+    if (bias) bias += cg;
+    if (y16) y16 += cg;
+    if (y32) y32 += cg;
 
     // the weight fragments of every pair and dy (a padded half gets zeros)
     const __amdgpu_buffer_rsrc_t wr = rsrc16(w, 16LL * K);
@@ -726,9 +736,12 @@ k_conv_rows(const uint16_t* __restrict__ x,
     for (int i = 0; i < 4; ++i) bq[i] = bias ? bias[q * 4 + i] : 0.0f;
     // r > 0 ? r : slope r is LeakyReLU(r, alpha) for any alpha, and r when act == 0
     const float slope = act ? alpha : 1.0f;
-    const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, y16 ? g.nvox() * 16 : 0);
+    const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, y16 ? g.nvox() * ys - cg : 0);
     float hw[4] = {0.f, 0.f, 0.f, 0.f}, hb = 0.0f;
     __amdgpu_buffer_rsrc_t rr_, or_;
+    if constexpr (OUT == kOutDz)
+        rr_ = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(head.ym), 0,
+                                                (int)(g.nvox() * 32), 0x00020000);
     if constexpr (OUT == kOutHead) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) hw[i] = head.w[q * 4 + i];
@@ -762,11 +775,18 @@ k_conv_rows(const uint16_t* __restrict__ x,
         const bool xzin = zz < g.D && xx < g.W;
         const int v0 = ((cur.b * g.D + zz) * g.H + y0) * g.W + xx;
         float res[MT];   // the head's residual input, loaded during the MFMAs
+        u32x2 ymk[MT];   // kOutDz: the activation's 4 channels, loaded during the MFMAs
         if constexpr (OUT == kOutHead) {
 #pragma unroll
             for (int m = 0; m < MT; ++m)
                 res[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
                     rr_, xzin && y0 + m < g.H ? (v0 + m * g.W) * 4 : kOob, 0, 0));
+        }
+        if constexpr (OUT == kOutDz) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                ymk[m] = __builtin_amdgcn_raw_buffer_load_b64(
+                    rr_, xzin && y0 + m < g.H ? ((v0 + m * g.W) * 16 + q * 4) * 2 : kOob, 0, 0);
         }
         // the accumulators start at the bias
         f32x4 acc[MT];
@@ -795,13 +815,22 @@ k_conv_rows(const uint16_t* __restrict__ x,
             const bool in = xzin && y0 + m < g.H;
             const int v = v0 + m * g.W;
             float r[4];
+            if constexpr (OUT == kOutDz) {
+                const float yv[4] = {__uint_as_float(ymk[m].x << 16),
+                                     __uint_as_float(ymk[m].x & 0xFFFF0000u),
+                                     __uint_as_float(ymk[m].y << 16),
+                                     __uint_as_float(ymk[m].y & 0xFFFF0000u)};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : slope * acc[m][i];
+                for (int i = 0; i < 4; ++i) r[i] = yv[i] > 0.0f ? acc[m][i] : alpha * acc[m][i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : slope * acc[m][i];
+            }
             if constexpr (!F32) {
                 // a store past the end of the resource is dropped: no branch
                 const uint32_t lo16 = pk_bf16(r[0], r[1]), hi16 = pk_bf16(r[2], r[3]);
                 __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
-                                                      in ? (v * 16 + q * 4) * 2 : kOob, 0, 0);
+                                                      in ? (v * ys + q * 4) * 2 : kOob, 0, 0);
                 if constexpr (OUT == kOutHead) {
                     // the head on the stored (bf16) values
                     float p = hw[0] * __uint_as_float(lo16 << 16);
@@ -819,9 +848,9 @@ k_conv_rows(const uint16_t* __restrict__ x,
                     uint2 pk;
                     pk.x = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
                     pk.y = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
-                    *reinterpret_cast<uint2*>(y16 + (long long)v * 16 + q * 4) = pk;
+                    *reinterpret_cast<uint2*>(y16 + (long long)v * ys + q * 4) = pk;
                 }
-                float4* d = reinterpret_cast<float4*>(y32 + (long long)v * 16 + q * 4);
+                float4* d = reinterpret_cast<float4*>(y32 + (long long)v * ys + q * 4);
                 float4 o4 = make_float4(r[0], r[1], r[2], r[3]);
                 if (accumulate) {
                     const float4 prev = *d;
@@ -1530,6 +1559,37 @@ __global__ void __launch_bounds__(1024) k_colsum(const float* part, int nrow, in
     }
 }
 
+// The weight and bias gradients' column sums in one launch: workgroups
+// [0, nbw) sum the weight partials (as k_colsum with ci_co), the rest the
+// bias partials; each column in the same fixed order as k_colsum.
+__global__ void __launch_bounds__(1024) k_colsum_wb(const float* part, const float* part_b,
+                                                    int nrow, int ncol, int nbw, int Co, float* dw,
+                                                    float* db, int ci_co) {
+    __shared__ float red[16][64];
+    const bool wpart = (int)blockIdx.x < nbw;
+    const float* src = wpart ? part : part_b;
+    const int nc = wpart ? ncol : Co;
+    const int o = threadIdx.x & 63, gr = threadIdx.x >> 6;
+    const int c = (wpart ? (int)blockIdx.x : (int)blockIdx.x - nbw) * 64 + o;
+    float s = 0.0f;
+    if (c < nc)
+        for (int r = gr; r < nrow; r += 16) s += src[(size_t)r * nc + c];
+    red[gr][o] = s;
+    __syncthreads();
+    if (gr == 0 && c < nc) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][o];
+        if (wpart) {
+            const int Ci = ci_co >> 16, Cw = ci_co & 0xFFFF;
+            const int ci = c % Ci, co = (c / Ci) % Cw, tap = c / (Ci * Cw);
+            dw[((size_t)co * 27 + tap) * Ci + ci] = t;
+        } else {
+            db[c] = t;
+        }
+    }
+}
+
 // dz = dy * (y > 0 ? 1 : alpha), in bf16 (LeakyReLU backward from the output sign).
 __global__ void k_lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n,
                             uint16_t* dz) {
@@ -1917,7 +1977,8 @@ inline int blocks_for(long long n, int bs = 256, int cap = 16384) {
 template <int CI, int CS, int OUT>
 hipError_t launch_rows_as(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
                           const float* bias, Geo g, float alpha, int act, uint16_t* y16,
-                          float* y32, int accumulate, hipStream_t s, HeadArgs head = {}) {
+                          float* y32, int accumulate, hipStream_t s, HeadArgs head = {},
+                          int groups = 1) {
     constexpr bool F32 = OUT == kOutF32;
     constexpr size_t lds = ((size_t)kRVox * brick_row(CI) + 256 * 8) * sizeof(uint16_t);
     static const int cap = [] {
@@ -1936,21 +1997,22 @@ hipError_t launch_rows_as(const uint16_t* x, const uint16_t* xl, const uint16_t*
     if (cap <= 0) return hipErrorInvalidConfiguration;
     const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                           ((g.D + kRZ - 1) / kRZ) * g.B;
-    if (nbk >= (1LL << 31) || g.nvox() * 16 * (F32 ? 4 : 2) >= (1LL << 31))
+    if (nbk >= (1LL << 31) || g.nvox() * 16 * groups * (F32 ? 4 : 2) >= (1LL << 31))
         return hipErrorInvalidValue;
     const int grid = (int)std::min<long long>(nbk, cap);
-    hipLaunchKernelGGL((k_conv_rows<CI, CS, OUT>), dim3((unsigned)grid), dim3(256), lds, s, x, xl,
-                       w, bias, g, alpha, act, y16, y32, accumulate, head);
+    hipLaunchKernelGGL((k_conv_rows<CI, CS, OUT>), dim3((unsigned)grid, groups), dim3(256), lds, s,
+                       x, xl, w, bias, g, alpha, act, y16, y32, accumulate, head, 16 * groups);
     return hipGetLastError();
 }
 
 template <int CI, int CS>
 hipError_t launch_rows(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
                        const float* bias, Geo g, float alpha, int act, uint16_t* y16, float* y32,
-                       int accumulate, hipStream_t s) {
+                       int accumulate, hipStream_t s, int groups = 1) {
     return y32 ? launch_rows_as<CI, CS, kOutF32>(x, xl, w, bias, g, alpha, act, y16, y32,
-                                                  accumulate, s)
-               : launch_rows_as<CI, CS, kOutBf16>(x, xl, w, bias, g, alpha, act, y16, y32, 0, s);
+                                                  accumulate, s, {}, groups)
+               : launch_rows_as<CI, CS, kOutBf16>(x, xl, w, bias, g, alpha, act, y16, y32, 0, s,
+                                                   {}, groups);
 }
 
 }  // namespace
@@ -1978,9 +2040,13 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
 #define LAUNCH_REG(CI, NT, CH)                                                             \
     hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk, nt / NT), dim3(256), \
                        lds_r, s, x, w, bias, g, Co, alpha, act, y16, y32, accumulate)
-        // 16 outputs: the persistent row-reuse form
+        // 16 outputs: the persistent row-reuse form (48 from 16 inputs: three
+        // groups of 16, blockIdx.y)
         if (Co == 16 && Ci == 16)
             return launch_rows<16, 16>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
+        if (Co == 48 && Ci == 16)
+            return launch_rows<16, 16>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s,
+                                       3);
         if (Co == 16 && Ci == 32)
             return launch_rows<32, 32>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
         if (Co == 16 && Ci == 48)
@@ -2081,13 +2147,22 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
     return launch_rows<48, 16>(skip, low, w, bias, g, alpha, act, y16, nullptr, 0, s);
 }
 
+hipError_t conv_dz_fwd(const uint16_t* x, const uint16_t* w, const int* dims, const uint16_t* ym,
+                       float alpha, uint16_t* dz, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (g.nvox() * 16 * 2 >= (1LL << 31) || !ym || !dz) return hipErrorInvalidValue;
+    HeadArgs a{};
+    a.ym = ym;
+    return launch_rows_as<16, 16, kOutDz>(x, nullptr, w, nullptr, g, alpha, 0, dz, nullptr, 0, s, a);
+}
+
 hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
                          float alpha, uint16_t* y16, const float* head_w, const float* head_b,
                          const float* resid, float* out, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     if (g.nvox() * 16 * 2 >= (1LL << 31)) return hipErrorInvalidValue;
     return launch_rows_as<16, 16, kOutHead>(x, nullptr, w, bias, g, alpha, 1, y16, nullptr, 0, s,
-                                            HeadArgs{head_w, head_b, resid, out});
+                                            HeadArgs{head_w, head_b, resid, out, nullptr});
 }
 
 hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
@@ -2108,6 +2183,26 @@ hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const flo
     const int grid = (int)std::min<long long>(nbk, cap);
     hipLaunchKernelGGL(k_conv_in, dim3((unsigned)grid), dim3(256), 0, s, x2, w, cin, bias, g, alpha,
                        y16);
+    return hipGetLastError();
+}
+
+// Every layer's flip in one launch: thread i handles element i of the
+// concatenation of the layers' weights (job k covers [start[k], start[k + 1])).
+__global__ void k_flip_all(FlipJobs jobs) {
+    const long long n = jobs.start[jobs.n];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        int k = 0;
+        while (k + 1 < jobs.n && i >= jobs.start[k + 1]) ++k;
+        const int e = (int)(i - jobs.start[k]), Ci = jobs.ci[k], Co = jobs.co[k];
+        const int ci = e % Ci, t = (e / Ci) % 27, co = e / (27 * Ci);
+        jobs.wt[k][((size_t)ci * 27 + (26 - t)) * Co + co] = jobs.w[k][e];
+    }
+}
+
+hipError_t flip_transpose_all(const FlipJobs& jobs, hipStream_t s) {
+    if (jobs.n < 1 || jobs.n > kMaxFlipJobs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flip_all, dim3(blocks_for(jobs.start[jobs.n])), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 
@@ -2172,13 +2267,9 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                                dz, x, g, Ci, bpc, (int)nbk, part, part_b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int n = 27 * Co * Ci;
-        hipLaunchKernelGGL(k_colsum, dim3((n + 63) / 64), dim3(1024), 0, s, part, (int)used, n, dw,
-                           (Ci << 16) | Co);
-        e = hipGetLastError();
-        if (e != hipSuccess || !db) return e;
-        hipLaunchKernelGGL(k_colsum, dim3((Co + 63) / 64), dim3(1024), 0, s, part_b, (int)used, Co,
-                           db, 0);
+        const int n = 27 * Co * Ci, nbw = (n + 63) / 64;
+        hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (Co + 63) / 64 : 0)), dim3(1024), 0, s,
+                           part, part_b, (int)used, n, nbw, Co, dw, db, (Ci << 16) | Co);
         return hipGetLastError();
     }
     const int tg = wgrad_taps_per_group(Ci, Co);
@@ -2191,13 +2282,9 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                        dz, x, g, Ci, Co, chunk, tg, part, part_b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = 27 * Co * Ci;
-    hipLaunchKernelGGL(k_colsum, dim3((n + 63) / 64), dim3(1024), 0, s, part, (int)nchunk, n, dw,
-                       (Ci << 16) | Co);
-    e = hipGetLastError();
-    if (e != hipSuccess || !db) return e;
-    hipLaunchKernelGGL(k_colsum, dim3((Co + 63) / 64), dim3(1024), 0, s, part_b, (int)nchunk, Co, db,
-                       0);
+    const int n = 27 * Co * Ci, nbw = (n + 63) / 64;
+    hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (Co + 63) / 64 : 0)), dim3(1024), 0, s, part,
+                       part_b, (int)nchunk, n, nbw, Co, dw, db, (Ci << 16) | Co);
     return hipGetLastError();
 }
 
