@@ -661,21 +661,30 @@ k_conv_rows(const uint16_t* __restrict__ x,
     const __amdgpu_buffer_rsrc_t lr = rsrc16(CS < CI ? xl : x, CS < CI ? g.nvox() / 8 * (CI - CS) : 0);
     const int planeb = g.H * g.W * CS * 2, planel = Hd * Wd * (CI - CS) * 2;
 
-    // bricks: this XCD's contiguous range; the brick coordinates advance by
-    // gn with mixed-radix carries (no divisions in the loop)
+    // bricks: this XCD's contiguous range, numbered x fastest, then y within
+    // a band of 4 brick rows, then z, then the band, so that the bricks in
+    // flight on an XCD (about gn consecutive ones) share their x, z and most
+    // y halo voxels in its L2; the coordinates advance by gn with
+    // mixed-radix carries (no divisions in the loop)
+    const int yt = nby % 4 == 0 ? 4 : 1, nyb = nby / yt;
     const int xcd = blockIdx.x % kXcds, gi = blockIdx.x / kXcds;
     const int gn = ((int)gridDim.x - xcd + kXcds - 1) / kXcds;
     const int per = nbk / kXcds, rem = nbk % kXcds;
     const int s0 = xcd * per + (xcd < rem ? xcd : rem), s1 = s0 + per + (xcd < rem ? 1 : 0);
-    struct Bk { int x, y, z, b; };
+    struct Bk {
+        int x, yi, z, yb, b;   // brick row y = yb yt + yi
+        __device__ int y(int t) const { return yb * t + yi; }
+    };
     auto split = [&](int bid) {
         Bk r;
         r.x = bid % nbx;
         bid /= nbx;
-        r.y = bid % nby;
-        bid /= nby;
+        r.yi = bid % yt;
+        bid /= yt;
         r.z = bid % nbz;
-        r.b = bid / nbz;
+        bid /= nbz;
+        r.yb = bid % nyb;
+        r.b = bid / nyb;
         return r;
     };
     const Bk step = split(gn);
@@ -683,17 +692,20 @@ k_conv_rows(const uint16_t* __restrict__ x,
         r.x += step.x;
         int c = r.x >= nbx;
         r.x -= c ? nbx : 0;
-        r.y += step.y + c;
-        c = r.y >= nby;
-        r.y -= c ? nby : 0;
+        r.yi += step.yi + c;
+        c = r.yi >= yt;
+        r.yi -= c ? yt : 0;
         r.z += step.z + c;
         c = r.z >= nbz;
         r.z -= c ? nbz : 0;
+        r.yb += step.yb + c;
+        c = r.yb >= nyb;
+        r.yb -= c ? nyb : 0;
         r.b += step.b + c;
         return r;
     };
     auto load_brick = [&](const Bk& bk, uint4 (&st)[NC][HZ]) {
-        const int x0 = bk.x * kRX, y0 = bk.y * kRY, z0 = bk.z * kRZ;
+        const int x0 = bk.x * kRX, y0 = bk.y(yt) * kRY, z0 = bk.z * kRZ;
         // corner voxel (x0 - 1, y0 - 1, z0 - 1) and its coarse parent's
         // corner (x0 / 2 - 1, ...): scalar, possibly negative
         const int cf = (((bk.b * g.D + z0 - 1) * g.H + y0 - 1) * g.W + x0 - 1) * (CS * 2);
@@ -771,7 +783,7 @@ k_conv_rows(const uint16_t* __restrict__ x,
         const Bk nxt = advance(cur);
         if (brick + gn < s1) load_brick(nxt, st);   // in flight during the MFMAs
         // output voxels of this lane: (x0 + lane % 16, y0 + m, z0 + wave)
-        const int xx = cur.x * kRX + (lane & 15), y0 = cur.y * kRY, zz = cur.z * kRZ + wave;
+        const int xx = cur.x * kRX + (lane & 15), y0 = cur.y(yt) * kRY, zz = cur.z * kRZ + wave;
         const bool xzin = zz < g.D && xx < g.W;
         const int v0 = ((cur.b * g.D + zz) * g.H + y0) * g.W + xx;
         float res[MT];   // the head's residual input, loaded during the MFMAs
