@@ -129,12 +129,16 @@ uint16_t* input_rows(sde_nn* n) { return n->cfg.train || !first_from_pairs(n) ? 
 int run_forward(sde_nn* n, const int* d0) {
     hipStream_t s = library_stream();
     int d[4], dc[4];
+    // the pool after a 16 -> 16 second conv is fused into that conv
+    auto pool_fused = [&](int l) {
+        return l + 1 < n->L && n->enc_b[l].ci == 16 && n->enc_b[l].co == 16;
+    };
     for (int l = 0; l < n->L; ++l) {
         dims_at(d0, l, d);
         Level& v = n->lv[l];
         const uint16_t* in = n->x16;
         if (l > 0) {
-            NN_TRY(pool_fwd(n->lv[l - 1].eb, d, n->c[l - 1], v.pin, s));
+            if (!pool_fused(l - 1)) NN_TRY(pool_fwd(n->lv[l - 1].eb, d, n->c[l - 1], v.pin, s));
             in = v.pin;
         }
         if (l == 0 && first_from_pairs(n)) {
@@ -144,7 +148,13 @@ int run_forward(sde_nn* n, const int* d0) {
         } else if (int r = conv_act(n, in, n->enc_a[l], d, v.ea)) {
             return r;
         }
-        if (int r = conv_act(n, v.ea, n->enc_b[l], d, v.eb)) return r;
+        if (pool_fused(l)) {
+            const ConvP& cb = n->enc_b[l];
+            NN_TRY(conv_pool_fwd(v.ea, n->P16 + cb.w, n->P + cb.b, d, n->cfg.leaky_alpha, v.eb,
+                                 n->lv[l + 1].pin, s));
+        } else if (int r = conv_act(n, v.ea, n->enc_b[l], d, v.eb)) {
+            return r;
+        }
     }
     const uint16_t* top = n->lv[n->L - 1].eb;
     for (int l = n->L - 2; l >= 0; --l) {

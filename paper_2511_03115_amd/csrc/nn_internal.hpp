@@ -37,6 +37,10 @@ hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias
 // input's two used channels as bf16 pairs x2 (weights [16][27][cin]).
 hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
                        const int* dims, float alpha, uint16_t* y16, hipStream_t s);
+// conv_fwd 16 -> 16 (LeakyReLU, bf16 y16) with pool_fwd of its output fused
+// in: pool (bf16, half size; D, H, W even) gets the values pool_fwd gives.
+hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
+                         float alpha, uint16_t* y16, uint16_t* pool, hipStream_t s);
 // The input gradient of a LeakyReLU layer through the next conv (16 -> 16):
 // dz = bf16(ym > 0 ? r : alpha r), r = conv(x, w) in FP32 (no bias); the same
 // values as conv_fwd into FP32 followed by lrelu_bwd.

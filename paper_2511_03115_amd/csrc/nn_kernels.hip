@@ -577,14 +577,16 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 // order, the quarters are added pairwise, (0 + 1) + (2 + 3)).
 // Or the input gradient of a LeakyReLU layer (kOutDz): dz[v][c] =
 // bf16(ym[v][c] > 0 ? r : alpha r) with r the FP32 conv output (no bias),
-// what conv_fwd into FP32 followed by lrelu_bwd gives.
-enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2, kOutDz = 3 };
+// what conv_fwd into FP32 followed by lrelu_bwd gives.  Or bf16 y16 and its
+// 2 x 2 x 2 average pool (kOutPool, into pool at half size, as pool_fwd).
+enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2, kOutDz = 3, kOutPool = 4 };
 struct HeadArgs {
     const float* w;       // [16]
     const float* b;       // [1]
     const float* resid;   // per voxel
     float* out;           // per voxel
     const uint16_t* ym;   // kOutDz: the layer's output activation, [voxel][16]
+    uint16_t* pool;       // kOutPool: [voxel at half size][16]
 };
 
 template <int CI, int CS, int OUT>
@@ -762,6 +764,11 @@ k_conv_rows(const uint16_t* __restrict__ x,
                                                 (int)(g.nvox() * 4), 0x00020000);
         or_ = __builtin_amdgcn_make_buffer_rsrc(head.out, 0, (int)(g.nvox() * 4), 0x00020000);
     }
+    // kOutPool: the pool partial sums of waves 1 and 3, handed to waves 0 and 2
+    __shared__ float pex[OUT == kOutPool ? 2 : 1][64][8];
+    const Geo gp{g.B, g.D >> 1, g.H >> 1, g.W >> 1};
+    const __amdgpu_buffer_rsrc_t pr =
+        rsrc16(head.pool, OUT == kOutPool && head.pool ? gp.nvox() * 16 : 0);
     uint4 st[NC][HZ];
     int brick = s0 + gi;
     Bk cur = split(brick < s1 ? brick : 0);
@@ -822,6 +829,7 @@ k_conv_rows(const uint16_t* __restrict__ x,
                                                                      0, 0, 0);
         }
         // acc[m][i]: output channel 4 q + i of voxel (x0 + lane % 16, y0 + m, z0 + wave)
+        float pc[MT][4];   // kOutPool: the stored (bf16) values as floats
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const bool in = xzin && y0 + m < g.H;
@@ -843,6 +851,12 @@ k_conv_rows(const uint16_t* __restrict__ x,
                 const uint32_t lo16 = pk_bf16(r[0], r[1]), hi16 = pk_bf16(r[2], r[3]);
                 __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
                                                       in ? (v * ys + q * 4) * 2 : kOob, 0, 0);
+                if constexpr (OUT == kOutPool) {
+                    pc[m][0] = __uint_as_float(lo16 << 16);
+                    pc[m][1] = __uint_as_float(lo16 & 0xFFFF0000u);
+                    pc[m][2] = __uint_as_float(hi16 << 16);
+                    pc[m][3] = __uint_as_float(hi16 & 0xFFFF0000u);
+                }
                 if constexpr (OUT == kOutHead) {
                     // the head on the stored (bf16) values
                     float p = hw[0] * __uint_as_float(lo16 << 16);
@@ -872,6 +886,43 @@ k_conv_rows(const uint16_t* __restrict__ x,
                     o4.w += prev.w;
                 }
                 *d = o4;
+            }
+        }
+        if constexpr (OUT == kOutPool) {
+            // children (c0 + c1) + (c2 + c3) over x pairs (lanes l, l ^ 1) and
+            // y pairs (rows m, m + 1) of this z-slice; waves 1 and 3 hand
+            // theirs to 0 and 2, which add them and store the pooled voxels
+            float t[2][4];
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float a0 = pc[2 * mp][i], a2 = pc[2 * mp + 1][i];
+                    const float a1 = __shfl_xor(a0, 1), a3 = __shfl_xor(a2, 1);
+                    t[mp][i] = (a0 + a1) + (a2 + a3);
+                }
+            if (wave & 1) {
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) pex[wave >> 1][lane][mp * 4 + i] = t[mp][i];
+            }
+            __syncthreads();
+            if (!(wave & 1)) {
+                const int px = (cur.x * kRX + (lane & 15)) >> 1, pz = (cur.z * kRZ + wave) >> 1;
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp) {
+                    float sv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        sv[i] = (t[mp][i] + pex[wave >> 1][lane][mp * 4 + i]) * 0.125f;
+                    const int py = (y0 >> 1) + mp;
+                    const bool pok = !(lane & 1) && px < gp.W && py < gp.H && pz < gp.D;
+                    const int pv = ((cur.b * gp.D + pz) * gp.H + py) * gp.W + px;
+                    __builtin_amdgcn_raw_buffer_store_b64(
+                        u32x2{pk_bf16(sv[0], sv[1]), pk_bf16(sv[2], sv[3])}, pr,
+                        pok ? (pv * 16 + q * 4) * 2 : kOob, 0, 0);
+                }
             }
         }
         cur = nxt;
@@ -1671,15 +1722,18 @@ __device__ __forceinline__ uint4 f32_to_bf16x8(const float* f) {
 __global__ void k_pool_fwd(const uint16_t* x, Geo go, int C, uint16_t* y) {
     VoxG o;
     if (!vox_of(go, C / 8, o)) return;
-    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int d = 0; d < 8; ++d) {
-        float f[8];
-        bf16x8_to_f32(*reinterpret_cast<const uint4*>(x + child(go, o, d) * C + o.grp * 8), f);
+    // children d = 4 dz + 2 dy + dx, summed as ((c0 + c1) + (c2 + c3)) +
+    // ((c4 + c5) + (c6 + c7)), the order of the pool fused into the
+    // row-reuse conv
+    float f[8][8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s[k] += f[k];
-    }
+    for (int d = 0; d < 8; ++d)
+        bf16x8_to_f32(*reinterpret_cast<const uint4*>(x + child(go, o, d) * C + o.grp * 8), f[d]);
+    float s[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s[k] *= 0.125f;
+    for (int k = 0; k < 8; ++k)
+        s[k] = (((f[0][k] + f[1][k]) + (f[2][k] + f[3][k])) +
+                ((f[4][k] + f[5][k]) + (f[6][k] + f[7][k]))) * 0.125f;
     *reinterpret_cast<uint4*>(y + o.v * C + o.grp * 8) = f32_to_bf16x8(s);
 }
 
@@ -2159,6 +2213,17 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
     return launch_rows<48, 16>(skip, low, w, bias, g, alpha, act, y16, nullptr, 0, s);
 }
 
+hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
+                         float alpha, uint16_t* y16, uint16_t* pool, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (g.nvox() * 16 * 2 >= (1LL << 31) || !y16 || !pool || ((g.D | g.H | g.W) & 1))
+        return hipErrorInvalidValue;
+    HeadArgs a{};
+    a.pool = pool;
+    return launch_rows_as<16, 16, kOutPool>(x, nullptr, w, bias, g, alpha, 1, y16, nullptr, 0, s,
+                                            a);
+}
+
 hipError_t conv_dz_fwd(const uint16_t* x, const uint16_t* w, const int* dims, const uint16_t* ym,
                        float alpha, uint16_t* dz, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
@@ -2174,7 +2239,7 @@ hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     if (g.nvox() * 16 * 2 >= (1LL << 31)) return hipErrorInvalidValue;
     return launch_rows_as<16, 16, kOutHead>(x, nullptr, w, bias, g, alpha, 1, y16, nullptr, 0, s,
-                                            HeadArgs{head_w, head_b, resid, out, nullptr});
+                                            HeadArgs{head_w, head_b, resid, out, nullptr, nullptr});
 }
 
 hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
