@@ -243,7 +243,11 @@ def gamma_leg() -> dict:
     # the denoiser's forward pass against the dense bf16 matrix-core peak
     m = 1 << (denoiser.LEVELS - 1)
     padded = [-(-n // m) * m for n in wl.phantom.material_id.shape]
-    flops = denoiser.forward_flops(padded)
+    # FLOPs of the sums the network has: the first conv over its 2 used input
+    # channels (the nominal count, with all 16, is given beside it)
+    flops = denoiser.forward_flops(padded, used_in=2)
+    nominal = denoiser.forward_flops(padded)
+    nvox = int(np.prod(padded))
     t_dn = [r.denoise_s for r in res.rungs if r.denoise_s]
     if t_dn:
         t = sum(t_dn) / len(t_dn)
@@ -251,8 +255,8 @@ def gamma_leg() -> dict:
             "bound": "mfma", "achieved": flops / t, "peak": BF16_PEAK, "unit": "FLOP/s",
             "frac": flops / t / BF16_PEAK, "traffic": None,
             "kernel": "denoiser forward (14 bf16 MFMA convs + layout kernels, whole pass)",
-            "ms": t * 1e3, "work_per_unit": "142560 FLOP per voxel",
-            "units_per_launch": int(np.prod(padded))}
+            "ms": t * 1e3, "work_per_unit": f"{flops // nvox} FLOP per voxel",
+            "units_per_launch": nvox, "frac_nominal_16_input_channels": nominal / t / BF16_PEAK}
     out["workload"] = ("plan: 1000 spots 70-230 MeV, lognormal weights, equal histories per "
                        "spot, 256x256x200 at 2 mm, random density + bone/lung ellipsoids")
     out["launch"] = launch

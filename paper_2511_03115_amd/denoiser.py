@@ -42,16 +42,20 @@ def param_layout(levels: int = LEVELS, c0: int = C0, cin: int = CIN) -> List[Tup
 
 
 def forward_flops(dims_zyx: Sequence[int], batch: int = 1, levels: int = LEVELS, c0: int = C0,
-                  cin: int = CIN) -> int:
+                  cin: int = CIN, used_in: Optional[int] = None) -> int:
     """Algorithmic FLOPs of one forward pass: 2 * 27 * Ci * Co per output
     voxel of every conv, at each level's resolution (D, H, W as the network
-    sees them, i.e. already padded to multiples of 2^(levels-1))."""
+    sees them, i.e. already padded to multiples of 2^(levels-1)).  With
+    used_in, the first conv counts only that many input channels (the input
+    has 2 used channels, the other cin - 2 are zero and drop out of its
+    sums)."""
     nv0 = batch * int(np.prod(dims_zyx))
     total = 0
     for name, shp in param_layout(levels, c0, cin):
         if name.endswith(".w") and len(shp) == 3:
             lvl = int(name[3])
-            total += 2 * 27 * shp[0] * shp[2] * (nv0 >> (3 * lvl))
+            ci = used_in if (used_in is not None and name == "enc0a.w") else shp[2]
+            total += 2 * 27 * shp[0] * ci * (nv0 >> (3 * lvl))
     return total
 
 
