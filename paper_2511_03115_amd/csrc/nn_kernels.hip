@@ -1476,7 +1476,8 @@ constexpr int kWbTaps = 7;             // taps per wave: w, w + 4, ..., < 27
 int wgrad_brick_lds_bytes(int Co) { return (3 * 16 * kWbXRow + Co * kWbDRow) * 2; }
 
 template <int NCO>
-__global__ void __launch_bounds__(256) k_wgrad_brick(const uint16_t* __restrict__ dz,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wgrad_brick(const uint16_t* __restrict__ dz,
                                                      const uint16_t* __restrict__ x, Geo g, int Ci,
                                                      int bpc, int nbk, float* __restrict__ part,
                                                      float* __restrict__ part_b) {
@@ -1495,7 +1496,19 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(const uint16_t* __restrict_
         for (int j = 0; j < NCO; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;
     const int bk1 = min(nbk, (c + 1) * bpc);
-    for (int bk = c * bpc; bk < bk1; ++bk) {
+    // Staging items: dz item i < 32 Co / 8 (8 voxels along x x 8 channels)
+    // and input item i < 3 x 36 x 4 (copy d, halo row, half, channel group),
+    // each 8 16-byte loads, transposed into LDS.  Thread t owns dz item t and
+    // input items t and t + 256; with 16 outputs the next brick's loads are
+    // issued into registers before the current brick's matrix-core work.
+    constexpr int NDZ = 32 * (Co / 8), NXI = 3 * 36 * 4;
+    uint4 rdz[8], rx[2][8];
+    // buffer loads (32-bit offsets; the host keeps both operands below 2 GiB):
+    // a voxel outside the volume is read at an offset past the end, which
+    // the hardware answers with zeros, so no load sits behind a branch
+    const __amdgpu_buffer_rsrc_t dzr = rsrc16(dz, g.nvox() * Co);
+    const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * Ci);
+    auto load_raw = [&](int bk) {
         int r = bk;
         const int x0 = (r % nbx) * kRX;
         r /= nbx;
@@ -1503,44 +1516,63 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(const uint16_t* __restrict_
         r /= nby;
         const int z0 = (r % nbz) * kRZ;
         const int b = r / nbz;
-        __syncthreads();   // the previous brick's LDS reads are done
-        // dz: item = 8 voxels along x x 8 channels
-        for (int i = tid; i < 32 * (Co / 8); i += 256) {
+        {
+            const int i = tid;
             const int vg = i / (Co / 8), ch = (i % (Co / 8)) * 8;
             const int rr = vg >> 1, zz = z0 + (rr >> 2), yy = y0 + (rr & 3), xs = x0 + (vg & 1) * 8;
-            uint4 in[8], out[8];
+            const bool rin = i < NDZ && zz < g.D && yy < g.H;
+            const int o = ((((b * g.D + zz) * g.H + yy) * g.W + xs) * Co + ch) * 2;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                in[k] = make_uint4(0, 0, 0, 0);
-                if (zz < g.D && yy < g.H && xs + k < g.W)
-                    in[k] = *reinterpret_cast<const uint4*>(
-                        dz + ((((long long)b * g.D + zz) * g.H + yy) * g.W + xs + k) * Co + ch);
-            }
-            transpose8x8(in, out);
+            for (int k = 0; k < 8; ++k)
+                rdz[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                       dzr, rin && xs + k < g.W ? o + k * Co * 2 : kOob,
+                                                       0, 0));
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = tid + 256 * h;
+            const int d = i / 144, rem = i % 144, row = rem >> 2, hh = (rem >> 1) & 1, cg = rem & 1;
+            const int zz = z0 - 1 + row / 6, yy = y0 - 1 + row % 6, xs = x0 + d - 1 + hh * 8;
+            const bool rin = i < NXI && zz >= 0 && yy >= 0 && zz < g.D && yy < g.H;
+            const int o = ((((b * g.D + zz) * g.H + yy) * g.W + xs) * Ci + ci0 + cg * 8) * 2;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                rx[h][k] = __builtin_bit_cast(
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                               xr, rin && xs + k >= 0 && xs + k < g.W ? o + k * Ci * 2 : kOob, 0, 0));
+        }
+    };
+    auto store_lds = [&]() {
+        uint4 out[8];
+        if (tid < NDZ) {
+            const int vg = tid / (Co / 8), ch = (tid % (Co / 8)) * 8;
+            transpose8x8(rdz, out);
 #pragma unroll
             for (int cc = 0; cc < 8; ++cc)
                 *reinterpret_cast<uint4*>(dzT + (ch + cc) * kWbDRow + vg * 8) = out[cc];
         }
-        // input brick: copy d (dx = d - 1) x 36 halo rows x 2 halves x 2 channel groups
-        for (int i = tid; i < 3 * 36 * 4; i += 256) {
-            const int d = i / 144, rem = i % 144, row = rem >> 2, hh = (rem >> 1) & 1, cg = rem & 1;
-            const int zz = z0 - 1 + row / 6, yy = y0 - 1 + row % 6, xs = x0 + d - 1 + hh * 8;
-            const bool rin = zz >= 0 && yy >= 0 && zz < g.D && yy < g.H;
-            const long long rbase = (((long long)b * g.D + zz) * g.H + yy) * g.W;
-            uint4 in[8], out[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                in[k] = make_uint4(0, 0, 0, 0);
-                if (rin && xs + k >= 0 && xs + k < g.W)
-                    in[k] = *reinterpret_cast<const uint4*>(x + (rbase + xs + k) * Ci + ci0 + cg * 8);
-            }
-            transpose8x8(in, out);
+        for (int h = 0; h < 2; ++h) {
+            const int i = tid + 256 * h;
+            if (i >= NXI) continue;
+            const int d = i / 144, rem = i % 144, row = rem >> 2, hh = (rem >> 1) & 1, cg = rem & 1;
+            transpose8x8(rx[h], out);
 #pragma unroll
             for (int cc = 0; cc < 8; ++cc)
                 *reinterpret_cast<uint4*>(xT + (d * 16 + cg * 8 + cc) * kWbXRow + row * 16 + hh * 8) =
                     out[cc];
         }
+    };
+    // 32 outputs: the registers of a prefetch would cost half the
+    // occupancy, so the brick is loaded just before it is staged
+    constexpr bool PF = NCO == 1;
+    if (PF && c * bpc < bk1) load_raw(c * bpc);
+    for (int bk = c * bpc; bk < bk1; ++bk) {
+        if (!PF) load_raw(bk);
+        __syncthreads();   // the previous brick's LDS reads are done
+        store_lds();
         __syncthreads();
+        if (PF && bk + 1 < bk1) load_raw(bk + 1);   // in flight during the MFMAs
         if (blockIdx.y == 0) {   // bias: thread (co = tid % Co) sums voxels tid / Co + k (256 / Co)
 #pragma unroll 4
             for (int v = tid / Co; v < 256; v += 256 / Co) bsum += bf2f(dzT[(tid % Co) * kWbDRow + v]);
@@ -2318,7 +2350,8 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                  float* part, float* dw, float* db, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     long long nchunk = wgrad_chunks(dims, chunk);
-    if (Co == 16 || Co == 32) {   // by bricks, within the same partial-sum buffer
+    if ((Co == 16 || Co == 32) && g.nvox() * std::max(Ci, Co) * 2 < (1LL << 31)) {
+        // by bricks, within the same partial-sum buffer (32-bit buffer offsets)
         static const hipError_t attr = [] {
             hipError_t e = hipFuncSetAttribute((const void*)k_wgrad_brick<1>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
