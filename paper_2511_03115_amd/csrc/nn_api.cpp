@@ -241,22 +241,26 @@ int run_backward(sde_nn* n, const int* d0) {
         }
     fj.start[fj.n] = start;
     NN_TRY(flip_transpose_all(fj, s));
+    // with a decoder, the head's input gradient feeds only the LeakyReLU of
+    // the last conv: it is handed on as that conv's bf16 output gradient
+    const bool head_dz = L > 1;
     NN_TRY(head_bwd(n->out /* holds dL/dout */, top0, n->P + n->head_w, nv0, n->c0, gtop0,
-                    n->head_part, s));
+                    n->head_part, s, n->cfg.leaky_alpha, head_dz ? n->dz : nullptr));
     NN_TRY(sum_rows(n->head_part, head_bwd_blocks(nv0), n->c0 + 1, n->G + n->head_w, s));
     for (int l = 0; l <= L - 2; ++l) {
         dims_at(d0, l, d);
         dims_at(d0, l + 1, dc);
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
+        const uint16_t* dzb = l == 0 && head_dz ? n->dz : nullptr;   // from the head
         if (dz_chain(n->dec_b[l])) {
-            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, nullptr, v.da,
+            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da,
                                  n->dz2))
                 return r;
             if (int r = conv_bwd(n, nullptr, nullptr, v.cat, n->dec_a[l], d, v.gCat, n->dz2))
                 return r;
         } else {
-            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa)) return r;
+            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa, dzb)) return r;
             if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, v.gCat)) return r;
         }
         NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));

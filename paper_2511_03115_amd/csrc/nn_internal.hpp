@@ -101,8 +101,12 @@ hipError_t max_abs(const double* a, long long n, unsigned long long* out_bits, h
 hipError_t head_fwd(const uint16_t* x, const float* w, const float* b, const float* resid,
                     long long nv, int C, float* out, hipStream_t s);
 int head_bwd_blocks(long long nv);
+// head backward: dx = dout w (FP32), or with dz non-null the gradient through
+// the LeakyReLU that produced x, dz = bf16(x > 0 ? dout w : alpha dout w)
+// (lrelu_bwd's values) in place of dx; per-block partials of dw and db
 hipError_t head_bwd(const float* dout, const uint16_t* x, const float* w, long long nv, int C,
-                    float* dx, float* part, hipStream_t s);
+                    float* dx, float* part, hipStream_t s, float alpha = 0.0f,
+                    uint16_t* dz = nullptr);
 int mse_blocks(long long n);
 hipError_t mse(const float* out, const float* tgt, const float* wgt, long long n, float* dout,
                float* part, hipStream_t s);

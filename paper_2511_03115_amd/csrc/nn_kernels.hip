@@ -1655,11 +1655,13 @@ __global__ void __launch_bounds__(1024) k_colsum(const float* part, int nrow, in
 }
 
 // The weight and bias gradients' column sums in one launch: workgroups
-// [0, nbw) sum the weight partials (as k_colsum with ci_co), the rest the
-// bias partials; each column in the same fixed order as k_colsum.
+// [0, nbw) sum the weight partials (columns (t, co, ci), written to
+// dW[co][t][ci]), the rest the bias partials; each column in a fixed order.
 __global__ void __launch_bounds__(1024) k_colsum_wb(const float* part, const float* part_b,
                                                     int nrow, int ncol, int nbw, int Co, float* dw,
                                                     float* db, int ci_co) {
+    // a workgroup: 64 columns x 16 row groups (row group g sums rows g,
+    // g + 16, ...), the 16 partial sums then added in a fixed order
     __shared__ float red[16][64];
     const bool wpart = (int)blockIdx.x < nbw;
     const float* src = wpart ? part : part_b;
@@ -1977,7 +1979,9 @@ __global__ void k_head_fwd(const uint16_t* x, const float* w, const float* b, co
 template <int C>
 __global__ void __launch_bounds__(256) k_head_bwd(const float* dout, const uint16_t* x,
                                                   const float* w, long long nv, float* dx,
-                                                  float* part) {
+                                                  float* part, float alpha, uint16_t* dz) {
+    // dz non-null: the gradient continues through the LeakyReLU whose output
+    // x is: dz = bf16(x > 0 ? dx : alpha dx) in place of dx (lrelu_bwd's values)
     float s[C + 1];
     float wr[C];
 #pragma unroll
@@ -1989,11 +1993,27 @@ __global__ void __launch_bounds__(256) k_head_bwd(const float* dout, const uint1
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nv;
          v += (long long)gridDim.x * blockDim.x) {
         const float d = dout[v];
+        float xv[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            dx[v * C + c] = d * wr[c];
-            s[c] += d * bf2f(x[v * C + c]);
+        for (int g8 = 0; g8 < C / 8; ++g8)
+            bf16x8_to_f32(*reinterpret_cast<const uint4*>(x + v * C + g8 * 8), xv + g8 * 8);
+        if (dz) {
+#pragma unroll
+            for (int g8 = 0; g8 < C / 8; ++g8) {
+                float t[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float gy = d * wr[g8 * 8 + k];
+                    t[k] = xv[g8 * 8 + k] > 0.0f ? gy : alpha * gy;
+                }
+                *reinterpret_cast<uint4*>(dz + v * C + g8 * 8) = f32_to_bf16x8(t);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) dx[v * C + c] = d * wr[c];
         }
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] += d * xv[c];
         s[C] += d;
     }
     __shared__ float red[256];
@@ -2502,12 +2522,14 @@ hipError_t head_fwd(const uint16_t* x, const float* w, const float* b, const flo
 int head_bwd_blocks(long long nv) { return blocks_for(nv, 256, 1024); }
 
 hipError_t head_bwd(const float* dout, const uint16_t* x, const float* w, long long nv, int C,
-                    float* dx, float* part, hipStream_t s) {
+                    float* dx, float* part, hipStream_t s, float alpha, uint16_t* dz) {
     const int g = head_bwd_blocks(nv);
     if (C == 16)
-        hipLaunchKernelGGL(k_head_bwd<16>, dim3(g), dim3(256), 0, s, dout, x, w, nv, dx, part);
+        hipLaunchKernelGGL(k_head_bwd<16>, dim3(g), dim3(256), 0, s, dout, x, w, nv, dx, part,
+                           alpha, dz);
     else if (C == 32)
-        hipLaunchKernelGGL(k_head_bwd<32>, dim3(g), dim3(256), 0, s, dout, x, w, nv, dx, part);
+        hipLaunchKernelGGL(k_head_bwd<32>, dim3(g), dim3(256), 0, s, dout, x, w, nv, dx, part,
+                           alpha, dz);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
