@@ -60,9 +60,10 @@ hipError_t flip_transpose_all(const FlipJobs& jobs, hipStream_t s);
 hipError_t flip_transpose(const uint16_t* w, uint16_t* wt, int Ci, int Co, hipStream_t s);
 // weight gradient: part needs wgrad_part_floats floats; dw [Co][27][Ci], db [Co]
 // (nullable).  Ci % 16 == 0, Co % 16 == 0, (Co/16)(Ci/16) <= 64, chunk from
-// wgrad_chunk_for (a multiple of 64).  16 or 32 outputs go by 4 x 4 x 16
-// bricks (at most as many split-K chunks as the chunk length gives), wider
-// layers by 64-voxel slices and tap groups.
+// wgrad_chunk_for (a multiple of 64).  16, 32, 64 or 128 outputs go by
+// 4 x 4 x 16 bricks (at most as many split-K chunks as the chunk length
+// gives; 64 and 128 as groups of 32), other widths by 64-voxel slices and
+// tap groups.
 long long wgrad_chunks(const int* dims, int chunk);
 int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats);
 long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk);

@@ -1480,7 +1480,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_wgrad_brick(const uint16_t* __restrict__ dz,
                                                      const uint16_t* __restrict__ x, Geo g, int Ci,
                                                      int bpc, int nbk, float* __restrict__ part,
-                                                     float* __restrict__ part_b) {
+                                                     float* __restrict__ part_b, int dzc) {
+    // dz: Co = 16 NCO output channels of dzc per voxel (a group of a wider layer)
     constexpr int Co = NCO * 16;
     extern __shared__ __align__(16) uint16_t lds[];
     uint16_t* xT = lds;                          // [3][16][kWbXRow]
@@ -1506,7 +1507,7 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
     // buffer loads (32-bit offsets; the host keeps both operands below 2 GiB):
     // a voxel outside the volume is read at an offset past the end, which
     // the hardware answers with zeros, so no load sits behind a branch
-    const __amdgpu_buffer_rsrc_t dzr = rsrc16(dz, g.nvox() * Co);
+    const __amdgpu_buffer_rsrc_t dzr = rsrc16(dz, g.nvox() * dzc);
     const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * Ci);
     auto load_raw = [&](int bk) {
         int r = bk;
@@ -1521,11 +1522,11 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
             const int vg = i / (Co / 8), ch = (i % (Co / 8)) * 8;
             const int rr = vg >> 1, zz = z0 + (rr >> 2), yy = y0 + (rr & 3), xs = x0 + (vg & 1) * 8;
             const bool rin = i < NDZ && zz < g.D && yy < g.H;
-            const int o = ((((b * g.D + zz) * g.H + yy) * g.W + xs) * Co + ch) * 2;
+            const int o = ((((b * g.D + zz) * g.H + yy) * g.W + xs) * dzc + ch) * 2;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 rdz[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                       dzr, rin && xs + k < g.W ? o + k * Co * 2 : kOob,
+                                                       dzr, rin && xs + k < g.W ? o + k * dzc * 2 : kOob,
                                                        0, 0));
         }
 #pragma unroll
@@ -2370,8 +2371,10 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                  float* part, float* dw, float* db, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     long long nchunk = wgrad_chunks(dims, chunk);
-    if ((Co == 16 || Co == 32) && g.nvox() * std::max(Ci, Co) * 2 < (1LL << 31)) {
-        // by bricks, within the same partial-sum buffer (32-bit buffer offsets)
+    if ((Co == 16 || Co == 32 || Co == 64 || Co == 128) &&
+        g.nvox() * std::max(Ci, Co) * 2 < (1LL << 31)) {
+        // by bricks, within the same partial-sum buffer (32-bit buffer offsets);
+        // 64 or 128 outputs as groups of 32, each with its own partials
         static const hipError_t attr = [] {
             hipError_t e = hipFuncSetAttribute((const void*)k_wgrad_brick<1>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
@@ -2388,19 +2391,27 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
         const int bpc = (int)((nbk + want - 1) / want);
         const long long used = (nbk + bpc - 1) / bpc;   // <= nchunk
         float* part_b = part + used * 27LL * Co * Ci;
-        const size_t lds = (size_t)wgrad_brick_lds_bytes(Co);
-        if (Co == 16)
-            hipLaunchKernelGGL(k_wgrad_brick<1>, dim3((unsigned)used, Ci / 16), dim3(256), lds, s,
-                               dz, x, g, Ci, bpc, (int)nbk, part, part_b);
-        else
-            hipLaunchKernelGGL(k_wgrad_brick<2>, dim3((unsigned)used, Ci / 16), dim3(256), lds, s,
-                               dz, x, g, Ci, bpc, (int)nbk, part, part_b);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        const int n = 27 * Co * Ci, nbw = (n + 63) / 64;
-        hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (Co + 63) / 64 : 0)), dim3(1024), 0, s,
-                           part, part_b, (int)used, n, nbw, Co, dw, db, (Ci << 16) | Co);
-        return hipGetLastError();
+        const int cg = Co == 16 ? 16 : 32;   // outputs per group
+        for (int co0 = 0; co0 < Co; co0 += cg) {
+            float* pw = part + used * 27LL * co0 * Ci;
+            float* pb = part_b + used * co0;
+            const size_t lds = (size_t)wgrad_brick_lds_bytes(cg);
+            if (cg == 16)
+                hipLaunchKernelGGL(k_wgrad_brick<1>, dim3((unsigned)used, Ci / 16), dim3(256), lds,
+                                   s, dz + co0, x, g, Ci, bpc, (int)nbk, pw, pb, Co);
+            else
+                hipLaunchKernelGGL(k_wgrad_brick<2>, dim3((unsigned)used, Ci / 16), dim3(256), lds,
+                                   s, dz + co0, x, g, Ci, bpc, (int)nbk, pw, pb, Co);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const int n = 27 * cg * Ci, nbw = (n + 63) / 64;
+            hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (cg + 63) / 64 : 0)), dim3(1024), 0, s,
+                               pw, pb, (int)used, n, nbw, cg, dw + (size_t)co0 * 27 * Ci,
+                               db ? db + co0 : nullptr, (Ci << 16) | cg);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
     const int tg = wgrad_taps_per_group(Ci, Co);
     const int groups = (27 + tg - 1) / tg;
