@@ -345,7 +345,7 @@ __host__ __device__ constexpr int halo_elem(int k) {
 constexpr int kXcds = 8;
 // Below this many bricks a launch of one workgroup per brick leaves the
 // device partly idle (256 CUs, two or more workgroups each), so the brick
-// kernels split 64 or 128 output channels into groups of 32, one per
+// kernels split 64 or more output channels into groups of 32, one per
 // blockIdx.y.
 constexpr long long kFewBricks = 2048;
 
@@ -1662,16 +1662,23 @@ __global__ void __launch_bounds__(1024) k_colsum_wb(const float* part, const flo
                                                     int nrow, int ncol, int nbw, int Co, float* dw,
                                                     float* db, int ci_co) {
     // a workgroup: 64 columns x 16 row groups (row group g sums rows g,
-    // g + 16, ...), the 16 partial sums then added in a fixed order
+    // g + 16, ...), the 16 partial sums then added in a fixed order.  The
+    // layer's Co outputs come in groups of cg = ci_co & 0xFFFF (each group's
+    // partials [row][t][co][ci] and bias partials [row][co] one after the
+    // other); column c < ncol = 27 Co Ci is (group, t, co, ci).
     __shared__ float red[16][64];
     const bool wpart = (int)blockIdx.x < nbw;
-    const float* src = wpart ? part : part_b;
-    const int nc = wpart ? ncol : Co;
+    const int Ci = ci_co >> 16, cg = ci_co & 0xFFFF;
     const int o = threadIdx.x & 63, gr = threadIdx.x >> 6;
     const int c = (wpart ? (int)blockIdx.x : (int)blockIdx.x - nbw) * 64 + o;
+    const int nc = wpart ? ncol : Co;
+    const int ng = 27 * cg * Ci;   // weight columns per group
+    const int grp = wpart ? c / ng : c / cg, cc = wpart ? c - grp * ng : c - grp * cg;
+    const float* src = wpart ? part + (size_t)grp * nrow * ng : part_b + (size_t)grp * nrow * cg;
+    const int stride = wpart ? ng : cg;
     float s = 0.0f;
     if (c < nc)
-        for (int r = gr; r < nrow; r += 16) s += src[(size_t)r * nc + c];
+        for (int r = gr; r < nrow; r += 16) s += src[(size_t)r * stride + cc];
     red[gr][o] = s;
     __syncthreads();
     if (gr == 0 && c < nc) {
@@ -1679,8 +1686,7 @@ __global__ void __launch_bounds__(1024) k_colsum_wb(const float* part, const flo
 #pragma unroll
         for (int k = 0; k < 16; ++k) t += red[k][o];
         if (wpart) {
-            const int Ci = ci_co >> 16, Cw = ci_co & 0xFFFF;
-            const int ci = c % Ci, co = (c / Ci) % Cw, tap = c / (Ci * Cw);
+            const int ci = cc % Ci, co = grp * cg + (cc / Ci) % cg, tap = cc / (Ci * cg);
             dw[((size_t)co * 27 + tap) * Ci + ci] = t;
         } else {
             db[c] = t;
@@ -2171,18 +2177,18 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         if (Co == 16 && Ci == 48)
             return launch_rows<48, 48>(x, nullptr, w, bias, g, alpha, act, y16, y32, accumulate, s);
         bool done = true;
-        // 32 outputs, or 64 in two groups when the bricks are too few to fill
-        // the device
+        // 32 outputs, 96 as three groups of 32, or 64 as two when the bricks
+        // are too few to fill the device
         const bool few = nbk < kFewBricks;
-        if (Ci == 16 && (nt == 2 || (nt == 4 && few))) LAUNCH_REG(16, 2, 14);
-        else if (Ci == 32 && (nt == 2 || (nt == 4 && few))) LAUNCH_REG(32, 2, 7);
+        if (Ci == 16 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(16, 2, 14);
+        else if (Ci == 32 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(32, 2, 7);
         else done = false;
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
     }
     const bool few = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                          ((g.D + kRZ - 1) / kRZ) * g.B < kFewBricks;
-    if (Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4 || (nt == 8 && few))) {
+    if (Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4 || (nt % 2 == 0 && few))) {
         // wide input, channel passes (on few bricks in groups of 32 outputs)
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
@@ -2387,7 +2393,11 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
         if (nbk > (1LL << 30)) return hipErrorInvalidValue;
-        const long long want = std::min(nchunk, nbk);
+        // about 512 workgroups per launch (two per CU, one round): fewer
+        // split-K rows for the column sums, more bricks per workgroup to
+        // pipeline
+        const long long want =
+            std::max(1LL, std::min({nchunk, nbk, 512LL / std::max(1, Ci / 16)}));
         const int bpc = (int)((nbk + want - 1) / want);
         const long long used = (nbk + bpc - 1) / bpc;   // <= nchunk
         float* part_b = part + used * 27LL * Co * Ci;
@@ -2404,14 +2414,11 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                                    s, dz + co0, x, g, Ci, bpc, (int)nbk, pw, pb, Co);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            const int n = 27 * cg * Ci, nbw = (n + 63) / 64;
-            hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (cg + 63) / 64 : 0)), dim3(1024), 0, s,
-                               pw, pb, (int)used, n, nbw, cg, dw + (size_t)co0 * 27 * Ci,
-                               db ? db + co0 : nullptr, (Ci << 16) | cg);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
         }
-        return hipSuccess;
+        const int n = 27 * Co * Ci, nbw = (n + 63) / 64;
+        hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (Co + 63) / 64 : 0)), dim3(1024), 0, s,
+                           part, part_b, (int)used, n, nbw, Co, dw, db, (Ci << 16) | cg);
+        return hipGetLastError();
     }
     const int tg = wgrad_taps_per_group(Ci, Co);
     const int groups = (27 + tg - 1) / tg;
