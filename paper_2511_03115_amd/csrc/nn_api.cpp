@@ -196,9 +196,12 @@ int run_forward(sde_nn* n, const int* d0) {
 // gradient goes (FP32) into dx when non-null, or, through the LeakyReLU
 // derivative of the input activation y_in, (bf16) into dz_next when that is
 // non-null (16 -> 16 convs).  The flipped weights are in n->wt_all (offset cp.w).
+// With dx_hi non-null the input gradient is split at channel cs: [0, cs)
+// into dx, [cs, ci) into dx_hi (conv_fwd_split).
 int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, const ConvP& cp,
              const int* d, float* dx, const uint16_t* dz_ready = nullptr,
-             const uint16_t* y_in = nullptr, uint16_t* dz_next = nullptr) {
+             const uint16_t* y_in = nullptr, uint16_t* dz_next = nullptr, float* dx_hi = nullptr,
+             int cs = 0) {
     hipStream_t s = library_stream();
     const uint16_t* dz = dz_ready;
     if (!dz) {
@@ -209,6 +212,8 @@ int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, c
     NN_TRY(wgrad(dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
     if (dz_next)
         NN_TRY(conv_dz_fwd(dz, n->wt_all + cp.w, d, y_in, n->cfg.leaky_alpha, dz_next, s));
+    else if (dx_hi)
+        NN_TRY(conv_fwd_split(dz, n->wt_all + cp.w, d, cp.co, cp.ci, cs, dx, dx_hi, s));
     else if (dx)
         NN_TRY(conv_fwd(dz, n->wt_all + cp.w, nullptr, d, cp.co, cp.ci, 0.0f, 0, nullptr, dx, 0, s));
     return SDE_OK;
@@ -253,19 +258,31 @@ int run_backward(sde_nn* n, const int* d0) {
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
         const uint16_t* dzb = l == 0 && head_dz ? n->dz : nullptr;   // from the head
+        // the level-0 decoder conv's input gradient goes straight into the
+        // skip's gradient and the upsampled half (kept in gCat's memory)
+        const bool split = n->dec_a[l].ci == 48 && n->dec_a[l].co == 16 && n->c[l] == 16;
+        float* dx = split ? v.gE : v.gCat;
+        float* dx_hi = split ? v.gCat : nullptr;
         if (dz_chain(n->dec_b[l])) {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da,
                                  n->dz2))
                 return r;
-            if (int r = conv_bwd(n, nullptr, nullptr, v.cat, n->dec_a[l], d, v.gCat, n->dz2))
+            if (int r = conv_bwd(n, nullptr, nullptr, v.cat, n->dec_a[l], d, dx, n->dz2, nullptr,
+                                 nullptr, dx_hi, n->c[l]))
                 return r;
         } else {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa, dzb)) return r;
-            if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, v.gCat)) return r;
+            if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, dx, nullptr, nullptr,
+                                 nullptr, dx_hi, n->c[l]))
+                return r;
         }
-        NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
         float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
-        NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s));
+        if (split) {
+            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], n->c[l + 1], 0, tgt, s));
+        } else {
+            NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
+            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s));
+        }
     }
     for (int l = L - 1; l >= 0; --l) {
         dims_at(d0, l, d);

@@ -2272,6 +2272,16 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
     return launch_rows<48, 16>(skip, low, w, bias, g, alpha, act, y16, nullptr, 0, s);
 }
 
+hipError_t conv_fwd_split(const uint16_t* x, const uint16_t* w, const int* dims, int Ci, int Co,
+                          int cs, float* ya, float* yb, hipStream_t s) {
+    Geo g{dims[0], dims[1], dims[2], dims[3]};
+    if (Ci != 16 || Co != 48 || cs != 16 || !ya || !yb) return hipErrorInvalidValue;
+    hipError_t e = launch_rows<16, 16>(x, nullptr, w, nullptr, g, 0.0f, 0, nullptr, ya, 0, s, 1);
+    if (e != hipSuccess) return e;
+    return launch_rows<16, 16>(x, nullptr, w + 16LL * 27 * 16, nullptr, g, 0.0f, 0, nullptr, yb, 0,
+                               s, 2);
+}
+
 hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
                          float alpha, uint16_t* y16, uint16_t* pool, hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
