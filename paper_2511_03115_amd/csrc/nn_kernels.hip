@@ -1085,7 +1085,9 @@ __global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2
 // The halo-brick convolution for wide inputs (Ci a multiple of 32, at least
 // 64) with 32 or 64 outputs: the input channels are taken 32 at a time
 // (one pass each), so the brick of one pass (6 x 6 x 18 voxels x 32
-// channels, 48 KB of LDS) leaves room for two workgroups per CU.  Within a
+// channels, 51 KB of LDS with the slot pad) leaves room for OCC workgroups
+// per CU: three for 32 outputs (weight chunks of 2 taps keep the registers
+// within three waves per SIMD), two for 64.  Within a
 // pass each K step is one tap over the pass's 32 channels, so the LDS
 // offset of a step is the tap's, uniform over the wave.  The next pass's
 // brick is fetched with every load in flight before the first store, and
@@ -1095,8 +1097,8 @@ __global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2
 // decoder's concatenation; cs = Ci for a plain input).  K order: pass,
 // tap, channel.
 // ---------------------------------------------------------------------------
-template <int NT, int CH>
-__global__ void __launch_bounds__(256, 2) k_conv_fwd_pass(const uint16_t* __restrict__ x,
+template <int NT, int CH, int OCC = 2>
+__global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __restrict__ x,
                                                        const uint16_t* __restrict__ xl,
                                                        const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias, Geo g,
@@ -2194,7 +2196,7 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
                               ((g.D + kRZ - 1) / kRZ) * g.B;
         const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
         if (nt == 2 || few)
-            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk, nt / 2), dim3(256),
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 2, 3>), dim3((unsigned)nbk, nt / 2), dim3(256),
                                lds_p, s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
                                accumulate);
         else
@@ -2260,7 +2262,7 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
     if (Co == 32 || Co == 64) {
         const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
         if (Co == 32 || nbk < kFewBricks)   // 64 outputs on few bricks: two groups of 32
-            hipLaunchKernelGGL((k_conv_fwd_pass<2, 5>), dim3((unsigned)nbk, Co / 32), dim3(256),
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 2, 3>), dim3((unsigned)nbk, Co / 32), dim3(256),
                                lds_p, s, skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16,
                                nullptr, 0);
         else
