@@ -1471,8 +1471,12 @@ __global__ void __launch_bounds__(256) k_wgrad_partial(const uint16_t* __restric
 // thread).  Row pads keep the 16 rows a quarter-wave reads on distinct
 // banks.
 // ---------------------------------------------------------------------------
-constexpr int kWbXRow = 36 * 16 + 8;   // per input channel: 6 x 6 halo rows of 16
-constexpr int kWbDRow = 256 + 8;       // per output channel: the brick's voxels
+// Row pads: a 16-byte fragment read is served 16 lanes a clock (8 lanes of
+// one lane quarter with the 8 of the next), and those lanes' rows then fall
+// on 16 distinct 16-byte bank groups when rows are 32, 96, 160 or 224 bytes
+// apart modulo 256 (gfx950's 64 banks of 4 bytes).
+constexpr int kWbXRow = 36 * 16 + 16;   // per input channel: 6 x 6 halo rows of 16 (1184 B)
+constexpr int kWbDRow = 256 + 16;       // per output channel: the brick's voxels (544 B)
 constexpr int kWbTaps = 7;             // taps per wave: w, w + 4, ..., < 27
 
 int wgrad_brick_lds_bytes(int Co) { return (3 * 16 * kWbXRow + Co * kWbDRow) * 2; }
