@@ -1503,13 +1503,15 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
         for (int j = 0; j < NCO; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;
     const int bk1 = min(nbk, (c + 1) * bpc);
-    // Staging items: dz item i < 32 Co / 8 (8 voxels along x x 8 channels)
-    // and input item i < 3 x 36 x 4 (copy d, halo row, half, channel group),
-    // each 8 16-byte loads, transposed into LDS.  Thread t owns dz item t and
-    // input items t and t + 256; with 16 outputs the next brick's loads are
-    // issued into registers before the current brick's matrix-core work.
-    constexpr int NDZ = 32 * (Co / 8), NXI = 3 * 36 * 4;
-    uint4 rdz[8], rx[2][8];
+    // Staging items: dz item i < 32 Co / 8 (8 voxels along x x 8 channels,
+    // 8 16-byte loads) and input item i < 36 x 4 (halo row, half, channel
+    // group: the 10 voxels x0 + 8 half - 1 + [0, 10), 10 loads, from which
+    // the three copies shifted by dx = -1, 0, +1 take 8 each), transposed
+    // into LDS.  Thread t owns dz item t and input item t; with 16 outputs
+    // the next brick's loads are issued into registers before the current
+    // brick's matrix-core work.
+    constexpr int NDZ = 32 * (Co / 8), NXI = 36 * 4;
+    uint4 rdz[8], rx[10];
     // buffer loads (32-bit offsets; the host keeps both operands below 2 GiB):
     // a voxel outside the volume is read at an offset past the end, which
     // the hardware answers with zeros, so no load sits behind a branch
@@ -1535,16 +1537,15 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
                                                        dzr, rin && xs + k < g.W ? o + k * dzc * 2 : kOob,
                                                        0, 0));
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = tid + 256 * h;
-            const int d = i / 144, rem = i % 144, row = rem >> 2, hh = (rem >> 1) & 1, cg = rem & 1;
-            const int zz = z0 - 1 + row / 6, yy = y0 - 1 + row % 6, xs = x0 + d - 1 + hh * 8;
+        {
+            const int i = tid;
+            const int row = i >> 2, hh = (i >> 1) & 1, cg = i & 1;
+            const int zz = z0 - 1 + row / 6, yy = y0 - 1 + row % 6, xs = x0 - 1 + hh * 8;
             const bool rin = i < NXI && zz >= 0 && yy >= 0 && zz < g.D && yy < g.H;
             const int o = ((((b * g.D + zz) * g.H + yy) * g.W + xs) * Ci + ci0 + cg * 8) * 2;
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                rx[h][k] = __builtin_bit_cast(
+            for (int k = 0; k < 10; ++k)
+                rx[k] = __builtin_bit_cast(
                     uint4, __builtin_amdgcn_raw_buffer_load_b128(
                                xr, rin && xs + k >= 0 && xs + k < g.W ? o + k * Ci * 2 : kOob, 0, 0));
         }
@@ -1558,16 +1559,19 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
             for (int cc = 0; cc < 8; ++cc)
                 *reinterpret_cast<uint4*>(dzT + (ch + cc) * kWbDRow + vg * 8) = out[cc];
         }
+        if (tid < NXI) {
+            const int row = tid >> 2, hh = (tid >> 1) & 1, cg = tid & 1;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = tid + 256 * h;
-            if (i >= NXI) continue;
-            const int d = i / 144, rem = i % 144, row = rem >> 2, hh = (rem >> 1) & 1, cg = rem & 1;
-            transpose8x8(rx[h], out);
+            for (int d = 0; d < 3; ++d) {
+                uint4 in8[8];
 #pragma unroll
-            for (int cc = 0; cc < 8; ++cc)
-                *reinterpret_cast<uint4*>(xT + (d * 16 + cg * 8 + cc) * kWbXRow + row * 16 + hh * 8) =
-                    out[cc];
+                for (int k = 0; k < 8; ++k) in8[k] = rx[d + k];
+                transpose8x8(in8, out);
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc)
+                    *reinterpret_cast<uint4*>(xT + (d * 16 + cg * 8 + cc) * kWbXRow + row * 16 +
+                                              hh * 8) = out[cc];
+            }
         }
     };
     // 32 outputs: the registers of a prefetch would cost half the
