@@ -126,6 +126,15 @@ bool first_from_pairs(const sde_nn* n) { return n->enc_a[0].co == 16; }
 // The input rows x16 are written when a conv reads them.
 uint16_t* input_rows(sde_nn* n) { return n->cfg.train || !first_from_pairs(n) ? n->x16 : nullptr; }
 
+// The decoder conv of level l reads the concatenation [skip, up(low)] in
+// place (inference always where the conv supports it; training also needs
+// the weight gradient to read it so); otherwise it is stored in lv[l].cat.
+bool cat_in_place(const sde_nn* n, int l, const int* d) {
+    const ConvP& cp = n->dec_a[l];
+    return conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co, nvox(d)) &&
+           (!n->cfg.train || wgrad_cat_supported(n->c[l], n->c[l + 1], cp.co, d));
+}
+
 int run_forward(sde_nn* n, const int* d0) {
     hipStream_t s = library_stream();
     int d[4], dc[4];
@@ -164,9 +173,7 @@ int run_forward(sde_nn* n, const int* d0) {
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
         const ConvP& cp = n->dec_a[l];
-        if (!n->cfg.train && conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co, nvox(d))) {
-            // inference: the concatenation is read in place (training keeps it
-            // for the weight gradient)
+        if (cat_in_place(n, l, d)) {
             NN_TRY(conv_cat_fwd(v.eb, top, n->P16 + cp.w, n->P + cp.b, d, n->c[l], n->c[l + 1],
                                 cp.co, n->cfg.leaky_alpha, 1, v.da, s));
         } else {
@@ -197,11 +204,12 @@ int run_forward(sde_nn* n, const int* d0) {
 // derivative of the input activation y_in, (bf16) into dz_next when that is
 // non-null (16 -> 16 convs).  The flipped weights are in n->wt_all (offset cp.w).
 // With dx_hi non-null the input gradient is split at channel cs: [0, cs)
-// into dx, [cs, ci) into dx_hi (conv_fwd_split).
+// into dx, [cs, ci) into dx_hi (conv_fwd_split).  With x_low non-null the
+// input is the concatenation [x (cs channels), up(x_low)] read in place.
 int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, const ConvP& cp,
              const int* d, float* dx, const uint16_t* dz_ready = nullptr,
              const uint16_t* y_in = nullptr, uint16_t* dz_next = nullptr, float* dx_hi = nullptr,
-             int cs = 0) {
+             int cs = 0, const uint16_t* x_low = nullptr) {
     hipStream_t s = library_stream();
     const uint16_t* dz = dz_ready;
     if (!dz) {
@@ -209,7 +217,11 @@ int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, c
         dz = n->dz;
     }
     const int chunk = wgrad_chunk_for(d, cp.ci, cp.co, kMaxPartFloats);
-    NN_TRY(wgrad(dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
+    if (x_low)
+        NN_TRY(wgrad_cat(dz, x, x_low, d, cs, cp.ci - cs, cp.co, chunk, n->wpart, n->G + cp.w,
+                         n->G + cp.b, s));
+    else
+        NN_TRY(wgrad(dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
     if (dz_next)
         NN_TRY(conv_dz_fwd(dz, n->wt_all + cp.w, d, y_in, n->cfg.leaky_alpha, dz_next, s));
     else if (dx_hi)
@@ -263,17 +275,23 @@ int run_backward(sde_nn* n, const int* d0) {
         const bool split = n->dec_a[l].ci == 48 && n->dec_a[l].co == 16 && n->c[l] == 16;
         float* dx = split ? v.gE : v.gCat;
         float* dx_hi = split ? v.gCat : nullptr;
+        // the decoder conv's input: the stored concatenation, or the skip and
+        // the level below read in place
+        const bool inplace = cat_in_place(n, l, d);
+        const uint16_t* low = l + 1 <= L - 2 ? n->lv[l + 1].db : n->lv[L - 1].eb;
+        const uint16_t* xin = inplace ? v.eb : v.cat;
+        const uint16_t* xlow = inplace ? low : nullptr;
         if (dz_chain(n->dec_b[l])) {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da,
                                  n->dz2))
                 return r;
-            if (int r = conv_bwd(n, nullptr, nullptr, v.cat, n->dec_a[l], d, dx, n->dz2, nullptr,
-                                 nullptr, dx_hi, n->c[l]))
+            if (int r = conv_bwd(n, nullptr, nullptr, xin, n->dec_a[l], d, dx, n->dz2, nullptr,
+                                 nullptr, dx_hi, n->c[l], xlow))
                 return r;
         } else {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa, dzb)) return r;
-            if (int r = conv_bwd(n, v.gDa, v.da, v.cat, n->dec_a[l], d, dx, nullptr, nullptr,
-                                 nullptr, dx_hi, n->c[l]))
+            if (int r = conv_bwd(n, v.gDa, v.da, xin, n->dec_a[l], d, dx, nullptr, nullptr,
+                                 nullptr, dx_hi, n->c[l], xlow))
                 return r;
         }
         float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;

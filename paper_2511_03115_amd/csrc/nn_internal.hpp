@@ -74,6 +74,14 @@ int wgrad_chunk_for(const int* dims, int Ci, int Co, long long max_part_floats);
 long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk);
 hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
                  float* part, float* dw, float* db, hipStream_t s);
+// wgrad of a conv whose input is the decoder's concatenation [skip (Cs
+// channels), nearest-upsampled low (Cu channels, half-size level)], read in
+// place.  Supported (by bricks) when wgrad_cat_supported says so; the part
+// buffer is sized as for wgrad with Ci = Cs + Cu.
+bool wgrad_cat_supported(int Cs, int Cu, int Co, const int* dims);
+hipError_t wgrad_cat(const uint16_t* dz, const uint16_t* skip, const uint16_t* low,
+                     const int* dims, int Cs, int Cu, int Co, int chunk, float* part, float* dw,
+                     float* db, hipStream_t s);
 hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n, uint16_t* dz,
                      hipStream_t s);
 hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, hipStream_t s);

@@ -1484,10 +1484,15 @@ int wgrad_brick_lds_bytes(int Co) { return (3 * 16 * kWbXRow + Co * kWbDRow) * 2
 template <int NCO>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_wgrad_brick(const uint16_t* __restrict__ dz,
-                                                     const uint16_t* __restrict__ x, Geo g, int Ci,
-                                                     int bpc, int nbk, float* __restrict__ part,
+                                                     const uint16_t* __restrict__ x,
+                                                     const uint16_t* __restrict__ xl, Geo g, int Ci,
+                                                     int Cs, int bpc, int nbk,
+                                                     float* __restrict__ part,
                                                      float* __restrict__ part_b, int dzc) {
-    // dz: Co = 16 NCO output channels of dzc per voxel (a group of a wider layer)
+    // dz: Co = 16 NCO output channels of dzc per voxel (a group of a wider layer).
+    // Input channels [0, Cs) come from x (Cs per voxel), [Cs, Ci) from the
+    // half-size level xl, nearest-neighbour upsampled (the decoder's
+    // concatenation read in place; Cs = Ci for a plain input).
     constexpr int Co = NCO * 16;
     extern __shared__ __align__(16) uint16_t lds[];
     uint16_t* xT = lds;                          // [3][16][kWbXRow]
@@ -1516,7 +1521,12 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
     // a voxel outside the volume is read at an offset past the end, which
     // the hardware answers with zeros, so no load sits behind a branch
     const __amdgpu_buffer_rsrc_t dzr = rsrc16(dz, g.nvox() * dzc);
-    const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * Ci);
+    // this workgroup's 16 input channels come from one source (Cs is a
+    // multiple of 16)
+    const bool lowsrc = ci0 >= Cs;
+    const int Cu = Ci - Cs, Dd = g.D >> 1, Hd = g.H >> 1, Wd = g.W >> 1;
+    const __amdgpu_buffer_rsrc_t xr =
+        lowsrc ? rsrc16(xl, (long long)Dd * Hd * Wd * g.B * Cu) : rsrc16(x, g.nvox() * Cs);
     auto load_raw = [&](int bk) {
         int r = bk;
         const int x0 = (r % nbx) * kRX;
@@ -1542,12 +1552,18 @@ k_wgrad_brick(const uint16_t* __restrict__ dz,
             const int row = i >> 2, hh = (i >> 1) & 1, cg = i & 1;
             const int zz = z0 - 1 + row / 6, yy = y0 - 1 + row % 6, xs = x0 - 1 + hh * 8;
             const bool rin = i < NXI && zz >= 0 && yy >= 0 && zz < g.D && yy < g.H;
-            const int o = ((((b * g.D + zz) * g.H + yy) * g.W + xs) * Ci + ci0 + cg * 8) * 2;
+            // voxel offset of (xs, yy, zz) and channel offset, in x or (the
+            // parent voxels) in xl
+            const int ov = lowsrc ? ((b * Dd + (zz >> 1)) * Hd + (yy >> 1)) * Wd
+                                  : ((b * g.D + zz) * g.H + yy) * g.W + xs;
+            const int oc = lowsrc ? ci0 - Cs + cg * 8 : ci0 + cg * 8;
 #pragma unroll
-            for (int k = 0; k < 10; ++k)
+            for (int k = 0; k < 10; ++k) {
+                const int o = lowsrc ? ((ov + ((xs + k) >> 1)) * Cu + oc) * 2 : ((ov + k) * Cs + oc) * 2;
                 rx[k] = __builtin_bit_cast(
                     uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                               xr, rin && xs + k >= 0 && xs + k < g.W ? o + k * Ci * 2 : kOob, 0, 0));
+                               xr, rin && xs + k >= 0 && xs + k < g.W ? o : kOob, 0, 0));
+            }
         }
     };
     auto store_lds = [&]() {
@@ -2393,12 +2409,19 @@ long long wgrad_part_floats(const int* dims, int Ci, int Co, int chunk) {
     return wgrad_chunks(dims, chunk) * (27LL * Ci * Co + Co);
 }
 
-hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
-                 float* part, float* dw, float* db, hipStream_t s) {
+namespace {
+bool wgrad_by_bricks(const Geo& g, int Ci, int Co) {
+    return (Co == 16 || Co == 32 || Co == 64 || Co == 128) &&
+           g.nvox() * std::max(Ci, Co) * 2 < (1LL << 31);
+}
+
+// x: Cs channels per voxel; xl (the half-size level, Ci - Cs channels) when Cs < Ci
+hipError_t wgrad_impl(const uint16_t* dz, const uint16_t* x, const uint16_t* xl, const int* dims,
+                      int Ci, int Cs, int Co, int chunk, float* part, float* dw, float* db,
+                      hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     long long nchunk = wgrad_chunks(dims, chunk);
-    if ((Co == 16 || Co == 32 || Co == 64 || Co == 128) &&
-        g.nvox() * std::max(Ci, Co) * 2 < (1LL << 31)) {
+    if (wgrad_by_bricks(g, Ci, Co)) {
         // by bricks, within the same partial-sum buffer (32-bit buffer offsets);
         // 64 or 128 outputs as groups of 32, each with its own partials
         static const hipError_t attr = [] {
@@ -2428,10 +2451,10 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
             const size_t lds = (size_t)wgrad_brick_lds_bytes(cg);
             if (cg == 16)
                 hipLaunchKernelGGL(k_wgrad_brick<1>, dim3((unsigned)used, Ci / 16), dim3(256), lds,
-                                   s, dz + co0, x, g, Ci, bpc, (int)nbk, pw, pb, Co);
+                                   s, dz + co0, x, xl, g, Ci, Cs, bpc, (int)nbk, pw, pb, Co);
             else
                 hipLaunchKernelGGL(k_wgrad_brick<2>, dim3((unsigned)used, Ci / 16), dim3(256), lds,
-                                   s, dz + co0, x, g, Ci, bpc, (int)nbk, pw, pb, Co);
+                                   s, dz + co0, x, xl, g, Ci, Cs, bpc, (int)nbk, pw, pb, Co);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -2440,6 +2463,7 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
                            part, part_b, (int)used, n, nbw, Co, dw, db, (Ci << 16) | cg);
         return hipGetLastError();
     }
+    if (Cs != Ci) return hipErrorInvalidValue;   // a concatenation is read in place by bricks only
     const int tg = wgrad_taps_per_group(Ci, Co);
     const int groups = (27 + tg - 1) / tg;
     if (tg * (Co / 16) * (Ci / 16) > kWgWaves * kWgMaxTiles && tg > 1) return hipErrorInvalidValue;
@@ -2454,6 +2478,25 @@ hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci,
     hipLaunchKernelGGL(k_colsum_wb, dim3(nbw + (db ? (Co + 63) / 64 : 0)), dim3(1024), 0, s, part,
                        part_b, (int)nchunk, n, nbw, Co, dw, db, (Ci << 16) | Co);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t wgrad(const uint16_t* dz, const uint16_t* x, const int* dims, int Ci, int Co, int chunk,
+                 float* part, float* dw, float* db, hipStream_t s) {
+    return wgrad_impl(dz, x, nullptr, dims, Ci, Ci, Co, chunk, part, dw, db, s);
+}
+
+bool wgrad_cat_supported(int Cs, int Cu, int Co, const int* dims) {
+    const Geo g{dims[0], dims[1], dims[2], dims[3]};
+    return Cs > 0 && Cu > 0 && Cs % 16 == 0 && Cu % 16 == 0 && ((g.D | g.H | g.W) & 1) == 0 &&
+           wgrad_by_bricks(g, Cs + Cu, Co);
+}
+
+hipError_t wgrad_cat(const uint16_t* dz, const uint16_t* skip, const uint16_t* low,
+                     const int* dims, int Cs, int Cu, int Co, int chunk, float* part, float* dw,
+                     float* db, hipStream_t s) {
+    if (!wgrad_cat_supported(Cs, Cu, Co, dims)) return hipErrorInvalidValue;
+    return wgrad_impl(dz, skip, low, dims, Cs + Cu, Cs, Co, chunk, part, dw, db, s);
 }
 
 hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n, uint16_t* dz,
