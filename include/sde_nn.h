@@ -54,6 +54,10 @@ typedef struct {
     int max_d, max_h, max_w;
     int train;           /* nonzero: allocate gradient, Adam and loss buffers */
     float adam_beta1, adam_beta2, adam_eps;
+    int store_concat;    /* nonzero: each decoder level stores concat[skip, up(lower)]
+                            before its conv; zero: the convs (and in training the
+                            weight gradients) read it in place where they support
+                            the shape (the same sums in the same order either way) */
 } sde_nn_config;
 
 /* Create a network; parameters start at zero (set them with

@@ -131,7 +131,7 @@ uint16_t* input_rows(sde_nn* n) { return n->cfg.train || !first_from_pairs(n) ? 
 // the weight gradient to read it so); otherwise it is stored in lv[l].cat.
 bool cat_in_place(const sde_nn* n, int l, const int* d) {
     const ConvP& cp = n->dec_a[l];
-    return conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co, nvox(d)) &&
+    return !n->cfg.store_concat && conv_cat_fwd_supported(n->c[l], n->c[l + 1], cp.co, nvox(d)) &&
            (!n->cfg.train || wgrad_cat_supported(n->c[l], n->c[l + 1], cp.co, d));
 }
 

@@ -28,7 +28,8 @@ class Config(C.Structure):
     _fields_ = [("levels", C.c_int), ("base_channels", C.c_int), ("in_channels", C.c_int),
                 ("leaky_alpha", C.c_float), ("max_batch", C.c_int), ("max_d", C.c_int),
                 ("max_h", C.c_int), ("max_w", C.c_int), ("train", C.c_int),
-                ("adam_beta1", C.c_float), ("adam_beta2", C.c_float), ("adam_eps", C.c_float)]
+                ("adam_beta1", C.c_float), ("adam_beta2", C.c_float), ("adam_eps", C.c_float),
+                ("store_concat", C.c_int)]
 
 
 def _setup():
@@ -71,9 +72,10 @@ class Net:
 
     def __init__(self, levels: int = 4, base_channels: int = 16, in_channels: int = 16,
                  alpha: float = 0.01, max_batch: int = 1, max_dims: Tuple[int, int, int] = (64, 64, 64),
-                 train: bool = False, betas=(0.9, 0.999), eps: float = 1e-8):
+                 train: bool = False, betas=(0.9, 0.999), eps: float = 1e-8,
+                 store_concat: bool = False):
         cfg = Config(levels, base_channels, in_channels, alpha, max_batch, *max_dims, int(train),
-                     betas[0], betas[1], eps)
+                     betas[0], betas[1], eps, int(store_concat))
         h = C.c_void_p()
         _check(lib.sde_nn_create(C.byref(cfg), C.byref(h)))
         self._h = h

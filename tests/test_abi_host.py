@@ -116,7 +116,7 @@ def test_nn_config_validation_without_gpu(lib):
     def create(**kw):
         base = dict(levels=4, base_channels=16, in_channels=16, leaky_alpha=0.01, max_batch=1,
                     max_d=64, max_h=64, max_w=64, train=0, adam_beta1=0.9, adam_beta2=0.999,
-                    adam_eps=1e-8)
+                    adam_eps=1e-8, store_concat=0)
         base.update(kw)
         cfg = nn.Config(*[base[f] for f, _ in nn.Config._fields_])
         return lib.sde_nn_create(C.byref(cfg), C.byref(h))

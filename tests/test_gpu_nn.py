@@ -211,29 +211,38 @@ def test_network_forward_and_gradients(levels, B, D, H, W):
 
 @pytest.mark.parametrize("levels,B,D,H,W", [(4, 1, 16, 24, 40), (2, 2, 6, 10, 14),
                                              (2, 2, 14, 18, 50)])
-def test_inference_reads_the_concatenation_in_place(levels, B, D, H, W):
-    """An inference network reads the decoder input concat[skip, up(lower)]
-    straight from the two levels; a training network stores it first.  The
-    sums are the same in the same order, so the outputs are bit-identical
-    (sizes with ragged bricks, and with bricks whose halo lies inside the
-    volume, which take the staging path without bounds tests, in a batch of 2)."""
+def test_concatenation_in_place_equals_stored(levels, B, D, H, W):
+    """The decoder input concat[skip, up(lower)] read straight from the two
+    levels (inference, and training's forward conv and weight gradient)
+    against the same network storing it first (store_concat): the sums are
+    the same in the same order, so the outputs, the loss and every gradient
+    are bit-identical (sizes with ragged bricks, and with bricks whose halo
+    lies inside the volume, which take the staging path without bounds
+    tests, in a batch of 2)."""
     import torch
     from paper_2511_03115_amd import nn
     c0, cin, alpha = 16, 16, 0.01
     flat = nno.flatten(he_params(levels, c0, cin, seed=21), levels, c0, cin).astype(np.float32)
-    dose, rho, _, _ = _net_inputs(B, D, H, W, seed=22)
+    dose, rho, tgt, wgt = _net_inputs(B, D, H, W, seed=22)
     dev = lambda a: torch.from_numpy(a).cuda()
-    outs = []
-    for train in (False, True):
-        log(f"case fused concat L={levels} dims={(B, D, H, W)} train={train}")
-        net = nn.Net(levels, c0, cin, alpha, max_batch=B, max_dims=(D, H, W), train=train)
+    outs, losses, grads = [], [], []
+    for train, stored in ((False, False), (True, False), (True, True)):
+        log(f"case concat L={levels} dims={(B, D, H, W)} train={train} stored={stored}")
+        net = nn.Net(levels, c0, cin, alpha, max_batch=B, max_dims=(D, H, W), train=train,
+                     store_concat=stored)
         net.set_params(flat)
         out = torch.zeros((B, D, H, W), dtype=torch.float32, device="cuda")
         net.forward(dev(dose), dev(rho), out)
         outs.append(out.cpu().numpy())
+        if train:
+            losses.append(net.loss_grad(dev(dose), dev(rho), dev(tgt), dev(wgt)))
+            grads.append(net.get_grads())
         net.close()
     assert np.isfinite(outs[0]).all()
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    assert losses[0] == losses[1]
+    assert np.isfinite(grads[0]).all() and np.abs(grads[0]).max() > 0
+    assert np.array_equal(grads[0], grads[1])
 
 
 def test_adam_update_matches_oracle():
