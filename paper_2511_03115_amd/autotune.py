@@ -88,21 +88,21 @@ def tile_candidates(spots, phantom, budget_bytes: int) -> List[dict]:
 
 def candidates(spots, phantom) -> List[dict]:
     n_cu, max_lds, table = sde.launch_limits()
-    cands = [{"block": 512, "grid": 2 * n_cu, "refill": r} for r in (1, 4, 8)]
+    cands = [{"block": 512, "grid": 2 * n_cu, "refill": r} for r in (2, 4, 8)]
     spread = max(s.sigma_xy_cm for s in spots)
     xs = [s.x_cm for s in spots]
     ys = [s.y_cm for s in spots]
     footprint = max(max(xs) - min(xs), max(ys) - min(ys)) + 6 * spread
     if footprint < 4.0:   # a concentrated beam: its core is worth privatising in LDS
         for t in tile_candidates(spots, phantom, max_lds - table):
-            for r in (1, 8):
+            for r in (2, 8):
                 cands.append(dict({"block": 1024, "grid": n_cu, "refill": r}, **t))
         for t in tile_candidates(spots, phantom, max_lds // 2 - table):
             cands.append(dict({"block": 512, "grid": 2 * n_cu, "refill": 1}, **t))
     return cands
 
 
-def tune(spots, phantom, seed: int = 0, n_tune: int = 1_000_000, use_cache: bool = True,
+def tune(spots, phantom, seed: int = 0, n_tune: int = 4_000_000, use_cache: bool = True,
          verbose: bool = False) -> dict:
     """Fastest launch configuration for this beam and (device) phantom."""
     import torch
