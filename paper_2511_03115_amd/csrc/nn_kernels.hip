@@ -1085,17 +1085,17 @@ __global__ void __launch_bounds__(256) k_conv_in(const uint32_t* __restrict__ x2
 // The halo-brick convolution for wide inputs (Ci a multiple of 32, at least
 // 64) with 32 or 64 outputs: the input channels are taken 32 at a time
 // (one pass each), so the brick of one pass (6 x 6 x 18 voxels x 32
-// channels, 51 KB of LDS with the slot pad) leaves room for OCC workgroups
-// per CU: three for 32 outputs (weight chunks of 2 taps keep the registers
-// within three waves per SIMD), two for 64.  Within a
-// pass each K step is one tap over the pass's 32 channels, so the LDS
-// offset of a step is the tap's, uniform over the wave.  The next pass's
-// brick is fetched with every load in flight before the first store, and
-// the weight fragments stream through registers in chunks of CH taps, the
-// next chunk in flight.  Channels [0, cs) come from x (cs per voxel) and
-// [cs, Ci) from the half-size level xl, nearest-neighbour upsampled (the
-// decoder's concatenation; cs = Ci for a plain input).  K order: pass,
-// tap, channel.
+// channels, 51 KB of LDS with the slot pad) and two weight chunks leave room
+// for two workgroups per CU.  Within a pass each K step is one tap over the
+// pass's 32 channels, so the LDS offset of a step is the tap's, uniform over
+// the wave.  The next pass's brick is fetched with every load in flight
+// before the first store; the weights go through LDS in chunks of CH taps,
+// each loaded once per workgroup (a 16-byte unit per thread) while the
+// previous chunk feeds the matrix cores (every wave fetching every fragment
+// from L2 kept the vector-memory queue full).  Channels [0, cs) come from x
+// (cs per voxel) and [cs, Ci) from the half-size level xl,
+// nearest-neighbour upsampled (the decoder's concatenation; cs = Ci for a
+// plain input).  K order: pass, tap, channel.
 // ---------------------------------------------------------------------------
 template <int NT, int CH, int OCC = 2>
 __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __restrict__ x,
@@ -1165,39 +1165,49 @@ __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __re
             }
         }
     };
-    // chunk c of pass p: taps [c CH, c CH + CH) over channels [p CP, p CP + CP).
-    // Buffer loads: the lane's part of the offset in a VGPR, the uniform
-    // part (tap, pass, column tile) in an SGPR.
-    // descriptor word 3 of gfx9: 32-bit data format (a zero format reads zeros)
+    // chunk c of pass p: taps [c CH, c CH + CH) over channels [p CP, p CP + CP),
+    // staged once per workgroup in LDS (two buffers: the next chunk is loaded
+    // while the current one feeds the matrix cores) instead of every wave
+    // fetching all of it.  A chunk is CH NT fragments B[k][n] = w[n][k] of
+    // 16 outputs x 32 channels; in LDS a fragment is [q / 2][n][q % 2][8]
+    // (q the lane quarter, 8 channels each), so that the 16 lanes one clock
+    // serves (8 of one quarter, 8 of the next) read 16 distinct bank groups.
+    constexpr int NFR = CH * NT;                // fragments per chunk
+    constexpr int PT = NFR * 64 / 256;          // 16-byte units per thread and chunk
+    static_assert(NFR * 64 % 256 == 0, "a chunk is whole 16-byte units per thread");
+    uint16_t* wl = hx + kRVox * ROW;            // [2][NFR][512] after the brick
     const __amdgpu_buffer_rsrc_t wres =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(w), 0, Co * K * 2, 0x00020000);
-    const int wlane = ((lane & 15) * K + q * 8) * 2;
-    // The uniform offset advances by one tap at a time behind an empty asm,
-    // so the compiler computes it where it is used instead of keeping the
-    // offsets of all 27 taps live in scalar registers.
-    auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int p, int c) {
-        int so = (c * CH * Ci + p * CP) * 2;
-        asm volatile("" : "+s"(so));
+    auto load_chunk = [&](uint4 (&r)[PT], int p, int c) {
 #pragma unroll
-        for (int s2 = 0; s2 < CH; ++s2) {
-            const int t = c * CH + s2;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (t < 27)
-                    v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                      wres, wlane, so + j * 32 * K, 0));
-                dst[s2][j] = as_bf16x8(v);
-            }
-            so += 2 * Ci;
-            asm volatile("" : "+s"(so));
+        for (int e = 0; e < PT; ++e) {
+            const int i = (int)threadIdx.x + 256 * e;   // 16-byte unit of the chunk
+            const int f = i >> 6, n = (i >> 2) & 15, qq = i & 3;
+            const int s2 = f / NT, j = f % NT, t = c * CH + s2;
+            r[e] = make_uint4(0, 0, 0, 0);
+            if (t < 27)
+                r[e] = __builtin_bit_cast(
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                               wres, ((j * 16 + n) * K + t * Ci + p * CP + qq * 8) * 2, 0, 0));
         }
     };
-    bf16x8 wb[2][CH][NT];
+    auto store_chunk = [&](const uint4 (&r)[PT], int buf) {
+#pragma unroll
+        for (int e = 0; e < PT; ++e) {
+            const int i = (int)threadIdx.x + 256 * e;
+            const int f = i >> 6, n = (i >> 2) & 15, qq = i & 3;
+            *reinterpret_cast<uint4*>(wl + (buf * NFR + f) * 512 + (qq >> 1) * 256 + n * 16 +
+                                      (qq & 1) * 8) = r[e];
+        }
+    };
+    // the lane's element offset within a fragment
+    const int wfl = (q >> 1) * 256 + (lane & 15) * 16 + (q & 1) * 8;
+    uint4 wr[PT];
     uint4 st[NU];
     load_brick(st, 0);
-    load_chunk(wb[0], 0, 0);
+    load_chunk(wr, 0, 0);
     store_brick(st);
+    store_chunk(wr, 0);
     __syncthreads();
     const int base = (((wave + 1) * (kRY + 2) + 1) * (kRX + 2) + (lane & 15) + 1) * ROW + q * 8;
     f32x4 acc[MT][NT];
@@ -1208,27 +1218,36 @@ __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __re
     for (int p = 0; p < P; ++p) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c + 1 < NCH) load_chunk(wb[(c + 1) & 1], p, c + 1);
-            else if (p + 1 < P) load_chunk(wb[0], p + 1, 0);
+            const bool more = c + 1 < NCH || p + 1 < P;
+            if (c + 1 < NCH) load_chunk(wr, p, c + 1);
+            else if (p + 1 < P) load_chunk(wr, p + 1, 0);
 #pragma unroll
             for (int s2 = 0; s2 < CH; ++s2) {
                 const int t = c * CH + s2;
                 if (t >= 27) break;
                 const int off = ((t / 9 - 1) * (kRY + 2) + (t / 3) % 3 - 1) * (kRX + 2) + t % 3 - 1;
-                bf16x8 a[MT];
+                bf16x8 a[MT], bv[NT];
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
                     a[m] = as_bf16x8(*reinterpret_cast<const uint4*>(
                         hx + base + off * ROW + m * (kRX + 2) * ROW));
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
+                    bv[j] = as_bf16x8(*reinterpret_cast<const uint4*>(
+                        wl + ((c & 1) * NFR + s2 * NT + j) * 512 + wfl));
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
-                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], wb[c & 1][s2][j],
+                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bv[j],
                                                                             acc[m][j], 0, 0, 0);
             }
+            // the next chunk into the other buffer (last read in the chunk
+            // before this one, which every wave finished before the barrier
+            // that ended it)
+            if (more) store_chunk(wr, (c + 1) & 1);
+            __syncthreads();
         }
-        __syncthreads();   // every wave is done with this pass's brick
         if (p + 1 < P) {
             load_brick(st, p + 1);
             store_brick(st);
@@ -1282,6 +1301,12 @@ __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __re
             }
         }
     }
+}
+
+// LDS of k_conv_fwd_pass<NT, CH>: the brick of one pass, then two weight
+// chunks of CH NT 1 KB fragments.
+constexpr size_t pass_lds_bytes(int nt, int ch) {
+    return ((size_t)kRVox * 40 + 2 * (size_t)nt * ch * 512) * sizeof(uint16_t);
 }
 
 // wt[ci][26 - t][co] = w[co][t][ci]: the weights of the input-gradient conv.
@@ -2218,14 +2243,15 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         // wide input, channel passes (on few bricks in groups of 32 outputs)
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
-        const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
         if (nt == 2 || few)
-            hipLaunchKernelGGL((k_conv_fwd_pass<2, 2, 3>), dim3((unsigned)nbk, nt / 2), dim3(256),
-                               lds_p, s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 2>), dim3((unsigned)nbk, nt / 2), dim3(256),
+                               pass_lds_bytes(2, 2), s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha,
+                               act, y16, y32,
                                accumulate);
         else
-            hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256), lds_p, s,
-                               x, nullptr, w, bias, g, Ci, Ci, Co, alpha, act, y16, y32,
+            hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256),
+                               pass_lds_bytes(4, 2), s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha,
+                               act, y16, y32,
                                accumulate);
         return hipGetLastError();
     }
@@ -2284,14 +2310,15 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
     const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                           ((g.D + kRZ - 1) / kRZ) * g.B;
     if (Co == 32 || Co == 64) {
-        const size_t lds_p = (size_t)kRVox * 40 * sizeof(uint16_t);
         if (Co == 32 || nbk < kFewBricks)   // 64 outputs on few bricks: two groups of 32
-            hipLaunchKernelGGL((k_conv_fwd_pass<2, 2, 3>), dim3((unsigned)nbk, Co / 32), dim3(256),
-                               lds_p, s, skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16,
+            hipLaunchKernelGGL((k_conv_fwd_pass<2, 2>), dim3((unsigned)nbk, Co / 32), dim3(256),
+                               pass_lds_bytes(2, 2), s, skip, low, w, bias, g, Cs + Cu, Cs, Co,
+                               alpha, act, y16,
                                nullptr, 0);
         else
-            hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256), lds_p, s,
-                               skip, low, w, bias, g, Cs + Cu, Cs, Co, alpha, act, y16, nullptr,
+            hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256),
+                               pass_lds_bytes(4, 2), s, skip, low, w, bias, g, Cs + Cu, Cs, Co,
+                               alpha, act, y16, nullptr,
                                0);
         return hipGetLastError();
     }
