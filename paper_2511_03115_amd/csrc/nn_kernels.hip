@@ -391,17 +391,34 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     // so no load sits behind a branch.
     const __amdgpu_buffer_rsrc_t xr = rsrc16(x, g.nvox() * CI);
     const __amdgpu_buffer_rsrc_t wr = rsrc16(w, (long long)NT * 16 * K);
-    bf16x8 wb[2][CH][NT];   // B[k][n] = w[n][k], two chunks of K steps (Co = 16 NT)
-    auto load_chunk = [&](bf16x8 (&dst)[CH][NT], int c) {
+    // The weights go through LDS in chunks of CH K steps, B[k][n] = w[n][k]
+    // (Co = 16 NT), each loaded once per workgroup (a 16-byte unit per
+    // thread) while the previous chunk feeds the matrix cores; two buffers
+    // after the brick, fragments laid out [q / 2][n][q % 2][8] (bank-disjoint
+    // for the 16 lanes one clock serves).
+    constexpr int NFR = CH * NT, PT = NFR * 64 / 256;
+    static_assert(NFR * 64 % 256 == 0, "a chunk is whole 16-byte units per thread");
+    uint16_t* wl = hx + kRVox * ROW;   // [2][NFR][512]
+    auto load_chunk = [&](uint4 (&r)[PT], int c) {
 #pragma unroll
-        for (int s2 = 0; s2 < CH; ++s2)
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int k = (c * CH + s2) * 32 + q * 8;
-                const bool kin = (c * CH + s2 + 1) * 32 <= K || k < K;
-                dst[s2][j] = as_bf16x8(ld16(wr, ((j * 16 + (lane & 15)) * K + k) * 2, kin));
-            }
+        for (int e = 0; e < PT; ++e) {
+            const int i = (int)threadIdx.x + 256 * e;
+            const int f = i >> 6, n = (i >> 2) & 15, qq = i & 3;
+            const int s2 = f / NT, j = f % NT, k = (c * CH + s2) * 32 + qq * 8;
+            r[e] = ld16(wr, ((j * 16 + n) * K + k) * 2, c * CH + s2 < KS && k < K);
+        }
     };
+    auto store_chunk = [&](const uint4 (&r)[PT], int buf) {
+#pragma unroll
+        for (int e = 0; e < PT; ++e) {
+            const int i = (int)threadIdx.x + 256 * e;
+            const int f = i >> 6, n = (i >> 2) & 15, qq = i & 3;
+            *reinterpret_cast<uint4*>(wl + (buf * NFR + f) * 512 + (qq >> 1) * 256 + n * 16 +
+                                      (qq & 1) * 8) = r[e];
+        }
+    };
+    const int wfl = (q >> 1) * 256 + (lane & 15) * 16 + (q & 1) * 8;
+    uint4 wrg[PT];
     // Staging: a thread owns one 16-byte column of the halo rows (voxel hxx
     // of the row, channel group c) and walks the 6 x 6 rows RP at a time, so
     // the x part of its index and bounds test is worked out once.
@@ -451,13 +468,14 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
             st[u] = ld16(xr, (((b * g.D + zz) * g.H + yy) * g.W + xx) * (CI * 2) + c * 2, in);
         }
     }
-    load_chunk(wb[0], 0);
+    load_chunk(wrg, 0);
 #pragma unroll
     for (int u = 0; u < NUR; ++u) {
         const int row = r0 + RP * u;
         if (r0 < RP && (NROW % RP == 0 || u < NUR - 1 || row < NROW))
             *reinterpret_cast<uint4*>(hx + (row * (kRX + 2) + hxx) * ROW + c) = st[u];
     }
+    store_chunk(wrg, 0);
     __syncthreads();
     // wave w owns z-slice w; row tile m is row m (16 voxels along x)
     const int base = (((wave + 1) * (kRY + 2) + 1) * (kRX + 2) + (lane & 15) + 1) * ROW;
@@ -468,7 +486,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
         for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        if (c + 1 < NCH) load_chunk(wb[(c + 1) & 1], c + 1);
+        if (c + 1 < NCH) load_chunk(wrg, c + 1);
 #pragma unroll
         for (int s2 = 0; s2 < CH; ++s2) {
             const int s = c * CH + s2;
@@ -485,12 +503,23 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
                 if (!kin) av = make_uint4(0, 0, 0, 0);
                 a[m] = as_bf16x8(av);
             }
+            bf16x8 bv[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                bv[j] = as_bf16x8(*reinterpret_cast<const uint4*>(
+                    wl + ((c & 1) * NFR + s2 * NT + j) * 512 + wfl));
 #pragma unroll
             for (int j = 0; j < NT; ++j)
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
-                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], wb[c & 1][s2][j],
-                                                                        acc[m][j], 0, 0, 0);
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bv[j], acc[m][j], 0,
+                                                                        0, 0);
+        }
+        // the next chunk into the other buffer, last read in the chunk before
+        // this one (finished by every wave before the barrier that ended it)
+        if (c + 1 < NCH) {
+            store_chunk(wrg, (c + 1) & 1);
+            __syncthreads();
         }
     }
     const int zz = z0 + wave;
@@ -2212,10 +2241,11 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
     if (nv * std::max(Ci, Co) * 2 < (1LL << 31)) {   // few channels, weights in registers
         const long long nbk = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
                               ((g.D + kRZ - 1) / kRZ) * g.B;
-        const size_t lds_r = (size_t)kRVox * (Ci + 8) * sizeof(uint16_t);
+        // the brick, then two weight chunks of CH NT 1 KB fragments
 #define LAUNCH_REG(CI, NT, CH)                                                             \
     hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk, nt / NT), dim3(256), \
-                       lds_r, s, x, w, bias, g, Co, alpha, act, y16, y32, accumulate)
+                       ((size_t)kRVox * (CI + 8) + 2 * NT * CH * 512) * sizeof(uint16_t), s, x, w, \
+                       bias, g, Co, alpha, act, y16, y32, accumulate)
         // 16 outputs: the persistent row-reuse form (48 from 16 inputs: three
         // groups of 16, blockIdx.y)
         if (Co == 16 && Ci == 16)
@@ -2231,8 +2261,8 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         // 32 outputs, 96 as three groups of 32, or 64 as two when the bricks
         // are too few to fill the device
         const bool few = nbk < kFewBricks;
-        if (Ci == 16 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(16, 2, 14);
-        else if (Ci == 32 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(32, 2, 7);
+        if (Ci == 16 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(16, 2, 4);
+        else if (Ci == 32 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(32, 2, 4);
         else done = false;
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
