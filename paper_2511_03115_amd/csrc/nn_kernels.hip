@@ -2262,7 +2262,7 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         // are too few to fill the device
         const bool few = nbk < kFewBricks;
         if (Ci == 16 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(16, 2, 4);
-        else if (Ci == 32 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(32, 2, 4);
+        else if (Ci == 32 && (nt == 2 || nt == 6 || (nt == 4 && few))) LAUNCH_REG(32, 2, 6);
         else done = false;
 #undef LAUNCH_REG
         if (done) return hipGetLastError();
