@@ -840,22 +840,45 @@ k_conv_rows(const uint16_t* __restrict__ x,
         f32x4 acc[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = f32x4{bq[0], bq[1], bq[2], bq[3]};
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
+        auto pair_rows = [&](int p, bf16x8 (&a)[MT + 2]) {
             const int u0 = 2 * p, u1 = 2 * p + 1 < NU ? 2 * p + 1 : 2 * p;
             const int o0 = ((u0 / (3 * NB)) * HY * HX + (u0 / NB) % 3) * ROW + (u0 % NB) * 16;
             const int o1 = ((u1 / (3 * NB)) * HY * HX + (u1 / NB) % 3) * ROW + (u1 % NB) * 16;
             const int o = (q & 2) ? o1 : o0;
-            bf16x8 a[MT + 2];
 #pragma unroll
             for (int i = 0; i < MT + 2; ++i)
                 a[i] = as_bf16x8(*reinterpret_cast<const uint4*>(hx + rbase + o + i * HX * ROW));
+        };
+        if constexpr (CI == 48) {
+            // one wave per SIMD: the next pair's rows are read while the
+            // current pair's MFMAs run (a scheduling barrier keeps the reads
+            // early), so that no other wave is needed to cover their latency
+            bf16x8 a[2][MT + 2];
+            pair_rows(0, a[0]);
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
+            for (int p = 0; p < NP; ++p) {
+                if (p + 1 < NP) pair_rows(p + 1, a[(p + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int m = 0; m < MT; ++m)
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[p][dy], a[m + dy], acc[m],
-                                                                     0, 0, 0);
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            wv[p][dy], a[p & 1][m + dy], acc[m], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                bf16x8 a[MT + 2];
+                pair_rows(p, a);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[p][dy], a[m + dy],
+                                                                         acc[m], 0, 0, 0);
+            }
         }
         // acc[m][i]: output channel 4 q + i of voxel (x0 + lane % 16, y0 + m, z0 + wave)
         float pc[MT][4];   // kOutPool: the stored (bf16) values as floats
