@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import asdict, dataclass, field
-from typing import Callable, List, Optional, Sequence
+from typing import Callable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -54,6 +54,20 @@ def _timed(fn) -> float:
     return time.perf_counter() - t
 
 
+def _timed_gpu(fn, stream) -> Tuple[float, float]:
+    """(wall seconds, GPU seconds between HIP events recorded on ``stream``
+    around fn's launches)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, e0.elapsed_time(e1) * 1e-3
+
+
 @dataclass
 class Rung:
     n_per_spot: int
@@ -62,6 +76,7 @@ class Rung:
     run_s: float
     gamma_plain: float
     denoise_s: Optional[float] = None
+    denoise_gpu_s: Optional[float] = None   # the same call between HIP events on its stream
     gamma_denoised: Optional[float] = None
     judge_s: Optional[float] = None       # the gamma evaluation of the denoised map
 
@@ -160,7 +175,8 @@ def time_to_gamma(spots_for: Callable[[int], list], phantom, seed: int, ladder: 
         rung = Rung(n, plan.n_histories, t_setup, t_run, gamma_pass(ref, dose, vcm))
         plan.close()
         if denoise is not None and not denoised_passed:
-            rung.denoise_s = _timed(lambda: denoise(dose, phantom.density, den))
+            rung.denoise_s, rung.denoise_gpu_s = _timed_gpu(
+                lambda: denoise(dose, phantom.density, den), sde.library_stream())
             g = []
             rung.judge_s = _timed(lambda: g.append(gamma_pass(ref, den, vcm)))
             rung.gamma_denoised = g[0]

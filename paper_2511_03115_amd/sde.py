@@ -197,8 +197,12 @@ def init_materials(materials: Sequence, params, nuclear=None) -> None:
                                   C.byref(nt) if nt is not None else None))
 
 
+_STREAM = None   # what set_stream was given
+
+
 def set_stream(stream=None) -> None:
     """Use a torch.cuda.Stream (or its raw handle); None = the null stream."""
+    global _STREAM
     if stream is None:
         h = None
     elif isinstance(stream, int):
@@ -206,6 +210,17 @@ def set_stream(stream=None) -> None:
     else:
         h = stream.cuda_stream
     _check(lib.sde_set_stream(C.c_void_p(h)))
+    _STREAM = stream
+
+
+def library_stream():
+    """The torch stream the library's work runs on (for events around it)."""
+    import torch
+    if _STREAM is None:
+        return torch.cuda.default_stream()
+    if isinstance(_STREAM, int):
+        return torch.cuda.ExternalStream(_STREAM)
+    return _STREAM
 
 
 def beam_struct(spots) -> tuple:
