@@ -76,9 +76,9 @@ class Rung:
     run_s: float
     gamma_plain: float
     denoise_s: Optional[float] = None
-    denoise_gpu_s: Optional[float] = None   # the same call between HIP events on its stream
     gamma_denoised: Optional[float] = None
     judge_s: Optional[float] = None       # the gamma evaluation of the denoised map
+    denoise_gpu_s: Optional[float] = None   # the denoise between HIP events on its stream
 
 
 @dataclass
