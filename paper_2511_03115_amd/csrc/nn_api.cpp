@@ -269,7 +269,9 @@ int run_backward(sde_nn* n, const int* d0) {
         dims_at(d0, l + 1, dc);
         Level& v = n->lv[l];
         const int Cf = n->c[l] + n->c[l + 1];
-        const uint16_t* dzb = l == 0 && head_dz ? n->dz : nullptr;   // from the head
+        // the output gradient of dec_b[l], through its LeakyReLU, already in
+        // n->dz: from the head (level 0) or from the up_bwd of level l - 1
+        const uint16_t* dzb = l == 0 ? (head_dz ? n->dz : nullptr) : n->dz;
         // the level-0 decoder conv's input gradient goes straight into the
         // skip's gradient and the upsampled half (kept in gCat's memory)
         const bool split = n->dec_a[l].ci == 48 && n->dec_a[l].co == 16 && n->c[l] == 16;
@@ -294,34 +296,44 @@ int run_backward(sde_nn* n, const int* d0) {
                                  nullptr, dx_hi, n->c[l], xlow))
                 return r;
         }
+        // the level below's output gradient: its only term, so it goes
+        // through that layer's LeakyReLU here, into n->dz for its conv_bwd
         float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
+        const uint16_t* ytgt = (l + 1 <= L - 2) ? n->lv[l + 1].db : n->lv[L - 1].eb;
+        const float al = n->cfg.leaky_alpha;
         if (split) {
-            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], n->c[l + 1], 0, tgt, s));
+            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], n->c[l + 1], 0, tgt, s, ytgt, al, n->dz));
         } else {
             NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
-            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s));
+            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s, ytgt, al, n->dz));
         }
     }
     for (int l = L - 1; l >= 0; --l) {
         dims_at(d0, l, d);
         Level& v = n->lv[l];
         const uint16_t* in = l == 0 ? n->x16 : v.pin;
+        // enc_b[l]'s output gradient, through its LeakyReLU, in n->dz: from
+        // the decoder's last up_bwd (bottom level) or this level's pool_bwd
+        // (which adds the pooled term to the skip term); a network of one
+        // level has neither
+        const uint16_t* dze = L > 1 ? n->dz : nullptr;
         if (dz_chain(n->enc_b[l])) {
-            if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, nullptr, nullptr, v.ea,
+            if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, nullptr, dze, v.ea,
                                  n->dz2))
                 return r;
             if (int r = conv_bwd(n, nullptr, nullptr, in, n->enc_a[l], d, l > 0 ? v.gP : nullptr,
                                  n->dz2))
                 return r;
         } else {
-            if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, v.gEa)) return r;
+            if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, v.gEa, dze)) return r;
             if (int r = conv_bwd(n, v.gEa, v.ea, in, n->enc_a[l], d, l > 0 ? v.gP : nullptr))
                 return r;
         }
         if (l > 0) {
             int df[4];
             dims_at(d0, l - 1, df);
-            NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gE, s));
+            NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gE, s, n->lv[l - 1].eb,
+                            n->cfg.leaky_alpha, n->dz));
         }
     }
     return SDE_OK;

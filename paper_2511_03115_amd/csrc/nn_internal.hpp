@@ -85,11 +85,16 @@ hipError_t wgrad_cat(const uint16_t* dz, const uint16_t* skip, const uint16_t* l
 hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long n, uint16_t* dz,
                      hipStream_t s);
 hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, hipStream_t s);
-hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s);
+// pool_bwd / up_bwd: with dz non-null the FP32 result is not stored; it goes
+// through the LeakyReLU derivative of y (the activation it is the gradient
+// of, same layout) into dz (bf16), as lrelu_bwd would turn it.
+hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s,
+                    const uint16_t* y = nullptr, float alpha = 0.0f, uint16_t* dz = nullptr);
 hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0, uint16_t* y,
                   hipStream_t s);
 hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
-                  hipStream_t s);
+                  hipStream_t s, const uint16_t* y = nullptr, float alpha = 0.0f,
+                  uint16_t* dz = nullptr);
 hipError_t copy_channels(const uint16_t* x, const int* dims, int C, int Cf, int c0, uint16_t* y,
                          hipStream_t s);
 hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, float* dx,

@@ -1881,18 +1881,38 @@ __global__ void k_pool_fwd(const uint16_t* x, Geo go, int C, uint16_t* y) {
     *reinterpret_cast<uint4*>(y + o.v * C + o.grp * 8) = f32_to_bf16x8(s);
 }
 
-// Pooling backward: dx (FP32, fine grid gi) += dy(parent) / 8, 4 channels per thread.
-__global__ void k_pool_bwd(const float* dy, Geo gi, int C, float* dx) {
+// The LeakyReLU input gradient of 4 channels, as k_lrelu_bwd computes it:
+// bf16(y > 0 ? r : alpha r), stored at dz + i (8 bytes).
+__device__ __forceinline__ void lrelu_dz4(float4 r, const uint16_t* y, float alpha, uint16_t* dz,
+                                          long long i) {
+    const uint2 yy = *reinterpret_cast<const uint2*>(y + i);
+    const float y0 = __uint_as_float(yy.x << 16), y1 = __uint_as_float(yy.x & 0xFFFF0000u),
+                y2 = __uint_as_float(yy.y << 16), y3 = __uint_as_float(yy.y & 0xFFFF0000u);
+    uint2 o;
+    o.x = (uint32_t)f2bf(y0 > 0.0f ? r.x : alpha * r.x) |
+          ((uint32_t)f2bf(y1 > 0.0f ? r.y : alpha * r.y) << 16);
+    o.y = (uint32_t)f2bf(y2 > 0.0f ? r.z : alpha * r.z) |
+          ((uint32_t)f2bf(y3 > 0.0f ? r.w : alpha * r.w) << 16);
+    *reinterpret_cast<uint2*>(dz + i) = o;
+}
+
+// Pooling backward: dx (FP32, fine grid gi) += dy(parent) / 8, 4 channels per
+// thread; with dz non-null the sum goes instead, through the LeakyReLU
+// derivative of y (the fine level's activation), to dz (bf16).
+__global__ void k_pool_bwd(const float* dy, Geo gi, int C, float* dx, const uint16_t* y,
+                           float alpha, uint16_t* dz) {
     VoxG f;
     if (!vox_of(gi, C / 4, f)) return;
     const float4 p = *reinterpret_cast<const float4*>(dy + parent(gi, f) * C + f.grp * 4);
-    float4* q = reinterpret_cast<float4*>(dx + f.v * C + f.grp * 4);
+    const long long i = f.v * C + f.grp * 4;
+    float4* q = reinterpret_cast<float4*>(dx + i);
     float4 r = *q;
     r.x += 0.125f * p.x;
     r.y += 0.125f * p.y;
     r.z += 0.125f * p.z;
     r.w += 0.125f * p.w;
-    *q = r;
+    if (dz) lrelu_dz4(r, y, alpha, dz, i);
+    else *q = r;
 }
 
 // Nearest x2 upsampling of a coarse tensor into channels [c0, c0+C) of a fine
@@ -1906,8 +1926,11 @@ __global__ void k_up_fwd(const uint16_t* x, Geo gf, int C, int Cf, int c0, uint1
 }
 
 // Upsampling backward: dx(coarse) = sum over the 8 children of dy[.][c0 + c];
-// grid over the coarse volume gc, 4 channels per thread.
-__global__ void k_up_bwd(const float* dy, Geo gc, int C, int Cf, int c0, float* dx) {
+// grid over the coarse volume gc, 4 channels per thread; with dz non-null
+// the sum goes instead, through the LeakyReLU derivative of y (the coarse
+// level's activation), to dz (bf16).
+__global__ void k_up_bwd(const float* dy, Geo gc, int C, int Cf, int c0, float* dx,
+                         const uint16_t* y, float alpha, uint16_t* dz) {
     VoxG o;
     if (!vox_of(gc, C / 4, o)) return;
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1918,7 +1941,8 @@ __global__ void k_up_bwd(const float* dy, Geo gc, int C, int Cf, int c0, float* 
         s.z += p.z;
         s.w += p.w;
     }
-    *reinterpret_cast<float4*>(dx + o.v * C + o.grp * 4) = s;
+    if (dz) lrelu_dz4(s, y, alpha, dz, o.v * C + o.grp * 4);
+    else *reinterpret_cast<float4*>(dx + o.v * C + o.grp * 4) = s;
 }
 
 // Copy channels [0, C) of x into channels [c0, c0+C) of y (Cf channels): the
@@ -2592,10 +2616,12 @@ hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, 
     return hipGetLastError();
 }
 
-hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s) {
+hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s,
+                    const uint16_t* y, float alpha, uint16_t* dz) {
     Geo g{dims_in[0], dims_in[1], dims_in[2], dims_in[3]};
-    if (C % 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pool_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, dx);
+    if (C % 4 || (dz && !y)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pool_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, dx, y, alpha,
+                       dz);
     return hipGetLastError();
 }
 
@@ -2608,10 +2634,11 @@ hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0
 }
 
 hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
-                  hipStream_t s) {
+                  hipStream_t s, const uint16_t* y, float alpha, uint16_t* dz) {
     Geo g{dims_coarse[0], dims_coarse[1], dims_coarse[2], dims_coarse[3]};
-    if (C % 4 || Cf % 4 || c0 % 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_up_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, Cf, c0, dx);
+    if (C % 4 || Cf % 4 || c0 % 4 || (dz && !y)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_up_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, Cf, c0, dx, y,
+                       alpha, dz);
     return hipGetLastError();
 }
 
