@@ -203,13 +203,16 @@ int run_forward(sde_nn* n, const int* d0) {
 // gradient goes (FP32) into dx when non-null, or, through the LeakyReLU
 // derivative of the input activation y_in, (bf16) into dz_next when that is
 // non-null (16 -> 16 convs).  The flipped weights are in n->wt_all (offset cp.w).
-// With dx_hi non-null the input gradient is split at channel cs: [0, cs)
-// into dx, [cs, ci) into dx_hi (conv_fwd_split).  With x_low non-null the
-// input is the concatenation [x (cs channels), up(x_low)] read in place.
+// With dz_up non-null the input gradient is split at channel cs: [0, cs)
+// into dx, and [cs, ci), the upsampled half, through the upsampling backward
+// and the LeakyReLU of the level below (activation y_up) into dz_up, bf16
+// at half size (conv_fwd_split).  With x_low non-null the input is the
+// concatenation [x (cs channels), up(x_low)] read in place.
 int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, const ConvP& cp,
              const int* d, float* dx, const uint16_t* dz_ready = nullptr,
-             const uint16_t* y_in = nullptr, uint16_t* dz_next = nullptr, float* dx_hi = nullptr,
-             int cs = 0, const uint16_t* x_low = nullptr) {
+             const uint16_t* y_in = nullptr, uint16_t* dz_next = nullptr, int cs = 0,
+             const uint16_t* x_low = nullptr, const uint16_t* y_up = nullptr,
+             uint16_t* dz_up = nullptr) {
     hipStream_t s = library_stream();
     const uint16_t* dz = dz_ready;
     if (!dz) {
@@ -224,8 +227,9 @@ int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, c
         NN_TRY(wgrad(dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
     if (dz_next)
         NN_TRY(conv_dz_fwd(dz, n->wt_all + cp.w, d, y_in, n->cfg.leaky_alpha, dz_next, s));
-    else if (dx_hi)
-        NN_TRY(conv_fwd_split(dz, n->wt_all + cp.w, d, cp.co, cp.ci, cs, dx, dx_hi, s));
+    else if (dz_up)
+        NN_TRY(conv_fwd_split(dz, n->wt_all + cp.w, d, cp.co, cp.ci, cs, dx, y_up,
+                              n->cfg.leaky_alpha, dz_up, s));
     else if (dx)
         NN_TRY(conv_fwd(dz, n->wt_all + cp.w, nullptr, d, cp.co, cp.ci, 0.0f, 0, nullptr, dx, 0, s));
     return SDE_OK;
@@ -234,6 +238,14 @@ int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, c
 // A 16 -> 16 conv whose input gradient feeds only the LeakyReLU before it
 // hands that layer its bf16 gradient directly.
 bool dz_chain(const ConvP& cp) { return cp.ci == 16 && cp.co == 16; }
+
+// The decoder conv at level l whose input gradient conv_fwd_split takes:
+// its skip half in FP32, its upsampled half straight to the level below as
+// bf16 LeakyReLU gradient (no FP32 concatenation gradient at that level).
+bool split_up(const sde_nn* n, int l) {
+    return dz_chain(n->dec_b[l]) && n->dec_a[l].ci == 48 && n->dec_a[l].co == 16 &&
+           n->c[l] == 16;
+}
 
 int run_backward(sde_nn* n, const int* d0) {
     hipStream_t s = library_stream();
@@ -272,11 +284,15 @@ int run_backward(sde_nn* n, const int* d0) {
         // the output gradient of dec_b[l], through its LeakyReLU, already in
         // n->dz: from the head (level 0) or from the up_bwd of level l - 1
         const uint16_t* dzb = l == 0 ? (head_dz ? n->dz : nullptr) : n->dz;
+        // the level below's output gradient: its only term, so it goes
+        // through that layer's LeakyReLU, into n->dz for its conv_bwd
+        float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
+        const uint16_t* ytgt = (l + 1 <= L - 2) ? n->lv[l + 1].db : n->lv[L - 1].eb;
+        const float al = n->cfg.leaky_alpha;
         // the level-0 decoder conv's input gradient goes straight into the
-        // skip's gradient and the upsampled half (kept in gCat's memory)
-        const bool split = n->dec_a[l].ci == 48 && n->dec_a[l].co == 16 && n->c[l] == 16;
-        float* dx = split ? v.gE : v.gCat;
-        float* dx_hi = split ? v.gCat : nullptr;
+        // skip's gradient, and its upsampled half through the upsampling
+        // backward and that LeakyReLU into n->dz (its input is n->dz2)
+        const bool split = split_up(n, l);
         // the decoder conv's input: the stored concatenation, or the skip and
         // the level below read in place
         const bool inplace = cat_in_place(n, l, d);
@@ -287,23 +303,17 @@ int run_backward(sde_nn* n, const int* d0) {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da,
                                  n->dz2))
                 return r;
-            if (int r = conv_bwd(n, nullptr, nullptr, xin, n->dec_a[l], d, dx, n->dz2, nullptr,
-                                 nullptr, dx_hi, n->c[l], xlow))
+            if (int r = conv_bwd(n, nullptr, nullptr, xin, n->dec_a[l], d, split ? v.gE : v.gCat,
+                                 n->dz2, nullptr, nullptr, n->c[l], xlow, split ? ytgt : nullptr,
+                                 split ? n->dz : nullptr))
                 return r;
         } else {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, v.gDa, dzb)) return r;
-            if (int r = conv_bwd(n, v.gDa, v.da, xin, n->dec_a[l], d, dx, nullptr, nullptr,
-                                 nullptr, dx_hi, n->c[l], xlow))
+            if (int r = conv_bwd(n, v.gDa, v.da, xin, n->dec_a[l], d, v.gCat, nullptr, nullptr,
+                                 nullptr, n->c[l], xlow))
                 return r;
         }
-        // the level below's output gradient: its only term, so it goes
-        // through that layer's LeakyReLU here, into n->dz for its conv_bwd
-        float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
-        const uint16_t* ytgt = (l + 1 <= L - 2) ? n->lv[l + 1].db : n->lv[L - 1].eb;
-        const float al = n->cfg.leaky_alpha;
-        if (split) {
-            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], n->c[l + 1], 0, tgt, s, ytgt, al, n->dz));
-        } else {
+        if (!split) {
             NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
             NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s, ytgt, al, n->dz));
         }
@@ -370,7 +380,7 @@ int alloc_all(sde_nn* n) {
         NN_TRY(dalloc(n, &v.gEa, nv * n->c[l]));
         if (l > 0) NN_TRY(dalloc(n, &v.gP, nv * n->c[l - 1]));
         if (l <= L - 2) {
-            NN_TRY(dalloc(n, &v.gCat, nv * (n->c[l] + n->c[l + 1])));
+            if (!split_up(n, l)) NN_TRY(dalloc(n, &v.gCat, nv * (n->c[l] + n->c[l + 1])));
             NN_TRY(dalloc(n, &v.gDa, nv * n->c[l]));
             NN_TRY(dalloc(n, &v.gDb, nv * n->c[l]));
         }

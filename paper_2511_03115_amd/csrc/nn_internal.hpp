@@ -37,11 +37,16 @@ hipError_t conv_head_fwd(const uint16_t* x, const uint16_t* w, const float* bias
 // input's two used channels as bf16 pairs x2 (weights [16][27][cin]).
 hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const float* bias,
                        const int* dims, float alpha, uint16_t* y16, hipStream_t s);
-// conv_fwd into FP32 without bias or activation, its output channels split:
-// [0, cs) into ya (cs per voxel), [cs, Co) into yb (Co - cs per voxel).
-// Ci = 16, Co = 48, cs = 16 (the input gradient of the level-0 decoder conv).
+// The input gradient of the level-0 decoder conv (Ci = 16, Co = 48, cs = 16):
+// conv_fwd without bias or activation, its output channels split.  [0, cs)
+// go in FP32 into ya (cs per voxel); [cs, Co), the upsampled half, go
+// through the upsampling backward and the LeakyReLU of the level below:
+// dzc (bf16, half size, Co - cs per voxel) gets what up_bwd with target
+// activation ym (half size, Co - cs per voxel) and alpha gives.  D, H, W
+// even; dzc must not be x.
 hipError_t conv_fwd_split(const uint16_t* x, const uint16_t* w, const int* dims, int Ci, int Co,
-                          int cs, float* ya, float* yb, hipStream_t s);
+                          int cs, float* ya, const uint16_t* ym, float alpha, uint16_t* dzc,
+                          hipStream_t s);
 // conv_fwd 16 -> 16 (LeakyReLU, bf16 y16) with pool_fwd of its output fused
 // in: pool (bf16, half size; D, H, W even) gets the values pool_fwd gives.
 hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,

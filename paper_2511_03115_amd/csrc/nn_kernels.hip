@@ -608,14 +608,22 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 // bf16(ym[v][c] > 0 ? r : alpha r) with r the FP32 conv output (no bias),
 // what conv_fwd into FP32 followed by lrelu_bwd gives.  Or bf16 y16 and its
 // 2 x 2 x 2 average pool (kOutPool, into pool at half size, as pool_fwd).
-enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2, kOutDz = 3, kOutPool = 4 };
+// Or the backward of a nearest x2 upsampling followed by a LeakyReLU
+// input gradient (kOutUpDz): the FP32 conv outputs (no bias) of each
+// 2 x 2 x 2 block summed, then dz[p][c] = bf16(ym[p][c] > 0 ? s : alpha s)
+// at the half-size parent p (ym and dz with ys channels), with nothing
+// stored at full size: what an FP32 conv output followed by up_bwd with a
+// LeakyReLU target gives, up to the order of the 8-term sum.
+enum { kOutBf16 = 0, kOutF32 = 1, kOutHead = 2, kOutDz = 3, kOutPool = 4, kOutUpDz = 5 };
 struct HeadArgs {
     const float* w;       // [16]
     const float* b;       // [1]
     const float* resid;   // per voxel
     float* out;           // per voxel
-    const uint16_t* ym;   // kOutDz: the layer's output activation, [voxel][16]
-    uint16_t* pool;       // kOutPool: [voxel at half size][16]
+    const uint16_t* ym;   // kOutDz: the layer's output activation, [voxel][16];
+                          // kOutUpDz: the half-size activation, [parent][ys]
+    uint16_t* pool;       // kOutPool: [voxel at half size][16]; kOutUpDz: dz,
+                          // [parent][ys]
 };
 
 template <int CI, int CS, int OUT>
@@ -793,11 +801,17 @@ k_conv_rows(const uint16_t* __restrict__ x,
                                                 (int)(g.nvox() * 4), 0x00020000);
         or_ = __builtin_amdgcn_make_buffer_rsrc(head.out, 0, (int)(g.nvox() * 4), 0x00020000);
     }
-    // kOutPool: the pool partial sums of waves 1 and 3, handed to waves 0 and 2
-    __shared__ float pex[OUT == kOutPool ? 2 : 1][64][8];
+    // kOutPool, kOutUpDz: the block partial sums of waves 1 and 3, handed to
+    // waves 0 and 2
+    constexpr bool BLK = OUT == kOutPool || OUT == kOutUpDz;
+    __shared__ float pex[BLK ? 2 : 1][64][8];
     const Geo gp{g.B, g.D >> 1, g.H >> 1, g.W >> 1};
     const __amdgpu_buffer_rsrc_t pr =
-        rsrc16(head.pool, OUT == kOutPool && head.pool ? gp.nvox() * 16 : 0);
+        rsrc16(head.pool, OUT == kOutPool && head.pool   ? gp.nvox() * 16
+                          : OUT == kOutUpDz && head.pool ? gp.nvox() * ys
+                                                         : 0);
+    const __amdgpu_buffer_rsrc_t ur =
+        rsrc16(head.ym, OUT == kOutUpDz && head.ym ? gp.nvox() * ys : 0);
     uint4 st[NC][HZ];
     int brick = s0 + gi;
     Bk cur = split(brick < s1 ? brick : 0);
@@ -824,6 +838,21 @@ k_conv_rows(const uint16_t* __restrict__ x,
         const int v0 = ((cur.b * g.D + zz) * g.H + y0) * g.W + xx;
         float res[MT];   // the head's residual input, loaded during the MFMAs
         u32x2 ymk[MT];   // kOutDz: the activation's 4 channels, loaded during the MFMAs
+        // kOutUpDz: the parents this lane stores (even lanes of waves 0 and
+        // 2, two y rows), their offsets and activations, loaded likewise
+        int upo[2];
+        u32x2 ymp[2];
+        if constexpr (OUT == kOutUpDz) {
+            const int px = xx >> 1, pz = zz >> 1;
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp) {
+                const int py = (y0 >> 1) + mp;
+                const bool pok = !(wave & 1) && !(lane & 1) && px < gp.W && py < gp.H && pz < gp.D;
+                upo[mp] = pok ? ((((cur.b * gp.D + pz) * gp.H + py) * gp.W + px) * ys + cg + q * 4) * 2
+                              : kOob;
+                ymp[mp] = __builtin_amdgcn_raw_buffer_load_b64(ur, upo[mp], 0, 0);
+            }
+        }
         if constexpr (OUT == kOutHead) {
 #pragma unroll
             for (int m = 0; m < MT; ++m)
@@ -898,7 +927,10 @@ k_conv_rows(const uint16_t* __restrict__ x,
 #pragma unroll
                 for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : slope * acc[m][i];
             }
-            if constexpr (!F32) {
+            if constexpr (OUT == kOutUpDz) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pc[m][i] = r[i];
+            } else if constexpr (!F32) {
                 // a store past the end of the resource is dropped: no branch
                 const uint32_t lo16 = pk_bf16(r[0], r[1]), hi16 = pk_bf16(r[2], r[3]);
                 __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo16, hi16}, yr,
@@ -974,6 +1006,43 @@ k_conv_rows(const uint16_t* __restrict__ x,
                     __builtin_amdgcn_raw_buffer_store_b64(
                         u32x2{pk_bf16(sv[0], sv[1]), pk_bf16(sv[2], sv[3])}, pr,
                         pok ? (pv * 16 + q * 4) * 2 : kOob, 0, 0);
+                }
+            }
+        }
+        if constexpr (OUT == kOutUpDz) {
+            // the block sums as for kOutPool (x pairs, y pairs, then z pairs
+            // through LDS), unscaled, through the parent's LeakyReLU
+            float t[2][4];
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float a0 = pc[2 * mp][i], a2 = pc[2 * mp + 1][i];
+                    const float a1 = __shfl_xor(a0, 1), a3 = __shfl_xor(a2, 1);
+                    t[mp][i] = (a0 + a1) + (a2 + a3);
+                }
+            if (wave & 1) {
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) pex[wave >> 1][lane][mp * 4 + i] = t[mp][i];
+            }
+            __syncthreads();
+            if (!(wave & 1)) {
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp) {
+                    const float yv[4] = {__uint_as_float(ymp[mp].x << 16),
+                                         __uint_as_float(ymp[mp].x & 0xFFFF0000u),
+                                         __uint_as_float(ymp[mp].y << 16),
+                                         __uint_as_float(ymp[mp].y & 0xFFFF0000u)};
+                    float dv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float sv = t[mp][i] + pex[wave >> 1][lane][mp * 4 + i];
+                        dv[i] = yv[i] > 0.0f ? sv : alpha * sv;
+                    }
+                    __builtin_amdgcn_raw_buffer_store_b64(
+                        u32x2{pk_bf16(dv[0], dv[1]), pk_bf16(dv[2], dv[3])}, pr, upo[mp], 0, 0);
                 }
             }
         }
@@ -2403,13 +2472,20 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
 }
 
 hipError_t conv_fwd_split(const uint16_t* x, const uint16_t* w, const int* dims, int Ci, int Co,
-                          int cs, float* ya, float* yb, hipStream_t s) {
+                          int cs, float* ya, const uint16_t* ym, float alpha, uint16_t* dzc,
+                          hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
-    if (Ci != 16 || Co != 48 || cs != 16 || !ya || !yb) return hipErrorInvalidValue;
+    const Geo gc{g.B, g.D >> 1, g.H >> 1, g.W >> 1};
+    if (Ci != 16 || Co != 48 || cs != 16 || !ya || !ym || !dzc || ((g.D | g.H | g.W) & 1) ||
+        gc.nvox() * 32 * 2 >= (1LL << 31) || dzc == x)
+        return hipErrorInvalidValue;
     hipError_t e = launch_rows<16, 16>(x, nullptr, w, nullptr, g, 0.0f, 0, nullptr, ya, 0, s, 1);
     if (e != hipSuccess) return e;
-    return launch_rows<16, 16>(x, nullptr, w + 16LL * 27 * 16, nullptr, g, 0.0f, 0, nullptr, yb, 0,
-                               s, 2);
+    HeadArgs a{};
+    a.ym = ym;
+    a.pool = dzc;
+    return launch_rows_as<16, 16, kOutUpDz>(x, nullptr, w + 16LL * 27 * 16, nullptr, g, alpha, 0,
+                                            nullptr, nullptr, 0, s, a, 2);
 }
 
 hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
