@@ -49,6 +49,9 @@ struct Level {
              *db = nullptr;
     float *gE = nullptr, *gEa = nullptr, *gP = nullptr, *gCat = nullptr, *gDa = nullptr,
           *gDb = nullptr;
+    // a split level's decoder conv input gradient (bf16), kept until the
+    // encoder's pool_bwd into this level takes its skip half
+    uint16_t* dzk = nullptr;
 };
 
 }  // namespace
@@ -289,10 +292,12 @@ int run_backward(sde_nn* n, const int* d0) {
         float* tgt = (l + 1 <= L - 2) ? n->lv[l + 1].gDb : n->lv[L - 1].gE;
         const uint16_t* ytgt = (l + 1 <= L - 2) ? n->lv[l + 1].db : n->lv[L - 1].eb;
         const float al = n->cfg.leaky_alpha;
-        // the level-0 decoder conv's input gradient goes straight into the
-        // skip's gradient, and its upsampled half through the upsampling
-        // backward and that LeakyReLU into n->dz (its input is n->dz2)
+        // the level-0 decoder conv's input gradient: its upsampled half
+        // goes through the upsampling backward and that LeakyReLU into n->dz;
+        // its input, the conv's output gradient, is kept in v.dzk, and the
+        // skip half is taken from it when the encoder reaches this level
         const bool split = split_up(n, l);
+        uint16_t* dzd = split ? v.dzk : n->dz2;
         // the decoder conv's input: the stored concatenation, or the skip and
         // the level below read in place
         const bool inplace = cat_in_place(n, l, d);
@@ -300,11 +305,10 @@ int run_backward(sde_nn* n, const int* d0) {
         const uint16_t* xin = inplace ? v.eb : v.cat;
         const uint16_t* xlow = inplace ? low : nullptr;
         if (dz_chain(n->dec_b[l])) {
-            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da,
-                                 n->dz2))
+            if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da, dzd))
                 return r;
-            if (int r = conv_bwd(n, nullptr, nullptr, xin, n->dec_a[l], d, split ? v.gE : v.gCat,
-                                 n->dz2, nullptr, nullptr, n->c[l], xlow, split ? ytgt : nullptr,
+            if (int r = conv_bwd(n, nullptr, nullptr, xin, n->dec_a[l], d, split ? nullptr : v.gCat,
+                                 dzd, nullptr, nullptr, n->c[l], xlow, split ? ytgt : nullptr,
                                  split ? n->dz : nullptr))
                 return r;
         } else {
@@ -342,8 +346,15 @@ int run_backward(sde_nn* n, const int* d0) {
         if (l > 0) {
             int df[4];
             dims_at(d0, l - 1, df);
-            NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gE, s, n->lv[l - 1].eb,
-                            n->cfg.leaky_alpha, n->dz));
+            if (split_up(n, l - 1)) {
+                // the skip half of the level's decoder conv input gradient
+                // and the pooled term, through enc_b[l - 1]'s LeakyReLU
+                NN_TRY(conv_dz_fwd(n->lv[l - 1].dzk, n->wt_all + n->dec_a[l - 1].w, df,
+                                   n->lv[l - 1].eb, n->cfg.leaky_alpha, n->dz, s, v.gP));
+            } else {
+                NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gE, s, n->lv[l - 1].eb,
+                                n->cfg.leaky_alpha, n->dz));
+            }
         }
     }
     return SDE_OK;
@@ -376,7 +387,8 @@ int alloc_all(sde_nn* n) {
             NN_TRY(dalloc(n, &v.db, nv * n->c[l]));
         }
         if (!c.train) continue;
-        NN_TRY(dalloc(n, &v.gE, nv * n->c[l]));
+        if (l <= L - 2 && split_up(n, l)) NN_TRY(dalloc(n, &v.dzk, nv * n->c[l]));
+        else NN_TRY(dalloc(n, &v.gE, nv * n->c[l]));
         NN_TRY(dalloc(n, &v.gEa, nv * n->c[l]));
         if (l > 0) NN_TRY(dalloc(n, &v.gP, nv * n->c[l - 1]));
         if (l <= L - 2) {

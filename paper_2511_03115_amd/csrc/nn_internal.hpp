@@ -39,7 +39,8 @@ hipError_t conv_in_fwd(const uint32_t* x2, const uint16_t* w, int cin, const flo
                        const int* dims, float alpha, uint16_t* y16, hipStream_t s);
 // The input gradient of the level-0 decoder conv (Ci = 16, Co = 48, cs = 16):
 // conv_fwd without bias or activation, its output channels split.  [0, cs)
-// go in FP32 into ya (cs per voxel); [cs, Co), the upsampled half, go
+// go in FP32 into ya (cs per voxel) when ya is non-null (else the caller
+// takes them later with conv_dz_fwd); [cs, Co), the upsampled half, go
 // through the upsampling backward and the LeakyReLU of the level below:
 // dzc (bf16, half size, Co - cs per voxel) gets what up_bwd with target
 // activation ym (half size, Co - cs per voxel) and alpha gives.  D, H, W
@@ -53,9 +54,12 @@ hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias
                          float alpha, uint16_t* y16, uint16_t* pool, hipStream_t s);
 // The input gradient of a LeakyReLU layer through the next conv (16 -> 16):
 // dz = bf16(ym > 0 ? r : alpha r), r = conv(x, w) in FP32 (no bias); the same
-// values as conv_fwd into FP32 followed by lrelu_bwd.
+// values as conv_fwd into FP32 followed by lrelu_bwd.  With par non-null (the
+// gradient of the pooled layer, FP32, half size, 16 channels; D, H, W even)
+// r = conv(x, w) + par[parent] / 8: conv_fwd into FP32 followed by pool_bwd
+// with a LeakyReLU target.  dz must not be x.
 hipError_t conv_dz_fwd(const uint16_t* x, const uint16_t* w, const int* dims, const uint16_t* ym,
-                       float alpha, uint16_t* dz, hipStream_t s);
+                       float alpha, uint16_t* dz, hipStream_t s, const float* par = nullptr);
 // flip_transpose of several layers in one launch
 constexpr int kMaxFlipJobs = 32;
 struct FlipJobs {

@@ -606,7 +606,9 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 // order, the quarters are added pairwise, (0 + 1) + (2 + 3)).
 // Or the input gradient of a LeakyReLU layer (kOutDz): dz[v][c] =
 // bf16(ym[v][c] > 0 ? r : alpha r) with r the FP32 conv output (no bias),
-// what conv_fwd into FP32 followed by lrelu_bwd gives.  Or bf16 y16 and its
+// what conv_fwd into FP32 followed by lrelu_bwd gives; with par non-null
+// r = conv + par[p(v)][c] / 8 (p(v) the half-size parent), what pool_bwd
+// with a LeakyReLU target adds and gives.  Or bf16 y16 and its
 // 2 x 2 x 2 average pool (kOutPool, into pool at half size, as pool_fwd).
 // Or the backward of a nearest x2 upsampling followed by a LeakyReLU
 // input gradient (kOutUpDz): the FP32 conv outputs (no bias) of each
@@ -624,6 +626,7 @@ struct HeadArgs {
                           // kOutUpDz: the half-size activation, [parent][ys]
     uint16_t* pool;       // kOutPool: [voxel at half size][16]; kOutUpDz: dz,
                           // [parent][ys]
+    const float* par;     // kOutDz: the pooled layer's gradient, [parent][16], or null
 };
 
 template <int CI, int CS, int OUT>
@@ -790,9 +793,14 @@ k_conv_rows(const uint16_t* __restrict__ x,
     const __amdgpu_buffer_rsrc_t yr = rsrc16(y16, y16 ? g.nvox() * ys - cg : 0);
     float hw[4] = {0.f, 0.f, 0.f, 0.f}, hb = 0.0f;
     __amdgpu_buffer_rsrc_t rr_, or_;
-    if constexpr (OUT == kOutDz)
+    __amdgpu_buffer_rsrc_t pa_;
+    if constexpr (OUT == kOutDz) {
         rr_ = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(head.ym), 0,
                                                 (int)(g.nvox() * 32), 0x00020000);
+        pa_ = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(head.par), 0,
+                                                head.par ? (int)(g.nvox() / 8 * 64) : 0,
+                                                0x00020000);
+    }
     if constexpr (OUT == kOutHead) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) hw[i] = head.w[q * 4 + i];
@@ -859,11 +867,26 @@ k_conv_rows(const uint16_t* __restrict__ x,
                 res[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
                     rr_, xzin && y0 + m < g.H ? (v0 + m * g.W) * 4 : kOob, 0, 0));
         }
+        f32x4 pp[MT / 2];   // kOutDz with par: the parents' 4 channels (rows m, m + 1 share one)
         if constexpr (OUT == kOutDz) {
 #pragma unroll
             for (int m = 0; m < MT; ++m)
                 ymk[m] = __builtin_amdgcn_raw_buffer_load_b64(
                     rr_, xzin && y0 + m < g.H ? ((v0 + m * g.W) * 16 + q * 4) * 2 : kOob, 0, 0);
+            if (head.par) {
+#pragma unroll
+                for (int mp = 0; mp < MT / 2; ++mp) {
+                    const int pv = ((cur.b * gp.D + (zz >> 1)) * gp.H + (y0 >> 1) + mp) * gp.W +
+                                   (xx >> 1);
+                    pp[mp] = __builtin_bit_cast(
+                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                   pa_, xzin && y0 + 2 * mp < g.H ? (pv * 16 + q * 4) * 4 : kOob,
+                                   0, 0));
+                }
+            } else {
+#pragma unroll
+                for (int mp = 0; mp < MT / 2; ++mp) pp[mp] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
         }
         // the accumulators start at the bias
         f32x4 acc[MT];
@@ -922,7 +945,10 @@ k_conv_rows(const uint16_t* __restrict__ x,
                                      __uint_as_float(ymk[m].y << 16),
                                      __uint_as_float(ymk[m].y & 0xFFFF0000u)};
 #pragma unroll
-                for (int i = 0; i < 4; ++i) r[i] = yv[i] > 0.0f ? acc[m][i] : alpha * acc[m][i];
+                for (int i = 0; i < 4; ++i) {
+                    const float t = head.par ? acc[m][i] + 0.125f * pp[m >> 1][i] : acc[m][i];
+                    r[i] = yv[i] > 0.0f ? t : alpha * t;
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) r[i] = acc[m][i] > 0.0f ? acc[m][i] : slope * acc[m][i];
@@ -2476,11 +2502,13 @@ hipError_t conv_fwd_split(const uint16_t* x, const uint16_t* w, const int* dims,
                           hipStream_t s) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     const Geo gc{g.B, g.D >> 1, g.H >> 1, g.W >> 1};
-    if (Ci != 16 || Co != 48 || cs != 16 || !ya || !ym || !dzc || ((g.D | g.H | g.W) & 1) ||
+    if (Ci != 16 || Co != 48 || cs != 16 || !ym || !dzc || ((g.D | g.H | g.W) & 1) ||
         gc.nvox() * 32 * 2 >= (1LL << 31) || dzc == x)
         return hipErrorInvalidValue;
-    hipError_t e = launch_rows<16, 16>(x, nullptr, w, nullptr, g, 0.0f, 0, nullptr, ya, 0, s, 1);
-    if (e != hipSuccess) return e;
+    if (ya) {
+        hipError_t e = launch_rows<16, 16>(x, nullptr, w, nullptr, g, 0.0f, 0, nullptr, ya, 0, s, 1);
+        if (e != hipSuccess) return e;
+    }
     HeadArgs a{};
     a.ym = ym;
     a.pool = dzc;
@@ -2500,11 +2528,14 @@ hipError_t conv_pool_fwd(const uint16_t* x, const uint16_t* w, const float* bias
 }
 
 hipError_t conv_dz_fwd(const uint16_t* x, const uint16_t* w, const int* dims, const uint16_t* ym,
-                       float alpha, uint16_t* dz, hipStream_t s) {
+                       float alpha, uint16_t* dz, hipStream_t s, const float* par) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
-    if (g.nvox() * 16 * 2 >= (1LL << 31) || !ym || !dz) return hipErrorInvalidValue;
+    if (g.nvox() * 16 * 2 >= (1LL << 31) || !ym || !dz || dz == x ||
+        (par && ((g.D | g.H | g.W) & 1)))
+        return hipErrorInvalidValue;
     HeadArgs a{};
     a.ym = ym;
+    a.par = par;
     return launch_rows_as<16, 16, kOutDz>(x, nullptr, w, nullptr, g, alpha, 0, dz, nullptr, 0, s, a);
 }
 
