@@ -317,10 +317,8 @@ int run_backward(sde_nn* n, const int* d0) {
                                  nullptr, n->c[l], xlow))
                 return r;
         }
-        if (!split) {
-            NN_TRY(slice_copy(v.gCat, d, n->c[l], Cf, 0, v.gE, s));
-            NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s, ytgt, al, n->dz));
-        }
+        // the skip half stays in gCat, where the encoder's pool_bwd reads it
+        if (!split) NN_TRY(up_bwd(v.gCat, dc, n->c[l + 1], Cf, n->c[l], tgt, s, ytgt, al, n->dz));
     }
     for (int l = L - 1; l >= 0; --l) {
         dims_at(d0, l, d);
@@ -352,8 +350,10 @@ int run_backward(sde_nn* n, const int* d0) {
                 NN_TRY(conv_dz_fwd(n->lv[l - 1].dzk, n->wt_all + n->dec_a[l - 1].w, df,
                                    n->lv[l - 1].eb, n->cfg.leaky_alpha, n->dz, s, v.gP));
             } else {
-                NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gE, s, n->lv[l - 1].eb,
-                                n->cfg.leaky_alpha, n->dz));
+                // the skip term: the decoder's input gradient, channels
+                // [0, c[l - 1]) of gCat
+                NN_TRY(pool_bwd(v.gP, df, n->c[l - 1], n->lv[l - 1].gCat, s, n->lv[l - 1].eb,
+                                n->cfg.leaky_alpha, n->dz, n->c[l - 1] + n->c[l]));
             }
         }
     }
@@ -387,8 +387,10 @@ int alloc_all(sde_nn* n) {
             NN_TRY(dalloc(n, &v.db, nv * n->c[l]));
         }
         if (!c.train) continue;
+        // above the bottom the skip gradient lives in gCat or is taken
+        // from dzk: gE is the head's target (one level) or unused
         if (l <= L - 2 && split_up(n, l)) NN_TRY(dalloc(n, &v.dzk, nv * n->c[l]));
-        else NN_TRY(dalloc(n, &v.gE, nv * n->c[l]));
+        else if (l == L - 1) NN_TRY(dalloc(n, &v.gE, nv * n->c[l]));
         NN_TRY(dalloc(n, &v.gEa, nv * n->c[l]));
         if (l > 0) NN_TRY(dalloc(n, &v.gP, nv * n->c[l - 1]));
         if (l <= L - 2) {

@@ -96,9 +96,11 @@ hipError_t lrelu_bwd(const float* dy, const uint16_t* y, float alpha, long long 
 hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, hipStream_t s);
 // pool_bwd / up_bwd: with dz non-null the FP32 result is not stored; it goes
 // through the LeakyReLU derivative of y (the activation it is the gradient
-// of, same layout) into dz (bf16), as lrelu_bwd would turn it.
+// of, same layout) into dz (bf16), as lrelu_bwd would turn it.  pool_bwd's
+// dx holds cx channels per voxel (0: C), of which the first C are added to.
 hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s,
-                    const uint16_t* y = nullptr, float alpha = 0.0f, uint16_t* dz = nullptr);
+                    const uint16_t* y = nullptr, float alpha = 0.0f, uint16_t* dz = nullptr,
+                    int cx = 0);
 hipError_t up_fwd(const uint16_t* x, const int* dims_fine, int C, int Cf, int c0, uint16_t* y,
                   hipStream_t s);
 hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0, float* dx,
@@ -106,8 +108,6 @@ hipError_t up_bwd(const float* dy, const int* dims_coarse, int C, int Cf, int c0
                   uint16_t* dz = nullptr);
 hipError_t copy_channels(const uint16_t* x, const int* dims, int C, int Cf, int c0, uint16_t* y,
                          hipStream_t s);
-hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, float* dx,
-                      hipStream_t s);
 // network input from normalised FP32 maps (rho nullable): channel 0 dose,
 // channel 1 density, the rest zero, as Cx-channel rows x (nullable) and as
 // bf16 pairs x2[v] = dose | density << 16 (nullable); resid = dose

@@ -1991,16 +1991,17 @@ __device__ __forceinline__ void lrelu_dz4(float4 r, const uint16_t* y, float alp
     *reinterpret_cast<uint2*>(dz + i) = o;
 }
 
-// Pooling backward: dx (FP32, fine grid gi) += dy(parent) / 8, 4 channels per
-// thread; with dz non-null the sum goes instead, through the LeakyReLU
-// derivative of y (the fine level's activation), to dz (bf16).
-__global__ void k_pool_bwd(const float* dy, Geo gi, int C, float* dx, const uint16_t* y,
+// Pooling backward: dx (FP32, fine grid gi, Cx channels per voxel, the first
+// C used) += dy(parent) / 8, 4 channels per thread; with dz non-null the sum
+// goes instead, through the LeakyReLU derivative of y (the fine level's
+// activation), to dz (bf16).
+__global__ void k_pool_bwd(const float* dy, Geo gi, int C, int Cx, float* dx, const uint16_t* y,
                            float alpha, uint16_t* dz) {
     VoxG f;
     if (!vox_of(gi, C / 4, f)) return;
     const float4 p = *reinterpret_cast<const float4*>(dy + parent(gi, f) * C + f.grp * 4);
     const long long i = f.v * C + f.grp * 4;
-    float4* q = reinterpret_cast<float4*>(dx + i);
+    float4* q = reinterpret_cast<float4*>(dx + f.v * Cx + f.grp * 4);
     float4 r = *q;
     r.x += 0.125f * p.x;
     r.y += 0.125f * p.y;
@@ -2041,20 +2042,12 @@ __global__ void k_up_bwd(const float* dy, Geo gc, int C, int Cf, int c0, float* 
 }
 
 // Copy channels [0, C) of x into channels [c0, c0+C) of y (Cf channels): the
-// skip half of a concatenation (8 bf16 per thread); and its backward, the
-// slice dx = dy[:, c0:c0+C] (4 FP32 per thread).
+// skip half of a concatenation (8 bf16 per thread).
 __global__ void k_copy_channels(const uint16_t* x, Geo g, int C, int Cf, int c0, uint16_t* y) {
     VoxG o;
     if (!vox_of(g, C / 8, o)) return;
     *reinterpret_cast<uint4*>(y + o.v * Cf + c0 + o.grp * 8) =
         *reinterpret_cast<const uint4*>(x + o.v * C + o.grp * 8);
-}
-
-__global__ void k_slice_copy(const float* dy, Geo g, int C, int Cf, int c0, float* dx) {
-    VoxG o;
-    if (!vox_of(g, C / 4, o)) return;
-    *reinterpret_cast<float4*>(dx + o.v * C + o.grp * 4) =
-        *reinterpret_cast<const float4*>(dy + o.v * Cf + c0 + o.grp * 4);
 }
 
 // Network input from normalised maps: x[v] = {dose, rho, 0, ...} (Cx channels).
@@ -2724,11 +2717,12 @@ hipError_t pool_fwd(const uint16_t* x, const int* dims_out, int C, uint16_t* y, 
 }
 
 hipError_t pool_bwd(const float* dy, const int* dims_in, int C, float* dx, hipStream_t s,
-                    const uint16_t* y, float alpha, uint16_t* dz) {
+                    const uint16_t* y, float alpha, uint16_t* dz, int cx) {
     Geo g{dims_in[0], dims_in[1], dims_in[2], dims_in[3]};
-    if (C % 4 || (dz && !y)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pool_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, dx, y, alpha,
-                       dz);
+    if (cx == 0) cx = C;
+    if (C % 4 || cx % 4 || cx < C || (dz && !y)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pool_bwd, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, cx, dx, y,
+                       alpha, dz);
     return hipGetLastError();
 }
 
@@ -2754,14 +2748,6 @@ hipError_t copy_channels(const uint16_t* x, const int* dims, int C, int Cf, int 
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     if (C % 8 || Cf % 8 || c0 % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy_channels, vox_grid(g, C / 8), dim3(256), 0, s, x, g, C, Cf, c0, y);
-    return hipGetLastError();
-}
-
-hipError_t slice_copy(const float* dy, const int* dims, int C, int Cf, int c0, float* dx,
-                      hipStream_t s) {
-    Geo g{dims[0], dims[1], dims[2], dims[3]};
-    if (C % 4 || Cf % 4 || c0 % 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_slice_copy, vox_grid(g, C / 4), dim3(256), 0, s, dy, g, C, Cf, c0, dx);
     return hipGetLastError();
 }
 
