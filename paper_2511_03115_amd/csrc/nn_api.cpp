@@ -228,8 +228,11 @@ int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, c
                          n->G + cp.b, s));
     else
         NN_TRY(wgrad(dz, x, d, cp.ci, cp.co, chunk, n->wpart, n->G + cp.w, n->G + cp.b, s));
-    if (dz_next)
+    if (dz_next && cp.ci == 16 && cp.co == 16)
         NN_TRY(conv_dz_fwd(dz, n->wt_all + cp.w, d, y_in, n->cfg.leaky_alpha, dz_next, s));
+    else if (dz_next)
+        NN_TRY(conv_fwd(dz, n->wt_all + cp.w, nullptr, d, cp.co, cp.ci, n->cfg.leaky_alpha, 0,
+                        dz_next, nullptr, 0, s, y_in));
     else if (dz_up)
         NN_TRY(conv_fwd_split(dz, n->wt_all + cp.w, d, cp.co, cp.ci, cs, dx, y_up,
                               n->cfg.leaky_alpha, dz_up, s));
@@ -238,16 +241,19 @@ int conv_bwd(sde_nn* n, const float* dy, const uint16_t* y, const uint16_t* x, c
     return SDE_OK;
 }
 
-// A 16 -> 16 conv whose input gradient feeds only the LeakyReLU before it
-// hands that layer its bf16 gradient directly.
-bool dz_chain(const ConvP& cp) { return cp.ci == 16 && cp.co == 16; }
+// A conv whose input gradient feeds only the LeakyReLU before it hands that
+// layer its bf16 gradient directly: 16 -> 16 convs, and the wider ones whose
+// input-gradient launch has the LeakyReLU-gradient epilogue at these dims.
+bool dz_chain(const ConvP& cp, const int* d) {
+    return (cp.ci == 16 && cp.co == 16) || conv_dz_wide_supported(cp.co, cp.ci, d);
+}
 
 // The decoder conv at level l whose input gradient conv_fwd_split takes:
 // its skip half in FP32, its upsampled half straight to the level below as
 // bf16 LeakyReLU gradient (no FP32 concatenation gradient at that level).
 bool split_up(const sde_nn* n, int l) {
-    return dz_chain(n->dec_b[l]) && n->dec_a[l].ci == 48 && n->dec_a[l].co == 16 &&
-           n->c[l] == 16;
+    return n->dec_b[l].ci == 16 && n->dec_b[l].co == 16 && n->dec_a[l].ci == 48 &&
+           n->dec_a[l].co == 16 && n->c[l] == 16;
 }
 
 int run_backward(sde_nn* n, const int* d0) {
@@ -304,7 +310,7 @@ int run_backward(sde_nn* n, const int* d0) {
         const uint16_t* low = l + 1 <= L - 2 ? n->lv[l + 1].db : n->lv[L - 1].eb;
         const uint16_t* xin = inplace ? v.eb : v.cat;
         const uint16_t* xlow = inplace ? low : nullptr;
-        if (dz_chain(n->dec_b[l])) {
+        if (dz_chain(n->dec_b[l], d)) {
             if (int r = conv_bwd(n, v.gDb, v.db, v.da, n->dec_b[l], d, nullptr, dzb, v.da, dzd))
                 return r;
             if (int r = conv_bwd(n, nullptr, nullptr, xin, n->dec_a[l], d, split ? nullptr : v.gCat,
@@ -329,7 +335,7 @@ int run_backward(sde_nn* n, const int* d0) {
         // (which adds the pooled term to the skip term); a network of one
         // level has neither
         const uint16_t* dze = L > 1 ? n->dz : nullptr;
-        if (dz_chain(n->enc_b[l])) {
+        if (dz_chain(n->enc_b[l], d)) {
             if (int r = conv_bwd(n, v.gE, v.eb, v.ea, n->enc_b[l], d, nullptr, dze, v.ea,
                                  n->dz2))
                 return r;
@@ -410,7 +416,7 @@ int alloc_all(sde_nn* n) {
     NN_TRY(hipMemset(n->M, 0, sizeof(float) * n->n_params));
     NN_TRY(hipMemset(n->V, 0, sizeof(float) * n->n_params));
     NN_TRY(dalloc(n, &n->dz, n->max_nv0 * n->c0));
-    NN_TRY(dalloc(n, &n->dz2, n->max_nv0 * 16));
+    NN_TRY(dalloc(n, &n->dz2, n->max_nv0 * std::max(n->c0, 16)));
     NN_TRY(dalloc(n, &n->wt_all, n->n_params));
     NN_TRY(dalloc(n, &n->wpart, std::max(kMaxPartFloats, max_w)));
     NN_TRY(dalloc(n, &n->dout, n->max_nv0));

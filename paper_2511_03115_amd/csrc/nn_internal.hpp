@@ -15,9 +15,15 @@ namespace nn {
 // The kernel is chosen by the channel counts: registers-held weights for
 // Ci <= 48 with 16 or 32 outputs, 32-channel passes for Ci >= 64 with 32 or
 // 64, LDS weight slabs otherwise.
+//
+// With ym non-null (bias, act, accumulate and y32 zero) y16 gets instead the
+// input gradient of a LeakyReLU layer whose output is ym (Co channels):
+// bf16(ym > 0 ? r : alpha r), r the FP32 conv output, what lrelu_bwd turns
+// it into; only where conv_dz_wide_supported(Ci, Co, dims) holds.
 hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
                     int Ci, int Co, float alpha, int act, uint16_t* y16, float* y32,
-                    int accumulate, hipStream_t s);
+                    int accumulate, hipStream_t s, const uint16_t* ym = nullptr);
+bool conv_dz_wide_supported(int Ci, int Co, const int* dims);
 // conv_fwd (bf16 output) of the decoder input concat[skip (Cs channels),
 // nearest-up(low) (Cu channels, half size)] without storing the
 // concatenation; only the shapes and sizes (nvox voxels at the skip level)

@@ -361,7 +361,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
                                                       const float* __restrict__ bias, Geo g,
                                                       int Co, float alpha, int act,
                                                       uint16_t* __restrict__ y16,
-                                                      float* __restrict__ y32, int accumulate) {
+                                                      float* __restrict__ y32, int accumulate,
+                                                      const uint16_t* __restrict__ ym) {
     constexpr int MT = 4;
     constexpr int K = 27 * CI;
     constexpr int KS = (K + 31) / 32;
@@ -385,6 +386,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
     if (bias) bias += cg;
     if (y16) y16 += cg;
     if (y32) y32 += cg;
+    if (ym) ym += cg;
     // Loads go through buffer resources with 32-bit offsets (the host keeps
     // every operand below 2 GiB); a load that must give zeros (outside the
     // volume, past the last K step) reads offset 0 and is replaced by zero,
@@ -538,6 +540,14 @@ __global__ void __launch_bounds__(256) k_conv_fwd_reg(const uint16_t* __restrict
                 for (int i = 0; i < 4; ++i) {
                     float rr = acc[m][j][i] + bb;
                     if (act) rr = lrelu(rr, alpha);
+                    if (ym) {   // a LeakyReLU input gradient, as lrelu_bwd turns rr
+                        const int yy = y0 + m, xx = x0 + q * 4 + i;
+                        const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                        const float yv = zz < g.D && yy < g.H && xx < g.W
+                                             ? bf2f(ym[v * Co + j * 16 + (lane & 15)])
+                                             : 0.0f;
+                        rr = yv > 0.0f ? rr : alpha * rr;
+                    }
                     ot[(m * 16 + q * 4 + i) * (NT * 16) + j * 16 + (lane & 15)] = f2bf(rr);
                 }
         }
@@ -1251,7 +1261,8 @@ __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __re
                                                        const float* __restrict__ bias, Geo g,
                                                        int Ci, int cs, int Co, float alpha,
                                                        int act, uint16_t* __restrict__ y16,
-                                                       float* __restrict__ y32, int accumulate) {
+                                                       float* __restrict__ y32, int accumulate,
+                                                       const uint16_t* __restrict__ ym) {
     constexpr int MT = 4;
     constexpr int CP = 32;
     constexpr int ROW = CP + 8;
@@ -1278,6 +1289,7 @@ __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __re
     if (bias) bias += cg;
     if (y16) y16 += cg;
     if (y32) y32 += cg;
+    if (ym) ym += cg;
     auto load_brick = [&](uint4 (&st)[NU], int p) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -1414,6 +1426,14 @@ __global__ void __launch_bounds__(256, OCC) k_conv_fwd_pass(const uint16_t* __re
                 for (int i = 0; i < 4; ++i) {
                     float rr = acc[m][j][i] + bb;
                     if (act) rr = lrelu(rr, alpha);
+                    if (ym) {   // a LeakyReLU input gradient, as lrelu_bwd turns rr
+                        const int yy = y0 + m, xx = x0 + q * 4 + i;
+                        const long long v = (((long long)b * g.D + zz) * g.H + yy) * g.W + xx;
+                        const float yv = zz < g.D && yy < g.H && xx < g.W
+                                             ? bf2f(ym[v * Co + j * 16 + (lane & 15)])
+                                             : 0.0f;
+                        rr = yv > 0.0f ? rr : alpha * rr;
+                    }
                     ot[(m * 16 + q * 4 + i) * (NT * 16) + j * 16 + (lane & 15)] = f2bf(rr);
                 }
         }
@@ -2357,12 +2377,27 @@ hipError_t launch_rows(const uint16_t* x, const uint16_t* xl, const uint16_t* w,
 
 }  // namespace
 
+bool conv_dz_wide_supported(int Ci, int Co, const int* dims) {
+    const Geo g{dims[0], dims[1], dims[2], dims[3]};
+    const int nt = (Co + 15) / 16;
+    const bool few = (long long)((g.W + kRX - 1) / kRX) * ((g.H + kRY - 1) / kRY) *
+                         ((g.D + kRZ - 1) / kRZ) * g.B < kFewBricks;
+    if (Co == 16) return false;
+    // the register kernel or the channel-pass kernel takes it (as conv_fwd routes)
+    if (g.nvox() * std::max(Ci, Co) * 2 < (1LL << 31) && (Ci == 16 || Ci == 32) &&
+        (nt == 2 || nt == 6 || (nt == 4 && few)))
+        return true;
+    return Ci % 32 == 0 && Ci >= 64 && (nt == 2 || nt == 4 || (nt % 2 == 0 && few));
+}
+
 hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, const int* dims,
                     int Ci, int Co, float alpha, int act, uint16_t* y16, float* y32,
-                    int accumulate, hipStream_t s) {
+                    int accumulate, hipStream_t s, const uint16_t* ym) {
     Geo g{dims[0], dims[1], dims[2], dims[3]};
     const long long nv = g.nvox();
     const int nt = (Co + 15) / 16;
+    if (ym && (y32 || !y16 || bias || act || accumulate || !conv_dz_wide_supported(Ci, Co, dims)))
+        return hipErrorInvalidValue;
     // the halo kernel may use more than the default 64 KB of dynamic LDS
     static const hipError_t attr = [] {
         hipError_t e = hipFuncSetAttribute((const void*)k_conv_fwd_halo<1>,
@@ -2380,7 +2415,7 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
 #define LAUNCH_REG(CI, NT, CH)                                                             \
     hipLaunchKernelGGL((k_conv_fwd_reg<CI, NT, CH>), dim3((unsigned)nbk, nt / NT), dim3(256), \
                        ((size_t)kRVox * (CI + 8) + 2 * NT * CH * 512) * sizeof(uint16_t), s, x, w, \
-                       bias, g, Co, alpha, act, y16, y32, accumulate)
+                       bias, g, Co, alpha, act, y16, y32, accumulate, ym)
         // 16 outputs: the persistent row-reuse form (48 from 16 inputs: three
         // groups of 16, blockIdx.y)
         if (Co == 16 && Ci == 16)
@@ -2411,13 +2446,11 @@ hipError_t conv_fwd(const uint16_t* x, const uint16_t* w, const float* bias, con
         if (nt == 2 || few)
             hipLaunchKernelGGL((k_conv_fwd_pass<2, 2>), dim3((unsigned)nbk, nt / 2), dim3(256),
                                pass_lds_bytes(2, 2), s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha,
-                               act, y16, y32,
-                               accumulate);
+                               act, y16, y32, accumulate, ym);
         else
             hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256),
                                pass_lds_bytes(4, 2), s, x, nullptr, w, bias, g, Ci, Ci, Co, alpha,
-                               act, y16, y32,
-                               accumulate);
+                               act, y16, y32, accumulate, ym);
         return hipGetLastError();
     }
     if (nt <= 2 && Ci <= 48) {   // few channels: input brick with halo in LDS
@@ -2478,13 +2511,11 @@ hipError_t conv_cat_fwd(const uint16_t* skip, const uint16_t* low, const uint16_
         if (Co == 32 || nbk < kFewBricks)   // 64 outputs on few bricks: two groups of 32
             hipLaunchKernelGGL((k_conv_fwd_pass<2, 2>), dim3((unsigned)nbk, Co / 32), dim3(256),
                                pass_lds_bytes(2, 2), s, skip, low, w, bias, g, Cs + Cu, Cs, Co,
-                               alpha, act, y16,
-                               nullptr, 0);
+                               alpha, act, y16, nullptr, 0, nullptr);
         else
             hipLaunchKernelGGL((k_conv_fwd_pass<4, 2>), dim3((unsigned)nbk), dim3(256),
                                pass_lds_bytes(4, 2), s, skip, low, w, bias, g, Cs + Cu, Cs, Co,
-                               alpha, act, y16, nullptr,
-                               0);
+                               alpha, act, y16, nullptr, 0, nullptr);
         return hipGetLastError();
     }
     return launch_rows<48, 16>(skip, low, w, bias, g, alpha, act, y16, nullptr, 0, s);
